@@ -1,0 +1,195 @@
+/*
+ * hashgraph.h -- C ABI of libhashgraph.so, the HashGraph hot path on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Method: O. Green, "HashGraph -- Scalable Hash Tables Using A Sparse Graph
+ * Data Structure", arXiv:1907.02900.  A HashGraph is a CSR structure whose
+ * vertices are the V hash values and whose edges point back at the N inputs
+ * (Sec. 3.1, Fig. 1): an offset array of V+1 entries and an edge array of
+ * exactly N entries, each edge holding the input key and its input index.
+ *
+ * Conventions for every entry point:
+ *   - Pointers named d_* are device pointers (HBM of the current device);
+ *     pointers named h_* are host pointers.
+ *   - Keys are unsigned integers of key_bits = 32 (uint32_t) or 64 (uint64_t).
+ *   - Buckets, offsets, ids and per-query counts are uint32_t, so N, M and V
+ *     must be below 2^32.  Totals of pairs are uint64_t.
+ *   - Work is enqueued on the given stream and returns before it completes,
+ *     except where a host result (h_*) is requested: those calls wait for the
+ *     stream.  Passing stream 0 uses the device's null stream.
+ *   - The caller owns every buffer it passes.  Inputs are read only while the
+ *     enqueued work runs; nothing the caller passes is retained afterwards.
+ *   - Tables (hg_table) own their device memory until hg_table_free.  A table
+ *     is immutable after its build; probes and intersections may run
+ *     concurrently on several streams once the build's stream has passed the
+ *     build (for example after hipStreamSynchronize or an event wait).
+ *   - No call throws.  Every call returns an hg_status; hg_status_string
+ *     gives a message.  Invalid arguments are detected on the host before any
+ *     work is enqueued, and then nothing is enqueued and no output is written.
+ *   - The library never falls back to the CPU: with no usable gfx950 device
+ *     every call that needs one returns HG_ERR_DEVICE.
+ */
+#ifndef HASHGRAPH_H
+#define HASHGRAPH_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum hg_status {
+    HG_OK = 0,
+    HG_ERR_INVALID_ARG = 1, /* bad key_bits, range, size or NULL pointer     */
+    HG_ERR_OOM = 2,         /* device allocation failed                      */
+    HG_ERR_DEVICE = 3,      /* HIP runtime error or no usable device         */
+    HG_ERR_CAPACITY = 4,    /* output capacity too small (total reported)    */
+    HG_ERR_MISMATCH = 5,    /* tables built with different hash parameters   */
+    HG_ERR_BUDGET = 6,      /* request exceeds the server's memory budget    */
+    HG_ERR_NOT_FOUND = 7    /* unknown table or request handle               */
+} hg_status;
+
+/* Build variants (Sec. 3.2 and Sec. 3.3). */
+#define HG_VARIANT_AUTO 0 /* V2 */
+#define HG_VARIANT_V1 1   /* Alg. 1: global atomic count and atomic scatter  */
+#define HG_VARIANT_V2 2   /* Alg. 2: bin partition, then per-bin build       */
+
+typedef struct hg_build_opts {
+    int32_t variant;   /* HG_VARIANT_*                                          */
+    int32_t stable;    /* 1: ids ascending inside every bucket.  V2 always
+                          places stably; V1 places by atomics (order inside a
+                          bucket unspecified) and rejects stable=1 with
+                          HG_ERR_INVALID_ARG.                                   */
+    uint32_t bins;     /* V2: number of bins (Alg. 2 "Bins"), rounded so that
+                          a bin spans a power-of-two range of buckets; 0 =
+                          choose from N and V.                                 */
+    uint32_t block;    /* V1: threads per block, 0 = 256                        */
+    uint32_t reserved[4];
+} hg_build_opts;
+
+typedef struct hg_table hg_table; /* opaque; device-resident */
+
+typedef struct hg_table_info {
+    const uint32_t *d_offsets; /* V+1 entries, offsets[0]=0, offsets[V]=n      */
+    const uint32_t *d_ids;     /* n entries: input index of each edge          */
+    const void *d_keys;        /* n keys, bucketed (edge order)                */
+    uint64_t n;                /* number of keys (edges)                       */
+    uint64_t hash_range;       /* V                                            */
+    uint64_t seed;             /* hash seed                                    */
+    int32_t key_bits;          /* 32 or 64                                     */
+    int32_t variant;           /* variant that built it                        */
+    uint64_t device_bytes;     /* device memory the table holds                */
+} hg_table_info;
+
+/* Message for a status code; never NULL. */
+const char *hg_status_string(hg_status s);
+
+/* Version of this ABI (major*10000 + minor*100 + patch). */
+uint32_t hg_version(void);
+
+/* ------------------------------------------------------------------------
+ * Single steps of the path, exposed so that each can be checked alone.
+ * ------------------------------------------------------------------------ */
+
+/* Eq. 1 for every key: d_buckets[i] = fmix(d_keys[i] XOR seed) mod V, where
+ * fmix is the MurmurHash3 32-bit finaliser for key_bits = 32 (XOR with the
+ * low 32 bits of seed) and the 64-bit finaliser for key_bits = 64, and the
+ * modulo is exact.  hash_range = V must be in [1, 2^32 - 1].
+ * d_keys: n keys; d_buckets: n uint32 (caller-allocated). */
+hg_status hg_hash(const void *d_keys, uint64_t n, int key_bits, uint64_t hash_range,
+                  uint64_t seed, uint32_t *d_buckets, hipStream_t stream);
+
+/* Alg. 1, loops two and three: d_counts[b] = number of keys whose bucket
+ * (as hg_hash) is b, for b in [0, V).  The call zeroes d_counts itself.
+ * d_counts: V uint32 (caller-allocated). */
+hg_status hg_histogram(const void *d_keys, uint64_t n, int key_bits, uint64_t hash_range,
+                       uint64_t seed, uint32_t *d_counts, hipStream_t stream);
+
+/* Alg. 1 PrefixSum producing the CSR offset array of Sec. 3.1:
+ * d_offsets[0] = 0, d_offsets[b+1] = d_offsets[b] + d_counts[b], for
+ * b in [0, V); V+1 outputs.  Sums wrap modulo 2^32.  d_counts: V uint32;
+ * d_offsets: V+1 uint32, may not alias d_counts.  V may be 0 (then only
+ * d_offsets[0] = 0 is written). */
+hg_status hg_exclusive_scan(const uint32_t *d_counts, uint64_t V, uint32_t *d_offsets,
+                            hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Tables: build (Alg. 1 / Alg. 2), view, free.
+ * ------------------------------------------------------------------------ */
+
+/* Build a HashGraph of n keys into a new table.  Equivalent to
+ * hg_table_create(n, hash_range, key_bits) followed by hg_table_build.
+ * opts may be NULL (defaults).  The device memory of the table and the
+ * temporary workspace are allocated by this call (workspace is freed in
+ * stream order before the call's work completes). */
+hg_status hg_build(const void *d_keys, uint64_t n, int key_bits, uint64_t hash_range,
+                   uint64_t seed, const hg_build_opts *opts, hipStream_t stream,
+                   hg_table **out);
+
+/* Allocate an empty table able to hold up to n_capacity keys and
+ * range_capacity buckets, including the workspace a V2 build needs, so that
+ * later hg_table_build calls allocate nothing. */
+hg_status hg_table_create(uint64_t n_capacity, uint64_t range_capacity, int key_bits,
+                          hg_table **out);
+
+/* (Re)build table t from n keys with range V = hash_range and the given seed.
+ * Returns HG_ERR_CAPACITY if n or V exceed the table's capacities.  The
+ * previous contents are replaced; the caller must not probe t while this
+ * build is in flight. */
+hg_status hg_table_build(hg_table *t, const void *d_keys, uint64_t n, uint64_t hash_range,
+                         uint64_t seed, const hg_build_opts *opts, hipStream_t stream);
+
+/* Describe a table: device pointers to its CSR arrays and its parameters. */
+hg_status hg_table_view(const hg_table *t, hg_table_info *info);
+
+/* Copy the table's CSR arrays into caller buffers (device to device, on the
+ * stream): d_offsets V+1 uint32, d_ids n uint32, d_keys n keys.  Any of the
+ * three may be NULL to skip it. */
+hg_status hg_table_export(const hg_table *t, uint32_t *d_offsets, uint32_t *d_ids, void *d_keys,
+                          hipStream_t stream);
+
+/* Release a table (waits for the device to finish using it).  NULL is a
+ * no-op. */
+void hg_table_free(hg_table *t);
+
+/* ------------------------------------------------------------------------
+ * Probing (Sec. 3.4).
+ * ------------------------------------------------------------------------ */
+
+/* HashGraph-Probe-Standard: for every query j, the number of table entries
+ * whose key equals d_queries[j] (all instances, not only the first).
+ * d_queries: m keys of the table's key_bits.  d_counts: m uint32 or NULL.
+ * h_total: if not NULL, receives the sum of all counts (uint64); this waits
+ * for the stream.  At least one of d_counts and h_total must be given. */
+hg_status hg_probe(const hg_table *t, const void *d_queries, uint64_t m, uint32_t *d_counts,
+                   uint64_t *h_total, hipStream_t stream);
+
+/* The matching pairs themselves: d_build_ids[p], d_probe_ids[p] for p below
+ * the total, grouped by probe id ascending; inside one probe id the build
+ * ids follow the table's bucket order (ascending for stable tables).
+ * Always writes *h_total (required) and waits for the stream.  If the total
+ * exceeds capacity, nothing is written to the pair arrays and
+ * HG_ERR_CAPACITY is returned. */
+hg_status hg_probe_pairs(const hg_table *t, const void *d_queries, uint64_t m,
+                         uint32_t *d_build_ids, uint32_t *d_probe_ids, uint64_t capacity,
+                         uint64_t *h_total, hipStream_t stream);
+
+/* HashGraph-Probe-New (Alg. 3): bucket-wise intersection of tables a and b,
+ * which must share key_bits, hash_range and seed (else HG_ERR_MISMATCH).
+ * d_counts_b: if not NULL, n_b uint32, indexed by b's INPUT index j: the
+ * number of entries of a whose key equals b's key j.  d_a_ids / d_b_ids with
+ * capacity > 0: the matching (a input index, b input index) pairs, grouped
+ * by b's edge order.  h_total: if not NULL receives the number of pairs and
+ * the call waits for the stream; required when capacity > 0.  Returns
+ * HG_ERR_CAPACITY (pairs not written, total reported) if the total exceeds
+ * a non-zero capacity. */
+hg_status hg_intersect(const hg_table *a, const hg_table *b, uint32_t *d_counts_b,
+                       uint32_t *d_a_ids, uint32_t *d_b_ids, uint64_t capacity,
+                       uint64_t *h_total, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HASHGRAPH_H */

@@ -1,0 +1,381 @@
+// C ABI of libhashgraph.so (declared in include/hashgraph.h).
+//
+// Host-side validation, table objects, workspace handling and dispatch to the
+// kernels.  Nothing here computes on the CPU: every step of the path runs in
+// the HIP kernels of hg_build.hip, hg_scan.hip and hg_probe.hip.
+#include <new>
+
+#include "hashgraph.h"
+#include "hg_internal.h"
+
+using namespace hg;
+
+struct hg_table {
+    int key_bits = 32;
+    int variant = 0;
+    uint64_t n = 0, V = 0, seed = 0;
+    uint64_t n_cap = 0, V_cap = 0;
+    uint32_t* offsets = nullptr;
+    uint32_t* ids = nullptr;
+    void* keys = nullptr;
+    void* ws = nullptr;  // workspace kept for rebuilds (hg_table_create only)
+    size_t ws_bytes = 0;
+    uint64_t bytes = 0;
+};
+
+namespace {
+
+constexpr uint64_t kU32Max = 0xffffffffull;
+
+hg_status from_hip(hipError_t e) {
+    if (e == hipSuccess) return HG_OK;
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return HG_ERR_OOM;
+    if (e == hipErrorInvalidValue) return HG_ERR_INVALID_ARG;
+    return HG_ERR_DEVICE;
+}
+
+#define HG_CALL(expr)                          \
+    do {                                       \
+        hipError_t e__ = (expr);               \
+        if (e__ != hipSuccess) return from_hip(e__); \
+    } while (0)
+
+hg_status device_ready() {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return HG_ERR_DEVICE;
+    return HG_OK;
+}
+
+bool valid_kb(int kb) { return kb == 32 || kb == 64; }
+bool valid_range(uint64_t V) { return V >= 1 && V <= kU32Max; }
+size_t key_size(int kb) { return kb == 64 ? 8 : 4; }
+
+// Stream-ordered temporary device memory, released in stream order.
+struct Scratch {
+    void* p = nullptr;
+    hipStream_t s;
+    explicit Scratch(hipStream_t st) : s(st) {}
+    hipError_t get(size_t bytes) {
+        if (bytes == 0) bytes = 256;
+        return hipMallocAsync(&p, bytes, s);
+    }
+    ~Scratch() {
+        if (p) (void)hipFreeAsync(p, s);
+    }
+};
+
+hg_status read_u64(const uint64_t* d, uint64_t* h, hipStream_t s) {
+    HG_CALL(hipMemcpyAsync(h, d, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    HG_CALL(hipStreamSynchronize(s));
+    return HG_OK;
+}
+
+hg_status build_into(hg_table* t, const void* keys, uint64_t n, uint64_t V, uint64_t seed,
+                     const hg_build_opts* opts, hipStream_t s) {
+    int variant = opts ? opts->variant : HG_VARIANT_AUTO;
+    if (variant == HG_VARIANT_AUTO) variant = HG_VARIANT_V2;
+    if (variant != HG_VARIANT_V1 && variant != HG_VARIANT_V2) return HG_ERR_INVALID_ARG;
+    const int stable = opts ? opts->stable : 0;
+    if (stable && variant == HG_VARIANT_V1) return HG_ERR_INVALID_ARG;
+    const uint32_t bins = opts ? opts->bins : 0;
+    const uint32_t block = opts ? opts->block : 0;
+    if (block && (block % 64 || block > 1024)) return HG_ERR_INVALID_ARG;
+    if (bins && bins > V) return HG_ERR_INVALID_ARG;
+
+    const size_t need = build_ws_bytes(variant, n, V, t->key_bits, bins);
+    Scratch tmp(s);
+    void* ws = t->ws;
+    if (!ws || t->ws_bytes < need) {
+        HG_CALL(tmp.get(need));
+        ws = tmp.p;
+    }
+    hipError_t e;
+    if (t->key_bits == 32) {
+        e = variant == HG_VARIANT_V1
+                ? run_build_v1<uint32_t>((const uint32_t*)keys, n, V, seed, t->offsets, t->ids,
+                                         (uint32_t*)t->keys, ws, block, s)
+                : run_build_v2<uint32_t>((const uint32_t*)keys, n, V, seed, t->offsets, t->ids,
+                                         (uint32_t*)t->keys, ws, bins, s);
+    } else {
+        e = variant == HG_VARIANT_V1
+                ? run_build_v1<uint64_t>((const uint64_t*)keys, n, V, seed, t->offsets, t->ids,
+                                         (uint64_t*)t->keys, ws, block, s)
+                : run_build_v2<uint64_t>((const uint64_t*)keys, n, V, seed, t->offsets, t->ids,
+                                         (uint64_t*)t->keys, ws, bins, s);
+    }
+    if (e != hipSuccess) return from_hip(e);
+    t->n = n;
+    t->V = V;
+    t->seed = seed;
+    t->variant = variant;
+    return HG_OK;
+}
+
+hg_status alloc_table(uint64_t n_cap, uint64_t V_cap, int kb, bool with_ws, hg_table** out) {
+    hg_table* t = new (std::nothrow) hg_table();
+    if (!t) return HG_ERR_OOM;
+    t->key_bits = kb;
+    t->n_cap = n_cap;
+    t->V_cap = V_cap;
+    hipError_t e = hipMalloc((void**)&t->offsets, (V_cap + 1) * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc((void**)&t->ids, (n_cap ? n_cap : 1) * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(&t->keys, (n_cap ? n_cap : 1) * key_size(kb));
+    t->bytes = (V_cap + 1) * 4 + (n_cap ? n_cap : 1) * (4 + key_size(kb));
+    if (e == hipSuccess && with_ws) {
+        size_t w1 = build_ws_bytes(1, n_cap, V_cap, kb, 0);
+        size_t w2 = build_ws_bytes(2, n_cap, V_cap, kb, 0);
+        t->ws_bytes = w1 > w2 ? w1 : w2;
+        e = hipMalloc(&t->ws, t->ws_bytes);
+        t->bytes += t->ws_bytes;
+    }
+    if (e != hipSuccess) {
+        hg_table_free(t);
+        return from_hip(e);
+    }
+    *out = t;
+    return HG_OK;
+}
+
+hg_status check_table_arg(const hg_table* t) { return t ? HG_OK : HG_ERR_INVALID_ARG; }
+
+TableDev dev_view(const hg_table* t) {
+    TableDev d;
+    d.offsets = t->offsets;
+    d.ids = t->ids;
+    d.keys = t->keys;
+    d.n = t->n;
+    d.V = t->V;
+    d.seed = t->seed;
+    return d;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hg_status_string(hg_status s) {
+    switch (s) {
+        case HG_OK: return "ok";
+        case HG_ERR_INVALID_ARG: return "invalid argument";
+        case HG_ERR_OOM: return "out of device memory";
+        case HG_ERR_DEVICE: return "HIP runtime error or no usable device";
+        case HG_ERR_CAPACITY: return "output capacity too small";
+        case HG_ERR_MISMATCH: return "tables differ in key width, hash range or seed";
+        case HG_ERR_BUDGET: return "request exceeds the memory budget";
+        case HG_ERR_NOT_FOUND: return "unknown table or request";
+    }
+    return "unknown status";
+}
+
+uint32_t hg_version(void) { return 100; }
+
+hg_status hg_hash(const void* d_keys, uint64_t n, int key_bits, uint64_t hash_range,
+                  uint64_t seed, uint32_t* d_buckets, hipStream_t stream) {
+    if (!valid_kb(key_bits) || !valid_range(hash_range) || n > kU32Max) return HG_ERR_INVALID_ARG;
+    if (n && (!d_keys || !d_buckets)) return HG_ERR_INVALID_ARG;
+    if (device_ready() != HG_OK) return HG_ERR_DEVICE;
+    hipError_t e = key_bits == 32
+                       ? run_hash<uint32_t>((const uint32_t*)d_keys, n, hash_range, seed, d_buckets, stream)
+                       : run_hash<uint64_t>((const uint64_t*)d_keys, n, hash_range, seed, d_buckets, stream);
+    return from_hip(e);
+}
+
+hg_status hg_histogram(const void* d_keys, uint64_t n, int key_bits, uint64_t hash_range,
+                       uint64_t seed, uint32_t* d_counts, hipStream_t stream) {
+    if (!valid_kb(key_bits) || !valid_range(hash_range) || n > kU32Max) return HG_ERR_INVALID_ARG;
+    if ((n && !d_keys) || !d_counts) return HG_ERR_INVALID_ARG;
+    if (device_ready() != HG_OK) return HG_ERR_DEVICE;
+    hipError_t e = key_bits == 32
+                       ? run_histogram<uint32_t>((const uint32_t*)d_keys, n, hash_range, seed, d_counts, 0, stream)
+                       : run_histogram<uint64_t>((const uint64_t*)d_keys, n, hash_range, seed, d_counts, 0, stream);
+    return from_hip(e);
+}
+
+hg_status hg_exclusive_scan(const uint32_t* d_counts, uint64_t V, uint32_t* d_offsets,
+                            hipStream_t stream) {
+    if (V > kU32Max || !d_offsets || (V && !d_counts)) return HG_ERR_INVALID_ARG;
+    if (V && d_counts == d_offsets) return HG_ERR_INVALID_ARG;
+    if (device_ready() != HG_OK) return HG_ERR_DEVICE;
+    Scratch ws(stream);
+    HG_CALL(ws.get(scan_ws_bytes(V)));
+    return from_hip(scan_excl<uint32_t>(d_counts, V, d_offsets, nullptr, ws.p, stream));
+}
+
+hg_status hg_table_create(uint64_t n_capacity, uint64_t range_capacity, int key_bits,
+                          hg_table** out) {
+    if (!out || !valid_kb(key_bits) || !valid_range(range_capacity) || n_capacity > kU32Max)
+        return HG_ERR_INVALID_ARG;
+    if (device_ready() != HG_OK) return HG_ERR_DEVICE;
+    return alloc_table(n_capacity, range_capacity, key_bits, true, out);
+}
+
+hg_status hg_table_build(hg_table* t, const void* d_keys, uint64_t n, uint64_t hash_range,
+                         uint64_t seed, const hg_build_opts* opts, hipStream_t stream) {
+    if (!t || !valid_range(hash_range) || n > kU32Max || (n && !d_keys)) return HG_ERR_INVALID_ARG;
+    if (n > t->n_cap || hash_range > t->V_cap) return HG_ERR_CAPACITY;
+    return build_into(t, d_keys, n, hash_range, seed, opts, stream);
+}
+
+hg_status hg_build(const void* d_keys, uint64_t n, int key_bits, uint64_t hash_range,
+                   uint64_t seed, const hg_build_opts* opts, hipStream_t stream, hg_table** out) {
+    if (!out || !valid_kb(key_bits) || !valid_range(hash_range) || n > kU32Max ||
+        (n && !d_keys))
+        return HG_ERR_INVALID_ARG;
+    if (opts && ((opts->variant != 0 && opts->variant != 1 && opts->variant != 2) ||
+                 (opts->stable && opts->variant == HG_VARIANT_V1) ||
+                 (opts->bins && opts->bins > hash_range)))
+        return HG_ERR_INVALID_ARG;
+    if (device_ready() != HG_OK) return HG_ERR_DEVICE;
+    hg_table* t = nullptr;
+    hg_status st = alloc_table(n, hash_range, key_bits, false, &t);
+    if (st != HG_OK) return st;
+    st = build_into(t, d_keys, n, hash_range, seed, opts, stream);
+    if (st != HG_OK) {
+        hg_table_free(t);
+        return st;
+    }
+    *out = t;
+    return HG_OK;
+}
+
+hg_status hg_table_view(const hg_table* t, hg_table_info* info) {
+    if (!t || !info) return HG_ERR_INVALID_ARG;
+    info->d_offsets = t->offsets;
+    info->d_ids = t->ids;
+    info->d_keys = t->keys;
+    info->n = t->n;
+    info->hash_range = t->V;
+    info->seed = t->seed;
+    info->key_bits = t->key_bits;
+    info->variant = t->variant;
+    info->device_bytes = t->bytes;
+    return HG_OK;
+}
+
+hg_status hg_table_export(const hg_table* t, uint32_t* d_offsets, uint32_t* d_ids, void* d_keys,
+                          hipStream_t stream) {
+    if (!t || t->V == 0) return HG_ERR_INVALID_ARG;
+    if (d_offsets)
+        HG_CALL(hipMemcpyAsync(d_offsets, t->offsets, (t->V + 1) * 4, hipMemcpyDeviceToDevice, stream));
+    if (d_ids && t->n)
+        HG_CALL(hipMemcpyAsync(d_ids, t->ids, t->n * 4, hipMemcpyDeviceToDevice, stream));
+    if (d_keys && t->n)
+        HG_CALL(hipMemcpyAsync(d_keys, t->keys, t->n * key_size(t->key_bits),
+                               hipMemcpyDeviceToDevice, stream));
+    return HG_OK;
+}
+
+void hg_table_free(hg_table* t) {
+    if (!t) return;
+    if (t->offsets) (void)hipFree(t->offsets);
+    if (t->ids) (void)hipFree(t->ids);
+    if (t->keys) (void)hipFree(t->keys);
+    if (t->ws) (void)hipFree(t->ws);
+    delete t;
+}
+
+hg_status hg_probe(const hg_table* t, const void* d_queries, uint64_t m, uint32_t* d_counts,
+                   uint64_t* h_total, hipStream_t stream) {
+    if (check_table_arg(t) != HG_OK || m > kU32Max || (m && !d_queries)) return HG_ERR_INVALID_ARG;
+    if (!d_counts && !h_total) return HG_ERR_INVALID_ARG;
+    if (t->V == 0) return HG_ERR_INVALID_ARG;  // never built
+    if (device_ready() != HG_OK) return HG_ERR_DEVICE;
+    Scratch ws(stream);
+    unsigned long long* d_total = nullptr;
+    if (h_total) {
+        HG_CALL(ws.get(256));
+        d_total = (unsigned long long*)ws.p;
+        HG_CALL(fill_u32((uint32_t*)d_total, 2, 0u, stream));
+    }
+    TableDev d = dev_view(t);
+    hipError_t e = t->key_bits == 32
+                       ? run_probe_counts<uint32_t>(d, (const uint32_t*)d_queries, m, d_counts, d_total, stream)
+                       : run_probe_counts<uint64_t>(d, (const uint64_t*)d_queries, m, d_counts, d_total, stream);
+    if (e != hipSuccess) return from_hip(e);
+    if (h_total) return read_u64((const uint64_t*)d_total, h_total, stream);
+    return HG_OK;
+}
+
+hg_status hg_probe_pairs(const hg_table* t, const void* d_queries, uint64_t m,
+                         uint32_t* d_build_ids, uint32_t* d_probe_ids, uint64_t capacity,
+                         uint64_t* h_total, hipStream_t stream) {
+    if (check_table_arg(t) != HG_OK || m > kU32Max || (m && !d_queries) || !h_total)
+        return HG_ERR_INVALID_ARG;
+    if (capacity && (!d_build_ids || !d_probe_ids)) return HG_ERR_INVALID_ARG;
+    if (t->V == 0) return HG_ERR_INVALID_ARG;
+    if (device_ready() != HG_OK) return HG_ERR_DEVICE;
+    if (m == 0) {
+        *h_total = 0;
+        return HG_OK;
+    }
+    Scratch ws(stream);
+    HG_CALL(ws.get(probe_ws_bytes(m)));
+    Carver c(ws.p);
+    uint32_t* counts = c.take<uint32_t>(m);
+    uint64_t* pos = c.take<uint64_t>(m + 1);
+    void* scan_ws = c.take<char>(scan_ws_bytes(m));
+    TableDev d = dev_view(t);
+    hipError_t e = t->key_bits == 32
+                       ? run_probe_counts<uint32_t>(d, (const uint32_t*)d_queries, m, counts, nullptr, stream)
+                       : run_probe_counts<uint64_t>(d, (const uint64_t*)d_queries, m, counts, nullptr, stream);
+    if (e != hipSuccess) return from_hip(e);
+    HG_CALL(scan_excl<uint64_t>(counts, m, pos, nullptr, scan_ws, stream));
+    hg_status st = read_u64(pos + m, h_total, stream);
+    if (st != HG_OK) return st;
+    if (*h_total > capacity) return HG_ERR_CAPACITY;
+    if (*h_total == 0) return HG_OK;
+    e = t->key_bits == 32
+            ? run_probe_pairs<uint32_t>(d, (const uint32_t*)d_queries, m, pos, d_build_ids, d_probe_ids, stream)
+            : run_probe_pairs<uint64_t>(d, (const uint64_t*)d_queries, m, pos, d_build_ids, d_probe_ids, stream);
+    if (e != hipSuccess) return from_hip(e);
+    HG_CALL(hipStreamSynchronize(stream));
+    return HG_OK;
+}
+
+hg_status hg_intersect(const hg_table* a, const hg_table* b, uint32_t* d_counts_b,
+                       uint32_t* d_a_ids, uint32_t* d_b_ids, uint64_t capacity,
+                       uint64_t* h_total, hipStream_t stream) {
+    if (!a || !b) return HG_ERR_INVALID_ARG;
+    if (capacity && (!d_a_ids || !d_b_ids || !h_total)) return HG_ERR_INVALID_ARG;
+    if (!d_counts_b && !h_total) return HG_ERR_INVALID_ARG;
+    if (a->V == 0 || b->V == 0) return HG_ERR_INVALID_ARG;
+    if (a->key_bits != b->key_bits || a->V != b->V || a->seed != b->seed) return HG_ERR_MISMATCH;
+    if (device_ready() != HG_OK) return HG_ERR_DEVICE;
+    const uint64_t nb = b->n;
+    if (nb == 0) {
+        if (h_total) *h_total = 0;
+        return HG_OK;
+    }
+    TableDev da = dev_view(a), db = dev_view(b);
+    const bool pairs = capacity > 0;
+    Scratch ws(stream);
+    HG_CALL(ws.get(probe_ws_bytes(nb)));
+    Carver c(ws.p);
+    uint32_t* edge = c.take<uint32_t>(nb);
+    uint64_t* pos = c.take<uint64_t>(nb + 1);
+    void* scan_ws = c.take<char>(scan_ws_bytes(nb));
+    unsigned long long* d_total = (unsigned long long*)c.take<uint64_t>(1);
+    if (h_total && !pairs) HG_CALL(fill_u32((uint32_t*)d_total, 2, 0u, stream));
+    hipError_t e = a->key_bits == 32
+                       ? run_intersect_counts<uint32_t>(da, db, pairs ? edge : nullptr, d_counts_b,
+                                                        (h_total && !pairs) ? d_total : nullptr, stream)
+                       : run_intersect_counts<uint64_t>(da, db, pairs ? edge : nullptr, d_counts_b,
+                                                        (h_total && !pairs) ? d_total : nullptr, stream);
+    if (e != hipSuccess) return from_hip(e);
+    if (!pairs) {
+        if (h_total) return read_u64((const uint64_t*)d_total, h_total, stream);
+        return HG_OK;
+    }
+    HG_CALL(scan_excl<uint64_t>(edge, nb, pos, nullptr, scan_ws, stream));
+    hg_status st = read_u64(pos + nb, h_total, stream);
+    if (st != HG_OK) return st;
+    if (*h_total > capacity) return HG_ERR_CAPACITY;
+    if (*h_total == 0) return HG_OK;
+    e = a->key_bits == 32 ? run_intersect_pairs<uint32_t>(da, db, pos, d_a_ids, d_b_ids, stream)
+                          : run_intersect_pairs<uint64_t>(da, db, pos, d_a_ids, d_b_ids, stream);
+    if (e != hipSuccess) return from_hip(e);
+    HG_CALL(hipStreamSynchronize(stream));
+    return HG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,130 @@
+// Internal host-side interface between the C ABI (hg_api.hip) and the kernel
+// translation units.  Not installed; not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "hg_device.h"
+
+namespace hg {
+
+#define HG_TRY(expr)                        \
+    do {                                    \
+        hipError_t e__ = (expr);            \
+        if (e__ != hipSuccess) return e__;  \
+    } while (0)
+
+inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+inline uint32_t log2_ceil(uint64_t x) {
+    uint32_t r = 0;
+    while ((1ull << r) < x) ++r;
+    return r;
+}
+inline uint64_t pow2_ceil(uint64_t x) { return 1ull << log2_ceil(x ? x : 1); }
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// A bump allocator over one workspace buffer (sizes first, then pointers).
+struct Carver {
+    char* base;
+    size_t off = 0;
+    explicit Carver(void* b) : base((char*)b) {}
+    template <typename T>
+    T* take(size_t count) {
+        off = align_up(off, 256);
+        T* p = base ? (T*)(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+// ---- partition geometry shared by the V2 kernels --------------------------
+constexpr int kPartThreads = 256;
+constexpr int kPartItems = 16;
+constexpr uint32_t kPartTile = kPartThreads * kPartItems;  // entries per tile
+constexpr int kLocalThreads = 256;
+constexpr int kLocalItems = 16;
+constexpr uint32_t kLocalCap = kLocalThreads * kLocalItems;  // entries a bin may hold in LDS
+constexpr uint32_t kMaxLocalBits = 12;                       // buckets per bin <= 4096
+constexpr uint32_t kMaxDigitBits = 11;                       // partition fan-out <= 2048
+constexpr uint32_t kOneTierBits = 9;                         // single partition pass up to 512 bins
+
+// How a V2 build splits the bucket index h (Alg. 2): the low `k` bits pick the
+// bucket inside a final bin, the bits above pick the final bin.  The final bin
+// index is split into one or two partition digits of b1 (and b2) bits.
+struct V2Plan {
+    uint32_t k = 0;        // log2 buckets per final bin
+    uint32_t bins = 0;     // final bins B2 = ceil(V / 2^k)
+    uint32_t tiers = 1;    // partition passes (1 or 2)
+    uint32_t b1 = 0, b2 = 0;
+    uint64_t n = 0, V = 0;
+    uint32_t ntiles1 = 0, nchunks1 = 0, ch1 = 1;
+    uint32_t ntiles2_ub = 0, nchunks2_ub = 0, ch2 = 1;
+};
+
+V2Plan plan_v2(uint64_t n, uint64_t V, int key_bits, uint32_t bins_hint);
+
+// Workspace bytes needed by a build.
+size_t build_ws_bytes(int variant, uint64_t n, uint64_t V, int key_bits, uint32_t bins_hint);
+
+// Scan workspace for `n` inputs.
+size_t scan_ws_bytes(uint64_t n);
+
+// Exclusive scan of n uint32 counts into n+1 outputs of OutT.  If `copy` is
+// not null it also receives the first n outputs (as uint32).
+template <typename OutT>
+hipError_t scan_excl(const uint32_t* in, uint64_t n, OutT* out, uint32_t* copy, void* ws,
+                     hipStream_t s);
+
+hipError_t fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
+
+template <typename Key>
+hipError_t run_hash(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, uint32_t* out,
+                    hipStream_t s);
+
+template <typename Key>
+hipError_t run_histogram(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, uint32_t* counts,
+                         uint32_t block, hipStream_t s);
+
+template <typename Key>
+hipError_t run_build_v1(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, uint32_t* offsets,
+                        uint32_t* ids, Key* ekeys, void* ws, uint32_t block, hipStream_t s);
+
+template <typename Key>
+hipError_t run_build_v2(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, uint32_t* offsets,
+                        uint32_t* ids, Key* ekeys, void* ws, uint32_t bins_hint, hipStream_t s);
+
+// ---- probing ---------------------------------------------------------------
+struct TableDev {
+    const uint32_t* offsets;
+    const uint32_t* ids;
+    const void* keys;
+    uint64_t n, V, seed;
+};
+
+size_t probe_ws_bytes(uint64_t m);
+
+// counts (may be null) and/or the total (device uint64, may be null).
+template <typename Key>
+hipError_t run_probe_counts(const TableDev& t, const Key* queries, uint64_t m, uint32_t* counts,
+                            unsigned long long* d_total, hipStream_t s);
+
+// positions[j] = first pair slot of query j (exclusive scan of counts).
+template <typename Key>
+hipError_t run_probe_pairs(const TableDev& t, const Key* queries, uint64_t m,
+                           const uint64_t* positions, uint32_t* build_ids, uint32_t* probe_ids,
+                           hipStream_t s);
+
+// Intersection over b's edges: per-edge counts (edge order) and, optionally,
+// counts scattered to b's input order.
+template <typename Key>
+hipError_t run_intersect_counts(const TableDev& a, const TableDev& b, uint32_t* edge_counts,
+                                uint32_t* counts_by_input, unsigned long long* d_total,
+                                hipStream_t s);
+
+template <typename Key>
+hipError_t run_intersect_pairs(const TableDev& a, const TableDev& b, const uint64_t* positions,
+                               uint32_t* a_ids, uint32_t* b_ids, hipStream_t s);
+
+}  // namespace hg

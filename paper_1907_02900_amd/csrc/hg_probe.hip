@@ -1,0 +1,223 @@
+// Probing a HashGraph (Sec. 3.4).
+//
+// HashGraph-Probe-Standard: each query is hashed with Eq. 1, the bucket's
+// segment [offsets[h], offsets[h+1]) of the edge array is scanned, and every
+// entry with an equal key is counted (all instances, not the first).  Each
+// thread owns several queries (coalesced, strided by the block) and issues
+// all their offset loads before scanning, to keep many random reads in
+// flight.  Pairs are written in a second pass at positions given by an
+// exclusive scan of the counts, so pairs are grouped by query id.
+//
+// HashGraph-Probe-New (Alg. 3): both inputs are built into HashGraphs with the
+// same hash and V, and bucket x of A is intersected with bucket x of B for
+// every x.  B's edges are walked in edge order, so the buckets of A are read
+// in increasing order (streaming, cache-friendly) instead of at random.
+#include "hg_internal.h"
+
+namespace hg {
+
+namespace {
+
+constexpr int kProbeThreads = 256;
+constexpr int kProbeItems = 4;
+
+template <typename Key>
+__device__ __forceinline__ uint32_t count_in_bucket(const Key* __restrict__ ekeys, uint32_t lo,
+                                                    uint32_t hi, Key q) {
+    uint32_t c = 0;
+    for (uint32_t p = lo; p < hi; ++p) c += (ekeys[p] == q) ? 1u : 0u;
+    return c;
+}
+
+template <typename Key>
+__global__ __launch_bounds__(kProbeThreads) void k_probe_count(
+    const Key* __restrict__ q, uint64_t m, typename KeyTraits<Key>::Params hp,
+    const uint32_t* __restrict__ off, const Key* __restrict__ ekeys, uint32_t* __restrict__ counts,
+    unsigned long long* __restrict__ total) {
+    __shared__ uint64_t red[kProbeThreads / kWave + 1];
+    const uint64_t base = (uint64_t)blockIdx.x * (kProbeThreads * kProbeItems) + threadIdx.x;
+    Key qq[kProbeItems];
+    uint32_t lo[kProbeItems], hi[kProbeItems];
+#pragma unroll
+    for (int r = 0; r < kProbeItems; ++r) {
+        const uint64_t j = base + (uint64_t)r * kProbeThreads;
+        qq[r] = (j < m) ? q[j] : (Key)0;
+    }
+#pragma unroll
+    for (int r = 0; r < kProbeItems; ++r) {
+        const uint64_t j = base + (uint64_t)r * kProbeThreads;
+        if (j < m) {
+            const uint32_t h = KeyTraits<Key>::bucket(qq[r], hp);
+            lo[r] = off[h];
+            hi[r] = off[h + 1];
+        } else {
+            lo[r] = hi[r] = 0;
+        }
+    }
+    uint64_t sum = 0;
+#pragma unroll
+    for (int r = 0; r < kProbeItems; ++r) {
+        const uint64_t j = base + (uint64_t)r * kProbeThreads;
+        const uint32_t c = count_in_bucket(ekeys, lo[r], hi[r], qq[r]);
+        if (j < m && counts) counts[j] = c;
+        sum += c;
+    }
+    if (total) {
+        uint64_t all;
+        block_excl_scan64<kProbeThreads>(sum, red, &all);
+        if (threadIdx.x == 0 && all) atomic_add_relaxed64(total, all);
+    }
+}
+
+template <typename Key>
+__global__ __launch_bounds__(kProbeThreads) void k_probe_pairs(
+    const Key* __restrict__ q, uint64_t m, typename KeyTraits<Key>::Params hp,
+    const uint32_t* __restrict__ off, const Key* __restrict__ ekeys,
+    const uint32_t* __restrict__ eids, const uint64_t* __restrict__ positions,
+    uint32_t* __restrict__ build_ids, uint32_t* __restrict__ probe_ids) {
+    uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t st = (uint64_t)gridDim.x * blockDim.x;
+    for (; j < m; j += st) {
+        const Key k = q[j];
+        const uint32_t h = KeyTraits<Key>::bucket(k, hp);
+        const uint32_t lo = off[h], hi = off[h + 1];
+        uint64_t pos = positions[j];
+        for (uint32_t p = lo; p < hi; ++p)
+            if (ekeys[p] == k) {
+                build_ids[pos] = eids[p];
+                probe_ids[pos] = (uint32_t)j;
+                ++pos;
+            }
+    }
+}
+
+// Alg. 3 over B's edges p: count the entries of A's bucket h(key_p) equal to
+// key_p.  A and B share hash parameters, so h is recomputed from B's key.
+template <typename Key>
+__global__ __launch_bounds__(kProbeThreads) void k_intersect_count(
+    const uint32_t* __restrict__ a_off, const Key* __restrict__ a_keys,
+    const Key* __restrict__ b_keys, const uint32_t* __restrict__ b_ids, uint64_t nb,
+    typename KeyTraits<Key>::Params hp, uint32_t* __restrict__ edge_counts,
+    uint32_t* __restrict__ counts_by_input, unsigned long long* __restrict__ total) {
+    __shared__ uint64_t red[kProbeThreads / kWave + 1];
+    uint64_t sum = 0;
+    const uint64_t base = (uint64_t)blockIdx.x * (kProbeThreads * kProbeItems) + threadIdx.x;
+#pragma unroll
+    for (int r = 0; r < kProbeItems; ++r) {
+        const uint64_t p = base + (uint64_t)r * kProbeThreads;
+        if (p < nb) {
+            const Key k = b_keys[p];
+            const uint32_t h = KeyTraits<Key>::bucket(k, hp);
+            const uint32_t c = count_in_bucket(a_keys, a_off[h], a_off[h + 1], k);
+            if (edge_counts) edge_counts[p] = c;
+            if (counts_by_input) counts_by_input[b_ids[p]] = c;
+            sum += c;
+        }
+    }
+    if (total) {
+        uint64_t all;
+        block_excl_scan64<kProbeThreads>(sum, red, &all);
+        if (threadIdx.x == 0 && all) atomic_add_relaxed64(total, all);
+    }
+}
+
+template <typename Key>
+__global__ __launch_bounds__(kProbeThreads) void k_intersect_pairs(
+    const uint32_t* __restrict__ a_off, const Key* __restrict__ a_keys,
+    const uint32_t* __restrict__ a_ids, const Key* __restrict__ b_keys,
+    const uint32_t* __restrict__ b_ids, uint64_t nb, typename KeyTraits<Key>::Params hp,
+    const uint64_t* __restrict__ positions, uint32_t* __restrict__ out_a,
+    uint32_t* __restrict__ out_b) {
+    uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t st = (uint64_t)gridDim.x * blockDim.x;
+    for (; p < nb; p += st) {
+        const Key k = b_keys[p];
+        const uint32_t h = KeyTraits<Key>::bucket(k, hp);
+        const uint32_t lo = a_off[h], hi = a_off[h + 1];
+        const uint32_t bid = b_ids[p];
+        uint64_t pos = positions[p];
+        for (uint32_t i = lo; i < hi; ++i)
+            if (a_keys[i] == k) {
+                out_a[pos] = a_ids[i];
+                out_b[pos] = bid;
+                ++pos;
+            }
+    }
+}
+
+uint32_t grid_for(uint64_t items, uint32_t per_block) {
+    uint64_t g = ceil_div(items, per_block);
+    return (uint32_t)(g ? g : 1);
+}
+
+}  // namespace
+
+size_t probe_ws_bytes(uint64_t m) {
+    // counts (m uint32), positions (m+1 uint64), scan workspace
+    return align_up(m * 4, 256) + align_up((m + 1) * 8, 256) + scan_ws_bytes(m) + 512;
+}
+
+template <typename Key>
+hipError_t run_probe_counts(const TableDev& t, const Key* queries, uint64_t m, uint32_t* counts,
+                            unsigned long long* d_total, hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    auto hp = KeyTraits<Key>::make(t.V, t.seed);
+    hipLaunchKernelGGL(k_probe_count<Key>, dim3(grid_for(m, kProbeThreads * kProbeItems)),
+                       dim3(kProbeThreads), 0, s, queries, m, hp, t.offsets, (const Key*)t.keys,
+                       counts, d_total);
+    return hipGetLastError();
+}
+
+template <typename Key>
+hipError_t run_probe_pairs(const TableDev& t, const Key* queries, uint64_t m,
+                           const uint64_t* positions, uint32_t* build_ids, uint32_t* probe_ids,
+                           hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    auto hp = KeyTraits<Key>::make(t.V, t.seed);
+    uint32_t g = grid_for(m, kProbeThreads);
+    if (g > 8192) g = 8192;
+    hipLaunchKernelGGL(k_probe_pairs<Key>, dim3(g), dim3(kProbeThreads), 0, s, queries, m, hp,
+                       t.offsets, (const Key*)t.keys, t.ids, positions, build_ids, probe_ids);
+    return hipGetLastError();
+}
+
+template <typename Key>
+hipError_t run_intersect_counts(const TableDev& a, const TableDev& b, uint32_t* edge_counts,
+                                uint32_t* counts_by_input, unsigned long long* d_total,
+                                hipStream_t s) {
+    if (b.n == 0) return hipSuccess;
+    auto hp = KeyTraits<Key>::make(a.V, a.seed);
+    hipLaunchKernelGGL(k_intersect_count<Key>, dim3(grid_for(b.n, kProbeThreads * kProbeItems)),
+                       dim3(kProbeThreads), 0, s, a.offsets, (const Key*)a.keys,
+                       (const Key*)b.keys, b.ids, b.n, hp, edge_counts, counts_by_input, d_total);
+    return hipGetLastError();
+}
+
+template <typename Key>
+hipError_t run_intersect_pairs(const TableDev& a, const TableDev& b, const uint64_t* positions,
+                               uint32_t* a_ids, uint32_t* b_ids, hipStream_t s) {
+    if (b.n == 0) return hipSuccess;
+    auto hp = KeyTraits<Key>::make(a.V, a.seed);
+    uint32_t g = grid_for(b.n, kProbeThreads);
+    if (g > 8192) g = 8192;
+    hipLaunchKernelGGL(k_intersect_pairs<Key>, dim3(g), dim3(kProbeThreads), 0, s, a.offsets,
+                       (const Key*)a.keys, a.ids, (const Key*)b.keys, b.ids, b.n, hp, positions,
+                       a_ids, b_ids);
+    return hipGetLastError();
+}
+
+#define HG_PINST(Key)                                                                           \
+    template hipError_t run_probe_counts<Key>(const TableDev&, const Key*, uint64_t, uint32_t*, \
+                                              unsigned long long*, hipStream_t);                \
+    template hipError_t run_probe_pairs<Key>(const TableDev&, const Key*, uint64_t,             \
+                                             const uint64_t*, uint32_t*, uint32_t*,             \
+                                             hipStream_t);                                      \
+    template hipError_t run_intersect_counts<Key>(const TableDev&, const TableDev&, uint32_t*,  \
+                                                  uint32_t*, unsigned long long*, hipStream_t); \
+    template hipError_t run_intersect_pairs<Key>(const TableDev&, const TableDev&,              \
+                                                 const uint64_t*, uint32_t*, uint32_t*,         \
+                                                 hipStream_t);
+HG_PINST(uint32_t)
+HG_PINST(uint64_t)
+
+}  // namespace hg

@@ -1,0 +1,288 @@
+"""Thin ctypes binding over libhashgraph.so (include/hashgraph.h).
+
+Only argument marshalling lives here: device buffers are torch tensors on the
+current ROCm device, the stream is torch's current stream, and every step of
+the HashGraph path runs in the library's HIP kernels.  Unsigned key and id
+arrays are carried in signed torch dtypes of the same width (uint32 <-> int32,
+uint64 <-> int64); ``to_device`` / ``to_numpy`` convert bit-for-bit.
+
+If the shared library is missing the import fails loudly: there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("HG_LIB", os.path.join(_PKG, "libhashgraph.so"))
+
+HG_OK, HG_ERR_INVALID_ARG, HG_ERR_OOM, HG_ERR_DEVICE = 0, 1, 2, 3
+HG_ERR_CAPACITY, HG_ERR_MISMATCH, HG_ERR_BUDGET, HG_ERR_NOT_FOUND = 4, 5, 6, 7
+VARIANT_AUTO, VARIANT_V1, VARIANT_V2 = 0, 1, 2
+
+
+class HGError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = int(status)
+        super().__init__("%s: %s (status %d)" % (where, status_string(status), status))
+
+
+class BuildOpts(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("stable", ctypes.c_int32),
+                ("bins", ctypes.c_uint32), ("block", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 4)]
+
+
+class TableInfo(ctypes.Structure):
+    _fields_ = [("d_offsets", ctypes.c_void_p), ("d_ids", ctypes.c_void_p),
+                ("d_keys", ctypes.c_void_p), ("n", ctypes.c_uint64),
+                ("hash_range", ctypes.c_uint64), ("seed", ctypes.c_uint64),
+                ("key_bits", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("device_bytes", ctypes.c_uint64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libhashgraph.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libhashgraph.so not built at %s; run `python -m "
+                          "paper_1907_02900_amd.build` (there is no CPU fallback)" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    vp, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
+    pu64 = ctypes.POINTER(ctypes.c_uint64)
+    sig = {
+        "hg_status_string": ([i32], ctypes.c_char_p),
+        "hg_version": ([], u32),
+        "hg_hash": ([vp, u64, i32, u64, u64, vp, vp], i32),
+        "hg_histogram": ([vp, u64, i32, u64, u64, vp, vp], i32),
+        "hg_exclusive_scan": ([vp, u64, vp, vp], i32),
+        "hg_build": ([vp, u64, i32, u64, u64, ctypes.POINTER(BuildOpts), vp,
+                      ctypes.POINTER(vp)], i32),
+        "hg_table_create": ([u64, u64, i32, ctypes.POINTER(vp)], i32),
+        "hg_table_build": ([vp, vp, u64, u64, u64, ctypes.POINTER(BuildOpts), vp], i32),
+        "hg_table_view": ([vp, ctypes.POINTER(TableInfo)], i32),
+        "hg_table_export": ([vp, vp, vp, vp, vp], i32),
+        "hg_table_free": ([vp], None),
+        "hg_probe": ([vp, vp, u64, vp, pu64, vp], i32),
+        "hg_probe_pairs": ([vp, vp, u64, vp, vp, u64, pu64, vp], i32),
+        "hg_intersect": ([vp, vp, vp, vp, vp, u64, pu64, vp], i32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def status_string(s: int) -> str:
+    return lib().hg_status_string(int(s)).decode()
+
+
+def _check(rc: int, where: str):
+    if rc != HG_OK:
+        raise HGError(rc, where)
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else None
+
+
+# ---------------------------------------------------------------- arrays ---
+
+def to_device(a: np.ndarray, device="cuda") -> torch.Tensor:
+    """numpy unsigned array -> device tensor of the same bits (signed dtype)."""
+    a = np.ascontiguousarray(a)
+    view = {4: np.int32, 8: np.int64}[a.dtype.itemsize]
+    return torch.from_numpy(a.view(view)).to(device)
+
+
+def to_numpy(t: torch.Tensor, dtype) -> np.ndarray:
+    """device tensor -> numpy array reinterpreted as `dtype` (uint32/uint64)."""
+    return t.detach().cpu().numpy().view(dtype)
+
+
+def _key_bits(t: torch.Tensor) -> int:
+    if t.dtype in (torch.int32, torch.uint32):
+        return 32
+    if t.dtype in (torch.int64, torch.uint64):
+        return 64
+    raise TypeError("keys must be 32- or 64-bit integer tensors, got %s" % t.dtype)
+
+
+def _dev_keys(t: torch.Tensor) -> torch.Tensor:
+    if not t.is_cuda:
+        raise ValueError("keys/queries must be device tensors")
+    if not t.is_contiguous():
+        raise ValueError("keys/queries must be contiguous")
+    return t
+
+
+def _u32(n, device) -> torch.Tensor:
+    return torch.empty(int(n), dtype=torch.int32, device=device)
+
+
+# ---------------------------------------------------------- single steps ---
+
+def hg_hash(keys: torch.Tensor, hash_range: int, seed: int = 0, out=None, stream=None):
+    keys = _dev_keys(keys)
+    out = out if out is not None else _u32(keys.numel(), keys.device)
+    _check(lib().hg_hash(_ptr(keys), keys.numel(), _key_bits(keys), int(hash_range),
+                         int(seed) & (2**64 - 1), _ptr(out), _stream(stream)), "hg_hash")
+    return out
+
+
+def hg_histogram(keys: torch.Tensor, hash_range: int, seed: int = 0, out=None, stream=None):
+    keys = _dev_keys(keys)
+    out = out if out is not None else _u32(hash_range, keys.device)
+    _check(lib().hg_histogram(_ptr(keys), keys.numel(), _key_bits(keys), int(hash_range),
+                              int(seed) & (2**64 - 1), _ptr(out), _stream(stream)),
+           "hg_histogram")
+    return out
+
+
+def hg_exclusive_scan(counts: torch.Tensor, out=None, stream=None):
+    out = out if out is not None else _u32(counts.numel() + 1, counts.device)
+    _check(lib().hg_exclusive_scan(_ptr(counts), counts.numel(), ctypes.c_void_p(out.data_ptr()),
+                                   _stream(stream)), "hg_exclusive_scan")
+    return out
+
+
+# ----------------------------------------------------------------- tables ---
+
+def _opts(variant=VARIANT_AUTO, stable=0, bins=0, block=0):
+    o = BuildOpts()
+    o.variant, o.stable, o.bins, o.block = int(variant), int(stable), int(bins), int(block)
+    return o
+
+
+class Table:
+    """A device-resident HashGraph (owns its library handle)."""
+
+    def __init__(self, handle: ctypes.c_void_p, device):
+        self._h = handle
+        self.device = device
+
+    @classmethod
+    def create(cls, n_capacity: int, range_capacity: int, key_bits: int = 32, device="cuda"):
+        h = ctypes.c_void_p()
+        _check(lib().hg_table_create(int(n_capacity), int(range_capacity), int(key_bits),
+                                     ctypes.byref(h)), "hg_table_create")
+        return cls(h, torch.device(device))
+
+    def rebuild(self, keys: torch.Tensor, hash_range: int, seed: int = 0, variant=VARIANT_AUTO,
+                stable=0, bins=0, block=0, stream=None):
+        keys = _dev_keys(keys)
+        o = _opts(variant, stable, bins, block)
+        _check(lib().hg_table_build(self._h, _ptr(keys), keys.numel(), int(hash_range),
+                                    int(seed) & (2**64 - 1), ctypes.byref(o), _stream(stream)),
+               "hg_table_build")
+        return self
+
+    def info(self) -> TableInfo:
+        i = TableInfo()
+        _check(lib().hg_table_view(self._h, ctypes.byref(i)), "hg_table_view")
+        return i
+
+    @property
+    def handle(self):
+        return self._h
+
+    def export(self, stream=None):
+        """(offsets[V+1], ids[n], keys[n]) copied into new device tensors."""
+        i = self.info()
+        off = _u32(i.hash_range + 1, self.device)
+        ids = _u32(i.n, self.device)
+        keys = torch.empty(int(i.n), dtype=torch.int64 if i.key_bits == 64 else torch.int32,
+                           device=self.device)
+        _check(lib().hg_table_export(self._h, _ptr(off), _ptr(ids), _ptr(keys), _stream(stream)),
+               "hg_table_export")
+        return off, ids, keys
+
+    def free(self):
+        if self._h is not None and self._h.value:
+            lib().hg_table_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def hg_build(keys: torch.Tensor, hash_range: int, seed: int = 0, variant=VARIANT_AUTO, stable=0,
+             bins=0, block=0, stream=None) -> Table:
+    keys = _dev_keys(keys)
+    o = _opts(variant, stable, bins, block)
+    h = ctypes.c_void_p()
+    _check(lib().hg_build(_ptr(keys), keys.numel(), _key_bits(keys), int(hash_range),
+                          int(seed) & (2**64 - 1), ctypes.byref(o), _stream(stream),
+                          ctypes.byref(h)), "hg_build")
+    return Table(h, keys.device)
+
+
+def hg_probe(table: Table, queries: torch.Tensor, counts=True, total=False, out=None,
+             stream=None):
+    """Per-query match counts (device uint32 as int32) and/or the total."""
+    queries = _dev_keys(queries)
+    c = None
+    if counts:
+        c = out if out is not None else _u32(queries.numel(), queries.device)
+    tot = ctypes.c_uint64(0)
+    _check(lib().hg_probe(table.handle, _ptr(queries), queries.numel(), _ptr(c),
+                          ctypes.byref(tot) if total else None, _stream(stream)), "hg_probe")
+    return c, (int(tot.value) if total else None)
+
+
+def hg_probe_pairs(table: Table, queries: torch.Tensor, capacity=None, stream=None):
+    """(build_ids, probe_ids, total).  With capacity None the total is taken
+    from a counting call first."""
+    queries = _dev_keys(queries)
+    if capacity is None:
+        _, capacity = hg_probe(table, queries, counts=False, total=True, stream=stream)
+    b = _u32(max(int(capacity), 1), queries.device)
+    p = _u32(max(int(capacity), 1), queries.device)
+    tot = ctypes.c_uint64(0)
+    rc = lib().hg_probe_pairs(table.handle, _ptr(queries), queries.numel(), _ptr(b), _ptr(p),
+                              int(capacity), ctypes.byref(tot), _stream(stream))
+    if rc == HG_ERR_CAPACITY:
+        return None, None, int(tot.value)
+    _check(rc, "hg_probe_pairs")
+    t = int(tot.value)
+    return b[:t], p[:t], t
+
+
+def hg_intersect(a: Table, b: Table, counts=True, total=True, capacity=0, stream=None):
+    """Alg. 3.  Returns (counts_b by b's input index or None, a_ids, b_ids,
+    total)."""
+    ib = b.info()
+    c = _u32(ib.n, b.device) if counts else None
+    cap = int(capacity)
+    ai = _u32(max(cap, 1), b.device) if cap else None
+    bi = _u32(max(cap, 1), b.device) if cap else None
+    tot = ctypes.c_uint64(0)
+    want_total = total or cap > 0
+    rc = lib().hg_intersect(a.handle, b.handle, _ptr(c), _ptr(ai), _ptr(bi), cap,
+                            ctypes.byref(tot) if want_total else None, _stream(stream))
+    if rc == HG_ERR_CAPACITY:
+        return c, None, None, int(tot.value)
+    _check(rc, "hg_intersect")
+    t = int(tot.value) if want_total else None
+    if cap:
+        return c, ai[:t], bi[:t], t
+    return c, None, None, t

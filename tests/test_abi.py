@@ -1,0 +1,82 @@
+"""CPU-side checks of the C ABI: the library loads, exports every entry point
+that include/*.h declares, rejects invalid arguments before touching a device,
+and reports HG_ERR_DEVICE (never a CPU result) when no GPU is usable."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1907_02900_amd", "libhashgraph.so")
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"^[A-Za-z_][\w \*]*?\b(hg_\w+)\s*\(", src, flags=re.M):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_1907_02900_amd import build
+        build.build()
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ["hg_build", "hg_probe", "hg_probe_pairs", "hg_intersect", "hg_table_view",
+                     "hg_table_free", "hg_status_string", "hg_hash", "hg_histogram",
+                     "hg_exclusive_scan"]:
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_status_strings(lib):
+    lib.hg_status_string.restype = ctypes.c_char_p
+    for s in range(8):
+        assert lib.hg_status_string(s)
+    assert lib.hg_status_string(0) == b"ok"
+
+
+def test_invalid_arguments_rejected_on_host(lib):
+    vp = ctypes.c_void_p
+    lib.hg_hash.argtypes = [vp, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
+                            vp, vp]
+    dummy = vp(0x1000)
+    assert lib.hg_hash(dummy, 10, 16, 100, 0, dummy, None) == 1      # key_bits
+    assert lib.hg_hash(dummy, 10, 32, 0, 0, dummy, None) == 1        # V = 0
+    assert lib.hg_hash(dummy, 10, 32, 1 << 32, 0, dummy, None) == 1  # V >= 2^32
+    assert lib.hg_hash(dummy, 1 << 32, 32, 7, 0, dummy, None) == 1   # n >= 2^32
+    assert lib.hg_hash(None, 10, 32, 7, 0, dummy, None) == 1         # NULL input
+    lib.hg_build.argtypes = [vp, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
+                             vp, vp, ctypes.POINTER(vp)]
+    out = vp()
+    assert lib.hg_build(dummy, 10, 64, 0, 0, None, None, ctypes.byref(out)) == 1
+    assert lib.hg_build(dummy, 10, 32, 5, 0, None, None, None) == 1
+    lib.hg_probe.argtypes = [vp, vp, ctypes.c_uint64, vp, vp, vp]
+    assert lib.hg_probe(None, dummy, 5, dummy, None, None) == 1
+    lib.hg_intersect.argtypes = [vp, vp, vp, vp, vp, ctypes.c_uint64, vp, vp]
+    assert lib.hg_intersect(None, None, None, None, None, 0, None, None) == 1
+
+
+def test_no_cpu_fallback_without_gpu(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    vp = ctypes.c_void_p
+    lib.hg_hash.argtypes = [vp, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
+                            vp, vp]
+    dummy = vp(0x1000)
+    assert lib.hg_hash(dummy, 10, 32, 100, 0, dummy, None) == 3  # HG_ERR_DEVICE
