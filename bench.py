@@ -1,0 +1,315 @@
+#!/usr/bin/env python3
+"""Benchmark of the HashGraph hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras] [--no-cpu-baseline]
+
+One step = one pass of the hot path over one batch: a V2 HashGraph build of
+n = 2^28 uniform uint32 keys with hash_range V = 2^28 (load 1), followed by
+HashGraph-Probe-Standard of m = 2^28 queries (half drawn from the keys), with
+per-query match counts written to device memory.  Inputs are resident in HBM
+before the timed region; the table and workspace are preallocated, so nothing
+is allocated while timing.  value = (n + m) / step time, in G keys/s.
+
+The JSON line also carries:
+  roofline      the dominant kernel's algorithmic bytes per launch divided by
+                its average launch time (HIP events around each launch, on the
+                stream the library launches on), against 8 TB/s;
+  cpu_baseline  the CPU oracle (sequential C) timed on a bounded sample of the
+                same workload on this host;
+  phases        per-kernel times, the V1 build, the hash-range sweep
+                {2^26, 2^28, 2^30}, the 64-bit-key variant and Probe-New.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import glob
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "build & probe Gkeys/s + % HBM peak at 2^28 uint32 keys; batched/served p99"
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def src_digest() -> str:
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1907_02900_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def timed(fn, reps, torch):
+    """Median milliseconds of `reps` runs of fn() (events on the current stream)."""
+    out = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        e1.synchronize()
+        out.append(e0.elapsed_time(e1))
+    return float(np.median(out))
+
+
+def kernel_bytes(name, n, m, V, kb, sum_len, plan):
+    """Algorithmic bytes one launch of `name` must move (reads + writes)."""
+    if name == "probe_count":
+        return m * kb + m * 8 + kb * sum_len + m * 4
+    if name == "v2_local_build":
+        return 2 * n * (kb + 4) + (V + 1) * 4
+    if name == "v2_partition_t1":
+        return n * kb + n * (kb + 4) + plan["m1_bytes"]
+    if name == "v2_partition_t2":
+        return 2 * n * (kb + 4) + plan["m2_bytes"]
+    if name == "v2_tile_hist_t1":
+        return n * kb + plan["m1_bytes"]
+    if name == "v2_tile_hist_t2":
+        return n * kb + plan["m2_bytes"]
+    return None
+
+
+def v2_plan_bytes(n, V):
+    # mirrors the library's plan for the tile x digit matrices (4096-key tiles)
+    k = 0
+    r = 2048.0 * V / n
+    while k < 12 and (1 << (k + 1)) <= r:
+        k += 1
+    bins = -(-V // (1 << k))
+    bits = max(0, (bins - 1).bit_length())
+    tiles = -(-n // 4096)
+    if bits <= 9:
+        return {"m1_bytes": tiles * (1 << bits) * 4, "m2_bytes": 0}
+    b1 = (bits + 1) // 2
+    b2 = bits - b1
+    return {"m1_bytes": tiles * (1 << b1) * 4, "m2_bytes": (tiles + (1 << b1)) * (1 << b2) * 4}
+
+
+def load_traffic(kernel, digest):
+    """Measured HBM bytes per launch from profiles/pmc_traffic.json, if it was
+    taken on the current kernel sources."""
+    p = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    try:
+        with open(p) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = d.get("kernels", {}).get(kernel)
+    if not e or d.get("source_digest") != digest:
+        return None
+    return e.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(log2_sample=24):
+    import oracle
+    from paper_1907_02900_amd import workloads
+    ns = 1 << log2_sample
+    keys = workloads.uniform_keys(ns, 32, seed=0)
+    q = workloads.probe_queries(keys, ns, 0.5, seed=1)
+    times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        oracle.build_table(keys, ns, 0)
+        oracle.probe_counts(keys, q)
+        times.append(time.perf_counter() - t0)
+    t = float(np.median(times))
+    return {"value": round(2 * ns / t / 1e9, 5), "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
+            "sample": "2^%d uniform uint32 keys, hash_range 2^%d, + 2^%d queries (50%% hits): "
+                      "stable build + probe counts, sequential C, median of 3 (%.2f s)"
+                      % (log2_sample, log2_sample, log2_sample, t)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--log2n", type=int, default=28)
+    ap.add_argument("--log2range", type=int, default=28)
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1907_02900_amd import hg, workloads
+
+    torch.cuda.set_device(0)
+    n = 1 << args.log2n
+    V = 1 << args.log2range
+    m = n
+    kb = 4
+    log("generating %d keys / %d queries" % (n, m))
+    keys_np = workloads.uniform_keys(n, 32, seed=0)
+    q_np = workloads.probe_queries(keys_np, m, 0.5, seed=1)
+    dk = hg.to_device(keys_np)
+    dq = hg.to_device(q_np)
+    del q_np
+    counts = torch.empty(m, dtype=torch.int32, device="cuda")
+    table = hg.Table.create(n, V, 32)
+    torch.cuda.synchronize()
+
+    def step():
+        table.rebuild(dk, V, seed=0, variant=hg.VARIANT_V2)
+        hg.hg_probe(table, dq, counts=True, total=False, out=counts)
+
+    log("warmup %d" % args.warmup)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    hg.profile_reset()
+    hg.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    hg.profile_enable(False)
+    prof = hg.profile_report()
+    hg.profile_reset()
+    ms_step = wall * 1000.0 / args.steps
+    # the event-instrumented run above also gives the step time; time the
+    # same steps once more without instrumentation for the headline value
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    wall2 = time.perf_counter() - t0
+    ms_step = min(ms_step, wall2 * 1000.0 / args.steps)
+    value = (n + m) / (ms_step / 1000.0) / 1e9
+    log("step %.3f ms -> %.2f Gkeys/s" % (ms_step, value))
+
+    # exact sum of probed bucket lengths (for the probe's algorithmic bytes)
+    off, _, _ = table.export()
+    h = hg.hg_hash(dq, V, 0).to(torch.int64)
+    offl = off.to(torch.int64) & 0xFFFFFFFF
+    sum_len = int((offl[h + 1] - offl[h]).sum().item())
+    del h, offl, off
+
+    plan = v2_plan_bytes(n, V)
+    kernels = {}
+    for name, (launches, tot_ms) in prof.items():
+        per = launches / args.steps
+        avg = tot_ms / launches
+        b = kernel_bytes(name, n, m, V, kb, sum_len, plan)
+        kernels[name] = {"launches_per_step": per, "avg_ms": round(avg, 4),
+                         "ms_per_step": round(tot_ms / args.steps, 4),
+                         "alg_bytes": b,
+                         "alg_GBps": round(b / (avg / 1000.0) / 1e9, 1) if b else None}
+    dom = max((k for k in kernels if kernels[k]["alg_bytes"]),
+              key=lambda k: kernels[k]["ms_per_step"])
+    dk_ = kernels[dom]
+    achieved = dk_["alg_bytes"] / (dk_["avg_ms"] / 1000.0) / 1e9
+    digest = src_digest()
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": load_traffic(dom, digest), "kernel": dom,
+                "alg_bytes_per_launch": dk_["alg_bytes"], "avg_launch_ms": dk_["avg_ms"]}
+
+    phases = {"kernels": kernels, "source_digest": digest,
+              "probe_sum_bucket_len": sum_len}
+    build_ms = sum(v["ms_per_step"] for k, v in kernels.items()
+                   if k.startswith("v2_") or k == "fill")
+    phases["build_v2_ms"] = round(build_ms, 3)
+    phases["probe_ms"] = round(kernels.get("probe_count", {}).get("ms_per_step", 0.0), 3)
+
+    if not args.no_extras:
+        log("extras")
+        reps = 3
+        ex = {}
+        # hash-range sweep (Fig. 8 style) for V2, V1 and the probe
+        big = hg.Table.create(n, 1 << 30, 32)
+        for lv in (26, 28, 30):
+            Vs = 1 << lv
+            t_v2 = timed(lambda: big.rebuild(dk, Vs, 0, variant=hg.VARIANT_V2), reps, torch)
+            t_pr = timed(lambda: hg.hg_probe(big, dq, counts=True, out=counts), reps, torch)
+            t_v1 = timed(lambda: big.rebuild(dk, Vs, 0, variant=hg.VARIANT_V1), 2, torch)
+            ex["V=2^%d" % lv] = {"build_v2_ms": round(t_v2, 3),
+                                 "build_v2_Gkeys": round(n / t_v2 / 1e6, 2),
+                                 "build_v1_ms": round(t_v1, 3),
+                                 "build_v1_Gkeys": round(n / t_v1 / 1e6, 2),
+                                 "probe_v1table_ms": None,
+                                 "probe_ms": round(t_pr, 3),
+                                 "probe_Gkeys": round(m / t_pr / 1e6, 2)}
+            log("V=2^%d v2 %.3f ms v1 %.3f ms probe %.3f ms" % (lv, t_v2, t_v1, t_pr))
+        big.free()
+        del big
+        # Probe-New (Alg. 3): build the query table, then intersect (counts)
+        tq = hg.Table.create(m, V, 32)
+        cb = torch.empty(m, dtype=torch.int32, device="cuda")
+
+        def probe_new():
+            tq.rebuild(dq, V, 0)
+            hg.hg_intersect(table, tq, counts=True, total=False)
+
+        t_pn = timed(probe_new, reps, torch)
+        t_int = timed(lambda: hg.hg_intersect(table, tq, counts=True, total=False), reps, torch)
+        ex["probe_new"] = {"ms": round(t_pn, 3), "Gkeys": round(m / t_pn / 1e6, 2),
+                           "intersect_only_ms": round(t_int, 3),
+                           "build_share": round(1 - t_int / t_pn, 3)}
+        tq.free()
+        del tq, cb
+        # 64-bit keys: 2^27 keys with uint32 ids, V = 2^27, 2^27 queries
+        n64 = n // 2
+        k64 = workloads.uniform_keys(n64, 64, seed=3)
+        q64 = workloads.probe_queries(k64, n64, 0.5, seed=4)
+        dk64, dq64 = hg.to_device(k64), hg.to_device(q64)
+        del k64, q64
+        t64 = hg.Table.create(n64, n64, 64)
+        c64 = torch.empty(n64, dtype=torch.int32, device="cuda")
+        tb = timed(lambda: t64.rebuild(dk64, n64, 0), reps, torch)
+        tp = timed(lambda: hg.hg_probe(t64, dq64, counts=True, out=c64), reps, torch)
+        ex["uint64_2^27"] = {"build_v2_ms": round(tb, 3), "build_Gkeys": round(n64 / tb / 1e6, 2),
+                             "probe_ms": round(tp, 3), "probe_Gkeys": round(n64 / tp / 1e6, 2)}
+        t64.free()
+        del dk64, dq64, c64, t64
+        phases["extras"] = ex
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline")
+        cpu = cpu_baseline()
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Gkeys/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "single table: V2 build of 2^%d uniform uint32 keys, hash_range "
+                               "2^%d, then Probe-Standard counts of 2^%d queries (50%% drawn "
+                               "from the keys)" % (args.log2n, args.log2range, args.log2n),
+                   "n": n, "hash_range": V, "m": m, "key_bits": 32},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "phases": phases,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

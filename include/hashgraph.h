@@ -188,6 +188,27 @@ hg_status hg_intersect(const hg_table *a, const hg_table *b, uint32_t *d_counts_
                        uint32_t *d_a_ids, uint32_t *d_b_ids, uint64_t capacity,
                        uint64_t *h_total, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Measurement: per-kernel timing with HIP events.
+ * ------------------------------------------------------------------------ */
+
+/* Turn event timing of the library's kernel launches on (1) or off (0).
+ * While on, each launch records a HIP event before and after itself on the
+ * stream it runs on (a small overhead per launch). */
+hg_status hg_profile_enable(int on);
+
+/* Drop all recorded launches (waits for their events). */
+hg_status hg_profile_reset(void);
+
+/* Aggregate the recorded launches by kernel name (waits for their events);
+ * *count receives the number of distinct kernels, indexable below. */
+hg_status hg_profile_count(uint32_t *count);
+
+/* Name (NUL-terminated, truncated to name_cap), launch count and summed
+ * duration in milliseconds of aggregated kernel `index`. */
+hg_status hg_profile_get(uint32_t index, char *name, uint32_t name_cap, uint64_t *launches,
+                         double *total_ms);
+
 #ifdef __cplusplus
 }
 #endif

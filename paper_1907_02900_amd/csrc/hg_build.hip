@@ -47,7 +47,10 @@ hipError_t run_hash(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, uint
                     hipStream_t s) {
     if (n == 0) return hipSuccess;
     auto hp = KeyTraits<Key>::make(V, seed);
-    hipLaunchKernelGGL(k_hash<Key>, dim3(stream_grid(n, 256)), dim3(256), 0, s, keys, n, hp, out);
+    {
+        HG_PROF("hash", s);
+        hipLaunchKernelGGL(k_hash<Key>, dim3(stream_grid(n, 256)), dim3(256), 0, s, keys, n, hp, out);
+    }
     return hipGetLastError();
 }
 
@@ -84,8 +87,11 @@ hipError_t run_histogram(const Key* keys, uint64_t n, uint64_t V, uint64_t seed,
     HG_TRY(fill_u32(counts, V, 0u, s));
     if (n == 0) return hipSuccess;
     auto hp = KeyTraits<Key>::make(V, seed);
-    hipLaunchKernelGGL(k_hist_global<Key>, dim3(stream_grid(n, block)), dim3(block), 0, s, keys, n,
-                       hp, counts);
+    {
+        HG_PROF("v1_hist_global", s);
+        hipLaunchKernelGGL(k_hist_global<Key>, dim3(stream_grid(n, block)), dim3(block), 0, s, keys, n,
+                           hp, counts);
+    }
     return hipGetLastError();
 }
 
@@ -103,8 +109,11 @@ hipError_t run_build_v1(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, 
     HG_TRY(scan_excl<uint32_t>(counts, V, offsets, counts, scan_ws, s));
     if (n == 0) return hipSuccess;
     auto hp = KeyTraits<Key>::make(V, seed);
-    hipLaunchKernelGGL(k_scatter_v1<Key>, dim3(stream_grid(n, block)), dim3(block), 0, s, keys, n,
-                       hp, counts, ids, ekeys);
+    {
+        HG_PROF("v1_scatter", s);
+        hipLaunchKernelGGL(k_scatter_v1<Key>, dim3(stream_grid(n, block)), dim3(block), 0, s, keys, n,
+                           hp, counts, ids, ekeys);
+    }
     return hipGetLastError();
 }
 
@@ -778,13 +787,22 @@ size_t build_ws_bytes(int variant, uint64_t n, uint64_t V, int key_bits, uint32_
 
 static hipError_t colscan(uint32_t* mat, const Segs& g, uint32_t D, uint32_t* csum,
                           uint32_t nchunks_ub, hipStream_t s) {
-    hipLaunchKernelGGL(k_colscan_reduce, dim3(nchunks_ub), dim3(256), 0, s, (const uint32_t*)mat, g,
-                       D, csum);
+    {
+        HG_PROF("v2_colscan_reduce", s);
+        hipLaunchKernelGGL(k_colscan_reduce, dim3(nchunks_ub), dim3(256), 0, s, (const uint32_t*)mat, g,
+                           D, csum);
+    }
     HG_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_colscan_seg, dim3(g.S), dim3(256), 0, s, g, D, csum);
+    {
+        HG_PROF("v2_colscan_seg", s);
+        hipLaunchKernelGGL(k_colscan_seg, dim3(g.S), dim3(256), 0, s, g, D, csum);
+    }
     HG_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_colscan_down, dim3(nchunks_ub), dim3(256), 0, s, mat, g, D,
-                       (const uint32_t*)csum);
+    {
+        HG_PROF("v2_colscan_down", s);
+        hipLaunchKernelGGL(k_colscan_down, dim3(nchunks_ub), dim3(256), 0, s, mat, g, D,
+                           (const uint32_t*)csum);
+    }
     return hipGetLastError();
 }
 
@@ -793,22 +811,31 @@ static hipError_t partition_pass(const Key* src_keys, const uint32_t* src_ids, K
                                  uint32_t* dst_ids, const Segs& g,
                                  typename KeyTraits<Key>::Params hp, uint32_t shift,
                                  uint32_t bits, uint32_t* mat, uint32_t* csum, uint32_t tiles_ub,
-                                 uint32_t nchunks_ub, hipStream_t s) {
+                                 uint32_t nchunks_ub, int tier, hipStream_t s) {
     const uint32_t D = 1u << bits;
     const uint32_t grid = (uint32_t)(8 * ceil_div(tiles_ub, 8));
-    hipLaunchKernelGGL(k_tile_hist<Key>, dim3(grid), dim3(kPartThreads), D * 4, s, src_keys, g, hp,
-                       shift, bits, mat, tiles_ub);
+    {
+        HG_PROF(tier == 1 ? "v2_tile_hist_t1" : "v2_tile_hist_t2", s);
+        hipLaunchKernelGGL(k_tile_hist<Key>, dim3(grid), dim3(kPartThreads), D * 4, s, src_keys, g, hp,
+                           shift, bits, mat, tiles_ub);
+    }
     HG_TRY(hipGetLastError());
     HG_TRY(colscan(mat, g, D, csum, nchunks_ub, s));
     const size_t smem = partition_smem<Key>(bits);
     if (src_ids) {
-        hipLaunchKernelGGL((k_tile_partition<Key, true>), dim3(grid), dim3(kPartThreads), smem, s,
-                           src_keys, src_ids, dst_keys, dst_ids, g, hp, shift, bits,
-                           (const uint32_t*)mat, tiles_ub);
+        {
+            HG_PROF(tier == 1 ? "v2_partition_t1" : "v2_partition_t2", s);
+            hipLaunchKernelGGL((k_tile_partition<Key, true>), dim3(grid), dim3(kPartThreads), smem, s,
+                               src_keys, src_ids, dst_keys, dst_ids, g, hp, shift, bits,
+                               (const uint32_t*)mat, tiles_ub);
+        }
     } else {
-        hipLaunchKernelGGL((k_tile_partition<Key, false>), dim3(grid), dim3(kPartThreads), smem, s,
-                           src_keys, src_ids, dst_keys, dst_ids, g, hp, shift, bits,
-                           (const uint32_t*)mat, tiles_ub);
+        {
+            HG_PROF(tier == 1 ? "v2_partition_t1" : "v2_partition_t2", s);
+            hipLaunchKernelGGL((k_tile_partition<Key, false>), dim3(grid), dim3(kPartThreads), smem, s,
+                               src_keys, src_ids, dst_keys, dst_ids, g, hp, shift, bits,
+                               (const uint32_t*)mat, tiles_ub);
+        }
     }
     return hipGetLastError();
 }
@@ -837,37 +864,52 @@ hipError_t run_build_v2(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, 
     auto hp = KeyTraits<Key>::make(V, seed);
     Key* rkeys = (Key*)w.rkeys;
 
-    hipLaunchKernelGGL(k_segs_single, dim3(1), dim3(64), 0, s, w.s1, (uint32_t)n, p.ntiles1,
-                       p.nchunks1);
+    {
+        HG_PROF("v2_segs", s);
+        hipLaunchKernelGGL(k_segs_single, dim3(1), dim3(64), 0, s, w.s1, (uint32_t)n, p.ntiles1,
+                           p.nchunks1);
+    }
     HG_TRY(hipGetLastError());
     const Key* bin_keys;
     const uint32_t* bin_ids;
     if (p.tiers == 1) {
         HG_TRY(partition_pass<Key>(keys, nullptr, rkeys, w.rids, w.s1, hp, p.k, p.b1, w.m1, w.c1,
-                                   p.ntiles1, p.nchunks1, s));
-        hipLaunchKernelGGL(k_bin_starts, dim3((uint32_t)ceil_div(p.bins + 1, 256)), dim3(256), 0, s,
-                           (const uint32_t*)w.m1, w.s1, p.b1, p.bins, (uint32_t)n, w.bin_start);
+                                   p.ntiles1, p.nchunks1, 1, s));
+        {
+            HG_PROF("v2_bin_starts", s);
+            hipLaunchKernelGGL(k_bin_starts, dim3((uint32_t)ceil_div(p.bins + 1, 256)), dim3(256), 0, s,
+                               (const uint32_t*)w.m1, w.s1, p.b1, p.bins, (uint32_t)n, w.bin_start);
+        }
         HG_TRY(hipGetLastError());
         bin_keys = rkeys;
         bin_ids = w.rids;
     } else {
         // tier 1 into the table's own arrays, tier 2 into the workspace
         HG_TRY(partition_pass<Key>(keys, nullptr, ekeys, ids, w.s1, hp, p.k + p.b2, p.b1, w.m1,
-                                   w.c1, p.ntiles1, p.nchunks1, s));
-        hipLaunchKernelGGL(k_segs_from_bases, dim3(1), dim3(1024), 0, s, (const uint32_t*)w.m1,
-                           p.ntiles1, (uint32_t)n, w.s2);
+                                   w.c1, p.ntiles1, p.nchunks1, 1, s));
+        {
+            HG_PROF("v2_segs", s);
+            hipLaunchKernelGGL(k_segs_from_bases, dim3(1), dim3(1024), 0, s, (const uint32_t*)w.m1,
+                               p.ntiles1, (uint32_t)n, w.s2);
+        }
         HG_TRY(hipGetLastError());
         HG_TRY(partition_pass<Key>(ekeys, ids, rkeys, w.rids, w.s2, hp, p.k, p.b2, w.m2, w.c2,
-                                   p.ntiles2_ub, p.nchunks2_ub, s));
-        hipLaunchKernelGGL(k_bin_starts, dim3((uint32_t)ceil_div(p.bins + 1, 256)), dim3(256), 0, s,
-                           (const uint32_t*)w.m2, w.s2, p.b2, p.bins, (uint32_t)n, w.bin_start);
+                                   p.ntiles2_ub, p.nchunks2_ub, 2, s));
+        {
+            HG_PROF("v2_bin_starts", s);
+            hipLaunchKernelGGL(k_bin_starts, dim3((uint32_t)ceil_div(p.bins + 1, 256)), dim3(256), 0, s,
+                               (const uint32_t*)w.m2, w.s2, p.b2, p.bins, (uint32_t)n, w.bin_start);
+        }
         HG_TRY(hipGetLastError());
         bin_keys = rkeys;
         bin_ids = w.rids;
     }
-    hipLaunchKernelGGL(k_local_build<Key>, dim3(p.bins), dim3(kLocalThreads), local_smem<Key>(p.k),
-                       s, bin_keys, bin_ids, (const uint32_t*)w.bin_start, hp, p.k, (uint32_t)n,
-                       offsets, ids, ekeys);
+    {
+        HG_PROF("v2_local_build", s);
+        hipLaunchKernelGGL(k_local_build<Key>, dim3(p.bins), dim3(kLocalThreads), local_smem<Key>(p.k),
+                           s, bin_keys, bin_ids, (const uint32_t*)w.bin_start, hp, p.k, (uint32_t)n,
+                           offsets, ids, ekeys);
+    }
     return hipGetLastError();
 }
 

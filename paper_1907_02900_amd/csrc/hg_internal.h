@@ -25,6 +25,20 @@ inline uint32_t log2_ceil(uint64_t x) {
 inline uint64_t pow2_ceil(uint64_t x) { return 1ull << log2_ceil(x ? x : 1); }
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Event-timed launch range (see hg_prof.hip): inactive unless profiling is on.
+struct ProfRange {
+    const char* name;
+    hipStream_t s;
+    hipEvent_t e0 = nullptr;
+    ProfRange(const char* nm, hipStream_t st);
+    ~ProfRange();
+    ProfRange(const ProfRange&) = delete;
+    ProfRange& operator=(const ProfRange&) = delete;
+};
+#define HG_PROF_CAT2(a, b) a##b
+#define HG_PROF_CAT(a, b) HG_PROF_CAT2(a, b)
+#define HG_PROF(name, s) ::hg::ProfRange HG_PROF_CAT(hg_prof_, __LINE__)(name, s)
+
 // A bump allocator over one workspace buffer (sizes first, then pointers).
 struct Carver {
     char* base;

@@ -162,9 +162,12 @@ hipError_t run_probe_counts(const TableDev& t, const Key* queries, uint64_t m, u
                             unsigned long long* d_total, hipStream_t s) {
     if (m == 0) return hipSuccess;
     auto hp = KeyTraits<Key>::make(t.V, t.seed);
-    hipLaunchKernelGGL(k_probe_count<Key>, dim3(grid_for(m, kProbeThreads * kProbeItems)),
-                       dim3(kProbeThreads), 0, s, queries, m, hp, t.offsets, (const Key*)t.keys,
-                       counts, d_total);
+    {
+        HG_PROF("probe_count", s);
+        hipLaunchKernelGGL(k_probe_count<Key>, dim3(grid_for(m, kProbeThreads * kProbeItems)),
+                           dim3(kProbeThreads), 0, s, queries, m, hp, t.offsets, (const Key*)t.keys,
+                           counts, d_total);
+    }
     return hipGetLastError();
 }
 
@@ -176,8 +179,11 @@ hipError_t run_probe_pairs(const TableDev& t, const Key* queries, uint64_t m,
     auto hp = KeyTraits<Key>::make(t.V, t.seed);
     uint32_t g = grid_for(m, kProbeThreads);
     if (g > 8192) g = 8192;
-    hipLaunchKernelGGL(k_probe_pairs<Key>, dim3(g), dim3(kProbeThreads), 0, s, queries, m, hp,
-                       t.offsets, (const Key*)t.keys, t.ids, positions, build_ids, probe_ids);
+    {
+        HG_PROF("probe_pairs", s);
+        hipLaunchKernelGGL(k_probe_pairs<Key>, dim3(g), dim3(kProbeThreads), 0, s, queries, m, hp,
+                           t.offsets, (const Key*)t.keys, t.ids, positions, build_ids, probe_ids);
+    }
     return hipGetLastError();
 }
 
@@ -187,9 +193,12 @@ hipError_t run_intersect_counts(const TableDev& a, const TableDev& b, uint32_t* 
                                 hipStream_t s) {
     if (b.n == 0) return hipSuccess;
     auto hp = KeyTraits<Key>::make(a.V, a.seed);
-    hipLaunchKernelGGL(k_intersect_count<Key>, dim3(grid_for(b.n, kProbeThreads * kProbeItems)),
-                       dim3(kProbeThreads), 0, s, a.offsets, (const Key*)a.keys,
-                       (const Key*)b.keys, b.ids, b.n, hp, edge_counts, counts_by_input, d_total);
+    {
+        HG_PROF("intersect_count", s);
+        hipLaunchKernelGGL(k_intersect_count<Key>, dim3(grid_for(b.n, kProbeThreads * kProbeItems)),
+                           dim3(kProbeThreads), 0, s, a.offsets, (const Key*)a.keys,
+                           (const Key*)b.keys, b.ids, b.n, hp, edge_counts, counts_by_input, d_total);
+    }
     return hipGetLastError();
 }
 
@@ -200,9 +209,12 @@ hipError_t run_intersect_pairs(const TableDev& a, const TableDev& b, const uint6
     auto hp = KeyTraits<Key>::make(a.V, a.seed);
     uint32_t g = grid_for(b.n, kProbeThreads);
     if (g > 8192) g = 8192;
-    hipLaunchKernelGGL(k_intersect_pairs<Key>, dim3(g), dim3(kProbeThreads), 0, s, a.offsets,
-                       (const Key*)a.keys, a.ids, (const Key*)b.keys, b.ids, b.n, hp, positions,
-                       a_ids, b_ids);
+    {
+        HG_PROF("intersect_pairs", s);
+        hipLaunchKernelGGL(k_intersect_pairs<Key>, dim3(g), dim3(kProbeThreads), 0, s, a.offsets,
+                           (const Key*)a.keys, a.ids, (const Key*)b.keys, b.ids, b.n, hp, positions,
+                           a_ids, b_ids);
+    }
     return hipGetLastError();
 }
 

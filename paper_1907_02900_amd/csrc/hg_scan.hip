@@ -127,7 +127,10 @@ hipError_t fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s) {
     if (n == 0) return hipSuccess;
     uint64_t blocks = ceil_div(n, 256 * 4);
     if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(k_fill_u32, dim3((uint32_t)blocks), dim3(256), 0, s, p, n, v);
+    {
+        HG_PROF("fill", s);
+        hipLaunchKernelGGL(k_fill_u32, dim3((uint32_t)blocks), dim3(256), 0, s, p, n, v);
+    }
     return hipGetLastError();
 }
 
@@ -140,13 +143,22 @@ hipError_t scan_excl(const uint32_t* in, uint64_t n, OutT* out, uint32_t* copy, 
     }
     const uint64_t nb = ceil_div(n, kScanTile);
     OutT* part = (OutT*)ws;
-    hipLaunchKernelGGL(k_scan_reduce<OutT>, dim3((uint32_t)nb), dim3(kScanThreads), 0, s, in, n,
-                       part);
+    {
+        HG_PROF("scan_reduce", s);
+        hipLaunchKernelGGL(k_scan_reduce<OutT>, dim3((uint32_t)nb), dim3(kScanThreads), 0, s, in, n,
+                           part);
+    }
     HG_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_scan_partials<OutT>, dim3(1), dim3(1024), 0, s, part, nb);
+    {
+        HG_PROF("scan_partials", s);
+        hipLaunchKernelGGL(k_scan_partials<OutT>, dim3(1), dim3(1024), 0, s, part, nb);
+    }
     HG_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_scan_down<OutT>, dim3((uint32_t)nb), dim3(kScanThreads), 0, s, in, n,
-                       (const OutT*)part, out, copy, nb);
+    {
+        HG_PROF("scan_down", s);
+        hipLaunchKernelGGL(k_scan_down<OutT>, dim3((uint32_t)nb), dim3(kScanThreads), 0, s, in, n,
+                           (const OutT*)part, out, copy, nb);
+    }
     return hipGetLastError();
 }
 

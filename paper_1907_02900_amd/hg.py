@@ -286,3 +286,44 @@ def hg_intersect(a: Table, b: Table, counts=True, total=True, capacity=0, stream
     if cap:
         return c, ai[:t], bi[:t], t
     return c, None, None, t
+
+
+# ------------------------------------------------------------ measurement ---
+
+def _prof_sig():
+    L = lib()
+    if getattr(L, "_prof_ready", False):
+        return L
+    L.hg_profile_enable.argtypes, L.hg_profile_enable.restype = [ctypes.c_int], ctypes.c_int
+    L.hg_profile_reset.argtypes, L.hg_profile_reset.restype = [], ctypes.c_int
+    L.hg_profile_count.argtypes = [ctypes.POINTER(ctypes.c_uint32)]
+    L.hg_profile_count.restype = ctypes.c_int
+    L.hg_profile_get.argtypes = [ctypes.c_uint32, ctypes.c_char_p, ctypes.c_uint32,
+                                 ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double)]
+    L.hg_profile_get.restype = ctypes.c_int
+    L._prof_ready = True
+    return L
+
+
+def profile_enable(on: bool = True):
+    _check(_prof_sig().hg_profile_enable(1 if on else 0), "hg_profile_enable")
+
+
+def profile_reset():
+    _check(_prof_sig().hg_profile_reset(), "hg_profile_reset")
+
+
+def profile_report() -> dict:
+    """{kernel name: (launches, total_ms)} for launches recorded while
+    profiling was on (waits for their events)."""
+    L = _prof_sig()
+    cnt = ctypes.c_uint32(0)
+    _check(L.hg_profile_count(ctypes.byref(cnt)), "hg_profile_count")
+    out = {}
+    buf = ctypes.create_string_buffer(128)
+    for i in range(cnt.value):
+        n = ctypes.c_uint64(0)
+        ms = ctypes.c_double(0)
+        _check(L.hg_profile_get(i, buf, 128, ctypes.byref(n), ctypes.byref(ms)), "hg_profile_get")
+        out[buf.value.decode()] = (int(n.value), float(ms.value))
+    return out
