@@ -1,11 +1,11 @@
 // Device-side building blocks shared by the HashGraph kernels (gfx950, wave64).
 //
 //  * the hash of Eq. 1: MurmurHash3 finalisers fmix32 / fmix64 followed by an
-//    exact modulo by V done with Lemire's direct-remainder method
-//    (Lemire, Kaser, Kurz, "Faster Remainder by Direct Computation", 2019):
-//    for a < 2^N and d < 2^L, M = ceil(2^F / d) with F >= N + L gives
-//    a mod d = floor(((M * a) mod 2^F) * d / 2^F).  32-bit hashes use F = 64,
-//    64-bit hashes use F = 128.
+//    exact modulo by V.  32-bit hashes divide by the invariant V with a
+//    multiply-high and a shift (Granlund & Montgomery 1994), 64-bit hashes
+//    use Lemire's direct remainder (Lemire, Kaser, Kurz, "Faster Remainder by
+//    Direct Computation", 2019): for a < 2^64 and d < 2^32,
+//    M = ceil(2^128 / d) gives a mod d = floor(((M * a) mod 2^128) * d / 2^128).
 //  * wave64 helpers: lane id, masked popcount below the lane (mbcnt), ballots,
 //    wave and block exclusive scans.
 #pragma once
@@ -17,14 +17,32 @@ namespace hg {
 
 constexpr int kWave = 64;
 
-// Hash parameters for 32-bit keys: h = fmix32(k ^ seed) mod range.
+// Hash parameters for 32-bit keys: h = fmix32(k ^ seed) mod range.  The
+// modulo uses division by an invariant integer (Granlund & Montgomery,
+// "Division by Invariant Integers using Multiplication", 1994): with
+// l = ceil(log2 d) and m = floor(2^(32+l) / d) + 1 (a 33-bit number, stored
+// as magic = m - 2^32), q = floor(a * m / 2^(32+l)) equals floor(a / d) for
+// every 32-bit a, and a mod d = a - q*d.  Two 32-bit multiplies.
 struct HashParams {
     uint64_t seed;   // low 32 bits are XOR-ed into the key
-    uint64_t m_lo;   // Lemire multiplier floor((2^64 - 1) / range) + 1
-    uint64_t m_hi;   // unused (0)
-    uint32_t range;  // V, 1 <= V < 2^32
-    uint32_t pad_;
+    uint32_t range;  // V = d, 1 <= V < 2^32
+    uint32_t magic;  // m - 2^32
+    uint32_t shift;  // l - 1
+    uint32_t is_one; // V == 1: every key goes to bucket 0
 };
+
+__host__ __device__ __forceinline__ uint32_t mulhi32(uint32_t a, uint32_t b) {
+    return (uint32_t)(((uint64_t)a * b) >> 32);
+}
+
+// a mod d for the divisor described by p
+__host__ __device__ __forceinline__ uint32_t mod_u32(uint32_t a, const HashParams& p) {
+    const uint32_t t = mulhi32(a, p.magic);
+    // floor((a + t) / 2^l) without overflowing 32 bits (t <= a)
+    const uint32_t q = (((a - t) >> 1) + t) >> p.shift;
+    const uint32_t r = a - q * p.range;
+    return p.is_one ? 0u : r;
+}
 
 __host__ __device__ __forceinline__ uint32_t fmix32(uint32_t x) {
     x ^= x >> 16;
@@ -48,13 +66,6 @@ __host__ __device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b) {
     return (uint64_t)(((unsigned __int128)a * b) >> 64);
 }
 
-// a mod d for a < 2^32 with M = floor((2^64 - 1) / d) + 1 (M wraps to 0 for
-// d = 1, which correctly yields 0).
-__host__ __device__ __forceinline__ uint32_t fastmod_u32(uint32_t a, uint64_t M, uint32_t d) {
-    uint64_t low = M * a;
-    return (uint32_t)mulhi64(low, d);
-}
-
 // a mod d for a < 2^64 and d < 2^32 with the 128-bit M = floor((2^128-1)/d)+1
 // given as (m_hi, m_lo).
 __host__ __device__ __forceinline__ uint32_t fastmod_u64(uint64_t a, uint64_t m_lo, uint64_t m_hi,
@@ -72,8 +83,15 @@ inline HashParams make_hash_params(uint64_t range, uint64_t seed) {
     HashParams p{};
     p.seed = seed;
     p.range = (uint32_t)range;
-    p.m_lo = ~0ull / (uint32_t)range + 1ull;  // wraps to 0 for range 1
-    p.m_hi = 0;
+    if (range <= 1) {
+        p.is_one = 1;
+        return p;
+    }
+    uint32_t l = 0;
+    while ((1ull << l) < range) ++l;  // l = ceil(log2 d), 1 <= l <= 32
+    const unsigned __int128 m = (((unsigned __int128)1) << (32 + l)) / range + 1;
+    p.magic = (uint32_t)(m - (((unsigned __int128)1) << 32));
+    p.shift = l - 1;
     return p;
 }
 
@@ -105,7 +123,7 @@ struct KeyTraits<uint32_t> {
     using Params = HashParams;
     static inline Params make(uint64_t range, uint64_t seed) { return make_hash_params(range, seed); }
     __host__ __device__ static __forceinline__ uint32_t bucket(uint32_t k, const Params& p) {
-        return fastmod_u32(fmix32(k ^ (uint32_t)p.seed), p.m_lo, p.range);
+        return mod_u32(fmix32(k ^ (uint32_t)p.seed), p);
     }
 };
 

@@ -58,9 +58,11 @@ constexpr int kPartThreads = 256;
 constexpr int kPartItems = 16;
 constexpr uint32_t kPartTile = kPartThreads * kPartItems;  // entries per tile
 constexpr int kLocalThreads = 256;
-constexpr int kLocalItems = 16;
-constexpr uint32_t kLocalCap = kLocalThreads * kLocalItems;  // entries a bin may hold in LDS
-constexpr uint32_t kMaxLocalBits = 12;                       // buckets per bin <= 4096
+constexpr int kLightItems = 12;
+constexpr uint32_t kLightCap = kLocalThreads * kLightItems;  // keys a bin may hold in LDS
+constexpr int kHeavyItems = 16;
+constexpr uint32_t kHeavyChunk = kLocalThreads * kHeavyItems;  // chunk of an oversize bin
+constexpr uint32_t kMaxLocalBits = 12;                          // buckets per bin <= 4096
 constexpr uint32_t kMaxDigitBits = 11;                       // partition fan-out <= 2048
 constexpr uint32_t kOneTierBits = 9;                         // single partition pass up to 512 bins
 

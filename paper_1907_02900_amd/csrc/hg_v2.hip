@@ -1,0 +1,1025 @@
+// HashGraph-V2 (Alg. 2) on gfx950.
+//
+// The paper's idea -- first move keys into bins of contiguous bucket ranges so
+// that the final placement is cache-local -- mapped onto CDNA4 without any
+// global atomics:
+//   * a final bin is a power-of-two range of 2^k buckets holding about 2048
+//     keys on average, so that its keys, ids and bucket counters fit in LDS;
+//   * keys reach their final bin by one or two stable partition passes over a
+//     digit (a bit-field) of the bucket index.  Each pass is: per-tile digit
+//     histograms (LDS), a segmented column scan of the tile x digit matrix
+//     (giving every tile an exact base per digit: deterministic, no atomics),
+//     and a partition kernel that ranks a tile's keys by digit with wave64
+//     ballots and writes digit-contiguous runs;
+//   * one workgroup per final bin counts, scans and stably places the bin's
+//     keys in LDS (two LSD ranking passes over the local bucket index) and
+//     writes the bin's edge segment and offsets with coalesced stores.  Bins
+//     larger than LDS (heavy skew only) are listed on the device and handled
+//     by a second kernel in chunks with running per-bucket cursors.
+// Every pass keeps input order among equal digits, so ids come out ascending
+// inside each bucket: the result is the stable layout, entry for entry.
+//
+// Stable ranking (rank_stable) finds equal digits in a round of 64 items with
+// one ballot per digit bit and keeps per-wave running counts in LDS, updated
+// with non-returning atomics so that rounds do not wait on each other.
+#include "hg_internal.h"
+
+namespace hg {
+
+namespace {
+
+constexpr int W_PART = kPartThreads / kWave;
+constexpr int W_LOCAL = kLocalThreads / kWave;
+constexpr uint32_t kFixMax = 16;  // longest bucket the insertion-sort path handles
+
+// Segments of the source array, each cut into tiles of kPartTile entries, and
+// the tiles grouped into chunks of `ch` consecutive tiles for the column scan.
+struct Segs {
+    uint32_t* seg_start;     // [S+1]
+    uint32_t* tile_prefix;   // [S+1]
+    uint32_t* chunk_prefix;  // [S+1]
+    uint32_t S;
+    uint32_t ch;
+};
+
+// largest s in [0, S) with pre[s] <= x (pre non-decreasing, pre[0] = 0)
+__device__ __forceinline__ uint32_t find_seg(const uint32_t* __restrict__ pre, uint32_t S,
+                                             uint32_t x) {
+    uint32_t lo = 0, hi = S;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (pre[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ bool locate_tile(const Segs& g, uint32_t t, uint32_t& seg,
+                                            uint32_t& begin, uint32_t& end) {
+    if (t >= g.tile_prefix[g.S]) return false;
+    seg = find_seg(g.tile_prefix, g.S, t);
+    begin = g.seg_start[seg] + (t - g.tile_prefix[seg]) * kPartTile;
+    const uint32_t se = g.seg_start[seg + 1];
+    end = (se - begin > kPartTile) ? begin + kPartTile : se;
+    return true;
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs.  Block b gets tile
+// (b % 8) * per + b / 8, so each XCD walks one contiguous range of tiles and
+// the runs that neighbouring tiles write for a digit meet in that XCD's L2.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t ub) {
+    const uint32_t per = (ub + 7) >> 3;
+    return (b & 7u) * per + (b >> 3);
+}
+
+// ------------------------------------------------------------ ranking -----
+
+// Digit-major exclusive scan of the per-wave digit counters wcnt[w][d]
+// (W waves, D digits): afterwards wcnt[w][d] holds the position of wave w's
+// first item of digit d in the stably sorted tile, and dstart[d] the start
+// of digit d.  Barrier on exit.
+template <int THREADS>
+__device__ __forceinline__ void scan_wave_digit_counts(uint32_t D, uint32_t* wcnt,
+                                                       uint32_t* dstart, uint32_t* tmp) {
+    constexpr int W = THREADS / kWave;
+    const uint32_t per = (D + THREADS - 1) / THREADS;
+    const uint32_t d0 = threadIdx.x * per;
+    uint32_t mine = 0;
+    for (uint32_t j = 0; j < per; ++j) {
+        const uint32_t d = d0 + j;
+        if (d < D)
+#pragma unroll
+            for (int w = 0; w < W; ++w) mine += wcnt[w * D + d];
+    }
+    uint32_t all;
+    uint32_t run = block_excl_scan<THREADS>(mine, tmp, &all);
+    for (uint32_t j = 0; j < per; ++j) {
+        const uint32_t d = d0 + j;
+        if (d < D) {
+            dstart[d] = run;
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                const uint32_t v = wcnt[w * D + d];
+                wcnt[w * D + d] = run;
+                run += v;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Stable rank of up to 64*ITEMS items per wave by a digit of `bits` bits
+// (D = 2^bits <= 2048).  Item r of a lane is entry (wave base + r*64 + lane);
+// items with dig >= D are ignored; `rounds` (wave-uniform) bounds the rounds
+// holding valid items.  Per round every lane reads its digit's running count
+// in the wave's counter row and the lowest lane of each group of equal digits
+// adds the group's size with a non-returning LDS atomic.  LDS performs a
+// wave's operations in issue order, so a read sees exactly the items of the
+// wave's earlier rounds, and no round waits for the previous one.  On return
+// pos[r] is the item's index in the tile sorted stably by digit.  Contains
+// barriers.
+template <int THREADS, int ITEMS>
+__device__ __forceinline__ void rank_stable(const uint32_t (&dig)[ITEMS], uint32_t rounds,
+                                            uint32_t bits, uint32_t* wcnt, uint32_t* dstart,
+                                            uint32_t* tmp, uint32_t (&pos)[ITEMS]) {
+    constexpr int W = THREADS / kWave;
+    const uint32_t D = 1u << bits;
+    const uint32_t w = threadIdx.x / kWave;
+    for (uint32_t i = threadIdx.x; i < W * D; i += THREADS) wcnt[i] = 0;
+    __syncthreads();
+    uint32_t* my = wcnt + w * D;
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+        if ((uint32_t)r >= rounds) break;
+        const uint32_t d = dig[r];
+        const bool valid = d < D;
+        const uint64_t peers = match_digit(d, (int)bits, ballot(valid));
+        if (valid) {
+            const uint32_t below = mbcnt(peers);
+            pos[r] = my[d] + below;
+            if (below == 0)
+                __hip_atomic_fetch_add(&my[d], (uint32_t)__popcll(peers), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+    }
+    __syncthreads();
+    scan_wave_digit_counts<THREADS>(D, wcnt, dstart, tmp);
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r)
+        if ((uint32_t)r < rounds && dig[r] < D) pos[r] += my[dig[r]];
+}
+
+// ---------------------------------------------------- tile histograms -----
+
+template <typename Key>
+__global__ __launch_bounds__(kPartThreads) void k_tile_hist(const Key* __restrict__ keys, Segs g,
+                                                            typename KeyTraits<Key>::Params hp,
+                                                            uint32_t shift, uint32_t bits,
+                                                            uint32_t* __restrict__ mat,
+                                                            uint32_t tiles_ub) {
+    extern __shared__ uint32_t cnt[];
+    const uint32_t D = 1u << bits;
+    const uint32_t t = xcd_tile(blockIdx.x, tiles_ub);
+    uint32_t seg, begin, end;
+    if (!locate_tile(g, t, seg, begin, end)) return;
+    for (uint32_t d = threadIdx.x; d < D; d += kPartThreads) cnt[d] = 0;
+    constexpr int IT = kPartItems;
+    Key k[IT];
+#pragma unroll
+    for (int r = 0; r < IT; ++r) {
+        const uint32_t i = begin + r * kPartThreads + threadIdx.x;
+        k[r] = (i < end) ? keys[i] : (Key)0;
+    }
+    __syncthreads();
+    const uint32_t mask = D - 1;
+#pragma unroll
+    for (int r = 0; r < IT; ++r) {
+        const uint32_t i = begin + r * kPartThreads + threadIdx.x;
+        if (i < end) atomicAdd(&cnt[(KeyTraits<Key>::bucket(k[r], hp) >> shift) & mask], 1u);
+    }
+    __syncthreads();
+    uint32_t* row = mat + (size_t)t * D;
+    for (uint32_t d = threadIdx.x; d < D; d += kPartThreads) row[d] = cnt[d];
+}
+
+// ------------------------------------- segmented column scan of [tile][digit]
+// base(t, d) = seg_start[s] + sum_{d' < d} total_s(d') + sum_{t' < t in s} M[t'][d]
+// i.e. the exclusive prefix in (segment, digit, tile) order: where tile t's
+// keys of digit d go in the stably partitioned output.
+
+__device__ __forceinline__ bool locate_chunk(const Segs& g, uint32_t c, uint32_t& seg,
+                                             uint32_t& t0, uint32_t& t1) {
+    if (c >= g.chunk_prefix[g.S]) return false;
+    seg = find_seg(g.chunk_prefix, g.S, c);
+    t0 = g.tile_prefix[seg] + (c - g.chunk_prefix[seg]) * g.ch;
+    const uint32_t te = g.tile_prefix[seg + 1];
+    t1 = (te - t0 > g.ch) ? t0 + g.ch : te;
+    return true;
+}
+
+__global__ __launch_bounds__(256) void k_colscan_reduce(const uint32_t* __restrict__ mat, Segs g,
+                                                        uint32_t D, uint32_t* __restrict__ csum) {
+    uint32_t seg, t0, t1;
+    if (!locate_chunk(g, blockIdx.x, seg, t0, t1)) return;
+    for (uint32_t d = threadIdx.x; d < D; d += 256) {
+        uint32_t s = 0;
+        uint32_t t = t0;
+        for (; t + 8 <= t1; t += 8) {
+            uint32_t v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = mat[(size_t)(t + u) * D + d];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += v[u];
+        }
+        for (; t < t1; ++t) s += mat[(size_t)t * D + d];
+        csum[(size_t)blockIdx.x * D + d] = s;
+    }
+}
+
+// One workgroup per segment: digit totals, their exclusive scan, then each
+// digit walks its chunks turning chunk sums into chunk bases.
+__global__ __launch_bounds__(256) void k_colscan_seg(Segs g, uint32_t D,
+                                                     uint32_t* __restrict__ csum) {
+    __shared__ uint32_t tmp[256 / kWave + 1];
+    const uint32_t s = blockIdx.x;
+    const uint32_t c0 = g.chunk_prefix[s], c1 = g.chunk_prefix[s + 1];
+    if (c0 == c1) return;
+    const uint32_t per = (D + 255) / 256;  // <= 8 (D <= 2048)
+    const uint32_t d0 = threadIdx.x * per;
+    uint32_t tot[8];
+    uint32_t mine = 0;
+    for (uint32_t j = 0; j < per; ++j) {
+        const uint32_t d = d0 + j;
+        uint32_t acc = 0;
+        if (d < D)
+            for (uint32_t c = c0; c < c1; ++c) acc += csum[(size_t)c * D + d];
+        tot[j] = acc;
+        mine += acc;
+    }
+    uint32_t all;
+    uint32_t run = g.seg_start[s] + block_excl_scan<256>(mine, tmp, &all);
+    for (uint32_t j = 0; j < per; ++j) {
+        const uint32_t d = d0 + j;
+        if (d < D) {
+            uint32_t r = run;
+            for (uint32_t c = c0; c < c1; ++c) {
+                const uint32_t v = csum[(size_t)c * D + d];
+                csum[(size_t)c * D + d] = r;
+                r += v;
+            }
+        }
+        run += tot[j];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_colscan_down(uint32_t* __restrict__ mat, Segs g, uint32_t D,
+                                                      const uint32_t* __restrict__ csum) {
+    uint32_t seg, t0, t1;
+    if (!locate_chunk(g, blockIdx.x, seg, t0, t1)) return;
+    for (uint32_t d = threadIdx.x; d < D; d += 256) {
+        uint32_t r = csum[(size_t)blockIdx.x * D + d];
+        uint32_t t = t0;
+        for (; t + 8 <= t1; t += 8) {
+            uint32_t v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = mat[(size_t)(t + u) * D + d];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                mat[(size_t)(t + u) * D + d] = r;
+                r += v[u];
+            }
+        }
+        for (; t < t1; ++t) {
+            const uint32_t v = mat[(size_t)t * D + d];
+            mat[(size_t)t * D + d] = r;
+            r += v;
+        }
+    }
+}
+
+// ------------------------------------------------------------ partition ---
+
+// Stable partition of one tile by a digit of the bucket index.  Writes every
+// entry to base(tile, digit) + its rank among the tile's entries of that
+// digit.
+template <typename Key, bool HAS_IDS>
+__global__ __launch_bounds__(kPartThreads) void k_tile_partition(
+    const Key* __restrict__ src_keys, const uint32_t* __restrict__ src_ids,
+    Key* __restrict__ dst_keys, uint32_t* __restrict__ dst_ids, Segs g,
+    typename KeyTraits<Key>::Params hp, uint32_t shift, uint32_t bits,
+    const uint32_t* __restrict__ base, uint32_t tiles_ub) {
+    constexpr int IT = kPartItems;
+    const uint32_t D = 1u << bits;
+    extern __shared__ __align__(16) unsigned char smem[];
+    Key* skeys = (Key*)smem;
+    uint32_t* sids = (uint32_t*)(skeys + kPartTile);
+    uint16_t* sdig = (uint16_t*)(sids + kPartTile);
+    uint32_t* wcnt = (uint32_t*)(sdig + kPartTile);
+    uint32_t* dstart = wcnt + W_PART * D;
+    uint32_t* tbase = dstart + D;
+    uint32_t* tmp = tbase + D;
+
+    const uint32_t t = xcd_tile(blockIdx.x, tiles_ub);
+    uint32_t seg, begin, end;
+    if (!locate_tile(g, t, seg, begin, end)) return;
+    const uint32_t cnt = end - begin;
+    const uint32_t w = threadIdx.x / kWave, lane = lane_id();
+    const uint32_t mask = D - 1;
+    const uint32_t wbase = w * (kWave * IT);
+    const uint32_t rounds = cnt > wbase ? (cnt - wbase + kWave - 1) / kWave : 0u;
+
+    Key k[IT];
+    uint32_t id[IT], dig[IT], pos[IT];
+#pragma unroll
+    for (int r = 0; r < IT; ++r) {
+        const uint32_t e = wbase + r * kWave + lane;
+        if (e < cnt) {
+            k[r] = src_keys[begin + e];
+            id[r] = HAS_IDS ? src_ids[begin + e] : begin + e;
+        } else {
+            k[r] = 0;
+            id[r] = 0;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < IT; ++r) {
+        const uint32_t e = wbase + r * kWave + lane;
+        dig[r] = (e < cnt) ? ((KeyTraits<Key>::bucket(k[r], hp) >> shift) & mask) : D;
+    }
+    rank_stable<kPartThreads, IT>(dig, rounds < IT ? rounds : IT, bits, wcnt, dstart, tmp, pos);
+    const uint32_t* row = base + (size_t)t * D;
+    for (uint32_t d = threadIdx.x; d < D; d += kPartThreads) tbase[d] = row[d] - dstart[d];
+#pragma unroll
+    for (int r = 0; r < IT; ++r) {
+        if (dig[r] < D) {
+            skeys[pos[r]] = k[r];
+            sids[pos[r]] = id[r];
+            sdig[pos[r]] = (uint16_t)dig[r];
+        }
+    }
+    __syncthreads();
+    // every output lies inside this segment's range; the guard keeps a
+    // corrupted base from turning into a stray store
+    const uint32_t seg_lo = g.seg_start[seg], seg_len = g.seg_start[seg + 1] - seg_lo;
+    for (uint32_t p = threadIdx.x; p < cnt; p += kPartThreads) {
+        const uint32_t o = tbase[sdig[p]] + p;
+        if (o - seg_lo < seg_len) {
+            dst_keys[o] = skeys[p];
+            dst_ids[o] = sids[p];
+        }
+    }
+}
+
+template <typename Key>
+size_t partition_smem(uint32_t bits) {
+    const size_t D = 1u << bits;
+    return kPartTile * (sizeof(Key) + 4 + 2) + W_PART * D * 4 + 2 * D * 4 + (W_PART + 1) * 4 +
+           64;
+}
+
+// -------------------------------------------------------- segment setup ---
+
+// Tier-1 segment: the whole input; also clears the oversize-bin counter.
+__global__ void k_segs_single(Segs g, uint32_t n, uint32_t ntiles, uint32_t nchunks,
+                              uint32_t* heavy_count) {
+    if (threadIdx.x == 0) {
+        g.seg_start[0] = 0;
+        g.seg_start[1] = n;
+        g.tile_prefix[0] = 0;
+        g.tile_prefix[1] = ntiles;
+        g.chunk_prefix[0] = 0;
+        g.chunk_prefix[1] = nchunks;
+        *heavy_count = 0;
+    }
+}
+
+// Tier-2 segments: one per tier-1 digit, from row 0 of the scanned tier-1
+// matrix (the start of every digit's range).  One workgroup; S <= 2048.
+__global__ __launch_bounds__(1024) void k_segs_from_bases(const uint32_t* __restrict__ base1,
+                                                          uint32_t ntiles1, uint32_t n, Segs g) {
+    __shared__ uint32_t tmp[1024 / kWave + 1];
+    const uint32_t S = g.S;
+    const uint32_t per = (S + 1023) / 1024;  // <= 2
+    uint32_t nt[2] = {0, 0}, nc[2] = {0, 0}, st[2] = {0, 0};
+    uint32_t mt = 0, mc = 0;
+    for (uint32_t j = 0; j < per; ++j) {
+        const uint32_t a = threadIdx.x * per + j;
+        if (a < S) {
+            const uint32_t s0 = ntiles1 ? base1[a] : 0u;
+            const uint32_t s1 = (a + 1 < S) ? (ntiles1 ? base1[a + 1] : 0u) : n;
+            st[j] = s0;
+            nt[j] = (s1 - s0 + kPartTile - 1) / kPartTile;
+            nc[j] = (nt[j] + g.ch - 1) / g.ch;
+            mt += nt[j];
+            mc += nc[j];
+        }
+    }
+    uint32_t tt, tc;
+    uint32_t rt = block_excl_scan<1024>(mt, tmp, &tt);
+    uint32_t rc = block_excl_scan<1024>(mc, tmp, &tc);
+    for (uint32_t j = 0; j < per; ++j) {
+        const uint32_t a = threadIdx.x * per + j;
+        if (a < S) {
+            g.seg_start[a] = st[j];
+            g.tile_prefix[a] = rt;
+            g.chunk_prefix[a] = rc;
+            rt += nt[j];
+            rc += nc[j];
+        }
+    }
+    if (threadIdx.x == 0) {
+        g.seg_start[S] = n;
+        g.tile_prefix[S] = tt;
+        g.chunk_prefix[S] = tc;
+    }
+}
+
+// Start of every final bin (bin = segment * 2^bits + digit) in the
+// partitioned array, bin_start[bins] = n, offsets[V] = n, and the list of
+// bins too large for the LDS kernel.
+__global__ void k_bin_starts(const uint32_t* __restrict__ base, Segs g, uint32_t bits,
+                             uint32_t bins, uint32_t n, uint32_t V, uint32_t* __restrict__ bin_start,
+                             uint32_t* __restrict__ offsets, uint32_t* __restrict__ heavy_list,
+                             uint32_t* __restrict__ heavy_count) {
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t st = 0, nx = 0;
+    bool have = false;
+    if (b <= bins) {
+        const uint32_t D = 1u << bits;
+        auto start_of = [&](uint32_t x) -> uint32_t {
+            if (x >= bins) return n;
+            const uint32_t s = x >> bits, d = x & (D - 1);
+            const uint32_t t0 = g.tile_prefix[s];
+            return (g.tile_prefix[s + 1] > t0) ? base[(size_t)t0 * D + d] : g.seg_start[s];
+        };
+        st = start_of(b);
+        bin_start[b] = st;
+        if (b == bins) offsets[V] = n;
+        if (b < bins) {
+            nx = start_of(b + 1);
+            have = nx - st > kLightCap;
+        }
+    }
+    if (have) {
+        const uint32_t slot = atomicAdd(heavy_count, 1u);
+        heavy_list[slot] = b;
+    }
+}
+
+// -------------------------------------------------- per-bin LDS build -----
+
+// Place one chunk of <= ITEMS*64*W entries held in registers: two stable LSD
+// ranking passes over the local bucket index (lo bits, then hi bits) leave
+// the chunk sorted by bucket in skeys/sids/sb.  Items are balanced over the
+// waves: wave w owns entries [w*chunk, (w+1)*chunk).
+template <typename Key, int ITEMS>
+__device__ __forceinline__ void sort_chunk_by_bucket(Key (&kk)[ITEMS], uint32_t (&id)[ITEMS],
+                                                     uint32_t (&b)[ITEMS], uint32_t rounds,
+                                                     uint32_t cl, uint32_t wchunk, uint32_t k,
+                                                     Key* skeys, uint32_t* sids, uint16_t* sb,
+                                                     uint32_t* wcnt, uint32_t* dstart,
+                                                     uint32_t* tmp) {
+    const uint32_t NB = 1u << k;
+    const uint32_t lo_bits = (k + 1) / 2, hi_bits = k / 2;
+    const uint32_t w = threadIdx.x / kWave, lane = lane_id();
+    uint32_t dig[ITEMS], pos[ITEMS];
+    if (k == 0) {
+#pragma unroll
+        for (int r = 0; r < ITEMS; ++r) {
+            const uint32_t e = w * wchunk + r * kWave + lane;
+            if ((uint32_t)r < rounds && r * kWave + lane < wchunk && e < cl) {
+                skeys[e] = kk[r];
+                sids[e] = id[r];
+                sb[e] = 0;
+            }
+        }
+        return;
+    }
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) dig[r] = (b[r] < NB) ? (b[r] & ((1u << lo_bits) - 1)) : 64u;
+    rank_stable<kLocalThreads, ITEMS>(dig, rounds, lo_bits, wcnt, dstart, tmp, pos);
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r)
+        if ((uint32_t)r < rounds && b[r] < NB) {
+            skeys[pos[r]] = kk[r];
+            sids[pos[r]] = id[r];
+            sb[pos[r]] = (uint16_t)b[r];
+        }
+    __syncthreads();
+    if (hi_bits == 0) return;
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+        const uint32_t e = w * wchunk + r * kWave + lane;
+        if ((uint32_t)r < rounds && r * kWave + lane < wchunk && e < cl) {
+            kk[r] = skeys[e];
+            id[r] = sids[e];
+            b[r] = sb[e];
+            dig[r] = b[r] >> lo_bits;
+        } else {
+            b[r] = NB;
+            dig[r] = 64u;
+        }
+    }
+    // rank_stable synchronises before counting, so every wave has finished
+    // reading the buffers before any wave overwrites them below
+    rank_stable<kLocalThreads, ITEMS>(dig, rounds, hi_bits, wcnt, dstart, tmp, pos);
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r)
+        if ((uint32_t)r < rounds && b[r] < NB) {
+            skeys[pos[r]] = kk[r];
+            sids[pos[r]] = id[r];
+            sb[pos[r]] = (uint16_t)b[r];
+        }
+}
+
+// Exclusive scan of cnt[0..NB) in place (NB a power of two); returns via
+// cnt; *total gets the sum.  All threads must call it.
+__device__ __forceinline__ void scan_counts(uint32_t* cnt, uint32_t NB, uint32_t base,
+                                            uint32_t* tmp) {
+    const uint32_t per = NB >= (uint32_t)kLocalThreads ? NB / kLocalThreads : 1u;
+    const uint32_t i0 = threadIdx.x * per;
+    uint32_t v[16];
+    uint32_t mine = 0;
+    for (uint32_t j = 0; j < per; ++j) {
+        v[j] = (i0 + j < NB) ? cnt[i0 + j] : 0u;
+        mine += v[j];
+    }
+    uint32_t all;
+    uint32_t run = base + block_excl_scan<kLocalThreads>(mine, tmp, &all);
+    for (uint32_t j = 0; j < per; ++j)
+        if (i0 + j < NB) {
+            cnt[i0 + j] = run;
+            run += v[j];
+        }
+    __syncthreads();
+}
+
+// Exclusive scan of cnt[0..NB) in place (base 0); returns the largest count.
+// `tmp` needs 2 * (waves per block) words.  All threads must call it.
+__device__ __forceinline__ uint32_t scan_counts_max(uint32_t* cnt, uint32_t NB, uint32_t* tmp) {
+    const uint32_t per = NB >= (uint32_t)kLocalThreads ? NB / kLocalThreads : 1u;
+    const uint32_t i0 = threadIdx.x * per;
+    uint32_t v[16];
+    uint32_t mine = 0, mx = 0;
+    for (uint32_t j = 0; j < per; ++j) {
+        v[j] = (i0 + j < NB) ? cnt[i0 + j] : 0u;
+        mine += v[j];
+        mx = v[j] > mx ? v[j] : mx;
+    }
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) {
+        const uint32_t o = __shfl_xor(mx, d, kWave);
+        mx = o > mx ? o : mx;
+    }
+    uint32_t all;
+    uint32_t run = block_excl_scan<kLocalThreads>(mine, tmp, &all);
+    if (lane_id() == 0) tmp[W_LOCAL + threadIdx.x / kWave] = mx;
+    for (uint32_t j = 0; j < per; ++j)
+        if (i0 + j < NB) {
+            cnt[i0 + j] = run;
+            run += v[j];
+        }
+    __syncthreads();
+    uint32_t m = 0;
+#pragma unroll
+    for (int i = 0; i < W_LOCAL; ++i) m = tmp[W_LOCAL + i] > m ? tmp[W_LOCAL + i] : m;
+    __syncthreads();
+    return m;
+}
+
+// One workgroup per final bin g (buckets [g*2^k, min((g+1)*2^k, V))) that
+// holds at most kLightCap keys.  Usual case (every bucket of the bin holds at
+// most kFixMax keys): LDS counting sort by bucket with atomic cursors, then
+// an insertion sort by id inside each bucket restores input order.  A bin
+// with a longer bucket is sorted by the stable two-pass ranking instead.
+template <typename Key>
+__global__ __launch_bounds__(kLocalThreads) void k_local_light(
+    const Key* __restrict__ src_keys, const uint32_t* __restrict__ src_ids,
+    const uint32_t* __restrict__ bin_start, typename KeyTraits<Key>::Params hp, uint32_t k,
+    uint32_t* __restrict__ offsets, uint32_t* __restrict__ ids, Key* __restrict__ ekeys) {
+    constexpr int IT = kLightItems;
+    const uint32_t NB = 1u << k;
+    extern __shared__ __align__(16) unsigned char smem[];
+    Key* skeys = (Key*)smem;
+    uint32_t* sids = (uint32_t*)(skeys + kLightCap);
+    uint16_t* sb = (uint16_t*)(sids + kLightCap);
+    uint32_t* cnt = (uint32_t*)(sb + kLightCap);  // NB
+    uint32_t* wcnt = cnt + NB;                     // W * 64
+    uint32_t* dstart = wcnt + W_LOCAL * 64;        // 64
+    uint32_t* tmp = dstart + 64;
+
+    const uint32_t g = blockIdx.x;
+    const uint32_t start = bin_start[g], end = bin_start[g + 1];
+    const uint32_t L = end - start;
+    if (L > kLightCap) return;  // oversize bins go to k_local_heavy
+    const uint32_t v0 = g << k;
+    const uint32_t V = hp.range;
+    const uint32_t nb = (V - v0 < NB) ? V - v0 : NB;
+    const uint32_t w = threadIdx.x / kWave, lane = lane_id();
+    // balance the bin over the waves in whole rounds of 64
+    const uint32_t wchunk = (((L + W_LOCAL - 1) / W_LOCAL) + kWave - 1) & ~(uint32_t)(kWave - 1);
+    const uint32_t wb = w * wchunk;
+    const uint32_t mylen = L > wb ? ((L - wb < wchunk) ? L - wb : wchunk) : 0u;
+    const uint32_t rounds = (mylen + kWave - 1) / kWave;
+
+    Key kk[IT];
+    uint32_t id[IT], b[IT];
+#pragma unroll
+    for (int r = 0; r < IT; ++r) {
+        const uint32_t e = wb + r * kWave + lane;
+        if ((uint32_t)r < rounds && r * kWave + lane < mylen) {
+            kk[r] = src_keys[start + e];
+            id[r] = src_ids[start + e];
+        } else {
+            kk[r] = 0;
+            id[r] = 0;
+        }
+    }
+    for (uint32_t i = threadIdx.x; i < NB; i += kLocalThreads) cnt[i] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < IT; ++r) {
+        if ((uint32_t)r < rounds && r * kWave + lane < mylen) {
+            b[r] = KeyTraits<Key>::bucket(kk[r], hp) - v0;
+            atomicAdd(&cnt[b[r]], 1u);
+        } else {
+            b[r] = NB;
+        }
+    }
+    __syncthreads();
+    // bucket starts (in place) and the largest bucket of the bin
+    const uint32_t maxc = scan_counts_max(cnt, NB, tmp);
+    if (maxc <= kFixMax) {
+        // counting-sort placement through per-bucket cursors, then the few
+        // entries of each bucket are put back in id order by insertion sort
+#pragma unroll
+        for (int r = 0; r < IT; ++r) {
+            if (b[r] < NB) {
+                const uint32_t slot = atomicAdd(&cnt[b[r]], 1u);
+                skeys[slot] = kk[r];
+                sids[slot] = id[r];
+            }
+        }
+        __syncthreads();
+        // cnt[v] is now the end of bucket v
+        for (uint32_t v = threadIdx.x; v < NB; v += kLocalThreads) {
+            const uint32_t lo = v ? cnt[v - 1] : 0u, hi = cnt[v];
+            for (uint32_t i = lo + 1; i < hi; ++i) {
+                const uint32_t idv = sids[i];
+                const Key kv = skeys[i];
+                uint32_t j = i;
+                while (j > lo && sids[j - 1] > idv) {
+                    sids[j] = sids[j - 1];
+                    skeys[j] = skeys[j - 1];
+                    --j;
+                }
+                sids[j] = idv;
+                skeys[j] = kv;
+            }
+        }
+        __syncthreads();
+        for (uint32_t v = threadIdx.x; v < nb; v += kLocalThreads)
+            offsets[v0 + v] = start + (v ? cnt[v - 1] : 0u);
+    } else {
+        // a long bucket: stable LSD ranking of the whole bin by local bucket
+        // (the bin arrives in id order from the stable partitions)
+        sort_chunk_by_bucket<Key, IT>(kk, id, b, rounds, L, wchunk, k, skeys, sids, sb, wcnt,
+                                      dstart, tmp);
+        __syncthreads();
+        for (uint32_t v = threadIdx.x; v < nb; v += kLocalThreads) offsets[v0 + v] = start + cnt[v];
+    }
+    for (uint32_t p = threadIdx.x; p < L; p += kLocalThreads) {
+        ekeys[start + p] = skeys[p];
+        ids[start + p] = sids[p];
+    }
+}
+
+// Oversize bins (from the device list): one workgroup per bin, the bin's
+// keys counted per bucket first, then placed chunk by chunk (in order) with
+// running per-bucket cursors, so placement stays stable.
+template <typename Key>
+__global__ __launch_bounds__(kLocalThreads) void k_local_heavy(
+    const Key* __restrict__ src_keys, const uint32_t* __restrict__ src_ids,
+    const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ heavy_list,
+    const uint32_t* __restrict__ heavy_count, typename KeyTraits<Key>::Params hp, uint32_t k,
+    uint32_t* __restrict__ offsets, uint32_t* __restrict__ ids, Key* __restrict__ ekeys) {
+    constexpr int IT = kHeavyItems;
+    constexpr uint32_t CAP = kHeavyChunk;
+    const uint32_t NB = 1u << k;
+    extern __shared__ __align__(16) unsigned char smem[];
+    Key* skeys = (Key*)smem;
+    uint32_t* sids = (uint32_t*)(skeys + CAP);
+    uint16_t* sb = (uint16_t*)(sids + CAP);
+    uint32_t* cur = (uint32_t*)(sb + CAP);  // NB: running cursors
+    uint32_t* tcnt = cur + NB;              // NB: chunk-local bucket starts
+    uint32_t* wcnt = tcnt + NB;
+    uint32_t* dstart = wcnt + W_LOCAL * 64;
+    uint32_t* tmp = dstart + 64;
+    const uint32_t V = hp.range;
+    const uint32_t w = threadIdx.x / kWave, lane = lane_id();
+    const uint32_t nheavy = *heavy_count;
+
+    for (uint32_t hi = blockIdx.x; hi < nheavy; hi += gridDim.x) {
+        const uint32_t g = heavy_list[hi];
+        const uint32_t start = bin_start[g], end = bin_start[g + 1];
+        const uint32_t L = end - start;
+        const uint32_t v0 = g << k;
+        const uint32_t nb = (V - v0 < NB) ? V - v0 : NB;
+        for (uint32_t i = threadIdx.x; i < NB; i += kLocalThreads) cur[i] = 0;
+        __syncthreads();
+        for (uint32_t i = start + threadIdx.x; i < end; i += kLocalThreads)
+            atomicAdd(&cur[KeyTraits<Key>::bucket(src_keys[i], hp) - v0], 1u);
+        __syncthreads();
+        scan_counts(cur, NB, start, tmp);
+        for (uint32_t i = threadIdx.x; i < nb; i += kLocalThreads) offsets[v0 + i] = cur[i];
+        const uint32_t nchunk = (uint32_t)(((uint64_t)L + CAP - 1) / CAP);
+        for (uint32_t ci = 0; ci < nchunk; ++ci) {
+            const uint32_t c0 = ci * CAP;
+            const uint32_t cl = (L - c0 < CAP) ? L - c0 : CAP;
+            const uint32_t wchunk =
+                (((cl + W_LOCAL - 1) / W_LOCAL) + kWave - 1) & ~(uint32_t)(kWave - 1);
+            const uint32_t wb = w * wchunk;
+            const uint32_t mylen = cl > wb ? ((cl - wb < wchunk) ? cl - wb : wchunk) : 0u;
+            const uint32_t rounds = (mylen + kWave - 1) / kWave;
+            Key kk[IT];
+            uint32_t id[IT], b[IT];
+#pragma unroll
+            for (int r = 0; r < IT; ++r) {
+                const uint32_t e = wb + r * kWave + lane;
+                if ((uint32_t)r < rounds && r * kWave + lane < mylen) {
+                    kk[r] = src_keys[start + c0 + e];
+                    id[r] = src_ids[start + c0 + e];
+                } else {
+                    kk[r] = 0;
+                    id[r] = 0;
+                }
+            }
+            for (uint32_t i = threadIdx.x; i < NB; i += kLocalThreads) tcnt[i] = 0;
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < IT; ++r) {
+                if ((uint32_t)r < rounds && r * kWave + lane < mylen) {
+                    b[r] = KeyTraits<Key>::bucket(kk[r], hp) - v0;
+                    atomicAdd(&tcnt[b[r]], 1u);
+                } else {
+                    b[r] = NB;
+                }
+            }
+            sort_chunk_by_bucket<Key, IT>(kk, id, b, rounds, cl, wchunk, k, skeys, sids, sb, wcnt,
+                                          dstart, tmp);
+            __syncthreads();
+            // chunk-local bucket starts: exclusive scan of tcnt, keeping the
+            // counts to advance the cursors afterwards
+            scan_counts(tcnt, NB, 0u, tmp);
+            for (uint32_t p = threadIdx.x; p < cl; p += kLocalThreads) {
+                const uint32_t bb = sb[p];
+                const uint32_t o = cur[bb] + (p - tcnt[bb]);
+                if (o - start < L) {
+                    ekeys[o] = skeys[p];
+                    ids[o] = sids[p];
+                }
+            }
+            __syncthreads();
+            for (uint32_t i = threadIdx.x; i < NB; i += kLocalThreads) {
+                const uint32_t nxt = (i + 1 < NB) ? tcnt[i + 1] : cl;
+                cur[i] += nxt - tcnt[i];
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <typename Key>
+size_t light_smem(uint32_t k) {
+    const size_t NB = 1u << k;
+    return kLightCap * (sizeof(Key) + 4 + 2) + NB * 4 + W_LOCAL * 64 * 4 + 64 * 4 +
+           (W_LOCAL + 1) * 4 + 64;
+}
+
+template <typename Key>
+size_t heavy_smem(uint32_t k) {
+    const size_t NB = 1u << k;
+    return kHeavyChunk * (sizeof(Key) + 4 + 2) + 2 * NB * 4 + W_LOCAL * 64 * 4 + 64 * 4 +
+           (W_LOCAL + 1) * 4 + 64;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ plan --
+
+V2Plan plan_v2(uint64_t n, uint64_t V, int key_bits, uint32_t bins_hint) {
+    (void)key_bits;
+    V2Plan p;
+    p.n = n;
+    p.V = V;
+    uint32_t k;
+    if (bins_hint) {
+        k = log2_ceil(ceil_div(V, bins_hint));
+    } else if (n == 0) {
+        k = kMaxLocalBits;
+    } else {
+        // about 2048 keys per final bin: 2^k * n / V ~ 2048
+        const double r = 2048.0 * (double)V / (double)n;
+        k = 0;
+        while (k < kMaxLocalBits && (double)(1ull << (k + 1)) <= r) ++k;
+    }
+    if (k > kMaxLocalBits) k = kMaxLocalBits;
+    const uint32_t kv = log2_ceil(V);
+    if (k > kv) k = kv;
+    p.k = k;
+    p.bins = (uint32_t)ceil_div(V, 1ull << k);
+    const uint32_t bits = log2_ceil(p.bins);
+    if (bits <= kOneTierBits) {
+        p.tiers = 1;
+        p.b1 = bits;
+        p.b2 = 0;
+    } else {
+        p.tiers = 2;
+        p.b2 = bits / 2;
+        p.b1 = bits - p.b2;
+    }
+    p.ntiles1 = (uint32_t)ceil_div(n, kPartTile);
+    p.ch1 = (uint32_t)pow2_ceil(ceil_div(p.ntiles1 ? p.ntiles1 : 1, 256));
+    p.nchunks1 = (uint32_t)ceil_div(p.ntiles1, p.ch1);
+    if (p.tiers == 2) {
+        const uint32_t S = 1u << p.b1;
+        p.ntiles2_ub = p.ntiles1 + S;
+        p.ch2 = (uint32_t)pow2_ceil(ceil_div(p.ntiles1 ? p.ntiles1 : 1, (uint64_t)S * 4));
+        p.nchunks2_ub = (uint32_t)ceil_div(p.ntiles2_ub, p.ch2) + S;
+    }
+    return p;
+}
+
+namespace {
+
+struct V2Ws {
+    void* rkeys;
+    uint32_t* rids;
+    uint32_t *m1, *c1, *m2, *c2, *bin_start, *heavy_list, *heavy_count;
+    Segs s1, s2;
+};
+
+// One layout used both to size the workspace (base == nullptr) and to carve it.
+size_t layout_v2(void* ws, const V2Plan& p, size_t key_size, V2Ws* out) {
+    Carver c(ws);
+    V2Ws w{};
+    w.rkeys = c.take<char>(p.n * key_size);
+    w.rids = c.take<uint32_t>(p.n);
+    const uint32_t D1 = 1u << p.b1, D2 = 1u << p.b2;
+    w.m1 = c.take<uint32_t>((size_t)p.ntiles1 * D1);
+    w.c1 = c.take<uint32_t>((size_t)p.nchunks1 * D1);
+    w.s1.seg_start = c.take<uint32_t>(2);
+    w.s1.tile_prefix = c.take<uint32_t>(2);
+    w.s1.chunk_prefix = c.take<uint32_t>(2);
+    w.s1.S = 1;
+    w.s1.ch = p.ch1;
+    if (p.tiers == 2) {
+        w.m2 = c.take<uint32_t>((size_t)p.ntiles2_ub * D2);
+        w.c2 = c.take<uint32_t>((size_t)p.nchunks2_ub * D2);
+        w.s2.seg_start = c.take<uint32_t>(D1 + 1);
+        w.s2.tile_prefix = c.take<uint32_t>(D1 + 1);
+        w.s2.chunk_prefix = c.take<uint32_t>(D1 + 1);
+        w.s2.S = D1;
+        w.s2.ch = p.ch2;
+    }
+    w.bin_start = c.take<uint32_t>((size_t)p.bins + 1);
+    w.heavy_list = c.take<uint32_t>((size_t)p.bins);
+    w.heavy_count = c.take<uint32_t>(1);
+    if (out) *out = w;
+    return c.off + 256;
+}
+
+hipError_t colscan(uint32_t* mat, const Segs& g, uint32_t D, uint32_t* csum, uint32_t nchunks_ub,
+                   hipStream_t s) {
+    {
+        HG_PROF("v2_colscan_reduce", s);
+        hipLaunchKernelGGL(k_colscan_reduce, dim3(nchunks_ub), dim3(256), 0, s,
+                           (const uint32_t*)mat, g, D, csum);
+    }
+    HG_TRY(hipGetLastError());
+    {
+        HG_PROF("v2_colscan_seg", s);
+        hipLaunchKernelGGL(k_colscan_seg, dim3(g.S), dim3(256), 0, s, g, D, csum);
+    }
+    HG_TRY(hipGetLastError());
+    {
+        HG_PROF("v2_colscan_down", s);
+        hipLaunchKernelGGL(k_colscan_down, dim3(nchunks_ub), dim3(256), 0, s, mat, g, D,
+                           (const uint32_t*)csum);
+    }
+    return hipGetLastError();
+}
+
+template <typename Key>
+hipError_t partition_pass(const Key* src_keys, const uint32_t* src_ids, Key* dst_keys,
+                          uint32_t* dst_ids, const Segs& g, typename KeyTraits<Key>::Params hp,
+                          uint32_t shift, uint32_t bits, uint32_t* mat, uint32_t* csum,
+                          uint32_t tiles_ub, uint32_t nchunks_ub, int tier, hipStream_t s) {
+    const uint32_t D = 1u << bits;
+    const uint32_t grid = (uint32_t)(8 * ceil_div(tiles_ub, 8));
+    {
+        HG_PROF(tier == 1 ? "v2_tile_hist_t1" : "v2_tile_hist_t2", s);
+        hipLaunchKernelGGL(k_tile_hist<Key>, dim3(grid), dim3(kPartThreads), D * 4, s, src_keys,
+                           g, hp, shift, bits, mat, tiles_ub);
+    }
+    HG_TRY(hipGetLastError());
+    HG_TRY(colscan(mat, g, D, csum, nchunks_ub, s));
+    const size_t smem = partition_smem<Key>(bits);
+    {
+        HG_PROF(tier == 1 ? "v2_partition_t1" : "v2_partition_t2", s);
+        if (src_ids)
+            hipLaunchKernelGGL((k_tile_partition<Key, true>), dim3(grid), dim3(kPartThreads), smem,
+                               s, src_keys, src_ids, dst_keys, dst_ids, g, hp, shift, bits, mat,
+                               tiles_ub);
+        else
+            hipLaunchKernelGGL((k_tile_partition<Key, false>), dim3(grid), dim3(kPartThreads), smem,
+                               s, src_keys, src_ids, dst_keys, dst_ids, g, hp, shift, bits, mat,
+                               tiles_ub);
+    }
+    return hipGetLastError();
+}
+
+template <typename Key>
+hipError_t set_smem_limits() {
+    static bool done = false;
+    if (done) return hipSuccess;
+    const int lim = 160 * 1024;
+    HG_TRY(hipFuncSetAttribute((const void*)k_tile_partition<Key, true>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+    HG_TRY(hipFuncSetAttribute((const void*)k_tile_partition<Key, false>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+    HG_TRY(hipFuncSetAttribute((const void*)k_local_light<Key>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+    HG_TRY(hipFuncSetAttribute((const void*)k_local_heavy<Key>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+    done = true;
+    return hipSuccess;
+}
+
+}  // namespace
+
+size_t build_ws_bytes(int variant, uint64_t n, uint64_t V, int key_bits, uint32_t bins_hint) {
+    const size_t ks = key_bits == 64 ? 8 : 4;
+    if (variant == 1) {
+        Carver c(nullptr);
+        c.take<uint32_t>(V);
+        c.take<char>(scan_ws_bytes(V));
+        return c.off + 256;
+    }
+    return layout_v2(nullptr, plan_v2(n, V, key_bits, bins_hint), ks, nullptr);
+}
+
+template <typename Key>
+hipError_t run_build_v2(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, uint32_t* offsets,
+                        uint32_t* ids, Key* ekeys, void* ws, uint32_t bins_hint, hipStream_t s) {
+    HG_TRY(set_smem_limits<Key>());
+    if (n == 0) return fill_u32(offsets, V + 1, 0u, s);
+    const V2Plan p = plan_v2(n, V, sizeof(Key) * 8, bins_hint);
+    V2Ws w;
+    layout_v2(ws, p, sizeof(Key), &w);
+    auto hp = KeyTraits<Key>::make(V, seed);
+    Key* rkeys = (Key*)w.rkeys;
+    {
+        HG_PROF("v2_segs", s);
+        hipLaunchKernelGGL(k_segs_single, dim3(1), dim3(64), 0, s, w.s1, (uint32_t)n, p.ntiles1,
+                           p.nchunks1, w.heavy_count);
+    }
+    HG_TRY(hipGetLastError());
+    const uint32_t* bin_mat;
+    Segs bin_segs;
+    uint32_t bin_bits;
+    if (p.tiers == 1) {
+        HG_TRY(partition_pass<Key>(keys, nullptr, rkeys, w.rids, w.s1, hp, p.k, p.b1, w.m1, w.c1,
+                                   p.ntiles1, p.nchunks1, 1, s));
+        bin_mat = w.m1;
+        bin_segs = w.s1;
+        bin_bits = p.b1;
+    } else {
+        // tier 1 into the table's own arrays, tier 2 into the workspace
+        HG_TRY(partition_pass<Key>(keys, nullptr, ekeys, ids, w.s1, hp, p.k + p.b2, p.b1, w.m1,
+                                   w.c1, p.ntiles1, p.nchunks1, 1, s));
+        {
+            HG_PROF("v2_segs", s);
+            hipLaunchKernelGGL(k_segs_from_bases, dim3(1), dim3(1024), 0, s,
+                               (const uint32_t*)w.m1, p.ntiles1, (uint32_t)n, w.s2);
+        }
+        HG_TRY(hipGetLastError());
+        HG_TRY(partition_pass<Key>(ekeys, ids, rkeys, w.rids, w.s2, hp, p.k, p.b2, w.m2, w.c2,
+                                   p.ntiles2_ub, p.nchunks2_ub, 2, s));
+        bin_mat = w.m2;
+        bin_segs = w.s2;
+        bin_bits = p.b2;
+    }
+    {
+        HG_PROF("v2_bin_starts", s);
+        hipLaunchKernelGGL(k_bin_starts, dim3((uint32_t)ceil_div(p.bins + 1, 256)), dim3(256), 0,
+                           s, bin_mat, bin_segs, bin_bits, p.bins, (uint32_t)n, (uint32_t)V,
+                           w.bin_start, offsets, w.heavy_list, w.heavy_count);
+    }
+    HG_TRY(hipGetLastError());
+    {
+        HG_PROF("v2_local_build", s);
+        hipLaunchKernelGGL(k_local_light<Key>, dim3(p.bins), dim3(kLocalThreads),
+                           light_smem<Key>(p.k), s, (const Key*)rkeys, (const uint32_t*)w.rids,
+                           (const uint32_t*)w.bin_start, hp, p.k, offsets, ids, ekeys);
+    }
+    HG_TRY(hipGetLastError());
+    {
+        HG_PROF("v2_local_heavy", s);
+        const uint32_t hg_grid = p.bins < 512 ? p.bins : 512;
+        hipLaunchKernelGGL(k_local_heavy<Key>, dim3(hg_grid), dim3(kLocalThreads),
+                           heavy_smem<Key>(p.k), s, (const Key*)rkeys, (const uint32_t*)w.rids,
+                           (const uint32_t*)w.bin_start, (const uint32_t*)w.heavy_list,
+                           (const uint32_t*)w.heavy_count, hp, p.k, offsets, ids, ekeys);
+    }
+    return hipGetLastError();
+}
+
+template hipError_t run_build_v2<uint32_t>(const uint32_t*, uint64_t, uint64_t, uint64_t,
+                                           uint32_t*, uint32_t*, uint32_t*, void*, uint32_t,
+                                           hipStream_t);
+template hipError_t run_build_v2<uint64_t>(const uint64_t*, uint64_t, uint64_t, uint64_t,
+                                           uint32_t*, uint32_t*, uint64_t*, void*, uint32_t,
+                                           hipStream_t);
+
+}  // namespace hg

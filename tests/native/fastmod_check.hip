@@ -1,4 +1,5 @@
-// Host-side check of the kernels' exact modulo (Lemire direct remainder) and
+// Host-side check of the kernels' exact modulo (invariant-divisor magic for
+// 32-bit hashes, Lemire direct remainder for 64-bit hashes) and
 // bucket function against the C++ '%' operator.  Built and run by
 // tests/test_fastmod.py; exits non-zero on the first mismatch.
 #include <cstdio>
@@ -12,7 +13,7 @@
 using namespace hg;
 
 static bool exhaustive_u32(uint32_t d) {
-    const uint64_t M = make_hash_params(d, 0).m_lo;
+    const HashParams P = make_hash_params(d, 0);
     const int T = 8;
     std::vector<int> bad(T, 0);
     std::vector<std::thread> th;
@@ -20,7 +21,7 @@ static bool exhaustive_u32(uint32_t d) {
         th.emplace_back([&, t] {
             const uint64_t lo = (1ull << 32) / T * t, hi = (1ull << 32) / T * (t + 1);
             for (uint64_t a = lo; a < hi; ++a)
-                if (fastmod_u32((uint32_t)a, M, d) != (uint32_t)(a % d)) {
+                if (mod_u32((uint32_t)a, P) != (uint32_t)(a % d)) {
                     bad[t] = 1;
                     return;
                 }
@@ -32,7 +33,7 @@ static bool exhaustive_u32(uint32_t d) {
 }
 
 int main() {
-    const uint32_t full[] = {1u, 3u, 10u, 1000003u, (1u << 31) - 1, 4294967291u};
+    const uint32_t full[] = {1u, 2u, 3u, 10u, 1000003u, (1u << 20), (1u << 31) - 1, 1u << 31, 4294967291u, 0xffffffffu};
     for (uint32_t d : full) {
         if (!exhaustive_u32(d)) {
             printf("FAIL u32 exhaustive d=%u\n", d);
@@ -49,7 +50,7 @@ int main() {
         const HashParams64 q = make_hash_params64(d, 0);
         for (int i = 0; i < 200000; ++i) {
             const uint32_t a = (uint32_t)rng();
-            if (fastmod_u32(a, p.m_lo, d) != a % d) {
+            if (mod_u32(a, p) != a % d) {
                 printf("FAIL u32 d=%u a=%u\n", d, a);
                 return 1;
             }
