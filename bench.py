@@ -112,6 +112,154 @@ def load_traffic(kernel, digest):
     return e.get("hbm_bytes_per_launch")
 
 
+def run_batched(hg, workloads, torch, tables=4096, reps=5, log=print):
+    """4096 tables, sizes floor(2^U), U ~ U[8, 20], V = n, m = n queries with
+    50% hits: one graph launch per run vs a per-table loop of hg_table_build
+    + hg_probe into preallocated tables."""
+    sizes = workloads.batched_sizes(tables, 8.0, 20.0, seed=7)
+    keys, qs = [], []
+    for i, n in enumerate(sizes):
+        k = workloads.uniform_keys(int(n), 32, seed=10_000 + i)
+        keys.append(hg.to_device(k))
+        qs.append(hg.to_device(workloads.probe_queries(k, int(n), 0.5, seed=20_000 + i)))
+    tot = int(sizes.sum()) * 2
+    t0 = time.perf_counter()
+    b = hg.Batch([{"keys": keys[i], "queries": qs[i], "hash_range": int(sizes[i]),
+                   "seed": i} for i in range(tables)], key_bits=32, autotune=True)
+    torch.cuda.synchronize()
+    create_s = time.perf_counter() - t0
+    t_graph = timed(b.run, reps, torch)
+    # per-table loop of the plain entry points, tables preallocated
+    loop_tabs = [hg.Table.create(int(n), int(n), 32) for n in sizes]
+    outs = [t["counts"] for t in b.tables]
+
+    def loop():
+        for i in range(tables):
+            loop_tabs[i].rebuild(keys[i], int(sizes[i]), seed=i)
+            hg.hg_probe(loop_tabs[i], qs[i], counts=True, out=outs[i])
+
+    t_loop = timed(loop, 2, torch)
+    info = b.info()
+    for t in loop_tabs:
+        t.free()
+    b.free()
+    log("batched: graph %.3f ms, loop %.3f ms" % (t_graph, t_loop))
+    return {"tables": tables, "keys_plus_queries": tot, "graph_ms": round(t_graph, 3),
+            "graph_Gkeys": round(tot / t_graph / 1e6, 2), "loop_ms": round(t_loop, 3),
+            "loop_Gkeys": round(tot / t_loop / 1e6, 2), "speedup": round(t_loop / t_graph, 2),
+            "bin_target": info["bin_target"], "plan_create_s": round(create_s, 2)}
+
+
+def run_serving(hg, workloads, torch, requests=600, log=print):
+    """Poisson stream, 30% builds (n log-uniform in [2^10, 2^24]) and 70%
+    probes (m log-uniform in [2^10, 2^22]) against resident tables, 64 GB
+    budget; the arrival rate is swept up to saturation.  Keys come from one
+    device pool of uniform keys; a probe takes half its queries from its
+    table's key range (hits) and half from elsewhere."""
+    pool_n = 1 << 26
+    pool = hg.to_device(workloads.uniform_keys(pool_n, 32, seed=99))
+    qpool = hg.to_device(workloads.uniform_keys(pool_n, 32, seed=98))
+    counts = torch.empty(1 << 22, dtype=torch.int32, device="cuda")
+    rng = np.random.default_rng(5)
+
+    def build_slice(n):
+        o = int(rng.integers(0, pool_n - n))
+        return pool[o:o + n], o
+
+    out = {"rates": []}
+    srv = hg.Server(budget_bytes=64 << 30, streams=4, max_inflight=16)
+    tables = []
+    for _ in range(64):  # warm-up: resident tables
+        n = int(np.exp2(rng.uniform(10, 24)))
+        k, o = build_slice(n)
+        tid, _ = srv.submit_build(k, n, seed=len(tables))
+        tables.append((tid, o, n))
+    srv.drain()
+
+    def one_run(rate, nreq, seed):
+        arr, isb, size, _ = workloads.serving_stream(nreq, rate, seed=seed)
+        # every input is made (and finished) before the clock starts: probe
+        # queries, half from the target table's keys and half from elsewhere,
+        # each probe with its own output slice
+        plan = []
+        mtot = int(sum(int(s) for b_, s in zip(isb, size) if not b_))
+        outc = torch.empty(max(mtot, 1), dtype=torch.int32, device="cuda")
+        mo = 0
+        for b_, s in zip(isb, size):
+            s = int(s)
+            if b_:
+                plan.append(("b",) + build_slice(s) + (s,))
+            else:
+                tid, o, n = tables[int(rng.integers(0, 64))]
+                half = min(s // 2, n)
+                q = torch.cat([pool[o:o + half], qpool[:s - half]])
+                plan.append(("p", tid, q, outc[mo:mo + s]))
+                mo += s
+        torch.cuda.synchronize()
+        srv.reset_stats()
+        t0 = time.perf_counter()
+        for a, item in zip(arr, plan):
+            while time.perf_counter() - t0 < a:
+                pass
+            if item[0] == "b":
+                _, k, o, s = item
+                tid, _ = srv.submit_build(k, s, seed=s)
+                tables.append((tid, o, s))
+            else:
+                _, tid, q, c = item
+                srv.submit_probe(tid, q, c)
+        srv.drain()
+        st = srv.stats()
+        return {"rate_per_s": rate, "requests": nreq, "p50_ms": round(st["p50_ms"], 3),
+                "p99_ms": round(st["p99_ms"], 3), "Gkeys": round(st["keys"] / max(st["busy_s"], 1e-9) / 1e9, 2),
+                "merged_requests": st["merged_requests"], "launches": st["launches"],
+                "evictions": st["evictions"], "failed": st["failed"]}
+
+    for rate in (200.0, 1000.0, 4000.0, 1e6):
+        r = one_run(rate, requests, seed=int(rate) % 1000 + 1)
+        out["rates"].append(r)
+        log("serving rate %g: p50 %.3f ms p99 %.3f ms %.2f Gkeys/s" % (rate, r["p50_ms"],
+                                                                        r["p99_ms"], r["Gkeys"]))
+    srv.close()
+    # the same saturated stream as a sequential loop of the plain calls
+    arr, isb, size, _ = workloads.serving_stream(requests, 1e6, seed=1)
+    plan, tabs = [], []
+    for b_, s in zip(isb, size):
+        s = int(s)
+        if b_ or not plan:
+            plan.append(("b",) + build_slice(s) + (s,))
+        else:
+            j = int(rng.integers(0, len([p for p in plan if p[0] == "b"])))
+            plan.append(("p", j, min(s, 1 << 22)))
+    builds = [p for p in plan if p[0] == "b"]
+    queries = {}
+    for i, p in enumerate(plan):
+        if p[0] == "p":
+            _, k, o, n = builds[p[1]]
+            s = p[2]
+            half = min(s // 2, n)
+            queries[i] = torch.cat([pool[o:o + half], qpool[:s - half]])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    keys_done = 0
+    for i, p in enumerate(plan):
+        if p[0] == "b":
+            _, k, o, s = p
+            tabs.append(hg.hg_build(k, s, seed=s))
+            keys_done += s
+        else:
+            t = tabs[min(p[1], len(tabs) - 1)]
+            q = queries[i]
+            hg.hg_probe(t, q, counts=True, out=counts[:max(q.numel(), 1)])
+            keys_done += q.numel()
+    torch.cuda.synchronize()
+    t_loop = time.perf_counter() - t0
+    out["loop_Gkeys"] = round(keys_done / t_loop / 1e9, 2)
+    for t in tabs:
+        t.free()
+    return out
+
+
 def cpu_baseline(log2_sample=24):
     import oracle
     from paper_1907_02900_amd import workloads
@@ -140,7 +288,22 @@ def main():
     ap.add_argument("--log2range", type=int, default=28)
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--tables", type=int, default=4096)
+    ap.add_argument("--requests", type=int, default=600)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 1 GiB device-to-device (reference for HBM counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 1 << 30, "launches": 3}))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -281,6 +444,13 @@ def main():
         t64.free()
         del dk64, dq64, c64, t64
         phases["extras"] = ex
+
+    if not args.no_batched:
+        log("batched")
+        phases["batched"] = run_batched(hg, workloads, torch, tables=args.tables, log=log)
+    if not args.no_serving:
+        log("serving")
+        phases["serving"] = run_serving(hg, workloads, torch, requests=args.requests, log=log)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -65,7 +65,14 @@ typedef struct hg_build_opts {
                           a bin spans a power-of-two range of buckets; 0 =
                           choose from N and V.                                 */
     uint32_t block;    /* V1: threads per block, 0 = 256                        */
-    uint32_t reserved[4];
+    int32_t no_index;  /* V2 also writes a probe index beside the CSR arrays:
+                          one 16-byte entry per bucket holding its start, its
+                          end and its first keys (two 32-bit keys, or one
+                          64-bit key), so a probe of a short bucket takes one
+                          random read.  1 = skip it (probes then read offsets
+                          and the edge array).  Results are identical either
+                          way.  V1 never writes it.                           */
+    uint32_t reserved[3];
 } hg_build_opts;
 
 typedef struct hg_table hg_table; /* opaque; device-resident */
@@ -187,6 +194,141 @@ hg_status hg_probe_pairs(const hg_table *t, const void *d_queries, uint64_t m,
 hg_status hg_intersect(const hg_table *a, const hg_table *b, uint32_t *d_counts_b,
                        uint32_t *d_a_ids, uint32_t *d_b_ids, uint64_t capacity,
                        uint64_t *h_total, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Batched build + probe: many independent tables in one hipGraph launch.
+ * Each table is built exactly as hg_build builds it with the V2 variant (the
+ * stable layout of Alg. 2) into the caller's output arrays, then probed as
+ * hg_probe probes it.  Intended for thousands of small and medium tables.
+ * ------------------------------------------------------------------------ */
+
+typedef struct hg_batch_item {
+    const void *d_keys;    /* n keys of the batch's key width                   */
+    uint64_t n;            /* < 2^32                                            */
+    uint64_t hash_range;   /* V in [1, 2^32 - 1]                                */
+    uint64_t seed;         /* hash seed                                         */
+    const void *d_queries; /* m queries (may be NULL when m == 0)               */
+    uint64_t m;            /* < 2^32                                            */
+    uint32_t *d_offsets;   /* out: V+1 CSR offsets                              */
+    uint32_t *d_ids;       /* out: n input indices, bucketed                    */
+    void *d_ekeys;         /* out: n keys, bucketed                             */
+    uint32_t *d_counts;    /* out: m per-query match counts (NULL when m == 0)  */
+} hg_batch_item;
+
+typedef struct hg_batch_opts {
+    uint32_t autotune;   /* 1: time candidate bin sizes on this batch and keep
+                            the fastest (default when opts is NULL); 0: use
+                            bin_target or 2048 keys per bin                     */
+    uint32_t bin_target; /* keys per final bin of the partitioned tables; 0 =
+                            autotune / default                                  */
+    uint32_t reserved[6];
+} hg_batch_opts;
+
+typedef struct hg_batch hg_batch; /* opaque plan: device descriptors, workspace
+                                     and the captured graph */
+
+/* Plan a batch of `count` tables (host array of descriptors; every pointer in
+ * it is a device pointer).  Uploads descriptors, allocates the shared
+ * workspace, autotunes (which runs the batch a few times on the device, so
+ * the output buffers are written) and captures the run into a hipGraph.  The
+ * plan keeps the pointers: the caller's buffers must stay allocated until
+ * hg_batch_free; their contents may change between runs.  Waits for the
+ * device.  Tables with a hash range above 2^23 (2048 bins of 4096 buckets;
+ * about 2^23 keys at load 1) are rejected with HG_ERR_INVALID_ARG: build those with
+ * hg_build. */
+hg_status hg_batch_create(const hg_batch_item *items, uint32_t count, int key_bits,
+                          const hg_batch_opts *opts, hg_batch **out);
+
+/* Build and probe every table of the batch: one graph launch on `stream`. */
+hg_status hg_batch_run(hg_batch *b, hipStream_t stream);
+
+/* The chosen keys-per-bin target and the workspace the plan holds. */
+hg_status hg_batch_info(const hg_batch *b, uint32_t *bin_target, uint64_t *workspace_bytes);
+
+/* Release a plan (waits for the device).  NULL is a no-op. */
+void hg_batch_free(hg_batch *b);
+
+/* ------------------------------------------------------------------------
+ * Serving: a request loop with continuous batching.
+ * Build and probe requests are queued and return at once; a host thread in
+ * the library admits them onto several HIP streams as launch slots and
+ * memory allow, so the work of different requests overlaps on the device.
+ * Small requests pending at the same time are merged into one launch of the
+ * batched kernels.  Tables stay resident on the device under a byte budget
+ * (resident tables plus in-flight workspace); when a request does not fit,
+ * the least recently used tables that no pending or running request needs
+ * are evicted.  Results are the same as hg_build (V2) / hg_probe give.
+ * Latency is measured from submission to the moment the loop observes the
+ * request's completion (resolution about 20 microseconds).
+ * ------------------------------------------------------------------------ */
+
+typedef struct hg_server hg_server;
+
+typedef struct hg_server_opts {
+    uint64_t budget_bytes; /* device bytes for resident tables + in-flight work;
+                              0 = 64 GiB                                       */
+    uint32_t streams;      /* HIP streams, default priority; 0 = 4 (max 16)    */
+    uint32_t max_inflight; /* launches in flight at once; 0 = 8 (max 256)      */
+    uint32_t merge_max;    /* most requests merged into one launch; 0 = 64,
+                              1 = never merge                                  */
+    uint32_t merge_keys;   /* requests of at most this many keys or queries
+                              may be merged; 0 = 65536                         */
+    uint32_t reserved[4];
+} hg_server_opts;
+
+typedef struct hg_server_stats {
+    uint64_t completed, failed, rejected, evictions;
+    uint64_t launches;        /* device launches issued                        */
+    uint64_t merged_requests; /* requests that ran inside merged launches      */
+    uint64_t keys;            /* keys + queries of completed requests          */
+    double p50_ms, p99_ms, mean_ms, max_ms; /* submission -> completion         */
+    double busy_s;            /* first submission -> last completion           */
+    uint64_t resident_bytes, peak_bytes;
+    uint32_t resident_tables;
+    uint32_t reserved;
+} hg_server_stats;
+
+/* Start a server on the current device (opts may be NULL). */
+hg_status hg_server_create(const hg_server_opts *opts, hg_server **out);
+
+/* Queue a build of n keys (device pointer, must stay valid until the request
+ * completes).  *table_id names the table for later probes; *request_id (may
+ * be NULL) can be waited on.  A table larger than the whole budget fails with
+ * HG_ERR_BUDGET (reported by hg_server_wait). */
+hg_status hg_server_submit_build(hg_server *s, const void *d_keys, uint64_t n, int key_bits,
+                                 uint64_t hash_range, uint64_t seed, uint64_t *table_id,
+                                 uint64_t *request_id);
+
+/* Queue a probe of m queries against a table; per-query counts go to
+ * d_counts (device, m uint32).  The table is pinned against eviction from
+ * now until this probe completes.  HG_ERR_NOT_FOUND if the table is unknown,
+ * was evicted or failed to build. */
+hg_status hg_server_submit_probe(hg_server *s, uint64_t table_id, const void *d_queries,
+                                 uint64_t m, uint32_t *d_counts, uint64_t *request_id);
+
+/* Block until a request has completed; *result (may be NULL) receives its
+ * status. */
+hg_status hg_server_wait(hg_server *s, uint64_t request_id, hg_status *result);
+
+/* Block until every submitted request has completed. */
+hg_status hg_server_drain(hg_server *s);
+
+/* The CSR arrays of a resident, built table (device pointers owned by the
+ * server, valid until the table is evicted or the server destroyed). */
+hg_status hg_server_table(hg_server *s, uint64_t table_id, hg_table_info *info);
+
+/* Copy a resident, built table's CSR arrays into caller buffers (device to
+ * device on `stream`; any pointer may be NULL).  HG_ERR_NOT_FOUND if the
+ * table is not resident.  The copy is ordered after the table's build and
+ * the call waits for it. */
+hg_status hg_server_export(hg_server *s, uint64_t table_id, uint32_t *d_offsets, uint32_t *d_ids,
+                           void *d_keys, hipStream_t stream);
+
+hg_status hg_server_stats_get(hg_server *s, hg_server_stats *out);
+hg_status hg_server_reset_stats(hg_server *s);
+
+/* Finish all queued work, free every table and stop the loop. */
+void hg_server_destroy(hg_server *s);
 
 /* ------------------------------------------------------------------------
  * Measurement: per-kernel timing with HIP events.

@@ -18,6 +18,8 @@ struct hg_table {
     uint32_t* offsets = nullptr;
     uint32_t* ids = nullptr;
     void* keys = nullptr;
+    uint4* head = nullptr;  // V_cap per-bucket probe index entries
+    bool has_head = false;  // the last build wrote head
     void* ws = nullptr;  // workspace kept for rebuilds (hg_table_create only)
     size_t ws_bytes = 0;
     uint64_t bytes = 0;
@@ -79,6 +81,7 @@ hg_status build_into(hg_table* t, const void* keys, uint64_t n, uint64_t V, uint
     if (stable && variant == HG_VARIANT_V1) return HG_ERR_INVALID_ARG;
     const uint32_t bins = opts ? opts->bins : 0;
     const uint32_t block = opts ? opts->block : 0;
+    const bool want_head = variant == HG_VARIANT_V2 && !(opts && opts->no_index);
     if (block && (block % 64 || block > 1024)) return HG_ERR_INVALID_ARG;
     if (bins && bins > V) return HG_ERR_INVALID_ARG;
 
@@ -95,19 +98,22 @@ hg_status build_into(hg_table* t, const void* keys, uint64_t n, uint64_t V, uint
                 ? run_build_v1<uint32_t>((const uint32_t*)keys, n, V, seed, t->offsets, t->ids,
                                          (uint32_t*)t->keys, ws, block, s)
                 : run_build_v2<uint32_t>((const uint32_t*)keys, n, V, seed, t->offsets, t->ids,
-                                         (uint32_t*)t->keys, ws, bins, s);
+                                         (uint32_t*)t->keys, want_head ? t->head : nullptr, ws,
+                                         bins, s);
     } else {
         e = variant == HG_VARIANT_V1
                 ? run_build_v1<uint64_t>((const uint64_t*)keys, n, V, seed, t->offsets, t->ids,
                                          (uint64_t*)t->keys, ws, block, s)
                 : run_build_v2<uint64_t>((const uint64_t*)keys, n, V, seed, t->offsets, t->ids,
-                                         (uint64_t*)t->keys, ws, bins, s);
+                                         (uint64_t*)t->keys, want_head ? t->head : nullptr, ws,
+                                         bins, s);
     }
     if (e != hipSuccess) return from_hip(e);
     t->n = n;
     t->V = V;
     t->seed = seed;
     t->variant = variant;
+    t->has_head = want_head;
     return HG_OK;
 }
 
@@ -120,7 +126,8 @@ hg_status alloc_table(uint64_t n_cap, uint64_t V_cap, int kb, bool with_ws, hg_t
     hipError_t e = hipMalloc((void**)&t->offsets, (V_cap + 1) * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc((void**)&t->ids, (n_cap ? n_cap : 1) * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc(&t->keys, (n_cap ? n_cap : 1) * key_size(kb));
-    t->bytes = (V_cap + 1) * 4 + (n_cap ? n_cap : 1) * (4 + key_size(kb));
+    if (e == hipSuccess) e = hipMalloc((void**)&t->head, V_cap * sizeof(uint4));
+    t->bytes = (V_cap + 1) * 4 + V_cap * sizeof(uint4) + (n_cap ? n_cap : 1) * (4 + key_size(kb));
     if (e == hipSuccess && with_ws) {
         size_t w1 = build_ws_bytes(1, n_cap, V_cap, kb, 0);
         size_t w2 = build_ws_bytes(2, n_cap, V_cap, kb, 0);
@@ -146,6 +153,7 @@ TableDev dev_view(const hg_table* t) {
     d.n = t->n;
     d.V = t->V;
     d.seed = t->seed;
+    d.head = t->has_head ? t->head : nullptr;
     return d;
 }
 
@@ -270,6 +278,7 @@ void hg_table_free(hg_table* t) {
     if (t->offsets) (void)hipFree(t->offsets);
     if (t->ids) (void)hipFree(t->ids);
     if (t->keys) (void)hipFree(t->keys);
+    if (t->head) (void)hipFree(t->head);
     if (t->ws) (void)hipFree(t->ws);
     delete t;
 }

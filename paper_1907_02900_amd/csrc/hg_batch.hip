@@ -1,0 +1,1418 @@
+// Batched HashGraph build + probe: many independent tables of uneven size in
+// one hipGraph launch.
+//
+// Every table is built exactly as hg_build's V2 path builds it (same stable
+// layout) and probed as hg_probe does; what changes is the launch structure.
+// The work items of all tables -- partition tiles, final bins and probe
+// tiles -- are numbered in one global index space per kernel, with per-table
+// descriptors on the device and prefix arrays that a workgroup searches to
+// find its table.  Tables small enough to be a single bin that fits in LDS
+// (n <= 3072 here) skip the partition entirely: their bin is built straight
+// from the caller's keys.  Larger tables take one stable partition pass into
+// a shared workspace, then the per-bin LDS build.  The six kernels of a run
+// (clear, tile histograms, per-table column scan, partition, per-bin build,
+// oversize bins, probe) are captured once into a hipGraph; a run is a single
+// graph launch.  The bin-size target (keys per final bin, which sets the
+// partition fan-out and the LDS footprint) is chosen by timing candidate
+// graphs on the actual batch.
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <tuple>
+#include <vector>
+
+#include "hashgraph.h"
+#include "hg_v2_device.h"
+
+namespace hg {
+
+namespace {
+
+using namespace v2dev;
+
+constexpr int kBProbeThreads = 256;
+constexpr int kBProbeItems = 4;
+constexpr uint32_t kBProbeTile = kBProbeThreads * kBProbeItems;
+
+enum : uint32_t { kDirect = 0, kPartitioned = 1, kEmpty = 2 };
+
+template <typename Key>
+struct BTable {
+    const Key* keys;
+    const Key* queries;
+    uint32_t* offsets;
+    uint32_t* ids;
+    Key* ekeys;
+    uint32_t* counts;
+    typename KeyTraits<Key>::Params hp;
+    uint32_t n, m, V;
+    uint32_t kind;      // kDirect / kPartitioned / kEmpty
+    uint32_t k;         // log2 buckets per bin
+    uint32_t b1;        // partition digit bits (kPartitioned)
+    uint32_t bins;      // final bins
+    uint32_t ntiles;    // partition tiles (kPartitioned)
+    uint32_t mat_base;  // first matrix entry
+    uint32_t key_base;  // first slot in the shared partition workspace
+};
+
+struct BPrefix {
+    const uint32_t* tile;   // [T+1] first partition tile of each table
+    const uint32_t* bin;    // [T+1] first final bin
+    const uint32_t* qtile;  // [T+1] first probe tile
+    uint32_t T;
+};
+
+__device__ __forceinline__ uint32_t find_table(const uint32_t* __restrict__ pre, uint32_t T,
+                                               uint32_t x) {
+    uint32_t lo = 0, hi = T;  // largest i with pre[i] <= x
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (pre[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint32_t xcd_map(uint32_t b, uint32_t ub) {
+    const uint32_t per = (ub + 7) >> 3;
+    return (b & 7u) * per + (b >> 3);
+}
+
+__global__ void k_bclear(uint32_t* heavy_count) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *heavy_count = 0;
+}
+
+template <typename Key>
+__global__ __launch_bounds__(kPartThreads) void k_bhist(const BTable<Key>* __restrict__ tabs,
+                                                        BPrefix pre, uint32_t tiles,
+                                                        uint32_t* __restrict__ mat) {
+    extern __shared__ uint32_t cnt[];
+    const uint32_t t = xcd_map(blockIdx.x, tiles);
+    if (t >= tiles) return;
+    const uint32_t i = find_table(pre.tile, pre.T, t);
+    const BTable<Key>& tb = tabs[i];
+    const uint32_t lt = t - pre.tile[i];
+    const uint32_t D = 1u << tb.b1;
+    const uint32_t begin = lt * kPartTile;
+    const uint32_t end = (tb.n - begin > kPartTile) ? begin + kPartTile : tb.n;
+    for (uint32_t d = threadIdx.x; d < D; d += kPartThreads) cnt[d] = 0;
+    constexpr int IT = kPartItems;
+    Key k[IT];
+#pragma unroll
+    for (int r = 0; r < IT; ++r) {
+        const uint32_t x = begin + r * kPartThreads + threadIdx.x;
+        k[r] = (x < end) ? tb.keys[x] : (Key)0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < IT; ++r) {
+        const uint32_t x = begin + r * kPartThreads + threadIdx.x;
+        if (x < end) atomicAdd(&cnt[(KeyTraits<Key>::bucket(k[r], tb.hp) >> tb.k) & (D - 1)], 1u);
+    }
+    __syncthreads();
+    uint32_t* row = mat + tb.mat_base + (size_t)lt * D;
+    for (uint32_t d = threadIdx.x; d < D; d += kPartThreads) row[d] = cnt[d];
+}
+
+// One workgroup per table: turn its [tile][digit] counts into absolute bases
+// key_base + (keys of smaller digits) + (keys of this digit in earlier tiles).
+template <typename Key>
+__global__ __launch_bounds__(256) void k_bcolscan(const BTable<Key>* __restrict__ tabs,
+                                                  uint32_t* __restrict__ mat) {
+    __shared__ uint32_t tmp[256 / kWave + 1];
+    const BTable<Key>& tb = tabs[blockIdx.x];
+    if (tb.kind != kPartitioned) return;
+    const uint32_t D = 1u << tb.b1, nt = tb.ntiles;
+    uint32_t* m = mat + tb.mat_base;
+    const uint32_t per = (D + 255) / 256;  // <= 8
+    const uint32_t d0 = threadIdx.x * per;
+    uint32_t tot[8];
+    uint32_t mine = 0;
+    for (uint32_t j = 0; j < per; ++j) {
+        const uint32_t d = d0 + j;
+        uint32_t acc = 0;
+        if (d < D)
+            for (uint32_t t = 0; t < nt; ++t) acc += m[(size_t)t * D + d];
+        tot[j] = acc;
+        mine += acc;
+    }
+    uint32_t all;
+    uint32_t run = tb.key_base + block_excl_scan<256>(mine, tmp, &all);
+    for (uint32_t j = 0; j < per; ++j) {
+        const uint32_t d = d0 + j;
+        if (d < D) {
+            uint32_t r = run;
+            for (uint32_t t = 0; t < nt; ++t) {
+                const uint32_t v = m[(size_t)t * D + d];
+                m[(size_t)t * D + d] = r;
+                r += v;
+            }
+        }
+        run += tot[j];
+    }
+}
+
+template <typename Key>
+__global__ __launch_bounds__(kPartThreads) void k_bpart(const BTable<Key>* __restrict__ tabs,
+                                                        BPrefix pre, uint32_t tiles,
+                                                        const uint32_t* __restrict__ mat,
+                                                        Key* __restrict__ rkeys,
+                                                        uint32_t* __restrict__ rids) {
+    constexpr int IT = kPartItems;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint32_t t = xcd_map(blockIdx.x, tiles);
+    if (t >= tiles) return;
+    const uint32_t i = find_table(pre.tile, pre.T, t);
+    const BTable<Key>& tb = tabs[i];
+    const uint32_t lt = t - pre.tile[i];
+    const uint32_t bits = tb.b1, D = 1u << bits;
+    Key* skeys = (Key*)smem;
+    uint32_t* sids = (uint32_t*)(skeys + kPartTile);
+    uint16_t* sdig = (uint16_t*)(sids + kPartTile);
+    uint32_t* wcnt = (uint32_t*)(sdig + kPartTile);
+    uint32_t* dstart = wcnt + W_PART * D;
+    uint32_t* tbase = dstart + D;
+    uint32_t* tmp = tbase + D;
+    const uint32_t begin = lt * kPartTile;
+    const uint32_t cnt = (tb.n - begin > kPartTile) ? kPartTile : tb.n - begin;
+    const uint32_t w = threadIdx.x / kWave, lane = lane_id();
+    const uint32_t wbase = w * (kWave * IT);
+    const uint32_t rounds = cnt > wbase ? (cnt - wbase + kWave - 1) / kWave : 0u;
+    Key k[IT];
+    uint32_t dig[IT], pos[IT];
+#pragma unroll
+    for (int r = 0; r < IT; ++r) {
+        const uint32_t e = wbase + r * kWave + lane;
+        k[r] = (e < cnt) ? tb.keys[begin + e] : (Key)0;
+    }
+#pragma unroll
+    for (int r = 0; r < IT; ++r) {
+        const uint32_t e = wbase + r * kWave + lane;
+        dig[r] = (e < cnt) ? ((KeyTraits<Key>::bucket(k[r], tb.hp) >> tb.k) & (D - 1)) : D;
+    }
+    rank_stable<kPartThreads, IT>(dig, rounds < IT ? rounds : IT, bits, wcnt, dstart, tmp, pos);
+    const uint32_t* row = mat + tb.mat_base + (size_t)lt * D;
+    for (uint32_t d = threadIdx.x; d < D; d += kPartThreads) tbase[d] = row[d] - dstart[d];
+#pragma unroll
+    for (int r = 0; r < IT; ++r) {
+        if (dig[r] < D) {
+            const uint32_t e = wbase + r * kWave + lane;
+            skeys[pos[r]] = k[r];
+            sids[pos[r]] = begin + e;
+            sdig[pos[r]] = (uint16_t)dig[r];
+        }
+    }
+    __syncthreads();
+    const uint32_t lo = tb.key_base, len = tb.n;
+    for (uint32_t p = threadIdx.x; p < cnt; p += kPartThreads) {
+        const uint32_t o = tbase[sdig[p]] + p;
+        if (o - lo < len) {
+            rkeys[o] = skeys[p];
+            rids[o] = sids[p];
+        }
+    }
+}
+
+// Source range of global bin gb: table, local bin and [start, end) in the
+// workspace (partitioned tables) or in the table's own keys (direct tables).
+template <typename Key>
+__device__ __forceinline__ void bin_range(const BTable<Key>* __restrict__ tabs, const BPrefix& pre,
+                                          const uint32_t* __restrict__ mat, uint32_t gb,
+                                          uint32_t& i, uint32_t& lb, uint32_t& start,
+                                          uint32_t& end) {
+    i = find_table(pre.bin, pre.T, gb);
+    const BTable<Key>& tb = tabs[i];
+    lb = gb - pre.bin[i];
+    if (tb.kind == kPartitioned) {
+        const uint32_t* row0 = mat + tb.mat_base;
+        start = row0[lb];
+        end = (lb + 1 < tb.bins) ? row0[lb + 1] : tb.key_base + tb.n;
+    } else {
+        start = 0;
+        end = tb.kind == kDirect ? tb.n : 0u;
+    }
+}
+
+template <typename Key>
+__global__ __launch_bounds__(kLocalThreads) void k_blocal(
+    const BTable<Key>* __restrict__ tabs, BPrefix pre, uint32_t bins,
+    const uint32_t* __restrict__ mat, const Key* __restrict__ rkeys,
+    const uint32_t* __restrict__ rids, uint32_t* __restrict__ heavy_list,
+    uint32_t* __restrict__ heavy_count) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint32_t gb = blockIdx.x;
+    if (gb >= bins) return;
+    uint32_t i, lb, start, end;
+    bin_range<Key>(tabs, pre, mat, gb, i, lb, start, end);
+    const BTable<Key>& tb = tabs[i];
+    const uint32_t L = end - start;
+    if (lb + 1 == tb.bins && threadIdx.x == 0) tb.offsets[tb.V] = tb.n;
+    if (L > kLightCap) {
+        if (threadIdx.x == 0) heavy_list[atomicAdd(heavy_count, 1u)] = gb;
+        return;
+    }
+    const uint32_t NB = 1u << tb.k, v0 = lb << tb.k;
+    const uint32_t nb = (tb.V - v0 < NB) ? tb.V - v0 : NB;
+    if (tb.kind == kPartitioned)
+        light_bin_body<Key>(rkeys + start, rids + start, 0u, L, start - tb.key_base, v0, tb.k, nb,
+                            tb.hp, tb.offsets, nullptr, tb.ids, tb.ekeys, smem);
+    else
+        light_bin_body<Key>(tb.keys, nullptr, 0u, L, 0u, v0, tb.k, nb, tb.hp, tb.offsets, nullptr,
+                            tb.ids, tb.ekeys, smem);
+}
+
+template <typename Key>
+__global__ __launch_bounds__(kLocalThreads) void k_bheavy(
+    const BTable<Key>* __restrict__ tabs, BPrefix pre, const uint32_t* __restrict__ mat,
+    const Key* __restrict__ rkeys, const uint32_t* __restrict__ rids,
+    const uint32_t* __restrict__ heavy_list, const uint32_t* __restrict__ heavy_count) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint32_t nheavy = *heavy_count;
+    for (uint32_t h = blockIdx.x; h < nheavy; h += gridDim.x) {
+        uint32_t i, lb, start, end;
+        bin_range<Key>(tabs, pre, mat, heavy_list[h], i, lb, start, end);
+        const BTable<Key>& tb = tabs[i];
+        const uint32_t NB = 1u << tb.k, v0 = lb << tb.k;
+        const uint32_t nb = (tb.V - v0 < NB) ? tb.V - v0 : NB;
+        if (tb.kind == kPartitioned)
+            heavy_bin_body<Key>(rkeys + start, rids + start, 0u, end - start, start - tb.key_base,
+                                v0, tb.k, nb, tb.hp, tb.offsets, nullptr, tb.ids, tb.ekeys, smem);
+        else
+            heavy_bin_body<Key>(tb.keys, nullptr, 0u, end - start, 0u, v0, tb.k, nb, tb.hp,
+                                tb.offsets, nullptr, tb.ids, tb.ekeys, smem);
+        __syncthreads();
+    }
+}
+
+template <typename Key>
+__global__ __launch_bounds__(kBProbeThreads) void k_bprobe(const BTable<Key>* __restrict__ tabs,
+                                                           BPrefix pre, uint32_t qtiles) {
+    const uint32_t qt = blockIdx.x;
+    if (qt >= qtiles) return;
+    const uint32_t i = find_table(pre.qtile, pre.T, qt);
+    const BTable<Key>& tb = tabs[i];
+    const uint32_t base = (qt - pre.qtile[i]) * kBProbeTile + threadIdx.x;
+    Key q[kBProbeItems];
+    uint32_t lo[kBProbeItems], hi[kBProbeItems];
+#pragma unroll
+    for (int r = 0; r < kBProbeItems; ++r) {
+        const uint32_t j = base + r * kBProbeThreads;
+        q[r] = (j < tb.m) ? tb.queries[j] : (Key)0;
+    }
+#pragma unroll
+    for (int r = 0; r < kBProbeItems; ++r) {
+        const uint32_t j = base + r * kBProbeThreads;
+        if (j < tb.m) {
+            const uint32_t h = KeyTraits<Key>::bucket(q[r], tb.hp);
+            lo[r] = tb.offsets[h];
+            hi[r] = tb.offsets[h + 1];
+        } else {
+            lo[r] = hi[r] = 0;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < kBProbeItems; ++r) {
+        const uint32_t j = base + r * kBProbeThreads;
+        uint32_t c = 0;
+        for (uint32_t p = lo[r]; p < hi[r]; ++p) c += (tb.ekeys[p] == q[r]) ? 1u : 0u;
+        if (j < tb.m) tb.counts[j] = c;
+    }
+}
+
+size_t part_smem_bytes(size_t key_size, uint32_t bits) {
+    const size_t D = 1u << bits;
+    return kPartTile * (key_size + 4 + 2) + W_PART * D * 4 + 2 * D * 4 + (W_PART + 1) * 4 + 64;
+}
+
+uint32_t pick_k(uint64_t n, uint64_t V, uint32_t target) {
+    if (n == 0) return kMaxLocalBits;
+    const double r = (double)target * (double)V / (double)n;
+    uint32_t k = 0;
+    while (k < kMaxLocalBits && (double)(1ull << (k + 1)) <= r) ++k;
+    const uint32_t kv = log2_ceil(V);
+    return k > kv ? kv : k;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------- plan ---
+
+struct BatchPlanBase {
+    virtual ~BatchPlanBase() {}
+};
+
+template <typename Key>
+struct BatchPlan : BatchPlanBase {
+    uint32_t T = 0;
+    uint32_t target = 2048;
+    uint32_t tiles = 0, bins = 0, qtiles = 0;
+    uint32_t max_b1 = 0, max_k = 0;
+    uint64_t mat_entries = 0, ws_keys = 0;
+    bool build = true;  // false: probe existing tables only
+    std::vector<BTable<Key>> host;
+    std::vector<uint32_t> tile_pre, bin_pre, qtile_pre;
+    // device memory (one block, owned or lent by the caller)
+    void* d_block = nullptr;
+    bool owns_block = false;
+    BTable<Key>* d_tabs = nullptr;
+    uint32_t* d_pre = nullptr;  // tile, bin, qtile prefixes
+    uint32_t* d_mat = nullptr;
+    Key* d_rkeys = nullptr;
+    uint32_t* d_rids = nullptr;
+    uint32_t* d_heavy = nullptr;  // [bins] list + [1] count
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+
+    ~BatchPlan() override { release(); }
+    void release() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        if (owns_block && d_block) (void)hipFree(d_block);
+        d_block = nullptr;
+        owns_block = false;
+    }
+
+    // device bytes of descriptors, prefixes and workspace; carve when base set
+    size_t carve(void* base) {
+        Carver c(base);
+        d_tabs = c.take<BTable<Key>>(T ? T : 1);
+        d_pre = c.take<uint32_t>(3 * ((size_t)T + 1));
+        d_mat = c.take<uint32_t>(mat_entries ? mat_entries : 1);
+        d_rkeys = c.take<Key>(ws_keys ? ws_keys : 1);
+        d_rids = c.take<uint32_t>(ws_keys ? ws_keys : 1);
+        d_heavy = c.take<uint32_t>((size_t)bins + 1);
+        d_block = base;
+        return c.off + 256;
+    }
+    // host image of the descriptors and prefixes, as copied to the device
+    size_t host_image_bytes() const { return sizeof(BTable<Key>) * T + 4 * 3 * ((size_t)T + 1); }
+    void host_image(void* dst) const {
+        char* p = (char*)dst;
+        std::memcpy(p, host.data(), sizeof(BTable<Key>) * T);
+        p += sizeof(BTable<Key>) * T;
+        std::memcpy(p, tile_pre.data(), 4 * (T + 1));
+        std::memcpy(p + 4 * (T + 1), bin_pre.data(), 4 * (T + 1));
+        std::memcpy(p + 8 * (T + 1), qtile_pre.data(), 4 * (T + 1));
+    }
+    hipError_t copy_image_async(const void* pinned, hipStream_t s) {
+        HG_TRY(hipMemcpyAsync(d_tabs, pinned, sizeof(BTable<Key>) * T, hipMemcpyHostToDevice, s));
+        return hipMemcpyAsync(d_pre, (const char*)pinned + sizeof(BTable<Key>) * T,
+                              4 * 3 * ((size_t)T + 1), hipMemcpyHostToDevice, s);
+    }
+
+    // probe-only layout over existing tables (used by the server to merge
+    // small probes into one launch)
+    void layout_probe(const std::vector<BTable<Key>>& tabs) {
+        build = false;
+        T = (uint32_t)tabs.size();
+        host = tabs;
+        tile_pre.assign(T + 1, 0);
+        bin_pre.assign(T + 1, 0);
+        qtile_pre.assign(T + 1, 0);
+        uint64_t qt = 0;
+        for (uint32_t i = 0; i < T; ++i) {
+            qtile_pre[i] = (uint32_t)qt;
+            qt += ceil_div(host[i].m, kBProbeTile);
+        }
+        qtile_pre[T] = (uint32_t)qt;
+        tiles = bins = 0;
+        qtiles = (uint32_t)qt;
+        mat_entries = ws_keys = 0;
+    }
+
+    // lay out every table for bin-size target `tgt` (host only)
+    hg_status layout(const hg_batch_item* items, uint32_t count, uint32_t tgt) {
+        build = true;
+        T = count;
+        target = tgt;
+        host.assign(count, BTable<Key>{});
+        tile_pre.assign(count + 1, 0);
+        bin_pre.assign(count + 1, 0);
+        qtile_pre.assign(count + 1, 0);
+        uint64_t tiles64 = 0, bins64 = 0, qt64 = 0, mat64 = 0, keys64 = 0;
+        max_b1 = 0;
+        max_k = 0;
+        for (uint32_t i = 0; i < count; ++i) {
+            const hg_batch_item& it = items[i];
+            BTable<Key>& tb = host[i];
+            tb.keys = (const Key*)it.d_keys;
+            tb.queries = (const Key*)it.d_queries;
+            tb.offsets = it.d_offsets;
+            tb.ids = it.d_ids;
+            tb.ekeys = (Key*)it.d_ekeys;
+            tb.counts = it.d_counts;
+            tb.hp = KeyTraits<Key>::make(it.hash_range, it.seed);
+            tb.n = (uint32_t)it.n;
+            tb.m = (uint32_t)it.m;
+            tb.V = (uint32_t)it.hash_range;
+            uint32_t k = pick_k(it.n, it.hash_range, tgt);
+            uint32_t bins = (uint32_t)ceil_div(it.hash_range, 1ull << k);
+            uint32_t bits = log2_ceil(bins);
+            while (bits > kMaxDigitBits && k < kMaxLocalBits) {
+                ++k;
+                bins = (uint32_t)ceil_div(it.hash_range, 1ull << k);
+                bits = log2_ceil(bins);
+            }
+            if (bits > kMaxDigitBits) return HG_ERR_INVALID_ARG;
+            tb.k = k;
+            tb.bins = bins;
+            if (it.n == 0) {
+                tb.kind = kEmpty;
+            } else if (bins == 1 && it.n <= kLightCap) {
+                tb.kind = kDirect;
+            } else {
+                tb.kind = kPartitioned;
+                tb.b1 = bits;
+                tb.ntiles = (uint32_t)ceil_div(it.n, kPartTile);
+                tb.mat_base = (uint32_t)mat64;
+                tb.key_base = (uint32_t)keys64;
+                mat64 += (uint64_t)tb.ntiles << bits;
+                keys64 += it.n;
+                if (bits > max_b1) max_b1 = bits;
+            }
+            if (k > max_k) max_k = k;
+            tile_pre[i] = (uint32_t)tiles64;
+            bin_pre[i] = (uint32_t)bins64;
+            qtile_pre[i] = (uint32_t)qt64;
+            tiles64 += tb.ntiles;
+            bins64 += bins;
+            qt64 += ceil_div(it.m, kBProbeTile);
+        }
+        tile_pre[count] = (uint32_t)tiles64;
+        bin_pre[count] = (uint32_t)bins64;
+        qtile_pre[count] = (uint32_t)qt64;
+        if (tiles64 > 0x7fffffffull || bins64 > 0x7fffffffull || qt64 > 0x7fffffffull ||
+            mat64 > 0xffffffffull || keys64 > 0xffffffffull)
+            return HG_ERR_INVALID_ARG;
+        tiles = (uint32_t)tiles64;
+        bins = (uint32_t)bins64;
+        qtiles = (uint32_t)qt64;
+        mat_entries = mat64;
+        ws_keys = keys64;
+        return HG_OK;
+    }
+
+    // owned device memory, synchronous upload (graph plans)
+    hipError_t upload() {
+        void* base = nullptr;
+        HG_TRY(hipMalloc(&base, carve(nullptr)));
+        carve(base);
+        owns_block = true;
+        std::vector<char> img(host_image_bytes());
+        host_image(img.data());
+        HG_TRY(hipMemcpy(d_tabs, img.data(), sizeof(BTable<Key>) * T, hipMemcpyHostToDevice));
+        return hipMemcpy(d_pre, img.data() + sizeof(BTable<Key>) * T, 4 * 3 * ((size_t)T + 1),
+                         hipMemcpyHostToDevice);
+    }
+
+    // the whole run, enqueued on s (also used inside stream capture)
+    hipError_t enqueue(hipStream_t s) {
+        BPrefix pre{d_pre, d_pre + (T + 1), d_pre + 2 * (T + 1), T};
+        uint32_t* heavy_count = d_heavy + bins;
+        if (build) {
+            hipLaunchKernelGGL(k_bclear, dim3(1), dim3(64), 0, s, heavy_count);
+            HG_TRY(hipGetLastError());
+        }
+        if (tiles) {
+            const uint32_t grid = (uint32_t)(8 * ceil_div(tiles, 8));
+            hipLaunchKernelGGL(k_bhist<Key>, dim3(grid), dim3(kPartThreads), (4u << max_b1), s,
+                               (const BTable<Key>*)d_tabs, pre, tiles, d_mat);
+            HG_TRY(hipGetLastError());
+            hipLaunchKernelGGL(k_bcolscan<Key>, dim3(T), dim3(256), 0, s,
+                               (const BTable<Key>*)d_tabs, d_mat);
+            HG_TRY(hipGetLastError());
+            hipLaunchKernelGGL(k_bpart<Key>, dim3(grid), dim3(kPartThreads),
+                               part_smem_bytes(sizeof(Key), max_b1), s, (const BTable<Key>*)d_tabs,
+                               pre, tiles, (const uint32_t*)d_mat, d_rkeys, d_rids);
+            HG_TRY(hipGetLastError());
+        }
+        if (bins) {
+            hipLaunchKernelGGL(k_blocal<Key>, dim3(bins), dim3(kLocalThreads),
+                               light_smem<Key>(max_k), s, (const BTable<Key>*)d_tabs, pre, bins,
+                               (const uint32_t*)d_mat, (const Key*)d_rkeys,
+                               (const uint32_t*)d_rids, d_heavy, heavy_count);
+            HG_TRY(hipGetLastError());
+            const uint32_t hgrid = bins < 256 ? bins : 256;
+            hipLaunchKernelGGL(k_bheavy<Key>, dim3(hgrid), dim3(kLocalThreads),
+                               heavy_smem<Key>(max_k), s, (const BTable<Key>*)d_tabs, pre,
+                               (const uint32_t*)d_mat, (const Key*)d_rkeys,
+                               (const uint32_t*)d_rids, (const uint32_t*)d_heavy,
+                               (const uint32_t*)heavy_count);
+            HG_TRY(hipGetLastError());
+        }
+        if (qtiles) {
+            hipLaunchKernelGGL(k_bprobe<Key>, dim3(qtiles), dim3(kBProbeThreads), 0, s,
+                               (const BTable<Key>*)d_tabs, pre, qtiles);
+            HG_TRY(hipGetLastError());
+        }
+        return hipSuccess;
+    }
+
+    hipError_t capture() {
+        hipStream_t cs;
+        HG_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t e1 = enqueue(cs);
+            hipGraph_t g = nullptr;
+            hipError_t e2 = hipStreamEndCapture(cs, &g);
+            e = e1 != hipSuccess ? e1 : e2;
+            if (e == hipSuccess) {
+                graph = g;
+                e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            } else if (g) {
+                (void)hipGraphDestroy(g);
+            }
+        }
+        (void)hipStreamDestroy(cs);
+        return e;
+    }
+};
+
+template <typename Key>
+static hipError_t set_batch_smem() {
+    static bool done = false;
+    if (done) return hipSuccess;
+    const int lim = 160 * 1024;
+    HG_TRY(hipFuncSetAttribute((const void*)k_bpart<Key>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               lim));
+    HG_TRY(hipFuncSetAttribute((const void*)k_blocal<Key>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+    HG_TRY(hipFuncSetAttribute((const void*)k_bheavy<Key>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+    done = true;
+    return hipSuccess;
+}
+
+// Autotuning cache: (tables, total keys, total queries, key bits) -> target.
+static std::mutex g_tune_mu;
+static std::map<std::tuple<uint32_t, uint64_t, uint64_t, int>, uint32_t> g_tune;
+
+}  // namespace hg
+
+using namespace hg;
+
+struct hg_batch {
+    int key_bits = 32;
+    BatchPlanBase* plan = nullptr;
+    uint32_t target = 0;
+};
+
+namespace {
+
+hg_status hstat(hipError_t e) {
+    if (e == hipSuccess) return HG_OK;
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return HG_ERR_OOM;
+    return HG_ERR_DEVICE;
+}
+
+template <typename Key>
+hg_status create_plan(const hg_batch_item* items, uint32_t count, const hg_batch_opts* opts,
+                      hg_batch* b) {
+    hipError_t e = set_batch_smem<Key>();
+    if (e != hipSuccess) return hstat(e);
+    uint64_t tn = 0, tm = 0;
+    for (uint32_t i = 0; i < count; ++i) {
+        tn += items[i].n;
+        tm += items[i].m;
+    }
+    const int kb = (int)sizeof(Key) * 8;
+    std::vector<uint32_t> cands;
+    if (opts && opts->bin_target) {
+        cands.push_back(opts->bin_target);
+    } else {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(std::make_tuple(count, tn, tm, kb));
+        if (it != g_tune.end()) cands.push_back(it->second);
+    }
+    const bool tune = cands.empty() && (!opts || opts->autotune != 0);
+    if (cands.empty()) {
+        if (tune) cands = {1024u, 2048u};
+        else cands = {2048u};
+    }
+    BatchPlan<Key>* best = nullptr;
+    float best_ms = 0.f;
+    for (uint32_t tgt : cands) {
+        BatchPlan<Key>* p = new (std::nothrow) BatchPlan<Key>();
+        if (!p) return HG_ERR_OOM;
+        hg_status st = p->layout(items, count, tgt);
+        if (st == HG_OK) st = hstat(p->upload());
+        if (st == HG_OK) st = hstat(p->capture());
+        if (st != HG_OK) {
+            delete p;
+            delete best;
+            return st;
+        }
+        if (cands.size() > 1) {
+            // time two replays of the candidate graph
+            hipStream_t ts;
+            hipEvent_t e0, e1;
+            float ms = 0.f;
+            hipError_t te = hipStreamCreateWithFlags(&ts, hipStreamNonBlocking);
+            if (te == hipSuccess) te = hipEventCreate(&e0);
+            if (te == hipSuccess) te = hipEventCreate(&e1);
+            if (te == hipSuccess) te = hipGraphLaunch(p->exec, ts);  // warm-up
+            if (te == hipSuccess) te = hipEventRecord(e0, ts);
+            for (int r = 0; r < 2 && te == hipSuccess; ++r) te = hipGraphLaunch(p->exec, ts);
+            if (te == hipSuccess) te = hipEventRecord(e1, ts);
+            if (te == hipSuccess) te = hipEventSynchronize(e1);
+            if (te == hipSuccess) te = hipEventElapsedTime(&ms, e0, e1);
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            (void)hipStreamDestroy(ts);
+            if (te != hipSuccess) {
+                delete p;
+                delete best;
+                return hstat(te);
+            }
+            if (!best || ms < best_ms) {
+                delete best;
+                best = p;
+                best_ms = ms;
+            } else {
+                delete p;
+            }
+        } else {
+            best = p;
+        }
+    }
+    if (tune) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[std::make_tuple(count, tn, tm, kb)] = best->target;
+    }
+    b->plan = best;
+    b->target = best->target;
+    return HG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hg_status hg_batch_create(const hg_batch_item* items, uint32_t count, int key_bits,
+                          const hg_batch_opts* opts, hg_batch** out) {
+    if (!out || (count && !items) || (key_bits != 32 && key_bits != 64)) return HG_ERR_INVALID_ARG;
+    for (uint32_t i = 0; i < count; ++i) {
+        const hg_batch_item& it = items[i];
+        if (it.hash_range < 1 || it.hash_range > 0xffffffffull || it.n > 0xffffffffull ||
+            it.m > 0xffffffffull)
+            return HG_ERR_INVALID_ARG;
+        if ((it.n && (!it.d_keys || !it.d_ids || !it.d_ekeys)) || !it.d_offsets ||
+            (it.m && (!it.d_queries || !it.d_counts)))
+            return HG_ERR_INVALID_ARG;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return HG_ERR_DEVICE;
+    hg_batch* b = new (std::nothrow) hg_batch();
+    if (!b) return HG_ERR_OOM;
+    b->key_bits = key_bits;
+    hg_status st = key_bits == 32 ? create_plan<uint32_t>(items, count, opts, b)
+                                  : create_plan<uint64_t>(items, count, opts, b);
+    if (st != HG_OK) {
+        delete b;
+        return st;
+    }
+    *out = b;
+    return HG_OK;
+}
+
+hg_status hg_batch_run(hg_batch* b, hipStream_t stream) {
+    if (!b || !b->plan) return HG_ERR_INVALID_ARG;
+    hipGraphExec_t exec = b->key_bits == 32 ? ((BatchPlan<uint32_t>*)b->plan)->exec
+                                            : ((BatchPlan<uint64_t>*)b->plan)->exec;
+    return hstat(hipGraphLaunch(exec, stream));
+}
+
+hg_status hg_batch_info(const hg_batch* b, uint32_t* bin_target, uint64_t* workspace_bytes) {
+    if (!b || !b->plan) return HG_ERR_INVALID_ARG;
+    if (bin_target) *bin_target = b->target;
+    if (workspace_bytes) {
+        if (b->key_bits == 32) {
+            auto* p = (BatchPlan<uint32_t>*)b->plan;
+            *workspace_bytes = p->mat_entries * 4 + p->ws_keys * 8;
+        } else {
+            auto* p = (BatchPlan<uint64_t>*)b->plan;
+            *workspace_bytes = p->mat_entries * 4 + p->ws_keys * 12;
+        }
+    }
+    return HG_OK;
+}
+
+void hg_batch_free(hg_batch* b) {
+    if (!b) return;
+    (void)hipDeviceSynchronize();
+    delete b->plan;
+    delete b;
+}
+
+}  // extern "C"
+
+// ===================================================================== serving
+//
+// A request loop on a host thread.  Build and probe requests are queued by
+// hg_server_submit_*; the loop admits them onto a few HIP streams (default
+// priority) as launch slots and memory allow, so work of different requests
+// overlaps on the device.  Small requests that are pending together are
+// merged into one launch of the batched kernels (continuous batching):
+// several small builds become one batched build, several small probes one
+// batched probe.  Tables stay resident in HBM until evicted; admission keeps
+// resident tables plus in-flight workspace under a byte budget, evicting the
+// least recently used tables that no pending or running request uses.
+// Latency is measured from submission to the moment the loop sees the
+// request's completion event.
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <thread>
+#include <unordered_map>
+
+namespace hg {
+namespace srv {
+
+using Clock = std::chrono::steady_clock;
+
+struct STable {
+    int key_bits = 32;
+    uint64_t n = 0, V = 0, seed = 0;
+    uint32_t* offsets = nullptr;
+    uint32_t* ids = nullptr;
+    void* keys = nullptr;
+    uint64_t bytes = 0;
+    uint64_t last_use = 0;
+    int pins = 0;            // requests (its build, pending probes) that need it
+    hipEvent_t ready = nullptr;
+    bool enqueued = false;   // build launched
+    bool built = false;      // build completed
+    bool failed = false;
+    int stream = -1;         // stream of the build
+};
+
+struct SReq {
+    int kind = 0;  // 0 build, 1 probe
+    uint64_t table = 0;
+    const void* data = nullptr;
+    uint64_t count = 0;
+    int key_bits = 32;
+    uint32_t* counts = nullptr;
+    double t_arrive = 0, t_done = 0;
+    hg_status status = HG_OK;
+    bool done = false;
+};
+
+struct Launch {
+    std::vector<uint64_t> reqs;
+    hipEvent_t ev = nullptr;
+    int stream = 0;
+    void* transient = nullptr;
+    uint64_t transient_bytes = 0;
+    void* pinned = nullptr;
+    size_t pinned_bytes = 0;
+};
+
+struct Server {
+    hg_server_opts o{};
+    int device = 0;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<uint64_t> pending;
+    std::unordered_map<uint64_t, SReq> reqs;
+    std::unordered_map<uint64_t, STable> tables;
+    std::vector<Launch> inflight;
+    std::vector<hipStream_t> streams;
+    std::vector<std::pair<void*, size_t>> pinned_free;
+    std::vector<hipEvent_t> event_pool;
+    int next_stream = 0;
+    uint64_t resident = 0, transient = 0, peak = 0, clock = 0;
+    uint64_t next_id = 1;
+    bool stop = false;
+    std::thread worker;
+    // statistics
+    std::vector<double> lat_ms;
+    uint64_t completed = 0, failed = 0, rejected = 0, evictions = 0, launches = 0, merged = 0,
+             keys = 0;
+    double first_arrive = -1, last_done = 0;
+    Clock::time_point t0 = Clock::now();
+
+    double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
+
+    hipEvent_t take_event() {
+        if (!event_pool.empty()) {
+            hipEvent_t e = event_pool.back();
+            event_pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        (void)hipEventCreateWithFlags(&e, hipEventDisableTiming);
+        return e;
+    }
+
+    void* take_pinned(size_t bytes) {
+        for (size_t i = 0; i < pinned_free.size(); ++i)
+            if (pinned_free[i].second >= bytes) {
+                void* p = pinned_free[i].first;
+                pinned_free.erase(pinned_free.begin() + i);
+                return p;
+            }
+        void* p = nullptr;
+        size_t sz = bytes < 65536 ? 65536 : bytes;
+        if (hipHostMalloc(&p, sz, hipHostMallocDefault) != hipSuccess) return nullptr;
+        pinned_sizes[p] = sz;
+        return p;
+    }
+    std::unordered_map<void*, size_t> pinned_sizes;
+
+    static uint64_t table_bytes(uint64_t n, uint64_t V, int kb) {
+        return (V + 1) * 4 + (n ? n : 1) * (4 + (uint64_t)kb / 8);
+    }
+
+    bool evict_for(uint64_t need) {
+        while (resident + transient + need > o.budget_bytes) {
+            uint64_t victim = 0, best = ~0ull;
+            for (auto& kv : tables) {
+                const STable& t = kv.second;
+                if (t.pins == 0 && t.built && t.last_use < best) {
+                    best = t.last_use;
+                    victim = kv.first;
+                }
+            }
+            if (!victim) return false;
+            STable& t = tables[victim];
+            (void)hipFreeAsync(t.offsets, streams[0]);
+            (void)hipFreeAsync(t.ids, streams[0]);
+            (void)hipFreeAsync(t.keys, streams[0]);
+            if (t.ready) event_pool.push_back(t.ready);
+            resident -= t.bytes;
+            tables.erase(victim);
+            ++evictions;
+        }
+        return true;
+    }
+
+    void finish_req(uint64_t rid, hg_status st, double t) {
+        SReq& r = reqs[rid];
+        r.status = st;
+        r.done = true;
+        r.t_done = t;
+        auto it = tables.find(r.table);
+        if (it != tables.end()) {
+            STable& tb = it->second;
+            tb.pins -= 1;
+            if (r.kind == 0) {
+                tb.built = st == HG_OK;
+                tb.failed = st != HG_OK;
+            }
+            tb.last_use = ++clock;
+        }
+        if (st == HG_OK) {
+            ++completed;
+            keys += r.count;
+            lat_ms.push_back((t - r.t_arrive) * 1e3);
+            if (t > last_done) last_done = t;
+        } else {
+            ++failed;
+        }
+    }
+
+    void retire() {
+        const double t = now();
+        for (size_t i = 0; i < inflight.size();) {
+            Launch& L = inflight[i];
+            const hipError_t q = hipEventQuery(L.ev);
+            if (q == hipErrorNotReady) {
+                ++i;
+                continue;
+            }
+            const hg_status st = q == hipSuccess ? HG_OK : HG_ERR_DEVICE;
+            for (uint64_t rid : L.reqs) finish_req(rid, st, t);
+            if (L.transient) {
+                (void)hipFreeAsync(L.transient, streams[L.stream]);
+                transient -= L.transient_bytes;
+            }
+            if (L.pinned) pinned_free.push_back({L.pinned, pinned_sizes[L.pinned]});
+            event_pool.push_back(L.ev);
+            inflight.erase(inflight.begin() + i);
+            cv_done.notify_all();
+        }
+    }
+
+    bool small(const SReq& r) const { return r.count <= o.merge_keys; }
+
+    // Start the oldest pending request, merged with other pending requests
+    // of the same kind and key width when they are small.  Returns false if
+    // it has to wait for memory.
+    bool admit_one() {
+        const uint64_t rid0 = pending.front();
+        SReq& r0 = reqs[rid0];
+        std::vector<uint64_t> group{rid0};
+        if (small(r0) && o.merge_max > 1) {
+            for (size_t j = 1; j < pending.size() && group.size() < o.merge_max; ++j) {
+                SReq& r = reqs[pending[j]];
+                if (r.kind == r0.kind && r.key_bits == r0.key_bits && small(r)) {
+                    if (r.kind == 1) {
+                        auto it = tables.find(r.table);
+                        if (it == tables.end() || !it->second.enqueued) continue;
+                    }
+                    group.push_back(pending[j]);
+                }
+            }
+        }
+        // probes: their table must exist and have its build launched
+        if (r0.kind == 1) {
+            auto it = tables.find(r0.table);
+            if (it == tables.end() || it->second.failed) {
+                pending.pop_front();
+                finish_req(rid0, HG_ERR_NOT_FOUND, now());
+                cv_done.notify_all();
+                return true;
+            }
+            if (!it->second.enqueued) return false;  // its build waits for memory
+        }
+        // memory: new tables (builds) plus workspace
+        uint64_t need_tables = 0, ws = 0;
+        const int kb = r0.key_bits;
+        if (r0.kind == 0) {
+            for (uint64_t rid : group) {
+                const SReq& r = reqs[rid];
+                need_tables += tables[r.table].bytes;
+            }
+            if (group.size() == 1)
+                ws = build_ws_bytes(2, r0.count, tables[r0.table].V, kb, 0);
+        }
+        uint64_t merged_ws = 0;
+        // merged launches carry descriptors + workspace in one block
+        BatchPlan<uint32_t> p32;
+        BatchPlan<uint64_t> p64;
+        std::vector<hg_batch_item> items;
+        if (group.size() > 1) {
+            if (r0.kind == 0) {
+                for (uint64_t rid : group) {
+                    const SReq& r = reqs[rid];
+                    const STable& t = tables[r.table];
+                    hg_batch_item it{};
+                    it.d_keys = r.data;
+                    it.n = r.count;
+                    it.hash_range = t.V;
+                    it.seed = t.seed;
+                    items.push_back(it);
+                }
+                // output pointers are filled after allocation
+                if (kb == 32) {
+                    if (p32.layout(items.data(), (uint32_t)items.size(), 2048) != HG_OK) group.resize(1);
+                    else merged_ws = p32.carve(nullptr);
+                } else {
+                    if (p64.layout(items.data(), (uint32_t)items.size(), 2048) != HG_OK) group.resize(1);
+                    else merged_ws = p64.carve(nullptr);
+                }
+                if (group.size() == 1) ws = build_ws_bytes(2, r0.count, tables[r0.table].V, kb, 0);
+            }
+        }
+        if (group.size() > 1 && r0.kind == 0) {
+            need_tables = 0;
+            for (uint64_t rid : group) need_tables += tables[reqs[rid].table].bytes;
+            ws = merged_ws;
+        }
+        if (resident + transient + need_tables + ws > o.budget_bytes) {
+            if (!evict_for(need_tables + ws)) {
+                if (inflight.empty()) {
+                    // can never fit: reject the oldest request
+                    pending.pop_front();
+                    if (r0.kind == 0) {
+                        tables[r0.table].failed = true;
+                        ++rejected;
+                    }
+                    finish_req(rid0, HG_ERR_BUDGET, now());
+                    cv_done.notify_all();
+                    return true;
+                }
+                return false;
+            }
+        }
+        // remove the group from pending
+        for (uint64_t rid : group)
+            for (size_t j = 0; j < pending.size(); ++j)
+                if (pending[j] == rid) {
+                    pending.erase(pending.begin() + j);
+                    break;
+                }
+        Launch L;
+        L.reqs = group;
+        L.stream = next_stream;
+        next_stream = (next_stream + 1) % (int)streams.size();
+        hipStream_t s = streams[L.stream];
+        hipError_t e = hipSuccess;
+        // allocate new tables
+        if (r0.kind == 0) {
+            for (uint64_t rid : group) {
+                STable& t = tables[reqs[rid].table];
+                if (e == hipSuccess) e = hipMallocAsync((void**)&t.offsets, (t.V + 1) * 4, s);
+                if (e == hipSuccess) e = hipMallocAsync((void**)&t.ids, (t.n ? t.n : 1) * 4, s);
+                if (e == hipSuccess)
+                    e = hipMallocAsync(&t.keys, (t.n ? t.n : 1) * (uint64_t)(t.key_bits / 8), s);
+                resident += t.bytes;
+                t.stream = L.stream;
+            }
+        }
+        if (e == hipSuccess && ws) {
+            e = hipMallocAsync(&L.transient, ws, s);
+            if (e == hipSuccess) {
+                L.transient_bytes = ws;
+                transient += ws;
+            }
+        }
+        if (resident + transient > peak) peak = resident + transient;
+        // probes wait for their tables' builds
+        if (e == hipSuccess && r0.kind == 1)
+            for (uint64_t rid : group) {
+                const STable& t = tables[reqs[rid].table];
+                if (!t.built && t.ready && t.stream != L.stream)
+                    e = hipStreamWaitEvent(s, t.ready, 0);
+            }
+        if (e == hipSuccess) {
+            if (r0.kind == 0 && group.size() == 1) {
+                STable& t = tables[r0.table];
+                e = kb == 32 ? run_build_v2<uint32_t>((const uint32_t*)r0.data, t.n, t.V, t.seed,
+                                                      t.offsets, t.ids, (uint32_t*)t.keys,
+                                                      nullptr, L.transient, 0, s)
+                             : run_build_v2<uint64_t>((const uint64_t*)r0.data, t.n, t.V, t.seed,
+                                                      t.offsets, t.ids, (uint64_t*)t.keys,
+                                                      nullptr, L.transient, 0, s);
+            } else if (r0.kind == 1 && group.size() == 1) {
+                const STable& t = tables[r0.table];
+                TableDev d{t.offsets, t.ids, t.keys, t.n, t.V, t.seed};
+                e = kb == 32 ? run_probe_counts<uint32_t>(d, (const uint32_t*)r0.data, r0.count,
+                                                          r0.counts, nullptr, s)
+                             : run_probe_counts<uint64_t>(d, (const uint64_t*)r0.data, r0.count,
+                                                          r0.counts, nullptr, s);
+            } else {
+                e = kb == 32 ? enqueue_merged<uint32_t>(p32, items, group, L, s)
+                             : enqueue_merged<uint64_t>(p64, items, group, L, s);
+                merged += group.size();
+            }
+        }
+        if (e == hipSuccess && r0.kind == 0)
+            for (uint64_t rid : group) {
+                STable& t = tables[reqs[rid].table];
+                if (!t.ready) t.ready = take_event();
+                e = hipEventRecord(t.ready, s);
+                t.enqueued = true;
+            }
+        L.ev = take_event();
+        if (e == hipSuccess) e = hipEventRecord(L.ev, s);
+        ++launches;
+        if (e != hipSuccess) {
+            (void)hipStreamSynchronize(s);
+            for (uint64_t rid : group) finish_req(rid, HG_ERR_DEVICE, now());
+            if (L.transient) {
+                (void)hipFreeAsync(L.transient, s);
+                transient -= L.transient_bytes;
+            }
+            event_pool.push_back(L.ev);
+            cv_done.notify_all();
+            return true;
+        }
+        inflight.push_back(L);
+        return true;
+    }
+
+    template <typename Key>
+    hipError_t enqueue_merged(BatchPlan<Key>& p, std::vector<hg_batch_item>& items,
+                              const std::vector<uint64_t>& group, Launch& L, hipStream_t s) {
+        if (reqs[group[0]].kind == 0) {
+            for (size_t i = 0; i < group.size(); ++i) {
+                const STable& t = tables[reqs[group[i]].table];
+                p.host[i].offsets = t.offsets;
+                p.host[i].ids = t.ids;
+                p.host[i].ekeys = (Key*)t.keys;
+            }
+        } else {
+            std::vector<BTable<Key>> tabs;
+            for (uint64_t rid : group) {
+                const SReq& r = reqs[rid];
+                const STable& t = tables[r.table];
+                BTable<Key> b{};
+                b.queries = (const Key*)r.data;
+                b.offsets = t.offsets;
+                b.ids = t.ids;
+                b.ekeys = (Key*)t.keys;
+                b.counts = r.counts;
+                b.hp = KeyTraits<Key>::make(t.V, t.seed);
+                b.n = (uint32_t)t.n;
+                b.m = (uint32_t)r.count;
+                b.V = (uint32_t)t.V;
+                b.kind = kEmpty;
+                tabs.push_back(b);
+            }
+            p.layout_probe(tabs);
+            const size_t need = p.carve(nullptr);
+            HG_TRY(hipMallocAsync(&L.transient, need, s));
+            L.transient_bytes = need;
+            transient += need;
+        }
+        (void)items;
+        p.carve(L.transient);
+        const size_t img = p.host_image_bytes();
+        L.pinned = take_pinned(img);
+        if (!L.pinned) return hipErrorOutOfMemory;
+        p.host_image(L.pinned);
+        HG_TRY(p.copy_image_async(L.pinned, s));
+        return p.enqueue(s);
+    }
+
+    void loop() {
+        (void)hipSetDevice(device);
+        std::unique_lock<std::mutex> lk(mu);
+        for (;;) {
+            retire();
+            while (!pending.empty() && inflight.size() < o.max_inflight)
+                if (!admit_one()) break;
+            if (stop && pending.empty() && inflight.empty()) break;
+            if (inflight.empty() && pending.empty())
+                cv_work.wait(lk);
+            else
+                cv_work.wait_for(lk, std::chrono::microseconds(20));
+        }
+    }
+};
+
+}  // namespace srv
+}  // namespace hg
+
+struct hg_server {
+    hg::srv::Server s;
+};
+
+extern "C" {
+
+hg_status hg_server_create(const hg_server_opts* opts, hg_server** out) {
+    if (!out) return HG_ERR_INVALID_ARG;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return HG_ERR_DEVICE;
+    hg_server* h = new (std::nothrow) hg_server();
+    if (!h) return HG_ERR_OOM;
+    hg::srv::Server& s = h->s;
+    if (opts) s.o = *opts;
+    if (!s.o.budget_bytes) s.o.budget_bytes = 64ull << 30;
+    if (!s.o.streams) s.o.streams = 4;
+    if (!s.o.max_inflight) s.o.max_inflight = 8;
+    if (!s.o.merge_max) s.o.merge_max = 64;
+    if (!s.o.merge_keys) s.o.merge_keys = 65536;
+    if (s.o.streams > 16 || s.o.max_inflight > 256) {
+        delete h;
+        return HG_ERR_INVALID_ARG;
+    }
+    (void)hipGetDevice(&s.device);
+    hg_status st = HG_OK;
+    if (hg::set_batch_smem<uint32_t>() != hipSuccess || hg::set_batch_smem<uint64_t>() != hipSuccess)
+        st = HG_ERR_DEVICE;
+    for (uint32_t i = 0; i < s.o.streams && st == HG_OK; ++i) {
+        hipStream_t q;
+        if (hipStreamCreateWithFlags(&q, hipStreamNonBlocking) != hipSuccess) st = HG_ERR_DEVICE;
+        else s.streams.push_back(q);
+    }
+    if (st != HG_OK) {
+        for (auto q : s.streams) (void)hipStreamDestroy(q);
+        delete h;
+        return st;
+    }
+    s.worker = std::thread([&s] { s.loop(); });
+    *out = h;
+    return HG_OK;
+}
+
+hg_status hg_server_submit_build(hg_server* h, const void* d_keys, uint64_t n, int key_bits,
+                                 uint64_t hash_range, uint64_t seed, uint64_t* table_id,
+                                 uint64_t* request_id) {
+    if (!h || !table_id || (key_bits != 32 && key_bits != 64) || hash_range < 1 ||
+        hash_range > 0xffffffffull || n > 0xffffffffull || (n && !d_keys))
+        return HG_ERR_INVALID_ARG;
+    hg::srv::Server& s = h->s;
+    std::lock_guard<std::mutex> lk(s.mu);
+    if (s.stop) return HG_ERR_INVALID_ARG;
+    const uint64_t tid = s.next_id++, rid = s.next_id++;
+    hg::srv::STable& t = s.tables[tid];
+    t.key_bits = key_bits;
+    t.n = n;
+    t.V = hash_range;
+    t.seed = seed;
+    t.bytes = hg::srv::Server::table_bytes(n, hash_range, key_bits);
+    t.pins = 1;
+    t.last_use = ++s.clock;
+    hg::srv::SReq& r = s.reqs[rid];
+    r.kind = 0;
+    r.table = tid;
+    r.data = d_keys;
+    r.count = n;
+    r.key_bits = key_bits;
+    r.t_arrive = s.now();
+    if (s.first_arrive < 0) s.first_arrive = r.t_arrive;
+    s.pending.push_back(rid);
+    *table_id = tid;
+    if (request_id) *request_id = rid;
+    s.cv_work.notify_one();
+    return HG_OK;
+}
+
+hg_status hg_server_submit_probe(hg_server* h, uint64_t table_id, const void* d_queries,
+                                 uint64_t m, uint32_t* d_counts, uint64_t* request_id) {
+    if (!h || m > 0xffffffffull || (m && (!d_queries || !d_counts))) return HG_ERR_INVALID_ARG;
+    hg::srv::Server& s = h->s;
+    std::lock_guard<std::mutex> lk(s.mu);
+    if (s.stop) return HG_ERR_INVALID_ARG;
+    auto it = s.tables.find(table_id);
+    if (it == s.tables.end() || it->second.failed) return HG_ERR_NOT_FOUND;
+    it->second.pins += 1;
+    it->second.last_use = ++s.clock;
+    const uint64_t rid = s.next_id++;
+    hg::srv::SReq& r = s.reqs[rid];
+    r.kind = 1;
+    r.table = table_id;
+    r.data = d_queries;
+    r.count = m;
+    r.key_bits = it->second.key_bits;
+    r.counts = d_counts;
+    r.t_arrive = s.now();
+    if (s.first_arrive < 0) s.first_arrive = r.t_arrive;
+    s.pending.push_back(rid);
+    if (request_id) *request_id = rid;
+    s.cv_work.notify_one();
+    return HG_OK;
+}
+
+hg_status hg_server_wait(hg_server* h, uint64_t request_id, hg_status* result) {
+    if (!h) return HG_ERR_INVALID_ARG;
+    hg::srv::Server& s = h->s;
+    std::unique_lock<std::mutex> lk(s.mu);
+    auto it = s.reqs.find(request_id);
+    if (it == s.reqs.end()) return HG_ERR_NOT_FOUND;
+    s.cv_done.wait(lk, [&] { return s.reqs[request_id].done; });
+    if (result) *result = s.reqs[request_id].status;
+    return HG_OK;
+}
+
+hg_status hg_server_drain(hg_server* h) {
+    if (!h) return HG_ERR_INVALID_ARG;
+    hg::srv::Server& s = h->s;
+    std::unique_lock<std::mutex> lk(s.mu);
+    s.cv_done.wait(lk, [&] { return s.pending.empty() && s.inflight.empty(); });
+    return HG_OK;
+}
+
+hg_status hg_server_table(hg_server* h, uint64_t table_id, hg_table_info* info) {
+    if (!h || !info) return HG_ERR_INVALID_ARG;
+    hg::srv::Server& s = h->s;
+    std::lock_guard<std::mutex> lk(s.mu);
+    auto it = s.tables.find(table_id);
+    if (it == s.tables.end() || !it->second.built) return HG_ERR_NOT_FOUND;
+    const hg::srv::STable& t = it->second;
+    info->d_offsets = t.offsets;
+    info->d_ids = t.ids;
+    info->d_keys = t.keys;
+    info->n = t.n;
+    info->hash_range = t.V;
+    info->seed = t.seed;
+    info->key_bits = t.key_bits;
+    info->variant = HG_VARIANT_V2;
+    info->device_bytes = t.bytes;
+    return HG_OK;
+}
+
+hg_status hg_server_export(hg_server* h, uint64_t table_id, uint32_t* d_offsets, uint32_t* d_ids,
+                           void* d_keys, hipStream_t stream) {
+    if (!h) return HG_ERR_INVALID_ARG;
+    hg::srv::Server& s = h->s;
+    std::lock_guard<std::mutex> lk(s.mu);
+    auto it = s.tables.find(table_id);
+    if (it == s.tables.end() || !it->second.built) return HG_ERR_NOT_FOUND;
+    const hg::srv::STable& t = it->second;
+    if (t.ready && hipStreamWaitEvent(stream, t.ready, 0) != hipSuccess) return HG_ERR_DEVICE;
+    hipError_t e = hipSuccess;
+    if (d_offsets)
+        e = hipMemcpyAsync(d_offsets, t.offsets, (t.V + 1) * 4, hipMemcpyDeviceToDevice, stream);
+    if (e == hipSuccess && d_ids && t.n)
+        e = hipMemcpyAsync(d_ids, t.ids, t.n * 4, hipMemcpyDeviceToDevice, stream);
+    if (e == hipSuccess && d_keys && t.n)
+        e = hipMemcpyAsync(d_keys, t.keys, t.n * (uint64_t)(t.key_bits / 8),
+                           hipMemcpyDeviceToDevice, stream);
+    // finish the copy before the table can be evicted
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    return e == hipSuccess ? HG_OK : HG_ERR_DEVICE;
+}
+
+hg_status hg_server_stats_get(hg_server* h, hg_server_stats* out) {
+    if (!h || !out) return HG_ERR_INVALID_ARG;
+    hg::srv::Server& s = h->s;
+    std::lock_guard<std::mutex> lk(s.mu);
+    hg_server_stats r{};
+    r.completed = s.completed;
+    r.failed = s.failed;
+    r.rejected = s.rejected;
+    r.evictions = s.evictions;
+    r.launches = s.launches;
+    r.merged_requests = s.merged;
+    r.keys = s.keys;
+    std::vector<double> v = s.lat_ms;
+    std::sort(v.begin(), v.end());
+    if (!v.empty()) {
+        auto q = [&](double f) {
+            size_t i = (size_t)(f * (double)(v.size() - 1) + 0.5);
+            return v[i < v.size() ? i : v.size() - 1];
+        };
+        r.p50_ms = q(0.50);
+        r.p99_ms = q(0.99);
+        r.max_ms = v.back();
+        double sum = 0;
+        for (double x : v) sum += x;
+        r.mean_ms = sum / (double)v.size();
+    }
+    r.busy_s = s.first_arrive >= 0 ? s.last_done - s.first_arrive : 0.0;
+    r.resident_bytes = s.resident;
+    r.peak_bytes = s.peak;
+    uint32_t nt = 0;
+    for (auto& kv : s.tables)
+        if (kv.second.built) ++nt;
+    r.resident_tables = nt;
+    *out = r;
+    return HG_OK;
+}
+
+hg_status hg_server_reset_stats(hg_server* h) {
+    if (!h) return HG_ERR_INVALID_ARG;
+    hg::srv::Server& s = h->s;
+    std::lock_guard<std::mutex> lk(s.mu);
+    s.lat_ms.clear();
+    s.completed = s.failed = s.rejected = s.evictions = s.launches = s.merged = s.keys = 0;
+    s.first_arrive = -1;
+    s.last_done = 0;
+    s.peak = s.resident + s.transient;
+    return HG_OK;
+}
+
+void hg_server_destroy(hg_server* h) {
+    if (!h) return;
+    hg::srv::Server& s = h->s;
+    {
+        std::lock_guard<std::mutex> lk(s.mu);
+        s.stop = true;
+        s.cv_work.notify_all();
+    }
+    if (s.worker.joinable()) s.worker.join();
+    for (auto q : s.streams) (void)hipStreamSynchronize(q);
+    for (auto& kv : s.tables) {
+        hg::srv::STable& t = kv.second;
+        if (t.offsets) (void)hipFreeAsync(t.offsets, s.streams[0]);
+        if (t.ids) (void)hipFreeAsync(t.ids, s.streams[0]);
+        if (t.keys) (void)hipFreeAsync(t.keys, s.streams[0]);
+        if (t.ready) (void)hipEventDestroy(t.ready);
+    }
+    for (auto q : s.streams) (void)hipStreamSynchronize(q);
+    for (auto e : s.event_pool) (void)hipEventDestroy(e);
+    for (auto& p : s.pinned_free) (void)hipHostFree(p.first);
+    for (auto q : s.streams) (void)hipStreamDestroy(q);
+    delete h;
+}
+
+}  // extern "C"

@@ -107,9 +107,11 @@ template <typename Key>
 hipError_t run_build_v1(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, uint32_t* offsets,
                         uint32_t* ids, Key* ekeys, void* ws, uint32_t block, hipStream_t s);
 
+// head (may be null): V 16-byte probe index entries, one per bucket.
 template <typename Key>
 hipError_t run_build_v2(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, uint32_t* offsets,
-                        uint32_t* ids, Key* ekeys, void* ws, uint32_t bins_hint, hipStream_t s);
+                        uint32_t* ids, Key* ekeys, uint4* head, void* ws, uint32_t bins_hint,
+                        hipStream_t s);
 
 // ---- probing ---------------------------------------------------------------
 struct TableDev {
@@ -117,6 +119,7 @@ struct TableDev {
     const uint32_t* ids;
     const void* keys;
     uint64_t n, V, seed;
+    const uint4* head = nullptr;  // per-bucket probe index, when the build wrote one
 };
 
 size_t probe_ws_bytes(uint64_t m);

@@ -2,7 +2,10 @@
 //
 // HashGraph-Probe-Standard: each query is hashed with Eq. 1, the bucket's
 // segment [offsets[h], offsets[h+1]) of the edge array is scanned, and every
-// entry with an equal key is counted (all instances, not the first).  Each
+// entry with an equal key is counted (all instances, not the first).  When
+// the V2 build wrote the per-bucket probe index, the segment bounds and the
+// bucket's first keys come from one 16-byte entry instead, so a query into a
+// bucket of at most two 32-bit keys (one 64-bit key) costs one random read.  Each
 // thread owns several queries (coalesced, strided by the block) and issues
 // all their offset loads before scanning, to keep many random reads in
 // flight.  Pairs are written in a second pass at positions given by an
@@ -29,15 +32,52 @@ __device__ __forceinline__ uint32_t count_in_bucket(const Key* __restrict__ ekey
     return c;
 }
 
+// Keys a probe index entry carries: {start, end, key0, key1} for 32-bit keys,
+// {start, end, key0 low, key0 high} for 64-bit keys.
 template <typename Key>
+struct HeadKeys;
+
+template <>
+struct HeadKeys<uint32_t> {
+    static constexpr uint32_t slots = 2;
+    __device__ static uint32_t key(const uint4& e, uint32_t i) { return i ? e.w : e.z; }
+};
+
+template <>
+struct HeadKeys<uint64_t> {
+    static constexpr uint32_t slots = 1;
+    __device__ static uint64_t key(const uint4& e, uint32_t) {
+        return (uint64_t)e.z | ((uint64_t)e.w << 32);
+    }
+};
+
+// Matches of q in a bucket described by its index entry: the keys held in the
+// entry are compared directly, the edge array is read only past them.
+template <typename Key>
+__device__ __forceinline__ uint32_t count_with_head(const uint4& e, const Key* __restrict__ ekeys,
+                                                    Key q) {
+    using HK = HeadKeys<Key>;
+    const uint32_t len = e.y - e.x;
+    uint32_t c = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < HK::slots; ++i) c += (len > i && HK::key(e, i) == q) ? 1u : 0u;
+    if (len > HK::slots) c += count_in_bucket(ekeys, e.x + HK::slots, e.y, q);
+    return c;
+}
+
+// Probe-Standard counts.  HEAD: each query reads its bucket's 16-byte index
+// entry (one random access for buckets of up to two keys); otherwise it reads
+// offsets[h], offsets[h+1] and scans the edge array.
+template <typename Key, bool HEAD>
 __global__ __launch_bounds__(kProbeThreads) void k_probe_count(
     const Key* __restrict__ q, uint64_t m, typename KeyTraits<Key>::Params hp,
-    const uint32_t* __restrict__ off, const Key* __restrict__ ekeys, uint32_t* __restrict__ counts,
+    const uint32_t* __restrict__ off, const uint4* __restrict__ head,
+    const Key* __restrict__ ekeys, uint32_t* __restrict__ counts,
     unsigned long long* __restrict__ total) {
     __shared__ uint64_t red[kProbeThreads / kWave + 1];
     const uint64_t base = (uint64_t)blockIdx.x * (kProbeThreads * kProbeItems) + threadIdx.x;
     Key qq[kProbeItems];
-    uint32_t lo[kProbeItems], hi[kProbeItems];
+    uint4 e[kProbeItems];
 #pragma unroll
     for (int r = 0; r < kProbeItems; ++r) {
         const uint64_t j = base + (uint64_t)r * kProbeThreads;
@@ -48,17 +88,22 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_count(
         const uint64_t j = base + (uint64_t)r * kProbeThreads;
         if (j < m) {
             const uint32_t h = KeyTraits<Key>::bucket(qq[r], hp);
-            lo[r] = off[h];
-            hi[r] = off[h + 1];
+            if (HEAD) {
+                e[r] = head[h];
+            } else {
+                e[r].x = off[h];
+                e[r].y = off[h + 1];
+            }
         } else {
-            lo[r] = hi[r] = 0;
+            e[r] = make_uint4(0u, 0u, 0u, 0u);
         }
     }
     uint64_t sum = 0;
 #pragma unroll
     for (int r = 0; r < kProbeItems; ++r) {
         const uint64_t j = base + (uint64_t)r * kProbeThreads;
-        const uint32_t c = count_in_bucket(ekeys, lo[r], hi[r], qq[r]);
+        const uint32_t c = HEAD ? count_with_head(e[r], ekeys, qq[r])
+                                : count_in_bucket(ekeys, e[r].x, e[r].y, qq[r]);
         if (j < m && counts) counts[j] = c;
         sum += c;
     }
@@ -69,21 +114,30 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_count(
     }
 }
 
-template <typename Key>
+template <typename Key, bool HEAD>
 __global__ __launch_bounds__(kProbeThreads) void k_probe_pairs(
     const Key* __restrict__ q, uint64_t m, typename KeyTraits<Key>::Params hp,
-    const uint32_t* __restrict__ off, const Key* __restrict__ ekeys,
-    const uint32_t* __restrict__ eids, const uint64_t* __restrict__ positions,
-    uint32_t* __restrict__ build_ids, uint32_t* __restrict__ probe_ids) {
+    const uint32_t* __restrict__ off, const uint4* __restrict__ head,
+    const Key* __restrict__ ekeys, const uint32_t* __restrict__ eids,
+    const uint64_t* __restrict__ positions, uint32_t* __restrict__ build_ids,
+    uint32_t* __restrict__ probe_ids) {
+    using HK = HeadKeys<Key>;
     uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t st = (uint64_t)gridDim.x * blockDim.x;
     for (; j < m; j += st) {
         const Key k = q[j];
         const uint32_t h = KeyTraits<Key>::bucket(k, hp);
-        const uint32_t lo = off[h], hi = off[h + 1];
+        uint4 e;
+        if (HEAD) {
+            e = head[h];
+        } else {
+            e.x = off[h];
+            e.y = off[h + 1];
+        }
+        const uint32_t lo = e.x, hi = e.y;
         uint64_t pos = positions[j];
         for (uint32_t p = lo; p < hi; ++p)
-            if (ekeys[p] == k) {
+            if ((HEAD && p - lo < HK::slots ? HK::key(e, p - lo) : ekeys[p]) == k) {
                 build_ids[pos] = eids[p];
                 probe_ids[pos] = (uint32_t)j;
                 ++pos;
@@ -164,9 +218,15 @@ hipError_t run_probe_counts(const TableDev& t, const Key* queries, uint64_t m, u
     auto hp = KeyTraits<Key>::make(t.V, t.seed);
     {
         HG_PROF("probe_count", s);
-        hipLaunchKernelGGL(k_probe_count<Key>, dim3(grid_for(m, kProbeThreads * kProbeItems)),
-                           dim3(kProbeThreads), 0, s, queries, m, hp, t.offsets, (const Key*)t.keys,
-                           counts, d_total);
+        const dim3 grid(grid_for(m, kProbeThreads * kProbeItems));
+        if (t.head)
+            hipLaunchKernelGGL((k_probe_count<Key, true>), grid, dim3(kProbeThreads), 0, s,
+                               queries, m, hp, t.offsets, t.head, (const Key*)t.keys, counts,
+                               d_total);
+        else
+            hipLaunchKernelGGL((k_probe_count<Key, false>), grid, dim3(kProbeThreads), 0, s,
+                               queries, m, hp, t.offsets, t.head, (const Key*)t.keys, counts,
+                               d_total);
     }
     return hipGetLastError();
 }
@@ -181,8 +241,14 @@ hipError_t run_probe_pairs(const TableDev& t, const Key* queries, uint64_t m,
     if (g > 8192) g = 8192;
     {
         HG_PROF("probe_pairs", s);
-        hipLaunchKernelGGL(k_probe_pairs<Key>, dim3(g), dim3(kProbeThreads), 0, s, queries, m, hp,
-                           t.offsets, (const Key*)t.keys, t.ids, positions, build_ids, probe_ids);
+        if (t.head)
+            hipLaunchKernelGGL((k_probe_pairs<Key, true>), dim3(g), dim3(kProbeThreads), 0, s,
+                               queries, m, hp, t.offsets, t.head, (const Key*)t.keys, t.ids,
+                               positions, build_ids, probe_ids);
+        else
+            hipLaunchKernelGGL((k_probe_pairs<Key, false>), dim3(g), dim3(kProbeThreads), 0, s,
+                               queries, m, hp, t.offsets, t.head, (const Key*)t.keys, t.ids,
+                               positions, build_ids, probe_ids);
     }
     return hipGetLastError();
 }

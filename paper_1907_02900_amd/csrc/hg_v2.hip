@@ -22,15 +22,13 @@
 // Stable ranking (rank_stable) finds equal digits in a round of 64 items with
 // one ballot per digit bit and keeps per-wave running counts in LDS, updated
 // with non-returning atomics so that rounds do not wait on each other.
-#include "hg_internal.h"
+#include "hg_v2_device.h"
 
 namespace hg {
 
 namespace {
 
-constexpr int W_PART = kPartThreads / kWave;
-constexpr int W_LOCAL = kLocalThreads / kWave;
-constexpr uint32_t kFixMax = 16;  // longest bucket the insertion-sort path handles
+using namespace v2dev;
 
 // Segments of the source array, each cut into tiles of kPartTile entries, and
 // the tiles grouped into chunks of `ch` consecutive tiles for the column scan.
@@ -70,83 +68,6 @@ __device__ __forceinline__ bool locate_tile(const Segs& g, uint32_t t, uint32_t&
 __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t ub) {
     const uint32_t per = (ub + 7) >> 3;
     return (b & 7u) * per + (b >> 3);
-}
-
-// ------------------------------------------------------------ ranking -----
-
-// Digit-major exclusive scan of the per-wave digit counters wcnt[w][d]
-// (W waves, D digits): afterwards wcnt[w][d] holds the position of wave w's
-// first item of digit d in the stably sorted tile, and dstart[d] the start
-// of digit d.  Barrier on exit.
-template <int THREADS>
-__device__ __forceinline__ void scan_wave_digit_counts(uint32_t D, uint32_t* wcnt,
-                                                       uint32_t* dstart, uint32_t* tmp) {
-    constexpr int W = THREADS / kWave;
-    const uint32_t per = (D + THREADS - 1) / THREADS;
-    const uint32_t d0 = threadIdx.x * per;
-    uint32_t mine = 0;
-    for (uint32_t j = 0; j < per; ++j) {
-        const uint32_t d = d0 + j;
-        if (d < D)
-#pragma unroll
-            for (int w = 0; w < W; ++w) mine += wcnt[w * D + d];
-    }
-    uint32_t all;
-    uint32_t run = block_excl_scan<THREADS>(mine, tmp, &all);
-    for (uint32_t j = 0; j < per; ++j) {
-        const uint32_t d = d0 + j;
-        if (d < D) {
-            dstart[d] = run;
-#pragma unroll
-            for (int w = 0; w < W; ++w) {
-                const uint32_t v = wcnt[w * D + d];
-                wcnt[w * D + d] = run;
-                run += v;
-            }
-        }
-    }
-    __syncthreads();
-}
-
-// Stable rank of up to 64*ITEMS items per wave by a digit of `bits` bits
-// (D = 2^bits <= 2048).  Item r of a lane is entry (wave base + r*64 + lane);
-// items with dig >= D are ignored; `rounds` (wave-uniform) bounds the rounds
-// holding valid items.  Per round every lane reads its digit's running count
-// in the wave's counter row and the lowest lane of each group of equal digits
-// adds the group's size with a non-returning LDS atomic.  LDS performs a
-// wave's operations in issue order, so a read sees exactly the items of the
-// wave's earlier rounds, and no round waits for the previous one.  On return
-// pos[r] is the item's index in the tile sorted stably by digit.  Contains
-// barriers.
-template <int THREADS, int ITEMS>
-__device__ __forceinline__ void rank_stable(const uint32_t (&dig)[ITEMS], uint32_t rounds,
-                                            uint32_t bits, uint32_t* wcnt, uint32_t* dstart,
-                                            uint32_t* tmp, uint32_t (&pos)[ITEMS]) {
-    constexpr int W = THREADS / kWave;
-    const uint32_t D = 1u << bits;
-    const uint32_t w = threadIdx.x / kWave;
-    for (uint32_t i = threadIdx.x; i < W * D; i += THREADS) wcnt[i] = 0;
-    __syncthreads();
-    uint32_t* my = wcnt + w * D;
-#pragma unroll
-    for (int r = 0; r < ITEMS; ++r) {
-        if ((uint32_t)r >= rounds) break;
-        const uint32_t d = dig[r];
-        const bool valid = d < D;
-        const uint64_t peers = match_digit(d, (int)bits, ballot(valid));
-        if (valid) {
-            const uint32_t below = mbcnt(peers);
-            pos[r] = my[d] + below;
-            if (below == 0)
-                __hip_atomic_fetch_add(&my[d], (uint32_t)__popcll(peers), __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP);
-        }
-    }
-    __syncthreads();
-    scan_wave_digit_counts<THREADS>(D, wcnt, dstart, tmp);
-#pragma unroll
-    for (int r = 0; r < ITEMS; ++r)
-        if ((uint32_t)r < rounds && dig[r] < D) pos[r] += my[dig[r]];
 }
 
 // ---------------------------------------------------- tile histograms -----
@@ -446,341 +367,45 @@ __global__ void k_bin_starts(const uint32_t* __restrict__ base, Segs g, uint32_t
     }
 }
 
-// -------------------------------------------------- per-bin LDS build -----
-
-// Place one chunk of <= ITEMS*64*W entries held in registers: two stable LSD
-// ranking passes over the local bucket index (lo bits, then hi bits) leave
-// the chunk sorted by bucket in skeys/sids/sb.  Items are balanced over the
-// waves: wave w owns entries [w*chunk, (w+1)*chunk).
-template <typename Key, int ITEMS>
-__device__ __forceinline__ void sort_chunk_by_bucket(Key (&kk)[ITEMS], uint32_t (&id)[ITEMS],
-                                                     uint32_t (&b)[ITEMS], uint32_t rounds,
-                                                     uint32_t cl, uint32_t wchunk, uint32_t k,
-                                                     Key* skeys, uint32_t* sids, uint16_t* sb,
-                                                     uint32_t* wcnt, uint32_t* dstart,
-                                                     uint32_t* tmp) {
-    const uint32_t NB = 1u << k;
-    const uint32_t lo_bits = (k + 1) / 2, hi_bits = k / 2;
-    const uint32_t w = threadIdx.x / kWave, lane = lane_id();
-    uint32_t dig[ITEMS], pos[ITEMS];
-    if (k == 0) {
-#pragma unroll
-        for (int r = 0; r < ITEMS; ++r) {
-            const uint32_t e = w * wchunk + r * kWave + lane;
-            if ((uint32_t)r < rounds && r * kWave + lane < wchunk && e < cl) {
-                skeys[e] = kk[r];
-                sids[e] = id[r];
-                sb[e] = 0;
-            }
-        }
-        return;
-    }
-#pragma unroll
-    for (int r = 0; r < ITEMS; ++r) dig[r] = (b[r] < NB) ? (b[r] & ((1u << lo_bits) - 1)) : 64u;
-    rank_stable<kLocalThreads, ITEMS>(dig, rounds, lo_bits, wcnt, dstart, tmp, pos);
-#pragma unroll
-    for (int r = 0; r < ITEMS; ++r)
-        if ((uint32_t)r < rounds && b[r] < NB) {
-            skeys[pos[r]] = kk[r];
-            sids[pos[r]] = id[r];
-            sb[pos[r]] = (uint16_t)b[r];
-        }
-    __syncthreads();
-    if (hi_bits == 0) return;
-#pragma unroll
-    for (int r = 0; r < ITEMS; ++r) {
-        const uint32_t e = w * wchunk + r * kWave + lane;
-        if ((uint32_t)r < rounds && r * kWave + lane < wchunk && e < cl) {
-            kk[r] = skeys[e];
-            id[r] = sids[e];
-            b[r] = sb[e];
-            dig[r] = b[r] >> lo_bits;
-        } else {
-            b[r] = NB;
-            dig[r] = 64u;
-        }
-    }
-    // rank_stable synchronises before counting, so every wave has finished
-    // reading the buffers before any wave overwrites them below
-    rank_stable<kLocalThreads, ITEMS>(dig, rounds, hi_bits, wcnt, dstart, tmp, pos);
-#pragma unroll
-    for (int r = 0; r < ITEMS; ++r)
-        if ((uint32_t)r < rounds && b[r] < NB) {
-            skeys[pos[r]] = kk[r];
-            sids[pos[r]] = id[r];
-            sb[pos[r]] = (uint16_t)b[r];
-        }
-}
-
-// Exclusive scan of cnt[0..NB) in place (NB a power of two); returns via
-// cnt; *total gets the sum.  All threads must call it.
-__device__ __forceinline__ void scan_counts(uint32_t* cnt, uint32_t NB, uint32_t base,
-                                            uint32_t* tmp) {
-    const uint32_t per = NB >= (uint32_t)kLocalThreads ? NB / kLocalThreads : 1u;
-    const uint32_t i0 = threadIdx.x * per;
-    uint32_t v[16];
-    uint32_t mine = 0;
-    for (uint32_t j = 0; j < per; ++j) {
-        v[j] = (i0 + j < NB) ? cnt[i0 + j] : 0u;
-        mine += v[j];
-    }
-    uint32_t all;
-    uint32_t run = base + block_excl_scan<kLocalThreads>(mine, tmp, &all);
-    for (uint32_t j = 0; j < per; ++j)
-        if (i0 + j < NB) {
-            cnt[i0 + j] = run;
-            run += v[j];
-        }
-    __syncthreads();
-}
-
-// Exclusive scan of cnt[0..NB) in place (base 0); returns the largest count.
-// `tmp` needs 2 * (waves per block) words.  All threads must call it.
-__device__ __forceinline__ uint32_t scan_counts_max(uint32_t* cnt, uint32_t NB, uint32_t* tmp) {
-    const uint32_t per = NB >= (uint32_t)kLocalThreads ? NB / kLocalThreads : 1u;
-    const uint32_t i0 = threadIdx.x * per;
-    uint32_t v[16];
-    uint32_t mine = 0, mx = 0;
-    for (uint32_t j = 0; j < per; ++j) {
-        v[j] = (i0 + j < NB) ? cnt[i0 + j] : 0u;
-        mine += v[j];
-        mx = v[j] > mx ? v[j] : mx;
-    }
-#pragma unroll
-    for (int d = kWave / 2; d >= 1; d >>= 1) {
-        const uint32_t o = __shfl_xor(mx, d, kWave);
-        mx = o > mx ? o : mx;
-    }
-    uint32_t all;
-    uint32_t run = block_excl_scan<kLocalThreads>(mine, tmp, &all);
-    if (lane_id() == 0) tmp[W_LOCAL + threadIdx.x / kWave] = mx;
-    for (uint32_t j = 0; j < per; ++j)
-        if (i0 + j < NB) {
-            cnt[i0 + j] = run;
-            run += v[j];
-        }
-    __syncthreads();
-    uint32_t m = 0;
-#pragma unroll
-    for (int i = 0; i < W_LOCAL; ++i) m = tmp[W_LOCAL + i] > m ? tmp[W_LOCAL + i] : m;
-    __syncthreads();
-    return m;
-}
-
 // One workgroup per final bin g (buckets [g*2^k, min((g+1)*2^k, V))) that
-// holds at most kLightCap keys.  Usual case (every bucket of the bin holds at
-// most kFixMax keys): LDS counting sort by bucket with atomic cursors, then
-// an insertion sort by id inside each bucket restores input order.  A bin
-// with a longer bucket is sorted by the stable two-pass ranking instead.
+// holds at most kLightCap keys.
 template <typename Key>
 __global__ __launch_bounds__(kLocalThreads) void k_local_light(
     const Key* __restrict__ src_keys, const uint32_t* __restrict__ src_ids,
     const uint32_t* __restrict__ bin_start, typename KeyTraits<Key>::Params hp, uint32_t k,
-    uint32_t* __restrict__ offsets, uint32_t* __restrict__ ids, Key* __restrict__ ekeys) {
-    constexpr int IT = kLightItems;
-    const uint32_t NB = 1u << k;
+    uint32_t* __restrict__ offsets, uint4* __restrict__ head, uint32_t* __restrict__ ids,
+    Key* __restrict__ ekeys) {
     extern __shared__ __align__(16) unsigned char smem[];
-    Key* skeys = (Key*)smem;
-    uint32_t* sids = (uint32_t*)(skeys + kLightCap);
-    uint16_t* sb = (uint16_t*)(sids + kLightCap);
-    uint32_t* cnt = (uint32_t*)(sb + kLightCap);  // NB
-    uint32_t* wcnt = cnt + NB;                     // W * 64
-    uint32_t* dstart = wcnt + W_LOCAL * 64;        // 64
-    uint32_t* tmp = dstart + 64;
-
     const uint32_t g = blockIdx.x;
     const uint32_t start = bin_start[g], end = bin_start[g + 1];
     const uint32_t L = end - start;
     if (L > kLightCap) return;  // oversize bins go to k_local_heavy
-    const uint32_t v0 = g << k;
-    const uint32_t V = hp.range;
+    const uint32_t NB = 1u << k, v0 = g << k, V = hp.range;
     const uint32_t nb = (V - v0 < NB) ? V - v0 : NB;
-    const uint32_t w = threadIdx.x / kWave, lane = lane_id();
-    // balance the bin over the waves in whole rounds of 64
-    const uint32_t wchunk = (((L + W_LOCAL - 1) / W_LOCAL) + kWave - 1) & ~(uint32_t)(kWave - 1);
-    const uint32_t wb = w * wchunk;
-    const uint32_t mylen = L > wb ? ((L - wb < wchunk) ? L - wb : wchunk) : 0u;
-    const uint32_t rounds = (mylen + kWave - 1) / kWave;
-
-    Key kk[IT];
-    uint32_t id[IT], b[IT];
-#pragma unroll
-    for (int r = 0; r < IT; ++r) {
-        const uint32_t e = wb + r * kWave + lane;
-        if ((uint32_t)r < rounds && r * kWave + lane < mylen) {
-            kk[r] = src_keys[start + e];
-            id[r] = src_ids[start + e];
-        } else {
-            kk[r] = 0;
-            id[r] = 0;
-        }
-    }
-    for (uint32_t i = threadIdx.x; i < NB; i += kLocalThreads) cnt[i] = 0;
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < IT; ++r) {
-        if ((uint32_t)r < rounds && r * kWave + lane < mylen) {
-            b[r] = KeyTraits<Key>::bucket(kk[r], hp) - v0;
-            atomicAdd(&cnt[b[r]], 1u);
-        } else {
-            b[r] = NB;
-        }
-    }
-    __syncthreads();
-    // bucket starts (in place) and the largest bucket of the bin
-    const uint32_t maxc = scan_counts_max(cnt, NB, tmp);
-    if (maxc <= kFixMax) {
-        // counting-sort placement through per-bucket cursors, then the few
-        // entries of each bucket are put back in id order by insertion sort
-#pragma unroll
-        for (int r = 0; r < IT; ++r) {
-            if (b[r] < NB) {
-                const uint32_t slot = atomicAdd(&cnt[b[r]], 1u);
-                skeys[slot] = kk[r];
-                sids[slot] = id[r];
-            }
-        }
-        __syncthreads();
-        // cnt[v] is now the end of bucket v
-        for (uint32_t v = threadIdx.x; v < NB; v += kLocalThreads) {
-            const uint32_t lo = v ? cnt[v - 1] : 0u, hi = cnt[v];
-            for (uint32_t i = lo + 1; i < hi; ++i) {
-                const uint32_t idv = sids[i];
-                const Key kv = skeys[i];
-                uint32_t j = i;
-                while (j > lo && sids[j - 1] > idv) {
-                    sids[j] = sids[j - 1];
-                    skeys[j] = skeys[j - 1];
-                    --j;
-                }
-                sids[j] = idv;
-                skeys[j] = kv;
-            }
-        }
-        __syncthreads();
-        for (uint32_t v = threadIdx.x; v < nb; v += kLocalThreads)
-            offsets[v0 + v] = start + (v ? cnt[v - 1] : 0u);
-    } else {
-        // a long bucket: stable LSD ranking of the whole bin by local bucket
-        // (the bin arrives in id order from the stable partitions)
-        sort_chunk_by_bucket<Key, IT>(kk, id, b, rounds, L, wchunk, k, skeys, sids, sb, wcnt,
-                                      dstart, tmp);
-        __syncthreads();
-        for (uint32_t v = threadIdx.x; v < nb; v += kLocalThreads) offsets[v0 + v] = start + cnt[v];
-    }
-    for (uint32_t p = threadIdx.x; p < L; p += kLocalThreads) {
-        ekeys[start + p] = skeys[p];
-        ids[start + p] = sids[p];
-    }
+    light_bin_body<Key>(src_keys + start, src_ids + start, 0u, L, start, v0, k, nb, hp, offsets,
+                        head, ids, ekeys, smem);
 }
 
-// Oversize bins (from the device list): one workgroup per bin, the bin's
-// keys counted per bucket first, then placed chunk by chunk (in order) with
-// running per-bucket cursors, so placement stays stable.
+// Oversize bins (from the device list), one workgroup per bin.
 template <typename Key>
 __global__ __launch_bounds__(kLocalThreads) void k_local_heavy(
     const Key* __restrict__ src_keys, const uint32_t* __restrict__ src_ids,
     const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ heavy_list,
     const uint32_t* __restrict__ heavy_count, typename KeyTraits<Key>::Params hp, uint32_t k,
-    uint32_t* __restrict__ offsets, uint32_t* __restrict__ ids, Key* __restrict__ ekeys) {
-    constexpr int IT = kHeavyItems;
-    constexpr uint32_t CAP = kHeavyChunk;
-    const uint32_t NB = 1u << k;
+    uint32_t* __restrict__ offsets, uint4* __restrict__ head, uint32_t* __restrict__ ids,
+    Key* __restrict__ ekeys) {
     extern __shared__ __align__(16) unsigned char smem[];
-    Key* skeys = (Key*)smem;
-    uint32_t* sids = (uint32_t*)(skeys + CAP);
-    uint16_t* sb = (uint16_t*)(sids + CAP);
-    uint32_t* cur = (uint32_t*)(sb + CAP);  // NB: running cursors
-    uint32_t* tcnt = cur + NB;              // NB: chunk-local bucket starts
-    uint32_t* wcnt = tcnt + NB;
-    uint32_t* dstart = wcnt + W_LOCAL * 64;
-    uint32_t* tmp = dstart + 64;
-    const uint32_t V = hp.range;
-    const uint32_t w = threadIdx.x / kWave, lane = lane_id();
+    const uint32_t NB = 1u << k, V = hp.range;
     const uint32_t nheavy = *heavy_count;
-
-    for (uint32_t hi = blockIdx.x; hi < nheavy; hi += gridDim.x) {
-        const uint32_t g = heavy_list[hi];
+    for (uint32_t i = blockIdx.x; i < nheavy; i += gridDim.x) {
+        const uint32_t g = heavy_list[i];
         const uint32_t start = bin_start[g], end = bin_start[g + 1];
-        const uint32_t L = end - start;
         const uint32_t v0 = g << k;
         const uint32_t nb = (V - v0 < NB) ? V - v0 : NB;
-        for (uint32_t i = threadIdx.x; i < NB; i += kLocalThreads) cur[i] = 0;
+        heavy_bin_body<Key>(src_keys + start, src_ids + start, 0u, end - start, start, v0, k, nb,
+                            hp, offsets, head, ids, ekeys, smem);
         __syncthreads();
-        for (uint32_t i = start + threadIdx.x; i < end; i += kLocalThreads)
-            atomicAdd(&cur[KeyTraits<Key>::bucket(src_keys[i], hp) - v0], 1u);
-        __syncthreads();
-        scan_counts(cur, NB, start, tmp);
-        for (uint32_t i = threadIdx.x; i < nb; i += kLocalThreads) offsets[v0 + i] = cur[i];
-        const uint32_t nchunk = (uint32_t)(((uint64_t)L + CAP - 1) / CAP);
-        for (uint32_t ci = 0; ci < nchunk; ++ci) {
-            const uint32_t c0 = ci * CAP;
-            const uint32_t cl = (L - c0 < CAP) ? L - c0 : CAP;
-            const uint32_t wchunk =
-                (((cl + W_LOCAL - 1) / W_LOCAL) + kWave - 1) & ~(uint32_t)(kWave - 1);
-            const uint32_t wb = w * wchunk;
-            const uint32_t mylen = cl > wb ? ((cl - wb < wchunk) ? cl - wb : wchunk) : 0u;
-            const uint32_t rounds = (mylen + kWave - 1) / kWave;
-            Key kk[IT];
-            uint32_t id[IT], b[IT];
-#pragma unroll
-            for (int r = 0; r < IT; ++r) {
-                const uint32_t e = wb + r * kWave + lane;
-                if ((uint32_t)r < rounds && r * kWave + lane < mylen) {
-                    kk[r] = src_keys[start + c0 + e];
-                    id[r] = src_ids[start + c0 + e];
-                } else {
-                    kk[r] = 0;
-                    id[r] = 0;
-                }
-            }
-            for (uint32_t i = threadIdx.x; i < NB; i += kLocalThreads) tcnt[i] = 0;
-            __syncthreads();
-#pragma unroll
-            for (int r = 0; r < IT; ++r) {
-                if ((uint32_t)r < rounds && r * kWave + lane < mylen) {
-                    b[r] = KeyTraits<Key>::bucket(kk[r], hp) - v0;
-                    atomicAdd(&tcnt[b[r]], 1u);
-                } else {
-                    b[r] = NB;
-                }
-            }
-            sort_chunk_by_bucket<Key, IT>(kk, id, b, rounds, cl, wchunk, k, skeys, sids, sb, wcnt,
-                                          dstart, tmp);
-            __syncthreads();
-            // chunk-local bucket starts: exclusive scan of tcnt, keeping the
-            // counts to advance the cursors afterwards
-            scan_counts(tcnt, NB, 0u, tmp);
-            for (uint32_t p = threadIdx.x; p < cl; p += kLocalThreads) {
-                const uint32_t bb = sb[p];
-                const uint32_t o = cur[bb] + (p - tcnt[bb]);
-                if (o - start < L) {
-                    ekeys[o] = skeys[p];
-                    ids[o] = sids[p];
-                }
-            }
-            __syncthreads();
-            for (uint32_t i = threadIdx.x; i < NB; i += kLocalThreads) {
-                const uint32_t nxt = (i + 1 < NB) ? tcnt[i + 1] : cl;
-                cur[i] += nxt - tcnt[i];
-            }
-            __syncthreads();
-        }
     }
-}
-
-template <typename Key>
-size_t light_smem(uint32_t k) {
-    const size_t NB = 1u << k;
-    return kLightCap * (sizeof(Key) + 4 + 2) + NB * 4 + W_LOCAL * 64 * 4 + 64 * 4 +
-           (W_LOCAL + 1) * 4 + 64;
-}
-
-template <typename Key>
-size_t heavy_smem(uint32_t k) {
-    const size_t NB = 1u << k;
-    return kHeavyChunk * (sizeof(Key) + 4 + 2) + 2 * NB * 4 + W_LOCAL * 64 * 4 + 64 * 4 +
-           (W_LOCAL + 1) * 4 + 64;
 }
 
 }  // namespace
@@ -951,9 +576,13 @@ size_t build_ws_bytes(int variant, uint64_t n, uint64_t V, int key_bits, uint32_
 
 template <typename Key>
 hipError_t run_build_v2(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, uint32_t* offsets,
-                        uint32_t* ids, Key* ekeys, void* ws, uint32_t bins_hint, hipStream_t s) {
+                        uint32_t* ids, Key* ekeys, uint4* head, void* ws, uint32_t bins_hint,
+                        hipStream_t s) {
     HG_TRY(set_smem_limits<Key>());
-    if (n == 0) return fill_u32(offsets, V + 1, 0u, s);
+    if (n == 0) {
+        if (head) HG_TRY(fill_u32((uint32_t*)head, 4 * V, 0u, s));
+        return fill_u32(offsets, V + 1, 0u, s);
+    }
     const V2Plan p = plan_v2(n, V, sizeof(Key) * 8, bins_hint);
     V2Ws w;
     layout_v2(ws, p, sizeof(Key), &w);
@@ -1001,7 +630,7 @@ hipError_t run_build_v2(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, 
         HG_PROF("v2_local_build", s);
         hipLaunchKernelGGL(k_local_light<Key>, dim3(p.bins), dim3(kLocalThreads),
                            light_smem<Key>(p.k), s, (const Key*)rkeys, (const uint32_t*)w.rids,
-                           (const uint32_t*)w.bin_start, hp, p.k, offsets, ids, ekeys);
+                           (const uint32_t*)w.bin_start, hp, p.k, offsets, head, ids, ekeys);
     }
     HG_TRY(hipGetLastError());
     {
@@ -1010,16 +639,17 @@ hipError_t run_build_v2(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, 
         hipLaunchKernelGGL(k_local_heavy<Key>, dim3(hg_grid), dim3(kLocalThreads),
                            heavy_smem<Key>(p.k), s, (const Key*)rkeys, (const uint32_t*)w.rids,
                            (const uint32_t*)w.bin_start, (const uint32_t*)w.heavy_list,
-                           (const uint32_t*)w.heavy_count, hp, p.k, offsets, ids, ekeys);
+                           (const uint32_t*)w.heavy_count, hp, p.k, offsets, head, ids,
+                           ekeys);
     }
     return hipGetLastError();
 }
 
 template hipError_t run_build_v2<uint32_t>(const uint32_t*, uint64_t, uint64_t, uint64_t,
-                                           uint32_t*, uint32_t*, uint32_t*, void*, uint32_t,
-                                           hipStream_t);
+                                           uint32_t*, uint32_t*, uint32_t*, uint4*, void*,
+                                           uint32_t, hipStream_t);
 template hipError_t run_build_v2<uint64_t>(const uint64_t*, uint64_t, uint64_t, uint64_t,
-                                           uint32_t*, uint32_t*, uint64_t*, void*, uint32_t,
-                                           hipStream_t);
+                                           uint32_t*, uint32_t*, uint64_t*, uint4*, void*,
+                                           uint32_t, hipStream_t);
 
 }  // namespace hg

@@ -1,0 +1,456 @@
+// Device code shared by the single-table V2 build (hg_v2.hip) and the batched
+// build (hg_batch.hip): stable ranking of a tile by a digit, in-LDS sorting of
+// a bin by bucket, and the per-bin build bodies.
+#pragma once
+
+#include "hg_internal.h"
+
+namespace hg {
+namespace v2dev {
+
+constexpr int W_PART = kPartThreads / kWave;
+constexpr int W_LOCAL = kLocalThreads / kWave;
+constexpr uint32_t kFixMax = 16;  // longest bucket the insertion-sort path handles
+
+// ------------------------------------------------------------ ranking -----
+
+// Digit-major exclusive scan of the per-wave digit counters wcnt[w][d]
+// (W waves, D digits): afterwards wcnt[w][d] holds the position of wave w's
+// first item of digit d in the stably sorted tile, and dstart[d] the start
+// of digit d.  Barrier on exit.
+template <int THREADS>
+__device__ __forceinline__ void scan_wave_digit_counts(uint32_t D, uint32_t* wcnt,
+                                                       uint32_t* dstart, uint32_t* tmp) {
+    constexpr int W = THREADS / kWave;
+    const uint32_t per = (D + THREADS - 1) / THREADS;
+    const uint32_t d0 = threadIdx.x * per;
+    uint32_t mine = 0;
+    for (uint32_t j = 0; j < per; ++j) {
+        const uint32_t d = d0 + j;
+        if (d < D)
+#pragma unroll
+            for (int w = 0; w < W; ++w) mine += wcnt[w * D + d];
+    }
+    uint32_t all;
+    uint32_t run = block_excl_scan<THREADS>(mine, tmp, &all);
+    for (uint32_t j = 0; j < per; ++j) {
+        const uint32_t d = d0 + j;
+        if (d < D) {
+            dstart[d] = run;
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                const uint32_t v = wcnt[w * D + d];
+                wcnt[w * D + d] = run;
+                run += v;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Stable rank of up to 64*ITEMS items per wave by a digit of `bits` bits
+// (D = 2^bits <= 2048).  Item r of a lane is entry (wave base + r*64 + lane);
+// items with dig >= D are ignored; `rounds` (wave-uniform) bounds the rounds
+// holding valid items.  Per round every lane reads its digit's running count
+// in the wave's counter row and the lowest lane of each group of equal digits
+// adds the group's size with a non-returning LDS atomic.  LDS performs a
+// wave's operations in issue order, so a read sees exactly the items of the
+// wave's earlier rounds, and no round waits for the previous one.  On return
+// pos[r] is the item's index in the tile sorted stably by digit.  Contains
+// barriers.
+template <int THREADS, int ITEMS>
+__device__ __forceinline__ void rank_stable(const uint32_t (&dig)[ITEMS], uint32_t rounds,
+                                            uint32_t bits, uint32_t* wcnt, uint32_t* dstart,
+                                            uint32_t* tmp, uint32_t (&pos)[ITEMS]) {
+    constexpr int W = THREADS / kWave;
+    const uint32_t D = 1u << bits;
+    const uint32_t w = threadIdx.x / kWave;
+    for (uint32_t i = threadIdx.x; i < W * D; i += THREADS) wcnt[i] = 0;
+    __syncthreads();
+    uint32_t* my = wcnt + w * D;
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+        if ((uint32_t)r < rounds) {  // wave-uniform
+            const uint32_t d = dig[r];
+            const bool valid = d < D;
+            const uint64_t peers = match_digit(d, (int)bits, ballot(valid));
+            if (valid) {
+                const uint32_t below = mbcnt(peers);
+                pos[r] = my[d] + below;
+                if (below == 0)
+                    __hip_atomic_fetch_add(&my[d], (uint32_t)__popcll(peers), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        }
+    }
+    __syncthreads();
+    scan_wave_digit_counts<THREADS>(D, wcnt, dstart, tmp);
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r)
+        if ((uint32_t)r < rounds && dig[r] < D) pos[r] += my[dig[r]];
+}
+
+// -------------------------------------------------- per-bin LDS build -----
+
+// Place one chunk of <= ITEMS*64*W entries held in registers: two stable LSD
+// ranking passes over the local bucket index (lo bits, then hi bits) leave
+// the chunk sorted by bucket in skeys/sids/sb.  Items are balanced over the
+// waves: wave w owns entries [w*chunk, (w+1)*chunk).
+template <typename Key, int ITEMS>
+__device__ __forceinline__ void sort_chunk_by_bucket(Key (&kk)[ITEMS], uint32_t (&id)[ITEMS],
+                                                     uint32_t (&b)[ITEMS], uint32_t rounds,
+                                                     uint32_t cl, uint32_t wchunk, uint32_t k,
+                                                     Key* skeys, uint32_t* sids, uint16_t* sb,
+                                                     uint32_t* wcnt, uint32_t* dstart,
+                                                     uint32_t* tmp) {
+    const uint32_t NB = 1u << k;
+    const uint32_t lo_bits = (k + 1) / 2, hi_bits = k / 2;
+    const uint32_t w = threadIdx.x / kWave, lane = lane_id();
+    uint32_t dig[ITEMS], pos[ITEMS];
+    if (k == 0) {
+#pragma unroll
+        for (int r = 0; r < ITEMS; ++r) {
+            const uint32_t e = w * wchunk + r * kWave + lane;
+            if ((uint32_t)r < rounds && r * kWave + lane < wchunk && e < cl) {
+                skeys[e] = kk[r];
+                sids[e] = id[r];
+                sb[e] = 0;
+            }
+        }
+        return;
+    }
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) dig[r] = (b[r] < NB) ? (b[r] & ((1u << lo_bits) - 1)) : 64u;
+    rank_stable<kLocalThreads, ITEMS>(dig, rounds, lo_bits, wcnt, dstart, tmp, pos);
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r)
+        if ((uint32_t)r < rounds && b[r] < NB) {
+            skeys[pos[r]] = kk[r];
+            sids[pos[r]] = id[r];
+            sb[pos[r]] = (uint16_t)b[r];
+        }
+    __syncthreads();
+    if (hi_bits == 0) return;
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+        const uint32_t e = w * wchunk + r * kWave + lane;
+        if ((uint32_t)r < rounds && r * kWave + lane < wchunk && e < cl) {
+            kk[r] = skeys[e];
+            id[r] = sids[e];
+            b[r] = sb[e];
+            dig[r] = b[r] >> lo_bits;
+        } else {
+            b[r] = NB;
+            dig[r] = 64u;
+        }
+    }
+    // rank_stable synchronises before counting, so every wave has finished
+    // reading the buffers before any wave overwrites them below
+    rank_stable<kLocalThreads, ITEMS>(dig, rounds, hi_bits, wcnt, dstart, tmp, pos);
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r)
+        if ((uint32_t)r < rounds && b[r] < NB) {
+            skeys[pos[r]] = kk[r];
+            sids[pos[r]] = id[r];
+            sb[pos[r]] = (uint16_t)b[r];
+        }
+}
+
+// Exclusive scan of cnt[0..NB) in place (NB a power of two); returns via
+// cnt; *total gets the sum.  All threads must call it.
+__device__ __forceinline__ void scan_counts(uint32_t* cnt, uint32_t NB, uint32_t base,
+                                            uint32_t* tmp) {
+    const uint32_t per = NB >= (uint32_t)kLocalThreads ? NB / kLocalThreads : 1u;
+    const uint32_t i0 = threadIdx.x * per;
+    uint32_t v[16];
+    uint32_t mine = 0;
+    for (uint32_t j = 0; j < per; ++j) {
+        v[j] = (i0 + j < NB) ? cnt[i0 + j] : 0u;
+        mine += v[j];
+    }
+    uint32_t all;
+    uint32_t run = base + block_excl_scan<kLocalThreads>(mine, tmp, &all);
+    for (uint32_t j = 0; j < per; ++j)
+        if (i0 + j < NB) {
+            cnt[i0 + j] = run;
+            run += v[j];
+        }
+    __syncthreads();
+}
+
+// Exclusive scan of cnt[0..NB) in place (base 0); returns the largest count.
+// `tmp` needs 2 * (waves per block) words.  All threads must call it.
+__device__ __forceinline__ uint32_t scan_counts_max(uint32_t* cnt, uint32_t NB, uint32_t* tmp) {
+    const uint32_t per = NB >= (uint32_t)kLocalThreads ? NB / kLocalThreads : 1u;
+    const uint32_t i0 = threadIdx.x * per;
+    uint32_t v[16];
+    uint32_t mine = 0, mx = 0;
+    for (uint32_t j = 0; j < per; ++j) {
+        v[j] = (i0 + j < NB) ? cnt[i0 + j] : 0u;
+        mine += v[j];
+        mx = v[j] > mx ? v[j] : mx;
+    }
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) {
+        const uint32_t o = __shfl_xor(mx, d, kWave);
+        mx = o > mx ? o : mx;
+    }
+    uint32_t all;
+    uint32_t run = block_excl_scan<kLocalThreads>(mine, tmp, &all);
+    if (lane_id() == 0) tmp[W_LOCAL + threadIdx.x / kWave] = mx;
+    for (uint32_t j = 0; j < per; ++j)
+        if (i0 + j < NB) {
+            cnt[i0 + j] = run;
+            run += v[j];
+        }
+    __syncthreads();
+    uint32_t m = 0;
+#pragma unroll
+    for (int i = 0; i < W_LOCAL; ++i) m = tmp[W_LOCAL + i] > m ? tmp[W_LOCAL + i] : m;
+    __syncthreads();
+    return m;
+}
+
+// LDS bytes of light_bin_body / heavy_bin_body for 2^k buckets per bin.
+template <typename Key>
+inline size_t light_smem(uint32_t k) {
+    const size_t NB = 1u << k;
+    return kLightCap * (sizeof(Key) + 4 + 2) + NB * 4 + W_LOCAL * 64 * 4 + 64 * 4 +
+           (2 * W_LOCAL + 2) * 4 + 64;
+}
+
+template <typename Key>
+inline size_t heavy_smem(uint32_t k) {
+    const size_t NB = 1u << k;
+    return kHeavyChunk * (sizeof(Key) + 4 + 2) + 2 * NB * 4 + W_LOCAL * 64 * 4 + 64 * 4 +
+           (2 * W_LOCAL + 2) * 4 + 64;
+}
+
+// Probe index entry of one bucket: {start, end, first key, second key} for
+// 32-bit keys, {start, end, low and high half of the first key} for 64-bit
+// keys (unused key slots are 0).  `k` points at the bucket's first key.
+template <typename Key>
+__device__ __forceinline__ uint4 head_entry(uint32_t start, uint32_t end, const Key* k);
+
+template <>
+__device__ __forceinline__ uint4 head_entry<uint32_t>(uint32_t start, uint32_t end,
+                                                      const uint32_t* k) {
+    const uint32_t len = end - start;
+    return make_uint4(start, end, len >= 1 ? k[0] : 0u, len >= 2 ? k[1] : 0u);
+}
+
+template <>
+__device__ __forceinline__ uint4 head_entry<uint64_t>(uint32_t start, uint32_t end,
+                                                      const uint64_t* k) {
+    const uint64_t k0 = (end - start >= 1) ? k[0] : 0ull;
+    return make_uint4(start, end, (uint32_t)k0, (uint32_t)(k0 >> 32));
+}
+
+// Build one bin of L <= kLightCap keys whose buckets are [v0, v0 + nb) with
+// nb <= 2^k.  Entry e (e < L) of the bin is src_keys[e], with id src_ids[e]
+// (or id_base + e when src_ids is null).  The bin's keys and ids go to
+// ekeys/ids[out + p] for p < L, sorted by bucket with ids ascending inside a
+// bucket, and offsets[v0 + v] = out + (start of bucket v in the bin).
+// Usual case (every bucket of the bin holds at most kFixMax keys): LDS
+// counting sort with atomic cursors, then an insertion sort by id inside each
+// bucket.  Otherwise the bin (in id order) is stably ranked by local bucket.
+// When `head` is not null it also receives each bucket's probe index entry.
+// Called by a whole workgroup of kLocalThreads threads.
+template <typename Key>
+__device__ __forceinline__ void light_bin_body(const Key* __restrict__ src_keys,
+                                               const uint32_t* __restrict__ src_ids,
+                                               uint32_t id_base, uint32_t L, uint32_t out,
+                                               uint32_t v0, uint32_t k, uint32_t nb,
+                                               const typename KeyTraits<Key>::Params& hp,
+                                               uint32_t* __restrict__ offsets,
+                                               uint4* __restrict__ head,
+                                               uint32_t* __restrict__ ids, Key* __restrict__ ekeys,
+                                               unsigned char* smem) {
+    constexpr int IT = kLightItems;
+    const uint32_t NB = 1u << k;
+    Key* skeys = (Key*)smem;
+    uint32_t* sids = (uint32_t*)(skeys + kLightCap);
+    uint16_t* sb = (uint16_t*)(sids + kLightCap);
+    uint32_t* cnt = (uint32_t*)(sb + kLightCap);  // NB
+    uint32_t* wcnt = cnt + NB;                     // W * 64
+    uint32_t* dstart = wcnt + W_LOCAL * 64;        // 64
+    uint32_t* tmp = dstart + 64;
+    const uint32_t w = threadIdx.x / kWave, lane = lane_id();
+    // balance the bin over the waves in whole rounds of 64
+    const uint32_t wchunk = (((L + W_LOCAL - 1) / W_LOCAL) + kWave - 1) & ~(uint32_t)(kWave - 1);
+    const uint32_t wb = w * wchunk;
+    const uint32_t mylen = L > wb ? ((L - wb < wchunk) ? L - wb : wchunk) : 0u;
+    const uint32_t rounds = (mylen + kWave - 1) / kWave;
+
+    Key kk[IT];
+    uint32_t id[IT], b[IT];
+#pragma unroll
+    for (int r = 0; r < IT; ++r) {
+        const uint32_t e = wb + r * kWave + lane;
+        if ((uint32_t)r < rounds && r * kWave + lane < mylen) {
+            kk[r] = src_keys[e];
+            id[r] = src_ids ? src_ids[e] : id_base + e;
+        } else {
+            kk[r] = 0;
+            id[r] = 0;
+        }
+    }
+    for (uint32_t i = threadIdx.x; i < NB; i += kLocalThreads) cnt[i] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < IT; ++r) {
+        if ((uint32_t)r < rounds && r * kWave + lane < mylen) {
+            b[r] = KeyTraits<Key>::bucket(kk[r], hp) - v0;
+            atomicAdd(&cnt[b[r]], 1u);
+        } else {
+            b[r] = NB;
+        }
+    }
+    __syncthreads();
+    // bucket starts (in place) and the largest bucket of the bin
+    const uint32_t maxc = scan_counts_max(cnt, NB, tmp);
+    if (maxc <= kFixMax) {
+#pragma unroll
+        for (int r = 0; r < IT; ++r) {
+            if (b[r] < NB) {
+                const uint32_t slot = atomicAdd(&cnt[b[r]], 1u);
+                skeys[slot] = kk[r];
+                sids[slot] = id[r];
+            }
+        }
+        __syncthreads();
+        // cnt[v] is now the end of bucket v
+        for (uint32_t v = threadIdx.x; v < NB; v += kLocalThreads) {
+            const uint32_t lo = v ? cnt[v - 1] : 0u, hi = cnt[v];
+            for (uint32_t i = lo + 1; i < hi; ++i) {
+                const uint32_t idv = sids[i];
+                const Key kv = skeys[i];
+                uint32_t j = i;
+                while (j > lo && sids[j - 1] > idv) {
+                    sids[j] = sids[j - 1];
+                    skeys[j] = skeys[j - 1];
+                    --j;
+                }
+                sids[j] = idv;
+                skeys[j] = kv;
+            }
+        }
+        __syncthreads();
+        for (uint32_t v = threadIdx.x; v < nb; v += kLocalThreads) {
+            const uint32_t lo = v ? cnt[v - 1] : 0u, hi = cnt[v];
+            offsets[v0 + v] = out + lo;
+            if (head) head[v0 + v] = head_entry<Key>(out + lo, out + hi, skeys + lo);
+        }
+    } else {
+        sort_chunk_by_bucket<Key, IT>(kk, id, b, rounds, L, wchunk, k, skeys, sids, sb, wcnt,
+                                      dstart, tmp);
+        __syncthreads();
+        for (uint32_t v = threadIdx.x; v < nb; v += kLocalThreads) {
+            const uint32_t lo = cnt[v], hi = (v + 1 < NB) ? cnt[v + 1] : L;
+            offsets[v0 + v] = out + lo;
+            if (head) head[v0 + v] = head_entry<Key>(out + lo, out + hi, skeys + lo);
+        }
+    }
+    for (uint32_t p = threadIdx.x; p < L; p += kLocalThreads) {
+        ekeys[out + p] = skeys[p];
+        ids[out + p] = sids[p];
+    }
+}
+
+// The same for a bin of any size (arriving in id order): keys counted per
+// bucket first, then placed chunk by chunk, in order, with running
+// per-bucket cursors, so placement stays stable.  Whole workgroup.
+template <typename Key>
+__device__ __forceinline__ void heavy_bin_body(const Key* __restrict__ src_keys,
+                                               const uint32_t* __restrict__ src_ids,
+                                               uint32_t id_base, uint32_t L, uint32_t out,
+                                               uint32_t v0, uint32_t k, uint32_t nb,
+                                               const typename KeyTraits<Key>::Params& hp,
+                                               uint32_t* __restrict__ offsets,
+                                               uint4* __restrict__ head,
+                                               uint32_t* __restrict__ ids, Key* __restrict__ ekeys,
+                                               unsigned char* smem) {
+    constexpr int IT = kHeavyItems;
+    constexpr uint32_t CAP = kHeavyChunk;
+    const uint32_t NB = 1u << k;
+    Key* skeys = (Key*)smem;
+    uint32_t* sids = (uint32_t*)(skeys + CAP);
+    uint16_t* sb = (uint16_t*)(sids + CAP);
+    uint32_t* cur = (uint32_t*)(sb + CAP);  // NB: running cursors
+    uint32_t* tcnt = cur + NB;              // NB: chunk-local bucket starts
+    uint32_t* wcnt = tcnt + NB;
+    uint32_t* dstart = wcnt + W_LOCAL * 64;
+    uint32_t* tmp = dstart + 64;
+    const uint32_t w = threadIdx.x / kWave, lane = lane_id();
+
+    for (uint32_t i = threadIdx.x; i < NB; i += kLocalThreads) cur[i] = 0;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < L; i += kLocalThreads)
+        atomicAdd(&cur[KeyTraits<Key>::bucket(src_keys[i], hp) - v0], 1u);
+    __syncthreads();
+    scan_counts(cur, NB, out, tmp);
+    for (uint32_t i = threadIdx.x; i < nb; i += kLocalThreads) offsets[v0 + i] = cur[i];
+    const uint32_t nchunk = (uint32_t)(((uint64_t)L + CAP - 1) / CAP);
+    for (uint32_t ci = 0; ci < nchunk; ++ci) {
+        const uint32_t c0 = ci * CAP;
+        const uint32_t cl = (L - c0 < CAP) ? L - c0 : CAP;
+        const uint32_t wchunk =
+            (((cl + W_LOCAL - 1) / W_LOCAL) + kWave - 1) & ~(uint32_t)(kWave - 1);
+        const uint32_t wb = w * wchunk;
+        const uint32_t mylen = cl > wb ? ((cl - wb < wchunk) ? cl - wb : wchunk) : 0u;
+        const uint32_t rounds = (mylen + kWave - 1) / kWave;
+        Key kk[IT];
+        uint32_t id[IT], b[IT];
+#pragma unroll
+        for (int r = 0; r < IT; ++r) {
+            const uint32_t e = c0 + wb + r * kWave + lane;
+            if ((uint32_t)r < rounds && r * kWave + lane < mylen) {
+                kk[r] = src_keys[e];
+                id[r] = src_ids ? src_ids[e] : id_base + e;
+            } else {
+                kk[r] = 0;
+                id[r] = 0;
+            }
+        }
+        for (uint32_t i = threadIdx.x; i < NB; i += kLocalThreads) tcnt[i] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < IT; ++r) {
+            if ((uint32_t)r < rounds && r * kWave + lane < mylen) {
+                b[r] = KeyTraits<Key>::bucket(kk[r], hp) - v0;
+                atomicAdd(&tcnt[b[r]], 1u);
+            } else {
+                b[r] = NB;
+            }
+        }
+        sort_chunk_by_bucket<Key, IT>(kk, id, b, rounds, cl, wchunk, k, skeys, sids, sb, wcnt,
+                                      dstart, tmp);
+        __syncthreads();
+        // chunk-local bucket starts (exclusive scan of tcnt)
+        scan_counts(tcnt, NB, 0u, tmp);
+        const uint32_t hi_out = out + L;
+        for (uint32_t p = threadIdx.x; p < cl; p += kLocalThreads) {
+            const uint32_t bb = sb[p];
+            const uint32_t o = cur[bb] + (p - tcnt[bb]);
+            if (o - out < hi_out - out) {
+                ekeys[o] = skeys[p];
+                ids[o] = sids[p];
+            }
+        }
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < NB; i += kLocalThreads) {
+            const uint32_t nxt = (i + 1 < NB) ? tcnt[i + 1] : cl;
+            cur[i] += nxt - tcnt[i];
+        }
+        __syncthreads();
+    }
+    // cur[v] is now the end of bucket v; the bin's edges are in ekeys
+    if (head)
+        for (uint32_t v = threadIdx.x; v < nb; v += kLocalThreads) {
+            const uint32_t lo = v ? cur[v - 1] : out;
+            head[v0 + v] = head_entry<Key>(lo, cur[v], ekeys + lo);
+        }
+}
+
+}  // namespace v2dev
+}  // namespace hg

@@ -34,7 +34,7 @@ class HGError(RuntimeError):
 class BuildOpts(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("stable", ctypes.c_int32),
                 ("bins", ctypes.c_uint32), ("block", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 4)]
+                ("no_index", ctypes.c_int32), ("reserved", ctypes.c_uint32 * 3)]
 
 
 class TableInfo(ctypes.Structure):
@@ -164,9 +164,10 @@ def hg_exclusive_scan(counts: torch.Tensor, out=None, stream=None):
 
 # ----------------------------------------------------------------- tables ---
 
-def _opts(variant=VARIANT_AUTO, stable=0, bins=0, block=0):
+def _opts(variant=VARIANT_AUTO, stable=0, bins=0, block=0, index=True):
     o = BuildOpts()
     o.variant, o.stable, o.bins, o.block = int(variant), int(stable), int(bins), int(block)
+    o.no_index = 0 if index else 1
     return o
 
 
@@ -185,9 +186,9 @@ class Table:
         return cls(h, torch.device(device))
 
     def rebuild(self, keys: torch.Tensor, hash_range: int, seed: int = 0, variant=VARIANT_AUTO,
-                stable=0, bins=0, block=0, stream=None):
+                stable=0, bins=0, block=0, index=True, stream=None):
         keys = _dev_keys(keys)
-        o = _opts(variant, stable, bins, block)
+        o = _opts(variant, stable, bins, block, index)
         _check(lib().hg_table_build(self._h, _ptr(keys), keys.numel(), int(hash_range),
                                     int(seed) & (2**64 - 1), ctypes.byref(o), _stream(stream)),
                "hg_table_build")
@@ -226,9 +227,9 @@ class Table:
 
 
 def hg_build(keys: torch.Tensor, hash_range: int, seed: int = 0, variant=VARIANT_AUTO, stable=0,
-             bins=0, block=0, stream=None) -> Table:
+             bins=0, block=0, index=True, stream=None) -> Table:
     keys = _dev_keys(keys)
-    o = _opts(variant, stable, bins, block)
+    o = _opts(variant, stable, bins, block, index)
     h = ctypes.c_void_p()
     _check(lib().hg_build(_ptr(keys), keys.numel(), _key_bits(keys), int(hash_range),
                           int(seed) & (2**64 - 1), ctypes.byref(o), _stream(stream),
@@ -327,3 +328,226 @@ def profile_report() -> dict:
         _check(L.hg_profile_get(i, buf, 128, ctypes.byref(n), ctypes.byref(ms)), "hg_profile_get")
         out[buf.value.decode()] = (int(n.value), float(ms.value))
     return out
+
+
+# ---------------------------------------------------------------- batched ---
+
+class BatchItem(ctypes.Structure):
+    _fields_ = [("d_keys", ctypes.c_void_p), ("n", ctypes.c_uint64),
+                ("hash_range", ctypes.c_uint64), ("seed", ctypes.c_uint64),
+                ("d_queries", ctypes.c_void_p), ("m", ctypes.c_uint64),
+                ("d_offsets", ctypes.c_void_p), ("d_ids", ctypes.c_void_p),
+                ("d_ekeys", ctypes.c_void_p), ("d_counts", ctypes.c_void_p)]
+
+
+class BatchOpts(ctypes.Structure):
+    _fields_ = [("autotune", ctypes.c_uint32), ("bin_target", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 6)]
+
+
+def _batch_sig():
+    L = lib()
+    if getattr(L, "_batch_ready", False):
+        return L
+    vp = ctypes.c_void_p
+    L.hg_batch_create.argtypes = [ctypes.POINTER(BatchItem), ctypes.c_uint32, ctypes.c_int,
+                                  ctypes.POINTER(BatchOpts), ctypes.POINTER(vp)]
+    L.hg_batch_create.restype = ctypes.c_int
+    L.hg_batch_run.argtypes, L.hg_batch_run.restype = [vp, vp], ctypes.c_int
+    L.hg_batch_info.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32),
+                                ctypes.POINTER(ctypes.c_uint64)]
+    L.hg_batch_info.restype = ctypes.c_int
+    L.hg_batch_free.argtypes, L.hg_batch_free.restype = [vp], None
+    L._batch_ready = True
+    return L
+
+
+class Batch:
+    """A batched build+probe plan over device tensors.
+
+    `tables` is a list of dicts with keys: keys, hash_range, seed, queries,
+    and (outputs) offsets, ids, ekeys, counts -- all device tensors except the
+    two integers.  Missing outputs are allocated here.  The plan keeps the
+    tensors alive."""
+
+    def __init__(self, tables, key_bits=32, autotune=True, bin_target=0):
+        L = _batch_sig()
+        self.tables = []
+        items = (BatchItem * max(1, len(tables)))()
+        kdt = torch.int64 if key_bits == 64 else torch.int32
+        for i, t in enumerate(tables):
+            keys, q = t["keys"], t.get("queries")
+            dev = keys.device
+            V = int(t["hash_range"])
+            n = keys.numel()
+            m = 0 if q is None else q.numel()
+            d = dict(t)
+            d.setdefault("offsets", torch.empty(V + 1, dtype=torch.int32, device=dev))
+            d.setdefault("ids", torch.empty(max(n, 1), dtype=torch.int32, device=dev))
+            d.setdefault("ekeys", torch.empty(max(n, 1), dtype=kdt, device=dev))
+            d.setdefault("counts", torch.empty(max(m, 1), dtype=torch.int32, device=dev))
+            it = items[i]
+            it.d_keys = keys.data_ptr() if n else None
+            it.n = n
+            it.hash_range = V
+            it.seed = int(t.get("seed", 0)) & (2**64 - 1)
+            it.d_queries = q.data_ptr() if m else None
+            it.m = m
+            it.d_offsets = d["offsets"].data_ptr()
+            it.d_ids = d["ids"].data_ptr()
+            it.d_ekeys = d["ekeys"].data_ptr()
+            it.d_counts = d["counts"].data_ptr() if m else None
+            self.tables.append(d)
+        o = BatchOpts()
+        o.autotune = 1 if autotune else 0
+        o.bin_target = int(bin_target)
+        h = ctypes.c_void_p()
+        _check(L.hg_batch_create(items, len(tables), int(key_bits), ctypes.byref(o),
+                                 ctypes.byref(h)), "hg_batch_create")
+        self._h = h
+
+    def run(self, stream=None):
+        _check(_batch_sig().hg_batch_run(self._h, _stream(stream)), "hg_batch_run")
+
+    def info(self):
+        t = ctypes.c_uint32(0)
+        w = ctypes.c_uint64(0)
+        _check(_batch_sig().hg_batch_info(self._h, ctypes.byref(t), ctypes.byref(w)),
+               "hg_batch_info")
+        return {"bin_target": int(t.value), "workspace_bytes": int(w.value)}
+
+    def free(self):
+        if self._h is not None and self._h.value:
+            _batch_sig().hg_batch_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- serving ---
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_uint64), ("streams", ctypes.c_uint32),
+                ("max_inflight", ctypes.c_uint32), ("merge_max", ctypes.c_uint32),
+                ("merge_keys", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 4)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64),
+                ("rejected", ctypes.c_uint64), ("evictions", ctypes.c_uint64),
+                ("launches", ctypes.c_uint64), ("merged_requests", ctypes.c_uint64),
+                ("keys", ctypes.c_uint64), ("p50_ms", ctypes.c_double),
+                ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
+                ("max_ms", ctypes.c_double), ("busy_s", ctypes.c_double),
+                ("resident_bytes", ctypes.c_uint64), ("peak_bytes", ctypes.c_uint64),
+                ("resident_tables", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+def _server_sig():
+    L = lib()
+    if getattr(L, "_server_ready", False):
+        return L
+    vp, u64, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int
+    pu64 = ctypes.POINTER(u64)
+    L.hg_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]
+    L.hg_server_submit_build.argtypes = [vp, vp, u64, i32, u64, u64, pu64, pu64]
+    L.hg_server_submit_probe.argtypes = [vp, u64, vp, u64, vp, pu64]
+    L.hg_server_wait.argtypes = [vp, u64, ctypes.POINTER(ctypes.c_int)]
+    L.hg_server_drain.argtypes = [vp]
+    L.hg_server_export.argtypes = [vp, u64, vp, vp, vp, vp]
+    L.hg_server_stats_get.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    L.hg_server_reset_stats.argtypes = [vp]
+    for f in ("hg_server_create", "hg_server_submit_build", "hg_server_submit_probe",
+              "hg_server_wait", "hg_server_drain", "hg_server_export", "hg_server_stats_get",
+              "hg_server_reset_stats"):
+        getattr(L, f).restype = i32
+    L.hg_server_destroy.argtypes, L.hg_server_destroy.restype = [vp], None
+    L._server_ready = True
+    return L
+
+
+class Server:
+    """The library's request loop.  Submitted tensors are kept alive here
+    until their request completes."""
+
+    def __init__(self, budget_bytes=0, streams=0, max_inflight=0, merge_max=0, merge_keys=0):
+        L = _server_sig()
+        o = ServerOpts()
+        o.budget_bytes, o.streams, o.max_inflight = int(budget_bytes), int(streams), int(max_inflight)
+        o.merge_max, o.merge_keys = int(merge_max), int(merge_keys)
+        h = ctypes.c_void_p()
+        _check(L.hg_server_create(ctypes.byref(o), ctypes.byref(h)), "hg_server_create")
+        self._h = h
+        self._keep = {}
+        self._meta = {}
+
+    def submit_build(self, keys: torch.Tensor, hash_range: int, seed: int = 0):
+        keys = _dev_keys(keys)
+        tid, rid = ctypes.c_uint64(0), ctypes.c_uint64(0)
+        _check(_server_sig().hg_server_submit_build(
+            self._h, _ptr(keys), keys.numel(), _key_bits(keys), int(hash_range),
+            int(seed) & (2**64 - 1), ctypes.byref(tid), ctypes.byref(rid)), "hg_server_submit_build")
+        self._keep[rid.value] = (keys,)
+        self._meta[tid.value] = (keys.numel(), int(hash_range), _key_bits(keys))
+        return tid.value, rid.value
+
+    def submit_probe(self, table_id: int, queries: torch.Tensor, counts: torch.Tensor = None):
+        queries = _dev_keys(queries)
+        if counts is None:
+            counts = _u32(max(queries.numel(), 1), queries.device)
+        rid = ctypes.c_uint64(0)
+        _check(_server_sig().hg_server_submit_probe(
+            self._h, int(table_id), _ptr(queries), queries.numel(), _ptr(counts),
+            ctypes.byref(rid)), "hg_server_submit_probe")
+        self._keep[rid.value] = (queries, counts)
+        return rid.value, counts
+
+    def wait(self, request_id: int) -> int:
+        st = ctypes.c_int(0)
+        _check(_server_sig().hg_server_wait(self._h, int(request_id), ctypes.byref(st)),
+               "hg_server_wait")
+        self._keep.pop(int(request_id), None)
+        return int(st.value)
+
+    def drain(self):
+        _check(_server_sig().hg_server_drain(self._h), "hg_server_drain")
+        self._keep.clear()
+
+    def export(self, table_id: int, stream=None):
+        """(offsets, ids, keys) copies of a resident table, or None if it is
+        not resident."""
+        n, V, kb = self._meta[int(table_id)]
+        dev = torch.device("cuda")
+        off = _u32(V + 1, dev)
+        ids = _u32(max(n, 1), dev)
+        keys = torch.empty(max(n, 1), dtype=torch.int64 if kb == 64 else torch.int32, device=dev)
+        rc = _server_sig().hg_server_export(self._h, int(table_id), _ptr(off), _ptr(ids),
+                                            _ptr(keys), _stream(stream))
+        if rc == HG_ERR_NOT_FOUND:
+            return None
+        _check(rc, "hg_server_export")
+        return off, ids[:n], keys[:n]
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _check(_server_sig().hg_server_stats_get(self._h, ctypes.byref(s)), "hg_server_stats_get")
+        return {f: getattr(s, f) for f, _ in ServerStats._fields_ if f != "reserved"}
+
+    def reset_stats(self):
+        _check(_server_sig().hg_server_reset_stats(self._h), "hg_server_reset_stats")
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            _server_sig().hg_server_destroy(self._h)
+        self._h = None
+        self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

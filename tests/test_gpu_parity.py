@@ -214,6 +214,51 @@ def test_probe_pairs_match_oracle_in_canonical_order(hg, kb):
     assert np.array_equal(hg.to_numpy(b, np.uint32), eb)
 
 
+@pytest.mark.parametrize("kb", [32, 64])
+@pytest.mark.parametrize("kind,n,V", [("uniform", 300007, 300007), ("uniform", 120000, 1 << 20),
+                                      ("dup8", 200000, 50000), ("equal", 20000, 97),
+                                      ("zipf", 150000, 150000)])
+def test_probe_index_on_and_off_agree_with_oracle(hg, kb, kind, n, V):
+    # the per-bucket index holds each bucket's bounds and first keys; buckets
+    # of 0, 1, 2 and many keys (light and heavy bins) all occur here
+    say("index", kb, kind, n, V)
+    k = keys_for(kind, n, kb, seed=11)
+    q = workloads.probe_queries(k, n + 4321, 0.5, seed=12, key_bits=kb)
+    exp, etot = oracle.probe_counts(k, q, kb)
+    eb, ep, _ = oracle.probe_pairs(k, q, kb) if etot <= 5_000_000 else (None, None, None)
+    dq = hg.to_device(q)
+    for index in (True, False):
+        t = hg.hg_build(hg.to_device(k), V, seed=21, index=index)
+        c, tot = hg.hg_probe(t, dq, counts=True, total=True)
+        assert np.array_equal(hg.to_numpy(c, np.uint32), exp), index
+        assert tot == etot
+        if eb is not None:
+            b, p, tot2 = hg.hg_probe_pairs(t, dq)
+            assert tot2 == etot
+            assert np.array_equal(hg.to_numpy(p, np.uint32), ep)
+            assert np.array_equal(hg.to_numpy(b, np.uint32), eb)
+
+
+def test_probe_index_follows_rebuilds(hg):
+    # one table object rebuilt with the index, without it, and with it again
+    # under other keys and ranges: a probe never sees a stale index
+    t = hg.Table.create(1 << 18, 1 << 18)
+    for step, (n, V, index) in enumerate([(200000, 150000, True), (100000, 90000, False),
+                                          (250000, 1 << 18, True), (0, 1000, True),
+                                          (5000, 3, True)]):
+        say("rebuild", step, n, V, index)
+        k = workloads.duplicate_keys(n, 2.0, 32, seed=30 + step) if n else \
+            np.zeros(0, np.uint32)
+        q = workloads.probe_queries(k if n else workloads.uniform_keys(8, 32, 0), 70000, 0.5,
+                                    seed=40 + step)
+        t.rebuild(hg.to_device(k), V, seed=step, index=index)
+        c, tot = hg.hg_probe(t, hg.to_device(q), counts=True, total=True)
+        exp, etot = oracle.probe_counts(k, q)
+        assert np.array_equal(hg.to_numpy(c, np.uint32), exp)
+        assert tot == etot
+    t.free()
+
+
 def test_probe_pairs_v1_as_sets_and_capacity(hg):
     n, m, V = 50000, 40000, 30000
     k = workloads.duplicate_keys(n, 2.0, 32, seed=8)
