@@ -64,12 +64,19 @@ def timed(fn, reps, torch):
     return float(np.median(out))
 
 
-def kernel_bytes(name, n, m, V, kb, sum_len, plan):
-    """Algorithmic bytes one launch of `name` must move (reads + writes)."""
+def kernel_bytes(name, n, m, V, kb, sum_len, plan, sum_tail=None):
+    """Algorithmic bytes one launch of `name` must move (reads + writes).
+
+    With the per-bucket probe index (sum_tail given), a query reads its
+    bucket's 16-byte entry and only the keys past the first two; without it,
+    two offsets and every key of its bucket.  The V2 local build writes the
+    index (16 bytes per bucket) beside offsets, ids and keys."""
     if name == "probe_count":
+        if sum_tail is not None:
+            return m * kb + m * 16 + kb * sum_tail + m * 4
         return m * kb + m * 8 + kb * sum_len + m * 4
     if name == "v2_local_build":
-        return 2 * n * (kb + 4) + (V + 1) * 4
+        return 2 * n * (kb + 4) + (V + 1) * 4 + (V * 16 if sum_tail is not None else 0)
     if name == "v2_partition_t1":
         return n * kb + n * (kb + 4) + plan["m1_bytes"]
     if name == "v2_partition_t2":
@@ -363,15 +370,17 @@ def main():
     off, _, _ = table.export()
     h = hg.hg_hash(dq, V, 0).to(torch.int64)
     offl = off.to(torch.int64) & 0xFFFFFFFF
-    sum_len = int((offl[h + 1] - offl[h]).sum().item())
-    del h, offl, off
+    blen = offl[h + 1] - offl[h]
+    sum_len = int(blen.sum().item())
+    sum_tail = int((blen - 2).clamp_(min=0).sum().item())
+    del h, offl, off, blen
 
     plan = v2_plan_bytes(n, V)
     kernels = {}
     for name, (launches, tot_ms) in prof.items():
         per = launches / args.steps
         avg = tot_ms / launches
-        b = kernel_bytes(name, n, m, V, kb, sum_len, plan)
+        b = kernel_bytes(name, n, m, V, kb, sum_len, plan, sum_tail)
         kernels[name] = {"launches_per_step": per, "avg_ms": round(avg, 4),
                          "ms_per_step": round(tot_ms / args.steps, 4),
                          "alg_bytes": b,
@@ -387,7 +396,7 @@ def main():
                 "alg_bytes_per_launch": dk_["alg_bytes"], "avg_launch_ms": dk_["avg_ms"]}
 
     phases = {"kernels": kernels, "source_digest": digest,
-              "probe_sum_bucket_len": sum_len}
+              "probe_sum_bucket_len": sum_len, "probe_sum_keys_past_index": sum_tail}
     build_ms = sum(v["ms_per_step"] for k, v in kernels.items()
                    if k.startswith("v2_") or k == "fill")
     phases["build_v2_ms"] = round(build_ms, 3)
@@ -403,15 +412,22 @@ def main():
             Vs = 1 << lv
             t_v2 = timed(lambda: big.rebuild(dk, Vs, 0, variant=hg.VARIANT_V2), reps, torch)
             t_pr = timed(lambda: hg.hg_probe(big, dq, counts=True, out=counts), reps, torch)
+            t_v2x = timed(lambda: big.rebuild(dk, Vs, 0, variant=hg.VARIANT_V2, index=False),
+                          reps, torch)
+            t_prx = timed(lambda: hg.hg_probe(big, dq, counts=True, out=counts), reps, torch)
             t_v1 = timed(lambda: big.rebuild(dk, Vs, 0, variant=hg.VARIANT_V1), 2, torch)
+            t_pr1 = timed(lambda: hg.hg_probe(big, dq, counts=True, out=counts), reps, torch)
             ex["V=2^%d" % lv] = {"build_v2_ms": round(t_v2, 3),
                                  "build_v2_Gkeys": round(n / t_v2 / 1e6, 2),
+                                 "build_v2_noindex_ms": round(t_v2x, 3),
                                  "build_v1_ms": round(t_v1, 3),
                                  "build_v1_Gkeys": round(n / t_v1 / 1e6, 2),
-                                 "probe_v1table_ms": None,
                                  "probe_ms": round(t_pr, 3),
-                                 "probe_Gkeys": round(m / t_pr / 1e6, 2)}
-            log("V=2^%d v2 %.3f ms v1 %.3f ms probe %.3f ms" % (lv, t_v2, t_v1, t_pr))
+                                 "probe_Gkeys": round(m / t_pr / 1e6, 2),
+                                 "probe_noindex_ms": round(t_prx, 3),
+                                 "probe_v1table_ms": round(t_pr1, 3)}
+            log("V=2^%d v2 %.3f (no index %.3f) ms v1 %.3f ms probe %.3f (no index %.3f, "
+                "v1 table %.3f) ms" % (lv, t_v2, t_v2x, t_v1, t_pr, t_prx, t_pr1))
         big.free()
         del big
         # Probe-New (Alg. 3): build the query table, then intersect (counts)

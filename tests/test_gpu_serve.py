@@ -41,7 +41,8 @@ def make_requests(seed=3, nbuild=24, nprobe=56):
         b = int(rng.integers(0, nbuild))
         m = int(np.floor(np.exp2(rng.uniform(6, 15))))
         q = workloads.probe_queries(builds[b][0], m, 0.5, seed=500 + p)
-        pos = int(rng.integers(b + 1, len(reqs) + 1))  # after its build
+        first = reqs.index(("build", b)) + 1  # after its build
+        pos = int(rng.integers(first, len(reqs) + 1))
         reqs.insert(pos, ("probe", (b, q)))
     return builds, reqs
 
