@@ -69,9 +69,16 @@ typedef struct hg_build_opts {
                           one 16-byte entry per bucket holding its start, its
                           end and its first keys (two 32-bit keys, or one
                           64-bit key), so a probe of a short bucket takes one
-                          random read.  1 = skip it (probes then read offsets
-                          and the edge array).  Results are identical either
-                          way.  V1 never writes it.                           */
+                          random read.  Buckets of more than 32 entries get a
+                          key-run summary instead (distinct keys ascending,
+                          each with its count and its ids grouped), so probes
+                          and intersections of skewed tables cost a binary
+                          search instead of a scan; building it waits for the
+                          build and, for tables made by hg_table_create,
+                          allocates the summary the first time a build has
+                          such buckets.  1 = skip the index (probes then read
+                          offsets and scan the edge array).  Results are
+                          identical either way.  V1 never writes it.         */
     uint32_t reserved[3];
 } hg_build_opts;
 

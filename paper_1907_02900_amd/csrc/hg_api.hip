@@ -20,6 +20,13 @@ struct hg_table {
     void* keys = nullptr;
     uint4* head = nullptr;  // V_cap per-bucket probe index entries
     bool has_head = false;  // the last build wrote head
+    // long buckets (> kRunBucket entries): their list, counters and key runs
+    uint32_t* long_list = nullptr;
+    uint32_t* long_stat = nullptr;  // [2]
+    uint64_t long_cap = 0;
+    RunsDev runs{};
+    uint64_t runs_cap = 0;          // runs the run arrays hold (kperm: n_cap)
+    bool has_runs = false;
     void* ws = nullptr;  // workspace kept for rebuilds (hg_table_create only)
     size_t ws_bytes = 0;
     uint64_t bytes = 0;
@@ -72,6 +79,55 @@ hg_status read_u64(const uint64_t* d, uint64_t* h, hipStream_t s) {
     return HG_OK;
 }
 
+#define HG_CALL_ST(expr)                     \
+    do {                                     \
+        hg_status st__ = (expr);             \
+        if (st__ != HG_OK) return st__;      \
+    } while (0)
+
+// After a V2 build with the index: read how many long buckets it listed and,
+// if any, build their key-run summary.  Waits for the build (the list's size
+// decides the summary's allocations and launches).
+hg_status build_runs(hg_table* t, hipStream_t s) {
+    uint32_t stat[2] = {0, 0};
+    HG_CALL(hipMemcpyAsync(stat, t->long_stat, sizeof(stat), hipMemcpyDeviceToHost, s));
+    HG_CALL(hipStreamSynchronize(s));
+    const uint32_t nlong = stat[0], total = stat[1];
+    if (nlong == 0) return HG_OK;
+    if (nlong > t->long_cap) return HG_ERR_DEVICE;  // cannot happen: each holds > kRunBucket keys
+    const size_t ks = key_size(t->key_bits);
+    if (!t->runs.kperm) {
+        HG_CALL(hipMalloc((void**)&t->runs.kperm, (t->n_cap ? t->n_cap : 1) * 4));
+        t->bytes += (t->n_cap ? t->n_cap : 1) * 4;
+    }
+    if (t->runs_cap < total) {
+        if (t->runs.run_key) {
+            (void)hipFree(t->runs.run_key);
+            (void)hipFree(t->runs.run_cnt);
+            (void)hipFree(t->runs.run_pos);
+            t->bytes -= t->runs_cap * (ks + 8);
+            t->runs.run_key = nullptr;
+            t->runs_cap = 0;
+        }
+        HG_CALL(hipMalloc(&t->runs.run_key, total * ks));
+        HG_CALL(hipMalloc((void**)&t->runs.run_cnt, (size_t)total * 4));
+        HG_CALL(hipMalloc((void**)&t->runs.run_pos, (size_t)total * 4));
+        t->runs_cap = total;
+        t->bytes += (uint64_t)total * (ks + 8);
+    }
+    Scratch tmp(s);
+    HG_CALL(tmp.get(runs_ws_bytes(nlong, total, t->key_bits)));
+    const hipError_t e =
+        t->key_bits == 32
+            ? run_key_runs<uint32_t>(t->offsets, t->ids, (const uint32_t*)t->keys, t->long_list,
+                                     nlong, total, t->head, t->runs, tmp.p, s)
+            : run_key_runs<uint64_t>(t->offsets, t->ids, (const uint64_t*)t->keys, t->long_list,
+                                     nlong, total, t->head, t->runs, tmp.p, s);
+    if (e != hipSuccess) return from_hip(e);
+    t->has_runs = true;
+    return HG_OK;
+}
+
 hg_status build_into(hg_table* t, const void* keys, uint64_t n, uint64_t V, uint64_t seed,
                      const hg_build_opts* opts, hipStream_t s) {
     int variant = opts ? opts->variant : HG_VARIANT_AUTO;
@@ -92,21 +148,26 @@ hg_status build_into(hg_table* t, const void* keys, uint64_t n, uint64_t V, uint
         HG_CALL(tmp.get(need));
         ws = tmp.p;
     }
+    IndexOut ix{};
+    if (want_head) {
+        ix.head = t->head;
+        ix.long_list = t->long_list;
+        ix.long_stat = t->long_stat;
+        ix.long_cap = (uint32_t)t->long_cap;
+    }
     hipError_t e;
     if (t->key_bits == 32) {
         e = variant == HG_VARIANT_V1
                 ? run_build_v1<uint32_t>((const uint32_t*)keys, n, V, seed, t->offsets, t->ids,
                                          (uint32_t*)t->keys, ws, block, s)
                 : run_build_v2<uint32_t>((const uint32_t*)keys, n, V, seed, t->offsets, t->ids,
-                                         (uint32_t*)t->keys, want_head ? t->head : nullptr, ws,
-                                         bins, s);
+                                         (uint32_t*)t->keys, ix, ws, bins, s);
     } else {
         e = variant == HG_VARIANT_V1
                 ? run_build_v1<uint64_t>((const uint64_t*)keys, n, V, seed, t->offsets, t->ids,
                                          (uint64_t*)t->keys, ws, block, s)
                 : run_build_v2<uint64_t>((const uint64_t*)keys, n, V, seed, t->offsets, t->ids,
-                                         (uint64_t*)t->keys, want_head ? t->head : nullptr, ws,
-                                         bins, s);
+                                         (uint64_t*)t->keys, ix, ws, bins, s);
     }
     if (e != hipSuccess) return from_hip(e);
     t->n = n;
@@ -114,6 +175,8 @@ hg_status build_into(hg_table* t, const void* keys, uint64_t n, uint64_t V, uint
     t->seed = seed;
     t->variant = variant;
     t->has_head = want_head;
+    t->has_runs = false;
+    if (want_head) HG_CALL_ST(build_runs(t, s));
     return HG_OK;
 }
 
@@ -127,7 +190,11 @@ hg_status alloc_table(uint64_t n_cap, uint64_t V_cap, int kb, bool with_ws, hg_t
     if (e == hipSuccess) e = hipMalloc((void**)&t->ids, (n_cap ? n_cap : 1) * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc(&t->keys, (n_cap ? n_cap : 1) * key_size(kb));
     if (e == hipSuccess) e = hipMalloc((void**)&t->head, V_cap * sizeof(uint4));
-    t->bytes = (V_cap + 1) * 4 + V_cap * sizeof(uint4) + (n_cap ? n_cap : 1) * (4 + key_size(kb));
+    t->long_cap = n_cap / (kRunBucket + 1) + 1;
+    if (e == hipSuccess) e = hipMalloc((void**)&t->long_list, t->long_cap * 4);
+    if (e == hipSuccess) e = hipMalloc((void**)&t->long_stat, 2 * 4);
+    t->bytes = (V_cap + 1) * 4 + V_cap * sizeof(uint4) + (n_cap ? n_cap : 1) * (4 + key_size(kb)) +
+               t->long_cap * 4 + 8;
     if (e == hipSuccess && with_ws) {
         size_t w1 = build_ws_bytes(1, n_cap, V_cap, kb, 0);
         size_t w2 = build_ws_bytes(2, n_cap, V_cap, kb, 0);
@@ -154,6 +221,7 @@ TableDev dev_view(const hg_table* t) {
     d.V = t->V;
     d.seed = t->seed;
     d.head = t->has_head ? t->head : nullptr;
+    if (t->has_head && t->has_runs) d.runs = t->runs;
     return d;
 }
 
@@ -279,6 +347,12 @@ void hg_table_free(hg_table* t) {
     if (t->ids) (void)hipFree(t->ids);
     if (t->keys) (void)hipFree(t->keys);
     if (t->head) (void)hipFree(t->head);
+    if (t->long_list) (void)hipFree(t->long_list);
+    if (t->long_stat) (void)hipFree(t->long_stat);
+    if (t->runs.kperm) (void)hipFree(t->runs.kperm);
+    if (t->runs.run_key) (void)hipFree(t->runs.run_key);
+    if (t->runs.run_cnt) (void)hipFree(t->runs.run_cnt);
+    if (t->runs.run_pos) (void)hipFree(t->runs.run_pos);
     if (t->ws) (void)hipFree(t->ws);
     delete t;
 }

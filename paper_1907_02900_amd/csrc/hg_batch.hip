@@ -179,7 +179,6 @@ __global__ __launch_bounds__(kPartThreads) void k_bpart(const BTable<Key>* __res
     const uint32_t cnt = (tb.n - begin > kPartTile) ? kPartTile : tb.n - begin;
     const uint32_t w = threadIdx.x / kWave, lane = lane_id();
     const uint32_t wbase = w * (kWave * IT);
-    const uint32_t rounds = cnt > wbase ? (cnt - wbase + kWave - 1) / kWave : 0u;
     Key k[IT];
     uint32_t dig[IT], pos[IT];
 #pragma unroll
@@ -192,7 +191,7 @@ __global__ __launch_bounds__(kPartThreads) void k_bpart(const BTable<Key>* __res
         const uint32_t e = wbase + r * kWave + lane;
         dig[r] = (e < cnt) ? ((KeyTraits<Key>::bucket(k[r], tb.hp) >> tb.k) & (D - 1)) : D;
     }
-    rank_stable<kPartThreads, IT>(dig, rounds < IT ? rounds : IT, bits, wcnt, dstart, tmp, pos);
+    rank_stable<kPartThreads, IT>(dig, bits, wcnt, dstart, tmp, pos);
     const uint32_t* row = mat + tb.mat_base + (size_t)lt * D;
     for (uint32_t d = threadIdx.x; d < D; d += kPartThreads) tbase[d] = row[d] - dstart[d];
 #pragma unroll
@@ -257,9 +256,9 @@ __global__ __launch_bounds__(kLocalThreads) void k_blocal(
     const uint32_t nb = (tb.V - v0 < NB) ? tb.V - v0 : NB;
     if (tb.kind == kPartitioned)
         light_bin_body<Key>(rkeys + start, rids + start, 0u, L, start - tb.key_base, v0, tb.k, nb,
-                            tb.hp, tb.offsets, nullptr, tb.ids, tb.ekeys, smem);
+                            tb.hp, tb.offsets, IndexOut{}, tb.ids, tb.ekeys, smem);
     else
-        light_bin_body<Key>(tb.keys, nullptr, 0u, L, 0u, v0, tb.k, nb, tb.hp, tb.offsets, nullptr,
+        light_bin_body<Key>(tb.keys, nullptr, 0u, L, 0u, v0, tb.k, nb, tb.hp, tb.offsets, IndexOut{},
                             tb.ids, tb.ekeys, smem);
 }
 
@@ -278,10 +277,10 @@ __global__ __launch_bounds__(kLocalThreads) void k_bheavy(
         const uint32_t nb = (tb.V - v0 < NB) ? tb.V - v0 : NB;
         if (tb.kind == kPartitioned)
             heavy_bin_body<Key>(rkeys + start, rids + start, 0u, end - start, start - tb.key_base,
-                                v0, tb.k, nb, tb.hp, tb.offsets, nullptr, tb.ids, tb.ekeys, smem);
+                                v0, tb.k, nb, tb.hp, tb.offsets, IndexOut{}, tb.ids, tb.ekeys, smem);
         else
             heavy_bin_body<Key>(tb.keys, nullptr, 0u, end - start, 0u, v0, tb.k, nb, tb.hp,
-                                tb.offsets, nullptr, tb.ids, tb.ekeys, smem);
+                                tb.offsets, IndexOut{}, tb.ids, tb.ekeys, smem);
         __syncthreads();
     }
 }
@@ -1076,10 +1075,10 @@ struct Server {
                 STable& t = tables[r0.table];
                 e = kb == 32 ? run_build_v2<uint32_t>((const uint32_t*)r0.data, t.n, t.V, t.seed,
                                                       t.offsets, t.ids, (uint32_t*)t.keys,
-                                                      nullptr, L.transient, 0, s)
+                                                      IndexOut{}, L.transient, 0, s)
                              : run_build_v2<uint64_t>((const uint64_t*)r0.data, t.n, t.V, t.seed,
                                                       t.offsets, t.ids, (uint64_t*)t.keys,
-                                                      nullptr, L.transient, 0, s);
+                                                      IndexOut{}, L.transient, 0, s);
             } else if (r0.kind == 1 && group.size() == 1) {
                 const STable& t = tables[r0.table];
                 TableDev d{t.offsets, t.ids, t.keys, t.n, t.V, t.seed};

@@ -28,20 +28,20 @@ struct HashParams {
     uint32_t range;  // V = d, 1 <= V < 2^32
     uint32_t magic;  // m - 2^32
     uint32_t shift;  // l - 1
-    uint32_t is_one; // V == 1: every key goes to bucket 0
+    uint32_t pow2;   // V is a power of two (V = 1 included): a mod V = a & (V - 1)
 };
 
 __host__ __device__ __forceinline__ uint32_t mulhi32(uint32_t a, uint32_t b) {
     return (uint32_t)(((uint64_t)a * b) >> 32);
 }
 
-// a mod d for the divisor described by p
+// a mod d for the divisor described by p (the branch is uniform across a launch)
 __host__ __device__ __forceinline__ uint32_t mod_u32(uint32_t a, const HashParams& p) {
+    if (p.pow2) return a & (p.range - 1u);
     const uint32_t t = mulhi32(a, p.magic);
     // floor((a + t) / 2^l) without overflowing 32 bits (t <= a)
     const uint32_t q = (((a - t) >> 1) + t) >> p.shift;
-    const uint32_t r = a - q * p.range;
-    return p.is_one ? 0u : r;
+    return a - q * p.range;
 }
 
 __host__ __device__ __forceinline__ uint32_t fmix32(uint32_t x) {
@@ -83,8 +83,8 @@ inline HashParams make_hash_params(uint64_t range, uint64_t seed) {
     HashParams p{};
     p.seed = seed;
     p.range = (uint32_t)range;
-    if (range <= 1) {
-        p.is_one = 1;
+    if ((range & (range - 1)) == 0) {
+        p.pow2 = 1;
         return p;
     }
     uint32_t l = 0;
@@ -101,7 +101,7 @@ struct HashParams64 {
     uint64_t m_lo;
     uint64_t m_hi;
     uint32_t range;
-    uint32_t pad_;
+    uint32_t pow2;  // V is a power of two (V = 1 included)
 };
 
 inline HashParams64 make_hash_params64(uint64_t range, uint64_t seed) {
@@ -112,6 +112,7 @@ inline HashParams64 make_hash_params64(uint64_t range, uint64_t seed) {
     unsigned __int128 M = all / (uint32_t)range + 1;
     p.m_lo = (uint64_t)M;
     p.m_hi = (uint64_t)(M >> 64);
+    p.pow2 = (range & (range - 1)) == 0;
     return p;
 }
 
@@ -132,7 +133,9 @@ struct KeyTraits<uint64_t> {
     using Params = HashParams64;
     static inline Params make(uint64_t range, uint64_t seed) { return make_hash_params64(range, seed); }
     __host__ __device__ static __forceinline__ uint32_t bucket(uint64_t k, const Params& p) {
-        return fastmod_u64(fmix64(k ^ p.seed), p.m_lo, p.m_hi, p.range);
+        const uint64_t x = fmix64(k ^ p.seed);
+        if (p.pow2) return (uint32_t)x & (p.range - 1u);
+        return fastmod_u64(x, p.m_lo, p.m_hi, p.range);
     }
 };
 

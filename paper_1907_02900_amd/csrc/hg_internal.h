@@ -107,11 +107,49 @@ template <typename Key>
 hipError_t run_build_v1(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, uint32_t* offsets,
                         uint32_t* ids, Key* ekeys, void* ws, uint32_t block, hipStream_t s);
 
-// head (may be null): V 16-byte probe index entries, one per bucket.
+// ---- probe index -------------------------------------------------------------
+// Buckets holding more entries than this get a key-run summary: their distinct
+// keys in ascending order, each with its count and the start of its run in a
+// key-grouped copy of the bucket's ids.
+constexpr uint32_t kRunBucket = 32;
+
+// Where a V2 build writes its probe index (head == null: none).  Buckets
+// longer than kRunBucket are appended to `long_list` (capacity long_cap >=
+// n / (kRunBucket + 1)); long_stat[0] counts them, long_stat[1] sums their
+// lengths.
+struct IndexOut {
+    uint4* head = nullptr;
+    uint32_t* long_list = nullptr;
+    uint32_t* long_stat = nullptr;
+    uint32_t long_cap = 0;
+};
+
+// Key-run summary arrays of a table (all sized for the summary's runs, kperm
+// for the edge array).
+struct RunsDev {
+    void* run_key = nullptr;       // Key[runs]: distinct keys, ascending per bucket
+    uint32_t* run_cnt = nullptr;   // [runs] entries with that key
+    uint32_t* run_pos = nullptr;   // [runs] edge position of the run in kperm
+    uint32_t* kperm = nullptr;     // [n] ids of long buckets grouped by key (ids ascending)
+};
+
+// Workspace for building the summary of `nlong` long buckets holding `total`
+// entries.
+size_t runs_ws_bytes(uint64_t nlong, uint64_t total, int key_bits);
+
+// Build the key-run summary of the long buckets listed in `long_list` and
+// point their head entries at it.  ws: runs_ws_bytes(nlong, total, kb).
+template <typename Key>
+hipError_t run_key_runs(const uint32_t* offsets, const uint32_t* ids, const Key* ekeys,
+                        const uint32_t* long_list, uint32_t nlong, uint32_t total, uint4* head,
+                        const RunsDev& r, void* ws, hipStream_t s);
+
+// ix.head (may be null): V 16-byte probe index entries, one per bucket; long
+// buckets are listed as IndexOut describes.
 template <typename Key>
 hipError_t run_build_v2(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, uint32_t* offsets,
-                        uint32_t* ids, Key* ekeys, uint4* head, void* ws, uint32_t bins_hint,
-                        hipStream_t s);
+                        uint32_t* ids, Key* ekeys, const IndexOut& ix, void* ws,
+                        uint32_t bins_hint, hipStream_t s);
 
 // ---- probing ---------------------------------------------------------------
 struct TableDev {
@@ -120,6 +158,7 @@ struct TableDev {
     const void* keys;
     uint64_t n, V, seed;
     const uint4* head = nullptr;  // per-bucket probe index, when the build wrote one
+    RunsDev runs{};               // key-run summary of long buckets (with head)
 };
 
 size_t probe_ws_bytes(uint64_t m);

@@ -51,13 +51,45 @@ struct HeadKeys<uint64_t> {
     }
 };
 
+// Key-run summary of the long buckets (see hg_runs.hip).
+template <typename Key>
+struct Runs {
+    const Key* key;        // distinct keys, ascending inside each long bucket
+    const uint32_t* cnt;   // entries per run
+    const uint32_t* pos;   // run start in kperm
+    const uint32_t* kperm; // ids grouped by key
+};
+
+template <typename Key>
+Runs<Key> runs_of(const TableDev& t) {
+    return Runs<Key>{(const Key*)t.runs.run_key, t.runs.run_cnt, t.runs.run_pos, t.runs.kperm};
+}
+
+// Run of q among runs [r0, r0 + d) (keys ascending), or ~0u if q is absent.
+template <typename Key>
+__device__ __forceinline__ uint32_t find_run(const Key* __restrict__ rk, uint32_t r0, uint32_t d,
+                                             Key q) {
+    uint32_t lo = r0, hi = r0 + d;  // first run with key >= q
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (rk[mid] < q) lo = mid + 1;
+        else hi = mid;
+    }
+    return (lo < r0 + d && rk[lo] == q) ? lo : ~0u;
+}
+
 // Matches of q in a bucket described by its index entry: the keys held in the
-// entry are compared directly, the edge array is read only past them.
+// entry are compared directly, the edge array is read only past them; a long
+// bucket's entry points at its key runs instead (z = first run, w = runs).
 template <typename Key>
 __device__ __forceinline__ uint32_t count_with_head(const uint4& e, const Key* __restrict__ ekeys,
-                                                    Key q) {
+                                                    const Runs<Key>& runs, Key q) {
     using HK = HeadKeys<Key>;
     const uint32_t len = e.y - e.x;
+    if (len > kRunBucket) {
+        const uint32_t r = find_run(runs.key, e.z, e.w, q);
+        return r != ~0u ? runs.cnt[r] : 0u;
+    }
     uint32_t c = 0;
 #pragma unroll
     for (uint32_t i = 0; i < HK::slots; ++i) c += (len > i && HK::key(e, i) == q) ? 1u : 0u;
@@ -71,7 +103,7 @@ __device__ __forceinline__ uint32_t count_with_head(const uint4& e, const Key* _
 template <typename Key, bool HEAD>
 __global__ __launch_bounds__(kProbeThreads) void k_probe_count(
     const Key* __restrict__ q, uint64_t m, typename KeyTraits<Key>::Params hp,
-    const uint32_t* __restrict__ off, const uint4* __restrict__ head,
+    const uint32_t* __restrict__ off, const uint4* __restrict__ head, Runs<Key> runs,
     const Key* __restrict__ ekeys, uint32_t* __restrict__ counts,
     unsigned long long* __restrict__ total) {
     __shared__ uint64_t red[kProbeThreads / kWave + 1];
@@ -102,7 +134,7 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_count(
 #pragma unroll
     for (int r = 0; r < kProbeItems; ++r) {
         const uint64_t j = base + (uint64_t)r * kProbeThreads;
-        const uint32_t c = HEAD ? count_with_head(e[r], ekeys, qq[r])
+        const uint32_t c = HEAD ? count_with_head(e[r], ekeys, runs, qq[r])
                                 : count_in_bucket(ekeys, e[r].x, e[r].y, qq[r]);
         if (j < m && counts) counts[j] = c;
         sum += c;
@@ -117,7 +149,7 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_count(
 template <typename Key, bool HEAD>
 __global__ __launch_bounds__(kProbeThreads) void k_probe_pairs(
     const Key* __restrict__ q, uint64_t m, typename KeyTraits<Key>::Params hp,
-    const uint32_t* __restrict__ off, const uint4* __restrict__ head,
+    const uint32_t* __restrict__ off, const uint4* __restrict__ head, Runs<Key> runs,
     const Key* __restrict__ ekeys, const uint32_t* __restrict__ eids,
     const uint64_t* __restrict__ positions, uint32_t* __restrict__ build_ids,
     uint32_t* __restrict__ probe_ids) {
@@ -136,6 +168,17 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_pairs(
         }
         const uint32_t lo = e.x, hi = e.y;
         uint64_t pos = positions[j];
+        if (HEAD && hi - lo > kRunBucket) {
+            // the ids of q's run, ascending
+            const uint32_t r = find_run(runs.key, e.z, e.w, k);
+            if (r != ~0u)
+                for (uint32_t t = runs.pos[r], te = t + runs.cnt[r]; t < te; ++t) {
+                    build_ids[pos] = runs.kperm[t];
+                    probe_ids[pos] = (uint32_t)j;
+                    ++pos;
+                }
+            continue;
+        }
         for (uint32_t p = lo; p < hi; ++p)
             if ((HEAD && p - lo < HK::slots ? HK::key(e, p - lo) : ekeys[p]) == k) {
                 build_ids[pos] = eids[p];
@@ -147,12 +190,30 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_pairs(
 
 // Alg. 3 over B's edges p: count the entries of A's bucket h(key_p) equal to
 // key_p.  A and B share hash parameters, so h is recomputed from B's key.
+// Matches of k in A's bucket h: a scan, or A's key runs when the bucket is
+// long and A has them (a_head not null).
+template <typename Key>
+__device__ __forceinline__ uint32_t count_in_a(const uint32_t* __restrict__ a_off,
+                                               const uint4* __restrict__ a_head,
+                                               const Runs<Key>& runs,
+                                               const Key* __restrict__ a_keys, uint32_t h,
+                                               Key k) {
+    const uint32_t lo = a_off[h], hi = a_off[h + 1];
+    if (a_head && hi - lo > kRunBucket) {
+        const uint4 e = a_head[h];
+        const uint32_t r = find_run(runs.key, e.z, e.w, k);
+        return r != ~0u ? runs.cnt[r] : 0u;
+    }
+    return count_in_bucket(a_keys, lo, hi, k);
+}
+
 template <typename Key>
 __global__ __launch_bounds__(kProbeThreads) void k_intersect_count(
-    const uint32_t* __restrict__ a_off, const Key* __restrict__ a_keys,
-    const Key* __restrict__ b_keys, const uint32_t* __restrict__ b_ids, uint64_t nb,
-    typename KeyTraits<Key>::Params hp, uint32_t* __restrict__ edge_counts,
-    uint32_t* __restrict__ counts_by_input, unsigned long long* __restrict__ total) {
+    const uint32_t* __restrict__ a_off, const uint4* __restrict__ a_head, Runs<Key> runs,
+    const Key* __restrict__ a_keys, const Key* __restrict__ b_keys,
+    const uint32_t* __restrict__ b_ids, uint64_t nb, typename KeyTraits<Key>::Params hp,
+    uint32_t* __restrict__ edge_counts, uint32_t* __restrict__ counts_by_input,
+    unsigned long long* __restrict__ total) {
     __shared__ uint64_t red[kProbeThreads / kWave + 1];
     uint64_t sum = 0;
     const uint64_t base = (uint64_t)blockIdx.x * (kProbeThreads * kProbeItems) + threadIdx.x;
@@ -162,7 +223,7 @@ __global__ __launch_bounds__(kProbeThreads) void k_intersect_count(
         if (p < nb) {
             const Key k = b_keys[p];
             const uint32_t h = KeyTraits<Key>::bucket(k, hp);
-            const uint32_t c = count_in_bucket(a_keys, a_off[h], a_off[h + 1], k);
+            const uint32_t c = count_in_a(a_off, a_head, runs, a_keys, h, k);
             if (edge_counts) edge_counts[p] = c;
             if (counts_by_input) counts_by_input[b_ids[p]] = c;
             sum += c;
@@ -177,11 +238,11 @@ __global__ __launch_bounds__(kProbeThreads) void k_intersect_count(
 
 template <typename Key>
 __global__ __launch_bounds__(kProbeThreads) void k_intersect_pairs(
-    const uint32_t* __restrict__ a_off, const Key* __restrict__ a_keys,
-    const uint32_t* __restrict__ a_ids, const Key* __restrict__ b_keys,
-    const uint32_t* __restrict__ b_ids, uint64_t nb, typename KeyTraits<Key>::Params hp,
-    const uint64_t* __restrict__ positions, uint32_t* __restrict__ out_a,
-    uint32_t* __restrict__ out_b) {
+    const uint32_t* __restrict__ a_off, const uint4* __restrict__ a_head, Runs<Key> runs,
+    const Key* __restrict__ a_keys, const uint32_t* __restrict__ a_ids,
+    const Key* __restrict__ b_keys, const uint32_t* __restrict__ b_ids, uint64_t nb,
+    typename KeyTraits<Key>::Params hp, const uint64_t* __restrict__ positions,
+    uint32_t* __restrict__ out_a, uint32_t* __restrict__ out_b) {
     uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t st = (uint64_t)gridDim.x * blockDim.x;
     for (; p < nb; p += st) {
@@ -190,6 +251,17 @@ __global__ __launch_bounds__(kProbeThreads) void k_intersect_pairs(
         const uint32_t lo = a_off[h], hi = a_off[h + 1];
         const uint32_t bid = b_ids[p];
         uint64_t pos = positions[p];
+        if (a_head && hi - lo > kRunBucket) {
+            const uint4 e = a_head[h];
+            const uint32_t r = find_run(runs.key, e.z, e.w, k);
+            if (r != ~0u)
+                for (uint32_t t = runs.pos[r], te = t + runs.cnt[r]; t < te; ++t) {
+                    out_a[pos] = runs.kperm[t];
+                    out_b[pos] = bid;
+                    ++pos;
+                }
+            continue;
+        }
         for (uint32_t i = lo; i < hi; ++i)
             if (a_keys[i] == k) {
                 out_a[pos] = a_ids[i];
@@ -221,12 +293,12 @@ hipError_t run_probe_counts(const TableDev& t, const Key* queries, uint64_t m, u
         const dim3 grid(grid_for(m, kProbeThreads * kProbeItems));
         if (t.head)
             hipLaunchKernelGGL((k_probe_count<Key, true>), grid, dim3(kProbeThreads), 0, s,
-                               queries, m, hp, t.offsets, t.head, (const Key*)t.keys, counts,
-                               d_total);
+                               queries, m, hp, t.offsets, t.head, runs_of<Key>(t),
+                               (const Key*)t.keys, counts, d_total);
         else
             hipLaunchKernelGGL((k_probe_count<Key, false>), grid, dim3(kProbeThreads), 0, s,
-                               queries, m, hp, t.offsets, t.head, (const Key*)t.keys, counts,
-                               d_total);
+                               queries, m, hp, t.offsets, t.head, runs_of<Key>(t),
+                               (const Key*)t.keys, counts, d_total);
     }
     return hipGetLastError();
 }
@@ -243,12 +315,12 @@ hipError_t run_probe_pairs(const TableDev& t, const Key* queries, uint64_t m,
         HG_PROF("probe_pairs", s);
         if (t.head)
             hipLaunchKernelGGL((k_probe_pairs<Key, true>), dim3(g), dim3(kProbeThreads), 0, s,
-                               queries, m, hp, t.offsets, t.head, (const Key*)t.keys, t.ids,
-                               positions, build_ids, probe_ids);
+                               queries, m, hp, t.offsets, t.head, runs_of<Key>(t),
+                               (const Key*)t.keys, t.ids, positions, build_ids, probe_ids);
         else
             hipLaunchKernelGGL((k_probe_pairs<Key, false>), dim3(g), dim3(kProbeThreads), 0, s,
-                               queries, m, hp, t.offsets, t.head, (const Key*)t.keys, t.ids,
-                               positions, build_ids, probe_ids);
+                               queries, m, hp, t.offsets, t.head, runs_of<Key>(t),
+                               (const Key*)t.keys, t.ids, positions, build_ids, probe_ids);
     }
     return hipGetLastError();
 }
@@ -262,8 +334,9 @@ hipError_t run_intersect_counts(const TableDev& a, const TableDev& b, uint32_t* 
     {
         HG_PROF("intersect_count", s);
         hipLaunchKernelGGL(k_intersect_count<Key>, dim3(grid_for(b.n, kProbeThreads * kProbeItems)),
-                           dim3(kProbeThreads), 0, s, a.offsets, (const Key*)a.keys,
-                           (const Key*)b.keys, b.ids, b.n, hp, edge_counts, counts_by_input, d_total);
+                           dim3(kProbeThreads), 0, s, a.offsets, a.head, runs_of<Key>(a),
+                           (const Key*)a.keys, (const Key*)b.keys, b.ids, b.n, hp, edge_counts,
+                           counts_by_input, d_total);
     }
     return hipGetLastError();
 }
@@ -278,8 +351,8 @@ hipError_t run_intersect_pairs(const TableDev& a, const TableDev& b, const uint6
     {
         HG_PROF("intersect_pairs", s);
         hipLaunchKernelGGL(k_intersect_pairs<Key>, dim3(g), dim3(kProbeThreads), 0, s, a.offsets,
-                           (const Key*)a.keys, a.ids, (const Key*)b.keys, b.ids, b.n, hp, positions,
-                           a_ids, b_ids);
+                           a.head, runs_of<Key>(a), (const Key*)a.keys, a.ids, (const Key*)b.keys,
+                           b.ids, b.n, hp, positions, a_ids, b_ids);
     }
     return hipGetLastError();
 }

@@ -227,7 +227,6 @@ __global__ __launch_bounds__(kPartThreads) void k_tile_partition(
     const uint32_t w = threadIdx.x / kWave, lane = lane_id();
     const uint32_t mask = D - 1;
     const uint32_t wbase = w * (kWave * IT);
-    const uint32_t rounds = cnt > wbase ? (cnt - wbase + kWave - 1) / kWave : 0u;
 
     Key k[IT];
     uint32_t id[IT], dig[IT], pos[IT];
@@ -247,7 +246,7 @@ __global__ __launch_bounds__(kPartThreads) void k_tile_partition(
         const uint32_t e = wbase + r * kWave + lane;
         dig[r] = (e < cnt) ? ((KeyTraits<Key>::bucket(k[r], hp) >> shift) & mask) : D;
     }
-    rank_stable<kPartThreads, IT>(dig, rounds < IT ? rounds : IT, bits, wcnt, dstart, tmp, pos);
+    rank_stable<kPartThreads, IT>(dig, bits, wcnt, dstart, tmp, pos);
     const uint32_t* row = base + (size_t)t * D;
     for (uint32_t d = threadIdx.x; d < D; d += kPartThreads) tbase[d] = row[d] - dstart[d];
 #pragma unroll
@@ -373,7 +372,7 @@ template <typename Key>
 __global__ __launch_bounds__(kLocalThreads) void k_local_light(
     const Key* __restrict__ src_keys, const uint32_t* __restrict__ src_ids,
     const uint32_t* __restrict__ bin_start, typename KeyTraits<Key>::Params hp, uint32_t k,
-    uint32_t* __restrict__ offsets, uint4* __restrict__ head, uint32_t* __restrict__ ids,
+    uint32_t* __restrict__ offsets, IndexOut ix, uint32_t* __restrict__ ids,
     Key* __restrict__ ekeys) {
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t g = blockIdx.x;
@@ -383,7 +382,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_local_light(
     const uint32_t NB = 1u << k, v0 = g << k, V = hp.range;
     const uint32_t nb = (V - v0 < NB) ? V - v0 : NB;
     light_bin_body<Key>(src_keys + start, src_ids + start, 0u, L, start, v0, k, nb, hp, offsets,
-                        head, ids, ekeys, smem);
+                        ix, ids, ekeys, smem);
 }
 
 // Oversize bins (from the device list), one workgroup per bin.
@@ -392,7 +391,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_local_heavy(
     const Key* __restrict__ src_keys, const uint32_t* __restrict__ src_ids,
     const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ heavy_list,
     const uint32_t* __restrict__ heavy_count, typename KeyTraits<Key>::Params hp, uint32_t k,
-    uint32_t* __restrict__ offsets, uint4* __restrict__ head, uint32_t* __restrict__ ids,
+    uint32_t* __restrict__ offsets, IndexOut ix, uint32_t* __restrict__ ids,
     Key* __restrict__ ekeys) {
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t NB = 1u << k, V = hp.range;
@@ -403,7 +402,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_local_heavy(
         const uint32_t v0 = g << k;
         const uint32_t nb = (V - v0 < NB) ? V - v0 : NB;
         heavy_bin_body<Key>(src_keys + start, src_ids + start, 0u, end - start, start, v0, k, nb,
-                            hp, offsets, head, ids, ekeys, smem);
+                            hp, offsets, ix, ids, ekeys, smem);
         __syncthreads();
     }
 }
@@ -576,11 +575,12 @@ size_t build_ws_bytes(int variant, uint64_t n, uint64_t V, int key_bits, uint32_
 
 template <typename Key>
 hipError_t run_build_v2(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, uint32_t* offsets,
-                        uint32_t* ids, Key* ekeys, uint4* head, void* ws, uint32_t bins_hint,
-                        hipStream_t s) {
+                        uint32_t* ids, Key* ekeys, const IndexOut& ix, void* ws,
+                        uint32_t bins_hint, hipStream_t s) {
     HG_TRY(set_smem_limits<Key>());
+    if (ix.head) HG_TRY(fill_u32(ix.long_stat, 2, 0u, s));
     if (n == 0) {
-        if (head) HG_TRY(fill_u32((uint32_t*)head, 4 * V, 0u, s));
+        if (ix.head) HG_TRY(fill_u32((uint32_t*)ix.head, 4 * V, 0u, s));
         return fill_u32(offsets, V + 1, 0u, s);
     }
     const V2Plan p = plan_v2(n, V, sizeof(Key) * 8, bins_hint);
@@ -630,7 +630,7 @@ hipError_t run_build_v2(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, 
         HG_PROF("v2_local_build", s);
         hipLaunchKernelGGL(k_local_light<Key>, dim3(p.bins), dim3(kLocalThreads),
                            light_smem<Key>(p.k), s, (const Key*)rkeys, (const uint32_t*)w.rids,
-                           (const uint32_t*)w.bin_start, hp, p.k, offsets, head, ids, ekeys);
+                           (const uint32_t*)w.bin_start, hp, p.k, offsets, ix, ids, ekeys);
     }
     HG_TRY(hipGetLastError());
     {
@@ -639,17 +639,17 @@ hipError_t run_build_v2(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, 
         hipLaunchKernelGGL(k_local_heavy<Key>, dim3(hg_grid), dim3(kLocalThreads),
                            heavy_smem<Key>(p.k), s, (const Key*)rkeys, (const uint32_t*)w.rids,
                            (const uint32_t*)w.bin_start, (const uint32_t*)w.heavy_list,
-                           (const uint32_t*)w.heavy_count, hp, p.k, offsets, head, ids,
+                           (const uint32_t*)w.heavy_count, hp, p.k, offsets, ix, ids,
                            ekeys);
     }
     return hipGetLastError();
 }
 
 template hipError_t run_build_v2<uint32_t>(const uint32_t*, uint64_t, uint64_t, uint64_t,
-                                           uint32_t*, uint32_t*, uint32_t*, uint4*, void*,
-                                           uint32_t, hipStream_t);
+                                           uint32_t*, uint32_t*, uint32_t*, const IndexOut&,
+                                           void*, uint32_t, hipStream_t);
 template hipError_t run_build_v2<uint64_t>(const uint64_t*, uint64_t, uint64_t, uint64_t,
-                                           uint32_t*, uint32_t*, uint64_t*, uint4*, void*,
-                                           uint32_t, hipStream_t);
+                                           uint32_t*, uint32_t*, uint64_t*, const IndexOut&,
+                                           void*, uint32_t, hipStream_t);
 
 }  // namespace hg

@@ -50,44 +50,40 @@ __device__ __forceinline__ void scan_wave_digit_counts(uint32_t D, uint32_t* wcn
 
 // Stable rank of up to 64*ITEMS items per wave by a digit of `bits` bits
 // (D = 2^bits <= 2048).  Item r of a lane is entry (wave base + r*64 + lane);
-// items with dig >= D are ignored; `rounds` (wave-uniform) bounds the rounds
-// holding valid items.  Per round every lane reads its digit's running count
-// in the wave's counter row and the lowest lane of each group of equal digits
-// adds the group's size with a non-returning LDS atomic.  LDS performs a
-// wave's operations in issue order, so a read sees exactly the items of the
-// wave's earlier rounds, and no round waits for the previous one.  On return
-// pos[r] is the item's index in the tile sorted stably by digit.  Contains
-// barriers.
+// items with dig >= D are ignored.  Per round every lane reads its digit's
+// running count in the wave's counter row and the lowest lane of each group
+// of equal digits adds the group's size with a non-returning LDS atomic.  LDS
+// performs a wave's operations in issue order, so a read sees exactly the
+// items of the wave's earlier rounds, and no round waits for the previous
+// one.  Every round runs unconditionally (a round without valid items costs
+// its ballots and changes nothing), which keeps the code straight-line.  On
+// return pos[r] is the item's index in the tile sorted stably by digit
+// (undefined for ignored items).  Contains barriers.
 template <int THREADS, int ITEMS>
-__device__ __forceinline__ void rank_stable(const uint32_t (&dig)[ITEMS], uint32_t rounds,
-                                            uint32_t bits, uint32_t* wcnt, uint32_t* dstart,
-                                            uint32_t* tmp, uint32_t (&pos)[ITEMS]) {
+__device__ __forceinline__ void rank_stable(const uint32_t (&dig)[ITEMS], uint32_t bits,
+                                            uint32_t* wcnt, uint32_t* dstart, uint32_t* tmp,
+                                            uint32_t (&pos)[ITEMS]) {
     constexpr int W = THREADS / kWave;
-    const uint32_t D = 1u << bits;
+    const uint32_t D = 1u << bits, mask = D - 1;
     const uint32_t w = threadIdx.x / kWave;
     for (uint32_t i = threadIdx.x; i < W * D; i += THREADS) wcnt[i] = 0;
     __syncthreads();
     uint32_t* my = wcnt + w * D;
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
-        if ((uint32_t)r < rounds) {  // wave-uniform
-            const uint32_t d = dig[r];
-            const bool valid = d < D;
-            const uint64_t peers = match_digit(d, (int)bits, ballot(valid));
-            if (valid) {
-                const uint32_t below = mbcnt(peers);
-                pos[r] = my[d] + below;
-                if (below == 0)
-                    __hip_atomic_fetch_add(&my[d], (uint32_t)__popcll(peers), __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_WORKGROUP);
-            }
-        }
+        const uint32_t d = dig[r];
+        const bool valid = d < D;
+        const uint64_t peers = match_digit(d, (int)bits, ballot(valid));
+        const uint32_t below = mbcnt(peers);
+        pos[r] = my[d & mask] + below;
+        if (valid && below == 0)
+            __hip_atomic_fetch_add(&my[d], (uint32_t)__popcll(peers), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
     }
     __syncthreads();
     scan_wave_digit_counts<THREADS>(D, wcnt, dstart, tmp);
 #pragma unroll
-    for (int r = 0; r < ITEMS; ++r)
-        if ((uint32_t)r < rounds && dig[r] < D) pos[r] += my[dig[r]];
+    for (int r = 0; r < ITEMS; ++r) pos[r] += my[dig[r] & mask];
 }
 
 // -------------------------------------------------- per-bin LDS build -----
@@ -121,7 +117,7 @@ __device__ __forceinline__ void sort_chunk_by_bucket(Key (&kk)[ITEMS], uint32_t 
     }
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) dig[r] = (b[r] < NB) ? (b[r] & ((1u << lo_bits) - 1)) : 64u;
-    rank_stable<kLocalThreads, ITEMS>(dig, rounds, lo_bits, wcnt, dstart, tmp, pos);
+    rank_stable<kLocalThreads, ITEMS>(dig, lo_bits, wcnt, dstart, tmp, pos);
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r)
         if ((uint32_t)r < rounds && b[r] < NB) {
@@ -146,7 +142,7 @@ __device__ __forceinline__ void sort_chunk_by_bucket(Key (&kk)[ITEMS], uint32_t 
     }
     // rank_stable synchronises before counting, so every wave has finished
     // reading the buffers before any wave overwrites them below
-    rank_stable<kLocalThreads, ITEMS>(dig, rounds, hi_bits, wcnt, dstart, tmp, pos);
+    rank_stable<kLocalThreads, ITEMS>(dig, hi_bits, wcnt, dstart, tmp, pos);
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r)
         if ((uint32_t)r < rounds && b[r] < NB) {
@@ -246,6 +242,20 @@ __device__ __forceinline__ uint4 head_entry<uint64_t>(uint32_t start, uint32_t e
     return make_uint4(start, end, (uint32_t)k0, (uint32_t)(k0 >> 32));
 }
 
+// Write bucket b's index entry; a bucket longer than kRunBucket is also
+// appended to the list of long buckets (its key slots are replaced later by
+// its key-run summary).
+template <typename Key>
+__device__ __forceinline__ void put_index(const IndexOut& ix, uint32_t b, uint32_t start,
+                                          uint32_t end, const Key* k) {
+    ix.head[b] = head_entry<Key>(start, end, k);
+    if (end - start > kRunBucket) {
+        const uint32_t slot = atomicAdd(&ix.long_stat[0], 1u);
+        if (slot < ix.long_cap) ix.long_list[slot] = b;
+        atomicAdd(&ix.long_stat[1], end - start);
+    }
+}
+
 // Build one bin of L <= kLightCap keys whose buckets are [v0, v0 + nb) with
 // nb <= 2^k.  Entry e (e < L) of the bin is src_keys[e], with id src_ids[e]
 // (or id_base + e when src_ids is null).  The bin's keys and ids go to
@@ -254,7 +264,7 @@ __device__ __forceinline__ uint4 head_entry<uint64_t>(uint32_t start, uint32_t e
 // Usual case (every bucket of the bin holds at most kFixMax keys): LDS
 // counting sort with atomic cursors, then an insertion sort by id inside each
 // bucket.  Otherwise the bin (in id order) is stably ranked by local bucket.
-// When `head` is not null it also receives each bucket's probe index entry.
+// When ix.head is not null it also receives each bucket's probe index entry.
 // Called by a whole workgroup of kLocalThreads threads.
 template <typename Key>
 __device__ __forceinline__ void light_bin_body(const Key* __restrict__ src_keys,
@@ -263,7 +273,7 @@ __device__ __forceinline__ void light_bin_body(const Key* __restrict__ src_keys,
                                                uint32_t v0, uint32_t k, uint32_t nb,
                                                const typename KeyTraits<Key>::Params& hp,
                                                uint32_t* __restrict__ offsets,
-                                               uint4* __restrict__ head,
+                                               const IndexOut& ix,
                                                uint32_t* __restrict__ ids, Key* __restrict__ ekeys,
                                                unsigned char* smem) {
     constexpr int IT = kLightItems;
@@ -339,7 +349,7 @@ __device__ __forceinline__ void light_bin_body(const Key* __restrict__ src_keys,
         for (uint32_t v = threadIdx.x; v < nb; v += kLocalThreads) {
             const uint32_t lo = v ? cnt[v - 1] : 0u, hi = cnt[v];
             offsets[v0 + v] = out + lo;
-            if (head) head[v0 + v] = head_entry<Key>(out + lo, out + hi, skeys + lo);
+            if (ix.head) put_index<Key>(ix, v0 + v, out + lo, out + hi, skeys + lo);
         }
     } else {
         sort_chunk_by_bucket<Key, IT>(kk, id, b, rounds, L, wchunk, k, skeys, sids, sb, wcnt,
@@ -348,7 +358,7 @@ __device__ __forceinline__ void light_bin_body(const Key* __restrict__ src_keys,
         for (uint32_t v = threadIdx.x; v < nb; v += kLocalThreads) {
             const uint32_t lo = cnt[v], hi = (v + 1 < NB) ? cnt[v + 1] : L;
             offsets[v0 + v] = out + lo;
-            if (head) head[v0 + v] = head_entry<Key>(out + lo, out + hi, skeys + lo);
+            if (ix.head) put_index<Key>(ix, v0 + v, out + lo, out + hi, skeys + lo);
         }
     }
     for (uint32_t p = threadIdx.x; p < L; p += kLocalThreads) {
@@ -367,7 +377,7 @@ __device__ __forceinline__ void heavy_bin_body(const Key* __restrict__ src_keys,
                                                uint32_t v0, uint32_t k, uint32_t nb,
                                                const typename KeyTraits<Key>::Params& hp,
                                                uint32_t* __restrict__ offsets,
-                                               uint4* __restrict__ head,
+                                               const IndexOut& ix,
                                                uint32_t* __restrict__ ids, Key* __restrict__ ekeys,
                                                unsigned char* smem) {
     constexpr int IT = kHeavyItems;
@@ -445,10 +455,10 @@ __device__ __forceinline__ void heavy_bin_body(const Key* __restrict__ src_keys,
         __syncthreads();
     }
     // cur[v] is now the end of bucket v; the bin's edges are in ekeys
-    if (head)
+    if (ix.head)
         for (uint32_t v = threadIdx.x; v < nb; v += kLocalThreads) {
             const uint32_t lo = v ? cur[v - 1] : out;
-            head[v0 + v] = head_entry<Key>(lo, cur[v], ekeys + lo);
+            put_index<Key>(ix, v0 + v, lo, cur[v], ekeys + lo);
         }
 }
 

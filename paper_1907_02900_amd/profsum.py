@@ -1,0 +1,130 @@
+"""Summaries of rocprofv3 output databases (rocpd SQLite, ``*_results.db``).
+
+Two commands, both reading what ``rocprofv3 -d DIR -o run`` wrote:
+
+``trace DB --title T --cmd C``
+    Markdown table of per-kernel statistics (calls, total and average
+    duration) from a ``--kernel-trace --stats`` run, plus the launch shape of
+    each library kernel.
+
+``traffic --fetch DB --write DB --copy-fetch DB --copy-write DB --out JSON``
+    HBM bytes per launch of the library's kernels from two ``--pmc`` runs
+    (FETCH_SIZE, then WRITE_SIZE; both in KiB per dispatch).  Each counter is
+    scaled by what it reads for a plain 1 GiB device-to-device copy (the
+    ``bench.py --copy-calibration`` run), so that the figures are in bytes of
+    HBM traffic.  The JSON carries the digest of the kernel sources it was
+    taken on; bench.py reports the traffic only while that digest matches.
+
+Usage: python3 -m paper_1907_02900_amd.profsum trace|traffic ...
+"""
+import argparse
+import collections
+import json
+import sqlite3
+import sys
+
+# library kernel -> name of the timed range bench.py reports it under
+RANGES = [
+    ("k_probe_count", "probe_count"),
+    ("k_local_light", "v2_local_build"),
+    ("k_local_heavy", "v2_local_heavy"),
+    ("k_tile_partition<unsigned int, false>", "v2_partition_t1"),
+    ("k_tile_partition<unsigned int, true>", "v2_partition_t2"),
+    ("k_tile_hist", "v2_tile_hist"),
+    ("k_hist_global", "v1_hist_global"),
+    ("k_scatter_v1", "v1_scatter"),
+    ("k_intersect_count", "intersect_count"),
+]
+
+
+def short_name(name):
+    s = name.replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "")
+    if "at::native" in s:
+        s = "torch:" + s.split("<")[0][-40:]
+    return s
+
+
+def cmd_trace(a):
+    c = sqlite3.connect(a.db)
+    out = ["# %s" % a.title, "", "Command (from the repository root, one MI355X):", "",
+           "    %s" % a.cmd, "", "rocprofv3 kernel statistics (durations in microseconds):", "",
+           "| kernel | calls | total us | avg us | % |", "|---|---|---|---|---|"]
+    for name, calls, tot, avg, pct in c.execute(
+            "select name, total_calls, total_duration, average, percentage from top_kernels"):
+        out.append("| %s | %d | %.1f | %.2f | %.2f |" % (short_name(name), calls, tot, avg, pct))
+    out += ["", "Launch shapes (grid in threads, workgroup size, LDS bytes, VGPRs):", ""]
+    seen = set()
+    for r in c.execute("select name, grid_x, workgroup_x, lds_size, vgpr_count from kernels"):
+        nm = short_name(r[0])
+        if nm in seen or not nm.startswith("hg::"):
+            continue
+        seen.add(nm)
+        out.append("- %s: grid %d, wg %d, lds %d, vgpr %d" % (nm, r[1], r[2], r[3], r[4]))
+    text = "\n".join(out) + "\n"
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write(text)
+    sys.stdout.write(text)
+
+
+def per_kernel(db, counter):
+    c = sqlite3.connect(db)
+    agg = collections.defaultdict(list)
+    for name, cn, cv in c.execute(
+            "select name, counter_name, counter_value from pmc_events"):
+        if cn == counter:
+            agg[name].append(cv)
+    return agg
+
+
+def median(v):
+    v = sorted(v)
+    return v[len(v) // 2]
+
+
+def cmd_traffic(a):
+    fc, wc = per_kernel(a.copy_fetch, "FETCH_SIZE"), per_kernel(a.copy_write, "WRITE_SIZE")
+
+    def copy_vals(d):
+        return [x for k, vs in d.items() if "copy" in k.lower() or "elementwise" in k.lower()
+                for x in vs]
+
+    # counters are KiB per dispatch; the calibration copy moves 1 GiB each way
+    sf = (1 << 30) / (median(copy_vals(fc)) * 1024.0)
+    sw = (1 << 30) / (median(copy_vals(wc)) * 1024.0)
+    fb, wb = per_kernel(a.fetch, "FETCH_SIZE"), per_kernel(a.write, "WRITE_SIZE")
+    res = {"source_digest": a.digest, "fetch_scale": sf, "write_scale": sw,
+           "command": a.cmd, "kernels": {}}
+    for full, vals in fb.items():
+        s = short_name(full).replace("hg::", "")
+        key = next((nm for pat, nm in RANGES if s.startswith(pat)), None)
+        if key is None:
+            continue
+        f = median(vals) * 1024.0 * sf
+        w = median(wb.get(full, [0.0])) * 1024.0 * sw
+        res["kernels"][key] = {"kernel": s, "fetch_bytes": f, "write_bytes": w,
+                               "hbm_bytes_per_launch": f + w, "dispatches": len(vals)}
+    with open(a.out, "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps(res, indent=1))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(prog="profsum")
+    sub = ap.add_subparsers(dest="what", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("db")
+    t.add_argument("--title", required=True)
+    t.add_argument("--cmd", required=True)
+    t.add_argument("--out")
+    t.set_defaults(fn=cmd_trace)
+    p = sub.add_parser("traffic")
+    for k in ("fetch", "write", "copy_fetch", "copy_write", "out", "digest", "cmd"):
+        p.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
+    p.set_defaults(fn=cmd_traffic)
+    a = ap.parse_args(argv)
+    a.fn(a)
+
+
+if __name__ == "__main__":
+    main()

@@ -53,20 +53,48 @@ def duplicate_keys(n: int, appearances: float, key_bits: int = 32, seed: int = 0
     return rng.integers(1, hi, size=int(n), dtype=_dtype(key_bits), endpoint=True)
 
 
-def zipf_keys(n: int, s: float, distinct: int = 1 << 24, seed: int = 0) -> np.ndarray:
+def _inverse_cdf(cdf: np.ndarray, u: np.ndarray) -> np.ndarray:
+    """For each u in [0, 1), the first index r with cdf[r] > u (what
+    np.searchsorted(cdf, u, side="right") returns; cdf ends at 1).  A guide
+    table over equal-width cells of [0, 1) (indexed search) brackets each
+    answer, and a vectorised bisection inside the bracket finishes it, so that
+    2^28 draws take seconds instead of a full binary search each."""
+    cells = min(1 << 24, max(1, cdf.size))
+    edges = np.arange(cells + 1, dtype=np.float64) / cells
+    guide = np.searchsorted(cdf, edges, side="right")
+    np.minimum(guide, cdf.size - 1, out=guide)
+    j = np.minimum((u * cells).astype(np.int64), cells - 1)
+    lo = guide[j]              # cdf[lo - 1] <= j / cells <= u
+    hi = guide[j + 1]          # cdf[hi] > u, or hi is the last index
+    idx = np.nonzero(lo < hi)[0]
+    while idx.size:
+        a, b = lo[idx], hi[idx]
+        mid = (a + b) >> 1
+        right = cdf[mid] <= u[idx]
+        lo[idx] = np.where(right, mid + 1, a)
+        hi[idx] = np.where(right, b, mid)
+        idx = idx[lo[idx] < hi[idx]]
+    return lo
+
+
+def zipf_keys(n: int, s: float, distinct: int = 1 << 24, seed: int = 0,
+              map_seed: int | None = None) -> np.ndarray:
     """n uint32 keys with a bounded Zipf law over `distinct` ranks,
     p(r) proportional to r^-s, sampled by inverse CDF.  Rank r maps to a key by
     a seeded odd-multiplier bijection on uint32 so that frequent keys are not
-    small integers."""
+    small integers.  The bijection comes from `map_seed` when given (so that a
+    build side and a probe side drawn with different seeds share one law over
+    the same keys), else from `seed`."""
     rng = _rng(seed)
     r = np.arange(1, int(distinct) + 1, dtype=np.float64)
     cdf = np.cumsum(r ** (-float(s)))
     cdf /= cdf[-1]
     u = rng.random(int(n))
-    rank = np.searchsorted(cdf, u, side="right").astype(np.uint64)
+    rank = _inverse_cdf(cdf, u).astype(np.uint64)
     rank = np.minimum(rank, distinct - 1)
-    mult = (int(rng.integers(1, 1 << 31)) << 1) | 1
-    add = int(rng.integers(0, 1 << 32))
+    mrng = rng if map_seed is None else _rng(map_seed)
+    mult = (int(mrng.integers(1, 1 << 31)) << 1) | 1
+    add = int(mrng.integers(0, 1 << 32))
     return ((rank * np.uint64(mult) + np.uint64(add)) & np.uint64(U32_MAX)).astype(np.uint32)
 
 

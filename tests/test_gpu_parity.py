@@ -300,6 +300,58 @@ def test_intersect_matches_oracle(hg, kb, na, nb, V, kind):
         assert np.array_equal(got, np.stack([ep, eb], 1))
 
 
+def skew_keys(kind, n, kb, seed):
+    if kind == "zipf15":
+        return workloads.zipf_keys(n, 1.5, distinct=1 << 12, seed=seed,
+                                   map_seed=5).astype(dt(kb))
+    if kind == "dup100":
+        return workloads.duplicate_keys(n, 100.0, kb, seed)
+    if kind == "few":  # a handful of keys, each in a long bucket
+        return (workloads.uniform_keys(n, 32, seed) % 7 + 1000).astype(dt(kb))
+    raise ValueError(kind)
+
+
+@pytest.mark.parametrize("kb", [32, 64])
+@pytest.mark.parametrize("kind,n,m,V", [("zipf15", 200000, 300000, 200000),
+                                        ("dup100", 150000, 150000, 1 << 14),
+                                        ("few", 60000, 50000, 5000),
+                                        ("zipf15", 30000, 40000, 1)])
+def test_long_buckets_use_key_runs_with_exact_results(hg, kb, kind, n, m, V):
+    # buckets longer than 32 entries are probed through their key runs:
+    # counts, pairs and intersections must equal the oracle's, and equal the
+    # same table probed by scanning (index off)
+    say("key runs", kb, kind, n, m, V)
+    k = skew_keys(kind, n, kb, seed=41)
+    q = skew_keys(kind, m, kb, seed=42)
+    q[::3] = workloads.uniform_keys(q[::3].size, kb, 43)  # some misses into long buckets
+    exp, etot = oracle.probe_counts(k, q, kb)
+    dq = hg.to_device(q)
+    t = hg.hg_build(hg.to_device(k), V, seed=17)
+    ts = hg.hg_build(hg.to_device(k), V, seed=17, index=False)
+    c, tot = hg.hg_probe(t, dq, counts=True, total=True)
+    assert np.array_equal(hg.to_numpy(c, np.uint32), exp) and tot == etot
+    c2, _ = hg.hg_probe(ts, dq, counts=True)
+    assert torch.equal(c, c2)
+    # pairs for the queries whose matches stay small
+    light = np.nonzero(exp <= 200)[0][:20000]
+    qs = q[light]
+    b, p, ptot = hg.hg_probe_pairs(t, hg.to_device(qs))
+    eb, ep, et = oracle.probe_pairs(k, qs, kb)
+    assert ptot == et
+    assert np.array_equal(hg.to_numpy(p, np.uint32), ep)
+    assert np.array_equal(hg.to_numpy(b, np.uint32), eb)
+    # intersection: A = the table with runs, B = a table of the light queries
+    tb = hg.hg_build(hg.to_device(qs), V, seed=17)
+    ci, _, _, itot = hg.hg_intersect(t, tb, counts=True, total=True)
+    assert itot == et
+    assert np.array_equal(hg.to_numpy(ci, np.uint32), oracle.probe_counts(k, qs, kb)[0])
+    if 0 < et < 5_000_000:
+        _, ai, bi, tot2 = hg.hg_intersect(t, tb, counts=False, capacity=et)
+        got = np.stack([hg.to_numpy(bi, np.uint32), hg.to_numpy(ai, np.uint32)], 1)
+        got = got[np.lexsort((got[:, 1], got[:, 0]))]
+        assert tot2 == et and np.array_equal(got, np.stack([ep, eb], 1))
+
+
 def test_intersect_rejects_mismatched_tables(hg):
     k = hg.to_device(workloads.uniform_keys(1000, 32, 1))
     a = hg.hg_build(k, 100, seed=1)
