@@ -58,7 +58,7 @@ def check_table(hg, table, keys_dev, h_dev, V, stable):
     n = keys_dev.numel()
     assert info.n == n and info.hash_range == V
     off, ids, ek = table.export()
-    off, ids = u64(off), u64(ids)
+    off, ids, ek = u64(off), u64(ids), u64(ek)
     cnt = torch.bincount(h_dev, minlength=V)
     exp_off = torch.zeros(V + 1, dtype=torch.int64, device=off.device)
     torch.cumsum(cnt, 0, out=exp_off[1:])
