@@ -141,8 +141,9 @@ def run_batched(hg, workloads, torch, tables=4096, reps=5, log=print):
     outs = [t["counts"] for t in b.tables]
 
     def loop():
+        # the same work as the graph: V2 tables without the probe index
         for i in range(tables):
-            loop_tabs[i].rebuild(keys[i], int(sizes[i]), seed=i)
+            loop_tabs[i].rebuild(keys[i], int(sizes[i]), seed=i, index=False)
             hg.hg_probe(loop_tabs[i], qs[i], counts=True, out=outs[i])
 
     t_loop = timed(loop, 2, torch)
@@ -390,10 +391,14 @@ def main():
     dk_ = kernels[dom]
     achieved = dk_["alg_bytes"] / (dk_["avg_ms"] / 1000.0) / 1e9
     digest = src_digest()
+    traffic = load_traffic(dom, digest)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": load_traffic(dom, digest), "kernel": dom,
-                "alg_bytes_per_launch": dk_["alg_bytes"], "avg_launch_ms": dk_["avg_ms"]}
+                "traffic": traffic, "kernel": dom,
+                "alg_bytes_per_launch": dk_["alg_bytes"], "avg_launch_ms": dk_["avg_ms"],
+                # HBM bytes the counters saw per launch, over the same launch time
+                "traffic_GBps": (round(traffic / (dk_["avg_ms"] / 1000.0) / 1e9, 1)
+                                 if traffic else None)}
 
     phases = {"kernels": kernels, "source_digest": digest,
               "probe_sum_bucket_len": sum_len, "probe_sum_keys_past_index": sum_tail}
@@ -459,6 +464,22 @@ def main():
                              "probe_ms": round(tp, 3), "probe_Gkeys": round(n64 / tp / 1e6, 2)}
         t64.free()
         del dk64, dq64, c64, t64
+        # skewed join: 2^27 Zipf(1.2) build keys over 2^24 values, V = 2^27,
+        # 2^28 probe keys from the same law (long buckets use key runs)
+        log("zipf join")
+        nz = n // 2
+        kz = hg.to_device(workloads.zipf_keys(nz, 1.2, 1 << 24, seed=21, map_seed=99))
+        qz = hg.to_device(workloads.zipf_keys(m, 1.2, 1 << 24, seed=22, map_seed=99))
+        tz = hg.Table.create(nz, nz, 32)
+        tb = timed(lambda: tz.rebuild(kz, nz, 9), 2, torch)
+        tp = timed(lambda: hg.hg_probe(tz, qz, counts=True, out=counts), 2, torch)
+        _, ztot = hg.hg_probe(tz, qz, counts=False, total=True)
+        ex["zipf1.2_join"] = {"build_ms": round(tb, 3), "build_Gkeys": round(nz / tb / 1e6, 2),
+                              "probe_ms": round(tp, 3), "probe_Gkeys": round(m / tp / 1e6, 2),
+                              "matches": ztot}
+        log("zipf join build %.3f ms probe %.3f ms, %d matches" % (tb, tp, ztot))
+        tz.free()
+        del kz, qz, tz
         phases["extras"] = ex
 
     if not args.no_batched:
