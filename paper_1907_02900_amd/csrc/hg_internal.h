@@ -62,6 +62,7 @@ constexpr int kLightItems = 12;
 constexpr uint32_t kLightCap = kLocalThreads * kLightItems;  // keys a bin may hold in LDS
 constexpr int kHeavyItems = 16;
 constexpr uint32_t kHeavyChunk = kLocalThreads * kHeavyItems;  // chunk of an oversize bin
+constexpr uint32_t kSliceKeys = 1u << 17;  // bins above this are split over workgroups
 constexpr uint32_t kMaxLocalBits = 12;                          // buckets per bin <= 4096
 constexpr uint32_t kMaxDigitBits = 11;                       // partition fan-out <= 2048
 constexpr uint32_t kOneTierBits = 9;                         // single partition pass up to 512 bins

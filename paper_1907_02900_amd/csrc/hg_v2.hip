@@ -279,9 +279,11 @@ size_t partition_smem(uint32_t bits) {
 
 // -------------------------------------------------------- segment setup ---
 
-// Tier-1 segment: the whole input; also clears the oversize-bin counter.
+// Tier-1 segment: the whole input; also clears the oversize-bin counters
+// (oversize bins, split bins, their slices).
 __global__ void k_segs_single(Segs g, uint32_t n, uint32_t ntiles, uint32_t nchunks,
-                              uint32_t* heavy_count) {
+                              uint32_t* ctr) {
+    if (threadIdx.x < 3) ctr[threadIdx.x] = 0;
     if (threadIdx.x == 0) {
         g.seg_start[0] = 0;
         g.seg_start[1] = n;
@@ -289,7 +291,6 @@ __global__ void k_segs_single(Segs g, uint32_t n, uint32_t ntiles, uint32_t nchu
         g.tile_prefix[1] = ntiles;
         g.chunk_prefix[0] = 0;
         g.chunk_prefix[1] = nchunks;
-        *heavy_count = 0;
     }
 }
 
@@ -337,10 +338,16 @@ __global__ __launch_bounds__(1024) void k_segs_from_bases(const uint32_t* __rest
 // Start of every final bin (bin = segment * 2^bits + digit) in the
 // partitioned array, bin_start[bins] = n, offsets[V] = n, and the list of
 // bins too large for the LDS kernel.
+// Bins above kSliceKeys keys are split into slices of kSliceKeys for several
+// workgroups: they are listed in huge_list with their first slice in huge_s0,
+// and slice_owner maps every slice back to its entry.  ctr: oversize bins,
+// split bins, slices.
 __global__ void k_bin_starts(const uint32_t* __restrict__ base, Segs g, uint32_t bits,
                              uint32_t bins, uint32_t n, uint32_t V, uint32_t* __restrict__ bin_start,
                              uint32_t* __restrict__ offsets, uint32_t* __restrict__ heavy_list,
-                             uint32_t* __restrict__ heavy_count) {
+                             uint32_t* __restrict__ ctr, uint32_t* __restrict__ huge_list,
+                             uint32_t* __restrict__ huge_s0, uint32_t* __restrict__ slice_owner,
+                             uint32_t huge_cap, uint32_t slice_cap) {
     const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t st = 0, nx = 0;
     bool have = false;
@@ -361,8 +368,151 @@ __global__ void k_bin_starts(const uint32_t* __restrict__ base, Segs g, uint32_t
         }
     }
     if (have) {
-        const uint32_t slot = atomicAdd(heavy_count, 1u);
-        heavy_list[slot] = b;
+        const uint32_t L = nx - st;
+        if (L <= kSliceKeys) {
+            const uint32_t slot = atomicAdd(&ctr[0], 1u);
+            heavy_list[slot] = b;
+        } else {
+            // capacities hold: a split bin has > kSliceKeys keys, so there are
+            // at most n / kSliceKeys of them and fewer than 2n / kSliceKeys slices
+            const uint32_t ns = (L + kSliceKeys - 1) / kSliceKeys;
+            const uint32_t idx = atomicAdd(&ctr[1], 1u);
+            const uint32_t s0 = atomicAdd(&ctr[2], ns);
+            if (idx < huge_cap && s0 + ns <= slice_cap) {
+                huge_list[idx] = b;
+                huge_s0[idx] = s0;
+                for (uint32_t j = 0; j < ns; ++j) slice_owner[s0 + j] = idx;
+            }
+        }
+    }
+}
+
+// Slice `item` of a split bin: its bin and key range.
+struct SliceRef {
+    uint32_t idx, b, begin, end;
+};
+
+__device__ __forceinline__ SliceRef slice_at(uint32_t item, const uint32_t* __restrict__ bin_start,
+                                             const uint32_t* __restrict__ huge_list,
+                                             const uint32_t* __restrict__ huge_s0,
+                                             const uint32_t* __restrict__ slice_owner) {
+    SliceRef r;
+    r.idx = slice_owner[item];
+    r.b = huge_list[r.idx];
+    const uint32_t j = item - huge_s0[r.idx];
+    const uint32_t bs = bin_start[r.b], be = bin_start[r.b + 1];
+    r.begin = bs + j * kSliceKeys;
+    r.end = (be - r.begin > kSliceKeys) ? r.begin + kSliceKeys : be;
+    return r;
+}
+
+// Per-slice bucket histograms of the split bins: hist[item][0 .. 2^k).
+template <typename Key>
+__global__ __launch_bounds__(kLocalThreads) void k_huge_hist(
+    const Key* __restrict__ src_keys, const uint32_t* __restrict__ bin_start,
+    const uint32_t* __restrict__ huge_list, const uint32_t* __restrict__ huge_s0,
+    const uint32_t* __restrict__ slice_owner, const uint32_t* __restrict__ ctr,
+    typename KeyTraits<Key>::Params hp, uint32_t k, uint32_t* __restrict__ hist) {
+    extern __shared__ uint32_t cnt[];
+    const uint32_t NB = 1u << k, nsl = ctr[2];
+    for (uint32_t item = blockIdx.x; item < nsl; item += gridDim.x) {
+        const SliceRef r = slice_at(item, bin_start, huge_list, huge_s0, slice_owner);
+        const uint32_t v0 = r.b << k;
+        for (uint32_t i = threadIdx.x; i < NB; i += kLocalThreads) cnt[i] = 0;
+        __syncthreads();
+        for (uint32_t i = r.begin + threadIdx.x; i < r.end; i += kLocalThreads)
+            atomicAdd(&cnt[KeyTraits<Key>::bucket(src_keys[i], hp) - v0], 1u);
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < NB; i += kLocalThreads)
+            hist[(size_t)item * NB + i] = cnt[i];
+        __syncthreads();
+    }
+}
+
+// One workgroup per split bin: bucket starts (written to offsets) and, in
+// place of each slice's counts, the position of the slice's first entry of
+// every bucket.
+__global__ __launch_bounds__(kLocalThreads) void k_huge_scan(
+    const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ huge_list,
+    const uint32_t* __restrict__ huge_s0, const uint32_t* __restrict__ ctr, uint32_t k,
+    uint32_t V, uint32_t* __restrict__ hist, uint32_t* __restrict__ offsets) {
+    __shared__ uint32_t tmp[kLocalThreads / kWave + 1];
+    const uint32_t NB = 1u << k, nh = ctr[1];
+    const uint32_t per = NB >= (uint32_t)kLocalThreads ? NB / kLocalThreads : 1u;  // <= 16
+    const uint32_t i0 = threadIdx.x * per;
+    for (uint32_t idx = blockIdx.x; idx < nh; idx += gridDim.x) {
+        const uint32_t b = huge_list[idx], s0 = huge_s0[idx];
+        const uint32_t bs = bin_start[b], L = bin_start[b + 1] - bs;
+        const uint32_t ns = (L + kSliceKeys - 1) / kSliceKeys;
+        const uint32_t v0 = b << k, nb = (V - v0 < NB) ? V - v0 : NB;
+        uint32_t tot[16];
+        uint32_t mine = 0;
+        for (uint32_t j = 0; j < per; ++j) {
+            uint32_t acc = 0;
+            if (i0 + j < NB)
+                for (uint32_t sl = 0; sl < ns; ++sl) acc += hist[(size_t)(s0 + sl) * NB + i0 + j];
+            tot[j] = acc;
+            mine += acc;
+        }
+        uint32_t all;
+        uint32_t run = bs + block_excl_scan<kLocalThreads>(mine, tmp, &all);
+        for (uint32_t j = 0; j < per; ++j) {
+            const uint32_t v = i0 + j;
+            if (v < NB) {
+                if (v < nb) offsets[v0 + v] = run;
+                uint32_t r = run;
+                for (uint32_t sl = 0; sl < ns; ++sl) {
+                    const size_t at = (size_t)(s0 + sl) * NB + v;
+                    const uint32_t x = hist[at];
+                    hist[at] = r;
+                    r += x;
+                }
+            }
+            run += tot[j];
+        }
+        __syncthreads();
+    }
+}
+
+// Stable placement of every slice of the split bins, from its cursors.
+template <typename Key>
+__global__ __launch_bounds__(kLocalThreads) void k_huge_place(
+    const Key* __restrict__ src_keys, const uint32_t* __restrict__ src_ids,
+    const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ huge_list,
+    const uint32_t* __restrict__ huge_s0, const uint32_t* __restrict__ slice_owner,
+    const uint32_t* __restrict__ ctr, typename KeyTraits<Key>::Params hp, uint32_t k,
+    const uint32_t* __restrict__ hist, uint32_t* __restrict__ ids, Key* __restrict__ ekeys) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint32_t NB = 1u << k, nsl = ctr[2];
+    const HeavyLds<Key> m(smem, NB);
+    for (uint32_t item = blockIdx.x; item < nsl; item += gridDim.x) {
+        const SliceRef r = slice_at(item, bin_start, huge_list, huge_s0, slice_owner);
+        for (uint32_t i = threadIdx.x; i < NB; i += kLocalThreads)
+            m.cur[i] = hist[(size_t)item * NB + i];
+        __syncthreads();
+        place_in_chunks<Key>(src_keys + r.begin, src_ids + r.begin, 0u, r.end - r.begin,
+                             bin_start[r.b], bin_start[r.b + 1], r.b << k, k, hp, ids, ekeys,
+                             smem);
+        __syncthreads();
+    }
+}
+
+// Probe index entries of the split bins' buckets (after their placement).
+template <typename Key>
+__global__ __launch_bounds__(kLocalThreads) void k_huge_index(
+    const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ huge_list,
+    const uint32_t* __restrict__ ctr, uint32_t k, uint32_t V,
+    const uint32_t* __restrict__ offsets, const Key* __restrict__ ekeys, IndexOut ix) {
+    const uint32_t NB = 1u << k, nh = ctr[1];
+    for (uint32_t idx = blockIdx.x; idx < nh; idx += gridDim.x) {
+        const uint32_t b = huge_list[idx];
+        const uint32_t v0 = b << k, nb = (V - v0 < NB) ? V - v0 : NB;
+        const uint32_t be = bin_start[b + 1];
+        for (uint32_t v = threadIdx.x; v < nb; v += kLocalThreads) {
+            const uint32_t lo = offsets[v0 + v];
+            const uint32_t hi = (v + 1 < nb) ? offsets[v0 + v + 1] : be;
+            put_index<Key>(ix, v0 + v, lo, hi, ekeys + lo);
+        }
     }
 }
 
@@ -459,7 +609,10 @@ namespace {
 struct V2Ws {
     void* rkeys;
     uint32_t* rids;
-    uint32_t *m1, *c1, *m2, *c2, *bin_start, *heavy_list, *heavy_count;
+    uint32_t *m1, *c1, *m2, *c2, *bin_start, *heavy_list;
+    uint32_t* ctr;  // [3]: oversize bins, split bins, slices of split bins
+    uint32_t *huge_list, *huge_s0, *slice_owner, *slice_hist;
+    uint32_t huge_cap, slice_cap;
     Segs s1, s2;
 };
 
@@ -488,7 +641,13 @@ size_t layout_v2(void* ws, const V2Plan& p, size_t key_size, V2Ws* out) {
     }
     w.bin_start = c.take<uint32_t>((size_t)p.bins + 1);
     w.heavy_list = c.take<uint32_t>((size_t)p.bins);
-    w.heavy_count = c.take<uint32_t>(1);
+    w.ctr = c.take<uint32_t>(3);
+    w.huge_cap = (uint32_t)(p.n / kSliceKeys + 1);
+    w.slice_cap = 2 * w.huge_cap;
+    w.huge_list = c.take<uint32_t>(w.huge_cap);
+    w.huge_s0 = c.take<uint32_t>(w.huge_cap);
+    w.slice_owner = c.take<uint32_t>(w.slice_cap);
+    w.slice_hist = c.take<uint32_t>((size_t)w.slice_cap << p.k);
     if (out) *out = w;
     return c.off + 256;
 }
@@ -556,6 +715,8 @@ hipError_t set_smem_limits() {
                                hipFuncAttributeMaxDynamicSharedMemorySize, lim));
     HG_TRY(hipFuncSetAttribute((const void*)k_local_heavy<Key>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+    HG_TRY(hipFuncSetAttribute((const void*)k_huge_place<Key>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lim));
     done = true;
     return hipSuccess;
 }
@@ -591,7 +752,7 @@ hipError_t run_build_v2(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, 
     {
         HG_PROF("v2_segs", s);
         hipLaunchKernelGGL(k_segs_single, dim3(1), dim3(64), 0, s, w.s1, (uint32_t)n, p.ntiles1,
-                           p.nchunks1, w.heavy_count);
+                           p.nchunks1, w.ctr);
     }
     HG_TRY(hipGetLastError());
     const uint32_t* bin_mat;
@@ -623,7 +784,8 @@ hipError_t run_build_v2(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, 
         HG_PROF("v2_bin_starts", s);
         hipLaunchKernelGGL(k_bin_starts, dim3((uint32_t)ceil_div(p.bins + 1, 256)), dim3(256), 0,
                            s, bin_mat, bin_segs, bin_bits, p.bins, (uint32_t)n, (uint32_t)V,
-                           w.bin_start, offsets, w.heavy_list, w.heavy_count);
+                           w.bin_start, offsets, w.heavy_list, w.ctr, w.huge_list, w.huge_s0,
+                           w.slice_owner, w.huge_cap, w.slice_cap);
     }
     HG_TRY(hipGetLastError());
     {
@@ -639,10 +801,38 @@ hipError_t run_build_v2(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, 
         hipLaunchKernelGGL(k_local_heavy<Key>, dim3(hg_grid), dim3(kLocalThreads),
                            heavy_smem<Key>(p.k), s, (const Key*)rkeys, (const uint32_t*)w.rids,
                            (const uint32_t*)w.bin_start, (const uint32_t*)w.heavy_list,
-                           (const uint32_t*)w.heavy_count, hp, p.k, offsets, ix, ids,
-                           ekeys);
+                           (const uint32_t*)w.ctr, hp, p.k, offsets, ix, ids, ekeys);
     }
-    return hipGetLastError();
+    HG_TRY(hipGetLastError());
+    if (n > kSliceKeys) {
+        // bins above kSliceKeys keys (skew): per-slice counts, per-bin scan,
+        // per-slice placement; the grids drain device-side work lists
+        HG_PROF("v2_split_bins", s);
+        const uint32_t* bs = w.bin_start;
+        hipLaunchKernelGGL(k_huge_hist<Key>, dim3(1024), dim3(kLocalThreads),
+                           (size_t)4 << p.k, s, (const Key*)rkeys, bs,
+                           (const uint32_t*)w.huge_list, (const uint32_t*)w.huge_s0,
+                           (const uint32_t*)w.slice_owner, (const uint32_t*)w.ctr, hp, p.k,
+                           w.slice_hist);
+        HG_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_huge_scan, dim3(256), dim3(kLocalThreads), 0, s, bs,
+                           (const uint32_t*)w.huge_list, (const uint32_t*)w.huge_s0,
+                           (const uint32_t*)w.ctr, p.k, (uint32_t)V, w.slice_hist, offsets);
+        HG_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_huge_place<Key>, dim3(1024), dim3(kLocalThreads),
+                           heavy_smem<Key>(p.k), s, (const Key*)rkeys, (const uint32_t*)w.rids,
+                           bs, (const uint32_t*)w.huge_list, (const uint32_t*)w.huge_s0,
+                           (const uint32_t*)w.slice_owner, (const uint32_t*)w.ctr, hp, p.k,
+                           (const uint32_t*)w.slice_hist, ids, ekeys);
+        HG_TRY(hipGetLastError());
+        if (ix.head) {
+            hipLaunchKernelGGL(k_huge_index<Key>, dim3(256), dim3(kLocalThreads), 0, s, bs,
+                               (const uint32_t*)w.huge_list, (const uint32_t*)w.ctr, p.k,
+                               (uint32_t)V, (const uint32_t*)offsets, (const Key*)ekeys, ix);
+            HG_TRY(hipGetLastError());
+        }
+    }
+    return hipSuccess;
 }
 
 template hipError_t run_build_v2<uint32_t>(const uint32_t*, uint64_t, uint64_t, uint64_t,

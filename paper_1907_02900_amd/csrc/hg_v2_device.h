@@ -367,39 +367,48 @@ __device__ __forceinline__ void light_bin_body(const Key* __restrict__ src_keys,
     }
 }
 
-// The same for a bin of any size (arriving in id order): keys counted per
-// bucket first, then placed chunk by chunk, in order, with running
-// per-bucket cursors, so placement stays stable.  Whole workgroup.
+// Pointers into the heavy_smem layout.
 template <typename Key>
-__device__ __forceinline__ void heavy_bin_body(const Key* __restrict__ src_keys,
-                                               const uint32_t* __restrict__ src_ids,
-                                               uint32_t id_base, uint32_t L, uint32_t out,
-                                               uint32_t v0, uint32_t k, uint32_t nb,
-                                               const typename KeyTraits<Key>::Params& hp,
-                                               uint32_t* __restrict__ offsets,
-                                               const IndexOut& ix,
-                                               uint32_t* __restrict__ ids, Key* __restrict__ ekeys,
-                                               unsigned char* smem) {
+struct HeavyLds {
+    Key* skeys;
+    uint32_t* sids;
+    uint16_t* sb;
+    uint32_t *cur, *tcnt, *wcnt, *dstart, *tmp;
+    __device__ HeavyLds(unsigned char* smem, uint32_t NB) {
+        skeys = (Key*)smem;
+        sids = (uint32_t*)(skeys + kHeavyChunk);
+        sb = (uint16_t*)(sids + kHeavyChunk);
+        cur = (uint32_t*)(sb + kHeavyChunk);  // NB: running cursors
+        tcnt = cur + NB;                      // NB: chunk-local bucket starts
+        wcnt = tcnt + NB;
+        dstart = wcnt + W_LOCAL * 64;
+        tmp = dstart + 64;
+    }
+};
+
+// Place L entries (arriving in id order) of one bin, chunk by chunk, in
+// order: each chunk is sorted by bucket in LDS and written at the running
+// per-bucket cursors cur[0 .. 2^k), which hold absolute edge positions on
+// entry and are advanced past the placed entries on return.  Writes outside
+// [lo, hi) are dropped (they cannot happen for consistent counts).  Uses the
+// heavy_smem layout; whole workgroup.
+template <typename Key>
+__device__ __forceinline__ void place_in_chunks(const Key* __restrict__ src_keys,
+                                                const uint32_t* __restrict__ src_ids,
+                                                uint32_t id_base, uint32_t L, uint32_t lo,
+                                                uint32_t hi, uint32_t v0, uint32_t k,
+                                                const typename KeyTraits<Key>::Params& hp,
+                                                uint32_t* __restrict__ ids,
+                                                Key* __restrict__ ekeys, unsigned char* smem) {
     constexpr int IT = kHeavyItems;
     constexpr uint32_t CAP = kHeavyChunk;
     const uint32_t NB = 1u << k;
-    Key* skeys = (Key*)smem;
-    uint32_t* sids = (uint32_t*)(skeys + CAP);
-    uint16_t* sb = (uint16_t*)(sids + CAP);
-    uint32_t* cur = (uint32_t*)(sb + CAP);  // NB: running cursors
-    uint32_t* tcnt = cur + NB;              // NB: chunk-local bucket starts
-    uint32_t* wcnt = tcnt + NB;
-    uint32_t* dstart = wcnt + W_LOCAL * 64;
-    uint32_t* tmp = dstart + 64;
+    const HeavyLds<Key> m(smem, NB);
+    Key* skeys = m.skeys;
+    uint32_t* sids = m.sids;
+    uint16_t* sb = m.sb;
+    uint32_t *cur = m.cur, *tcnt = m.tcnt, *wcnt = m.wcnt, *dstart = m.dstart, *tmp = m.tmp;
     const uint32_t w = threadIdx.x / kWave, lane = lane_id();
-
-    for (uint32_t i = threadIdx.x; i < NB; i += kLocalThreads) cur[i] = 0;
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < L; i += kLocalThreads)
-        atomicAdd(&cur[KeyTraits<Key>::bucket(src_keys[i], hp) - v0], 1u);
-    __syncthreads();
-    scan_counts(cur, NB, out, tmp);
-    for (uint32_t i = threadIdx.x; i < nb; i += kLocalThreads) offsets[v0 + i] = cur[i];
     const uint32_t nchunk = (uint32_t)(((uint64_t)L + CAP - 1) / CAP);
     for (uint32_t ci = 0; ci < nchunk; ++ci) {
         const uint32_t c0 = ci * CAP;
@@ -438,11 +447,10 @@ __device__ __forceinline__ void heavy_bin_body(const Key* __restrict__ src_keys,
         __syncthreads();
         // chunk-local bucket starts (exclusive scan of tcnt)
         scan_counts(tcnt, NB, 0u, tmp);
-        const uint32_t hi_out = out + L;
         for (uint32_t p = threadIdx.x; p < cl; p += kLocalThreads) {
             const uint32_t bb = sb[p];
             const uint32_t o = cur[bb] + (p - tcnt[bb]);
-            if (o - out < hi_out - out) {
+            if (o - lo < hi - lo) {
                 ekeys[o] = skeys[p];
                 ids[o] = sids[p];
             }
@@ -454,6 +462,34 @@ __device__ __forceinline__ void heavy_bin_body(const Key* __restrict__ src_keys,
         }
         __syncthreads();
     }
+}
+
+// The same for a bin of any size (arriving in id order) in one workgroup:
+// keys counted per bucket first, then placed with place_in_chunks, so
+// placement stays stable.
+template <typename Key>
+__device__ __forceinline__ void heavy_bin_body(const Key* __restrict__ src_keys,
+                                               const uint32_t* __restrict__ src_ids,
+                                               uint32_t id_base, uint32_t L, uint32_t out,
+                                               uint32_t v0, uint32_t k, uint32_t nb,
+                                               const typename KeyTraits<Key>::Params& hp,
+                                               uint32_t* __restrict__ offsets,
+                                               const IndexOut& ix,
+                                               uint32_t* __restrict__ ids, Key* __restrict__ ekeys,
+                                               unsigned char* smem) {
+    const uint32_t NB = 1u << k;
+    const HeavyLds<Key> m(smem, NB);
+    uint32_t *cur = m.cur, *tmp = m.tmp;
+
+    for (uint32_t i = threadIdx.x; i < NB; i += kLocalThreads) cur[i] = 0;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < L; i += kLocalThreads)
+        atomicAdd(&cur[KeyTraits<Key>::bucket(src_keys[i], hp) - v0], 1u);
+    __syncthreads();
+    scan_counts(cur, NB, out, tmp);
+    for (uint32_t i = threadIdx.x; i < nb; i += kLocalThreads) offsets[v0 + i] = cur[i];
+    place_in_chunks<Key>(src_keys, src_ids, id_base, L, out, out + L, v0, k, hp, ids, ekeys,
+                         smem);
     // cur[v] is now the end of bucket v; the bin's edges are in ekeys
     if (ix.head)
         for (uint32_t v = threadIdx.x; v < nb; v += kLocalThreads) {

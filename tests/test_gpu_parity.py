@@ -108,6 +108,10 @@ BUILD_CASES = [
     ("uniform", 300000, 1 << 30),
     ("uniform", 200000, 1),
     ("uniform", 200000, 3),
+    # bins above 2^17 keys are split over several workgroups
+    ("equal", 600000, 1000),
+    ("uniform", (1 << 19) + 3, 2),
+    ("zipf", 1 << 20, 1 << 20),
     ("dup8", 500000, 250000),
     ("zipf", 400000, 400000),
     ("equal", 70000, 4096),
@@ -217,6 +221,7 @@ def test_probe_pairs_match_oracle_in_canonical_order(hg, kb):
 @pytest.mark.parametrize("kb", [32, 64])
 @pytest.mark.parametrize("kind,n,V", [("uniform", 300007, 300007), ("uniform", 120000, 1 << 20),
                                       ("dup8", 200000, 50000), ("equal", 20000, 97),
+                                      ("equal", 400000, 97), ("uniform", 300000, 1),
                                       ("zipf", 150000, 150000)])
 def test_probe_index_on_and_off_agree_with_oracle(hg, kb, kind, n, V):
     # the per-bucket index holds each bucket's bounds and first keys; buckets
