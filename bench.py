@@ -300,6 +300,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--tables", type=int, default=4096)
     ap.add_argument("--requests", type=int, default=600)
+    ap.add_argument("--stable", action="store_true",
+                    help="time the stable (ids ascending in each bucket) V2 layout")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device-to-device (reference for HBM counters)")
     args = ap.parse_args()
@@ -336,7 +338,7 @@ def main():
     torch.cuda.synchronize()
 
     def step():
-        table.rebuild(dk, V, seed=0, variant=hg.VARIANT_V2)
+        table.rebuild(dk, V, seed=0, variant=hg.VARIANT_V2, any_order=not args.stable)
         hg.hg_probe(table, dq, counts=True, total=False, out=counts)
 
     log("warmup %d" % args.warmup)
@@ -417,6 +419,8 @@ def main():
             Vs = 1 << lv
             t_v2 = timed(lambda: big.rebuild(dk, Vs, 0, variant=hg.VARIANT_V2), reps, torch)
             t_pr = timed(lambda: hg.hg_probe(big, dq, counts=True, out=counts), reps, torch)
+            t_v2a = timed(lambda: big.rebuild(dk, Vs, 0, variant=hg.VARIANT_V2, any_order=True),
+                          reps, torch)
             t_v2x = timed(lambda: big.rebuild(dk, Vs, 0, variant=hg.VARIANT_V2, index=False),
                           reps, torch)
             t_prx = timed(lambda: hg.hg_probe(big, dq, counts=True, out=counts), reps, torch)
@@ -425,14 +429,16 @@ def main():
             ex["V=2^%d" % lv] = {"build_v2_ms": round(t_v2, 3),
                                  "build_v2_Gkeys": round(n / t_v2 / 1e6, 2),
                                  "build_v2_noindex_ms": round(t_v2x, 3),
+                                 "build_v2_any_order_ms": round(t_v2a, 3),
                                  "build_v1_ms": round(t_v1, 3),
                                  "build_v1_Gkeys": round(n / t_v1 / 1e6, 2),
                                  "probe_ms": round(t_pr, 3),
                                  "probe_Gkeys": round(m / t_pr / 1e6, 2),
                                  "probe_noindex_ms": round(t_prx, 3),
                                  "probe_v1table_ms": round(t_pr1, 3)}
-            log("V=2^%d v2 %.3f (no index %.3f) ms v1 %.3f ms probe %.3f (no index %.3f, "
-                "v1 table %.3f) ms" % (lv, t_v2, t_v2x, t_v1, t_pr, t_prx, t_pr1))
+            log("V=2^%d v2 %.3f (any order %.3f, no index %.3f) ms v1 %.3f ms probe %.3f "
+                "(no index %.3f, v1 table %.3f) ms" % (lv, t_v2, t_v2a, t_v2x, t_v1, t_pr, t_prx,
+                                                       t_pr1))
         big.free()
         del big
         # Probe-New (Alg. 3): build the query table, then intersect (counts)
@@ -508,9 +514,14 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": "single table: V2 build of 2^%d uniform uint32 keys, hash_range "
-                               "2^%d, then Probe-Standard counts of 2^%d queries (50%% drawn "
-                               "from the keys)" % (args.log2n, args.log2range, args.log2n),
-                   "n": n, "hash_range": V, "m": m, "key_bits": 32},
+                               "2^%d (%s), with the per-bucket probe index, then "
+                               "Probe-Standard counts of 2^%d queries (50%% drawn from the "
+                               "keys)" % (args.log2n, args.log2range,
+                                          "stable layout" if args.stable else
+                                          "order inside a bucket unspecified, as in the paper",
+                                          args.log2n),
+                   "n": n, "hash_range": V, "m": m, "key_bits": 32,
+                   "bucket_order": "stable" if args.stable else "any"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "phases": phases,

@@ -57,10 +57,10 @@ typedef enum hg_status {
 
 typedef struct hg_build_opts {
     int32_t variant;   /* HG_VARIANT_*                                          */
-    int32_t stable;    /* 1: ids ascending inside every bucket.  V2 always
-                          places stably; V1 places by atomics (order inside a
-                          bucket unspecified) and rejects stable=1 with
-                          HG_ERR_INVALID_ARG.                                   */
+    int32_t stable;    /* 1: ids ascending inside every bucket.  V2 places
+                          stably unless any_order is set; V1 places by atomics
+                          (order inside a bucket unspecified) and rejects
+                          stable=1 with HG_ERR_INVALID_ARG.                     */
     uint32_t bins;     /* V2: number of bins (Alg. 2 "Bins"), rounded so that
                           a bin spans a power-of-two range of buckets; 0 =
                           choose from N and V.                                 */
@@ -79,7 +79,13 @@ typedef struct hg_build_opts {
                           such buckets.  1 = skip the index (probes then read
                           offsets and scan the edge array).  Results are
                           identical either way.  V1 never writes it.         */
-    uint32_t reserved[3];
+    int32_t any_order; /* V2: 1 = the order of ids inside a bucket is
+                          unspecified (as in the paper), which lets the
+                          partition passes rank without ballots and skips the
+                          per-bucket id ordering; offsets, bucket contents as
+                          multisets and probe counts are unchanged.  Rejected
+                          with stable=1.  0 = stable layout (default).        */
+    uint32_t reserved[2];
 } hg_build_opts;
 
 typedef struct hg_table hg_table; /* opaque; device-resident */

@@ -138,6 +138,8 @@ hg_status build_into(hg_table* t, const void* keys, uint64_t n, uint64_t V, uint
     const uint32_t bins = opts ? opts->bins : 0;
     const uint32_t block = opts ? opts->block : 0;
     const bool want_head = variant == HG_VARIANT_V2 && !(opts && opts->no_index);
+    const bool any_order = opts && opts->any_order;
+    if (any_order && stable) return HG_ERR_INVALID_ARG;
     if (block && (block % 64 || block > 1024)) return HG_ERR_INVALID_ARG;
     if (bins && bins > V) return HG_ERR_INVALID_ARG;
 
@@ -161,13 +163,13 @@ hg_status build_into(hg_table* t, const void* keys, uint64_t n, uint64_t V, uint
                 ? run_build_v1<uint32_t>((const uint32_t*)keys, n, V, seed, t->offsets, t->ids,
                                          (uint32_t*)t->keys, ws, block, s)
                 : run_build_v2<uint32_t>((const uint32_t*)keys, n, V, seed, t->offsets, t->ids,
-                                         (uint32_t*)t->keys, ix, ws, bins, s);
+                                         (uint32_t*)t->keys, ix, ws, bins, !any_order, s);
     } else {
         e = variant == HG_VARIANT_V1
                 ? run_build_v1<uint64_t>((const uint64_t*)keys, n, V, seed, t->offsets, t->ids,
                                          (uint64_t*)t->keys, ws, block, s)
                 : run_build_v2<uint64_t>((const uint64_t*)keys, n, V, seed, t->offsets, t->ids,
-                                         (uint64_t*)t->keys, ix, ws, bins, s);
+                                         (uint64_t*)t->keys, ix, ws, bins, !any_order, s);
     }
     if (e != hipSuccess) return from_hip(e);
     t->n = n;

@@ -146,11 +146,12 @@ hipError_t run_key_runs(const uint32_t* offsets, const uint32_t* ids, const Key*
                         const RunsDev& r, void* ws, hipStream_t s);
 
 // ix.head (may be null): V 16-byte probe index entries, one per bucket; long
-// buckets are listed as IndexOut describes.
+// buckets are listed as IndexOut describes.  stable: ids ascend inside every
+// bucket (otherwise their order there is unspecified).
 template <typename Key>
 hipError_t run_build_v2(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, uint32_t* offsets,
                         uint32_t* ids, Key* ekeys, const IndexOut& ix, void* ws,
-                        uint32_t bins_hint, hipStream_t s);
+                        uint32_t bins_hint, bool stable, hipStream_t s);
 
 // ---- probing ---------------------------------------------------------------
 struct TableDev {

@@ -203,7 +203,9 @@ __global__ __launch_bounds__(256) void k_colscan_down(uint32_t* __restrict__ mat
 // Stable partition of one tile by a digit of the bucket index.  Writes every
 // entry to base(tile, digit) + its rank among the tile's entries of that
 // digit.
-template <typename Key, bool HAS_IDS>
+// STABLE: entries of equal digit keep their order (rank_stable); otherwise
+// their order inside a run is unspecified (rank_any, no ballots).
+template <typename Key, bool HAS_IDS, bool STABLE>
 __global__ __launch_bounds__(kPartThreads) void k_tile_partition(
     const Key* __restrict__ src_keys, const uint32_t* __restrict__ src_ids,
     Key* __restrict__ dst_keys, uint32_t* __restrict__ dst_ids, Segs g,
@@ -246,7 +248,8 @@ __global__ __launch_bounds__(kPartThreads) void k_tile_partition(
         const uint32_t e = wbase + r * kWave + lane;
         dig[r] = (e < cnt) ? ((KeyTraits<Key>::bucket(k[r], hp) >> shift) & mask) : D;
     }
-    rank_stable<kPartThreads, IT>(dig, bits, wcnt, dstart, tmp, pos);
+    if (STABLE) rank_stable<kPartThreads, IT>(dig, bits, wcnt, dstart, tmp, pos);
+    else rank_any<kPartThreads, IT>(dig, bits, wcnt, dstart, tmp, pos);
     const uint32_t* row = base + (size_t)t * D;
     for (uint32_t d = threadIdx.x; d < D; d += kPartThreads) tbase[d] = row[d] - dstart[d];
 #pragma unroll
@@ -523,7 +526,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_local_light(
     const Key* __restrict__ src_keys, const uint32_t* __restrict__ src_ids,
     const uint32_t* __restrict__ bin_start, typename KeyTraits<Key>::Params hp, uint32_t k,
     uint32_t* __restrict__ offsets, IndexOut ix, uint32_t* __restrict__ ids,
-    Key* __restrict__ ekeys) {
+    Key* __restrict__ ekeys, bool any_order) {
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t g = blockIdx.x;
     const uint32_t start = bin_start[g], end = bin_start[g + 1];
@@ -532,7 +535,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_local_light(
     const uint32_t NB = 1u << k, v0 = g << k, V = hp.range;
     const uint32_t nb = (V - v0 < NB) ? V - v0 : NB;
     light_bin_body<Key>(src_keys + start, src_ids + start, 0u, L, start, v0, k, nb, hp, offsets,
-                        ix, ids, ekeys, smem);
+                        ix, ids, ekeys, smem, any_order);
 }
 
 // Oversize bins (from the device list), one workgroup per bin.
@@ -673,11 +676,22 @@ hipError_t colscan(uint32_t* mat, const Segs& g, uint32_t D, uint32_t* csum, uin
     return hipGetLastError();
 }
 
+template <typename Key, bool HAS_IDS, bool STABLE>
+void launch_partition(dim3 grid, size_t smem, hipStream_t s, const Key* src_keys,
+                      const uint32_t* src_ids, Key* dst_keys, uint32_t* dst_ids, const Segs& g,
+                      typename KeyTraits<Key>::Params hp, uint32_t shift, uint32_t bits,
+                      const uint32_t* mat, uint32_t tiles_ub) {
+    hipLaunchKernelGGL((k_tile_partition<Key, HAS_IDS, STABLE>), grid, dim3(kPartThreads), smem,
+                       s, src_keys, src_ids, dst_keys, dst_ids, g, hp, shift, bits, mat,
+                       tiles_ub);
+}
+
 template <typename Key>
 hipError_t partition_pass(const Key* src_keys, const uint32_t* src_ids, Key* dst_keys,
                           uint32_t* dst_ids, const Segs& g, typename KeyTraits<Key>::Params hp,
                           uint32_t shift, uint32_t bits, uint32_t* mat, uint32_t* csum,
-                          uint32_t tiles_ub, uint32_t nchunks_ub, int tier, hipStream_t s) {
+                          uint32_t tiles_ub, uint32_t nchunks_ub, int tier, bool stable,
+                          hipStream_t s) {
     const uint32_t D = 1u << bits;
     const uint32_t grid = (uint32_t)(8 * ceil_div(tiles_ub, 8));
     {
@@ -690,14 +704,19 @@ hipError_t partition_pass(const Key* src_keys, const uint32_t* src_ids, Key* dst
     const size_t smem = partition_smem<Key>(bits);
     {
         HG_PROF(tier == 1 ? "v2_partition_t1" : "v2_partition_t2", s);
-        if (src_ids)
-            hipLaunchKernelGGL((k_tile_partition<Key, true>), dim3(grid), dim3(kPartThreads), smem,
-                               s, src_keys, src_ids, dst_keys, dst_ids, g, hp, shift, bits, mat,
-                               tiles_ub);
+        const dim3 gr(grid);
+        if (src_ids && stable)
+            launch_partition<Key, true, true>(gr, smem, s, src_keys, src_ids, dst_keys, dst_ids,
+                                              g, hp, shift, bits, mat, tiles_ub);
+        else if (src_ids)
+            launch_partition<Key, true, false>(gr, smem, s, src_keys, src_ids, dst_keys, dst_ids,
+                                               g, hp, shift, bits, mat, tiles_ub);
+        else if (stable)
+            launch_partition<Key, false, true>(gr, smem, s, src_keys, src_ids, dst_keys, dst_ids,
+                                               g, hp, shift, bits, mat, tiles_ub);
         else
-            hipLaunchKernelGGL((k_tile_partition<Key, false>), dim3(grid), dim3(kPartThreads), smem,
-                               s, src_keys, src_ids, dst_keys, dst_ids, g, hp, shift, bits, mat,
-                               tiles_ub);
+            launch_partition<Key, false, false>(gr, smem, s, src_keys, src_ids, dst_keys,
+                                                dst_ids, g, hp, shift, bits, mat, tiles_ub);
     }
     return hipGetLastError();
 }
@@ -707,9 +726,13 @@ hipError_t set_smem_limits() {
     static bool done = false;
     if (done) return hipSuccess;
     const int lim = 160 * 1024;
-    HG_TRY(hipFuncSetAttribute((const void*)k_tile_partition<Key, true>,
+    HG_TRY(hipFuncSetAttribute((const void*)k_tile_partition<Key, true, true>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, lim));
-    HG_TRY(hipFuncSetAttribute((const void*)k_tile_partition<Key, false>,
+    HG_TRY(hipFuncSetAttribute((const void*)k_tile_partition<Key, false, true>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+    HG_TRY(hipFuncSetAttribute((const void*)k_tile_partition<Key, true, false>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+    HG_TRY(hipFuncSetAttribute((const void*)k_tile_partition<Key, false, false>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, lim));
     HG_TRY(hipFuncSetAttribute((const void*)k_local_light<Key>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, lim));
@@ -737,7 +760,7 @@ size_t build_ws_bytes(int variant, uint64_t n, uint64_t V, int key_bits, uint32_
 template <typename Key>
 hipError_t run_build_v2(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, uint32_t* offsets,
                         uint32_t* ids, Key* ekeys, const IndexOut& ix, void* ws,
-                        uint32_t bins_hint, hipStream_t s) {
+                        uint32_t bins_hint, bool stable, hipStream_t s) {
     HG_TRY(set_smem_limits<Key>());
     if (ix.head) HG_TRY(fill_u32(ix.long_stat, 2, 0u, s));
     if (n == 0) {
@@ -760,14 +783,14 @@ hipError_t run_build_v2(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, 
     uint32_t bin_bits;
     if (p.tiers == 1) {
         HG_TRY(partition_pass<Key>(keys, nullptr, rkeys, w.rids, w.s1, hp, p.k, p.b1, w.m1, w.c1,
-                                   p.ntiles1, p.nchunks1, 1, s));
+                                   p.ntiles1, p.nchunks1, 1, stable, s));
         bin_mat = w.m1;
         bin_segs = w.s1;
         bin_bits = p.b1;
     } else {
         // tier 1 into the table's own arrays, tier 2 into the workspace
         HG_TRY(partition_pass<Key>(keys, nullptr, ekeys, ids, w.s1, hp, p.k + p.b2, p.b1, w.m1,
-                                   w.c1, p.ntiles1, p.nchunks1, 1, s));
+                                   w.c1, p.ntiles1, p.nchunks1, 1, stable, s));
         {
             HG_PROF("v2_segs", s);
             hipLaunchKernelGGL(k_segs_from_bases, dim3(1), dim3(1024), 0, s,
@@ -775,7 +798,7 @@ hipError_t run_build_v2(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, 
         }
         HG_TRY(hipGetLastError());
         HG_TRY(partition_pass<Key>(ekeys, ids, rkeys, w.rids, w.s2, hp, p.k, p.b2, w.m2, w.c2,
-                                   p.ntiles2_ub, p.nchunks2_ub, 2, s));
+                                   p.ntiles2_ub, p.nchunks2_ub, 2, stable, s));
         bin_mat = w.m2;
         bin_segs = w.s2;
         bin_bits = p.b2;
@@ -792,7 +815,8 @@ hipError_t run_build_v2(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, 
         HG_PROF("v2_local_build", s);
         hipLaunchKernelGGL(k_local_light<Key>, dim3(p.bins), dim3(kLocalThreads),
                            light_smem<Key>(p.k), s, (const Key*)rkeys, (const uint32_t*)w.rids,
-                           (const uint32_t*)w.bin_start, hp, p.k, offsets, ix, ids, ekeys);
+                           (const uint32_t*)w.bin_start, hp, p.k, offsets, ix, ids, ekeys,
+                           !stable);
     }
     HG_TRY(hipGetLastError());
     {
@@ -837,9 +861,9 @@ hipError_t run_build_v2(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, 
 
 template hipError_t run_build_v2<uint32_t>(const uint32_t*, uint64_t, uint64_t, uint64_t,
                                            uint32_t*, uint32_t*, uint32_t*, const IndexOut&,
-                                           void*, uint32_t, hipStream_t);
+                                           void*, uint32_t, bool, hipStream_t);
 template hipError_t run_build_v2<uint64_t>(const uint64_t*, uint64_t, uint64_t, uint64_t,
                                            uint32_t*, uint32_t*, uint64_t*, const IndexOut&,
-                                           void*, uint32_t, hipStream_t);
+                                           void*, uint32_t, bool, hipStream_t);
 
 }  // namespace hg

@@ -86,6 +86,40 @@ __device__ __forceinline__ void rank_stable(const uint32_t (&dig)[ITEMS], uint32
     for (int r = 0; r < ITEMS; ++r) pos[r] += my[dig[r] & mask];
 }
 
+// Rank of up to THREADS*ITEMS items by a digit of `bits` bits with no order
+// among equal digits: one returning LDS atomic per item on per-workgroup
+// counters, then an exclusive scan of the counts.  pos[r] is the item's index
+// in the tile grouped by digit (undefined for items with dig >= D);
+// dstart[d] the start of digit d.  `cnt` holds D counters.  Contains
+// barriers.
+template <int THREADS, int ITEMS>
+__device__ __forceinline__ void rank_any(const uint32_t (&dig)[ITEMS], uint32_t bits,
+                                         uint32_t* cnt, uint32_t* dstart, uint32_t* tmp,
+                                         uint32_t (&pos)[ITEMS]) {
+    const uint32_t D = 1u << bits, mask = D - 1;
+    for (uint32_t i = threadIdx.x; i < D; i += THREADS) cnt[i] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r)
+        if (dig[r] < D) pos[r] = atomicAdd(&cnt[dig[r]], 1u);
+    __syncthreads();
+    const uint32_t per = (D + THREADS - 1) / THREADS;
+    const uint32_t d0 = threadIdx.x * per;
+    uint32_t mine = 0;
+    for (uint32_t j = 0; j < per; ++j)
+        if (d0 + j < D) mine += cnt[d0 + j];
+    uint32_t all;
+    uint32_t run = block_excl_scan<THREADS>(mine, tmp, &all);
+    for (uint32_t j = 0; j < per; ++j)
+        if (d0 + j < D) {
+            dstart[d0 + j] = run;
+            run += cnt[d0 + j];
+        }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) pos[r] += dstart[dig[r] & mask];
+}
+
 // -------------------------------------------------- per-bin LDS build -----
 
 // Place one chunk of <= ITEMS*64*W entries held in registers: two stable LSD
@@ -263,7 +297,8 @@ __device__ __forceinline__ void put_index(const IndexOut& ix, uint32_t b, uint32
 // bucket, and offsets[v0 + v] = out + (start of bucket v in the bin).
 // Usual case (every bucket of the bin holds at most kFixMax keys): LDS
 // counting sort with atomic cursors, then an insertion sort by id inside each
-// bucket.  Otherwise the bin (in id order) is stably ranked by local bucket.
+// bucket (skipped with any_order: order inside a bucket is then unspecified).
+// Otherwise the bin (in id order) is stably ranked by local bucket.
 // When ix.head is not null it also receives each bucket's probe index entry.
 // Called by a whole workgroup of kLocalThreads threads.
 template <typename Key>
@@ -275,7 +310,7 @@ __device__ __forceinline__ void light_bin_body(const Key* __restrict__ src_keys,
                                                uint32_t* __restrict__ offsets,
                                                const IndexOut& ix,
                                                uint32_t* __restrict__ ids, Key* __restrict__ ekeys,
-                                               unsigned char* smem) {
+                                               unsigned char* smem, bool any_order = false) {
     constexpr int IT = kLightItems;
     const uint32_t NB = 1u << k;
     Key* skeys = (Key*)smem;
@@ -329,8 +364,9 @@ __device__ __forceinline__ void light_bin_body(const Key* __restrict__ src_keys,
             }
         }
         __syncthreads();
-        // cnt[v] is now the end of bucket v
-        for (uint32_t v = threadIdx.x; v < NB; v += kLocalThreads) {
+        // cnt[v] is now the end of bucket v; ids are put back in ascending
+        // order inside each (short) bucket unless any order is allowed
+        for (uint32_t v = threadIdx.x; v < NB && !any_order; v += kLocalThreads) {
             const uint32_t lo = v ? cnt[v - 1] : 0u, hi = cnt[v];
             for (uint32_t i = lo + 1; i < hi; ++i) {
                 const uint32_t idv = sids[i];

@@ -34,7 +34,8 @@ class HGError(RuntimeError):
 class BuildOpts(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("stable", ctypes.c_int32),
                 ("bins", ctypes.c_uint32), ("block", ctypes.c_uint32),
-                ("no_index", ctypes.c_int32), ("reserved", ctypes.c_uint32 * 3)]
+                ("no_index", ctypes.c_int32), ("any_order", ctypes.c_int32),
+                ("reserved", ctypes.c_uint32 * 2)]
 
 
 class TableInfo(ctypes.Structure):
@@ -164,10 +165,11 @@ def hg_exclusive_scan(counts: torch.Tensor, out=None, stream=None):
 
 # ----------------------------------------------------------------- tables ---
 
-def _opts(variant=VARIANT_AUTO, stable=0, bins=0, block=0, index=True):
+def _opts(variant=VARIANT_AUTO, stable=0, bins=0, block=0, index=True, any_order=False):
     o = BuildOpts()
     o.variant, o.stable, o.bins, o.block = int(variant), int(stable), int(bins), int(block)
     o.no_index = 0 if index else 1
+    o.any_order = 1 if any_order else 0
     return o
 
 
@@ -186,9 +188,9 @@ class Table:
         return cls(h, torch.device(device))
 
     def rebuild(self, keys: torch.Tensor, hash_range: int, seed: int = 0, variant=VARIANT_AUTO,
-                stable=0, bins=0, block=0, index=True, stream=None):
+                stable=0, bins=0, block=0, index=True, any_order=False, stream=None):
         keys = _dev_keys(keys)
-        o = _opts(variant, stable, bins, block, index)
+        o = _opts(variant, stable, bins, block, index, any_order)
         _check(lib().hg_table_build(self._h, _ptr(keys), keys.numel(), int(hash_range),
                                     int(seed) & (2**64 - 1), ctypes.byref(o), _stream(stream)),
                "hg_table_build")
@@ -227,9 +229,9 @@ class Table:
 
 
 def hg_build(keys: torch.Tensor, hash_range: int, seed: int = 0, variant=VARIANT_AUTO, stable=0,
-             bins=0, block=0, index=True, stream=None) -> Table:
+             bins=0, block=0, index=True, any_order=False, stream=None) -> Table:
     keys = _dev_keys(keys)
-    o = _opts(variant, stable, bins, block, index)
+    o = _opts(variant, stable, bins, block, index, any_order)
     h = ctypes.c_void_p()
     _check(lib().hg_build(_ptr(keys), keys.numel(), _key_bits(keys), int(hash_range),
                           int(seed) & (2**64 - 1), ctypes.byref(o), _stream(stream),

@@ -148,7 +148,7 @@ def check_v1(off, ids, ek, k, V, seed, kb):
     o_off, o_ids, _ = oracle.build_table(k, V, seed, kb)
     assert np.array_equal(off, o_off)
     # bucket contents as multisets: sort ids inside each bucket
-    seg = np.repeat(np.arange(V, dtype=np.int64), np.diff(off.astype(np.int64)))
+    seg = np.searchsorted(off.astype(np.int64), np.arange(ids.size), side="right") - 1
     order = np.lexsort((ids, seg))
     assert np.array_equal(ids[order], o_ids)
     assert np.array_equal(ek, k[ids])
@@ -164,6 +164,30 @@ def test_build_v1_matches_oracle_as_multisets(hg, kb, kind, n, V):
     t = hg.hg_build(hg.to_device(k), V, seed=99, variant=hg.VARIANT_V1)
     off, ids, ek = table_np(hg, t, kb)
     check_v1(off, ids, ek, k, V, 99, kb)
+
+
+@pytest.mark.parametrize("kb", [32, 64])
+@pytest.mark.parametrize("kind,n,V", BUILD_CASES)
+def test_build_v2_any_order_matches_oracle_as_multisets(hg, kb, kind, n, V):
+    # any_order: offsets exact, buckets as multisets, probes exact
+    say("build-v2-any", kb, kind, n, V)
+    k = keys_for(kind, n, kb, seed=n % 89)
+    t = hg.hg_build(hg.to_device(k), V, seed=777, any_order=True)
+    off, ids, ek = table_np(hg, t, kb)
+    check_v1(off, ids, ek, k, V, 777, kb)
+    q = workloads.probe_queries(k if n else workloads.uniform_keys(8, kb, 0), 50000, 0.5,
+                                seed=3, key_bits=kb)
+    c, tot = hg.hg_probe(t, hg.to_device(q), counts=True, total=True)
+    exp, etot = oracle.probe_counts(k, q, kb)
+    assert np.array_equal(hg.to_numpy(c, np.uint32), exp) and tot == etot
+    t.free()
+
+
+def test_any_order_rejects_stable(hg):
+    k = hg.to_device(workloads.uniform_keys(100, 32, 1))
+    with pytest.raises(hg.HGError) as e:
+        hg.hg_build(k, 10, any_order=True, stable=1)
+    assert e.value.status == hg.HG_ERR_INVALID_ARG
 
 
 def test_table_rebuild_reuses_capacity(hg):
