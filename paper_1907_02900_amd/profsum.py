@@ -28,8 +28,8 @@ RANGES = [
     ("k_probe_count", "probe_count"),
     ("k_local_light", "v2_local_build"),
     ("k_local_heavy", "v2_local_heavy"),
-    ("k_tile_partition<unsigned int, false>", "v2_partition_t1"),
-    ("k_tile_partition<unsigned int, true>", "v2_partition_t2"),
+    ("k_tile_partition<unsigned int, false", "v2_partition_t1"),
+    ("k_tile_partition<unsigned int, true", "v2_partition_t2"),
     ("k_tile_hist", "v2_tile_hist"),
     ("k_hist_global", "v1_hist_global"),
     ("k_scatter_v1", "v1_scatter"),
