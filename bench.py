@@ -119,7 +119,7 @@ def load_traffic(kernel, digest):
     return e.get("hbm_bytes_per_launch")
 
 
-def run_batched(hg, workloads, torch, tables=4096, reps=5, log=print):
+def run_batched(hg, workloads, torch, tables=4096, reps=5, log=print, any_order=True):
     """4096 tables, sizes floor(2^U), U ~ U[8, 20], V = n, m = n queries with
     50% hits: one graph launch per run vs a per-table loop of hg_table_build
     + hg_probe into preallocated tables."""
@@ -132,7 +132,8 @@ def run_batched(hg, workloads, torch, tables=4096, reps=5, log=print):
     tot = int(sizes.sum()) * 2
     t0 = time.perf_counter()
     b = hg.Batch([{"keys": keys[i], "queries": qs[i], "hash_range": int(sizes[i]),
-                   "seed": i} for i in range(tables)], key_bits=32, autotune=True)
+                   "seed": i} for i in range(tables)], key_bits=32, autotune=True,
+                 any_order=any_order)
     torch.cuda.synchronize()
     create_s = time.perf_counter() - t0
     t_graph = timed(b.run, reps, torch)
@@ -143,7 +144,8 @@ def run_batched(hg, workloads, torch, tables=4096, reps=5, log=print):
     def loop():
         # the same work as the graph: V2 tables without the probe index
         for i in range(tables):
-            loop_tabs[i].rebuild(keys[i], int(sizes[i]), seed=i, index=False)
+            loop_tabs[i].rebuild(keys[i], int(sizes[i]), seed=i, index=False,
+                                 any_order=any_order)
             hg.hg_probe(loop_tabs[i], qs[i], counts=True, out=outs[i])
 
     t_loop = timed(loop, 2, torch)
@@ -376,6 +378,7 @@ def main():
     blen = offl[h + 1] - offl[h]
     sum_len = int(blen.sum().item())
     sum_tail = int((blen - 2).clamp_(min=0).sum().item())
+    n_tail = int((blen > 2).sum().item())  # queries that also read the edge array
     del h, offl, off, blen
 
     plan = v2_plan_bytes(n, V)
@@ -401,6 +404,13 @@ def main():
                 # HBM bytes the counters saw per launch, over the same launch time
                 "traffic_GBps": (round(traffic / (dk_["avg_ms"] / 1000.0) / 1e9, 1)
                                  if traffic else None)}
+    if dom == "probe_count":
+        # a random read costs one 128-byte line of HBM traffic: the index
+        # entry of every query, plus the edge array for long buckets
+        lines = m + n_tail
+        roofline["random_lines_per_launch"] = lines
+        roofline["line_bytes"] = 128
+        roofline["line_GBps"] = round(lines * 128 / (dk_["avg_ms"] / 1000.0) / 1e9, 1)
 
     phases = {"kernels": kernels, "source_digest": digest,
               "probe_sum_bucket_len": sum_len, "probe_sum_keys_past_index": sum_tail}
@@ -490,7 +500,8 @@ def main():
 
     if not args.no_batched:
         log("batched")
-        phases["batched"] = run_batched(hg, workloads, torch, tables=args.tables, log=log)
+        phases["batched"] = run_batched(hg, workloads, torch, tables=args.tables, log=log,
+                                        any_order=not args.stable)
     if not args.no_serving:
         log("serving")
         phases["serving"] = run_serving(hg, workloads, torch, requests=args.requests, log=log)

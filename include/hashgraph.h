@@ -74,9 +74,11 @@ typedef struct hg_build_opts {
                           each with its count and its ids grouped), so probes
                           and intersections of skewed tables cost a binary
                           search instead of a scan; building it waits for the
-                          build and, for tables made by hg_table_create,
-                          allocates the summary the first time a build has
-                          such buckets.  1 = skip the index (probes then read
+                          build.  The index (16 bytes per bucket of the
+                          table's range capacity) is allocated by the first
+                          build that writes it, the summary the first time a
+                          build has such buckets, also for tables made by
+                          hg_table_create.  1 = skip the index (probes then read
                           offsets and scan the edge array).  Results are
                           identical either way.  V1 never writes it.         */
     int32_t any_order; /* V2: 1 = the order of ids inside a bucket is
@@ -148,8 +150,10 @@ hg_status hg_build(const void *d_keys, uint64_t n, int key_bits, uint64_t hash_r
                    hg_table **out);
 
 /* Allocate an empty table able to hold up to n_capacity keys and
- * range_capacity buckets, including the workspace a V2 build needs, so that
- * later hg_table_build calls allocate nothing. */
+ * range_capacity buckets, including the workspace a V2 build needs.  Later
+ * hg_table_build calls allocate nothing, except the probe index on the first
+ * build that writes it and the key-run summary of long buckets (see
+ * hg_build_opts.no_index); a build with no_index = 1 never allocates. */
 hg_status hg_table_create(uint64_t n_capacity, uint64_t range_capacity, int key_bits,
                           hg_table **out);
 
@@ -234,7 +238,9 @@ typedef struct hg_batch_opts {
                             bin_target or 2048 keys per bin                     */
     uint32_t bin_target; /* keys per final bin of the partitioned tables; 0 =
                             autotune / default                                  */
-    uint32_t reserved[6];
+    uint32_t any_order;  /* 1: order of ids inside a bucket unspecified (as
+                            hg_build_opts.any_order); 0: stable layout          */
+    uint32_t reserved[5];
 } hg_batch_opts;
 
 typedef struct hg_batch hg_batch; /* opaque plan: device descriptors, workspace

@@ -150,6 +150,13 @@ hg_status build_into(hg_table* t, const void* keys, uint64_t n, uint64_t V, uint
         HG_CALL(tmp.get(need));
         ws = tmp.p;
     }
+    if (want_head && !t->head) {
+        // the probe index is allocated by the first build that writes it
+        HG_CALL(hipMalloc((void**)&t->head, t->V_cap * sizeof(uint4)));
+        HG_CALL(hipMalloc((void**)&t->long_list, t->long_cap * 4));
+        HG_CALL(hipMalloc((void**)&t->long_stat, 2 * 4));
+        t->bytes += t->V_cap * sizeof(uint4) + t->long_cap * 4 + 8;
+    }
     IndexOut ix{};
     if (want_head) {
         ix.head = t->head;
@@ -191,12 +198,8 @@ hg_status alloc_table(uint64_t n_cap, uint64_t V_cap, int kb, bool with_ws, hg_t
     hipError_t e = hipMalloc((void**)&t->offsets, (V_cap + 1) * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc((void**)&t->ids, (n_cap ? n_cap : 1) * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc(&t->keys, (n_cap ? n_cap : 1) * key_size(kb));
-    if (e == hipSuccess) e = hipMalloc((void**)&t->head, V_cap * sizeof(uint4));
     t->long_cap = n_cap / (kRunBucket + 1) + 1;
-    if (e == hipSuccess) e = hipMalloc((void**)&t->long_list, t->long_cap * 4);
-    if (e == hipSuccess) e = hipMalloc((void**)&t->long_stat, 2 * 4);
-    t->bytes = (V_cap + 1) * 4 + V_cap * sizeof(uint4) + (n_cap ? n_cap : 1) * (4 + key_size(kb)) +
-               t->long_cap * 4 + 8;
+    t->bytes = (V_cap + 1) * 4 + (n_cap ? n_cap : 1) * (4 + key_size(kb));
     if (e == hipSuccess && with_ws) {
         size_t w1 = build_ws_bytes(1, n_cap, V_cap, kb, 0);
         size_t w2 = build_ws_bytes(2, n_cap, V_cap, kb, 0);

@@ -154,7 +154,9 @@ __global__ __launch_bounds__(256) void k_bcolscan(const BTable<Key>* __restrict_
     }
 }
 
-template <typename Key>
+// STABLE: equal digits keep their order; otherwise their order is
+// unspecified (ranked with LDS atomics, no ballots).
+template <typename Key, bool STABLE>
 __global__ __launch_bounds__(kPartThreads) void k_bpart(const BTable<Key>* __restrict__ tabs,
                                                         BPrefix pre, uint32_t tiles,
                                                         const uint32_t* __restrict__ mat,
@@ -191,7 +193,8 @@ __global__ __launch_bounds__(kPartThreads) void k_bpart(const BTable<Key>* __res
         const uint32_t e = wbase + r * kWave + lane;
         dig[r] = (e < cnt) ? ((KeyTraits<Key>::bucket(k[r], tb.hp) >> tb.k) & (D - 1)) : D;
     }
-    rank_stable<kPartThreads, IT>(dig, bits, wcnt, dstart, tmp, pos);
+    if (STABLE) rank_stable<kPartThreads, IT>(dig, bits, wcnt, dstart, tmp, pos);
+    else rank_any<kPartThreads, IT>(dig, bits, wcnt, dstart, tmp, pos);
     const uint32_t* row = mat + tb.mat_base + (size_t)lt * D;
     for (uint32_t d = threadIdx.x; d < D; d += kPartThreads) tbase[d] = row[d] - dstart[d];
 #pragma unroll
@@ -239,7 +242,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_blocal(
     const BTable<Key>* __restrict__ tabs, BPrefix pre, uint32_t bins,
     const uint32_t* __restrict__ mat, const Key* __restrict__ rkeys,
     const uint32_t* __restrict__ rids, uint32_t* __restrict__ heavy_list,
-    uint32_t* __restrict__ heavy_count) {
+    uint32_t* __restrict__ heavy_count, bool any_order) {
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t gb = blockIdx.x;
     if (gb >= bins) return;
@@ -256,10 +259,10 @@ __global__ __launch_bounds__(kLocalThreads) void k_blocal(
     const uint32_t nb = (tb.V - v0 < NB) ? tb.V - v0 : NB;
     if (tb.kind == kPartitioned)
         light_bin_body<Key>(rkeys + start, rids + start, 0u, L, start - tb.key_base, v0, tb.k, nb,
-                            tb.hp, tb.offsets, IndexOut{}, tb.ids, tb.ekeys, smem);
+                            tb.hp, tb.offsets, IndexOut{}, tb.ids, tb.ekeys, smem, any_order);
     else
         light_bin_body<Key>(tb.keys, nullptr, 0u, L, 0u, v0, tb.k, nb, tb.hp, tb.offsets, IndexOut{},
-                            tb.ids, tb.ekeys, smem);
+                            tb.ids, tb.ekeys, smem, any_order);
 }
 
 template <typename Key>
@@ -350,6 +353,7 @@ struct BatchPlan : BatchPlanBase {
     uint32_t max_b1 = 0, max_k = 0;
     uint64_t mat_entries = 0, ws_keys = 0;
     bool build = true;  // false: probe existing tables only
+    bool any_order = false;  // order inside a bucket unspecified
     std::vector<BTable<Key>> host;
     std::vector<uint32_t> tile_pre, bin_pre, qtile_pre;
     // device memory (one block, owned or lent by the caller)
@@ -524,16 +528,23 @@ struct BatchPlan : BatchPlanBase {
             hipLaunchKernelGGL(k_bcolscan<Key>, dim3(T), dim3(256), 0, s,
                                (const BTable<Key>*)d_tabs, d_mat);
             HG_TRY(hipGetLastError());
-            hipLaunchKernelGGL(k_bpart<Key>, dim3(grid), dim3(kPartThreads),
-                               part_smem_bytes(sizeof(Key), max_b1), s, (const BTable<Key>*)d_tabs,
-                               pre, tiles, (const uint32_t*)d_mat, d_rkeys, d_rids);
+            if (any_order)
+                hipLaunchKernelGGL((k_bpart<Key, false>), dim3(grid), dim3(kPartThreads),
+                                   part_smem_bytes(sizeof(Key), max_b1), s,
+                                   (const BTable<Key>*)d_tabs, pre, tiles, (const uint32_t*)d_mat,
+                                   d_rkeys, d_rids);
+            else
+                hipLaunchKernelGGL((k_bpart<Key, true>), dim3(grid), dim3(kPartThreads),
+                                   part_smem_bytes(sizeof(Key), max_b1), s,
+                                   (const BTable<Key>*)d_tabs, pre, tiles, (const uint32_t*)d_mat,
+                                   d_rkeys, d_rids);
             HG_TRY(hipGetLastError());
         }
         if (bins) {
             hipLaunchKernelGGL(k_blocal<Key>, dim3(bins), dim3(kLocalThreads),
                                light_smem<Key>(max_k), s, (const BTable<Key>*)d_tabs, pre, bins,
                                (const uint32_t*)d_mat, (const Key*)d_rkeys,
-                               (const uint32_t*)d_rids, d_heavy, heavy_count);
+                               (const uint32_t*)d_rids, d_heavy, heavy_count, any_order);
             HG_TRY(hipGetLastError());
             const uint32_t hgrid = bins < 256 ? bins : 256;
             hipLaunchKernelGGL(k_bheavy<Key>, dim3(hgrid), dim3(kLocalThreads),
@@ -577,8 +588,10 @@ static hipError_t set_batch_smem() {
     static bool done = false;
     if (done) return hipSuccess;
     const int lim = 160 * 1024;
-    HG_TRY(hipFuncSetAttribute((const void*)k_bpart<Key>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               lim));
+    HG_TRY(hipFuncSetAttribute((const void*)k_bpart<Key, true>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+    HG_TRY(hipFuncSetAttribute((const void*)k_bpart<Key, false>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lim));
     HG_TRY(hipFuncSetAttribute((const void*)k_blocal<Key>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, lim));
     HG_TRY(hipFuncSetAttribute((const void*)k_bheavy<Key>,
@@ -589,7 +602,7 @@ static hipError_t set_batch_smem() {
 
 // Autotuning cache: (tables, total keys, total queries, key bits) -> target.
 static std::mutex g_tune_mu;
-static std::map<std::tuple<uint32_t, uint64_t, uint64_t, int>, uint32_t> g_tune;
+static std::map<std::tuple<uint32_t, uint64_t, uint64_t, int, bool>, uint32_t> g_tune;
 
 }  // namespace hg
 
@@ -625,7 +638,7 @@ hg_status create_plan(const hg_batch_item* items, uint32_t count, const hg_batch
         cands.push_back(opts->bin_target);
     } else {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        auto it = g_tune.find(std::make_tuple(count, tn, tm, kb));
+        auto it = g_tune.find(std::make_tuple(count, tn, tm, kb, opts && opts->any_order));
         if (it != g_tune.end()) cands.push_back(it->second);
     }
     const bool tune = cands.empty() && (!opts || opts->autotune != 0);
@@ -638,6 +651,7 @@ hg_status create_plan(const hg_batch_item* items, uint32_t count, const hg_batch
     for (uint32_t tgt : cands) {
         BatchPlan<Key>* p = new (std::nothrow) BatchPlan<Key>();
         if (!p) return HG_ERR_OOM;
+        p->any_order = opts && opts->any_order;
         hg_status st = p->layout(items, count, tgt);
         if (st == HG_OK) st = hstat(p->upload());
         if (st == HG_OK) st = hstat(p->capture());
@@ -681,7 +695,7 @@ hg_status create_plan(const hg_batch_item* items, uint32_t count, const hg_batch
     }
     if (tune) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune[std::make_tuple(count, tn, tm, kb)] = best->target;
+        g_tune[std::make_tuple(count, tn, tm, kb, opts && opts->any_order)] = best->target;
     }
     b->plan = best;
     b->target = best->target;

@@ -344,7 +344,7 @@ class BatchItem(ctypes.Structure):
 
 class BatchOpts(ctypes.Structure):
     _fields_ = [("autotune", ctypes.c_uint32), ("bin_target", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 6)]
+                ("any_order", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 5)]
 
 
 def _batch_sig():
@@ -372,7 +372,7 @@ class Batch:
     two integers.  Missing outputs are allocated here.  The plan keeps the
     tensors alive."""
 
-    def __init__(self, tables, key_bits=32, autotune=True, bin_target=0):
+    def __init__(self, tables, key_bits=32, autotune=True, bin_target=0, any_order=False):
         L = _batch_sig()
         self.tables = []
         items = (BatchItem * max(1, len(tables)))()
@@ -403,6 +403,7 @@ class Batch:
         o = BatchOpts()
         o.autotune = 1 if autotune else 0
         o.bin_target = int(bin_target)
+        o.any_order = 1 if any_order else 0
         h = ctypes.c_void_p()
         _check(L.hg_batch_create(items, len(tables), int(key_bits), ctypes.byref(o),
                                  ctypes.byref(h)), "hg_batch_create")

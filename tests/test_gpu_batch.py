@@ -108,6 +108,33 @@ def test_batch_equals_per_table_loop(hg):
         assert torch.equal(c, t["counts"][:q.size])
 
 
+@pytest.mark.parametrize("kb", [32, 64])
+def test_batch_any_order_matches_oracle_as_multisets(hg, kb):
+    print("[case] batch any order", kb, flush=True)
+    data = make_tables(kb, seed=3, count=80)
+    tabs = [{"keys": hg.to_device(k), "queries": hg.to_device(q), "hash_range": V, "seed": s}
+            for k, q, V, s in data]
+    b = hg.Batch(tabs, key_bits=kb, autotune=False, any_order=True)
+    dt = np.uint64 if kb == 64 else np.uint32
+    for rep in range(2):
+        b.run()
+        torch.cuda.synchronize()
+        for (k, q, V, seed), t in zip(data, b.tables):
+            n = k.size
+            off = hg.to_numpy(t["offsets"], np.uint32)
+            ids = hg.to_numpy(t["ids"], np.uint32)[:n]
+            ek = hg.to_numpy(t["ekeys"], dt)[:n]
+            o_off, o_ids, _ = oracle.build_table(k, V, seed, kb)
+            assert np.array_equal(off, o_off), (rep, n, V)
+            seg = np.searchsorted(off.astype(np.int64), np.arange(n), side="right") - 1
+            order = np.lexsort((ids, seg))
+            assert np.array_equal(ids[order], o_ids), (rep, n, V)
+            assert np.array_equal(ek, k[ids]), (rep, n, V)
+            c = hg.to_numpy(t["counts"], np.uint32)[:q.size]
+            assert np.array_equal(c, oracle.probe_counts(k, q, kb)[0]), (rep, n, V)
+    b.free()
+
+
 def test_batch_rejects_bad_items(hg):
     k = hg.to_device(workloads.uniform_keys(10, 32, 1))
     with pytest.raises(hg.HGError):
