@@ -23,7 +23,6 @@ from __future__ import annotations
 
 import argparse
 import hashlib
-import glob
 import json
 import os
 import sys
@@ -42,10 +41,17 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+# sources of the kernels the timed step launches (build, index, probe, scans)
+STEP_KERNEL_SOURCES = ("hg_device.h", "hg_internal.h", "hg_v2_device.h", "hg_v2.hip",
+                       "hg_probe.hip", "hg_scan.hip", "hg_runs.hip")
+
+
 def src_digest() -> str:
+    """Digest of the step's kernel sources: HBM counters stored with another
+    digest were taken on other kernels and are not reported."""
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1907_02900_amd", "csrc", "*"))):
-        with open(f, "rb") as fh:
+    for name in STEP_KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1907_02900_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
