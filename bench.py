@@ -276,6 +276,59 @@ def run_serving(hg, workloads, torch, requests=600, log=print):
     return out
 
 
+def copy_gbps(torch, nbytes=1 << 30, reps=5):
+    """Achievable stream bandwidth: an elementwise kernel reading and writing
+    1 GiB each (read + write bytes over its time; a plain tensor copy goes to
+    the copy engines, which are slower)."""
+    src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    t = timed(lambda: torch.bitwise_xor(src, 1, out=dst), reps, torch)
+    del src, dst
+    return 2 * nbytes / (t / 1000.0) / 1e9
+
+
+def hbm_fractions(build_ms, probe_ms, n, m, V, kb, sum_len, digest, copy):
+    """Per phase of the step: HBM bytes the counters saw (profiles/
+    pmc_traffic.json, same kernel sources) over the phase time, against the
+    8 TB/s peak and the measured copy bandwidth; and the compulsory bytes
+    (build: read keys, write keys + ids + offsets; probe: read the query, two
+    offsets and its bucket's keys, write the count) over the same time."""
+    tr = {k: load_traffic(k, digest) for k in ("v2_tile_hist", "v2_partition_t1",
+                                               "v2_partition_t2", "v2_local_build",
+                                               "probe_count")}
+    b_min = {"build": n * kb + n * (kb + 4) + 4 * (V + 1),
+             "probe": m * kb + 8 * m + kb * sum_len + 4 * m}
+    ms = {"build": build_ms, "probe": probe_ms}
+    meas = None
+    if all(tr.values()):
+        meas = {"build": 2 * tr["v2_tile_hist"] + tr["v2_partition_t1"] +
+                tr["v2_partition_t2"] + tr["v2_local_build"],
+                "probe": tr["probe_count"]}
+    out = {"peak_GBps": HBM_PEAK_GBS, "copy_GBps": round(copy, 1)}
+    for ph in ("build", "probe"):
+        t = ms[ph] / 1000.0
+        e = {"ms": round(ms[ph], 3), "compulsory_bytes": b_min[ph],
+             "compulsory_pct_peak": round(100 * b_min[ph] / t / 1e9 / HBM_PEAK_GBS, 1)}
+        if meas:
+            g = meas[ph] / t / 1e9
+            e.update({"hbm_bytes": int(meas[ph]), "hbm_GBps": round(g, 1),
+                      "hbm_pct_peak": round(100 * g / HBM_PEAK_GBS, 1),
+                      "hbm_pct_copy": round(100 * g / copy, 1)})
+        out[ph] = e
+    return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(log2_sample=24):
     import oracle
     from paper_1907_02900_amd import workloads
@@ -290,6 +343,7 @@ def cpu_baseline(log2_sample=24):
         times.append(time.perf_counter() - t0)
     t = float(np.median(times))
     return {"value": round(2 * ns / t / 1e9, 5), "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
+            "host": {"nproc": os.cpu_count(), "model": cpu_model()},
             "sample": "2^%d uniform uint32 keys, hash_range 2^%d, + 2^%d queries (50%% hits): "
                       "stable build + probe counts, sequential C, median of 3 (%.2f s)"
                       % (log2_sample, log2_sample, log2_sample, t)}
@@ -422,8 +476,11 @@ def main():
               "probe_sum_bucket_len": sum_len, "probe_sum_keys_past_index": sum_tail}
     build_ms = sum(v["ms_per_step"] for k, v in kernels.items()
                    if k.startswith("v2_") or k == "fill")
+    probe_ms = kernels.get("probe_count", {}).get("ms_per_step", 0.0)
     phases["build_v2_ms"] = round(build_ms, 3)
-    phases["probe_ms"] = round(kernels.get("probe_count", {}).get("ms_per_step", 0.0), 3)
+    phases["probe_ms"] = round(probe_ms, 3)
+    phases["hbm"] = hbm_fractions(build_ms, probe_ms, n, m, V, kb, sum_len, digest,
+                                  copy_gbps(torch))
 
     if not args.no_extras:
         log("extras")
@@ -502,6 +559,27 @@ def main():
         log("zipf join build %.3f ms probe %.3f ms, %d matches" % (tb, tp, ztot))
         tz.free()
         del kz, qz, tz
+        # the paper's own input: the sequence 1..2^25 at loads 0.5 / 1 / 2 / 4
+        # (V = N / load); build, then probe every key (all hits).  The paper
+        # reports up to 2.5 Gkeys/s build on a GV100 for this input.
+        ns = 1 << 25
+        ks = hg.to_device(workloads.sequence_keys(ns, 32))
+        cs = torch.empty(ns, dtype=torch.int32, device="cuda")
+        seq = {}
+        for load in (0.5, 1, 2, 4):
+            Vs = int(ns / load)
+            ts = hg.Table.create(ns, Vs, 32)
+            tb_any = timed(lambda: ts.rebuild(ks, Vs, 0, any_order=True), reps, torch)
+            tb_st = timed(lambda: ts.rebuild(ks, Vs, 0), reps, torch)
+            tp = timed(lambda: hg.hg_probe(ts, ks, counts=True, out=cs), reps, torch)
+            seq["load %g" % load] = {"build_any_order_Gkeys": round(ns / tb_any / 1e6, 2),
+                                     "build_stable_Gkeys": round(ns / tb_st / 1e6, 2),
+                                     "probe_Gkeys": round(ns / tp / 1e6, 2)}
+            ts.free()
+        seq["paper_gv100_build_peak_Gkeys"] = 2.5
+        ex["sequence_2^25"] = seq
+        log("sequence 1..2^25: %s" % seq)
+        del ks, cs
         phases["extras"] = ex
 
     if not args.no_batched:
