@@ -20,9 +20,12 @@ struct hg_table {
     void* keys = nullptr;
     uint4* head = nullptr;  // V_cap per-bucket probe index entries
     bool has_head = false;  // the last build wrote head
-    // long buckets (> kRunBucket entries): their list, counters and key runs
+    // long buckets (> kRunBucket entries): per-bin tallies, their prefix sums,
+    // the list of long buckets and their key runs
+    uint2* tally = nullptr;
+    uint32_t* tally_pre = nullptr;  // [2 * (tally_cap + 1)]: counts, lengths
+    uint64_t tally_cap = 0;
     uint32_t* long_list = nullptr;
-    uint32_t* long_stat = nullptr;  // [2]
     uint64_t long_cap = 0;
     RunsDev runs{};
     uint64_t runs_cap = 0;          // runs the run arrays hold (kperm: n_cap)
@@ -85,16 +88,26 @@ hg_status read_u64(const uint64_t* d, uint64_t* h, hipStream_t s) {
         if (st__ != HG_OK) return st__;      \
     } while (0)
 
-// After a V2 build with the index: read how many long buckets it listed and,
-// if any, build their key-run summary.  Waits for the build (the list's size
-// decides the summary's allocations and launches).
-hg_status build_runs(hg_table* t, hipStream_t s) {
-    uint32_t stat[2] = {0, 0};
-    HG_CALL(hipMemcpyAsync(stat, t->long_stat, sizeof(stat), hipMemcpyDeviceToHost, s));
+// After a V2 build with the index: sum the bins' long-bucket tallies and, if
+// there are long buckets, list them and build their key-run summary.  Waits
+// for the build (the totals decide the summary's allocations and launches).
+hg_status build_runs(hg_table* t, const IndexOut& ix, hipStream_t s) {
+    if (ix.bins == 0) return HG_OK;
+    uint32_t* pre_cnt = t->tally_pre;
+    uint32_t* pre_len = t->tally_pre + (t->tally_cap + 1);
+    {
+        Scratch tw(s);
+        HG_CALL(tw.get(tally_ws_bytes(ix.bins)));
+        HG_CALL(scan_tally(t->tally, ix.bins, pre_cnt, pre_len, tw.p, s));
+    }
+    uint32_t nlong = 0, total = 0;
+    HG_CALL(hipMemcpyAsync(&nlong, pre_cnt + ix.bins, 4, hipMemcpyDeviceToHost, s));
+    HG_CALL(hipMemcpyAsync(&total, pre_len + ix.bins, 4, hipMemcpyDeviceToHost, s));
     HG_CALL(hipStreamSynchronize(s));
-    const uint32_t nlong = stat[0], total = stat[1];
     if (nlong == 0) return HG_OK;
     if (nlong > t->long_cap) return HG_ERR_DEVICE;  // cannot happen: each holds > kRunBucket keys
+    HG_CALL(list_long_buckets(t->offsets, t->V, ix.k, ix.bins, t->tally, pre_cnt, t->long_list,
+                              s));
     const size_t ks = key_size(t->key_bits);
     if (!t->runs.kperm) {
         HG_CALL(hipMalloc((void**)&t->runs.kperm, (t->n_cap ? t->n_cap : 1) * 4));
@@ -154,15 +167,28 @@ hg_status build_into(hg_table* t, const void* keys, uint64_t n, uint64_t V, uint
         // the probe index is allocated by the first build that writes it
         HG_CALL(hipMalloc((void**)&t->head, t->V_cap * sizeof(uint4)));
         HG_CALL(hipMalloc((void**)&t->long_list, t->long_cap * 4));
-        HG_CALL(hipMalloc((void**)&t->long_stat, 2 * 4));
-        t->bytes += t->V_cap * sizeof(uint4) + t->long_cap * 4 + 8;
+        t->bytes += t->V_cap * sizeof(uint4) + t->long_cap * 4;
+    }
+    if (want_head) {
+        const uint32_t nbins = n ? plan_v2(n, V, t->key_bits, bins).bins : 0u;
+        if (nbins > t->tally_cap) {  // per-bin tallies, grown when a plan needs more bins
+            if (t->tally) {
+                (void)hipFree(t->tally);
+                (void)hipFree(t->tally_pre);
+                t->bytes -= t->tally_cap * 8 + 2 * (t->tally_cap + 1) * 4;
+                t->tally = nullptr;
+                t->tally_cap = 0;
+            }
+            HG_CALL(hipMalloc((void**)&t->tally, (size_t)nbins * sizeof(uint2)));
+            HG_CALL(hipMalloc((void**)&t->tally_pre, 2 * ((size_t)nbins + 1) * 4));
+            t->tally_cap = nbins;
+            t->bytes += (uint64_t)nbins * 8 + 2 * ((uint64_t)nbins + 1) * 4;
+        }
     }
     IndexOut ix{};
     if (want_head) {
         ix.head = t->head;
-        ix.long_list = t->long_list;
-        ix.long_stat = t->long_stat;
-        ix.long_cap = (uint32_t)t->long_cap;
+        ix.bin_tally = t->tally;
     }
     hipError_t e;
     if (t->key_bits == 32) {
@@ -185,7 +211,7 @@ hg_status build_into(hg_table* t, const void* keys, uint64_t n, uint64_t V, uint
     t->variant = variant;
     t->has_head = want_head;
     t->has_runs = false;
-    if (want_head) HG_CALL_ST(build_runs(t, s));
+    if (want_head) HG_CALL_ST(build_runs(t, ix, s));
     return HG_OK;
 }
 
@@ -353,7 +379,8 @@ void hg_table_free(hg_table* t) {
     if (t->keys) (void)hipFree(t->keys);
     if (t->head) (void)hipFree(t->head);
     if (t->long_list) (void)hipFree(t->long_list);
-    if (t->long_stat) (void)hipFree(t->long_stat);
+    if (t->tally) (void)hipFree(t->tally);
+    if (t->tally_pre) (void)hipFree(t->tally_pre);
     if (t->runs.kperm) (void)hipFree(t->runs.kperm);
     if (t->runs.run_key) (void)hipFree(t->runs.run_key);
     if (t->runs.run_cnt) (void)hipFree(t->runs.run_cnt);

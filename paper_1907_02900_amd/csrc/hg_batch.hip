@@ -1087,12 +1087,13 @@ struct Server {
         if (e == hipSuccess) {
             if (r0.kind == 0 && group.size() == 1) {
                 STable& t = tables[r0.table];
+                IndexOut none{};  // served tables carry no probe index
                 e = kb == 32 ? run_build_v2<uint32_t>((const uint32_t*)r0.data, t.n, t.V, t.seed,
                                                       t.offsets, t.ids, (uint32_t*)t.keys,
-                                                      IndexOut{}, L.transient, 0, true, s)
+                                                      none, L.transient, 0, true, s)
                              : run_build_v2<uint64_t>((const uint64_t*)r0.data, t.n, t.V, t.seed,
                                                       t.offsets, t.ids, (uint64_t*)t.keys,
-                                                      IndexOut{}, L.transient, 0, true, s);
+                                                      none, L.transient, 0, true, s);
             } else if (r0.kind == 1 && group.size() == 1) {
                 const STable& t = tables[r0.table];
                 TableDev d{t.offsets, t.ids, t.keys, t.n, t.V, t.seed};

@@ -114,15 +114,15 @@ hipError_t run_build_v1(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, 
 // key-grouped copy of the bucket's ids.
 constexpr uint32_t kRunBucket = 32;
 
-// Where a V2 build writes its probe index (head == null: none).  Buckets
-// longer than kRunBucket are appended to `long_list` (capacity long_cap >=
-// n / (kRunBucket + 1)); long_stat[0] counts them, long_stat[1] sums their
-// lengths.
+// Where a V2 build writes its probe index (head == null: none).  Every final
+// bin also writes bin_tally[bin] = {buckets longer than kRunBucket, their
+// total length} with plain stores (no device atomics: same-address atomics
+// serialise at the memory side across the XCDs).  k and bins are set by the
+// build (its plan) for the long-bucket listing that follows.
 struct IndexOut {
     uint4* head = nullptr;
-    uint32_t* long_list = nullptr;
-    uint32_t* long_stat = nullptr;
-    uint32_t long_cap = 0;
+    uint2* bin_tally = nullptr;  // [bins]
+    uint32_t k = 0, bins = 0;
 };
 
 // Key-run summary arrays of a table (all sized for the summary's runs, kperm
@@ -133,6 +133,17 @@ struct RunsDev {
     uint32_t* run_pos = nullptr;   // [runs] edge position of the run in kperm
     uint32_t* kperm = nullptr;     // [n] ids of long buckets grouped by key (ids ascending)
 };
+
+// Long-bucket listing after a build with the index: tally_ws_bytes(bins)
+// bytes of workspace; scan the per-bin tallies (pre[bins+1] = {count, length}
+// prefix sums, device), then, once their totals are known on the host, list
+// the long buckets (bucket ids, ascending) into long_list.
+size_t tally_ws_bytes(uint32_t bins);
+hipError_t scan_tally(const uint2* tally, uint32_t bins, uint32_t* pre_cnt, uint32_t* pre_len,
+                      void* ws, hipStream_t s);
+hipError_t list_long_buckets(const uint32_t* offsets, uint64_t V, uint32_t k, uint32_t bins,
+                             const uint2* tally, const uint32_t* pre_cnt, uint32_t* long_list,
+                             hipStream_t s);
 
 // Workspace for building the summary of `nlong` long buckets holding `total`
 // entries.
@@ -145,12 +156,12 @@ hipError_t run_key_runs(const uint32_t* offsets, const uint32_t* ids, const Key*
                         const uint32_t* long_list, uint32_t nlong, uint32_t total, uint4* head,
                         const RunsDev& r, void* ws, hipStream_t s);
 
-// ix.head (may be null): V 16-byte probe index entries, one per bucket; long
-// buckets are listed as IndexOut describes.  stable: ids ascend inside every
+// ix.head (may be null): V 16-byte probe index entries, one per bucket, and
+// the per-bin tally of long buckets (IndexOut).  stable: ids ascend inside every
 // bucket (otherwise their order there is unspecified).
 template <typename Key>
 hipError_t run_build_v2(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, uint32_t* offsets,
-                        uint32_t* ids, Key* ekeys, const IndexOut& ix, void* ws,
+                        uint32_t* ids, Key* ekeys, IndexOut& ix, void* ws,
                         uint32_t bins_hint, bool stable, hipStream_t s);
 
 // ---- probing ---------------------------------------------------------------

@@ -12,10 +12,11 @@
 // binary-searches the runs; its pairs are the ids of one run.  Counts and
 // pairs are exactly those of a scan.
 //
-// Construction: the long buckets were listed by the per-bin build.  Their
-// entries are gathered with the sort key (list index, key), sorted (a device
-// radix sort, stable, so equal keys keep ascending ids), and a flag/scan pass
-// marks the runs.
+// Construction: every final bin of the build tallied its long buckets; a scan
+// of the tallies sizes the summary, a per-bin pass lists the long buckets,
+// and their entries are gathered with the sort key (list index, key), sorted
+// (a device radix sort, stable, so equal keys keep ascending ids), and a
+// flag/scan pass marks the runs.
 #include <rocprim/device/device_radix_sort.hpp>
 
 #include "hg_internal.h"
@@ -184,6 +185,40 @@ __global__ void k_run_head(const uint32_t* __restrict__ list, uint32_t nlong,
     head[list[i]] = e;
 }
 
+// per-bin tallies -> two count arrays
+__global__ void k_split_tally(const uint2* __restrict__ tally, uint32_t bins,
+                              uint32_t* __restrict__ cnt, uint32_t* __restrict__ len) {
+    const uint32_t g = blockIdx.x * kThreads + threadIdx.x;
+    if (g < bins) {
+        const uint2 t = tally[g];
+        cnt[g] = t.x;
+        len[g] = t.y;
+    }
+}
+
+// Long buckets of every bin with any, ascending, at the bin's slot range.
+__global__ __launch_bounds__(kThreads) void k_list_long(const uint32_t* __restrict__ off,
+                                                        uint32_t V, uint32_t k, uint32_t bins,
+                                                        const uint2* __restrict__ tally,
+                                                        const uint32_t* __restrict__ pre,
+                                                        uint32_t* __restrict__ list) {
+    __shared__ uint32_t tmp[kThreads / kWave + 1];
+    const uint32_t NB = 1u << k;
+    for (uint32_t g = blockIdx.x; g < bins; g += gridDim.x) {
+        if (tally[g].x == 0) continue;  // uniform across the workgroup
+        const uint32_t v0 = g << k, nb = (V - v0 < NB) ? V - v0 : NB;
+        uint32_t at = pre[g];
+        for (uint32_t c0 = 0; c0 < nb; c0 += kThreads) {
+            const uint32_t v = c0 + threadIdx.x;
+            const uint32_t f = (v < nb && off[v0 + v + 1] - off[v0 + v] > kRunBucket) ? 1u : 0u;
+            uint32_t all;
+            const uint32_t r = block_excl_scan<kThreads>(f, tmp, &all);
+            if (f) list[at + r] = v0 + v;
+            at += all;
+        }
+    }
+}
+
 size_t sort_tmp_bytes(uint32_t total, int key_bits) {
     size_t a = 0, b = 0;
     (void)rocprim::radix_sort_pairs((void*)nullptr, a, (uint64_t*)nullptr, (uint64_t*)nullptr,
@@ -235,6 +270,32 @@ size_t layout_runs(void* ws, uint64_t nlong, uint64_t total, int key_bits, RunsW
 }
 
 }  // namespace
+
+size_t tally_ws_bytes(uint32_t bins) {
+    return 2 * align_up(((size_t)bins + 1) * 4, 256) + scan_ws_bytes(bins) + 512;
+}
+
+hipError_t scan_tally(const uint2* tally, uint32_t bins, uint32_t* pre_cnt, uint32_t* pre_len,
+                      void* ws, hipStream_t s) {
+    Carver c(ws);
+    uint32_t* cnt = c.take<uint32_t>((size_t)bins + 1);
+    uint32_t* len = c.take<uint32_t>((size_t)bins + 1);
+    void* sws = c.take<char>(scan_ws_bytes(bins));
+    hipLaunchKernelGGL(k_split_tally, dim3(blocks_for(bins)), dim3(kThreads), 0, s, tally, bins,
+                       cnt, len);
+    HG_TRY(hipGetLastError());
+    HG_TRY(scan_excl<uint32_t>(cnt, bins, pre_cnt, nullptr, sws, s));
+    return scan_excl<uint32_t>(len, bins, pre_len, nullptr, sws, s);
+}
+
+hipError_t list_long_buckets(const uint32_t* offsets, uint64_t V, uint32_t k, uint32_t bins,
+                             const uint2* tally, const uint32_t* pre_cnt, uint32_t* long_list,
+                             hipStream_t s) {
+    const uint32_t grid = bins < 16384 ? bins : 16384;
+    hipLaunchKernelGGL(k_list_long, dim3(grid ? grid : 1), dim3(kThreads), 0, s, offsets,
+                       (uint32_t)V, k, bins, tally, pre_cnt, long_list);
+    return hipGetLastError();
+}
 
 size_t runs_ws_bytes(uint64_t nlong, uint64_t total, int key_bits) {
     return layout_runs(nullptr, nlong, total, key_bits, nullptr);

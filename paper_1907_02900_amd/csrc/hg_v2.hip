@@ -506,16 +506,19 @@ __global__ __launch_bounds__(kLocalThreads) void k_huge_index(
     const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ huge_list,
     const uint32_t* __restrict__ ctr, uint32_t k, uint32_t V,
     const uint32_t* __restrict__ offsets, const Key* __restrict__ ekeys, IndexOut ix) {
+    __shared__ uint32_t tmp[kLocalThreads / kWave + 1];
     const uint32_t NB = 1u << k, nh = ctr[1];
     for (uint32_t idx = blockIdx.x; idx < nh; idx += gridDim.x) {
         const uint32_t b = huge_list[idx];
         const uint32_t v0 = b << k, nb = (V - v0 < NB) ? V - v0 : NB;
         const uint32_t be = bin_start[b + 1];
+        uint32_t nlong = 0, nlen = 0;
         for (uint32_t v = threadIdx.x; v < nb; v += kLocalThreads) {
             const uint32_t lo = offsets[v0 + v];
             const uint32_t hi = (v + 1 < nb) ? offsets[v0 + v + 1] : be;
-            put_index<Key>(ix, v0 + v, lo, hi, ekeys + lo);
+            put_index<Key>(ix, v0 + v, lo, hi, ekeys + lo, nlong, nlen);
         }
+        put_tally(ix, b, nlong, nlen, tmp);
     }
 }
 
@@ -759,15 +762,18 @@ size_t build_ws_bytes(int variant, uint64_t n, uint64_t V, int key_bits, uint32_
 
 template <typename Key>
 hipError_t run_build_v2(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, uint32_t* offsets,
-                        uint32_t* ids, Key* ekeys, const IndexOut& ix, void* ws,
+                        uint32_t* ids, Key* ekeys, IndexOut& ix, void* ws,
                         uint32_t bins_hint, bool stable, hipStream_t s) {
     HG_TRY(set_smem_limits<Key>());
-    if (ix.head) HG_TRY(fill_u32(ix.long_stat, 2, 0u, s));
+    ix.k = 0;
+    ix.bins = 0;
     if (n == 0) {
         if (ix.head) HG_TRY(fill_u32((uint32_t*)ix.head, 4 * V, 0u, s));
         return fill_u32(offsets, V + 1, 0u, s);
     }
     const V2Plan p = plan_v2(n, V, sizeof(Key) * 8, bins_hint);
+    ix.k = p.k;
+    ix.bins = p.bins;
     V2Ws w;
     layout_v2(ws, p, sizeof(Key), &w);
     auto hp = KeyTraits<Key>::make(V, seed);
@@ -860,10 +866,10 @@ hipError_t run_build_v2(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, 
 }
 
 template hipError_t run_build_v2<uint32_t>(const uint32_t*, uint64_t, uint64_t, uint64_t,
-                                           uint32_t*, uint32_t*, uint32_t*, const IndexOut&,
-                                           void*, uint32_t, bool, hipStream_t);
+                                           uint32_t*, uint32_t*, uint32_t*, IndexOut&, void*,
+                                           uint32_t, bool, hipStream_t);
 template hipError_t run_build_v2<uint64_t>(const uint64_t*, uint64_t, uint64_t, uint64_t,
-                                           uint32_t*, uint32_t*, uint64_t*, const IndexOut&,
-                                           void*, uint32_t, bool, hipStream_t);
+                                           uint32_t*, uint32_t*, uint64_t*, IndexOut&, void*,
+                                           uint32_t, bool, hipStream_t);
 
 }  // namespace hg

@@ -276,18 +276,27 @@ __device__ __forceinline__ uint4 head_entry<uint64_t>(uint32_t start, uint32_t e
     return make_uint4(start, end, (uint32_t)k0, (uint32_t)(k0 >> 32));
 }
 
-// Write bucket b's index entry; a bucket longer than kRunBucket is also
-// appended to the list of long buckets (its key slots are replaced later by
-// its key-run summary).
+// Write bucket b's index entry (the key slots of a bucket longer than
+// kRunBucket are replaced later by its key-run summary) and add it to this
+// thread's tally of long buckets.
 template <typename Key>
 __device__ __forceinline__ void put_index(const IndexOut& ix, uint32_t b, uint32_t start,
-                                          uint32_t end, const Key* k) {
+                                          uint32_t end, const Key* k, uint32_t& nlong,
+                                          uint32_t& nlen) {
     ix.head[b] = head_entry<Key>(start, end, k);
     if (end - start > kRunBucket) {
-        const uint32_t slot = atomicAdd(&ix.long_stat[0], 1u);
-        if (slot < ix.long_cap) ix.long_list[slot] = b;
-        atomicAdd(&ix.long_stat[1], end - start);
+        ++nlong;
+        nlen += end - start;
     }
+}
+
+// The workgroup's long-bucket tally for bin g (all threads call; barriers).
+__device__ __forceinline__ void put_tally(const IndexOut& ix, uint32_t g, uint32_t nlong,
+                                          uint32_t nlen, uint32_t* tmp) {
+    uint32_t tc, tl;
+    block_excl_scan<kLocalThreads>(nlong, tmp, &tc);
+    block_excl_scan<kLocalThreads>(nlen, tmp, &tl);
+    if (threadIdx.x == 0) ix.bin_tally[g] = make_uint2(tc, tl);
 }
 
 // Build one bin of L <= kLightCap keys whose buckets are [v0, v0 + nb) with
@@ -295,7 +304,8 @@ __device__ __forceinline__ void put_index(const IndexOut& ix, uint32_t b, uint32
 // (or id_base + e when src_ids is null).  The bin's keys and ids go to
 // ekeys/ids[out + p] for p < L, sorted by bucket with ids ascending inside a
 // bucket, and offsets[v0 + v] = out + (start of bucket v in the bin).
-// Usual case (every bucket of the bin holds at most kFixMax keys): LDS
+// Usual case (every bucket of the bin holds at most kFixMax keys, or any order
+// is allowed): LDS
 // counting sort with atomic cursors, then an insertion sort by id inside each
 // bucket (skipped with any_order: order inside a bucket is then unspecified).
 // Otherwise the bin (in id order) is stably ranked by local bucket.
@@ -320,6 +330,7 @@ __device__ __forceinline__ void light_bin_body(const Key* __restrict__ src_keys,
     uint32_t* wcnt = cnt + NB;                     // W * 64
     uint32_t* dstart = wcnt + W_LOCAL * 64;        // 64
     uint32_t* tmp = dstart + 64;
+    uint32_t nlong = 0, nlen = 0;  // this thread's long buckets (probe index)
     const uint32_t w = threadIdx.x / kWave, lane = lane_id();
     // balance the bin over the waves in whole rounds of 64
     const uint32_t wchunk = (((L + W_LOCAL - 1) / W_LOCAL) + kWave - 1) & ~(uint32_t)(kWave - 1);
@@ -354,7 +365,7 @@ __device__ __forceinline__ void light_bin_body(const Key* __restrict__ src_keys,
     __syncthreads();
     // bucket starts (in place) and the largest bucket of the bin
     const uint32_t maxc = scan_counts_max(cnt, NB, tmp);
-    if (maxc <= kFixMax) {
+    if (maxc <= kFixMax || any_order) {
 #pragma unroll
         for (int r = 0; r < IT; ++r) {
             if (b[r] < NB) {
@@ -385,7 +396,7 @@ __device__ __forceinline__ void light_bin_body(const Key* __restrict__ src_keys,
         for (uint32_t v = threadIdx.x; v < nb; v += kLocalThreads) {
             const uint32_t lo = v ? cnt[v - 1] : 0u, hi = cnt[v];
             offsets[v0 + v] = out + lo;
-            if (ix.head) put_index<Key>(ix, v0 + v, out + lo, out + hi, skeys + lo);
+            if (ix.head) put_index<Key>(ix, v0 + v, out + lo, out + hi, skeys + lo, nlong, nlen);
         }
     } else {
         sort_chunk_by_bucket<Key, IT>(kk, id, b, rounds, L, wchunk, k, skeys, sids, sb, wcnt,
@@ -394,9 +405,10 @@ __device__ __forceinline__ void light_bin_body(const Key* __restrict__ src_keys,
         for (uint32_t v = threadIdx.x; v < nb; v += kLocalThreads) {
             const uint32_t lo = cnt[v], hi = (v + 1 < NB) ? cnt[v + 1] : L;
             offsets[v0 + v] = out + lo;
-            if (ix.head) put_index<Key>(ix, v0 + v, out + lo, out + hi, skeys + lo);
+            if (ix.head) put_index<Key>(ix, v0 + v, out + lo, out + hi, skeys + lo, nlong, nlen);
         }
     }
+    if (ix.head) put_tally(ix, v0 >> k, nlong, nlen, tmp);
     for (uint32_t p = threadIdx.x; p < L; p += kLocalThreads) {
         ekeys[out + p] = skeys[p];
         ids[out + p] = sids[p];
@@ -527,11 +539,14 @@ __device__ __forceinline__ void heavy_bin_body(const Key* __restrict__ src_keys,
     place_in_chunks<Key>(src_keys, src_ids, id_base, L, out, out + L, v0, k, hp, ids, ekeys,
                          smem);
     // cur[v] is now the end of bucket v; the bin's edges are in ekeys
-    if (ix.head)
+    if (ix.head) {
+        uint32_t nlong = 0, nlen = 0;
         for (uint32_t v = threadIdx.x; v < nb; v += kLocalThreads) {
             const uint32_t lo = v ? cur[v - 1] : out;
-            put_index<Key>(ix, v0 + v, lo, cur[v], ekeys + lo);
+            put_index<Key>(ix, v0 + v, lo, cur[v], ekeys + lo, nlong, nlen);
         }
+        put_tally(ix, v0 >> k, nlong, nlen, tmp);
+    }
 }
 
 }  // namespace v2dev
