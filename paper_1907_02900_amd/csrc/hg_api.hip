@@ -27,6 +27,8 @@ struct hg_table {
     uint64_t tally_cap = 0;
     uint32_t* long_list = nullptr;
     uint64_t long_cap = 0;
+    void* runs_ws = nullptr;  // workspace of the listing and the summary (grow-only)
+    size_t runs_ws_bytes = 0;
     RunsDev runs{};
     uint64_t runs_cap = 0;          // runs the run arrays hold (kperm: n_cap)
     bool has_runs = false;
@@ -88,6 +90,23 @@ hg_status read_u64(const uint64_t* d, uint64_t* h, hipStream_t s) {
         if (st__ != HG_OK) return st__;      \
     } while (0)
 
+// The table's long-bucket workspace holds at least `bytes` (the stream has
+// no work queued on the old one when this runs: callers synchronise first or
+// use it in stream order).
+hg_status ensure_runs_ws(hg_table* t, size_t bytes) {
+    if (t->runs_ws_bytes >= bytes) return HG_OK;
+    if (t->runs_ws) {
+        (void)hipFree(t->runs_ws);  // waits for the device
+        t->bytes -= t->runs_ws_bytes;
+        t->runs_ws = nullptr;
+        t->runs_ws_bytes = 0;
+    }
+    HG_CALL(hipMalloc(&t->runs_ws, bytes));
+    t->runs_ws_bytes = bytes;
+    t->bytes += bytes;
+    return HG_OK;
+}
+
 // After a V2 build with the index: sum the bins' long-bucket tallies and, if
 // there are long buckets, list them and build their key-run summary.  Waits
 // for the build (the totals decide the summary's allocations and launches).
@@ -95,11 +114,8 @@ hg_status build_runs(hg_table* t, const IndexOut& ix, hipStream_t s) {
     if (ix.bins == 0) return HG_OK;
     uint32_t* pre_cnt = t->tally_pre;
     uint32_t* pre_len = t->tally_pre + (t->tally_cap + 1);
-    {
-        Scratch tw(s);
-        HG_CALL(tw.get(tally_ws_bytes(ix.bins)));
-        HG_CALL(scan_tally(t->tally, ix.bins, pre_cnt, pre_len, tw.p, s));
-    }
+    HG_CALL_ST(ensure_runs_ws(t, tally_ws_bytes(ix.bins)));
+    HG_CALL(scan_tally(t->tally, ix.bins, pre_cnt, pre_len, t->runs_ws, s));
     uint32_t nlong = 0, total = 0;
     HG_CALL(hipMemcpyAsync(&nlong, pre_cnt + ix.bins, 4, hipMemcpyDeviceToHost, s));
     HG_CALL(hipMemcpyAsync(&total, pre_len + ix.bins, 4, hipMemcpyDeviceToHost, s));
@@ -128,14 +144,13 @@ hg_status build_runs(hg_table* t, const IndexOut& ix, hipStream_t s) {
         t->runs_cap = total;
         t->bytes += (uint64_t)total * (ks + 8);
     }
-    Scratch tmp(s);
-    HG_CALL(tmp.get(runs_ws_bytes(nlong, total, t->key_bits)));
+    HG_CALL_ST(ensure_runs_ws(t, runs_ws_bytes(nlong, total, t->key_bits)));
     const hipError_t e =
         t->key_bits == 32
             ? run_key_runs<uint32_t>(t->offsets, t->ids, (const uint32_t*)t->keys, t->long_list,
-                                     nlong, total, t->head, t->runs, tmp.p, s)
+                                     nlong, total, t->head, t->runs, t->runs_ws, s)
             : run_key_runs<uint64_t>(t->offsets, t->ids, (const uint64_t*)t->keys, t->long_list,
-                                     nlong, total, t->head, t->runs, tmp.p, s);
+                                     nlong, total, t->head, t->runs, t->runs_ws, s);
     if (e != hipSuccess) return from_hip(e);
     t->has_runs = true;
     return HG_OK;
@@ -381,6 +396,7 @@ void hg_table_free(hg_table* t) {
     if (t->long_list) (void)hipFree(t->long_list);
     if (t->tally) (void)hipFree(t->tally);
     if (t->tally_pre) (void)hipFree(t->tally_pre);
+    if (t->runs_ws) (void)hipFree(t->runs_ws);
     if (t->runs.kperm) (void)hipFree(t->runs.kperm);
     if (t->runs.run_key) (void)hipFree(t->runs.run_key);
     if (t->runs.run_cnt) (void)hipFree(t->runs.run_cnt);
