@@ -559,6 +559,20 @@ def main():
         log("zipf join build %.3f ms probe %.3f ms, %d matches" % (tb, tp, ztot))
         tz.free()
         del kz, qz, tz
+        # 2^30 keys, V = 2^30 (two partition passes of 10 and 9 bits)
+        log("2^30 keys")
+        n30 = 1 << 30
+        k30 = hg.to_device(workloads.uniform_keys(n30, 32, seed=8))
+        t30 = hg.Table.create(n30, n30, 32)
+        tb30a = timed(lambda: t30.rebuild(k30, n30, 0, any_order=True), 2, torch)
+        tb30 = timed(lambda: t30.rebuild(k30, n30, 0), 2, torch)
+        ex["keys_2^30"] = {"build_any_order_ms": round(tb30a, 3),
+                           "build_any_order_Gkeys": round(n30 / tb30a / 1e6, 2),
+                           "build_stable_ms": round(tb30, 3),
+                           "build_stable_Gkeys": round(n30 / tb30 / 1e6, 2)}
+        log("2^30 keys: build any order %.3f ms, stable %.3f ms" % (tb30a, tb30))
+        t30.free()
+        del k30, t30
         # the paper's own input: the sequence 1..2^25 at loads 0.5 / 1 / 2 / 4
         # (V = N / load); build, then probe every key (all hits).  The paper
         # reports up to 2.5 Gkeys/s build on a GV100 for this input.

@@ -154,6 +154,27 @@ def test_full_uint64_keys(hg):
     table.free()
 
 
+def test_full_2p30_keys_two_tier_build(hg):
+    # 2^30 keys, V = 2^30: 2^19 final bins reached by two partition passes of
+    # 10 and 9 bits; the table is checked by the same properties, and the
+    # counts of 2^20 sampled queries against the oracle
+    n = 1 << 30
+    say("2^30 keys, V = 2^30")
+    keys = workloads.uniform_keys(n, 32, seed=8)
+    dk = hg.to_device(keys)
+    table = hg.Table.create(n, n, 32)
+    table.rebuild(dk, n, seed=3)
+    h = torch.from_numpy(oracle.hash_buckets(keys, n, 3).astype(np.int64)).cuda()
+    check_table(hg, table, u64(dk), h, n, stable=True)
+    del h
+    q = workloads.probe_queries(keys, 1 << 20, 0.5, seed=9)
+    c, tot = hg.hg_probe(table, hg.to_device(q), counts=True, total=True)
+    say("oracle counts 2^30 x 2^20")
+    exp, etot = oracle.probe_counts(keys, q)
+    assert np.array_equal(hg.to_numpy(c, np.uint32), exp) and tot == etot
+    table.free()
+
+
 @pytest.mark.parametrize("s", [0.8, 1.2, 1.5])
 def test_full_zipf_join(hg, s):
     nb, V = N // 2, N // 2
