@@ -559,6 +559,24 @@ def main():
         log("zipf join build %.3f ms probe %.3f ms, %d matches" % (tb, tp, ztot))
         tz.free()
         del kz, qz, tz
+        # erasing keys: 2^22 distinct keys removed from a 2^28 table (about 1.6%
+        # of its entries), then a probe of all 2^28 queries
+        log("erase")
+        te = hg.Table.create(n, V, 32)
+        te.rebuild(dk, V, 0)
+        gone = hg.to_device(np.unique(keys_np[: 1 << 22]))
+        te.erase(gone[:0])  # allocates the length and mark arrays
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        removed = te.erase(gone)
+        torch.cuda.synchronize()
+        t_er = (time.perf_counter() - t0) * 1e3
+        t_pe = timed(lambda: hg.hg_probe(te, dq, counts=True, out=counts), reps, torch)
+        ex["erase_2^22_keys_from_2^28"] = {"erase_ms": round(t_er, 3), "removed": removed,
+                                           "probe_after_ms": round(t_pe, 3)}
+        log("erase %d entries %.3f ms, probe after %.3f ms" % (removed, t_er, t_pe))
+        te.free()
+        del te, gone
         # 2^30 keys, V = 2^30 (two partition passes of 10 and 9 bits)
         log("2^30 keys")
         n30 = 1 << 30

@@ -169,9 +169,36 @@ hg_status hg_table_view(const hg_table *t, hg_table_info *info);
 
 /* Copy the table's CSR arrays into caller buffers (device to device, on the
  * stream): d_offsets V+1 uint32, d_ids n uint32, d_keys n keys.  Any of the
- * three may be NULL to skip it. */
+ * three may be NULL to skip it.  After hg_table_erase the copy is the
+ * compacted CSR of the live entries (their number from hg_table_lengths), in
+ * bucket order and, inside a bucket, in the order the build left them. */
 hg_status hg_table_export(const hg_table *t, uint32_t *d_offsets, uint32_t *d_ids, void *d_keys,
                           hipStream_t stream);
+
+/* Decremental HashGraph (the per-bucket length array of the paper's
+ * conclusion): remove every entry whose key equals one of d_keys[0 .. m)
+ * (device array of the table's key width; repeated and absent keys allowed).
+ * Bucket h then holds its live entries in [offsets[h], offsets[h] + len[h]);
+ * the edge array keeps its size and its order inside each bucket, so a stable
+ * table stays stable.  Probes, pairs, intersections and exports see only live
+ * entries; a long bucket touched by an erase loses its key runs and is
+ * scanned.  Cost: each key scans its bucket, then one pass over the buckets.
+ * Requires a V2 table built with the probe index (HG_ERR_INVALID_ARG
+ * otherwise); a rebuild starts from a full table again.  h_removed (may be
+ * NULL) gets the number of entries removed; waits for the stream.  The first
+ * erase allocates the length array and 1 byte per bucket and per entry of
+ * scratch flags. */
+hg_status hg_table_erase(hg_table *t, const void *d_keys, uint64_t m, uint64_t *h_removed,
+                         hipStream_t stream);
+
+/* After an erase: *d_lengths (may be NULL) = device pointer to the per-bucket
+ * live lengths (V uint32), or NULL if the table has not been erased since its
+ * build; *live (may be NULL) = the number of live entries (n when never
+ * erased).  hg_table_view's d_offsets then give each bucket's first slot, its
+ * d_ids / d_keys hold stale copies behind each bucket's live entries, and its
+ * n stays the number of entries built (the range of ids; size
+ * hg_intersect's per-B-entry counts by it). */
+hg_status hg_table_lengths(const hg_table *t, const uint32_t **d_lengths, uint64_t *live);
 
 /* Release a table (waits for the device to finish using it).  NULL is a
  * no-op. */

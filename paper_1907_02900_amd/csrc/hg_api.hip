@@ -29,6 +29,12 @@ struct hg_table {
     uint64_t long_cap = 0;
     void* runs_ws = nullptr;  // workspace of the listing and the summary (grow-only)
     size_t runs_ws_bytes = 0;
+    // erasing keys: live entries per bucket, scratch flags, live entry count
+    uint32_t* len = nullptr;   // [V_cap]
+    uint8_t* dead = nullptr;   // [n_cap]
+    uint8_t* touched = nullptr;  // [V_cap]
+    bool has_len = false;
+    uint64_t live = 0;
     RunsDev runs{};
     uint64_t runs_cap = 0;          // runs the run arrays hold (kperm: n_cap)
     bool has_runs = false;
@@ -226,6 +232,8 @@ hg_status build_into(hg_table* t, const void* keys, uint64_t n, uint64_t V, uint
     t->variant = variant;
     t->has_head = want_head;
     t->has_runs = false;
+    t->has_len = false;
+    t->live = n;
     if (want_head) HG_CALL_ST(build_runs(t, ix, s));
     return HG_OK;
 }
@@ -268,6 +276,7 @@ TableDev dev_view(const hg_table* t) {
     d.seed = t->seed;
     d.head = t->has_head ? t->head : nullptr;
     if (t->has_head && t->has_runs) d.runs = t->runs;
+    if (t->has_len) d.len = t->len;
     return d;
 }
 
@@ -377,6 +386,21 @@ hg_status hg_table_view(const hg_table* t, hg_table_info* info) {
 hg_status hg_table_export(const hg_table* t, uint32_t* d_offsets, uint32_t* d_ids, void* d_keys,
                           hipStream_t stream) {
     if (!t || t->V == 0) return HG_ERR_INVALID_ARG;
+    if (t->has_len) {
+        // compacted CSR of the live entries
+        Scratch ws(stream);
+        HG_CALL(ws.get(align_up((t->V + 1) * 4, 256) + scan_ws_bytes(t->V)));
+        Carver c(ws.p);
+        uint32_t* own = c.take<uint32_t>(t->V + 1);
+        uint32_t* off = d_offsets ? d_offsets : own;
+        void* sws = c.take<char>(scan_ws_bytes(t->V));
+        HG_CALL(scan_excl<uint32_t>(t->len, t->V, off, nullptr, sws, stream));
+        const TableDev d = dev_view(t);
+        HG_CALL(t->key_bits == 32
+                    ? run_export_live<uint32_t>(d, t->len, off, d_ids, (uint32_t*)d_keys, stream)
+                    : run_export_live<uint64_t>(d, t->len, off, d_ids, (uint64_t*)d_keys, stream));
+        return HG_OK;
+    }
     if (d_offsets)
         HG_CALL(hipMemcpyAsync(d_offsets, t->offsets, (t->V + 1) * 4, hipMemcpyDeviceToDevice, stream));
     if (d_ids && t->n)
@@ -384,6 +408,48 @@ hg_status hg_table_export(const hg_table* t, uint32_t* d_offsets, uint32_t* d_id
     if (d_keys && t->n)
         HG_CALL(hipMemcpyAsync(d_keys, t->keys, t->n * key_size(t->key_bits),
                                hipMemcpyDeviceToDevice, stream));
+    return HG_OK;
+}
+
+hg_status hg_table_erase(hg_table* t, const void* d_keys, uint64_t m, uint64_t* h_removed,
+                         hipStream_t stream) {
+    if (!t || t->V == 0 || (m && !d_keys)) return HG_ERR_INVALID_ARG;
+    if (!t->has_head) return HG_ERR_INVALID_ARG;  // needs a V2 table with the probe index
+    if (device_ready() != HG_OK) return HG_ERR_DEVICE;
+    if (!t->len) {
+        HG_CALL(hipMalloc((void**)&t->len, t->V_cap * 4));
+        HG_CALL(hipMalloc((void**)&t->dead, t->n_cap ? t->n_cap : 1));
+        HG_CALL(hipMalloc((void**)&t->touched, t->V_cap));
+        t->bytes += t->V_cap * 5 + (t->n_cap ? t->n_cap : 1);
+        HG_CALL(hipMemsetAsync(t->dead, 0, t->n_cap ? t->n_cap : 1, stream));
+        HG_CALL(hipMemsetAsync(t->touched, 0, t->V_cap, stream));
+    }
+    if (!t->has_len) {
+        HG_CALL(init_lengths(t->offsets, t->V, t->len, stream));
+        t->has_len = true;
+    }
+    Scratch ws(stream);
+    HG_CALL(ws.get(256));
+    unsigned long long* d_removed = (unsigned long long*)ws.p;
+    HG_CALL(fill_u32((uint32_t*)d_removed, 2, 0u, stream));
+    const TableDev d = dev_view(t);
+    HG_CALL(t->key_bits == 32
+                ? run_erase<uint32_t>(d, t->len, t->dead, t->touched, t->head,
+                                      (const uint32_t*)d_keys, m, d_removed, stream)
+                : run_erase<uint64_t>(d, t->len, t->dead, t->touched, t->head,
+                                      (const uint64_t*)d_keys, m, d_removed, stream));
+    uint64_t removed = 0;
+    const hg_status st = read_u64((const uint64_t*)d_removed, &removed, stream);
+    if (st != HG_OK) return st;
+    t->live -= removed;
+    if (h_removed) *h_removed = removed;
+    return HG_OK;
+}
+
+hg_status hg_table_lengths(const hg_table* t, const uint32_t** d_lengths, uint64_t* live) {
+    if (!t || (!d_lengths && !live)) return HG_ERR_INVALID_ARG;
+    if (d_lengths) *d_lengths = t->has_len ? t->len : nullptr;
+    if (live) *live = t->live;
     return HG_OK;
 }
 
@@ -397,6 +463,9 @@ void hg_table_free(hg_table* t) {
     if (t->tally) (void)hipFree(t->tally);
     if (t->tally_pre) (void)hipFree(t->tally_pre);
     if (t->runs_ws) (void)hipFree(t->runs_ws);
+    if (t->len) (void)hipFree(t->len);
+    if (t->dead) (void)hipFree(t->dead);
+    if (t->touched) (void)hipFree(t->touched);
     if (t->runs.kperm) (void)hipFree(t->runs.kperm);
     if (t->runs.run_key) (void)hipFree(t->runs.run_key);
     if (t->runs.run_cnt) (void)hipFree(t->runs.run_cnt);

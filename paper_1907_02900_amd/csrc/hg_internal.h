@@ -172,7 +172,26 @@ struct TableDev {
     uint64_t n, V, seed;
     const uint4* head = nullptr;  // per-bucket probe index, when the build wrote one
     RunsDev runs{};               // key-run summary of long buckets (with head)
+    const uint32_t* len = nullptr;  // live entries per bucket, after an erase (n = slots)
 };
+
+// ---- erasing keys ----------------------------------------------------------
+// len[h] = offsets[h+1] - offsets[h]
+hipError_t init_lengths(const uint32_t* offsets, uint64_t V, uint32_t* len, hipStream_t s);
+
+// Remove every live entry whose key is one of del[0 .. m); dead and touched
+// are zeroed byte arrays of t.n and t.V entries (left zeroed); head is the
+// table's probe index; *d_removed (device, zeroed) gets the number removed.
+template <typename Key>
+hipError_t run_erase(const TableDev& t, uint32_t* len, uint8_t* dead, uint8_t* touched,
+                     uint4* head, const Key* del, uint64_t m, unsigned long long* d_removed,
+                     hipStream_t s);
+
+// Compacted ids / keys of the live entries at new_off (the exclusive scan of
+// len); either output may be null.
+template <typename Key>
+hipError_t run_export_live(const TableDev& t, const uint32_t* len, const uint32_t* new_off,
+                           uint32_t* out_ids, Key* out_keys, hipStream_t s);
 
 size_t probe_ws_bytes(uint64_t m);
 

@@ -103,6 +103,7 @@ __device__ __forceinline__ uint32_t count_with_head(const uint4& e, const Key* _
     using HK = HeadKeys<Key>;
     const uint32_t len = e.y - e.x;
     if (len > kRunBucket) {
+        if (e.z == ~0u) return count_in_bucket(ekeys, e.x, e.y, q);  // runs dropped by an erase
         const uint32_t r = find_run(runs.key, e.z, e.w, q);
         return r != ~0u ? runs.cnt[r] : 0u;
     }
@@ -184,8 +185,9 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_pairs(
         }
         const uint32_t lo = e.x, hi = e.y;
         uint64_t pos = positions[j];
-        if (HEAD && hi - lo > kRunBucket) {
-            // the ids of q's run, ascending
+        const bool longb = HEAD && hi - lo > kRunBucket;
+        if (longb && e.z != ~0u) {
+            // the ids of q's run, in bucket order
             const uint32_t r = find_run(runs.key, e.z, e.w, k);
             if (r != ~0u)
                 for (uint32_t t = runs.pos[r], te = t + runs.cnt[r]; t < te; ++t) {
@@ -196,7 +198,7 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_pairs(
             continue;
         }
         for (uint32_t p = lo; p < hi; ++p)
-            if ((HEAD && p - lo < HK::slots ? HK::key(e, p - lo) : ekeys[p]) == k) {
+            if ((HEAD && !longb && p - lo < HK::slots ? HK::key(e, p - lo) : ekeys[p]) == k) {
                 build_ids[pos] = eids[p];
                 probe_ids[pos] = (uint32_t)j;
                 ++pos;
@@ -210,12 +212,13 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_pairs(
 // long and A has them (a_head not null).
 template <typename Key>
 __device__ __forceinline__ uint32_t count_in_a(const uint32_t* __restrict__ a_off,
+                                               const uint32_t* __restrict__ a_len,
                                                const uint4* __restrict__ a_head,
                                                const Runs<Key>& runs,
                                                const Key* __restrict__ a_keys, uint32_t h,
                                                Key k) {
-    const uint32_t lo = a_off[h], hi = a_off[h + 1];
-    if (a_head && hi - lo > kRunBucket) {
+    const uint32_t lo = a_off[h], hi = a_len ? lo + a_len[h] : a_off[h + 1];
+    if (a_head && hi - lo > kRunBucket && a_head[h].z != ~0u) {
         const uint4 e = a_head[h];
         const uint32_t r = find_run(runs.key, e.z, e.w, k);
         return r != ~0u ? runs.cnt[r] : 0u;
@@ -223,13 +226,16 @@ __device__ __forceinline__ uint32_t count_in_a(const uint32_t* __restrict__ a_of
     return count_in_bucket(a_keys, lo, hi, k);
 }
 
+// B's stale slots (behind a bucket's live entries after an erase) are skipped:
+// they get edge count 0 and write no count by input.
 template <typename Key>
 __global__ __launch_bounds__(kProbeThreads) void k_intersect_count(
-    const uint32_t* __restrict__ a_off, const uint4* __restrict__ a_head, Runs<Key> runs,
-    const Key* __restrict__ a_keys, const Key* __restrict__ b_keys,
-    const uint32_t* __restrict__ b_ids, uint64_t nb, typename KeyTraits<Key>::Params hp,
-    uint32_t* __restrict__ edge_counts, uint32_t* __restrict__ counts_by_input,
-    unsigned long long* __restrict__ total) {
+    const uint32_t* __restrict__ a_off, const uint32_t* __restrict__ a_len,
+    const uint4* __restrict__ a_head, Runs<Key> runs, const Key* __restrict__ a_keys,
+    const uint32_t* __restrict__ b_off, const uint32_t* __restrict__ b_len,
+    const Key* __restrict__ b_keys, const uint32_t* __restrict__ b_ids, uint64_t nb,
+    typename KeyTraits<Key>::Params hp, uint32_t* __restrict__ edge_counts,
+    uint32_t* __restrict__ counts_by_input, unsigned long long* __restrict__ total) {
     __shared__ uint64_t red[kProbeThreads / kWave + 1];
     uint64_t sum = 0;
     const uint64_t base = (uint64_t)blockIdx.x * (kProbeThreads * kProbeItems) + threadIdx.x;
@@ -239,7 +245,11 @@ __global__ __launch_bounds__(kProbeThreads) void k_intersect_count(
         if (p < nb) {
             const Key k = b_keys[p];
             const uint32_t h = KeyTraits<Key>::bucket(k, hp);
-            const uint32_t c = count_in_a(a_off, a_head, runs, a_keys, h, k);
+            if (b_len && p - b_off[h] >= b_len[h]) {
+                if (edge_counts) edge_counts[p] = 0;
+                continue;
+            }
+            const uint32_t c = count_in_a(a_off, a_len, a_head, runs, a_keys, h, k);
             if (edge_counts) edge_counts[p] = c;
             if (counts_by_input) counts_by_input[b_ids[p]] = c;
             sum += c;
@@ -254,20 +264,23 @@ __global__ __launch_bounds__(kProbeThreads) void k_intersect_count(
 
 template <typename Key>
 __global__ __launch_bounds__(kProbeThreads) void k_intersect_pairs(
-    const uint32_t* __restrict__ a_off, const uint4* __restrict__ a_head, Runs<Key> runs,
-    const Key* __restrict__ a_keys, const uint32_t* __restrict__ a_ids,
-    const Key* __restrict__ b_keys, const uint32_t* __restrict__ b_ids, uint64_t nb,
-    typename KeyTraits<Key>::Params hp, const uint64_t* __restrict__ positions,
-    uint32_t* __restrict__ out_a, uint32_t* __restrict__ out_b) {
+    const uint32_t* __restrict__ a_off, const uint32_t* __restrict__ a_len,
+    const uint4* __restrict__ a_head, Runs<Key> runs, const Key* __restrict__ a_keys,
+    const uint32_t* __restrict__ a_ids, const uint32_t* __restrict__ b_off,
+    const uint32_t* __restrict__ b_len, const Key* __restrict__ b_keys,
+    const uint32_t* __restrict__ b_ids, uint64_t nb, typename KeyTraits<Key>::Params hp,
+    const uint64_t* __restrict__ positions, uint32_t* __restrict__ out_a,
+    uint32_t* __restrict__ out_b) {
     uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t st = (uint64_t)gridDim.x * blockDim.x;
     for (; p < nb; p += st) {
         const Key k = b_keys[p];
         const uint32_t h = KeyTraits<Key>::bucket(k, hp);
-        const uint32_t lo = a_off[h], hi = a_off[h + 1];
+        if (b_len && p - b_off[h] >= b_len[h]) continue;  // stale slot of B
+        const uint32_t lo = a_off[h], hi = a_len ? lo + a_len[h] : a_off[h + 1];
         const uint32_t bid = b_ids[p];
         uint64_t pos = positions[p];
-        if (a_head && hi - lo > kRunBucket) {
+        if (a_head && hi - lo > kRunBucket && a_head[h].z != ~0u) {
             const uint4 e = a_head[h];
             const uint32_t r = find_run(runs.key, e.z, e.w, k);
             if (r != ~0u)
@@ -350,9 +363,9 @@ hipError_t run_intersect_counts(const TableDev& a, const TableDev& b, uint32_t* 
     {
         HG_PROF("intersect_count", s);
         hipLaunchKernelGGL(k_intersect_count<Key>, dim3(grid_for(b.n, kProbeThreads * kProbeItems)),
-                           dim3(kProbeThreads), 0, s, a.offsets, a.head, runs_of<Key>(a),
-                           (const Key*)a.keys, (const Key*)b.keys, b.ids, b.n, hp, edge_counts,
-                           counts_by_input, d_total);
+                           dim3(kProbeThreads), 0, s, a.offsets, a.len, a.head, runs_of<Key>(a),
+                           (const Key*)a.keys, b.offsets, b.len, (const Key*)b.keys, b.ids, b.n,
+                           hp, edge_counts, counts_by_input, d_total);
     }
     return hipGetLastError();
 }
@@ -367,8 +380,8 @@ hipError_t run_intersect_pairs(const TableDev& a, const TableDev& b, const uint6
     {
         HG_PROF("intersect_pairs", s);
         hipLaunchKernelGGL(k_intersect_pairs<Key>, dim3(g), dim3(kProbeThreads), 0, s, a.offsets,
-                           a.head, runs_of<Key>(a), (const Key*)a.keys, a.ids, (const Key*)b.keys,
-                           b.ids, b.n, hp, positions, a_ids, b_ids);
+                           a.len, a.head, runs_of<Key>(a), (const Key*)a.keys, a.ids, b.offsets,
+                           b.len, (const Key*)b.keys, b.ids, b.n, hp, positions, a_ids, b_ids);
     }
     return hipGetLastError();
 }

@@ -76,6 +76,8 @@ def lib():
         "hg_probe": ([vp, vp, u64, vp, pu64, vp], i32),
         "hg_probe_pairs": ([vp, vp, u64, vp, vp, u64, pu64, vp], i32),
         "hg_intersect": ([vp, vp, vp, vp, vp, u64, pu64, vp], i32),
+        "hg_table_erase": ([vp, vp, u64, pu64, vp], i32),
+        "hg_table_lengths": ([vp, ctypes.POINTER(vp), pu64], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -208,13 +210,34 @@ class Table:
     def export(self, stream=None):
         """(offsets[V+1], ids[n], keys[n]) copied into new device tensors."""
         i = self.info()
+        n = self.live()
         off = _u32(i.hash_range + 1, self.device)
-        ids = _u32(i.n, self.device)
-        keys = torch.empty(int(i.n), dtype=torch.int64 if i.key_bits == 64 else torch.int32,
+        ids = _u32(n, self.device)
+        keys = torch.empty(n, dtype=torch.int64 if i.key_bits == 64 else torch.int32,
                            device=self.device)
         _check(lib().hg_table_export(self._h, _ptr(off), _ptr(ids), _ptr(keys), _stream(stream)),
                "hg_table_export")
         return off, ids, keys
+
+    def erase(self, keys: torch.Tensor, stream=None) -> int:
+        """Remove every entry whose key is in `keys`; returns how many."""
+        keys = _dev_keys(keys)
+        removed = ctypes.c_uint64(0)
+        _check(lib().hg_table_erase(self._h, _ptr(keys), keys.numel(), ctypes.byref(removed),
+                                    _stream(stream)), "hg_table_erase")
+        return int(removed.value)
+
+    def lengths(self):
+        """Device pointer (int) of the live bucket lengths after an erase, or None."""
+        p = ctypes.c_void_p()
+        _check(lib().hg_table_lengths(self._h, ctypes.byref(p), None), "hg_table_lengths")
+        return p.value
+
+    def live(self) -> int:
+        """Number of live entries (the built count until an erase)."""
+        n = ctypes.c_uint64(0)
+        _check(lib().hg_table_lengths(self._h, None, ctypes.byref(n)), "hg_table_lengths")
+        return int(n.value)
 
     def free(self):
         if self._h is not None and self._h.value:
