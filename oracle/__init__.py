@@ -162,3 +162,62 @@ def count_one(keys, q: int, key_bits=None) -> int:
     """Brute-force count of one query over all keys."""
     k, kb = _keys(keys, key_bits)
     return int(_load().orc_count_one(_p(k), k.size, kb, int(q) & 0xFFFFFFFFFFFFFFFF))
+
+
+# ---- collections of sets (build once, intersect many; Sec. 3.4) -------------
+
+
+def set_hash_range(n: int, shift: int = 0) -> int:
+    """Hash range of one set of a collection: the smallest power of two that
+    is >= max(n, 1), times 2**shift, clamped to [1, 2**31].  (A layout rule of
+    the collections, which the paper leaves open: powers of two let every
+    set's bucket be the low bits of the same hash.)"""
+    p = 1
+    while p < max(int(n), 1):
+        p *= 2
+    e = p.bit_length() - 1 + int(shift)
+    return 1 << min(max(e, 0), 31)
+
+
+def collection_table(keys, set_off, seed: int = 0, shift: int = 0, key_bits=None):
+    """Every set's stable table (build_table of its keys with range
+    set_hash_range(n_s, shift)), concatenated: returns (bucket_base[S+1],
+    offsets[sum V + 1], ids[n], keys[n]) where set s owns buckets
+    [bucket_base[s], bucket_base[s+1]), offsets are absolute positions and
+    ids are positions in the concatenated input."""
+    k, kb = _keys(keys, key_bits)
+    so = np.asarray(set_off, dtype=np.int64)
+    S = so.size - 1
+    ranges = [set_hash_range(so[s + 1] - so[s], shift) for s in range(S)]
+    bb = np.zeros(S + 1, dtype=np.uint64)
+    bb[1:] = np.cumsum(np.asarray(ranges, dtype=np.uint64))
+    off = np.empty(int(bb[-1]) + 1, dtype=np.uint32)
+    ids = np.empty(k.size, dtype=np.uint32)
+    ek = np.empty(k.size, dtype=k.dtype)
+    for s in range(S):
+        lo, hi = int(so[s]), int(so[s + 1])
+        o, i, e = build_table(k[lo:hi], ranges[s], seed, kb)
+        off[int(bb[s]):int(bb[s + 1])] = o[:-1] + lo
+        ids[lo:hi] = i + lo
+        ek[lo:hi] = e
+    off[-1] = k.size
+    return bb, off, ids, ek
+
+
+def pair_match_counts(keys_a, off_a, keys_b, off_b, pairs, key_bits=None):
+    """For each pair (i, j): the number of (x, y) with x an entry of set i of
+    a, y an entry of set j of b and equal keys (the join size of the two
+    sets), as the total of Probe-Standard counts of set j's keys against set
+    i's keys."""
+    ka, kb = _keys(keys_a, key_bits)
+    kbk, _ = _keys(keys_b, kb)
+    oa = np.asarray(off_a, dtype=np.int64)
+    ob = np.asarray(off_b, dtype=np.int64)
+    pr = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
+    out = np.zeros(pr.shape[0], dtype=np.uint64)
+    for q, (i, j) in enumerate(pr):
+        a = ka[oa[i]:oa[i + 1]]
+        b = kbk[ob[j]:ob[j + 1]]
+        if a.size and b.size:
+            out[q] = probe_counts(a, b, kb)[1]
+    return out

@@ -377,3 +377,83 @@ def test_property_build_and_probe_small(keys, queries, V, seed):
         b = oracle.bucket_one(int(x), V, seed)
         via_table.append(int(np.count_nonzero(ek[off[b]:off[b + 1]] == x)))
     assert c.tolist() == via_table
+
+
+# ---------------------------------------------------------------------------
+# Collections (build once, intersect many): the per-set hash range rule, the
+# concatenated tables against nested loops, and join sizes of set pairs
+# against brute force, symmetry and closed forms.
+# ---------------------------------------------------------------------------
+
+
+def test_set_hash_range_closed_forms():
+    assert [oracle.set_hash_range(n) for n in (0, 1, 2, 3, 4, 5, 8, 9, 1000, 1024, 1025)] == \
+        [1, 1, 2, 4, 4, 8, 8, 16, 1024, 1024, 2048]
+    assert oracle.set_hash_range(5, 1) == 16 and oracle.set_hash_range(5, -2) == 2
+    assert oracle.set_hash_range(5, -10) == 1 and oracle.set_hash_range(3, 40) == 2 ** 31
+    assert oracle.set_hash_range(2 ** 31 + 1) == 2 ** 31
+
+
+def brute_collection(keys, set_off, seed, shift, key_bits):
+    bb, off, ids = [0], [], []
+    for s in range(len(set_off) - 1):
+        lo, hi = set_off[s], set_off[s + 1]
+        p = 1
+        while p < max(hi - lo, 1):
+            p *= 2
+        V = min(max(p * 2 ** shift if shift >= 0 else p // 2 ** -shift, 1), 2 ** 31)
+        for x in range(V):
+            off.append(len(ids))
+            ids.extend(i for i in range(lo, hi)
+                       if oracle.bucket_one(int(keys[i]), V, seed, key_bits) == x)
+        bb.append(bb[-1] + V)
+    off.append(len(ids))
+    return bb, off, ids
+
+
+@pytest.mark.parametrize("shift", [0, 1, -1])
+@pytest.mark.parametrize("key_bits", [32, 64])
+def test_collection_table_matches_nested_loops(shift, key_bits):
+    rng = np.random.default_rng(3 + shift)
+    sizes = [0, 1, 5, 0, 17, 2, 40, 3]
+    set_off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    keys = rng.integers(0, 30, set_off[-1]).astype(np.uint64 if key_bits == 64 else np.uint32)
+    if key_bits == 64:
+        keys = keys | (np.uint64(7) << np.uint64(40))
+    bb, off, ids, ek = oracle.collection_table(keys, set_off, seed=11, shift=shift)
+    e_bb, e_off, e_ids = brute_collection(keys, set_off.tolist(), 11, shift, key_bits)
+    assert bb.tolist() == e_bb and off.tolist() == e_off and ids.tolist() == e_ids
+    assert ek.tolist() == [int(keys[i]) for i in e_ids]
+
+
+def brute_join(a, b):
+    return sum(1 for x in a for y in b if int(x) == int(y))
+
+
+@pytest.mark.parametrize("key_bits", [32, 64])
+def test_pair_match_counts_brute_force_and_closed_forms(key_bits):
+    rng = np.random.default_rng(9)
+    dt = np.uint64 if key_bits == 64 else np.uint32
+    sizes = [0, 3, 12, 30, 1, 25]
+    oa = np.concatenate([[0], np.cumsum(sizes)])
+    ka = rng.integers(0, 15, oa[-1]).astype(dt)
+    sizes_b = [7, 0, 40]
+    ob = np.concatenate([[0], np.cumsum(sizes_b)])
+    kb = rng.integers(5, 25, ob[-1]).astype(dt)
+    pairs = [(i, j) for i in range(len(sizes)) for j in range(len(sizes_b))]
+    got = oracle.pair_match_counts(ka, oa, kb, ob, pairs)
+    assert got.tolist() == [brute_join(ka[oa[i]:oa[i + 1]], kb[ob[j]:ob[j + 1]]) for i, j in pairs]
+    # symmetric, and a set with itself gives the sum of squared multiplicities
+    back = oracle.pair_match_counts(kb, ob, ka, oa, [(j, i) for i, j in pairs])
+    assert np.array_equal(back, got)
+    self_pairs = [(i, i) for i in range(len(sizes))]
+    sq = [int((np.unique(ka[oa[i]:oa[i + 1]], return_counts=True)[1].astype(np.int64) ** 2).sum())
+          for i in range(len(sizes))]
+    assert oracle.pair_match_counts(ka, oa, ka, oa, self_pairs).tolist() == sq
+    # sets without repeats: the size of the intersection
+    da = np.unique(ka[oa[3]:oa[4]])
+    db = np.unique(kb[ob[2]:ob[3]])
+    both = np.concatenate([da, db])
+    c = oracle.pair_match_counts(both, [0, da.size, both.size], both, [0, da.size, both.size],
+                                 [(0, 1)])
+    assert int(c[0]) == np.intersect1d(da, db).size
