@@ -240,6 +240,84 @@ hg_status hg_intersect(const hg_table *a, const hg_table *b, uint32_t *d_counts_
                        uint64_t *h_total, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Collections: build once, intersect many (Sec. 3.4).  Probe-New pays for a
+ * second table; in sparse products that cost is amortised, because the table
+ * of every row or column is built once and takes part in many
+ * intersections.  A collection holds S key sets, each with its own table;
+ * hg_collection_intersect then counts the matches of many (set, set) pairs.
+ *
+ * Layout.  Set s is d_keys[set_offsets[s] .. set_offsets[s+1]) with n_s keys.
+ * Its hash range V_s is a power of two: the smallest one >= max(n_s, 1),
+ * times 2^range_shift, clamped to [1, 2^31]; its buckets use the hash of
+ * Eq. 1 (fmix32 / fmix64 of key ^ seed, low bits).  The tables are
+ * concatenated: set s owns buckets [bucket_base[s], bucket_base[s+1]) of one
+ * offsets array, whose entries are absolute positions in the shared ids and
+ * keys arrays, and its entries fill [set_offsets[s], set_offsets[s+1]) of
+ * them, grouped by bucket with ids ascending inside a bucket.  Ids are
+ * positions in the concatenated input.  Set s's table is thus the stable
+ * HashGraph of its keys with range V_s (Alg. 2), its offsets and ids shifted
+ * by set_offsets[s].
+ * ------------------------------------------------------------------------ */
+
+typedef struct hg_collection hg_collection; /* opaque; owns its device arrays */
+
+typedef struct hg_collection_info {
+    uint32_t sets;                 /* S                                          */
+    int32_t key_bits;              /* 32 or 64                                   */
+    uint64_t seed;                 /* hash seed                                  */
+    int32_t range_shift;           /* see the layout above                       */
+    uint32_t reserved;
+    uint64_t n;                    /* entries, set_offsets[S]                    */
+    uint64_t buckets;              /* sum of V_s                                 */
+    uint64_t heavy_keys;           /* entries of the sets built by the sort path */
+    uint64_t bytes;                /* device bytes the collection holds          */
+    const uint32_t *d_set_offsets; /* S + 1 (a copy of the input's)              */
+    const uint64_t *d_bucket_base; /* S + 2; bucket_base[S] = bucket_base[S+1] = buckets */
+    const uint32_t *d_offsets;     /* buckets + 1                                */
+    const uint32_t *d_ids;         /* n                                          */
+    const void *d_keys;            /* n keys of key_bits                         */
+} hg_collection_info;
+
+/* Build every set's table.  d_keys: set_offsets[S] device keys of key_bits;
+ * d_set_offsets: S + 1 device uint32, set_offsets[0] = 0, non-decreasing
+ * (checked on the device: HG_ERR_INVALID_ARG otherwise, nothing kept).
+ * range_shift in [-31, 31]; HG_ERR_INVALID_ARG if the total of the V_s
+ * reaches 2^32 - 1.  Sets of a few thousand keys or fewer are built in LDS,
+ * several per workgroup; heavier sets together by one radix sort.  Allocates
+ * the collection (4 (buckets + 1) + (4 + key_bits / 8) n + 12 (S + 2) bytes)
+ * and workspace; waits for the stream.  The input may be freed afterwards. */
+hg_status hg_collection_build(const void *d_keys, const uint32_t *d_set_offsets, uint32_t sets,
+                              int key_bits, uint64_t seed, int32_t range_shift,
+                              hg_collection **out, hipStream_t stream);
+
+/* Describe a collection: its sizes and device pointers to its arrays. */
+hg_status hg_collection_view(const hg_collection *c, hg_collection_info *info);
+
+/* Copy the collection's arrays into caller buffers (device to device, on the
+ * stream): d_bucket_base S + 2 uint64, d_offsets buckets + 1 uint32, d_ids n
+ * uint32, d_keys n keys.  Any of them may be NULL to skip it. */
+hg_status hg_collection_export(const hg_collection *c, uint64_t *d_bucket_base,
+                               uint32_t *d_offsets, uint32_t *d_ids, void *d_keys,
+                               hipStream_t stream);
+
+/* Match counts of set pairs: for q < pairs, with (i, j) = (d_pairs[2q],
+ * d_pairs[2q+1]) naming set i of a and set j of b, d_counts[q] (uint64, may
+ * be NULL) = the number of (x, y) with x an entry of a's set i, y an entry of
+ * b's set j and equal keys (the join size; for sets without repeated keys,
+ * the size of their intersection).  The smaller set of each pair is walked in
+ * its table's order and looked up in the other's buckets.  a and b may be the
+ * same collection; they must share key_bits and seed (HG_ERR_MISMATCH).  An
+ * index out of range gives HG_ERR_INVALID_ARG (counts then unspecified).
+ * h_total (may be NULL) receives the sum over all pairs.  Waits for the
+ * stream (the pair work is sized on the host). */
+hg_status hg_collection_intersect(const hg_collection *a, const hg_collection *b,
+                                  const uint32_t *d_pairs, uint64_t pairs, uint64_t *d_counts,
+                                  uint64_t *h_total, hipStream_t stream);
+
+/* Release a collection (waits for the device).  NULL is a no-op. */
+void hg_collection_free(hg_collection *c);
+
+/* ------------------------------------------------------------------------
  * Batched build + probe: many independent tables in one hipGraph launch.
  * Each table is built exactly as hg_build builds it with the V2 variant (the
  * stable layout of Alg. 2) into the caller's output arrays, then probed as

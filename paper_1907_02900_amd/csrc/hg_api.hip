@@ -453,6 +453,155 @@ hg_status hg_table_lengths(const hg_table* t, const uint32_t** d_lengths, uint64
     return HG_OK;
 }
 
+struct hg_collection {
+    int key_bits = 32;
+    uint64_t seed = 0;
+    int32_t shift = 0;
+    uint32_t S = 0;
+    uint64_t n = 0, buckets = 0, heavy_keys = 0, bytes = 0;
+    uint32_t* set_off = nullptr;
+    uint64_t* bb = nullptr;
+    uint32_t* offsets = nullptr;
+    uint32_t* ids = nullptr;
+    void* keys = nullptr;
+};
+
+namespace {
+
+void coll_release(hg_collection* c) {
+    if (c->set_off) (void)hipFree(c->set_off);
+    if (c->bb) (void)hipFree(c->bb);
+    if (c->offsets) (void)hipFree(c->offsets);
+    if (c->ids) (void)hipFree(c->ids);
+    if (c->keys) (void)hipFree(c->keys);
+    delete c;
+}
+
+hg_status coll_build_into(hg_collection* c, const void* d_keys, const uint32_t* d_set_offsets,
+                          hipStream_t stream) {
+    const uint32_t S = c->S;
+    HG_CALL(hipMalloc((void**)&c->set_off, ((uint64_t)S + 1) * 4));
+    HG_CALL(hipMalloc((void**)&c->bb, ((uint64_t)S + 2) * 8));
+    HG_CALL(hipMemcpyAsync(c->set_off, d_set_offsets, ((uint64_t)S + 1) * 4,
+                           hipMemcpyDeviceToDevice, stream));
+    Scratch pws(stream);
+    HG_CALL(pws.get(coll_plan_ws_bytes(S)));
+    CollPlan plan{};
+    HG_CALL(coll_plan(c->set_off, S, c->shift, pws.p, c->bb, &plan, stream));
+    if (plan.bad || plan.buckets >= kU32Max || (plan.n && !d_keys)) return HG_ERR_INVALID_ARG;
+    c->n = plan.n;
+    c->buckets = plan.buckets;
+    c->heavy_keys = plan.big_keys;
+    const size_t ks = key_size(c->key_bits);
+    HG_CALL(hipMalloc((void**)&c->offsets, (plan.buckets + 1) * 4));
+    HG_CALL(hipMalloc((void**)&c->ids, (plan.n ? plan.n : 1) * 4));
+    HG_CALL(hipMalloc(&c->keys, (plan.n ? plan.n : 1) * ks));
+    c->bytes = ((uint64_t)S + 1) * 4 + ((uint64_t)S + 2) * 8 + (plan.buckets + 1) * 4 +
+               plan.n * (4 + ks);
+    Scratch bws(stream);
+    HG_CALL(bws.get(coll_build_ws_bytes(plan, c->key_bits)));
+    bool bad = false;
+    HG_CALL(c->key_bits == 32
+                ? run_coll_build<uint32_t>((const uint32_t*)d_keys, c->set_off, S, c->seed, c->bb,
+                                           plan, bws.p, c->offsets, c->ids, (uint32_t*)c->keys,
+                                           &bad, stream)
+                : run_coll_build<uint64_t>((const uint64_t*)d_keys, c->set_off, S, c->seed, c->bb,
+                                           plan, bws.p, c->offsets, c->ids, (uint64_t*)c->keys,
+                                           &bad, stream));
+    return bad ? HG_ERR_DEVICE : HG_OK;
+}
+
+CollDev coll_view(const hg_collection* c) {
+    return CollDev{c->set_off, c->bb, c->offsets, c->ids, c->keys, c->S};
+}
+
+}  // namespace
+
+hg_status hg_collection_build(const void* d_keys, const uint32_t* d_set_offsets, uint32_t sets,
+                              int key_bits, uint64_t seed, int32_t range_shift,
+                              hg_collection** out, hipStream_t stream) {
+    if (!out) return HG_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!d_set_offsets || !valid_kb(key_bits) || range_shift < -31 || range_shift > 31 ||
+        sets >= 0xfffffffeu)
+        return HG_ERR_INVALID_ARG;
+    if (device_ready() != HG_OK) return HG_ERR_DEVICE;
+    hg_collection* c = new (std::nothrow) hg_collection();
+    if (!c) return HG_ERR_OOM;
+    c->key_bits = key_bits;
+    c->seed = seed;
+    c->shift = range_shift;
+    c->S = sets;
+    const hg_status st = coll_build_into(c, d_keys, d_set_offsets, stream);
+    if (st != HG_OK) {
+        (void)hipStreamSynchronize(stream);
+        coll_release(c);
+        return st;
+    }
+    *out = c;
+    return HG_OK;
+}
+
+hg_status hg_collection_view(const hg_collection* c, hg_collection_info* info) {
+    if (!c || !info) return HG_ERR_INVALID_ARG;
+    *info = hg_collection_info{};
+    info->sets = c->S;
+    info->key_bits = c->key_bits;
+    info->seed = c->seed;
+    info->range_shift = c->shift;
+    info->n = c->n;
+    info->buckets = c->buckets;
+    info->heavy_keys = c->heavy_keys;
+    info->bytes = c->bytes;
+    info->d_set_offsets = c->set_off;
+    info->d_bucket_base = c->bb;
+    info->d_offsets = c->offsets;
+    info->d_ids = c->ids;
+    info->d_keys = c->keys;
+    return HG_OK;
+}
+
+hg_status hg_collection_export(const hg_collection* c, uint64_t* d_bucket_base,
+                               uint32_t* d_offsets, uint32_t* d_ids, void* d_keys,
+                               hipStream_t stream) {
+    if (!c) return HG_ERR_INVALID_ARG;
+    if (device_ready() != HG_OK) return HG_ERR_DEVICE;
+    const hipMemcpyKind k = hipMemcpyDeviceToDevice;
+    if (d_bucket_base)
+        HG_CALL(hipMemcpyAsync(d_bucket_base, c->bb, ((uint64_t)c->S + 2) * 8, k, stream));
+    if (d_offsets) HG_CALL(hipMemcpyAsync(d_offsets, c->offsets, (c->buckets + 1) * 4, k, stream));
+    if (d_ids && c->n) HG_CALL(hipMemcpyAsync(d_ids, c->ids, c->n * 4, k, stream));
+    if (d_keys && c->n)
+        HG_CALL(hipMemcpyAsync(d_keys, c->keys, c->n * key_size(c->key_bits), k, stream));
+    return HG_OK;
+}
+
+hg_status hg_collection_intersect(const hg_collection* a, const hg_collection* b,
+                                  const uint32_t* d_pairs, uint64_t pairs, uint64_t* d_counts,
+                                  uint64_t* h_total, hipStream_t stream) {
+    if (!a || !b || (pairs && !d_pairs) || (!d_counts && !h_total)) return HG_ERR_INVALID_ARG;
+    if (a->key_bits != b->key_bits || a->seed != b->seed) return HG_ERR_MISMATCH;
+    if (device_ready() != HG_OK) return HG_ERR_DEVICE;
+    if (h_total) *h_total = 0;
+    Scratch ws(stream);
+    HG_CALL(ws.get(coll_pairs_ws_bytes(pairs)));
+    bool bad = false;
+    HG_CALL(a->key_bits == 32
+                ? run_coll_intersect<uint32_t>(coll_view(a), coll_view(b), a->seed, d_pairs, pairs,
+                                               (unsigned long long*)d_counts, h_total, ws.p, &bad,
+                                               stream)
+                : run_coll_intersect<uint64_t>(coll_view(a), coll_view(b), a->seed, d_pairs, pairs,
+                                               (unsigned long long*)d_counts, h_total, ws.p, &bad,
+                                               stream));
+    return bad ? HG_ERR_INVALID_ARG : HG_OK;
+}
+
+void hg_collection_free(hg_collection* c) {
+    if (!c) return;
+    (void)hipDeviceSynchronize();
+    coll_release(c);
+}
+
 void hg_table_free(hg_table* t) {
     if (!t) return;
     if (t->offsets) (void)hipFree(t->offsets);

@@ -217,4 +217,39 @@ template <typename Key>
 hipError_t run_intersect_pairs(const TableDev& a, const TableDev& b, const uint64_t* positions,
                                uint32_t* a_ids, uint32_t* b_ids, hipStream_t s);
 
+// ---- collections: many small tables built once, intersected many times ----
+
+// Device view of a collection (every pointer device memory).
+struct CollDev {
+    const uint32_t* set_off;  // S + 1 entry offsets of the sets
+    const uint64_t* bb;       // S + 2 bucket bases (bb[S] = bb[S+1] = total buckets)
+    const uint32_t* offsets;  // total buckets + 1
+    const uint32_t* ids;
+    const void* keys;
+    uint32_t S;
+};
+
+// Sizes decided on the device, read back by coll_plan.
+struct CollPlan {
+    uint64_t *cw, *cb, *cv;  // S + 2 entries each, in the plan workspace
+    uint64_t n, buckets, weight, big_keys, big_buckets;
+    bool bad;  // set_off not a valid non-decreasing offset array from 0
+};
+
+size_t coll_plan_ws_bytes(uint32_t S);
+// bb: S + 2 entries, receives the bucket bases; waits for the device.
+hipError_t coll_plan(const uint32_t* set_off, uint32_t S, int shift, void* ws, uint64_t* bb,
+                     CollPlan* plan, hipStream_t s);
+size_t coll_build_ws_bytes(const CollPlan& p, int key_bits);
+template <typename Key>
+hipError_t run_coll_build(const Key* keys, const uint32_t* set_off, uint32_t S, uint64_t seed,
+                          const uint64_t* bb, const CollPlan& p, void* ws, uint32_t* offsets,
+                          uint32_t* ids, Key* ekeys, bool* bad, hipStream_t s);
+size_t coll_pairs_ws_bytes(uint64_t Q);
+// counts (Q entries) and h_total may be null; *bad when a pair index is out of range.
+template <typename Key>
+hipError_t run_coll_intersect(const CollDev& a, const CollDev& b, uint64_t seed,
+                              const uint32_t* pairs, uint64_t Q, unsigned long long* counts,
+                              uint64_t* h_total, void* ws, bool* bad, hipStream_t s);
+
 }  // namespace hg

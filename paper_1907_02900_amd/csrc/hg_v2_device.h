@@ -243,7 +243,7 @@ __device__ __forceinline__ uint32_t scan_counts_max(uint32_t* cnt, uint32_t NB, 
 
 // LDS bytes of light_bin_body / heavy_bin_body for 2^k buckets per bin.
 template <typename Key>
-inline size_t light_smem(uint32_t k) {
+__host__ __device__ inline size_t light_smem(uint32_t k) {
     const size_t NB = 1u << k;
     return kLightCap * (sizeof(Key) + 4 + 2) + NB * 4 + W_LOCAL * 64 * 4 + 64 * 4 +
            (2 * W_LOCAL + 2) * 4 + 64;
@@ -310,17 +310,18 @@ __device__ __forceinline__ void put_tally(const IndexOut& ix, uint32_t g, uint32
 // bucket (skipped with any_order: order inside a bucket is then unspecified).
 // Otherwise the bin (in id order) is stably ranked by local bucket.
 // When ix.head is not null it also receives each bucket's probe index entry.
+// `bucket_of(key, e)` gives the local bucket (< nb) of entry e.
 // Called by a whole workgroup of kLocalThreads threads.
-template <typename Key>
-__device__ __forceinline__ void light_bin_body(const Key* __restrict__ src_keys,
-                                               const uint32_t* __restrict__ src_ids,
-                                               uint32_t id_base, uint32_t L, uint32_t out,
-                                               uint32_t v0, uint32_t k, uint32_t nb,
-                                               const typename KeyTraits<Key>::Params& hp,
-                                               uint32_t* __restrict__ offsets,
-                                               const IndexOut& ix,
-                                               uint32_t* __restrict__ ids, Key* __restrict__ ekeys,
-                                               unsigned char* smem, bool any_order = false) {
+template <typename Key, typename BucketOf>
+__device__ __forceinline__ void light_bin_body_by(const Key* __restrict__ src_keys,
+                                                  const uint32_t* __restrict__ src_ids,
+                                                  uint32_t id_base, uint32_t L, uint32_t out,
+                                                  uint32_t v0, uint32_t k, uint32_t nb,
+                                                  BucketOf bucket_of,
+                                                  uint32_t* __restrict__ offsets,
+                                                  const IndexOut& ix, uint32_t* __restrict__ ids,
+                                                  Key* __restrict__ ekeys, unsigned char* smem,
+                                                  bool any_order) {
     constexpr int IT = kLightItems;
     const uint32_t NB = 1u << k;
     Key* skeys = (Key*)smem;
@@ -356,7 +357,7 @@ __device__ __forceinline__ void light_bin_body(const Key* __restrict__ src_keys,
 #pragma unroll
     for (int r = 0; r < IT; ++r) {
         if ((uint32_t)r < rounds && r * kWave + lane < mylen) {
-            b[r] = KeyTraits<Key>::bucket(kk[r], hp) - v0;
+            b[r] = bucket_of(kk[r], wb + r * kWave + lane);
             atomicAdd(&cnt[b[r]], 1u);
         } else {
             b[r] = NB;
@@ -413,6 +414,23 @@ __device__ __forceinline__ void light_bin_body(const Key* __restrict__ src_keys,
         ekeys[out + p] = skeys[p];
         ids[out + p] = sids[p];
     }
+}
+
+// The usual bin: buckets [v0, v0 + nb) of the table's hash function.
+template <typename Key>
+__device__ __forceinline__ void light_bin_body(const Key* __restrict__ src_keys,
+                                               const uint32_t* __restrict__ src_ids,
+                                               uint32_t id_base, uint32_t L, uint32_t out,
+                                               uint32_t v0, uint32_t k, uint32_t nb,
+                                               const typename KeyTraits<Key>::Params& hp,
+                                               uint32_t* __restrict__ offsets,
+                                               const IndexOut& ix,
+                                               uint32_t* __restrict__ ids, Key* __restrict__ ekeys,
+                                               unsigned char* smem, bool any_order = false) {
+    light_bin_body_by<Key>(
+        src_keys, src_ids, id_base, L, out, v0, k, nb,
+        [&](Key key, uint32_t) { return KeyTraits<Key>::bucket(key, hp) - v0; }, offsets, ix, ids,
+        ekeys, smem, any_order);
 }
 
 // Pointers into the heavy_smem layout.

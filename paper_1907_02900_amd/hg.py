@@ -314,6 +314,110 @@ def hg_intersect(a: Table, b: Table, counts=True, total=True, capacity=0, stream
     return c, None, None, t
 
 
+# ------------------------------------------------------------ collections ---
+
+class CollectionInfo(ctypes.Structure):
+    _fields_ = [("sets", ctypes.c_uint32), ("key_bits", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("range_shift", ctypes.c_int32),
+                ("reserved", ctypes.c_uint32), ("n", ctypes.c_uint64),
+                ("buckets", ctypes.c_uint64), ("heavy_keys", ctypes.c_uint64),
+                ("bytes", ctypes.c_uint64), ("d_set_offsets", ctypes.c_void_p),
+                ("d_bucket_base", ctypes.c_void_p), ("d_offsets", ctypes.c_void_p),
+                ("d_ids", ctypes.c_void_p), ("d_keys", ctypes.c_void_p)]
+
+
+def _coll_sig():
+    L = lib()
+    if getattr(L, "_coll_sig", False):
+        return L
+    vp, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
+    L.hg_collection_build.argtypes = [vp, vp, u32, i32, u64, ctypes.c_int32,
+                                      ctypes.POINTER(vp), vp]
+    L.hg_collection_build.restype = i32
+    L.hg_collection_view.argtypes = [vp, ctypes.POINTER(CollectionInfo)]
+    L.hg_collection_view.restype = i32
+    L.hg_collection_intersect.argtypes = [vp, vp, vp, u64, vp, ctypes.POINTER(ctypes.c_uint64),
+                                          vp]
+    L.hg_collection_intersect.restype = i32
+    L.hg_collection_export.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.hg_collection_export.restype = i32
+    L.hg_collection_free.argtypes = [vp]
+    L.hg_collection_free.restype = None
+    L._coll_sig = True
+    return L
+
+
+class Collection:
+    """Many key sets, each with its own table, built once (hg_collection_build).
+
+    keys: device tensor of all sets' keys, concatenated; set_offsets: device
+    int32 tensor of S + 1 offsets (set s = keys[set_offsets[s]:set_offsets[s+1]])."""
+
+    def __init__(self, keys: torch.Tensor, set_offsets: torch.Tensor, seed: int = 0,
+                 range_shift: int = 0, stream=None):
+        keys = _dev_keys(keys)
+        if set_offsets.dtype not in (torch.int32, torch.uint32) or not set_offsets.is_cuda:
+            raise ValueError("set_offsets must be a 32-bit device tensor")
+        set_offsets = set_offsets.contiguous()
+        self.device = keys.device
+        self._h = ctypes.c_void_p()
+        S = set_offsets.numel() - 1
+        if S < 0:
+            raise ValueError("set_offsets needs at least one entry")
+        _check(_coll_sig().hg_collection_build(
+            _ptr(keys), ctypes.c_void_p(set_offsets.data_ptr()), S, _key_bits(keys),
+            int(seed) & 0xFFFFFFFFFFFFFFFF, int(range_shift), ctypes.byref(self._h),
+            _stream(stream)), "hg_collection_build")
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> CollectionInfo:
+        i = CollectionInfo()
+        _check(_coll_sig().hg_collection_view(self._h, ctypes.byref(i)), "hg_collection_view")
+        return i
+
+    def arrays(self, stream=None):
+        """Device copies (hg_collection_export): (bucket_base int64[S+2],
+        offsets int32[buckets+1], ids int32[n], keys[n])."""
+        i = self.info()
+        kdt = torch.int64 if i.key_bits == 64 else torch.int32
+        bb = torch.empty(i.sets + 2, dtype=torch.int64, device=self.device)
+        off = torch.empty(i.buckets + 1, dtype=torch.int32, device=self.device)
+        ids = torch.empty(i.n, dtype=torch.int32, device=self.device)
+        ek = torch.empty(i.n, dtype=kdt, device=self.device)
+        _check(_coll_sig().hg_collection_export(self._h, _ptr(bb), _ptr(off), _ptr(ids), _ptr(ek),
+                                                _stream(stream)), "hg_collection_export")
+        return bb, off, ids, ek
+
+    def intersect(self, other: "Collection", pairs: torch.Tensor, counts=True, total=True,
+                  stream=None):
+        """Join sizes of (set i of self, set j of other) for each row (i, j) of
+        pairs (device int32 [Q, 2]).  Returns (counts int64[Q] or None, total or None)."""
+        if pairs.dtype not in (torch.int32, torch.uint32) or not pairs.is_cuda:
+            raise ValueError("pairs must be a 32-bit device tensor")
+        pairs = pairs.contiguous()
+        Q = pairs.numel() // 2
+        c = torch.empty(Q, dtype=torch.int64, device=self.device) if counts else None
+        tot = ctypes.c_uint64(0)
+        _check(_coll_sig().hg_collection_intersect(
+            self._h, other._h, _ptr(pairs), Q, _ptr(c),
+            ctypes.byref(tot) if total else None, _stream(stream)), "hg_collection_intersect")
+        return c, (int(tot.value) if total else None)
+
+    def free(self):
+        if self._h is not None and self._h.value:
+            _coll_sig().hg_collection_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
 # ------------------------------------------------------------ measurement ---
 
 def _prof_sig():

@@ -12,7 +12,9 @@ Shapes (see Sec. 4 "Input sizes & Key Distribution" and Sec. 5):
     average (the duplicate-key experiments of Sec. 5.1),
   * bounded Zipf keys (heavy skew, many keys per bucket),
   * probe sets with a given fraction drawn from the build keys,
-  * size mixes for batched tables and a Poisson request stream for serving.
+  * size mixes for batched tables and a Poisson request stream for serving,
+  * collections of sets with power-law sizes (rows of a sparse matrix) and
+    random set pairs, for build-once / intersect-many (Sec. 3.4).
 """
 from __future__ import annotations
 
@@ -148,3 +150,29 @@ def serving_stream(requests: int, rate_per_s: float, build_fraction: float = 0.3
     size = np.where(is_build, bsz, psz)
     data_seed = rng.integers(0, 1 << 40, size=r, dtype=np.int64)
     return arrival, is_build, size, data_seed
+
+
+def collection_sets(sets: int, mean_size: float, key_range: int, key_bits: int = 32,
+                    seed: int = 0, tail: float = 1.5, max_size: int = 1 << 16):
+    """`sets` key sets shaped like the rows of a sparse matrix: sizes from a
+    Pareto (Lomax) law with tail exponent `tail`, mean about `mean_size`,
+    clipped to [1, max_size]; keys (column indices) uniform in [0, key_range),
+    drawn independently, so a set may repeat a key (rarely, for sets much
+    smaller than key_range).  Returns (keys, offsets int64[sets + 1])."""
+    r = _rng(seed)
+    scale = max(mean_size - 1.0, 0.0) * (tail - 1.0)
+    sizes = np.minimum(1 + np.floor(r.pareto(tail, sets) * scale), max_size).astype(np.int64)
+    off = np.zeros(sets + 1, dtype=np.int64)
+    np.cumsum(sizes, out=off[1:])
+    keys = r.integers(0, key_range, int(off[-1]), dtype=np.uint64)
+    return keys.astype(_dtype(key_bits)), off
+
+
+def set_pairs(count: int, sets_a: int, sets_b: int, seed: int = 0) -> np.ndarray:
+    """`count` uniformly random (i, j) pairs, i < sets_a, j < sets_b, as
+    uint32[count, 2]."""
+    r = _rng(seed)
+    p = np.empty((count, 2), dtype=np.uint32)
+    p[:, 0] = r.integers(0, max(sets_a, 1), count)
+    p[:, 1] = r.integers(0, max(sets_b, 1), count)
+    return p

@@ -69,6 +69,18 @@ def test_invalid_arguments_rejected_on_host(lib):
     assert lib.hg_probe(None, dummy, 5, dummy, None, None) == 1
     lib.hg_intersect.argtypes = [vp, vp, vp, vp, vp, ctypes.c_uint64, vp, vp]
     assert lib.hg_intersect(None, None, None, None, None, 0, None, None) == 1
+    lib.hg_collection_build.argtypes = [vp, vp, ctypes.c_uint32, ctypes.c_int, ctypes.c_uint64,
+                                        ctypes.c_int32, ctypes.POINTER(vp), vp]
+    assert lib.hg_collection_build(dummy, dummy, 4, 32, 0, 0, None, None) == 1   # no out
+    assert lib.hg_collection_build(dummy, None, 4, 32, 0, 0, ctypes.byref(out), None) == 1
+    assert lib.hg_collection_build(dummy, dummy, 4, 16, 0, 0, ctypes.byref(out), None) == 1
+    assert lib.hg_collection_build(dummy, dummy, 4, 32, 0, 32, ctypes.byref(out), None) == 1
+    assert lib.hg_collection_build(dummy, dummy, 0xFFFFFFFE, 32, 0, 0, ctypes.byref(out),
+                                   None) == 1
+    lib.hg_collection_intersect.argtypes = [vp, vp, vp, ctypes.c_uint64, vp, vp, vp]
+    assert lib.hg_collection_intersect(None, None, dummy, 1, dummy, None, None) == 1
+    lib.hg_collection_view.argtypes = [vp, vp]
+    assert lib.hg_collection_view(None, dummy) == 1
 
 
 def test_no_cpu_fallback_without_gpu(lib):
@@ -80,3 +92,8 @@ def test_no_cpu_fallback_without_gpu(lib):
                             vp, vp]
     dummy = vp(0x1000)
     assert lib.hg_hash(dummy, 10, 32, 100, 0, dummy, None) == 3  # HG_ERR_DEVICE
+    lib.hg_collection_build.argtypes = [vp, vp, ctypes.c_uint32, ctypes.c_int, ctypes.c_uint64,
+                                        ctypes.c_int32, ctypes.POINTER(vp), vp]
+    out = vp()
+    assert lib.hg_collection_build(dummy, dummy, 4, 32, 0, 0, ctypes.byref(out), None) == 3
+    assert not out.value
