@@ -577,6 +577,44 @@ def main():
         log("erase %d entries %.3f ms, probe after %.3f ms" % (removed, t_er, t_pe))
         te.free()
         del te, gone
+        # build once, intersect many: 2^20 sets shaped like sparse rows (mean
+        # 32 keys, Pareto tail 1.5, at most 2^16), columns uniform over 2^20,
+        # and 2^24 random set pairs (each set takes part in 32 pairs on average)
+        log("collection")
+        S = 1 << 20
+        kc, oc = workloads.collection_sets(S, 32, 1 << 20, seed=31)
+        pc = workloads.set_pairs(1 << 24, S, S, seed=32)
+        dkc = hg.to_device(kc)
+        doc = torch.from_numpy(oc.astype(np.int32)).cuda()
+        dpc = torch.from_numpy(pc.view(np.int32)).cuda()
+        walked = int(np.minimum(np.diff(oc)[pc[:, 0]], np.diff(oc)[pc[:, 1]]).sum())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        coll = hg.Collection(dkc, doc, seed=5)
+        torch.cuda.synchronize()
+        t_cb = (time.perf_counter() - t0) * 1e3
+        t_ci = timed(lambda: coll.intersect(coll, dpc, counts=True, total=False), reps, torch)
+        hg.profile_reset()
+        hg.profile_enable(True)
+        coll2 = hg.Collection(dkc, doc, seed=5)
+        coll.intersect(coll, dpc, counts=True, total=False)
+        torch.cuda.synchronize()
+        hg.profile_enable(False)
+        pr = hg.profile_report()
+        hg.profile_reset()
+        k_build = sum(v[1] for k, v in pr.items() if k in ("coll_plan", "coll_groups", "coll_big"))
+        info = coll.info()
+        ex["collection_2^20_sets_2^24_pairs"] = {
+            "keys": int(kc.size), "heavy_set_keys": int(info.heavy_keys),
+            "build_ms": round(t_cb, 3), "build_device_ms": round(k_build, 3),
+            "build_Gkeys": round(kc.size / k_build / 1e6, 2),
+            "intersect_ms": round(t_ci, 3), "pairs_G_per_s": round(len(pc) / t_ci / 1e6, 2),
+            "walked_items": walked, "walked_G_per_s": round(walked / t_ci / 1e6, 2),
+            "pair_count_kernel_ms": round(pr.get("coll_pair_count", (0, 0.0))[1], 3)}
+        log("collection: build %.3f ms (kernels %.3f), intersect %.3f ms" % (t_cb, k_build, t_ci))
+        coll.free()
+        coll2.free()
+        del dkc, doc, dpc, kc, oc, pc
         # 2^30 keys, V = 2^30 (two partition passes of 10 and 9 bits)
         log("2^30 keys")
         n30 = 1 << 30

@@ -214,3 +214,43 @@ def test_full_zipf_join(hg, s):
     assert np.array_equal(hg.to_numpy(cb, np.uint32), exp)
     tq.free()
     table.free()
+
+
+def test_full_collection_build_once_intersect_many(hg):
+    """The benchmark's collection: 2^20 sets (mean 32 keys, Pareto tail 1.5,
+    at most 2^16), columns uniform over 2^20, 2^24 random pairs.  Sampled sets
+    (every heavy one and 3000 others) equal the oracle's per-set tables; the
+    counts of 20000 sampled pairs equal the oracle's join sizes, the total
+    equals the sum of all counts, and the total is the same when it is asked
+    for alone."""
+    S = 1 << 20
+    kc, oc = workloads.collection_sets(S, 32, 1 << 20, seed=31)
+    pc = workloads.set_pairs(1 << 24, S, S, seed=32)
+    say("collection", S, kc.size)
+    c = hg.Collection(hg.to_device(kc), torch.from_numpy(oc.astype(np.int32)).cuda(), seed=5)
+    bb, off, ids, ek = c.arrays()
+    torch.cuda.synchronize()
+    bb = hg.to_numpy(bb, np.uint64)
+    off = hg.to_numpy(off, np.uint32)
+    ids = hg.to_numpy(ids, np.uint32)
+    ek = hg.to_numpy(ek, np.uint32)
+    sizes = np.diff(oc)
+    rng = np.random.default_rng(8)
+    sample = np.union1d(np.flatnonzero(sizes > 1536), rng.choice(S, 3000, replace=False))
+    for s in sample:
+        lo, hi = int(oc[s]), int(oc[s + 1])
+        V = oracle.set_hash_range(hi - lo)
+        assert int(bb[s + 1] - bb[s]) == V
+        o, i, e = oracle.build_table(kc[lo:hi], V, 5, 32)
+        b0 = int(bb[s])
+        assert np.array_equal(off[b0:b0 + V + 1].astype(np.int64) - lo, o.astype(np.int64)), s
+        assert np.array_equal(ids[lo:hi].astype(np.int64) - lo, i.astype(np.int64)), s
+        assert np.array_equal(ek[lo:hi], e), s
+    cnt, tot = c.intersect(c, torch.from_numpy(pc.view(np.int32)).cuda())
+    got = hg.to_numpy(cnt, np.uint64)
+    assert tot == int(got.sum())
+    q = rng.choice(pc.shape[0], 20000, replace=False)
+    assert np.array_equal(got[q], oracle.pair_match_counts(kc, oc, kc, oc, pc[q]))
+    _, tot2 = c.intersect(c, torch.from_numpy(pc.view(np.int32)).cuda(), counts=False)
+    assert tot2 == tot
+    c.free()
