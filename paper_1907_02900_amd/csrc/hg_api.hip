@@ -632,9 +632,8 @@ hg_status hg_probe(const hg_table* t, const void* d_queries, uint64_t m, uint32_
     Scratch ws(stream);
     unsigned long long* d_total = nullptr;
     if (h_total) {
-        HG_CALL(ws.get(256));
+        HG_CALL(ws.get(probe_total_slots(m) * 8));
         d_total = (unsigned long long*)ws.p;
-        HG_CALL(fill_u32((uint32_t*)d_total, 2, 0u, stream));
     }
     TableDev d = dev_view(t);
     hipError_t e = t->key_bits == 32
@@ -698,13 +697,12 @@ hg_status hg_intersect(const hg_table* a, const hg_table* b, uint32_t* d_counts_
     TableDev da = dev_view(a), db = dev_view(b);
     const bool pairs = capacity > 0;
     Scratch ws(stream);
-    HG_CALL(ws.get(probe_ws_bytes(nb)));
+    HG_CALL(ws.get(probe_ws_bytes(nb) + probe_total_slots(nb) * 8 + 256));
     Carver c(ws.p);
     uint32_t* edge = c.take<uint32_t>(nb);
     uint64_t* pos = c.take<uint64_t>(nb + 1);
     void* scan_ws = c.take<char>(scan_ws_bytes(nb));
-    unsigned long long* d_total = (unsigned long long*)c.take<uint64_t>(1);
-    if (h_total && !pairs) HG_CALL(fill_u32((uint32_t*)d_total, 2, 0u, stream));
+    unsigned long long* d_total = (unsigned long long*)c.take<uint64_t>(probe_total_slots(nb));
     hipError_t e = a->key_bits == 32
                        ? run_intersect_counts<uint32_t>(da, db, pairs ? edge : nullptr, d_counts_b,
                                                         (h_total && !pairs) ? d_total : nullptr, stream)

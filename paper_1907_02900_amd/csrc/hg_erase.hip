@@ -24,6 +24,7 @@ namespace {
 using namespace v2dev;
 
 constexpr int kT = 256;
+constexpr uint32_t kCompactBlocks = 2048;
 
 uint32_t grid_of(uint64_t n) {
     const uint64_t g = ceil_div(n, kT);
@@ -54,8 +55,43 @@ __global__ void k_erase_mark(const Key* __restrict__ del, uint64_t m,
     if (any) touched[h] = 1;
 }
 
-// One thread per bucket; `removed` gets the number of erased entries (one
-// device atomic per workgroup that erased any).
+// Compacts one touched bucket h; returns the number of entries it dropped.
+template <typename Key>
+__device__ __forceinline__ uint32_t compact_bucket(uint64_t h, const uint32_t* __restrict__ off,
+                                                   uint32_t* __restrict__ len,
+                                                   Key* __restrict__ ekeys,
+                                                   uint32_t* __restrict__ ids,
+                                                   uint8_t* __restrict__ dead,
+                                                   uint4* __restrict__ head) {
+    const uint32_t lo = off[h], L = len[h];
+    uint32_t w = lo;
+    for (uint32_t p = lo; p < lo + L; ++p) {
+        if (dead[p]) {
+            dead[p] = 0;
+            continue;
+        }
+        if (w != p) {
+            ekeys[w] = ekeys[p];
+            ids[w] = ids[p];
+        }
+        ++w;
+    }
+    const uint32_t nl = w - lo;
+    len[h] = nl;
+    uint4 e = head_entry<Key>(lo, w, ekeys + lo);
+    if (nl > kRunBucket) {  // no key runs any more: probes scan the bucket
+        e.z = ~0u;
+        e.w = 0;
+    }
+    head[h] = e;
+    return L - nl;
+}
+
+// Each thread takes groups of 16 buckets (one 16-byte load of their touched
+// flags) at a stride of the grid and compacts the touched ones; `removed`
+// gets the number of erased entries with one device atomic per workgroup (a
+// fixed grid of at most kCompactBlocks workgroups: same-address atomics
+// serialise across the chip).
 template <typename Key>
 __global__ __launch_bounds__(kT) void k_erase_compact(uint64_t V, const uint32_t* __restrict__ off,
                                                       uint32_t* __restrict__ len,
@@ -65,37 +101,34 @@ __global__ __launch_bounds__(kT) void k_erase_compact(uint64_t V, const uint32_t
                                                       uint8_t* __restrict__ touched,
                                                       uint4* __restrict__ head,
                                                       unsigned long long* __restrict__ removed) {
-    __shared__ uint32_t tmp[kT / kWave + 1];
-    const uint64_t h = (uint64_t)blockIdx.x * kT + threadIdx.x;
-    uint32_t gone = 0;
-    if (h < V && touched[h]) {
-        touched[h] = 0;
-        const uint32_t lo = off[h], L = len[h];
-        uint32_t w = lo;
-        for (uint32_t p = lo; p < lo + L; ++p) {
-            if (dead[p]) {
-                dead[p] = 0;
-                continue;
-            }
-            if (w != p) {
-                ekeys[w] = ekeys[p];
-                ids[w] = ids[p];
-            }
-            ++w;
-        }
-        const uint32_t nl = w - lo;
-        len[h] = nl;
-        gone = L - nl;
-        uint4 e = head_entry<Key>(lo, w, ekeys + lo);
-        if (nl > kRunBucket) {  // no key runs any more: probes scan the bucket
-            e.z = ~0u;
-            e.w = 0;
-        }
-        head[h] = e;
+    __shared__ unsigned long long red[kT / kWave];
+    unsigned long long gone = 0;
+    const uint64_t groups = V / 16;
+    const uint64_t stride = (uint64_t)gridDim.x * kT;
+    const uint64_t t0 = (uint64_t)blockIdx.x * kT + threadIdx.x;
+    for (uint64_t g = t0; g < groups; g += stride) {
+        uint4 f = ((const uint4*)touched)[g];
+        if ((f.x | f.y | f.z | f.w) == 0) continue;
+        ((uint4*)touched)[g] = make_uint4(0u, 0u, 0u, 0u);
+        const uint32_t word[4] = {f.x, f.y, f.z, f.w};
+        for (int i = 0; i < 16; ++i)
+            if ((word[i >> 2] >> (8 * (i & 3))) & 0xffu)
+                gone += compact_bucket<Key>(g * 16 + i, off, len, ekeys, ids, dead, head);
     }
-    uint32_t all;
-    block_excl_scan<kT>(gone, tmp, &all);
-    if (threadIdx.x == 0 && all) atomicAdd(removed, (unsigned long long)all);
+    // the last V % 16 buckets one by one
+    for (uint64_t h = groups * 16 + t0; h < V; h += stride) {
+        if (!touched[h]) continue;
+        touched[h] = 0;
+        gone += compact_bucket<Key>(h, off, len, ekeys, ids, dead, head);
+    }
+    gone = wave_sum64(gone);
+    if (lane_id() == 0) red[threadIdx.x / kWave] = gone;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long all = 0;
+        for (int i = 0; i < kT / kWave; ++i) all += red[i];
+        if (all) atomicAdd(removed, all);
+    }
 }
 
 // Compacted copy of the live entries: slot p holds a key of its own bucket
@@ -129,13 +162,16 @@ hipError_t run_erase(const TableDev& t, uint32_t* len, uint8_t* dead, uint8_t* t
                      uint4* head, const Key* del, uint64_t m, unsigned long long* d_removed,
                      hipStream_t s) {
     auto hp = KeyTraits<Key>::make(t.V, t.seed);
-    HG_PROF("erase", s);
     if (m) {
+        HG_PROF("erase_mark", s);
         hipLaunchKernelGGL(k_erase_mark<Key>, dim3(grid_of(m)), dim3(kT), 0, s, del, m, hp,
                            t.offsets, (const uint32_t*)len, (const Key*)t.keys, dead, touched);
         HG_TRY(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_erase_compact<Key>, dim3(grid_of(t.V)), dim3(kT), 0, s, t.V, t.offsets,
+    HG_PROF("erase_compact", s);
+    const uint32_t g16 = grid_of(ceil_div(t.V, 16));
+    const uint32_t cb = g16 < kCompactBlocks ? g16 : kCompactBlocks;
+    hipLaunchKernelGGL(k_erase_compact<Key>, dim3(cb), dim3(kT), 0, s, t.V, t.offsets,
                        len, (Key*)t.keys, (uint32_t*)t.ids, dead, touched, head, d_removed);
     return hipGetLastError();
 }

@@ -96,6 +96,14 @@ hipError_t scan_excl(const uint32_t* in, uint64_t n, OutT* out, uint32_t* copy, 
 
 hipError_t fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
 
+// *out = sum of v[0..n) (out outside v).
+hipError_t sum_u64(const unsigned long long* v, uint64_t n, unsigned long long* out,
+                   hipStream_t s);
+
+// uint64 slots of a probe / intersection total buffer for m queries (or B
+// entries): slot 0 receives the total, the others hold per-workgroup sums.
+uint64_t probe_total_slots(uint64_t m);
+
 template <typename Key>
 hipError_t run_hash(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, uint32_t* out,
                     hipStream_t s);
@@ -195,7 +203,8 @@ hipError_t run_export_live(const TableDev& t, const uint32_t* len, const uint32_
 
 size_t probe_ws_bytes(uint64_t m);
 
-// counts (may be null) and/or the total (device uint64, may be null).
+// counts (may be null) and/or the total (may be null: else a buffer of
+// probe_total_slots(m) uint64, the total lands in slot 0).
 template <typename Key>
 hipError_t run_probe_counts(const TableDev& t, const Key* queries, uint64_t m, uint32_t* counts,
                             unsigned long long* d_total, hipStream_t s);

@@ -159,7 +159,7 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_count(
     if (total) {
         uint64_t all;
         block_excl_scan64<kProbeThreads>(sum, red, &all);
-        if (threadIdx.x == 0 && all) atomic_add_relaxed64(total, all);
+        if (threadIdx.x == 0) total[1 + blockIdx.x] = all;  // reduced by sum_u64
     }
 }
 
@@ -258,7 +258,7 @@ __global__ __launch_bounds__(kProbeThreads) void k_intersect_count(
     if (total) {
         uint64_t all;
         block_excl_scan64<kProbeThreads>(sum, red, &all);
-        if (threadIdx.x == 0 && all) atomic_add_relaxed64(total, all);
+        if (threadIdx.x == 0) total[1 + blockIdx.x] = all;  // reduced by sum_u64
     }
 }
 
@@ -312,14 +312,18 @@ size_t probe_ws_bytes(uint64_t m) {
     return align_up(m * 4, 256) + align_up((m + 1) * 8, 256) + scan_ws_bytes(m) + 512;
 }
 
+uint64_t probe_total_slots(uint64_t m) {
+    return 1 + (m ? grid_for(m, kProbeThreads * kProbeItems) : 0);
+}
+
 template <typename Key>
 hipError_t run_probe_counts(const TableDev& t, const Key* queries, uint64_t m, uint32_t* counts,
                             unsigned long long* d_total, hipStream_t s) {
-    if (m == 0) return hipSuccess;
+    if (m == 0) return d_total ? fill_u32((uint32_t*)d_total, 2, 0u, s) : hipSuccess;
     auto hp = KeyTraits<Key>::make(t.V, t.seed);
+    const dim3 grid(grid_for(m, kProbeThreads * kProbeItems));
     {
         HG_PROF("probe_count", s);
-        const dim3 grid(grid_for(m, kProbeThreads * kProbeItems));
         if (t.head)
             hipLaunchKernelGGL((k_probe_count<Key, true>), grid, dim3(kProbeThreads), 0, s,
                                queries, m, hp, t.offsets, t.head, runs_of<Key>(t),
@@ -329,7 +333,8 @@ hipError_t run_probe_counts(const TableDev& t, const Key* queries, uint64_t m, u
                                queries, m, hp, t.offsets, t.head, runs_of<Key>(t),
                                (const Key*)t.keys, counts, d_total);
     }
-    return hipGetLastError();
+    HG_TRY(hipGetLastError());
+    return d_total ? sum_u64(d_total + 1, grid.x, d_total, s) : hipSuccess;
 }
 
 template <typename Key>
@@ -358,16 +363,18 @@ template <typename Key>
 hipError_t run_intersect_counts(const TableDev& a, const TableDev& b, uint32_t* edge_counts,
                                 uint32_t* counts_by_input, unsigned long long* d_total,
                                 hipStream_t s) {
-    if (b.n == 0) return hipSuccess;
+    if (b.n == 0) return d_total ? fill_u32((uint32_t*)d_total, 2, 0u, s) : hipSuccess;
     auto hp = KeyTraits<Key>::make(a.V, a.seed);
+    const uint32_t grid = grid_for(b.n, kProbeThreads * kProbeItems);
     {
         HG_PROF("intersect_count", s);
-        hipLaunchKernelGGL(k_intersect_count<Key>, dim3(grid_for(b.n, kProbeThreads * kProbeItems)),
+        hipLaunchKernelGGL(k_intersect_count<Key>, dim3(grid),
                            dim3(kProbeThreads), 0, s, a.offsets, a.len, a.head, runs_of<Key>(a),
                            (const Key*)a.keys, b.offsets, b.len, (const Key*)b.keys, b.ids, b.n,
                            hp, edge_counts, counts_by_input, d_total);
     }
-    return hipGetLastError();
+    HG_TRY(hipGetLastError());
+    return d_total ? sum_u64(d_total + 1, grid, d_total, s) : hipSuccess;
 }
 
 template <typename Key>

@@ -114,6 +114,25 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint64_t n, uint32_t v) {
     for (; i < n; i += st) p[i] = v;
 }
 
+// Sum of v[0..n) added into *out (zeroed by the caller's fill): a few
+// hundred workgroups, one device atomic each.
+__global__ __launch_bounds__(256) void k_sum_u64(const unsigned long long* __restrict__ v,
+                                                 uint64_t n, unsigned long long* __restrict__ out) {
+    __shared__ unsigned long long red[256 / kWave];
+    unsigned long long s = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * 256)
+        s += v[i];
+    s = wave_sum64(s);
+    if (lane_id() == 0) red[threadIdx.x / kWave] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long all = 0;
+        for (int i = 0; i < 256 / kWave; ++i) all += red[i];
+        if (all) atomicAdd(out, all);
+    }
+}
+
 template <typename OutT>
 __global__ void k_set_one(OutT* p, OutT v) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
@@ -122,6 +141,16 @@ __global__ void k_set_one(OutT* p, OutT v) {
 }  // namespace
 
 size_t scan_ws_bytes(uint64_t n) { return (ceil_div(n, kScanTile) + 2) * sizeof(uint64_t) + 256; }
+
+hipError_t sum_u64(const unsigned long long* v, uint64_t n, unsigned long long* out,
+                   hipStream_t s) {
+    HG_TRY(fill_u32((uint32_t*)out, 2, 0u, s));
+    if (n == 0) return hipSuccess;
+    uint64_t blocks = ceil_div(n, 256 * 8);
+    if (blocks > 256) blocks = 256;
+    hipLaunchKernelGGL(k_sum_u64, dim3((uint32_t)blocks), dim3(256), 0, s, v, n, out);
+    return hipGetLastError();
+}
 
 hipError_t fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s) {
     if (n == 0) return hipSuccess;

@@ -595,8 +595,8 @@ V2Plan plan_v2(uint64_t n, uint64_t V, int key_bits, uint32_t bins_hint) {
         p.b2 = 0;
     } else {
         p.tiers = 2;
-        p.b2 = bits / 2;
-        p.b1 = bits - p.b2;
+        p.b1 = bits / 2;
+        p.b2 = bits - p.b1;
     }
     p.ntiles1 = (uint32_t)ceil_div(n, kPartTile);
     p.ch1 = (uint32_t)pow2_ceil(ceil_div(p.ntiles1 ? p.ntiles1 : 1, 256));
