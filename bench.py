@@ -56,6 +56,19 @@ def src_digest() -> str:
     return h.hexdigest()[:16]
 
 
+def micro_roofline(hg):
+    """Random-transaction rates (G accesses/s) over L2-, MALL- and HBM-sized
+    footprints: 4-byte and 16-byte reads and 4-byte atomic adds."""
+    out = {}
+    for label, fp in (("4MiB", 1 << 22), ("128MiB", 1 << 27), ("4GiB", 1 << 32)):
+        out[label] = {
+            "read4_G_per_s": round(hg.random_access_rate(hg.MICRO_READ4, fp, 1 << 27) / 1e9, 2),
+            "read16_G_per_s": round(hg.random_access_rate(hg.MICRO_READ16, fp, 1 << 27) / 1e9, 2),
+            "atomic4_G_per_s": round(hg.random_access_rate(hg.MICRO_ATOMIC4, fp, 1 << 26) / 1e9,
+                                     2)}
+    return out
+
+
 def timed(fn, reps, torch):
     """Median milliseconds of `reps` runs of fn() (events on the current stream)."""
     out = []
@@ -471,6 +484,15 @@ def main():
         roofline["random_lines_per_launch"] = lines
         roofline["line_bytes"] = 128
         roofline["line_GBps"] = round(lines * 128 / (dk_["avg_ms"] / 1000.0) / 1e9, 1)
+        # the measured ceiling of independent random 16-byte reads over a
+        # 4 GiB footprint (the probe index is 4 GiB at this size)
+        micro = micro_roofline(hg)
+        rate = micro["4GiB"]["read16_G_per_s"]
+        roofline["random_read16_G_per_s_4GiB"] = rate
+        roofline["random_lines_G_per_s"] = round(lines / (dk_["avg_ms"] / 1000.0) / 1e9, 2)
+        roofline["frac_of_random_read_rate"] = round(
+            roofline["random_lines_G_per_s"] / rate, 3)
+        roofline["micro_roofline"] = micro
 
     phases = {"kernels": kernels, "source_digest": digest,
               "probe_sum_bucket_len": sum_len, "probe_sum_keys_past_index": sum_tail}

@@ -475,6 +475,21 @@ hg_status hg_profile_count(uint32_t *count);
 hg_status hg_profile_get(uint32_t index, char *name, uint32_t name_cap, uint64_t *launches,
                          double *total_ms);
 
+/* Random-transaction micro-roofline: the ceiling of random-access kernels
+ * (the probe makes one random 16-byte read per query, V1 one random atomic
+ * add per key).  Allocates a zeroed buffer of footprint_bytes (a power of two,
+ * >= 4096), runs `accesses` independent random accesses of the given kind
+ * over it once to warm up and once timed (HIP events on `stream`), frees the
+ * buffer and stores the timed run's milliseconds in *h_ms.  Waits for the
+ * device. */
+enum {
+    HG_MICRO_READ4 = 0,   /* random 4-byte loads           */
+    HG_MICRO_READ16 = 1,  /* random 16-byte (uint4) loads  */
+    HG_MICRO_ATOMIC4 = 2  /* random 4-byte atomic adds     */
+};
+hg_status hg_random_access_rate(int kind, uint64_t footprint_bytes, uint64_t accesses,
+                                double *h_ms, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -435,6 +435,22 @@ def _prof_sig():
     return L
 
 
+MICRO_READ4, MICRO_READ16, MICRO_ATOMIC4 = 0, 1, 2
+
+
+def random_access_rate(kind: int, footprint_bytes: int, accesses: int, stream=None) -> float:
+    """Random accesses per second (hg_random_access_rate) of the given kind
+    over a power-of-two footprint."""
+    L = lib()
+    L.hg_random_access_rate.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
+                                        ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]
+    L.hg_random_access_rate.restype = ctypes.c_int
+    ms = ctypes.c_double(0)
+    _check(L.hg_random_access_rate(int(kind), int(footprint_bytes), int(accesses),
+                                   ctypes.byref(ms), _stream(stream)), "hg_random_access_rate")
+    return accesses / (ms.value * 1e-3)
+
+
 def profile_enable(on: bool = True):
     _check(_prof_sig().hg_profile_enable(1 if on else 0), "hg_profile_enable")
 
