@@ -22,7 +22,7 @@ namespace hg {
 namespace {
 
 constexpr int kProbeThreads = 256;
-constexpr int kProbeItems = 4;
+constexpr int kProbeItems = 8;
 
 // Entries of ekeys[lo, hi) equal to q.  Past the first few keys the scan
 // reads 16 bytes at a time (aligned), so a medium bucket costs a few wide
