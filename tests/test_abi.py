@@ -81,6 +81,13 @@ def test_invalid_arguments_rejected_on_host(lib):
     assert lib.hg_collection_intersect(None, None, dummy, 1, dummy, None, None) == 1
     lib.hg_collection_view.argtypes = [vp, vp]
     assert lib.hg_collection_view(None, dummy) == 1
+    lib.hg_random_access_rate.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, vp, vp]
+    ms = ctypes.c_double(0)
+    assert lib.hg_random_access_rate(1, 3 << 20, 1000, ctypes.byref(ms), None) == 1  # not 2^k
+    assert lib.hg_random_access_rate(1, 1024, 1000, ctypes.byref(ms), None) == 1     # < 4096
+    assert lib.hg_random_access_rate(7, 1 << 20, 1000, ctypes.byref(ms), None) == 1  # kind
+    assert lib.hg_random_access_rate(1, 1 << 20, 0, ctypes.byref(ms), None) == 1     # none
+    assert lib.hg_random_access_rate(1, 1 << 20, 1000, None, None) == 1
 
 
 def test_no_cpu_fallback_without_gpu(lib):

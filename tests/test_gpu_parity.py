@@ -404,3 +404,13 @@ def test_probe_counts_do_not_depend_on_range_seed_or_variant(hg):
             ref = got
         assert np.array_equal(got, ref)
     assert np.array_equal(ref, oracle.probe_counts(k, q)[0])
+
+
+def test_random_access_micro_roofline(hg):
+    """The micro-roofline kernels run and order as the memory hierarchy does:
+    an L2-sized footprint serves random reads faster than an HBM-sized one."""
+    l2 = hg.random_access_rate(hg.MICRO_READ16, 1 << 22, 1 << 24)
+    hbm = hg.random_access_rate(hg.MICRO_READ16, 1 << 30, 1 << 24)
+    at = hg.random_access_rate(hg.MICRO_ATOMIC4, 1 << 22, 1 << 22)
+    r4 = hg.random_access_rate(hg.MICRO_READ4, 1 << 12, 1 << 20)
+    assert l2 > hbm > 0 and at > 0 and r4 > 0
