@@ -165,3 +165,49 @@ def test_erase_needs_the_probe_index(hg):
         with pytest.raises(hg.HGError) as e:
             t.erase(k[:10])
         assert e.value.status == hg.HG_ERR_INVALID_ARG
+
+
+def test_erase_from_split_bins_and_key_runs(hg):
+    """Three keys share 600000 entries: buckets of 200000 entries (key runs,
+    bins split over workgroups).  Erasing one key leaves two long buckets
+    that lost their key runs (scanned); probes, pairs and the export still
+    match the oracle on what remains."""
+    rng = np.random.default_rng(41)
+    vals = np.array([7, 123456789, 4000000000], np.uint32)
+    k = vals[rng.integers(0, 3, 600000)]
+    V = 1000
+    t = hg.hg_build(hg.to_device(k), V, seed=3)
+    removed = t.erase(hg.to_device(vals[1:2]))
+    live = k != vals[1]
+    assert removed == int((~live).sum())
+    off, ids, ek = export_np(hg, t, 32)
+    e_off, e_ids, e_ek = remaining_table(oracle.build_table(k, V, 3), V, vals[1:2])
+    assert np.array_equal(off, e_off) and np.array_equal(ids, e_ids) and np.array_equal(ek, e_ek)
+    q = np.concatenate([vals, workloads.uniform_keys(50, 32, 5)]).astype(np.uint32)
+    c, tot = hg.hg_probe(t, hg.to_device(q), counts=True, total=True)
+    exp = oracle.probe_counts(k[live], q)[0]
+    assert np.array_equal(hg.to_numpy(c, np.uint32), exp) and tot == int(exp.sum())
+    q1 = np.array([vals[0], vals[2], vals[1]], np.uint32)
+    b, p, ptot = hg.hg_probe_pairs(t, hg.to_device(q1))
+    eb, ep, etot = oracle.probe_pairs(k[live], q1)
+    assert ptot == etot
+    # the oracle numbers build entries among the live keys: map back to ids
+    live_ids = np.flatnonzero(live).astype(np.uint32)
+    assert np.array_equal(hg.to_numpy(p, np.uint32), ep)
+    assert np.array_equal(hg.to_numpy(b, np.uint32), live_ids[eb])
+    t.free()
+
+
+def test_erase_everything(hg):
+    k = workloads.duplicate_keys(100000, 2.0, 32, seed=8)
+    V = 50000
+    t = hg.hg_build(hg.to_device(k), V, seed=1)
+    assert t.erase(hg.to_device(np.unique(k))) == k.size
+    assert t.live() == 0
+    off, ids, ek = export_np(hg, t, 32)
+    assert np.array_equal(off, np.zeros(V + 1, np.uint32)) and ids.size == 0 and ek.size == 0
+    c, tot = hg.hg_probe(t, hg.to_device(k[:1000]), counts=True, total=True)
+    assert tot == 0 and not hg.to_numpy(c, np.uint32).any()
+    # erasing again (nothing left) removes nothing
+    assert t.erase(hg.to_device(k[:10])) == 0
+    t.free()
