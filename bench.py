@@ -546,8 +546,11 @@ def main():
 
         t_pn = timed(probe_new, reps, torch)
         t_int = timed(lambda: hg.hg_intersect(table, tq, counts=True, total=False), reps, torch)
+        # the join size alone: no per-query counts scattered back to input order
+        t_tot = timed(lambda: hg.hg_intersect(table, tq, counts=False, total=True), reps, torch)
         ex["probe_new"] = {"ms": round(t_pn, 3), "Gkeys": round(m / t_pn / 1e6, 2),
                            "intersect_only_ms": round(t_int, 3),
+                           "intersect_total_only_ms": round(t_tot, 3),
                            "build_share": round(1 - t_int / t_pn, 3)}
         tq.free()
         del tq, cb
