@@ -30,8 +30,10 @@
 // entry pairs with equal keys, the size of the join of the two sets (Alg. 3
 // over the pair of tables).  Work is balanced over all pairs: an exclusive
 // scan of the walked sizes maps work items to pairs, each workgroup takes
-// 2048 consecutive items, and per-item counts are summed per pair inside each
-// wave before one atomic add per (wave, pair).
+// 2048 consecutive items and stages its pairs' metadata (walked keys' start,
+// looked-up set's buckets) in LDS, so that an item costs an LDS search, its
+// walked key and the looked-up bucket; per-item counts are summed per pair
+// inside each wave before one atomic add per (wave, pair).
 #include <rocprim/device/device_radix_sort.hpp>
 
 #include "hg_v2_device.h"
@@ -250,6 +252,8 @@ __global__ void k_pair_work(const uint32_t* __restrict__ pairs, uint64_t Q, Sets
     work[q] = ni < nj ? ni : nj;
 }
 
+constexpr uint32_t kPairMeta = 1024;  // pairs of a workgroup whose metadata LDS holds
+
 template <typename Key>
 __global__ __launch_bounds__(kT) void k_pair_count(const uint32_t* __restrict__ pairs,
                                                    const uint64_t* __restrict__ W, uint64_t Q,
@@ -259,6 +263,12 @@ __global__ __launch_bounds__(kT) void k_pair_count(const uint32_t* __restrict__ 
                                                    unsigned long long* __restrict__ partial) {
     __shared__ uint64_t qrange[2];
     __shared__ unsigned long long red[kT / kWave];
+    // per pair of the chunk: its first item relative to the chunk (clamped at
+    // 0), the walked key index of the chunk's first item (mod 2^32), the
+    // looked-up set's first bucket, and its V - 1 with bit 31 set when a's
+    // set is the walked one
+    __shared__ uint16_t s_w[kPairMeta];
+    __shared__ uint32_t s_kpos[kPairMeta], s_tb[kPairMeta], s_vm[kPairMeta];
     const uint64_t base = (uint64_t)blockIdx.x * kPairChunk;
     if (threadIdx.x == 0) {
         const uint64_t last = (base + kPairChunk < T ? base + kPairChunk : T) - 1;
@@ -267,6 +277,24 @@ __global__ __launch_bounds__(kT) void k_pair_count(const uint32_t* __restrict__ 
     }
     __syncthreads();
     const uint64_t qa = qrange[0], nq = qrange[1] - qa + 1;
+    const bool staged = nq <= kPairMeta;  // uniform over the workgroup
+    if (staged) {
+        for (uint32_t j = threadIdx.x; j < nq; j += kT) {
+            const uint64_t q = qa + j;
+            const uint32_t i = pairs[2 * q], jj = pairs[2 * q + 1];
+            const uint32_t ni = a.set_off[i + 1] - a.set_off[i];
+            const uint32_t nj = b.set_off[jj + 1] - b.set_off[jj];
+            const bool walk_a = ni < nj;
+            const uint32_t wstart = walk_a ? a.set_off[i] : b.set_off[jj];
+            const uint64_t* obb = walk_a ? b.bb + jj : a.bb + i;
+            const uint64_t wq = W[q];
+            s_w[j] = (uint16_t)(wq > base ? wq - base : 0);
+            s_kpos[j] = wstart + (uint32_t)base - (uint32_t)wq;
+            s_tb[j] = (uint32_t)obb[0];
+            s_vm[j] = ((uint32_t)(obb[1] - obb[0]) - 1u) | (walk_a ? 0x80000000u : 0u);
+        }
+        __syncthreads();
+    }
     const uint32_t lane = lane_id();
     unsigned long long mine = 0;
     for (uint32_t r = 0; r < kPairItems; ++r) {
@@ -274,18 +302,39 @@ __global__ __launch_bounds__(kT) void k_pair_count(const uint32_t* __restrict__ 
         uint64_t q = ~0ull;
         unsigned long long c = 0;
         if (t < T) {
-            q = qa + last_le(W + qa, nq, t);
-            const uint32_t i = pairs[2 * q], j = pairs[2 * q + 1];
-            const uint32_t ni = a.set_off[i + 1] - a.set_off[i];
-            const uint32_t nj = b.set_off[j + 1] - b.set_off[j];
-            const bool walk_a = ni < nj;
-            const SetsView& w = walk_a ? a : b;
+            Key key;
+            uint64_t g;
+            bool walk_a;
+            if (staged) {
+                const uint32_t rel = (uint32_t)(t - base);
+                uint32_t lo = 0, hi = (uint32_t)nq;  // the last pair starting at or before rel
+                while (hi - lo > 1) {
+                    const uint32_t m = (lo + hi) >> 1;
+                    if (s_w[m] <= rel)
+                        lo = m;
+                    else
+                        hi = m;
+                }
+                q = qa + lo;
+                const uint32_t vm = s_vm[lo];
+                walk_a = (vm >> 31) != 0;
+                key = ((const Key*)(walk_a ? a.keys : b.keys))[s_kpos[lo] + rel];
+                g = (uint64_t)s_tb[lo] + (set_hash<Key>(key, seed) & (vm & 0x7fffffffu));
+            } else {
+                q = qa + last_le(W + qa, nq, t);
+                const uint32_t i = pairs[2 * q], j = pairs[2 * q + 1];
+                const uint32_t ni = a.set_off[i + 1] - a.set_off[i];
+                const uint32_t nj = b.set_off[j + 1] - b.set_off[j];
+                walk_a = ni < nj;
+                const SetsView& w = walk_a ? a : b;
+                const SetsView& o = walk_a ? b : a;
+                const uint32_t sw = walk_a ? i : j, so = walk_a ? j : i;
+                key = ((const Key*)w.keys)[w.set_off[sw] + (uint32_t)(t - W[q])];
+                const uint64_t ob = o.bb[so];
+                const uint32_t V = (uint32_t)(o.bb[so + 1] - ob);
+                g = ob + (set_hash<Key>(key, seed) & (V - 1u));
+            }
             const SetsView& o = walk_a ? b : a;
-            const uint32_t sw = walk_a ? i : j, so = walk_a ? j : i;
-            const Key key = ((const Key*)w.keys)[w.set_off[sw] + (uint32_t)(t - W[q])];
-            const uint64_t ob = o.bb[so];
-            const uint32_t V = (uint32_t)(o.bb[so + 1] - ob);
-            const uint64_t g = ob + (set_hash<Key>(key, seed) & (V - 1u));
             const uint32_t lo = o.offsets[g], hi = o.offsets[g + 1];
             const Key* ok = (const Key*)o.keys;
             for (uint32_t p = lo; p < hi; ++p) c += ok[p] == key;

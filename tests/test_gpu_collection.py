@@ -162,3 +162,21 @@ def test_pairs_across_two_collections(hg):
     assert c0.numel() == 0 and t0 == 0
     for x in (a, b, other):
         x.free()
+
+
+@pytest.mark.parametrize("size_hi", [2, 200])
+def test_pair_counts_both_staging_paths(hg, size_hi):
+    """Sets of one or two keys give workgroups of 2048 work items with more
+    pairs than the LDS metadata holds (the direct path); sets of up to 200
+    keys give few pairs per workgroup (the staged path)."""
+    rng = np.random.default_rng(size_hi)
+    sizes = rng.integers(1, size_hi + 1, 20000)
+    off = np.zeros(sizes.size + 1, np.int64)
+    np.cumsum(sizes, out=off[1:])
+    keys = rng.integers(0, 300, int(off[-1])).astype(np.uint32)
+    c = hg.Collection(hg.to_device(keys), dev_off(off), seed=2)
+    pairs = workloads.set_pairs(60000, sizes.size, sizes.size, seed=3)
+    cnt, tot = c.intersect(c, torch.from_numpy(pairs.view(np.int32)).cuda())
+    exp = oracle.pair_match_counts(keys, off, keys, off, pairs)
+    assert np.array_equal(hg.to_numpy(cnt, np.uint64), exp) and tot == int(exp.sum())
+    c.free()
