@@ -548,9 +548,13 @@ def main():
         t_int = timed(lambda: hg.hg_intersect(table, tq, counts=True, total=False), reps, torch)
         # the join size alone: no per-query counts scattered back to input order
         t_tot = timed(lambda: hg.hg_intersect(table, tq, counts=False, total=True), reps, torch)
+        # counts in the query table's edge order (Alg. 3's own order, sequential writes)
+        t_edge = timed(lambda: hg.hg_intersect_edges(table, tq, counts=True, total=False, out=cb),
+                       reps, torch)
         ex["probe_new"] = {"ms": round(t_pn, 3), "Gkeys": round(m / t_pn / 1e6, 2),
                            "intersect_only_ms": round(t_int, 3),
                            "intersect_total_only_ms": round(t_tot, 3),
+                           "intersect_edge_order_ms": round(t_edge, 3),
                            "build_share": round(1 - t_int / t_pn, 3)}
         tq.free()
         del tq, cb

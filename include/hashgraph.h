@@ -239,6 +239,16 @@ hg_status hg_intersect(const hg_table *a, const hg_table *b, uint32_t *d_counts_
                        uint32_t *d_a_ids, uint32_t *d_b_ids, uint64_t capacity,
                        uint64_t *h_total, hipStream_t stream);
 
+/* Alg. 3's counts in the order it produces them: d_counts_edges[p] (n_b
+ * uint32, may be NULL) = the number of entries of a whose key equals the key
+ * at b's edge position p (b's input index of that entry is d_ids[p] of
+ * hg_table_view; after an erase, stale positions get 0).  Unlike
+ * hg_intersect's per-input counts, nothing is scattered: every write is
+ * sequential.  h_total (may be NULL; waits for the stream) receives the join
+ * size.  Same requirements and errors as hg_intersect. */
+hg_status hg_intersect_edges(const hg_table *a, const hg_table *b, uint32_t *d_counts_edges,
+                             uint64_t *h_total, hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Collections: build once, intersect many (Sec. 3.4).  Probe-New pays for a
  * second table; in sparse products that cost is amortised, because the table

@@ -680,6 +680,30 @@ hg_status hg_probe_pairs(const hg_table* t, const void* d_queries, uint64_t m,
     return HG_OK;
 }
 
+hg_status hg_intersect_edges(const hg_table* a, const hg_table* b, uint32_t* d_counts_edges,
+                             uint64_t* h_total, hipStream_t stream) {
+    if (!a || !b || (!d_counts_edges && !h_total)) return HG_ERR_INVALID_ARG;
+    if (a->V == 0 || b->V == 0) return HG_ERR_INVALID_ARG;
+    if (a->key_bits != b->key_bits || a->V != b->V || a->seed != b->seed) return HG_ERR_MISMATCH;
+    if (device_ready() != HG_OK) return HG_ERR_DEVICE;
+    if (b->n == 0) {
+        if (h_total) *h_total = 0;
+        return HG_OK;
+    }
+    Scratch ws(stream);
+    unsigned long long* d_total = nullptr;
+    if (h_total) {
+        HG_CALL(ws.get(probe_total_slots(b->n) * 8));
+        d_total = (unsigned long long*)ws.p;
+    }
+    const TableDev da = dev_view(a), db = dev_view(b);
+    HG_CALL(a->key_bits == 32
+                ? run_intersect_counts<uint32_t>(da, db, d_counts_edges, nullptr, d_total, stream)
+                : run_intersect_counts<uint64_t>(da, db, d_counts_edges, nullptr, d_total, stream));
+    if (h_total) return read_u64((const uint64_t*)d_total, h_total, stream);
+    return HG_OK;
+}
+
 hg_status hg_intersect(const hg_table* a, const hg_table* b, uint32_t* d_counts_b,
                        uint32_t* d_a_ids, uint32_t* d_b_ids, uint64_t capacity,
                        uint64_t* h_total, hipStream_t stream) {

@@ -76,6 +76,7 @@ def lib():
         "hg_probe": ([vp, vp, u64, vp, pu64, vp], i32),
         "hg_probe_pairs": ([vp, vp, u64, vp, vp, u64, pu64, vp], i32),
         "hg_intersect": ([vp, vp, vp, vp, vp, u64, pu64, vp], i32),
+        "hg_intersect_edges": ([vp, vp, vp, pu64, vp], i32),
         "hg_table_erase": ([vp, vp, u64, pu64, vp], i32),
         "hg_table_lengths": ([vp, ctypes.POINTER(vp), pu64], i32),
     }
@@ -312,6 +313,18 @@ def hg_intersect(a: Table, b: Table, counts=True, total=True, capacity=0, stream
     if cap:
         return c, ai[:t], bi[:t], t
     return c, None, None, t
+
+
+def hg_intersect_edges(a: Table, b: Table, counts=True, total=True, out=None, stream=None):
+    """Alg. 3's counts in b's edge order (no scatter).  Returns (counts or
+    None, total or None)."""
+    ib = b.info()
+    c = (out if out is not None else _u32(ib.n, b.device)) if counts else None
+    tot = ctypes.c_uint64(0)
+    _check(lib().hg_intersect_edges(a.handle, b.handle, _ptr(c),
+                                    ctypes.byref(tot) if total else None, _stream(stream)),
+           "hg_intersect_edges")
+    return c, (int(tot.value) if total else None)
 
 
 # ------------------------------------------------------------ collections ---

@@ -7,7 +7,8 @@ seeded generators and the C ABI, and prints one JSON object:
                  range of N / R values (R appearances per key on average,
                  R = 1/8 ... 32), V = N.  V1 build, V2 build (stable and any
                  order), Probe-Standard counts and Probe-New (build the query
-                 table, intersect) with queries from the same range.
+                 table, intersect: counts in its edge order) with queries from
+                 the same range.
 ``bins``         Fig. 4 / 5: V2 build time over sizes 2^21, 2^23, 2^25 and bin
                  counts 2^10 ... 2^16 (the `bins` option; a bin spans a power
                  of two of at most 2^12 buckets here, so small counts are
@@ -62,7 +63,7 @@ def appearances(n=1 << 25):
 
         def probe_new():
             tq.rebuild(q, n, 0)
-            hg.hg_intersect(t, tq, counts=True, total=False)
+            hg.hg_intersect_edges(t, tq, counts=True, total=False, out=counts)
 
         pn = _timed(probe_new)
         rows.append({"R": R, "v1_Gkeys": _rate(n, v1), "v2_stable_Gkeys": _rate(n, v2),

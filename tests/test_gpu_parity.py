@@ -329,6 +329,25 @@ def test_intersect_matches_oracle(hg, kb, na, nb, V, kind):
         assert np.array_equal(got, np.stack([ep, eb], 1))
 
 
+@pytest.mark.parametrize("kb", [32, 64])
+@pytest.mark.parametrize("kind", ["uniform", "dup100"])
+def test_intersect_edge_order_counts(hg, kb, kind):
+    """hg_intersect_edges: per B edge, the count of A entries with that edge's
+    key; the same counts as hg_intersect, in B's edge order."""
+    ka = keys_for(kind, 150000, kb, seed=51) if kind == "uniform" else \
+        workloads.duplicate_keys(150000, 100.0, kb, seed=51)
+    kbk = workloads.probe_queries(ka, 120000, 0.6, seed=52, key_bits=kb)
+    V = 100000
+    a = hg.hg_build(hg.to_device(ka), V, seed=7)
+    b = hg.hg_build(hg.to_device(kbk), V, seed=7)
+    c, tot = hg.hg_intersect_edges(a, b)
+    _, _, bek = b.export()
+    exp, etot = oracle.probe_counts(ka, hg.to_numpy(bek, dt(kb)), kb)
+    assert np.array_equal(hg.to_numpy(c, np.uint32), exp) and tot == etot
+    _, tot2 = hg.hg_intersect_edges(a, b, counts=False)
+    assert tot2 == etot
+
+
 def skew_keys(kind, n, kb, seed):
     if kind == "zipf15":
         return workloads.zipf_keys(n, 1.5, distinct=1 << 12, seed=seed,
