@@ -545,6 +545,13 @@ def main():
             hg.hg_intersect(table, tq, counts=True, total=False)
 
         t_pn = timed(probe_new, reps, torch)
+
+        def probe_new_edges():
+            # the query table in any order and Alg. 3's counts in its edge order
+            tq.rebuild(dq, V, 0, any_order=True)
+            hg.hg_intersect_edges(table, tq, counts=True, total=False, out=cb)
+
+        t_pne = timed(probe_new_edges, reps, torch)
         t_int = timed(lambda: hg.hg_intersect(table, tq, counts=True, total=False), reps, torch)
         # the join size alone: no per-query counts scattered back to input order
         t_tot = timed(lambda: hg.hg_intersect(table, tq, counts=False, total=True), reps, torch)
@@ -555,6 +562,7 @@ def main():
                            "intersect_only_ms": round(t_int, 3),
                            "intersect_total_only_ms": round(t_tot, 3),
                            "intersect_edge_order_ms": round(t_edge, 3),
+                           "any_order_build_and_edge_order_ms": round(t_pne, 3),
                            "build_share": round(1 - t_int / t_pn, 3)}
         tq.free()
         del tq, cb
