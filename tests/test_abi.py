@@ -69,6 +69,9 @@ def test_invalid_arguments_rejected_on_host(lib):
     assert lib.hg_probe(None, dummy, 5, dummy, None, None) == 1
     lib.hg_intersect.argtypes = [vp, vp, vp, vp, vp, ctypes.c_uint64, vp, vp]
     assert lib.hg_intersect(None, None, None, None, None, 0, None, None) == 1
+    lib.hg_intersect_edges.argtypes = [vp, vp, vp, vp, vp]
+    assert lib.hg_intersect_edges(None, None, dummy, None, None) == 1
+    assert lib.hg_intersect_edges(dummy, dummy, None, None, None) == 1  # nothing asked for
     lib.hg_collection_build.argtypes = [vp, vp, ctypes.c_uint32, ctypes.c_int, ctypes.c_uint64,
                                         ctypes.c_int32, ctypes.POINTER(vp), vp]
     assert lib.hg_collection_build(dummy, dummy, 4, 32, 0, 0, None, None) == 1   # no out
