@@ -87,7 +87,8 @@ def kernel_bytes(name, n, m, V, kb, sum_len, plan, sum_tail=None):
     """Algorithmic bytes one launch of `name` must move (reads + writes).
 
     With the per-bucket probe index (sum_tail given), a query reads its
-    bucket's 16-byte entry and only the keys past the first two; without it,
+    bucket's 16-byte entry and only the keys the entry does not hold (it holds
+    all of a bucket of up to three 32-bit keys, else the first two); without it,
     two offsets and every key of its bucket.  The V2 local build writes the
     index (16 bytes per bucket) beside offsets, ids and keys."""
     if name == "probe_count":
@@ -450,8 +451,11 @@ def main():
     offl = off.to(torch.int64) & 0xFFFFFFFF
     blen = offl[h + 1] - offl[h]
     sum_len = int(blen.sum().item())
-    sum_tail = int((blen - 2).clamp_(min=0).sum().item())
-    n_tail = int((blen > 2).sum().item())  # queries that also read the edge array
+    # a bucket of up to 3 keys is held whole in its index entry; a longer one
+    # holds 2, the rest is read from the edge array
+    longer = blen > 3
+    sum_tail = int(((blen - 2) * longer).sum().item())
+    n_tail = int(longer.sum().item())  # queries that also read the edge array
     del h, offl, off, blen
 
     plan = v2_plan_bytes(n, V)

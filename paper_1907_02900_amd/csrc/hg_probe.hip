@@ -48,21 +48,30 @@ __device__ __forceinline__ uint32_t count_in_bucket(const Key* __restrict__ ekey
     return c;
 }
 
-// Keys a probe index entry carries: {start, end, key0, key1} for 32-bit keys,
-// {start, end, key0 low, key0 high} for 64-bit keys.
+// What a probe index entry holds (x = the bucket's length; see head_entry):
+// 32-bit keys: all keys of a bucket of at most three in y, z, w, else the
+// start in y and the first two keys in z, w; 64-bit keys: the start in y and
+// the first key in z, w.  A bucket longer than kRunBucket has its key-run
+// summary in z, w instead of keys.
 template <typename Key>
 struct HeadKeys;
 
 template <>
 struct HeadKeys<uint32_t> {
-    static constexpr uint32_t slots = 2;
-    __device__ static uint32_t key(const uint4& e, uint32_t i) { return i ? e.w : e.z; }
+    static constexpr uint32_t full = 3;  // buckets this short keep every key, no start
+    __device__ static bool has_start(uint32_t len) { return len > full; }
+    __device__ static uint32_t stored(uint32_t len) { return len <= full ? len : 2u; }
+    __device__ static uint32_t key(const uint4& e, uint32_t len, uint32_t i) {
+        if (len <= full) return i == 0 ? e.y : (i == 1 ? e.z : e.w);
+        return i == 0 ? e.z : e.w;
+    }
 };
 
 template <>
 struct HeadKeys<uint64_t> {
-    static constexpr uint32_t slots = 1;
-    __device__ static uint64_t key(const uint4& e, uint32_t) {
+    __device__ static bool has_start(uint32_t) { return true; }
+    __device__ static uint32_t stored(uint32_t len) { return len ? 1u : 0u; }
+    __device__ static uint64_t key(const uint4& e, uint32_t, uint32_t) {
         return (uint64_t)e.z | ((uint64_t)e.w << 32);
     }
 };
@@ -101,21 +110,23 @@ template <typename Key>
 __device__ __forceinline__ uint32_t count_with_head(const uint4& e, const Key* __restrict__ ekeys,
                                                     const Runs<Key>& runs, Key q) {
     using HK = HeadKeys<Key>;
-    const uint32_t len = e.y - e.x;
+    const uint32_t len = e.x;
     if (len > kRunBucket) {
-        if (e.z == ~0u) return count_in_bucket(ekeys, e.x, e.y, q);  // runs dropped by an erase
+        if (e.z == ~0u) return count_in_bucket(ekeys, e.y, e.y + len, q);  // runs dropped by an erase
         const uint32_t r = find_run(runs.key, e.z, e.w, q);
         return r != ~0u ? runs.cnt[r] : 0u;
     }
+    const uint32_t n = HK::stored(len);
     uint32_t c = 0;
 #pragma unroll
-    for (uint32_t i = 0; i < HK::slots; ++i) c += (len > i && HK::key(e, i) == q) ? 1u : 0u;
-    if (len > HK::slots) c += count_in_bucket(ekeys, e.x + HK::slots, e.y, q);
+    for (uint32_t i = 0; i < 3; ++i) c += (i < n && HK::key(e, len, i) == q) ? 1u : 0u;
+    if (len > n) c += count_in_bucket(ekeys, e.y + n, e.y + len, q);  // the start is stored
     return c;
 }
 
 // Probe-Standard counts.  HEAD: each query reads its bucket's 16-byte index
-// entry (one random access for buckets of up to two keys); otherwise it reads
+// entry (one random access for buckets of up to three 32-bit keys or one
+// 64-bit key); otherwise it reads
 // offsets[h], offsets[h+1] and scans the edge array.
 template <typename Key, bool HEAD>
 __global__ __launch_bounds__(kProbeThreads) void k_probe_count(
@@ -176,29 +187,41 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_pairs(
     for (; j < m; j += st) {
         const Key k = q[j];
         const uint32_t h = KeyTraits<Key>::bucket(k, hp);
-        uint4 e;
+        uint32_t start, len, n = 0;  // n: leading keys held in the entry
+        uint4 e = make_uint4(0u, 0u, 0u, 0u);
         if (HEAD) {
             e = head[h];
+            len = e.x;
+            const bool longb = len > kRunBucket;
+            if (longb && e.z != ~0u) {
+                // the ids of q's run, in bucket order
+                uint64_t pos = positions[j];
+                const uint32_t r = find_run(runs.key, e.z, e.w, k);
+                if (r != ~0u)
+                    for (uint32_t t = runs.pos[r], te = t + runs.cnt[r]; t < te; ++t) {
+                        build_ids[pos] = runs.kperm[t];
+                        probe_ids[pos] = (uint32_t)j;
+                        ++pos;
+                    }
+                continue;
+            }
+            n = longb ? 0u : HK::stored(len);
+            if (HK::has_start(len)) {
+                start = e.y;
+            } else {
+                // every key is in the entry: the ids need the bucket's start
+                bool any = false;
+                for (uint32_t i = 0; i < n; ++i) any |= HK::key(e, len, i) == k;
+                if (!any) continue;
+                start = off[h];
+            }
         } else {
-            e.x = off[h];
-            e.y = off[h + 1];
+            start = off[h];
+            len = off[h + 1] - start;
         }
-        const uint32_t lo = e.x, hi = e.y;
         uint64_t pos = positions[j];
-        const bool longb = HEAD && hi - lo > kRunBucket;
-        if (longb && e.z != ~0u) {
-            // the ids of q's run, in bucket order
-            const uint32_t r = find_run(runs.key, e.z, e.w, k);
-            if (r != ~0u)
-                for (uint32_t t = runs.pos[r], te = t + runs.cnt[r]; t < te; ++t) {
-                    build_ids[pos] = runs.kperm[t];
-                    probe_ids[pos] = (uint32_t)j;
-                    ++pos;
-                }
-            continue;
-        }
-        for (uint32_t p = lo; p < hi; ++p)
-            if ((HEAD && !longb && p - lo < HK::slots ? HK::key(e, p - lo) : ekeys[p]) == k) {
+        for (uint32_t p = start; p < start + len; ++p)
+            if ((p - start < n ? HK::key(e, len, p - start) : ekeys[p]) == k) {
                 build_ids[pos] = eids[p];
                 probe_ids[pos] = (uint32_t)j;
                 ++pos;

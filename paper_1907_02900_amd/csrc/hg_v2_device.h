@@ -256,9 +256,12 @@ inline size_t heavy_smem(uint32_t k) {
            (2 * W_LOCAL + 2) * 4 + 64;
 }
 
-// Probe index entry of one bucket: {start, end, first key, second key} for
-// 32-bit keys, {start, end, low and high half of the first key} for 64-bit
-// keys (unused key slots are 0).  `k` points at the bucket's first key.
+// Probe index entry of one bucket, x = its length.  32-bit keys: a bucket of
+// at most three keys holds them all in y, z, w (its start is not needed to
+// count matches); a longer one holds {len, start, first key, second key}.
+// 64-bit keys: {len, start, low and high half of the first key}.  Unused key
+// slots are 0.  A bucket longer than kRunBucket later gets its key-run
+// summary in z, w.  `k` points at the bucket's first key.
 template <typename Key>
 __device__ __forceinline__ uint4 head_entry(uint32_t start, uint32_t end, const Key* k);
 
@@ -266,14 +269,16 @@ template <>
 __device__ __forceinline__ uint4 head_entry<uint32_t>(uint32_t start, uint32_t end,
                                                       const uint32_t* k) {
     const uint32_t len = end - start;
-    return make_uint4(start, end, len >= 1 ? k[0] : 0u, len >= 2 ? k[1] : 0u);
+    if (len <= 3)
+        return make_uint4(len, len >= 1 ? k[0] : 0u, len >= 2 ? k[1] : 0u, len >= 3 ? k[2] : 0u);
+    return make_uint4(len, start, k[0], k[1]);
 }
 
 template <>
 __device__ __forceinline__ uint4 head_entry<uint64_t>(uint32_t start, uint32_t end,
                                                       const uint64_t* k) {
     const uint64_t k0 = (end - start >= 1) ? k[0] : 0ull;
-    return make_uint4(start, end, (uint32_t)k0, (uint32_t)(k0 >> 32));
+    return make_uint4(end - start, start, (uint32_t)k0, (uint32_t)(k0 >> 32));
 }
 
 // Write bucket b's index entry (the key slots of a bucket longer than
