@@ -87,8 +87,9 @@ def kernel_bytes(name, n, m, V, kb, sum_len, plan, sum_tail=None):
     """Algorithmic bytes one launch of `name` must move (reads + writes).
 
     With the per-bucket probe index (sum_tail given), a query reads its
-    bucket's 16-byte entry and only the keys the entry does not hold (it holds
-    all of a bucket of up to three 32-bit keys, else the first two); without it,
+    bucket's 16-byte entry and only the keys the entry does not account for
+    (all of a bucket of up to three 32-bit keys; in a longer one the first
+    key and its count); without it,
     two offsets and every key of its bucket.  The V2 local build writes the
     index (16 bytes per bucket) beside offsets, ids and keys."""
     if name == "probe_count":
@@ -446,17 +447,21 @@ def main():
     log("step %.3f ms -> %.2f Gkeys/s" % (ms_step, value))
 
     # exact sum of probed bucket lengths (for the probe's algorithmic bytes)
-    off, _, _ = table.export()
+    off, _, ek = table.export()
     h = hg.hg_hash(dq, V, 0).to(torch.int64)
     offl = off.to(torch.int64) & 0xFFFFFFFF
     blen = offl[h + 1] - offl[h]
     sum_len = int(blen.sum().item())
     # a bucket of up to 3 keys is held whole in its index entry; a longer one
-    # holds 2, the rest is read from the edge array
-    longer = blen > 3
-    sum_tail = int(((blen - 2) * longer).sum().item())
-    n_tail = int(longer.sum().item())  # queries that also read the edge array
-    del h, offl, off, blen
+    # holds its first key and that key's count, and a query equal to the first
+    # key needs nothing more; other queries read the rest of the bucket (the
+    # shortcut for buckets of one repeated key is left out: it does not occur
+    # with uniform 32-bit keys at these sizes)
+    first = (ek.to(torch.int64) & 0xFFFFFFFF)[offl[h].clamp_(max=n - 1)]
+    reads = (blen > 3) & ((dq.to(torch.int64) & 0xFFFFFFFF) != first)
+    sum_tail = int(((blen - 1) * reads).sum().item())
+    n_tail = int(reads.sum().item())  # queries that also read the edge array
+    del h, offl, off, blen, ek, first, reads
 
     plan = v2_plan_bytes(n, V)
     kernels = {}

@@ -50,9 +50,9 @@ __device__ __forceinline__ uint32_t count_in_bucket(const Key* __restrict__ ekey
 
 // What a probe index entry holds (x = the bucket's length; see head_entry):
 // 32-bit keys: all keys of a bucket of at most three in y, z, w, else the
-// start in y and the first two keys in z, w; 64-bit keys: the start in y and
-// the first key in z, w.  A bucket longer than kRunBucket has its key-run
-// summary in z, w instead of keys.
+// start in y, the first key in z and the number of entries equal to it in w;
+// 64-bit keys: the start in y and the first key in z, w.  A bucket longer
+// than kRunBucket has its key-run summary in z, w instead.
 template <typename Key>
 struct HeadKeys;
 
@@ -60,10 +60,10 @@ template <>
 struct HeadKeys<uint32_t> {
     static constexpr uint32_t full = 3;  // buckets this short keep every key, no start
     __device__ static bool has_start(uint32_t len) { return len > full; }
-    __device__ static uint32_t stored(uint32_t len) { return len <= full ? len : 2u; }
+    __device__ static uint32_t stored(uint32_t len) { return len <= full ? len : 1u; }
     __device__ static uint32_t key(const uint4& e, uint32_t len, uint32_t i) {
         if (len <= full) return i == 0 ? e.y : (i == 1 ? e.z : e.w);
-        return i == 0 ? e.z : e.w;
+        return e.z;
     }
 };
 
@@ -115,6 +115,14 @@ __device__ __forceinline__ uint32_t count_with_head(const uint4& e, const Key* _
         if (e.z == ~0u) return count_in_bucket(ekeys, e.y, e.y + len, q);  // runs dropped by an erase
         const uint32_t r = find_run(runs.key, e.z, e.w, q);
         return r != ~0u ? runs.cnt[r] : 0u;
+    }
+    if (sizeof(Key) == 4 && len > HeadKeys<uint32_t>::full) {
+        // {len, start, first key, its count}: the first key's matches are
+        // counted in the entry; the rest of the bucket is read only when it
+        // holds other keys and the query is not the first key
+        if ((uint32_t)q == e.z) return e.w;
+        if (e.w == len) return 0u;
+        return count_in_bucket(ekeys, e.y + 1, e.y + len, q);
     }
     const uint32_t n = HK::stored(len);
     uint32_t c = 0;

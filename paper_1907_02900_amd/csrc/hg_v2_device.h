@@ -258,7 +258,9 @@ inline size_t heavy_smem(uint32_t k) {
 
 // Probe index entry of one bucket, x = its length.  32-bit keys: a bucket of
 // at most three keys holds them all in y, z, w (its start is not needed to
-// count matches); a longer one holds {len, start, first key, second key}.
+// count matches); a longer one holds {len, start, first key, entries equal to
+// the first key}, so a query equal to the first key, or any query against a
+// bucket of one repeated key, is answered without reading the edge array.
 // 64-bit keys: {len, start, low and high half of the first key}.  Unused key
 // slots are 0.  A bucket longer than kRunBucket later gets its key-run
 // summary in z, w.  `k` points at the bucket's first key.
@@ -271,7 +273,14 @@ __device__ __forceinline__ uint4 head_entry<uint32_t>(uint32_t start, uint32_t e
     const uint32_t len = end - start;
     if (len <= 3)
         return make_uint4(len, len >= 1 ? k[0] : 0u, len >= 2 ? k[1] : 0u, len >= 3 ? k[2] : 0u);
-    return make_uint4(len, start, k[0], k[1]);
+    const uint32_t k0 = k[0];
+    uint32_t c0 = 0;  // long buckets get their key runs in z, w instead
+    if (len <= kRunBucket) {
+        c0 = 1;
+#pragma unroll 1
+        for (uint32_t i = 1; i < len; ++i) c0 += k[i] == k0;
+    }
+    return make_uint4(len, start, k0, c0);
 }
 
 template <>
