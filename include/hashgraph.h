@@ -66,9 +66,10 @@ typedef struct hg_build_opts {
                           choose from N and V.                                 */
     uint32_t block;    /* V1: threads per block, 0 = 256                        */
     int32_t no_index;  /* V2 also writes a probe index beside the CSR arrays:
-                          one 16-byte entry per bucket holding its start, its
-                          end and its first keys (two 32-bit keys, or one
-                          64-bit key), so a probe of a short bucket takes one
+                          one 16-byte entry per bucket holding its length and
+                          either all its keys (up to three 32-bit keys) or its
+                          start and first key (32-bit keys: with that key's
+                          count in the bucket), so most probes take one
                           random read.  Buckets of more than 32 entries get a
                           key-run summary instead (distinct keys ascending,
                           each with its count and its ids grouped), so probes
