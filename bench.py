@@ -661,7 +661,7 @@ def main():
         coll.free()
         coll2.free()
         del dkc, doc, dpc, kc, oc, pc
-        # 2^30 keys, V = 2^30 (two partition passes of 9 and 10 bits)
+        # 2^30 keys, V = 2^30 (two partition passes of 9 bits each)
         log("2^30 keys")
         n30 = 1 << 30
         k30 = hg.to_device(workloads.uniform_keys(n30, 32, seed=8))

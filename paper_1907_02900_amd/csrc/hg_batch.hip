@@ -251,7 +251,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_blocal(
     const BTable<Key>& tb = tabs[i];
     const uint32_t L = end - start;
     if (lb + 1 == tb.bins && threadIdx.x == 0) tb.offsets[tb.V] = tb.n;
-    if (L > kLightCap) {
+    if (L > light_cap<Key>()) {
         if (threadIdx.x == 0) heavy_list[atomicAdd(heavy_count, 1u)] = gb;
         return;
     }
@@ -465,7 +465,7 @@ struct BatchPlan : BatchPlanBase {
             tb.bins = bins;
             if (it.n == 0) {
                 tb.kind = kEmpty;
-            } else if (bins == 1 && it.n <= kLightCap) {
+            } else if (bins == 1 && it.n <= light_cap<Key>()) {
                 tb.kind = kDirect;
             } else {
                 tb.kind = kPartitioned;

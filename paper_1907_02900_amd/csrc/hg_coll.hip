@@ -50,7 +50,8 @@ constexpr uint32_t kGroupBuckets = 2 * kGroupW;   // buckets a window's sets can
 constexpr uint32_t kPairItems = 8;                // work items per thread
 constexpr uint32_t kPairChunk = kT * kPairItems;  // work items per workgroup
 
-static_assert(kLightCap >= 3 * kGroupW / 2, "a window's keys must fit one LDS bin");
+static_assert(light_cap<uint32_t>() >= 3 * kGroupW / 2 && light_cap<uint64_t>() >= 3 * kGroupW / 2,
+              "a window's keys must fit one LDS bin");
 
 uint32_t grid_of(uint64_t n) {
     const uint64_t g = ceil_div(n, kT);
@@ -148,7 +149,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_coll_groups(
     const uint32_t ns = s1 - s0, key0 = set_off[s0], L = set_off[s1] - key0;
     const uint64_t B0 = bb[s0];
     const uint32_t NBk = (uint32_t)(bb[s1] - B0);
-    if (L > kLightCap || NBk > kGroupBuckets || ns > kGroupBuckets) {  // excluded by the packing
+    if (L > light_cap<Key>() || NBk > kGroupBuckets || ns > kGroupBuckets) {  // excluded by the packing
         if (threadIdx.x == 0) *bad = 1;
         return;
     }

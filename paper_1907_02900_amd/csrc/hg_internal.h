@@ -57,10 +57,16 @@ struct Carver {
 constexpr int kPartThreads = 256;
 constexpr int kPartItems = 16;
 constexpr uint32_t kPartTile = kPartThreads * kPartItems;  // entries per tile
-constexpr int kLocalThreads = 256;
-constexpr int kLightItems = 12;
-constexpr uint32_t kLightCap = kLocalThreads * kLightItems;  // keys a bin may hold in LDS
-constexpr int kHeavyItems = 16;
+constexpr int kLocalThreads = 512;
+// Keys per thread a bin held in LDS may have, and the bin's capacity: 9 for
+// 32-bit keys (4608 keys, bins planned at about 4096); 6 for 64-bit keys
+// (3072 keys, bins planned at about 2048, so that a bin's LDS leaves room for
+// more workgroups per CU).
+template <typename Key>
+constexpr int light_items() { return sizeof(Key) == 8 ? 6 : 9; }
+template <typename Key>
+constexpr uint32_t light_cap() { return kLocalThreads * light_items<Key>(); }
+constexpr int kHeavyItems = 8;
 constexpr uint32_t kHeavyChunk = kLocalThreads * kHeavyItems;  // chunk of an oversize bin
 constexpr uint32_t kSliceKeys = 1u << 17;  // bins above this are split over workgroups
 constexpr uint32_t kMaxLocalBits = 12;                          // buckets per bin <= 4096

@@ -346,6 +346,7 @@ __global__ __launch_bounds__(1024) void k_segs_from_bases(const uint32_t* __rest
 // and slice_owner maps every slice back to its entry.  ctr: oversize bins,
 // split bins, slices.
 __global__ void k_bin_starts(const uint32_t* __restrict__ base, Segs g, uint32_t bits,
+                             uint32_t light_keys,
                              uint32_t bins, uint32_t n, uint32_t V, uint32_t* __restrict__ bin_start,
                              uint32_t* __restrict__ offsets, uint32_t* __restrict__ heavy_list,
                              uint32_t* __restrict__ ctr, uint32_t* __restrict__ huge_list,
@@ -367,7 +368,7 @@ __global__ void k_bin_starts(const uint32_t* __restrict__ base, Segs g, uint32_t
         if (b == bins) offsets[V] = n;
         if (b < bins) {
             nx = start_of(b + 1);
-            have = nx - st > kLightCap;
+            have = nx - st > light_keys;
         }
     }
     if (have) {
@@ -523,7 +524,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_huge_index(
 }
 
 // One workgroup per final bin g (buckets [g*2^k, min((g+1)*2^k, V))) that
-// holds at most kLightCap keys.
+// holds at most light_cap<Key>() keys.
 template <typename Key>
 __global__ __launch_bounds__(kLocalThreads) void k_local_light(
     const Key* __restrict__ src_keys, const uint32_t* __restrict__ src_ids,
@@ -534,7 +535,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_local_light(
     const uint32_t g = blockIdx.x;
     const uint32_t start = bin_start[g], end = bin_start[g + 1];
     const uint32_t L = end - start;
-    if (L > kLightCap) return;  // oversize bins go to k_local_heavy
+    if (L > light_cap<Key>()) return;  // oversize bins go to k_local_heavy
     const uint32_t NB = 1u << k, v0 = g << k, V = hp.range;
     const uint32_t nb = (V - v0 < NB) ? V - v0 : NB;
     light_bin_body<Key>(src_keys + start, src_ids + start, 0u, L, start, v0, k, nb, hp, offsets,
@@ -568,7 +569,6 @@ __global__ __launch_bounds__(kLocalThreads) void k_local_heavy(
 // ------------------------------------------------------------------ plan --
 
 V2Plan plan_v2(uint64_t n, uint64_t V, int key_bits, uint32_t bins_hint) {
-    (void)key_bits;
     V2Plan p;
     p.n = n;
     p.V = V;
@@ -578,8 +578,11 @@ V2Plan plan_v2(uint64_t n, uint64_t V, int key_bits, uint32_t bins_hint) {
     } else if (n == 0) {
         k = kMaxLocalBits;
     } else {
-        // about 2048 keys per final bin: 2^k * n / V ~ 2048
-        const double r = 2048.0 * (double)V / (double)n;
+        // about 4096 keys per final bin for 32-bit keys (2^k * n / V ~ 4096),
+        // 2048 for 64-bit keys, whose LDS bin then still leaves room for two
+        // workgroups per CU
+        const double target = key_bits == 64 ? 2048.0 : 4096.0;
+        const double r = target * (double)V / (double)n;
         k = 0;
         while (k < kMaxLocalBits && (double)(1ull << (k + 1)) <= r) ++k;
     }
@@ -812,7 +815,8 @@ hipError_t run_build_v2(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, 
     {
         HG_PROF("v2_bin_starts", s);
         hipLaunchKernelGGL(k_bin_starts, dim3((uint32_t)ceil_div(p.bins + 1, 256)), dim3(256), 0,
-                           s, bin_mat, bin_segs, bin_bits, p.bins, (uint32_t)n, (uint32_t)V,
+                           s, bin_mat, bin_segs, bin_bits, light_cap<Key>(), p.bins, (uint32_t)n,
+                           (uint32_t)V,
                            w.bin_start, offsets, w.heavy_list, w.ctr, w.huge_list, w.huge_s0,
                            w.slice_owner, w.huge_cap, w.slice_cap);
     }

@@ -245,7 +245,7 @@ __device__ __forceinline__ uint32_t scan_counts_max(uint32_t* cnt, uint32_t NB, 
 template <typename Key>
 __host__ __device__ inline size_t light_smem(uint32_t k) {
     const size_t NB = 1u << k;
-    return kLightCap * (sizeof(Key) + 4 + 2) + NB * 4 + W_LOCAL * 64 * 4 + 64 * 4 +
+    return light_cap<Key>() * (sizeof(Key) + 4 + 2) + NB * 4 + W_LOCAL * 64 * 4 + 64 * 4 +
            (2 * W_LOCAL + 2) * 4 + 64;
 }
 
@@ -313,7 +313,7 @@ __device__ __forceinline__ void put_tally(const IndexOut& ix, uint32_t g, uint32
     if (threadIdx.x == 0) ix.bin_tally[g] = make_uint2(tc, tl);
 }
 
-// Build one bin of L <= kLightCap keys whose buckets are [v0, v0 + nb) with
+// Build one bin of L <= light_cap<Key>() keys whose buckets are [v0, v0 + nb) with
 // nb <= 2^k.  Entry e (e < L) of the bin is src_keys[e], with id src_ids[e]
 // (or id_base + e when src_ids is null).  The bin's keys and ids go to
 // ekeys/ids[out + p] for p < L, sorted by bucket with ids ascending inside a
@@ -336,7 +336,8 @@ __device__ __forceinline__ void light_bin_body_by(const Key* __restrict__ src_ke
                                                   const IndexOut& ix, uint32_t* __restrict__ ids,
                                                   Key* __restrict__ ekeys, unsigned char* smem,
                                                   bool any_order) {
-    constexpr int IT = kLightItems;
+    constexpr int IT = light_items<Key>();
+    constexpr uint32_t kLightCap = light_cap<Key>();
     const uint32_t NB = 1u << k;
     Key* skeys = (Key*)smem;
     uint32_t* sids = (uint32_t*)(skeys + kLightCap);

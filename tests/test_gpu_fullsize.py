@@ -155,8 +155,8 @@ def test_full_uint64_keys(hg):
 
 
 def test_full_2p30_keys_two_tier_build(hg):
-    # 2^30 keys, V = 2^30: 2^19 final bins reached by two partition passes of
-    # 9 and 10 bits; the table is checked by the same properties, and the
+    # 2^30 keys, V = 2^30: 2^18 final bins reached by two partition passes of
+    # 9 bits each; the table is checked by the same properties, and the
     # counts of 2^20 sampled queries against the oracle
     n = 1 << 30
     say("2^30 keys, V = 2^30")
