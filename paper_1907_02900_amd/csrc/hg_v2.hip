@@ -3,8 +3,9 @@
 // The paper's idea -- first move keys into bins of contiguous bucket ranges so
 // that the final placement is cache-local -- mapped onto CDNA4 without any
 // global atomics:
-//   * a final bin is a power-of-two range of 2^k buckets holding about 2048
-//     keys on average, so that its keys, ids and bucket counters fit in LDS;
+//   * a final bin is a power-of-two range of 2^k buckets holding about 4096
+//     32-bit keys (2048 64-bit keys) on average, so that its keys, ids and
+//     bucket counters fit in the LDS of one 512-thread workgroup;
 //   * keys reach their final bin by one or two stable partition passes over a
 //     digit (a bit-field) of the bucket index.  Each pass is: per-tile digit
 //     histograms (LDS), a segmented column scan of the tile x digit matrix
