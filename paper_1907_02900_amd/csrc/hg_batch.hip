@@ -643,7 +643,9 @@ hg_status create_plan(const hg_batch_item* items, uint32_t count, const hg_batch
     }
     const bool tune = cands.empty() && (!opts || opts->autotune != 0);
     if (cands.empty()) {
-        if (tune) cands = {1024u, 2048u};
+        // a light bin holds up to light_cap<Key>() keys (4608 / 3072)
+        if (tune && sizeof(Key) == 4) cands = {1024u, 2048u, 4096u};
+        else if (tune) cands = {1024u, 2048u};
         else cands = {2048u};
     }
     BatchPlan<Key>* best = nullptr;
