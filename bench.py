@@ -545,6 +545,13 @@ def main():
                                                        t_pr1))
         big.free()
         del big
+        # all matching pairs of the step's probe (two passes: counts and
+        # offsets, then the pairs)
+        _, _, npairs = hg.hg_probe_pairs(table, dq, capacity=0)
+        t_pairs = timed(lambda: hg.hg_probe_pairs(table, dq, capacity=npairs), reps, torch)
+        ex["probe_pairs_2^28"] = {"ms": round(t_pairs, 3), "pairs": npairs,
+                                  "G_pairs_per_s": round(npairs / t_pairs / 1e6, 3)}
+        log("pairs: %d in %.3f ms" % (npairs, t_pairs))
         # Probe-New (Alg. 3): build the query table, then intersect (counts)
         tq = hg.Table.create(m, V, 32)
         cb = torch.empty(m, dtype=torch.int32, device="cuda")

@@ -190,46 +190,79 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_pairs(
     const uint64_t* __restrict__ positions, uint32_t* __restrict__ build_ids,
     uint32_t* __restrict__ probe_ids) {
     using HK = HeadKeys<Key>;
-    uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t st = (uint64_t)gridDim.x * blockDim.x;
-    for (; j < m; j += st) {
-        const Key k = q[j];
-        const uint32_t h = KeyTraits<Key>::bucket(k, hp);
-        uint32_t start, len, n = 0;  // n: leading keys held in the entry
-        uint4 e = make_uint4(0u, 0u, 0u, 0u);
-        if (HEAD) {
-            e = head[h];
-            len = e.x;
-            const bool longb = len > kRunBucket;
-            if (longb && e.z != ~0u) {
-                // the ids of q's run, in bucket order
-                uint64_t pos = positions[j];
-                const uint32_t r = find_run(runs.key, e.z, e.w, k);
-                if (r != ~0u)
-                    for (uint32_t t = runs.pos[r], te = t + runs.cnt[r]; t < te; ++t) {
-                        build_ids[pos] = runs.kperm[t];
-                        probe_ids[pos] = (uint32_t)j;
-                        ++pos;
-                    }
-                continue;
-            }
-            n = longb ? 0u : HK::stored(len);
-            if (HK::has_start(len)) {
-                start = e.y;
-            } else {
-                // every key is in the entry: the ids need the bucket's start
-                bool any = false;
-                for (uint32_t i = 0; i < n; ++i) any |= HK::key(e, len, i) == k;
-                if (!any) continue;
-                start = off[h];
-            }
+    // as in k_probe_count: every thread first loads the index entries (or
+    // offsets) of its kProbeItems queries, so that their random reads overlap
+    const uint64_t base = (uint64_t)blockIdx.x * (kProbeThreads * kProbeItems) + threadIdx.x;
+    Key qq[kProbeItems];
+    uint32_t hh[kProbeItems];
+    uint4 e[kProbeItems];
+#pragma unroll
+    for (int r = 0; r < kProbeItems; ++r) {
+        const uint64_t j = base + (uint64_t)r * kProbeThreads;
+        qq[r] = (j < m) ? q[j] : (Key)0;
+    }
+#pragma unroll
+    for (int r = 0; r < kProbeItems; ++r) {
+        const uint64_t j = base + (uint64_t)r * kProbeThreads;
+        hh[r] = KeyTraits<Key>::bucket(qq[r], hp);
+        if (j >= m) {
+            e[r] = make_uint4(0u, 0u, 0u, 0u);
+        } else if (HEAD) {
+            e[r] = head[hh[r]];
         } else {
-            start = off[h];
-            len = off[h + 1] - start;
+            e[r].x = off[hh[r]];
+            e[r].y = off[hh[r] + 1];
         }
+    }
+    // where each query's bucket starts (a bucket whose keys are all in its
+    // entry needs offsets[h], read only when one of those keys matches), and
+    // how many leading keys the entry holds; the loads overlap across queries
+    uint32_t st[kProbeItems], nn[kProbeItems];
+    bool skip[kProbeItems], via_runs[kProbeItems];
+#pragma unroll
+    for (int r = 0; r < kProbeItems; ++r) {
+        const uint64_t j = base + (uint64_t)r * kProbeThreads;
+        const uint4 er = e[r];
+        skip[r] = j >= m;
+        via_runs[r] = false;
+        nn[r] = 0;
+        st[r] = er.x;
+        if (HEAD && !skip[r]) {
+            const uint32_t len = er.x;
+            const bool longb = len > kRunBucket;
+            via_runs[r] = longb && er.z != ~0u;
+            nn[r] = longb ? 0u : HK::stored(len);
+            if (HK::has_start(len)) {
+                st[r] = er.y;
+            } else {
+                bool any = false;
+                for (uint32_t i = 0; i < nn[r]; ++i) any |= HK::key(er, len, i) == qq[r];
+                skip[r] = !any;
+                st[r] = any ? off[hh[r]] : 0u;
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < kProbeItems; ++r) {
+        if (skip[r]) continue;
+        const uint64_t j = base + (uint64_t)r * kProbeThreads;
+        const Key k = qq[r];
+        const uint4 er = e[r];
         uint64_t pos = positions[j];
+        if (via_runs[r]) {
+            // the ids of q's run, in bucket order
+            const uint32_t rr = find_run(runs.key, er.z, er.w, k);
+            if (rr != ~0u)
+                for (uint32_t t = runs.pos[rr], te = t + runs.cnt[rr]; t < te; ++t) {
+                    build_ids[pos] = runs.kperm[t];
+                    probe_ids[pos] = (uint32_t)j;
+                    ++pos;
+                }
+            continue;
+        }
+        const uint32_t start = st[r], len = HEAD ? er.x : er.y - er.x, n = nn[r];
         for (uint32_t p = start; p < start + len; ++p)
-            if ((p - start < n ? HK::key(e, len, p - start) : ekeys[p]) == k) {
+            if ((p - start < n ? HK::key(er, len, p - start) : ekeys[p]) == k) {
                 build_ids[pos] = eids[p];
                 probe_ids[pos] = (uint32_t)j;
                 ++pos;
@@ -374,8 +407,7 @@ hipError_t run_probe_pairs(const TableDev& t, const Key* queries, uint64_t m,
                            hipStream_t s) {
     if (m == 0) return hipSuccess;
     auto hp = KeyTraits<Key>::make(t.V, t.seed);
-    uint32_t g = grid_for(m, kProbeThreads);
-    if (g > 8192) g = 8192;
+    const uint32_t g = grid_for(m, kProbeThreads * kProbeItems);
     {
         HG_PROF("probe_pairs", s);
         if (t.head)

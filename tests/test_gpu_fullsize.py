@@ -113,6 +113,30 @@ def test_full_uniform_bench_configuration(hg, uniform):
     table.free()
 
 
+def test_full_uniform_pairs_materialised(hg, uniform):
+    """All ~1.5e8 matching pairs of the 2^28 x 2^28 uniform workload: the
+    total equals the oracle's, every pair joins equal keys, each probe id
+    appears exactly its oracle count times, probe ids ascend, and (stable
+    table) build ids ascend inside each probe id, which with the counts
+    leaves exactly the oracle's pair set."""
+    keys, q, exp, etot = uniform
+    V = N
+    say("pairs, n = V = m = 2^28")
+    dk, dq = hg.to_device(keys), hg.to_device(q)
+    table = hg.hg_build(dk, V, seed=0)
+    b, p, tot = hg.hg_probe_pairs(table, dq)
+    torch.cuda.synchronize()
+    assert tot == etot
+    bi, pi = u64(b), u64(p)
+    assert bool((pi[1:] >= pi[:-1]).all())
+    cnt = torch.bincount(pi, minlength=N)
+    assert np.array_equal(cnt.cpu().numpy().astype(np.uint32), exp)
+    assert bool((u64(dk)[bi] == u64(dq)[pi]).all())
+    same = pi[1:] == pi[:-1]
+    assert bool((bi[1:][same] > bi[:-1][same]).all())
+    table.free()
+
+
 @pytest.mark.parametrize("log2V", [26, 28, 30])
 def test_full_range_sweep_v1_and_v2(hg, uniform, log2V):
     keys, q, exp, etot = uniform
