@@ -585,19 +585,19 @@ struct BatchPlan : BatchPlanBase {
 
 template <typename Key>
 static hipError_t set_batch_smem() {
-    static bool done = false;
-    if (done) return hipSuccess;
-    const int lim = 160 * 1024;
-    HG_TRY(hipFuncSetAttribute((const void*)k_bpart<Key, true>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, lim));
-    HG_TRY(hipFuncSetAttribute((const void*)k_bpart<Key, false>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, lim));
-    HG_TRY(hipFuncSetAttribute((const void*)k_blocal<Key>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, lim));
-    HG_TRY(hipFuncSetAttribute((const void*)k_bheavy<Key>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, lim));
-    done = true;
-    return hipSuccess;
+    static std::atomic<uint64_t> done{0};
+    return once_per_device(done, [] {
+        const int lim = 160 * 1024;
+        HG_TRY(hipFuncSetAttribute((const void*)k_bpart<Key, true>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+        HG_TRY(hipFuncSetAttribute((const void*)k_bpart<Key, false>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+        HG_TRY(hipFuncSetAttribute((const void*)k_blocal<Key>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+        HG_TRY(hipFuncSetAttribute((const void*)k_bheavy<Key>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+        return hipSuccess;
+    });
 }
 
 // Autotuning cache: (tables, total keys, total queries, key bits) -> target.

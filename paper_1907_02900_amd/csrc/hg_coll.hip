@@ -391,12 +391,13 @@ __global__ void k_zero_u64(unsigned long long* __restrict__ p, uint64_t n) {
 
 template <typename Key>
 hipError_t set_group_smem() {
-    static bool done = false;
-    if (done) return hipSuccess;
-    HG_TRY(hipFuncSetAttribute((const void*)k_coll_groups<Key>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)groups_smem<Key>()));
-    done = true;
-    return hipSuccess;
+    static std::atomic<uint64_t> done{0};
+    return once_per_device(done, [] {
+        HG_TRY(hipFuncSetAttribute((const void*)k_coll_groups<Key>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)groups_smem<Key>()));
+        return hipSuccess;
+    });
 }
 
 hipError_t copy_to_host(void* h, const void* d, size_t bytes, hipStream_t s) {

@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include "hg_device.h"
 
 namespace hg {
@@ -15,6 +17,21 @@ namespace hg {
         hipError_t e__ = (expr);            \
         if (e__ != hipSuccess) return e__;  \
     } while (0)
+
+// Calls f() the first time it is reached with a given device current and
+// then never again for that device (kernel attributes such as the dynamic LDS
+// limit are set per device).  Two threads arriving together may both call f,
+// which must therefore be idempotent; a failed f is tried again next time.
+template <typename F>
+hipError_t once_per_device(std::atomic<uint64_t>& done, F&& f) {
+    int dev = 0;
+    HG_TRY(hipGetDevice(&dev));
+    const uint64_t bit = dev >= 0 && dev < 64 ? 1ull << dev : 0;
+    if (bit && (done.load(std::memory_order_acquire) & bit)) return hipSuccess;
+    HG_TRY(f());
+    done.fetch_or(bit, std::memory_order_release);
+    return hipSuccess;
+}
 
 inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 inline uint32_t log2_ceil(uint64_t x) {

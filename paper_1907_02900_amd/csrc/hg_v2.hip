@@ -730,25 +730,25 @@ hipError_t partition_pass(const Key* src_keys, const uint32_t* src_ids, Key* dst
 
 template <typename Key>
 hipError_t set_smem_limits() {
-    static bool done = false;
-    if (done) return hipSuccess;
-    const int lim = 160 * 1024;
-    HG_TRY(hipFuncSetAttribute((const void*)k_tile_partition<Key, true, true>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, lim));
-    HG_TRY(hipFuncSetAttribute((const void*)k_tile_partition<Key, false, true>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, lim));
-    HG_TRY(hipFuncSetAttribute((const void*)k_tile_partition<Key, true, false>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, lim));
-    HG_TRY(hipFuncSetAttribute((const void*)k_tile_partition<Key, false, false>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, lim));
-    HG_TRY(hipFuncSetAttribute((const void*)k_local_light<Key>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, lim));
-    HG_TRY(hipFuncSetAttribute((const void*)k_local_heavy<Key>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, lim));
-    HG_TRY(hipFuncSetAttribute((const void*)k_huge_place<Key>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, lim));
-    done = true;
-    return hipSuccess;
+    static std::atomic<uint64_t> done{0};
+    return once_per_device(done, [] {
+        const int lim = 160 * 1024;
+        HG_TRY(hipFuncSetAttribute((const void*)k_tile_partition<Key, true, true>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+        HG_TRY(hipFuncSetAttribute((const void*)k_tile_partition<Key, false, true>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+        HG_TRY(hipFuncSetAttribute((const void*)k_tile_partition<Key, true, false>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+        HG_TRY(hipFuncSetAttribute((const void*)k_tile_partition<Key, false, false>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+        HG_TRY(hipFuncSetAttribute((const void*)k_local_light<Key>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+        HG_TRY(hipFuncSetAttribute((const void*)k_local_heavy<Key>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+        HG_TRY(hipFuncSetAttribute((const void*)k_huge_place<Key>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+        return hipSuccess;
+    });
 }
 
 }  // namespace
