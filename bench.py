@@ -89,7 +89,8 @@ def kernel_bytes(name, n, m, V, kb, sum_len, plan, sum_tail=None):
     With the per-bucket probe index (sum_tail given), a query reads its
     bucket's 16-byte entry and only the keys the entry does not account for
     (all of a bucket of up to three 32-bit keys; in a longer one the first
-    key and its count); without it,
+    key and its count, and the rest of the bucket when the entry's filter
+    rules the query out); without it,
     two offsets and every key of its bucket.  The V2 local build writes the
     index (16 bytes per bucket) beside offsets, ids and keys."""
     if name == "probe_count":
@@ -453,15 +454,27 @@ def main():
     blen = offl[h + 1] - offl[h]
     sum_len = int(blen.sum().item())
     # a bucket of up to 3 keys is held whole in its index entry; a longer one
-    # holds its first key and that key's count, and a query equal to the first
-    # key needs nothing more; other queries read the rest of the bucket (the
-    # shortcut for buckets of one repeated key is left out: it does not occur
-    # with uniform 32-bit keys at these sizes)
-    first = (ek.to(torch.int64) & 0xFFFFFFFF)[offl[h].clamp_(max=n - 1)]
-    reads = (blen > 3) & ((dq.to(torch.int64) & 0xFFFFFFFF) != first)
+    # holds its first key, that key's count and a 24-bit filter of its other
+    # keys: a query equal to the first key, or whose filter bit no other key
+    # of the bucket sets, needs nothing more; other queries read the rest of
+    # the bucket (a bucket of more than 32 keys is counted as read whole)
+    eku = ek.to(torch.int64) & 0xFFFFFFFF
+    qu = dq.to(torch.int64) & 0xFFFFFFFF
+    first = eku[offl[h].clamp(max=n - 1)]
+    reads = (blen > 3) & (qu != first)
+    sel = torch.nonzero(reads).squeeze(1)
+    if sel.numel():
+        def fbit(x):  # the entry's filter bit of a key (multiplicative hash)
+            return (((x * 0x9E3779B1) & 0xFFFFFFFF) * 24) >> 32
+        st, ln = offl[h[sel]], blen[sel]
+        pos = st[:, None] + torch.arange(1, int(ln.max().item()), device=st.device)[None, :]
+        kk = eku[pos.clamp(max=n - 1)]
+        other = (pos < (st + ln)[:, None]) & (kk != first[sel][:, None])
+        reads[sel] = (other & (fbit(kk) == fbit(qu[sel])[:, None])).any(1) | (ln > 32)
+        del st, ln, pos, kk, other
     sum_tail = int(((blen - 1) * reads).sum().item())
     n_tail = int(reads.sum().item())  # queries that also read the edge array
-    del h, offl, off, blen, ek, first, reads
+    del h, offl, off, blen, ek, eku, qu, first, reads, sel
 
     plan = v2_plan_bytes(n, V)
     kernels = {}

@@ -145,6 +145,18 @@ hipError_t run_build_v1(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, 
 // key-grouped copy of the bucket's ids.
 constexpr uint32_t kRunBucket = 32;
 
+// A 32-bit-key bucket of 4..kRunBucket entries keeps, beside its first key and
+// that key's count (low 8 bits of the entry's w), a 24-bit filter of its other
+// keys (w's high 24 bits): bit filter_bit(k) is set for every key k of the
+// bucket that differs from the first.  A query whose bit is clear matches
+// nothing past the first key, so the edge array is not read.  The bit comes
+// from a multiplicative hash of the key, not from the bucket hash, so keys of
+// one bucket spread over the 24 bits.
+constexpr uint32_t kFilterBits = 24;
+__host__ __device__ inline uint32_t filter_bit(uint32_t k) {
+    return (uint32_t)(((uint64_t)(k * 0x9E3779B1u) * kFilterBits) >> 32);
+}
+
 // Where a V2 build writes its probe index (head == null: none).  Every final
 // bin also writes bin_tally[bin] = {buckets longer than kRunBucket, their
 // total length} with plain stores (no device atomics: same-address atomics

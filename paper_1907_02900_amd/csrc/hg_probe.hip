@@ -50,7 +50,8 @@ __device__ __forceinline__ uint32_t count_in_bucket(const Key* __restrict__ ekey
 
 // What a probe index entry holds (x = the bucket's length; see head_entry):
 // 32-bit keys: all keys of a bucket of at most three in y, z, w, else the
-// start in y, the first key in z and the number of entries equal to it in w;
+// start in y, the first key in z and, in w, the number of entries equal to it
+// (low 8 bits) and the filter of the bucket's other keys (high 24 bits);
 // 64-bit keys: the start in y and the first key in z, w.  A bucket longer
 // than kRunBucket has its key-run summary in z, w instead.
 template <typename Key>
@@ -117,11 +118,12 @@ __device__ __forceinline__ uint32_t count_with_head(const uint4& e, const Key* _
         return r != ~0u ? runs.cnt[r] : 0u;
     }
     if (sizeof(Key) == 4 && len > HeadKeys<uint32_t>::full) {
-        // {len, start, first key, its count}: the first key's matches are
-        // counted in the entry; the rest of the bucket is read only when it
-        // holds other keys and the query is not the first key
-        if ((uint32_t)q == e.z) return e.w;
-        if (e.w == len) return 0u;
+        // {len, start, first key, its count | filter}: the first key's
+        // matches are counted in the entry; the rest of the bucket is read
+        // only when the query is not the first key and its filter bit is set
+        // (a clear bit: no other key of the bucket equals q)
+        if ((uint32_t)q == e.z) return e.w & 0xffu;
+        if (!((e.w >> (8 + filter_bit((uint32_t)q))) & 1u)) return 0u;
         return count_in_bucket(ekeys, e.y + 1, e.y + len, q);
     }
     const uint32_t n = HK::stored(len);

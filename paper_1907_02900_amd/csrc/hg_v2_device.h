@@ -258,12 +258,14 @@ inline size_t heavy_smem(uint32_t k) {
 
 // Probe index entry of one bucket, x = its length.  32-bit keys: a bucket of
 // at most three keys holds them all in y, z, w (its start is not needed to
-// count matches); a longer one holds {len, start, first key, entries equal to
-// the first key}, so a query equal to the first key, or any query against a
-// bucket of one repeated key, is answered without reading the edge array.
-// 64-bit keys: {len, start, low and high half of the first key}.  Unused key
-// slots are 0.  A bucket longer than kRunBucket later gets its key-run
-// summary in z, w.  `k` points at the bucket's first key.
+// count matches); a longer one holds {len, start, first key, c0 | filter << 8}
+// with c0 the entries equal to the first key and the filter of the other keys
+// (filter_bit), so a query equal to the first key, any query against a bucket
+// of one repeated key, and most queries matching no other key are answered
+// without reading the edge array.  64-bit keys: {len, start, low and high
+// half of the first key}.  Unused key slots are 0.  A bucket longer than
+// kRunBucket later gets its key-run summary in z, w.  `k` points at the
+// bucket's first key.
 template <typename Key>
 __device__ __forceinline__ uint4 head_entry(uint32_t start, uint32_t end, const Key* k);
 
@@ -274,13 +276,24 @@ __device__ __forceinline__ uint4 head_entry<uint32_t>(uint32_t start, uint32_t e
     if (len <= 3)
         return make_uint4(len, len >= 1 ? k[0] : 0u, len >= 2 ? k[1] : 0u, len >= 3 ? k[2] : 0u);
     const uint32_t k0 = k[0];
-    uint32_t c0 = 0;  // long buckets get their key runs in z, w instead
+    uint32_t c0 = 0, filt = 0;  // long buckets get their key runs in z, w instead
     if (len <= kRunBucket) {
         c0 = 1;
+        // four keys per round, so that their loads overlap
 #pragma unroll 1
-        for (uint32_t i = 1; i < len; ++i) c0 += k[i] == k0;
+        for (uint32_t i = 1; i < len; i += 4) {
+            uint32_t kv[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) kv[j] = i + j < len ? k[i + j] : k0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (i + j >= len) continue;
+                if (kv[j] == k0) ++c0;
+                else filt |= 1u << filter_bit(kv[j]);
+            }
+        }
     }
-    return make_uint4(len, start, k0, c0);
+    return make_uint4(len, start, k0, c0 | filt << 8);
 }
 
 template <>

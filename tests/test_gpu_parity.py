@@ -213,7 +213,9 @@ def test_table_rebuild_reuses_capacity(hg):
                                         ("uniform", 100003, 200001, 100003),
                                         ("dup8", 300000, 300000, 1 << 16),
                                         ("zipf", 200000, 300000, 200000),
-                                        ("uniform", 50000, 50000, 1)])
+                                        ("uniform", 50000, 50000, 1),
+                                        # load 8: most buckets hold 4..32 keys
+                                        ("uniform", 400000, 300000, 50000)])
 def test_probe_counts_match_oracle(hg, kb, variant, kind, n, m, V):
     say("probe", kb, variant, kind, n, m, V)
     k = keys_for(kind, n, kb, seed=1)
