@@ -70,7 +70,9 @@ typedef struct hg_build_opts {
                           either all its keys (up to three 32-bit keys) or its
                           start and first key (32-bit keys: with that key's
                           count in the bucket and a 24-bit filter of the
-                          bucket's other keys), so most probes take one
+                          bucket's other keys; 64-bit keys: a filter of all
+                          keys in place of the first key when the bucket
+                          holds two or more), so most probes take one
                           random read.  Buckets of more than 32 entries get a
                           key-run summary instead (distinct keys ascending,
                           each with its count and its ids grouped), so probes

@@ -157,6 +157,15 @@ __host__ __device__ inline uint32_t filter_bit(uint32_t k) {
     return (uint32_t)(((uint64_t)(k * 0x9E3779B1u) * kFilterBits) >> 32);
 }
 
+// A 64-bit-key bucket of 2..kRunBucket entries keeps a 64-bit filter of all
+// its keys in place of the first key: two bits per key, from the top twelve
+// bits of a multiplicative hash.  A query with either bit clear matches none
+// of the bucket's keys.
+__host__ __device__ inline uint64_t filter_bits64(uint64_t k) {
+    const uint64_t x = k * 0x9E3779B97F4A7C15ull;
+    return (1ull << (x >> 58)) | (1ull << ((x >> 52) & 63u));
+}
+
 // Where a V2 build writes its probe index (head == null: none).  Every final
 // bin also writes bin_tally[bin] = {buckets longer than kRunBucket, their
 // total length} with plain stores (no device atomics: same-address atomics

@@ -52,8 +52,9 @@ __device__ __forceinline__ uint32_t count_in_bucket(const Key* __restrict__ ekey
 // 32-bit keys: all keys of a bucket of at most three in y, z, w, else the
 // start in y, the first key in z and, in w, the number of entries equal to it
 // (low 8 bits) and the filter of the bucket's other keys (high 24 bits);
-// 64-bit keys: the start in y and the first key in z, w.  A bucket longer
-// than kRunBucket has its key-run summary in z, w instead.
+// 64-bit keys: the start in y and in z, w the key of a one-key bucket or the
+// filter of a longer bucket's keys.  A bucket longer than kRunBucket has its
+// key-run summary in z, w instead.
 template <typename Key>
 struct HeadKeys;
 
@@ -71,7 +72,7 @@ struct HeadKeys<uint32_t> {
 template <>
 struct HeadKeys<uint64_t> {
     __device__ static bool has_start(uint32_t) { return true; }
-    __device__ static uint32_t stored(uint32_t len) { return len ? 1u : 0u; }
+    __device__ static uint32_t stored(uint32_t len) { return len == 1 ? 1u : 0u; }
     __device__ static uint64_t key(const uint4& e, uint32_t, uint32_t) {
         return (uint64_t)e.z | ((uint64_t)e.w << 32);
     }
@@ -125,6 +126,13 @@ __device__ __forceinline__ uint32_t count_with_head(const uint4& e, const Key* _
         if ((uint32_t)q == e.z) return e.w & 0xffu;
         if (!((e.w >> (8 + filter_bit((uint32_t)q))) & 1u)) return 0u;
         return count_in_bucket(ekeys, e.y + 1, e.y + len, q);
+    }
+    if (sizeof(Key) == 8 && len > 1) {
+        // {len, start, filter of the bucket's keys}: read the bucket only
+        // when both of q's filter bits are set
+        const uint64_t f = (uint64_t)e.z | ((uint64_t)e.w << 32), b = filter_bits64((uint64_t)q);
+        if ((f & b) != b) return 0u;
+        return count_in_bucket(ekeys, e.y, e.y + len, q);
     }
     const uint32_t n = HK::stored(len);
     uint32_t c = 0;

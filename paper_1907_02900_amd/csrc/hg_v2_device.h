@@ -263,9 +263,11 @@ inline size_t heavy_smem(uint32_t k) {
 // (filter_bit), so a query equal to the first key, any query against a bucket
 // of one repeated key, and most queries matching no other key are answered
 // without reading the edge array.  64-bit keys: {len, start, low and high
-// half of the first key}.  Unused key slots are 0.  A bucket longer than
-// kRunBucket later gets its key-run summary in z, w.  `k` points at the
-// bucket's first key.
+// half of the key} for a bucket of at most one key, {len, start, filter of
+// all its keys (filter_bits64), low and high half} for a longer one, so that
+// most queries matching none of its keys skip the edge array.  Unused key
+// slots are 0.  A bucket longer than kRunBucket later gets its key-run
+// summary in z, w.  `k` points at the bucket's first key.
 template <typename Key>
 __device__ __forceinline__ uint4 head_entry(uint32_t start, uint32_t end, const Key* k);
 
@@ -299,8 +301,19 @@ __device__ __forceinline__ uint4 head_entry<uint32_t>(uint32_t start, uint32_t e
 template <>
 __device__ __forceinline__ uint4 head_entry<uint64_t>(uint32_t start, uint32_t end,
                                                       const uint64_t* k) {
-    const uint64_t k0 = (end - start >= 1) ? k[0] : 0ull;
-    return make_uint4(end - start, start, (uint32_t)k0, (uint32_t)(k0 >> 32));
+    const uint32_t len = end - start;
+    uint64_t z = len == 1 ? k[0] : 0ull;
+    if (len >= 2 && len <= kRunBucket) {
+#pragma unroll 1
+        for (uint32_t i = 0; i < len; i += 4) {
+            uint64_t kv[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) kv[j] = i + j < len ? k[i + j] : k[0];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) z |= filter_bits64(kv[j]);
+        }
+    }
+    return make_uint4(len, start, (uint32_t)z, (uint32_t)(z >> 32));
 }
 
 // Write bucket b's index entry (the key slots of a bucket longer than
