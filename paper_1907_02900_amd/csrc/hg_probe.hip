@@ -201,21 +201,26 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_pairs(
     uint32_t* __restrict__ probe_ids) {
     using HK = HeadKeys<Key>;
     // as in k_probe_count: every thread first loads the index entries (or
-    // offsets) of its kProbeItems queries, so that their random reads overlap
+    // offsets) of its kProbeItems queries, so that their random reads overlap;
+    // a query whose output range [positions[j], positions[j+1]) is empty has
+    // no match and reads nothing more
     const uint64_t base = (uint64_t)blockIdx.x * (kProbeThreads * kProbeItems) + threadIdx.x;
     Key qq[kProbeItems];
     uint32_t hh[kProbeItems];
     uint4 e[kProbeItems];
+    uint64_t pend[kProbeItems];
+    bool none[kProbeItems];
 #pragma unroll
     for (int r = 0; r < kProbeItems; ++r) {
         const uint64_t j = base + (uint64_t)r * kProbeThreads;
         qq[r] = (j < m) ? q[j] : (Key)0;
+        pend[r] = (j < m) ? positions[j + 1] : 0ull;
+        none[r] = j >= m || positions[j] == pend[r];
     }
 #pragma unroll
     for (int r = 0; r < kProbeItems; ++r) {
-        const uint64_t j = base + (uint64_t)r * kProbeThreads;
         hh[r] = KeyTraits<Key>::bucket(qq[r], hp);
-        if (j >= m) {
+        if (none[r]) {
             e[r] = make_uint4(0u, 0u, 0u, 0u);
         } else if (HEAD) {
             e[r] = head[hh[r]];
@@ -231,9 +236,8 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_pairs(
     bool skip[kProbeItems], via_runs[kProbeItems];
 #pragma unroll
     for (int r = 0; r < kProbeItems; ++r) {
-        const uint64_t j = base + (uint64_t)r * kProbeThreads;
         const uint4 er = e[r];
-        skip[r] = j >= m;
+        skip[r] = none[r];
         via_runs[r] = false;
         nn[r] = 0;
         st[r] = er.x;
@@ -263,7 +267,8 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_pairs(
             // the ids of q's run, in bucket order
             const uint32_t rr = find_run(runs.key, er.z, er.w, k);
             if (rr != ~0u)
-                for (uint32_t t = runs.pos[rr], te = t + runs.cnt[rr]; t < te; ++t) {
+                for (uint32_t t = runs.pos[rr], te = t + runs.cnt[rr]; t < te && pos < pend[r];
+                     ++t) {
                     build_ids[pos] = runs.kperm[t];
                     probe_ids[pos] = (uint32_t)j;
                     ++pos;
@@ -271,7 +276,7 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_pairs(
             continue;
         }
         const uint32_t start = st[r], len = HEAD ? er.x : er.y - er.x, n = nn[r];
-        for (uint32_t p = start; p < start + len; ++p)
+        for (uint32_t p = start; p < start + len && pos < pend[r]; ++p)
             if ((p - start < n ? HK::key(er, len, p - start) : ekeys[p]) == k) {
                 build_ids[pos] = eids[p];
                 probe_ids[pos] = (uint32_t)j;
