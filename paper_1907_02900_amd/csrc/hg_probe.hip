@@ -353,24 +353,28 @@ __global__ __launch_bounds__(kProbeThreads) void k_intersect_pairs(
     uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t st = (uint64_t)gridDim.x * blockDim.x;
     for (; p < nb; p += st) {
+        // an edge whose output range is empty (no match, or a stale slot of
+        // B, whose count is 0) reads nothing more
+        uint64_t pos = positions[p];
+        const uint64_t pend = positions[p + 1];
+        if (pos == pend) continue;
         const Key k = b_keys[p];
         const uint32_t h = KeyTraits<Key>::bucket(k, hp);
         if (b_len && p - b_off[h] >= b_len[h]) continue;  // stale slot of B
         const uint32_t lo = a_off[h], hi = a_len ? lo + a_len[h] : a_off[h + 1];
         const uint32_t bid = b_ids[p];
-        uint64_t pos = positions[p];
         if (a_head && hi - lo > kRunBucket && a_head[h].z != ~0u) {
             const uint4 e = a_head[h];
             const uint32_t r = find_run(runs.key, e.z, e.w, k);
             if (r != ~0u)
-                for (uint32_t t = runs.pos[r], te = t + runs.cnt[r]; t < te; ++t) {
+                for (uint32_t t = runs.pos[r], te = t + runs.cnt[r]; t < te && pos < pend; ++t) {
                     out_a[pos] = runs.kperm[t];
                     out_b[pos] = bid;
                     ++pos;
                 }
             continue;
         }
-        for (uint32_t i = lo; i < hi; ++i)
+        for (uint32_t i = lo; i < hi && pos < pend; ++i)
             if (a_keys[i] == k) {
                 out_a[pos] = a_ids[i];
                 out_b[pos] = bid;
