@@ -11,11 +11,14 @@ before the timed region; the table and workspace are preallocated, so nothing
 is allocated while timing.  value = (n + m) / step time, in G keys/s.
 
 The JSON line also carries:
-  roofline      the dominant kernel's algorithmic bytes per launch divided by
+  roofline      the dominant kernel's algorithmic bytes per launch (the
+                method's own passes; for the probe its compulsory bytes:
+                query, two offsets, the bucket's keys, the count) divided by
                 its average launch time (HIP events around each launch, on the
                 stream the library launches on), against 8 TB/s;
-  cpu_baseline  the CPU oracle (sequential C) timed on a bounded sample of the
-                same workload on this host;
+  cpu_baseline  the CPU oracle on this host's cores: its multi-core variant
+                on the step's own arrays, and the sequential oracle on a
+                bounded sample;
   phases        per-kernel times, the V1 build, the hash-range sweep
                 {2^26, 2^28, 2^30}, the 64-bit-key variant and Probe-New.
 """
@@ -83,22 +86,27 @@ def timed(fn, reps, torch):
     return float(np.median(out))
 
 
-def kernel_bytes(name, n, m, V, kb, sum_len, plan, sum_tail=None):
-    """Algorithmic bytes one launch of `name` must move (reads + writes).
+def kernel_bytes(name, n, m, V, kb, sum_len, plan):
+    """Algorithmic bytes one launch of `name` must move (reads + writes), by
+    the method's own passes (Sec. 3.3 phases; the probe's compulsory bytes):
 
-    With the per-bucket probe index (sum_tail given), a query reads its
-    bucket's 16-byte entry and only the keys the entry does not account for
-    (all of a bucket of up to three 32-bit keys; in a longer one the first
-    key and its count, and the rest of the bucket when the entry's filter
-    rules the query out); without it,
-    two offsets and every key of its bucket.  The V2 local build writes the
-    index (16 bytes per bucket) beside offsets, ids and keys."""
+      probe_count     a query reads its key, the two offsets of its bucket and
+                      every key of the bucket, and writes its count:
+                      m*kb + 8m + kb*sum(|bucket|) + 4m (about 22 B per query
+                      at load 1 with 50% hits);
+      v2_local_build  phase 3 reads and writes every (key, id) and writes the
+                      offsets: 2n(kb+4) + 4(V+1);
+      v2_partition_*  phase 2: the first pass reads keys and writes (key, id),
+                      a second pass reads and writes (key, id); plus the
+                      tile x digit bases it reads;
+      v2_tile_hist_*  phase 1: reads the keys, writes the tile histograms.
+
+    The per-bucket probe index is this design's addition and is not counted
+    here (index_bytes gives the bytes with it)."""
     if name == "probe_count":
-        if sum_tail is not None:
-            return m * kb + m * 16 + kb * sum_tail + m * 4
-        return m * kb + m * 8 + kb * sum_len + m * 4
+        return m * kb + 8 * m + kb * sum_len + 4 * m
     if name == "v2_local_build":
-        return 2 * n * (kb + 4) + (V + 1) * 4 + (V * 16 if sum_tail is not None else 0)
+        return 2 * n * (kb + 4) + (V + 1) * 4
     if name == "v2_partition_t1":
         return n * kb + n * (kb + 4) + plan["m1_bytes"]
     if name == "v2_partition_t2":
@@ -110,20 +118,24 @@ def kernel_bytes(name, n, m, V, kb, sum_len, plan, sum_tail=None):
     return None
 
 
-def v2_plan_bytes(n, V):
-    # mirrors the library's plan for the tile x digit matrices (4096-key tiles)
-    k = 0
-    r = 2048.0 * V / n
-    while k < 12 and (1 << (k + 1)) <= r:
-        k += 1
-    bins = -(-V // (1 << k))
-    bits = max(0, (bins - 1).bit_length())
-    tiles = -(-n // 4096)
-    if bits <= 9:
-        return {"m1_bytes": tiles * (1 << bits) * 4, "m2_bytes": 0}
-    b1 = (bits + 1) // 2
-    b2 = bits - b1
-    return {"m1_bytes": tiles * (1 << b1) * 4, "m2_bytes": (tiles + (1 << b1)) * (1 << b2) * 4}
+def index_bytes(name, n, m, V, kb, sum_tail):
+    """Bytes the kernels move with the per-bucket probe index: the probe reads
+    one 16-byte entry per query and only the keys the entry does not account
+    for (sum_tail); the per-bin build also writes 16 bytes per bucket."""
+    if name == "probe_count":
+        return m * kb + m * 16 + kb * sum_tail + m * 4
+    if name == "v2_local_build":
+        return 2 * n * (kb + 4) + (V + 1) * 4 + V * 16
+    return None
+
+
+def v2_plan_bytes(hg, n, V, kb=4):
+    """Tile x digit matrix bytes of each partition pass, from the library's
+    own plan (hg_build_plan)."""
+    p = hg.build_plan(n, V, 8 * kb)
+    m1 = p["tiles"][0] * (1 << p["digit_bits"][0]) * 4
+    m2 = p["tiles"][1] * (1 << p["digit_bits"][1]) * 4 if p["passes"] == 2 else 0
+    return {"m1_bytes": m1, "m2_bytes": m2, "plan": p}
 
 
 def load_traffic(kernel, digest):
@@ -345,24 +357,43 @@ def cpu_model():
     return None
 
 
-def cpu_baseline(log2_sample=24):
+def cpu_baseline(keys, queries, V, log2_sample=24):
+    """The CPU oracle on this host: its multi-core variant (OpenMP, the same
+    definitions, bit-identical output) on the step's own arrays -- the stable
+    build of all keys, then the counts of all queries -- and the sequential
+    oracle on a bounded sample of the same workload."""
     import oracle
     from paper_1907_02900_amd import workloads
-    ns = 1 << log2_sample
-    keys = workloads.uniform_keys(ns, 32, seed=0)
-    q = workloads.probe_queries(keys, ns, 0.5, seed=1)
+    n, m = keys.size, queries.size
+    threads = oracle.omp_threads()
     times = []
+    for _ in range(2):
+        t0 = time.perf_counter()
+        oracle.build_table_omp(keys, V, 0)
+        oracle.probe_counts_omp(keys, queries)
+        times.append(time.perf_counter() - t0)
+    t = float(np.min(times))
+    ns = 1 << log2_sample
+    sk = workloads.uniform_keys(ns, 32, seed=0)
+    sq = workloads.probe_queries(sk, ns, 0.5, seed=1)
+    seq = []
     for _ in range(3):
         t0 = time.perf_counter()
-        oracle.build_table(keys, ns, 0)
-        oracle.probe_counts(keys, q)
-        times.append(time.perf_counter() - t0)
-    t = float(np.median(times))
-    return {"value": round(2 * ns / t / 1e9, 5), "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
+        oracle.build_table(sk, ns, 0)
+        oracle.probe_counts(sk, sq)
+        seq.append(time.perf_counter() - t0)
+    ts = float(np.median(seq))
+    return {"value": round((n + m) / t / 1e9, 5), "unit": "Gkeys/s", "cores": threads,
+            "kind": "oracle",
             "host": {"nproc": os.cpu_count(), "model": cpu_model()},
-            "sample": "2^%d uniform uint32 keys, hash_range 2^%d, + 2^%d queries (50%% hits): "
-                      "stable build + probe counts, sequential C, median of 3 (%.2f s)"
-                      % (log2_sample, log2_sample, log2_sample, t)}
+            "sample": "the step's own arrays: stable build of %d uniform uint32 keys, hash_range "
+                      "%d, then probe counts of %d queries (50%% hits), by the oracle's "
+                      "multi-core variant (OpenMP, %d threads, output identical to the "
+                      "sequential oracle), best of 2 (%.2f s)" % (n, V, m, threads, t),
+            "sequential": {"value": round(2 * ns / ts / 1e9, 5), "unit": "Gkeys/s", "cores": 1,
+                           "sample": "2^%d uniform uint32 keys, hash_range 2^%d, + 2^%d "
+                                     "queries: sequential oracle, median of 3 (%.2f s)"
+                                     % (log2_sample, log2_sample, log2_sample, ts)}}
 
 
 def main():
@@ -410,7 +441,6 @@ def main():
     q_np = workloads.probe_queries(keys_np, m, 0.5, seed=1)
     dk = hg.to_device(keys_np)
     dq = hg.to_device(q_np)
-    del q_np
     counts = torch.empty(m, dtype=torch.int32, device="cuda")
     table = hg.Table.create(n, V, 32)
     torch.cuda.synchronize()
@@ -476,16 +506,20 @@ def main():
     n_tail = int(reads.sum().item())  # queries that also read the edge array
     del h, offl, off, blen, ek, eku, qu, first, reads, sel
 
-    plan = v2_plan_bytes(n, V)
+    plan = v2_plan_bytes(hg, n, V, kb)
     kernels = {}
     for name, (launches, tot_ms) in prof.items():
         per = launches / args.steps
         avg = tot_ms / launches
-        b = kernel_bytes(name, n, m, V, kb, sum_len, plan, sum_tail)
+        b = kernel_bytes(name, n, m, V, kb, sum_len, plan)
+        bi = index_bytes(name, n, m, V, kb, sum_tail)
         kernels[name] = {"launches_per_step": per, "avg_ms": round(avg, 4),
                          "ms_per_step": round(tot_ms / args.steps, 4),
                          "alg_bytes": b,
                          "alg_GBps": round(b / (avg / 1000.0) / 1e9, 1) if b else None}
+        if bi:
+            kernels[name]["index_bytes"] = bi
+            kernels[name]["index_GBps"] = round(bi / (avg / 1000.0) / 1e9, 1)
     dom = max((k for k in kernels if kernels[k]["alg_bytes"]),
               key=lambda k: kernels[k]["ms_per_step"])
     dk_ = kernels[dom]
@@ -496,6 +530,10 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "kernel": dom,
                 "alg_bytes_per_launch": dk_["alg_bytes"], "avg_launch_ms": dk_["avg_ms"],
+                # the same kernel's bytes counting the per-bucket probe index
+                # it reads (16 B per query) in place of the two offsets
+                "index_bytes_per_launch": dk_.get("index_bytes"),
+                "index_GBps": dk_.get("index_GBps"),
                 # HBM bytes the counters saw per launch, over the same launch time
                 "traffic_GBps": (round(traffic / (dk_["avg_ms"] / 1000.0) / 1e9, 1)
                                  if traffic else None)}
@@ -729,7 +767,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline")
-        cpu = cpu_baseline()
+        cpu = cpu_baseline(keys_np, q_np, V)
 
     out = {
         "metric": METRIC,

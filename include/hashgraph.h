@@ -153,6 +153,26 @@ hg_status hg_build(const void *d_keys, uint64_t n, int key_bits, uint64_t hash_r
                    uint64_t seed, const hg_build_opts *opts, hipStream_t stream,
                    hg_table **out);
 
+/* The plan a V2 build (Alg. 2) of n keys over hash_range buckets follows:
+ * final bins of 2^bucket_bits consecutive buckets (the paper's Bins, here
+ * sized so that a bin's keys fit in LDS), reached by one or two stable
+ * partition passes over digits of the bin index, and the workspace the build
+ * needs.  bins: as hg_build_opts.bins (0 = the library's choice).  Host only:
+ * needs no device.  HG_ERR_INVALID_ARG for key_bits not 32/64, hash_range
+ * outside [1, 2^32 - 1], n >= 2^32, bins > hash_range or out NULL. */
+typedef struct hg_plan_info {
+    uint32_t bucket_bits;     /* k: log2 of the buckets per final bin          */
+    uint32_t bins;            /* final bins, ceil(V / 2^k)                     */
+    uint32_t passes;          /* partition passes before the per-bin build     */
+    uint32_t digit_bits[2];   /* digit width of each pass (0 if unused)        */
+    uint32_t tiles[2];        /* partition tiles of each pass (second: bound)  */
+    uint32_t tile_keys;       /* keys per partition tile                       */
+    uint64_t workspace_bytes; /* device workspace of the build                 */
+} hg_plan_info;
+
+hg_status hg_build_plan(uint64_t n, uint64_t hash_range, int key_bits, uint32_t bins,
+                        hg_plan_info *out);
+
 /* Allocate an empty table able to hold up to n_capacity keys and
  * range_capacity buckets, including the workspace a V2 build needs.  Later
  * hg_table_build calls allocate nothing, except the probe index on the first

@@ -6,8 +6,10 @@ this package.  The GPU library never does, and this package never imports the
 GPU library: the two share no code.
 
 The arithmetic lives in ``hg_oracle.c`` (plain sequential C, compiled with
-gcc); this module only marshals numpy arrays.  See the header of that file for
-which section, equation or algorithm of the paper each function follows.
+gcc) and, for the multi-core CPU baseline, ``hg_oracle_omp.c`` (the same
+definitions on all host cores, pinned against the sequential functions); this
+module only marshals numpy arrays.  See the headers of those files for which
+section, equation or algorithm of the paper each function follows.
 """
 from __future__ import annotations
 
@@ -19,6 +21,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "hg_oracle.c")
+_SRC_OMP = os.path.join(_HERE, "hg_oracle_omp.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -26,10 +29,12 @@ OK, EINVAL, ENOMEM, ECAPACITY = 0, 1, 2, 3
 
 
 def build(force: bool = True) -> str:
-    """Compile hg_oracle.c into liboracle.so (gcc -O2, no GPU code)."""
+    """Compile hg_oracle.c and hg_oracle_omp.c into liboracle.so (gcc -O2,
+    OpenMP for the multi-core variant, no GPU code)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-shared", "-fPIC", "-o", tmp, _SRC])
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-shared", "-fPIC", "-o",
+                               tmp, _SRC, _SRC_OMP])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -55,6 +60,11 @@ def _load():
     lib.orc_probe_pairs.argtypes = [vp, u64, vp, u64, i32, vp, vp, u64, ctypes.POINTER(u64)]
     lib.orc_probe_pairs.restype = i32
     lib.orc_count_one.argtypes, lib.orc_count_one.restype = [vp, u64, i32, u64], u64
+    lib.orc_omp_threads.argtypes, lib.orc_omp_threads.restype = [], i32
+    lib.orc_build_omp.argtypes, lib.orc_build_omp.restype = [vp, u64, i32, u64, u64, vp, vp,
+                                                             vp], i32
+    lib.orc_probe_counts_omp.argtypes = [vp, u64, vp, u64, i32, vp, ctypes.POINTER(u64)]
+    lib.orc_probe_counts_omp.restype = i32
     _lib = lib
     return lib
 
@@ -156,6 +166,37 @@ def probe_pairs(keys, queries, key_bits=None, capacity=None):
     if rc:
         raise ValueError("orc_probe_pairs rc=%d" % rc)
     return b, p, int(tot.value)
+
+
+def omp_threads() -> int:
+    """Threads the multi-core variant uses (OpenMP's current maximum)."""
+    return int(_load().orc_omp_threads())
+
+
+def build_table_omp(keys, V: int, seed: int = 0, key_bits=None):
+    """build_table on all host cores (same output, bit for bit)."""
+    k, kb = _keys(keys, key_bits)
+    off = np.empty(int(V) + 1, dtype=np.uint32)
+    ids = np.empty(k.size, dtype=np.uint32)
+    ek = np.empty(k.size, dtype=k.dtype)
+    rc = _load().orc_build_omp(_p(k), k.size, kb, int(V), int(seed) & 0xFFFFFFFFFFFFFFFF,
+                               _p(off), _p(ids), _p(ek))
+    if rc:
+        raise ValueError("orc_build_omp rc=%d" % rc)
+    return off, ids, ek
+
+
+def probe_counts_omp(keys, queries, key_bits=None):
+    """probe_counts on all host cores (same output, bit for bit)."""
+    k, kb = _keys(keys, key_bits)
+    q, _ = _keys(queries, kb)
+    c = np.empty(q.size, dtype=np.uint32)
+    tot = ctypes.c_uint64(0)
+    rc = _load().orc_probe_counts_omp(_p(k), k.size, _p(q), q.size, kb, _p(c),
+                                      ctypes.byref(tot))
+    if rc:
+        raise ValueError("orc_probe_counts_omp rc=%d" % rc)
+    return c, int(tot.value)
 
 
 def count_one(keys, q: int, key_bits=None) -> int:

@@ -332,6 +332,25 @@ hg_status hg_exclusive_scan(const uint32_t* d_counts, uint64_t V, uint32_t* d_of
     return from_hip(scan_excl<uint32_t>(d_counts, V, d_offsets, nullptr, ws.p, stream));
 }
 
+hg_status hg_build_plan(uint64_t n, uint64_t hash_range, int key_bits, uint32_t bins,
+                        hg_plan_info* out) {
+    if (!out || !valid_kb(key_bits) || !valid_range(hash_range) || n > kU32Max ||
+        (bins && bins > hash_range))
+        return HG_ERR_INVALID_ARG;
+    const V2Plan p = plan_v2(n, hash_range, key_bits, bins);
+    *out = hg_plan_info{};
+    out->bucket_bits = p.k;
+    out->bins = p.bins;
+    out->passes = p.tiers;
+    out->digit_bits[0] = p.b1;
+    out->digit_bits[1] = p.tiers == 2 ? p.b2 : 0u;
+    out->tiles[0] = p.ntiles1;
+    out->tiles[1] = p.tiers == 2 ? p.ntiles2_ub : 0u;
+    out->tile_keys = kPartTile;
+    out->workspace_bytes = build_ws_bytes(HG_VARIANT_V2, n, hash_range, key_bits, bins);
+    return HG_OK;
+}
+
 hg_status hg_table_create(uint64_t n_capacity, uint64_t range_capacity, int key_bits,
                           hg_table** out) {
     if (!out || !valid_kb(key_bits) || !valid_range(range_capacity) || n_capacity > kU32Max)

@@ -46,6 +46,13 @@ class TableInfo(ctypes.Structure):
                 ("device_bytes", ctypes.c_uint64)]
 
 
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("bucket_bits", ctypes.c_uint32), ("bins", ctypes.c_uint32),
+                ("passes", ctypes.c_uint32), ("digit_bits", ctypes.c_uint32 * 2),
+                ("tiles", ctypes.c_uint32 * 2), ("tile_keys", ctypes.c_uint32),
+                ("workspace_bytes", ctypes.c_uint64)]
+
+
 _lib = None
 
 
@@ -69,6 +76,7 @@ def lib():
         "hg_build": ([vp, u64, i32, u64, u64, ctypes.POINTER(BuildOpts), vp,
                       ctypes.POINTER(vp)], i32),
         "hg_table_create": ([u64, u64, i32, ctypes.POINTER(vp)], i32),
+        "hg_build_plan": ([u64, u64, i32, u32, ctypes.POINTER(PlanInfo)], i32),
         "hg_table_build": ([vp, vp, u64, u64, u64, ctypes.POINTER(BuildOpts), vp], i32),
         "hg_table_view": ([vp, ctypes.POINTER(TableInfo)], i32),
         "hg_table_export": ([vp, vp, vp, vp, vp], i32),
@@ -167,6 +175,17 @@ def hg_exclusive_scan(counts: torch.Tensor, out=None, stream=None):
 
 
 # ----------------------------------------------------------------- tables ---
+
+def build_plan(n: int, hash_range: int, key_bits: int = 32, bins: int = 0) -> dict:
+    """The V2 plan (Alg. 2) the library follows for n keys over hash_range
+    buckets (host only)."""
+    p = PlanInfo()
+    _check(lib().hg_build_plan(int(n), int(hash_range), int(key_bits), int(bins),
+                               ctypes.byref(p)), "hg_build_plan")
+    return {"bucket_bits": p.bucket_bits, "bins": p.bins, "passes": p.passes,
+            "digit_bits": list(p.digit_bits), "tiles": list(p.tiles),
+            "tile_keys": p.tile_keys, "workspace_bytes": p.workspace_bytes}
+
 
 def _opts(variant=VARIANT_AUTO, stable=0, bins=0, block=0, index=True, any_order=False):
     o = BuildOpts()

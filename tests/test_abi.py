@@ -107,3 +107,34 @@ def test_no_cpu_fallback_without_gpu(lib):
     out = vp()
     assert lib.hg_collection_build(dummy, dummy, 4, 32, 0, 0, ctypes.byref(out), None) == 3
     assert not out.value
+
+
+def test_build_plan_is_host_only_and_consistent(lib):
+    """hg_build_plan needs no device.  The plan's bins cover the range with
+    power-of-two bucket ranges, the digits of its passes address every bin,
+    a bin holds about 4096 32-bit (2048 64-bit) keys on average, and one pass
+    suffices up to 512 bins."""
+    from paper_1907_02900_amd import hg
+    for kb, target in ((32, 4096), (64, 2048)):
+        for n, V in ((1 << 28, 1 << 28), (1 << 28, 1 << 26), (1 << 28, 1 << 30), (1 << 27, 1 << 27),
+                     (1 << 20, 1 << 20), (1000, 7), (5, (1 << 32) - 1), (0, 100), (300007, 300007)):
+            p = hg.build_plan(n, V, kb)
+            k = p["bucket_bits"]
+            assert k <= 12 and p["bins"] == -(-V // (1 << k))
+            bits = sum(p["digit_bits"][:p["passes"]])
+            assert (1 << bits) >= p["bins"] and (bits == 0 or (1 << (bits - 1)) < p["bins"])
+            assert p["passes"] == (1 if bits <= 9 else 2)
+            assert p["tiles"][0] == -(-n // p["tile_keys"])
+            if n and k < 12 and (1 << k) < V:
+                per_bin = n * (1 << k) / V
+                assert target / 2 <= per_bin <= target
+            assert p["workspace_bytes"] >= n * (kb // 8 + 4)
+    p = hg.build_plan(1 << 28, 1 << 28, 32)
+    assert (p["bucket_bits"], p["bins"], p["passes"], p["digit_bits"]) == (12, 1 << 16, 2, [8, 8])
+    assert hg.build_plan(1 << 16, 1 << 16, 32, bins=64)["bins"] == 64
+    # a bin spans at most 2^12 buckets, so fewer bins than V / 2^12 are not planned
+    assert hg.build_plan(1 << 20, 1 << 20, 32, bins=64)["bins"] == 256
+    for bad in ((10, 0, 32, 0), (10, 1 << 32, 32, 0), (1 << 32, 7, 32, 0), (10, 7, 16, 0),
+                (10, 7, 32, 8)):
+        with pytest.raises(hg.HGError):
+            hg.build_plan(*bad)

@@ -62,7 +62,12 @@ def test_batch_matches_oracle_over_replays(hg, kb, autotune):
         tabs.append({"keys": hg.to_device(k), "queries": hg.to_device(q), "hash_range": V,
                      "seed": seed})
     b = hg.Batch(tabs, key_bits=kb, autotune=autotune)
-    assert b.info()["bin_target"] in (1024, 2048)
+    # the tuner keeps the fastest candidate: 1024, 2048 or (32-bit keys) 4096
+    # keys per bin; without tuning the default is 2048
+    if autotune:
+        assert b.info()["bin_target"] in ((1024, 2048, 4096) if kb == 32 else (1024, 2048))
+    else:
+        assert b.info()["bin_target"] == 2048
     dt = np.uint64 if kb == 64 else np.uint32
     for rep in range(3):
         flip = dt((rep * 0x9E3779B1) & 0xFFFFFFFF)
@@ -139,3 +144,53 @@ def test_batch_rejects_bad_items(hg):
     k = hg.to_device(workloads.uniform_keys(10, 32, 1))
     with pytest.raises(hg.HGError):
         hg.Batch([{"keys": k, "queries": None, "hash_range": 0, "seed": 0}])
+
+
+@pytest.fixture(scope="module")
+def config_shape():
+    """320 tables shaped like the benchmark's batch (sizes floor(2^U), U
+    uniform in [8, 20], V = n, per-table seed, as many 50%-hit queries as
+    keys), so that about a quarter of them hold 2^17 to 2^20 keys, plus the
+    largest size itself; the oracle's stable table and counts of every one."""
+    sizes = [int(x) for x in workloads.batched_sizes(320, 8.0, 20.0, seed=41)] + [1 << 20]
+    data = []
+    for i, n in enumerate(sizes):
+        k = workloads.uniform_keys(n, 32, seed=50_000 + i)
+        q = workloads.probe_queries(k, n, 0.5, seed=60_000 + i)
+        off, ids, ek = oracle.build_table(k, n, i)
+        data.append((k, q, n, i, off, ids, oracle.probe_counts(k, q)[0]))
+    assert sum(1 for d in data if d[2] > (1 << 17)) >= 60
+    return data
+
+
+@pytest.mark.parametrize("any_order", [True, False])
+@pytest.mark.parametrize("bin_target", [1024, 2048, 4096])
+def test_batch_config_shape_every_bin_target(hg, config_shape, bin_target, any_order):
+    """The batched configuration's table sizes (up to 2^20 keys, whose
+    partition has up to 1024 digits) with each bin size the tuner can pick,
+    in both layouts: offsets and counts equal the oracle's for every table;
+    stable tables equal the oracle's table entry for entry, any-order tables
+    as multisets per bucket (ids sorted inside each bucket)."""
+    print("[case] batch config shape", bin_target, any_order, flush=True)
+    tabs = [{"keys": hg.to_device(k), "queries": hg.to_device(q), "hash_range": V, "seed": s}
+            for k, q, V, s, _, _, _ in config_shape]
+    b = hg.Batch(tabs, key_bits=32, autotune=False, bin_target=bin_target, any_order=any_order)
+    assert b.info()["bin_target"] == bin_target
+    for rep in range(2):
+        b.run()
+        torch.cuda.synchronize()
+        for (k, q, V, s, o_off, o_ids, o_cnt), t in zip(config_shape, b.tables):
+            n = k.size
+            off = t["offsets"].to(torch.int64) & 0xFFFFFFFF
+            assert torch.equal(off, torch.from_numpy(o_off.astype(np.int64)).cuda()), (rep, n)
+            ids = t["ids"][:n].to(torch.int64) & 0xFFFFFFFF
+            ek = t["ekeys"][:n]
+            assert torch.equal(ek, t["keys"][ids]), (rep, n)
+            if any_order:
+                seg = torch.repeat_interleave(torch.arange(V, device=ids.device),
+                                              off[1:] - off[:-1], output_size=n)
+                ids = ids[torch.argsort(seg * (1 << 32) + ids)]
+            assert torch.equal(ids, torch.from_numpy(o_ids.astype(np.int64)).cuda()), (rep, n)
+            c = t["counts"][:q.size].to(torch.int64) & 0xFFFFFFFF
+            assert torch.equal(c, torch.from_numpy(o_cnt.astype(np.int64)).cuda()), (rep, n)
+    b.free()

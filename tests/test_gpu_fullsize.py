@@ -95,43 +95,71 @@ def uniform(hg):
     return keys, q, exp, etot
 
 
-def test_full_uniform_bench_configuration(hg, uniform):
+@pytest.mark.parametrize("layout", ["any_order", "stable"])
+def test_full_uniform_bench_step(hg, uniform, layout):
+    """The benchmark's timed step exactly as bench.py runs it: a table created
+    at capacity (2^28 keys, V = 2^28), rebuilt in place with the probe index
+    (any order, as timed by default; stable with --stable), then
+    Probe-Standard counts of all 2^28 queries into a preallocated buffer.
+    Offsets are exact; the buckets, as multisets, equal the oracle's (ids
+    sorted inside each bucket equal torch's stable argsort of the oracle's
+    buckets); the stable layout equals it entry for entry; every count and the
+    total equal the oracle's."""
     keys, q, exp, etot = uniform
     V = N
-    say("V2 build + probe, n = V = m = 2^28")
+    any_order = layout == "any_order"
+    say("V2 build (%s, index) + probe, n = V = m = 2^28" % layout)
     dk, dq = hg.to_device(keys), hg.to_device(q)
     table = hg.Table.create(N, V, 32)
     counts = torch.empty(N, dtype=torch.int32, device="cuda")
-    table.rebuild(dk, V, seed=0, variant=hg.VARIANT_V2)
-    hg.hg_probe(table, dq, counts=True, total=False, out=counts)
+    for _ in range(2):  # a rebuild over a previous build, as in the timed loop
+        table.rebuild(dk, V, seed=0, variant=hg.VARIANT_V2, any_order=any_order)
+        hg.hg_probe(table, dq, counts=True, total=False, out=counts)
     _, tot = hg.hg_probe(table, dq, counts=False, total=True)
     torch.cuda.synchronize()
     assert np.array_equal(hg.to_numpy(counts, np.uint32), exp)
     assert tot == etot
+    del counts
     h = torch.from_numpy(oracle.hash_buckets(keys, V, 0).astype(np.int64)).cuda()
-    check_table(hg, table, u64(dk), h, V, stable=True)
+    off, ids = check_table(hg, table, u64(dk), h, V, stable=not any_order)
+    stable_ids = torch.sort(h, stable=True).indices
+    del h
+    if any_order:
+        ids = sort_within_buckets(off, ids, V)
+    assert torch.equal(ids, stable_ids), "buckets differ from the oracle's as multisets"
     table.free()
 
 
-def test_full_uniform_pairs_materialised(hg, uniform):
+@pytest.mark.parametrize("layout", ["stable", "any_order"])
+def test_full_uniform_pairs_materialised(hg, uniform, layout):
     """All ~1.5e8 matching pairs of the 2^28 x 2^28 uniform workload: the
     total equals the oracle's, every pair joins equal keys, each probe id
-    appears exactly its oracle count times, probe ids ascend, and (stable
-    table) build ids ascend inside each probe id, which with the counts
-    leaves exactly the oracle's pair set."""
+    appears exactly its oracle count times, probe ids ascend and no pair
+    repeats, which with the counts leaves exactly the oracle's pair set.  In
+    the stable table build ids also ascend inside each probe id (the oracle's
+    canonical order); in the any-order table (the benchmark's layout) they
+    follow the table's bucket order."""
     keys, q, exp, etot = uniform
     V = N
-    say("pairs, n = V = m = 2^28")
+    any_order = layout == "any_order"
+    say("pairs, n = V = m = 2^28, %s" % layout)
     dk, dq = hg.to_device(keys), hg.to_device(q)
-    table = hg.hg_build(dk, V, seed=0)
+    table = hg.Table.create(N, V, 32)
+    table.rebuild(dk, V, seed=0, variant=hg.VARIANT_V2, any_order=any_order)
     b, p, tot = hg.hg_probe_pairs(table, dq)
     torch.cuda.synchronize()
     assert tot == etot
     bi, pi = u64(b), u64(p)
+    del b, p
     assert bool((pi[1:] >= pi[:-1]).all())
     cnt = torch.bincount(pi, minlength=N)
     assert np.array_equal(cnt.cpu().numpy().astype(np.uint32), exp)
+    del cnt
     assert bool((u64(dk)[bi] == u64(dq)[pi]).all())
+    if any_order:
+        order = torch.argsort(pi * (1 << 32) + bi)
+        bi, pi = bi[order], pi[order]
+        del order
     same = pi[1:] == pi[:-1]
     assert bool((bi[1:][same] > bi[:-1][same]).all())
     table.free()

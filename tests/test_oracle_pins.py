@@ -478,3 +478,37 @@ def test_pair_match_counts_brute_force_and_closed_forms(key_bits):
     c = oracle.pair_match_counts(both, [0, da.size, both.size], both, [0, da.size, both.size],
                                  [(0, 1)])
     assert int(c[0]) == np.intersect1d(da, db).size
+
+
+# ---------------------------------------------------------------------------
+# The multi-core oracle variant (CPU baseline) equals the sequential oracle
+# bit for bit: tables (offsets, ids, bucketed keys) and probe counts.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("key_bits", [32, 64])
+@pytest.mark.parametrize("kind,n,V", [("uniform", 0, 1), ("uniform", 0, 9), ("uniform", 1, 1),
+                                      ("uniform", 17, 3), ("uniform", 1000, 1),
+                                      ("uniform", 300007, 300007), ("uniform", 200000, 1 << 20),
+                                      ("uniform", 250000, (1 << 26) + 1),
+                                      ("dup", 400000, 1 << 16), ("zipf", 300000, 300000),
+                                      ("seq", 123457, 65536)])
+def test_omp_variant_equals_sequential_oracle(key_bits, kind, n, V):
+    if kind == "uniform":
+        keys = workloads.uniform_keys(n, key_bits, seed=n + 3)
+    elif kind == "dup":
+        keys = workloads.duplicate_keys(n, 16.0, key_bits, seed=4)
+    elif kind == "zipf":
+        keys = workloads.zipf_keys(n, 1.5, distinct=1 << 12, seed=5).astype(
+            np.uint64 if key_bits == 64 else np.uint32)
+    else:
+        keys = workloads.sequence_keys(n, key_bits)
+    seed = 0x1234_5678_9ABC | (1 << 63)
+    a = oracle.build_table(keys, V, seed, key_bits)
+    b = oracle.build_table_omp(keys, V, seed, key_bits)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    q = workloads.probe_queries(keys if n else workloads.uniform_keys(3, key_bits, 1),
+                                max(n, 7), 0.5, seed=9, key_bits=key_bits)
+    ca, ta = oracle.probe_counts(keys, q, key_bits)
+    cb, tb = oracle.probe_counts_omp(keys, q, key_bits)
+    assert ta == tb and np.array_equal(ca, cb)
+    assert oracle.omp_threads() >= 1
