@@ -634,14 +634,16 @@ hg_status create_plan(const hg_batch_item* items, uint32_t count, const hg_batch
     }
     const int kb = (int)sizeof(Key) * 8;
     std::vector<uint32_t> cands;
+    const bool autotune = !opts || opts->autotune != 0;
     if (opts && opts->bin_target) {
         cands.push_back(opts->bin_target);
-    } else {
+    } else if (autotune) {
+        // a batch of the same shape tuned before keeps its choice
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune.find(std::make_tuple(count, tn, tm, kb, opts && opts->any_order));
         if (it != g_tune.end()) cands.push_back(it->second);
     }
-    const bool tune = cands.empty() && (!opts || opts->autotune != 0);
+    const bool tune = cands.empty() && autotune;
     if (cands.empty()) {
         // a light bin holds up to light_cap<Key>() keys (4608 / 3072)
         if (tune && sizeof(Key) == 4) cands = {1024u, 2048u, 4096u};
