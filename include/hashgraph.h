@@ -75,14 +75,15 @@ typedef struct hg_build_opts {
                           holds two or more), so most probes take one
                           random read.  Buckets of more than 32 entries get a
                           key-run summary instead (distinct keys ascending,
-                          each with its count and its ids grouped), so probes
+                          each with the end of its group of ids), so probes
                           and intersections of skewed tables cost a binary
-                          search instead of a scan; building it waits for the
-                          build.  The index (16 bytes per bucket of the
-                          table's range capacity) is allocated by the first
-                          build that writes it, the summary the first time a
-                          build has such buckets, also for tables made by
-                          hg_table_create.  1 = skip the index (probes then read
+                          search instead of a scan.  The whole index is built
+                          on the device, in stream order: the build never
+                          waits for it.  Its arrays (16 bytes per bucket of
+                          the range capacity, and key + 8 bytes per entry of
+                          the key capacity for the summary) are allocated by
+                          hg_table_create, or by hg_build when it writes the
+                          index.  1 = skip the index (probes then read
                           offsets and scan the edge array).  Results are
                           identical either way.  V1 never writes it.         */
     int32_t any_order; /* V2: 1 = the order of ids inside a bucket is
@@ -174,10 +175,11 @@ hg_status hg_build_plan(uint64_t n, uint64_t hash_range, int key_bits, uint32_t 
                         hg_plan_info *out);
 
 /* Allocate an empty table able to hold up to n_capacity keys and
- * range_capacity buckets, including the workspace a V2 build needs.  Later
- * hg_table_build calls allocate nothing, except the probe index on the first
- * build that writes it and the key-run summary of long buckets (see
- * hg_build_opts.no_index); a build with no_index = 1 never allocates. */
+ * range_capacity buckets, including the workspace a V2 build of that size
+ * needs and the probe index with its key-run summary (hg_build_opts.no_index).
+ * Later hg_table_build calls of up to those sizes (with the library's choice
+ * of bins) allocate nothing and never wait for the device, so a rebuild and
+ * the probes after it can be captured into a HIP graph. */
 hg_status hg_table_create(uint64_t n_capacity, uint64_t range_capacity, int key_bits,
                           hg_table **out);
 

@@ -20,24 +20,13 @@ struct hg_table {
     void* keys = nullptr;
     uint4* head = nullptr;  // V_cap per-bucket probe index entries
     bool has_head = false;  // the last build wrote head
-    // long buckets (> kRunBucket entries): per-bin tallies, their prefix sums,
-    // the list of long buckets and their key runs
-    uint2* tally = nullptr;
-    uint32_t* tally_pre = nullptr;  // [2 * (tally_cap + 1)]: counts, lengths
-    uint64_t tally_cap = 0;
-    uint32_t* long_list = nullptr;
-    uint64_t long_cap = 0;
-    void* runs_ws = nullptr;  // workspace of the listing and the summary (grow-only)
-    size_t runs_ws_bytes = 0;
+    RunsDev runs{};         // key runs of long buckets: n_cap entries per array
     // erasing keys: live entries per bucket, scratch flags, live entry count
     uint32_t* len = nullptr;   // [V_cap]
     uint8_t* dead = nullptr;   // [n_cap]
     uint8_t* touched = nullptr;  // [V_cap]
     bool has_len = false;
     uint64_t live = 0;
-    RunsDev runs{};
-    uint64_t runs_cap = 0;          // runs the run arrays hold (kperm: n_cap)
-    bool has_runs = false;
     void* ws = nullptr;  // workspace kept for rebuilds (hg_table_create only)
     size_t ws_bytes = 0;
     uint64_t bytes = 0;
@@ -96,69 +85,18 @@ hg_status read_u64(const uint64_t* d, uint64_t* h, hipStream_t s) {
         if (st__ != HG_OK) return st__;      \
     } while (0)
 
-// The table's long-bucket workspace holds at least `bytes` (the stream has
-// no work queued on the old one when this runs: callers synchronise first or
-// use it in stream order).
-hg_status ensure_runs_ws(hg_table* t, size_t bytes) {
-    if (t->runs_ws_bytes >= bytes) return HG_OK;
-    if (t->runs_ws) {
-        (void)hipFree(t->runs_ws);  // waits for the device
-        t->bytes -= t->runs_ws_bytes;
-        t->runs_ws = nullptr;
-        t->runs_ws_bytes = 0;
-    }
-    HG_CALL(hipMalloc(&t->runs_ws, bytes));
-    t->runs_ws_bytes = bytes;
-    t->bytes += bytes;
-    return HG_OK;
-}
-
-// After a V2 build with the index: sum the bins' long-bucket tallies and, if
-// there are long buckets, list them and build their key-run summary.  Waits
-// for the build (the totals decide the summary's allocations and launches).
-hg_status build_runs(hg_table* t, const IndexOut& ix, hipStream_t s) {
-    if (ix.bins == 0) return HG_OK;
-    uint32_t* pre_cnt = t->tally_pre;
-    uint32_t* pre_len = t->tally_pre + (t->tally_cap + 1);
-    HG_CALL_ST(ensure_runs_ws(t, tally_ws_bytes(ix.bins)));
-    HG_CALL(scan_tally(t->tally, ix.bins, pre_cnt, pre_len, t->runs_ws, s));
-    uint32_t nlong = 0, total = 0;
-    HG_CALL(hipMemcpyAsync(&nlong, pre_cnt + ix.bins, 4, hipMemcpyDeviceToHost, s));
-    HG_CALL(hipMemcpyAsync(&total, pre_len + ix.bins, 4, hipMemcpyDeviceToHost, s));
-    HG_CALL(hipStreamSynchronize(s));
-    if (nlong == 0) return HG_OK;
-    if (nlong > t->long_cap) return HG_ERR_DEVICE;  // cannot happen: each holds > kRunBucket keys
-    HG_CALL(list_long_buckets(t->offsets, t->V, ix.k, ix.bins, t->tally, pre_cnt, t->long_list,
-                              s));
+// The probe index (16 bytes per bucket of the range capacity) and the key-run
+// arrays of long buckets (sized for the worst case: every entry in a long
+// bucket), allocated once per table.
+hg_status ensure_index(hg_table* t) {
+    if (t->head) return HG_OK;
+    const size_t nc = t->n_cap ? t->n_cap : 1;
     const size_t ks = key_size(t->key_bits);
-    if (!t->runs.kperm) {
-        HG_CALL(hipMalloc((void**)&t->runs.kperm, (t->n_cap ? t->n_cap : 1) * 4));
-        t->bytes += (t->n_cap ? t->n_cap : 1) * 4;
-    }
-    if (t->runs_cap < total) {
-        if (t->runs.run_key) {
-            (void)hipFree(t->runs.run_key);
-            (void)hipFree(t->runs.run_cnt);
-            (void)hipFree(t->runs.run_pos);
-            t->bytes -= t->runs_cap * (ks + 8);
-            t->runs.run_key = nullptr;
-            t->runs_cap = 0;
-        }
-        HG_CALL(hipMalloc(&t->runs.run_key, total * ks));
-        HG_CALL(hipMalloc((void**)&t->runs.run_cnt, (size_t)total * 4));
-        HG_CALL(hipMalloc((void**)&t->runs.run_pos, (size_t)total * 4));
-        t->runs_cap = total;
-        t->bytes += (uint64_t)total * (ks + 8);
-    }
-    HG_CALL_ST(ensure_runs_ws(t, runs_ws_bytes(nlong, total, t->key_bits)));
-    const hipError_t e =
-        t->key_bits == 32
-            ? run_key_runs<uint32_t>(t->offsets, t->ids, (const uint32_t*)t->keys, t->long_list,
-                                     nlong, total, t->head, t->runs, t->runs_ws, s)
-            : run_key_runs<uint64_t>(t->offsets, t->ids, (const uint64_t*)t->keys, t->long_list,
-                                     nlong, total, t->head, t->runs, t->runs_ws, s);
-    if (e != hipSuccess) return from_hip(e);
-    t->has_runs = true;
+    HG_CALL(hipMalloc((void**)&t->head, t->V_cap * sizeof(uint4)));
+    HG_CALL(hipMalloc(&t->runs.run_key, nc * ks));
+    HG_CALL(hipMalloc((void**)&t->runs.run_end, nc * 4));
+    HG_CALL(hipMalloc((void**)&t->runs.kperm, nc * 4));
+    t->bytes += t->V_cap * sizeof(uint4) + nc * (ks + 8);
     return HG_OK;
 }
 
@@ -184,32 +122,11 @@ hg_status build_into(hg_table* t, const void* keys, uint64_t n, uint64_t V, uint
         HG_CALL(tmp.get(need));
         ws = tmp.p;
     }
-    if (want_head && !t->head) {
-        // the probe index is allocated by the first build that writes it
-        HG_CALL(hipMalloc((void**)&t->head, t->V_cap * sizeof(uint4)));
-        HG_CALL(hipMalloc((void**)&t->long_list, t->long_cap * 4));
-        t->bytes += t->V_cap * sizeof(uint4) + t->long_cap * 4;
-    }
-    if (want_head) {
-        const uint32_t nbins = n ? plan_v2(n, V, t->key_bits, bins).bins : 0u;
-        if (nbins > t->tally_cap) {  // per-bin tallies, grown when a plan needs more bins
-            if (t->tally) {
-                (void)hipFree(t->tally);
-                (void)hipFree(t->tally_pre);
-                t->bytes -= t->tally_cap * 8 + 2 * (t->tally_cap + 1) * 4;
-                t->tally = nullptr;
-                t->tally_cap = 0;
-            }
-            HG_CALL(hipMalloc((void**)&t->tally, (size_t)nbins * sizeof(uint2)));
-            HG_CALL(hipMalloc((void**)&t->tally_pre, 2 * ((size_t)nbins + 1) * 4));
-            t->tally_cap = nbins;
-            t->bytes += (uint64_t)nbins * 8 + 2 * ((uint64_t)nbins + 1) * 4;
-        }
-    }
+    if (want_head) HG_CALL_ST(ensure_index(t));
     IndexOut ix{};
     if (want_head) {
         ix.head = t->head;
-        ix.bin_tally = t->tally;
+        ix.runs = t->runs;
     }
     hipError_t e;
     if (t->key_bits == 32) {
@@ -231,10 +148,8 @@ hg_status build_into(hg_table* t, const void* keys, uint64_t n, uint64_t V, uint
     t->seed = seed;
     t->variant = variant;
     t->has_head = want_head;
-    t->has_runs = false;
     t->has_len = false;
     t->live = n;
-    if (want_head) HG_CALL_ST(build_runs(t, ix, s));
     return HG_OK;
 }
 
@@ -247,7 +162,6 @@ hg_status alloc_table(uint64_t n_cap, uint64_t V_cap, int kb, bool with_ws, hg_t
     hipError_t e = hipMalloc((void**)&t->offsets, (V_cap + 1) * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc((void**)&t->ids, (n_cap ? n_cap : 1) * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc(&t->keys, (n_cap ? n_cap : 1) * key_size(kb));
-    t->long_cap = n_cap / (kRunBucket + 1) + 1;
     t->bytes = (V_cap + 1) * 4 + (n_cap ? n_cap : 1) * (4 + key_size(kb));
     if (e == hipSuccess && with_ws) {
         size_t w1 = build_ws_bytes(1, n_cap, V_cap, kb, 0);
@@ -259,6 +173,14 @@ hg_status alloc_table(uint64_t n_cap, uint64_t V_cap, int kb, bool with_ws, hg_t
     if (e != hipSuccess) {
         hg_table_free(t);
         return from_hip(e);
+    }
+    if (with_ws) {
+        // a table made for rebuilds holds the index too, so that no build allocates
+        const hg_status st = ensure_index(t);
+        if (st != HG_OK) {
+            hg_table_free(t);
+            return st;
+        }
     }
     *out = t;
     return HG_OK;
@@ -275,7 +197,7 @@ TableDev dev_view(const hg_table* t) {
     d.V = t->V;
     d.seed = t->seed;
     d.head = t->has_head ? t->head : nullptr;
-    if (t->has_head && t->has_runs) d.runs = t->runs;
+    if (t->has_head) d.runs = t->runs;
     if (t->has_len) d.len = t->len;
     return d;
 }
@@ -627,17 +549,12 @@ void hg_table_free(hg_table* t) {
     if (t->ids) (void)hipFree(t->ids);
     if (t->keys) (void)hipFree(t->keys);
     if (t->head) (void)hipFree(t->head);
-    if (t->long_list) (void)hipFree(t->long_list);
-    if (t->tally) (void)hipFree(t->tally);
-    if (t->tally_pre) (void)hipFree(t->tally_pre);
-    if (t->runs_ws) (void)hipFree(t->runs_ws);
     if (t->len) (void)hipFree(t->len);
     if (t->dead) (void)hipFree(t->dead);
     if (t->touched) (void)hipFree(t->touched);
     if (t->runs.kperm) (void)hipFree(t->runs.kperm);
     if (t->runs.run_key) (void)hipFree(t->runs.run_key);
-    if (t->runs.run_cnt) (void)hipFree(t->runs.run_cnt);
-    if (t->runs.run_pos) (void)hipFree(t->runs.run_pos);
+    if (t->runs.run_end) (void)hipFree(t->runs.run_end);
     if (t->ws) (void)hipFree(t->ws);
     delete t;
 }

@@ -798,6 +798,9 @@ struct STable {
     uint32_t* offsets = nullptr;
     uint32_t* ids = nullptr;
     void* keys = nullptr;
+    uint4* head = nullptr;   // probe index (tables built by a launch of their own)
+    RunsDev runs{};          // key runs of long buckets (with head)
+    bool has_index = false;
     uint64_t bytes = 0;
     uint64_t last_use = 0;
     int pins = 0;            // requests (its build, pending probes) that need it
@@ -882,8 +885,19 @@ struct Server {
     }
     std::unordered_map<void*, size_t> pinned_sizes;
 
-    static uint64_t table_bytes(uint64_t n, uint64_t V, int kb) {
-        return (V + 1) * 4 + (n ? n : 1) * (4 + (uint64_t)kb / 8);
+    // device bytes of a table; with the probe index also 16 per bucket and the
+    // key-run arrays (key, end, kperm) per entry
+    static uint64_t table_bytes(uint64_t n, uint64_t V, int kb, bool index) {
+        const uint64_t nn = n ? n : 1;
+        return (V + 1) * 4 + nn * (4 + (uint64_t)kb / 8) +
+               (index ? V * 16 + nn * ((uint64_t)kb / 8 + 8) : 0);
+    }
+
+    void free_table(STable& t, hipStream_t s) {
+        void* ptrs[] = {t.offsets, t.ids, t.keys, t.head, t.runs.run_key, t.runs.run_end,
+                        t.runs.kperm};
+        for (void* q : ptrs)
+            if (q) (void)hipFreeAsync(q, s);
     }
 
     bool evict_for(uint64_t need) {
@@ -898,9 +912,7 @@ struct Server {
             }
             if (!victim) return false;
             STable& t = tables[victim];
-            (void)hipFreeAsync(t.offsets, streams[0]);
-            (void)hipFreeAsync(t.ids, streams[0]);
-            (void)hipFreeAsync(t.keys, streams[0]);
+            free_table(t, streams[0]);
             if (t.ready) event_pool.push_back(t.ready);
             resident -= t.bytes;
             tables.erase(victim);
@@ -991,14 +1003,6 @@ struct Server {
         // memory: new tables (builds) plus workspace
         uint64_t need_tables = 0, ws = 0;
         const int kb = r0.key_bits;
-        if (r0.kind == 0) {
-            for (uint64_t rid : group) {
-                const SReq& r = reqs[rid];
-                need_tables += tables[r.table].bytes;
-            }
-            if (group.size() == 1)
-                ws = build_ws_bytes(2, r0.count, tables[r0.table].V, kb, 0);
-        }
         uint64_t merged_ws = 0;
         // merged launches carry descriptors + workspace in one block
         BatchPlan<uint32_t> p32;
@@ -1024,13 +1028,19 @@ struct Server {
                     if (p64.layout(items.data(), (uint32_t)items.size(), 2048) != HG_OK) group.resize(1);
                     else merged_ws = p64.carve(nullptr);
                 }
-                if (group.size() == 1) ws = build_ws_bytes(2, r0.count, tables[r0.table].V, kb, 0);
             }
         }
-        if (group.size() > 1 && r0.kind == 0) {
-            need_tables = 0;
-            for (uint64_t rid : group) need_tables += tables[reqs[rid].table].bytes;
-            ws = merged_ws;
+        if (r0.kind == 0) {
+            // a build of its own writes the probe index and key runs; merged
+            // small builds (the batched kernels) do not
+            const bool idx = group.size() == 1;
+            for (uint64_t rid : group) {
+                STable& t = tables[reqs[rid].table];
+                t.has_index = idx;
+                t.bytes = table_bytes(t.n, t.V, t.key_bits, idx);
+                need_tables += t.bytes;
+            }
+            ws = idx ? build_ws_bytes(2, r0.count, tables[r0.table].V, kb, 0) : merged_ws;
         }
         if (resident + transient + need_tables + ws > o.budget_bytes) {
             if (!evict_for(need_tables + ws)) {
@@ -1067,8 +1077,14 @@ struct Server {
                 STable& t = tables[reqs[rid].table];
                 if (e == hipSuccess) e = hipMallocAsync((void**)&t.offsets, (t.V + 1) * 4, s);
                 if (e == hipSuccess) e = hipMallocAsync((void**)&t.ids, (t.n ? t.n : 1) * 4, s);
-                if (e == hipSuccess)
-                    e = hipMallocAsync(&t.keys, (t.n ? t.n : 1) * (uint64_t)(t.key_bits / 8), s);
+                const uint64_t nn = t.n ? t.n : 1, ks = (uint64_t)(t.key_bits / 8);
+                if (e == hipSuccess) e = hipMallocAsync(&t.keys, nn * ks, s);
+                if (e == hipSuccess && t.has_index) {
+                    e = hipMallocAsync((void**)&t.head, t.V * 16, s);
+                    if (e == hipSuccess) e = hipMallocAsync(&t.runs.run_key, nn * ks, s);
+                    if (e == hipSuccess) e = hipMallocAsync((void**)&t.runs.run_end, nn * 4, s);
+                    if (e == hipSuccess) e = hipMallocAsync((void**)&t.runs.kperm, nn * 4, s);
+                }
                 resident += t.bytes;
                 t.stream = L.stream;
             }
@@ -1091,16 +1107,22 @@ struct Server {
         if (e == hipSuccess) {
             if (r0.kind == 0 && group.size() == 1) {
                 STable& t = tables[r0.table];
-                IndexOut none{};  // served tables carry no probe index
+                IndexOut ix{};
+                ix.head = t.head;
+                ix.runs = t.runs;
                 e = kb == 32 ? run_build_v2<uint32_t>((const uint32_t*)r0.data, t.n, t.V, t.seed,
                                                       t.offsets, t.ids, (uint32_t*)t.keys,
-                                                      none, L.transient, 0, true, s)
+                                                      ix, L.transient, 0, true, s)
                              : run_build_v2<uint64_t>((const uint64_t*)r0.data, t.n, t.V, t.seed,
                                                       t.offsets, t.ids, (uint64_t*)t.keys,
-                                                      none, L.transient, 0, true, s);
+                                                      ix, L.transient, 0, true, s);
             } else if (r0.kind == 1 && group.size() == 1) {
                 const STable& t = tables[r0.table];
                 TableDev d{t.offsets, t.ids, t.keys, t.n, t.V, t.seed};
+                if (t.has_index) {
+                    d.head = t.head;
+                    d.runs = t.runs;
+                }
                 e = kb == 32 ? run_probe_counts<uint32_t>(d, (const uint32_t*)r0.data, r0.count,
                                                           r0.counts, nullptr, s)
                              : run_probe_counts<uint64_t>(d, (const uint64_t*)r0.data, r0.count,
@@ -1256,7 +1278,7 @@ hg_status hg_server_submit_build(hg_server* h, const void* d_keys, uint64_t n, i
     t.n = n;
     t.V = hash_range;
     t.seed = seed;
-    t.bytes = hg::srv::Server::table_bytes(n, hash_range, key_bits);
+    t.bytes = hg::srv::Server::table_bytes(n, hash_range, key_bits, true);
     t.pins = 1;
     t.last_use = ++s.clock;
     hg::srv::SReq& r = s.reqs[rid];
@@ -1421,9 +1443,7 @@ void hg_server_destroy(hg_server* h) {
     for (auto q : s.streams) (void)hipStreamSynchronize(q);
     for (auto& kv : s.tables) {
         hg::srv::STable& t = kv.second;
-        if (t.offsets) (void)hipFreeAsync(t.offsets, s.streams[0]);
-        if (t.ids) (void)hipFreeAsync(t.ids, s.streams[0]);
-        if (t.keys) (void)hipFreeAsync(t.keys, s.streams[0]);
+        s.free_table(t, s.streams[0]);
         if (t.ready) (void)hipEventDestroy(t.ready);
     }
     for (auto q : s.streams) (void)hipStreamSynchronize(q);

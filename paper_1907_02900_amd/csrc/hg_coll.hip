@@ -34,7 +34,6 @@
 // looked-up set's buckets) in LDS, so that an item costs an LDS search, its
 // walked key and the looked-up bucket; per-item counts are summed per pair
 // inside each wave before one atomic add per (wave, pair).
-#include <rocprim/device/device_radix_sort.hpp>
 
 #include "hg_v2_device.h"
 
@@ -405,13 +404,7 @@ hipError_t copy_to_host(void* h, const void* d, size_t bytes, hipStream_t s) {
 }
 
 // temporary storage of the (bucket, position) radix sort
-size_t pair_sort_bytes(uint64_t n) {
-    if (n == 0) return 0;  // nothing to sort (and no size query that could fail)
-    size_t b = 0;
-    (void)rocprim::radix_sort_pairs((void*)nullptr, b, (uint32_t*)nullptr, (uint32_t*)nullptr,
-                                    (uint32_t*)nullptr, (uint32_t*)nullptr, (uint32_t)n, 0, 32);
-    return b;
-}
+size_t pair_sort_bytes(uint64_t n) { return n ? sort_pairs_ws_bytes(n) : 0; }
 
 // stream-ordered buffer released at scope exit
 struct AsyncBuf {
@@ -534,10 +527,13 @@ hipError_t run_coll_build(const Key* keys, const uint32_t* set_off, uint32_t S, 
         hipLaunchKernelGGL(k_big_keys<Key>, dim3(grid_of(nbk)), dim3(kT), 0, s, keys, set_off, bb,
                            (const uint64_t*)p.cb, S, nbk, seed, gb, pos);
         HG_TRY(hipGetLastError());
-        size_t tmp = pair_sort_bytes(nbk);
         const uint32_t bits = p.buckets <= 1 ? 1u : 64u - (uint32_t)__builtin_clzll(p.buckets - 1);
-        HG_TRY(rocprim::radix_sort_pairs(sort_tmp, tmp, gb, gb_s, pos, pos_s, (uint32_t)nbk, 0,
-                                         bits, s));
+        bool alt = false;
+        HG_TRY(sort_pairs_u32(gb, pos, gb_s, pos_s, nbk, bits, sort_tmp, &alt, s));
+        if (!alt) {  // the sorted pairs are in the first buffers
+            std::swap(gb, gb_s);
+            std::swap(pos, pos_s);
+        }
         hipLaunchKernelGGL(k_big_place<Key>, dim3(grid_of(nbk)), dim3(kT), 0, s, keys, set_off,
                            (const uint64_t*)p.cb, S, nbk, (const uint32_t*)pos_s, ids, ekeys);
         HG_TRY(hipGetLastError());

@@ -11,7 +11,7 @@
 //   2. each touched bucket moves its live entries down in order (the layout
 //      stays stable: ids keep their order inside the bucket), sets its new
 //      length and rewrites its probe index entry.  A bucket still longer
-//      than kRunBucket loses its key runs (z = ~0) and is scanned by probes.
+//      than kRunBucket loses its key runs (R = 0 in its entry) and is scanned by probes.
 // Readers take the length into account: the index entry carries the live end,
 // intersections skip stale slots of the walked table, and an export writes the
 // compacted CSR of the live entries.
@@ -79,8 +79,8 @@ __device__ __forceinline__ uint32_t compact_bucket(uint64_t h, const uint32_t* _
     const uint32_t nl = w - lo;
     len[h] = nl;
     uint4 e = head_entry<Key>(lo, w, ekeys + lo);
-    if (nl > kRunBucket) {  // no key runs any more: probes scan the bucket
-        e.z = ~0u;
+    if (nl > kRunBucket) {  // no key runs any more (R = 0): probes scan the bucket
+        e.z = 0;
         e.w = 0;
     }
     head[h] = e;

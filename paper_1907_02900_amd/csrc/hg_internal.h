@@ -119,6 +119,14 @@ hipError_t scan_excl(const uint32_t* in, uint64_t n, OutT* out, uint32_t* copy, 
 
 hipError_t fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
 
+// Stable LSD radix sort of n (key, value) uint32 pairs by the low `bits` bits
+// of the key (hg_sort.hip): ping-pongs between (k0, v0) and (k1, v1); the
+// sorted pairs end in (k1, v1) when *in_alt, else in (k0, v0).  ws:
+// sort_pairs_ws_bytes(n).
+size_t sort_pairs_ws_bytes(uint64_t n);
+hipError_t sort_pairs_u32(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, uint64_t n,
+                          uint32_t bits, void* ws, bool* in_alt, hipStream_t s);
+
 // *out = sum of v[0..n) (out outside v).
 hipError_t sum_u64(const unsigned long long* v, uint64_t n, unsigned long long* out,
                    hipStream_t s);
@@ -166,51 +174,57 @@ __host__ __device__ inline uint64_t filter_bits64(uint64_t k) {
     return (1ull << (x >> 58)) | (1ull << ((x >> 52) & 63u));
 }
 
-// Where a V2 build writes its probe index (head == null: none).  Every final
-// bin also writes bin_tally[bin] = {buckets longer than kRunBucket, their
-// total length} with plain stores (no device atomics: same-address atomics
-// serialise at the memory side across the XCDs).  k and bins are set by the
-// build (its plan) for the long-bucket listing that follows.
+// Key-run summary of the long buckets (more than kRunBucket entries): three
+// arrays parallel to the edge array.  For a long bucket at edge positions
+// [st, st + len) holding R distinct keys, run r < R has the key
+// run_key[st + r] (ascending in r) and ends at run_end[st + r] (an offset
+// from st: runs are cumulative), and kperm[st .. st + len) lists the bucket's
+// ids grouped by key in run order, in bucket order inside each group.  A
+// bucket of one repeated key (R = 1) writes no kperm: its ids are the edge
+// array's own.  The bucket's probe index entry is {len, st, R, key} with key
+// the (32-bit) key when R = 1, else 0; R = 0 marks a long bucket without runs
+// (after an erase): probes then scan it.
+struct RunsDev {
+    void* run_key = nullptr;     // Key[n]
+    uint32_t* run_end = nullptr; // [n]
+    uint32_t* kperm = nullptr;   // [n]
+};
+
+// Long buckets a per-bin kernel leaves to the general pass: bin g lists them
+// in gen_list[gen_region(start of bin g, g) ...] and stores their number in
+// gen_cnt[g].  A bin of L entries has at most L / (kRunBucket + 1) long
+// buckets, so the regions of consecutive bins never overlap and the list
+// needs n / (kRunBucket + 1) + bins + 1 entries.
+__host__ __device__ inline uint32_t gen_region(uint32_t bin_start, uint32_t g) {
+    return bin_start / (kRunBucket + 1) + g;
+}
+inline uint64_t gen_list_cap(uint64_t n, uint64_t bins) { return n / (kRunBucket + 1) + bins + 1; }
+
+// Where a V2 build writes its probe index (head == null: none) and the
+// key-run summary of its long buckets.  k and bins are set by the build.
 struct IndexOut {
     uint4* head = nullptr;
-    uint2* bin_tally = nullptr;  // [bins]
+    RunsDev runs{};
+    uint32_t* gen_list = nullptr;
+    uint32_t* gen_cnt = nullptr;  // [bins]
     uint32_t k = 0, bins = 0;
 };
 
-// Key-run summary arrays of a table (all sized for the summary's runs, kperm
-// for the edge array).
-struct RunsDev {
-    void* run_key = nullptr;       // Key[runs]: distinct keys, ascending per bucket
-    uint32_t* run_cnt = nullptr;   // [runs] entries with that key
-    uint32_t* run_pos = nullptr;   // [runs] edge position of the run in kperm
-    uint32_t* kperm = nullptr;     // [n] ids of long buckets grouped by key (ids ascending)
-};
-
-// Long-bucket listing after a build with the index: tally_ws_bytes(bins)
-// bytes of workspace; scan the per-bin tallies (pre[bins+1] = {count, length}
-// prefix sums, device), then, once their totals are known on the host, list
-// the long buckets (bucket ids, ascending) into long_list.
-size_t tally_ws_bytes(uint32_t bins);
-hipError_t scan_tally(const uint2* tally, uint32_t bins, uint32_t* pre_cnt, uint32_t* pre_len,
-                      void* ws, hipStream_t s);
-hipError_t list_long_buckets(const uint32_t* offsets, uint64_t V, uint32_t k, uint32_t bins,
-                             const uint2* tally, const uint32_t* pre_cnt, uint32_t* long_list,
-                             hipStream_t s);
-
-// Workspace for building the summary of `nlong` long buckets holding `total`
-// entries.
-size_t runs_ws_bytes(uint64_t nlong, uint64_t total, int key_bits);
-
-// Build the key-run summary of the long buckets listed in `long_list` and
-// point their head entries at it.  ws: runs_ws_bytes(nlong, total, kb).
+// The general pass over the long buckets the per-bin kernels listed (buckets
+// of many distinct keys, and every long bucket of the bins too large for
+// LDS).  Enqueued after the per-bin build; its work lists live on the device,
+// so nothing waits for the host.  ws: runs_ws_bytes(n, bins) bytes; rkeys /
+// rids: the build's reorganisation arrays (n entries), free by then and used
+// as scratch; ctr: two zeroed counters.
+size_t runs_ws_bytes(uint64_t n, uint64_t bins);
 template <typename Key>
 hipError_t run_key_runs(const uint32_t* offsets, const uint32_t* ids, const Key* ekeys,
-                        const uint32_t* long_list, uint32_t nlong, uint32_t total, uint4* head,
-                        const RunsDev& r, void* ws, hipStream_t s);
+                        uint64_t n, const uint32_t* bin_start, uint32_t bins, const IndexOut& ix,
+                        Key* rkeys, uint32_t* rids, uint32_t* ctr, void* ws, hipStream_t s);
 
 // ix.head (may be null): V 16-byte probe index entries, one per bucket, and
-// the per-bin tally of long buckets (IndexOut).  stable: ids ascend inside every
-// bucket (otherwise their order there is unspecified).
+// the key-run summary of long buckets (IndexOut).  stable: ids ascend inside
+// every bucket (otherwise their order there is unspecified).
 template <typename Key>
 hipError_t run_build_v2(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, uint32_t* offsets,
                         uint32_t* ids, Key* ekeys, IndexOut& ix, void* ws,

@@ -78,18 +78,18 @@ struct HeadKeys<uint64_t> {
     }
 };
 
-// Key-run summary of the long buckets (see hg_runs.hip).
+// Key-run summary of the long buckets (see hg_runs.hip and RunsDev): runs
+// of a bucket starting at edge position st are at [st, st + R) of key / end.
 template <typename Key>
 struct Runs {
-    const Key* key;        // distinct keys, ascending inside each long bucket
-    const uint32_t* cnt;   // entries per run
-    const uint32_t* pos;   // run start in kperm
-    const uint32_t* kperm; // ids grouped by key
+    const Key* key;         // distinct keys, ascending inside each long bucket
+    const uint32_t* end;    // end of each run's group (offset from the bucket start)
+    const uint32_t* kperm;  // ids grouped by key (buckets of several keys)
 };
 
 template <typename Key>
 Runs<Key> runs_of(const TableDev& t) {
-    return Runs<Key>{(const Key*)t.runs.run_key, t.runs.run_cnt, t.runs.run_pos, t.runs.kperm};
+    return Runs<Key>{(const Key*)t.runs.run_key, t.runs.run_end, t.runs.kperm};
 }
 
 // Run of q among runs [r0, r0 + d) (keys ascending), or ~0u if q is absent.
@@ -105,18 +105,39 @@ __device__ __forceinline__ uint32_t find_run(const Key* __restrict__ rk, uint32_
     return (lo < r0 + d && rk[lo] == q) ? lo : ~0u;
 }
 
+// Group [*b, *e) (offsets from the bucket start) of q in a long bucket whose
+// index entry is e = {len, st, R, key}; false if q is not in the bucket.  A
+// bucket of one key (R = 1) is answered from its entry (32-bit keys) or its
+// single run key.
+template <typename Key>
+__device__ __forceinline__ bool run_group(const uint4& e, const Runs<Key>& runs, Key q,
+                                          uint32_t* gb, uint32_t* ge) {
+    const uint32_t st = e.y, R = e.z;
+    if (R == 1) {
+        const bool hit = sizeof(Key) == 4 ? (uint32_t)q == e.w : runs.key[st] == q;
+        *gb = 0;
+        *ge = e.x;
+        return hit;
+    }
+    const uint32_t r = find_run(runs.key, st, R, q);
+    if (r == ~0u) return false;
+    *gb = r > st ? runs.end[r - 1] : 0u;
+    *ge = runs.end[r];
+    return true;
+}
+
 // Matches of q in a bucket described by its index entry: the keys held in the
 // entry are compared directly, the edge array is read only past them; a long
-// bucket's entry points at its key runs instead (z = first run, w = runs).
+// bucket's entry points at its key runs instead (R = 0: no runs, scanned).
 template <typename Key>
 __device__ __forceinline__ uint32_t count_with_head(const uint4& e, const Key* __restrict__ ekeys,
                                                     const Runs<Key>& runs, Key q) {
     using HK = HeadKeys<Key>;
     const uint32_t len = e.x;
     if (len > kRunBucket) {
-        if (e.z == ~0u) return count_in_bucket(ekeys, e.y, e.y + len, q);  // runs dropped by an erase
-        const uint32_t r = find_run(runs.key, e.z, e.w, q);
-        return r != ~0u ? runs.cnt[r] : 0u;
+        if (e.z == 0) return count_in_bucket(ekeys, e.y, e.y + len, q);  // runs dropped by an erase
+        uint32_t gb, ge;
+        return run_group(e, runs, q, &gb, &ge) ? ge - gb : 0u;
     }
     if (sizeof(Key) == 4 && len > HeadKeys<uint32_t>::full) {
         // {len, start, first key, its count | filter}: the first key's
@@ -244,7 +265,7 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_pairs(
         if (HEAD && !skip[r]) {
             const uint32_t len = er.x;
             const bool longb = len > kRunBucket;
-            via_runs[r] = longb && er.z != ~0u;
+            via_runs[r] = longb && er.z != 0u;
             nn[r] = longb ? 0u : HK::stored(len);
             if (HK::has_start(len)) {
                 st[r] = er.y;
@@ -264,15 +285,17 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_pairs(
         const uint4 er = e[r];
         uint64_t pos = positions[j];
         if (via_runs[r]) {
-            // the ids of q's run, in bucket order
-            const uint32_t rr = find_run(runs.key, er.z, er.w, k);
-            if (rr != ~0u)
-                for (uint32_t t = runs.pos[rr], te = t + runs.cnt[rr]; t < te && pos < pend[r];
-                     ++t) {
-                    build_ids[pos] = runs.kperm[t];
+            // the ids of q's group, in bucket order: the edge array's own for
+            // a bucket of one key, else its group in kperm
+            uint32_t gb, ge;
+            if (run_group(er, runs, k, &gb, &ge)) {
+                const uint32_t* src = er.z == 1 ? eids + er.y : runs.kperm + er.y;
+                for (uint32_t t = gb; t < ge && pos < pend[r]; ++t) {
+                    build_ids[pos] = src[t];
                     probe_ids[pos] = (uint32_t)j;
                     ++pos;
                 }
+            }
             continue;
         }
         const uint32_t start = st[r], len = HEAD ? er.x : er.y - er.x, n = nn[r];
@@ -297,10 +320,10 @@ __device__ __forceinline__ uint32_t count_in_a(const uint32_t* __restrict__ a_of
                                                const Key* __restrict__ a_keys, uint32_t h,
                                                Key k) {
     const uint32_t lo = a_off[h], hi = a_len ? lo + a_len[h] : a_off[h + 1];
-    if (a_head && hi - lo > kRunBucket && a_head[h].z != ~0u) {
+    if (a_head && hi - lo > kRunBucket) {
         const uint4 e = a_head[h];
-        const uint32_t r = find_run(runs.key, e.z, e.w, k);
-        return r != ~0u ? runs.cnt[r] : 0u;
+        uint32_t gb, ge;
+        if (e.z != 0) return run_group(e, runs, k, &gb, &ge) ? ge - gb : 0u;
     }
     return count_in_bucket(a_keys, lo, hi, k);
 }
@@ -363,16 +386,20 @@ __global__ __launch_bounds__(kProbeThreads) void k_intersect_pairs(
         if (b_len && p - b_off[h] >= b_len[h]) continue;  // stale slot of B
         const uint32_t lo = a_off[h], hi = a_len ? lo + a_len[h] : a_off[h + 1];
         const uint32_t bid = b_ids[p];
-        if (a_head && hi - lo > kRunBucket && a_head[h].z != ~0u) {
+        if (a_head && hi - lo > kRunBucket) {
             const uint4 e = a_head[h];
-            const uint32_t r = find_run(runs.key, e.z, e.w, k);
-            if (r != ~0u)
-                for (uint32_t t = runs.pos[r], te = t + runs.cnt[r]; t < te && pos < pend; ++t) {
-                    out_a[pos] = runs.kperm[t];
-                    out_b[pos] = bid;
-                    ++pos;
+            if (e.z != 0) {
+                uint32_t gb, ge;
+                if (run_group(e, runs, k, &gb, &ge)) {
+                    const uint32_t* src = e.z == 1 ? a_ids + e.y : runs.kperm + e.y;
+                    for (uint32_t t = gb; t < ge && pos < pend; ++t) {
+                        out_a[pos] = src[t];
+                        out_b[pos] = bid;
+                        ++pos;
+                    }
                 }
-            continue;
+                continue;
+            }
         }
         for (uint32_t i = lo; i < hi && pos < pend; ++i)
             if (a_keys[i] == k) {

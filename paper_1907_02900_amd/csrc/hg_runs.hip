@@ -5,488 +5,578 @@
 // large share of the input -- every probe of that bucket pays its full
 // length, so a skewed join costs as much as the number of matching pairs.
 // For each bucket longer than kRunBucket the table therefore also keeps the
-// bucket's distinct keys in ascending order, each with the number of entries
-// holding it and the start of its run in `kperm`, a copy of the bucket's ids
-// grouped by key (ids in bucket order inside each group).  The bucket's probe
-// index entry points at its runs.  A probe of a long bucket binary-searches
-// the runs; its pairs are the ids of one run.  Counts and pairs are exactly
-// those of a scan.
+// bucket's distinct keys in ascending order (its runs), each with the end of
+// its group in `kperm`, a copy of the bucket's ids grouped by key (bucket
+// order inside each group).  A probe of a long bucket binary-searches the
+// runs; its pairs are the ids of one group.  Counts and pairs are exactly
+// those of a scan.  The arrays are parallel to the edge array (see RunsDev),
+// so every bucket's summary has a fixed place and nothing is sized on the
+// host: a build with the index never waits for the device.
 //
-// Construction: every final bin of the build tallied its long buckets; a scan
-// of the tallies sizes the summary and a per-bin pass lists the long buckets.
-// A long bucket is usually one key repeated (duplicates) or dominated by one
-// key (skew), so the entries equal to their bucket's first key ("lead" key)
-// form a run directly, in bucket order, and only the other entries are
-// gathered, sorted by (bucket, key) with a stable device radix sort and cut
-// into runs.  The lead run is then slotted in at its place among the bucket's
-// sorted runs.
-#include <rocprim/device/device_radix_sort.hpp>
-
-#include "hg_internal.h"
+// Most long buckets are built inside the per-bin kernel, from LDS
+// (bin_long_runs): a long bucket is usually one key repeated (duplicates) or
+// dominated by one key (skew), so the entries equal to the bucket's first key
+// (the lead key) form one run and the few others are sorted across a wave.
+// This file holds the general pass for the rest, which the per-bin kernels
+// list per bin:
+//   * buckets of up to light_cap keys (one workgroup each, in LDS): the
+//     others are gathered, sorted (bitonic network in LDS) and cut into runs;
+//   * longer buckets (from bins too large for LDS), in chunks of kChunk
+//     entries spread over the grid: per chunk the others and those below the
+//     lead key are counted, a per-bucket scan turns the counts into chunk
+//     bases, each chunk then writes its others contiguously to scratch and its
+//     lead ids to kperm, and one workgroup per bucket sorts the others (LDS,
+//     or a workgroup-wide radix sort through global memory when they exceed
+//     LDS) and writes their runs.
+// Every kernel takes its amount of work from device counters and strides
+// over it with a fixed grid.
+#include "hg_v2_device.h"
 
 namespace hg {
 
 namespace {
 
-constexpr int kThreads = 256;
+using namespace v2dev;
 
-uint32_t blocks_for(uint64_t n) {
-    const uint64_t g = ceil_div(n, kThreads);
-    return (uint32_t)(g ? g : 1);
+constexpr int kRT = kLocalThreads;      // threads of the per-bucket kernels (512)
+constexpr int kCT = 256;                // threads of the per-chunk kernels
+constexpr int kCItems = 16;             // consecutive entries per thread of a chunk
+constexpr uint32_t kChunk = kCT * kCItems;  // 4096
+constexpr uint32_t kGenGrid = 2048;
+constexpr uint32_t kChunkGrid = 2048;
+constexpr uint32_t kBucketGrid = 512;
+
+// Entries the LDS sort of a bucket's other keys holds: light_cap rounded up
+// to a power of two (8192 for 32-bit keys, 4096 for 64-bit keys).
+template <typename Key>
+constexpr uint32_t lds_sort_cap() {
+    return sizeof(Key) == 8 ? 4096u : 8192u;
 }
 
-uint32_t bits_for(uint64_t count) {  // bits to hold values 0 .. count-1
-    uint32_t b = 0;
-    while (b < 32 && (1ull << b) < count) ++b;
-    return b;
+// Buckets longer than light_cap go through the chunked path.
+template <typename Key>
+constexpr uint32_t small_cap() {
+    return light_cap<Key>();
 }
 
-__global__ void k_long_len(const uint32_t* __restrict__ off, const uint32_t* __restrict__ list,
-                           uint32_t nlong, uint32_t* __restrict__ len) {
-    const uint32_t i = blockIdx.x * kThreads + threadIdx.x;
-    if (i < nlong) {
-        const uint32_t b = list[i];
-        len[i] = off[b + 1] - off[b];
+template <typename Key>
+__device__ __forceinline__ uint32_t key32(Key k) {
+    return sizeof(Key) == 4 ? (uint32_t)k : 0u;
+}
+
+// LDS of the per-bucket kernels: sort buffer, radix counters, scan temporaries.
+template <typename Key>
+struct BucketLds {
+    Key* sk;          // [lds_sort_cap]
+    uint32_t* sp;     // [lds_sort_cap]
+    uint32_t* wcnt;   // [W_LOCAL * 256]
+    uint32_t* dstart; // [256]
+    uint32_t* base;   // [256]
+    uint32_t* tmp;    // [2 * W_LOCAL + 2]
+    uint32_t* sh;     // [8] broadcast words
+    __host__ __device__ static constexpr size_t bytes() {
+        return (size_t)lds_sort_cap<Key>() * (sizeof(Key) + 4) + 4 * (W_LOCAL * 256 + 256 + 256 +
+                                                                     2 * W_LOCAL + 2 + 8) + 64;
+    }
+    __device__ explicit BucketLds(unsigned char* p) {
+        sk = (Key*)p;
+        sp = (uint32_t*)(sk + lds_sort_cap<Key>());
+        wcnt = sp + lds_sort_cap<Key>();
+        dstart = wcnt + W_LOCAL * 256;
+        base = dstart + 256;
+        tmp = base + 256;
+        sh = tmp + 2 * W_LOCAL + 2;
+    }
+};
+
+// Bitonic sort of n2 (a power of two) (key, position) pairs in LDS,
+// ascending; positions are distinct, so the order is total.  Barriers.
+template <typename Key>
+__device__ void lds_bitonic(Key* k, uint32_t* p, uint32_t n2) {
+    for (uint32_t size = 2; size <= n2; size <<= 1)
+        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+            for (uint32_t i = threadIdx.x; i < n2 / 2; i += kRT) {
+                const uint32_t lo = 2 * stride * (i / stride) + (i % stride), hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const Key ka = k[lo], kb = k[hi];
+                const uint32_t pa = p[lo], pb = p[hi];
+                const bool b_less = kb < ka || (kb == ka && pb < pa);
+                if (b_less == up) {
+                    k[lo] = kb;
+                    k[hi] = ka;
+                    p[lo] = pb;
+                    p[hi] = pa;
+                }
+            }
+            __syncthreads();
+        }
+}
+
+// Stable LSD radix sort (8-bit digits, every bit of the key) of O pairs
+// through global memory by one workgroup: (ka, pa) -> (kb, pb) -> ... The
+// number of passes is even, so the result ends in (ka, pa).  Barriers.
+template <typename Key>
+__device__ void wg_radix_sort(Key* ka, uint32_t* pa, Key* kb, uint32_t* pb, uint32_t O,
+                              const BucketLds<Key>& m) {
+    constexpr int IT = 8;
+    constexpr uint32_t tile = kRT * IT;
+    const uint32_t w = threadIdx.x / kWave, lane = lane_id();
+    for (uint32_t shift = 0; shift < sizeof(Key) * 8; shift += 8) {
+        for (uint32_t d = threadIdx.x; d < 256; d += kRT) m.base[d] = 0;
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < O; i += kRT)
+            atomicAdd(&m.base[(uint32_t)(ka[i] >> shift) & 255u], 1u);
+        __syncthreads();
+        uint32_t all;
+        const uint32_t v = threadIdx.x < 256 ? m.base[threadIdx.x] : 0u;
+        const uint32_t ex = block_excl_scan<kRT>(v, m.tmp, &all);
+        if (threadIdx.x < 256) m.base[threadIdx.x] = ex;
+        __syncthreads();
+        for (uint32_t t0 = 0; t0 < O; t0 += tile) {
+            const uint32_t cnt = O - t0 < tile ? O - t0 : tile;
+            Key k[IT];
+            uint32_t p[IT], dig[IT], pos[IT];
+#pragma unroll
+            for (int r = 0; r < IT; ++r) {
+                const uint32_t e = w * (kWave * IT) + r * kWave + lane;
+                if (e < cnt) {
+                    k[r] = ka[t0 + e];
+                    p[r] = pa[t0 + e];
+                    dig[r] = (uint32_t)(k[r] >> shift) & 255u;
+                } else {
+                    k[r] = 0;
+                    p[r] = 0;
+                    dig[r] = 256u;  // ignored by the ranking
+                }
+            }
+            rank_stable<kRT, IT>(dig, 8, m.wcnt, m.dstart, m.tmp, pos);
+#pragma unroll
+            for (int r = 0; r < IT; ++r)
+                if (dig[r] < 256u) {
+                    const uint32_t o = m.base[dig[r]] + pos[r] - m.dstart[dig[r]];
+                    kb[o] = k[r];
+                    pb[o] = p[r];
+                }
+            __syncthreads();
+            for (uint32_t d = threadIdx.x; d < 256; d += kRT)
+                m.base[d] += (d + 1 < 256 ? m.dstart[d + 1] : cnt) - m.dstart[d];
+            __syncthreads();
+        }
+        Key* tk = ka;
+        ka = kb;
+        kb = tk;
+        uint32_t* tp = pa;
+        pa = pb;
+        pb = tp;
     }
 }
 
-// largest i in [lo, hi) with base[i] <= j (base non-decreasing, base[lo] <= j)
-__device__ __forceinline__ uint32_t owner_in(const uint32_t* __restrict__ base, uint32_t lo,
-                                             uint32_t hi, uint32_t j) {
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (base[mid] <= j) lo = mid;
-        else hi = mid;
-    }
-    return lo;
-}
-
-// Owner (long-bucket list index) of gathered entry j = blockIdx.x * kThreads
-// + threadIdx.x: the workgroup finds the owners of its first and last entry
-// once, so each thread searches only the few buckets its workgroup spans.
-// All threads of the workgroup call it (barrier).
-__device__ __forceinline__ uint32_t block_owner(const uint32_t* __restrict__ base,
-                                                uint32_t nlong, uint32_t total, uint32_t j,
-                                                uint32_t* range) {
+// Runs of a long bucket (edge positions [st, st + len), lead key `lead`) from
+// its O > 0 other entries sorted by (key, position in the bucket) in sk / sp:
+// every other entry's id goes to kperm (before the lead key's group when its
+// key is smaller, after it otherwise), every run gets its key and end, the
+// lead run is slotted in, and the bucket's index entry points at the runs.
+// The lead key's ids are written by the caller.  Returns (via m.sh[0]) the
+// number of others below the lead key.  Whole workgroup; barriers.
+template <typename Key>
+__device__ void emit_runs(const Key* sk, const uint32_t* sp, uint32_t O, Key lead, uint32_t len,
+                          uint32_t st, uint32_t b, const uint32_t* __restrict__ ids,
+                          const IndexOut& ix, const BucketLds<Key>& m) {
+    Key* rkey = (Key*)ix.runs.run_key;
+    uint32_t* rend = ix.runs.run_end;
+    uint32_t* kperm = ix.runs.kperm;
     if (threadIdx.x == 0) {
-        const uint32_t j0 = blockIdx.x * kThreads;
-        const uint32_t j1 = (j0 + kThreads < total ? j0 + kThreads : total) - 1;
-        range[0] = owner_in(base, 0, nlong, j0);
-        range[1] = owner_in(base, range[0], nlong, j1) + 1;
+        uint32_t lo = 0, hi = O;  // others below the lead key
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (sk[mid] < lead) lo = mid + 1;
+            else hi = mid;
+        }
+        m.sh[0] = lo;
+        m.sh[1] = 0;  // runs below the lead key
     }
     __syncthreads();
-    return owner_in(base, range[0], range[1], j < total ? j : total - 1);
-}
-
-// other[j] = 1 if gathered entry j's key differs from its bucket's lead key.
-template <typename Key>
-__global__ __launch_bounds__(kThreads) void k_mark_others(
-    const uint32_t* __restrict__ off, const uint32_t* __restrict__ list,
-    const uint32_t* __restrict__ base, uint32_t nlong, uint32_t total,
-    const Key* __restrict__ ekeys, uint32_t* __restrict__ other) {
-    __shared__ uint32_t range[2];
-    const uint32_t j = blockIdx.x * kThreads + threadIdx.x;
-    const uint32_t i = block_owner(base, nlong, total, j, range);
-    if (j >= total) return;
-    const uint32_t s = off[list[i]];
-    other[j] = (ekeys[s + (j - base[i])] != ekeys[s]) ? 1u : 0u;
-}
-
-// Gather the other entries at their compacted slots: 32-bit keys get one
-// 64-bit sort key (list index << 32 | key) and their edge position; 64-bit
-// keys their key, slot, list index and edge position (two sort passes).
-template <typename Key>
-__global__ __launch_bounds__(kThreads) void k_gather_others(
-    const uint32_t* __restrict__ off, const uint32_t* __restrict__ list,
-    const uint32_t* __restrict__ base, uint32_t nlong, uint32_t total,
-    const Key* __restrict__ ekeys, const uint32_t* __restrict__ other,
-    const uint32_t* __restrict__ opos, uint64_t* __restrict__ sk, uint32_t* __restrict__ idx,
-    uint32_t* __restrict__ seg, uint32_t* __restrict__ pos) {
-    __shared__ uint32_t range[2];
-    const uint32_t j = blockIdx.x * kThreads + threadIdx.x;
-    const uint32_t i = block_owner(base, nlong, total, j, range);
-    if (j >= total || !other[j]) return;
-    const uint32_t t = opos[j];
-    const uint32_t p = off[list[i]] + (j - base[i]);
-    pos[t] = p;
-    if constexpr (sizeof(Key) == 4) {
-        sk[t] = ((uint64_t)i << 32) | ekeys[p];
-    } else {
-        sk[t] = ekeys[p];
-        idx[t] = t;
-        seg[t] = i;
+    const uint32_t nless = m.sh[0], clead = len - O;
+    uint32_t runs = 0;  // other runs before this tile
+    for (uint32_t t0 = 0; t0 < O; t0 += kRT) {
+        const uint32_t i = t0 + threadIdx.x;
+        const bool valid = i < O;
+        const Key k = valid ? sk[i] : (Key)0;
+        const bool first = valid && (i == 0 || sk[i - 1] != k);
+        const bool last = valid && (i + 1 == O || sk[i + 1] != k);
+        uint32_t all;
+        const uint32_t ex = block_excl_scan<kRT>(first ? 1u : 0u, m.tmp, &all);
+        if (valid) {
+            const bool below = i < nless;
+            const uint32_t ro = runs + ex + (first ? 1u : 0u) - 1u;  // run among the others
+            const uint32_t r = ro + (below ? 0u : 1u);
+            kperm[st + i + (below ? 0u : clead)] = ids[st + sp[i]];
+            if (first) rkey[st + r] = k;
+            if (last) rend[st + r] = i + 1 + (below ? 0u : clead);
+            if (i + 1 == nless) m.sh[1] = ro + 1;
+        }
+        runs += all;
     }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t rl = m.sh[1];
+        rkey[st + rl] = lead;
+        rend[st + rl] = nless + clead;
+        ix.head[b] = make_uint4(len, st, runs + 1, 0u);
+    }
+    __syncthreads();
 }
 
-// after the key sort of 64-bit keys: out[u] = val[idx[u]], ord[u] = u
-__global__ void k_take(const uint32_t* __restrict__ idx, const uint32_t* __restrict__ val,
-                       uint32_t total, uint32_t* __restrict__ out, uint32_t* __restrict__ ord) {
-    const uint32_t u = blockIdx.x * kThreads + threadIdx.x;
-    if (u >= total) return;
-    out[u] = val[idx[u]];
-    if (ord) ord[u] = u;
-}
-
-// Sorted view of the other entries: entry t has list index, key, edge position.
+// A bucket of one key: a single run, no kperm (its ids are the edge array's).
 template <typename Key>
-struct Sorted {
-    const uint32_t* sseg;  // 64-bit keys: list index by sorted position
-    const Key* skey;       // 64-bit keys: key by key-sorted index
-    const uint64_t* comp;  // 32-bit keys: (list index << 32 | key)
-    const uint32_t* spos;  // edge position (by sorted position / key-sorted index)
-    const uint32_t* ord;   // 64-bit keys: sorted position -> key-sorted index
+__device__ __forceinline__ void single_run(const IndexOut& ix, uint32_t b, uint32_t st,
+                                           uint32_t len, Key lead) {
+    ((Key*)ix.runs.run_key)[st] = lead;
+    ix.runs.run_end[st] = len;
+    ix.head[b] = make_uint4(len, st, 1u, key32(lead));
+}
+
+struct G2 {
+    uint32_t* list;    // [cap] bucket ids
+    uint32_t* c0;      // [cap] first chunk
+    uint32_t* info;    // [2 * cap] others, others below the lead key
+    uint32_t* owner;   // [chunks] bucket (index in list) of each chunk
+    uint32_t* oth;     // [chunks] others, then their exclusive prefix in the bucket
+    uint32_t* less;    // [chunks] others below the lead key, then their prefix
+    uint32_t cap, chunk_cap;
 };
 
-template <typename Key>
-__device__ __forceinline__ void sorted_at(const Sorted<Key>& s, uint32_t t, uint32_t& seg, Key& k,
-                                          uint32_t& p) {
-    if constexpr (sizeof(Key) == 4) {
-        const uint64_t c = s.comp[t];
-        seg = (uint32_t)(c >> 32);
-        k = (Key)(uint32_t)c;
-        p = s.spos[t];
-    } else {
-        const uint32_t u = s.ord[t];
-        seg = s.sseg[t];
-        k = s.skey[u];
-        p = s.spos[u];
-    }
-}
-
-template <typename Key>
-__global__ void k_run_flags(Sorted<Key> s, uint32_t total, uint32_t* __restrict__ flag) {
-    const uint32_t t = blockIdx.x * kThreads + threadIdx.x;
-    if (t >= total) return;
-    uint32_t seg, p;
-    Key k;
-    sorted_at(s, t, seg, k, p);
-    uint32_t f = 1;
-    if (t) {
-        uint32_t seg0, p0;
-        Key k0;
-        sorted_at(s, t - 1, seg0, k0, p0);
-        f = (seg0 != seg || k0 != k) ? 1u : 0u;
-    }
-    flag[t] = f;
-}
-
-// Per long bucket: its first edge, lead-run size, first other entry in sorted
-// order, others below the lead key, first run, runs below the lead key.
-struct BucketRuns {
-    uint32_t start, lead_cnt, obase, nless, rbase, nrless;
+struct G2Layout {
+    G2 g;
+    size_t bytes;
 };
 
-// One thread per long bucket: place the lead run among the bucket's runs and
-// point the index entry at them.
+G2Layout layout_g2(void* ws, uint64_t n) {
+    Carver c(ws);
+    G2 g{};
+    g.cap = (uint32_t)(n / (light_cap<uint64_t>() + 1) + 1);
+    g.chunk_cap = (uint32_t)(n / kChunk + g.cap + 1);
+    g.list = c.take<uint32_t>(g.cap);
+    g.c0 = c.take<uint32_t>(g.cap);
+    g.info = c.take<uint32_t>(2 * (size_t)g.cap);
+    g.owner = c.take<uint32_t>(g.chunk_cap);
+    g.oth = c.take<uint32_t>(g.chunk_cap);
+    g.less = c.take<uint32_t>(g.chunk_cap);
+    return G2Layout{g, c.off + 256};
+}
+
+// The listed long buckets of every bin: small ones are finished here, in
+// LDS; longer ones are handed to the chunked path (ctr[0] buckets, ctr[1]
+// chunks).
 template <typename Key>
-__global__ void k_bucket_runs(const uint32_t* __restrict__ off, const uint32_t* __restrict__ list,
-                              const uint32_t* __restrict__ base, uint32_t nlong,
-                              const uint32_t* __restrict__ opos, const uint32_t* __restrict__ rid,
-                              Sorted<Key> s, const Key* __restrict__ ekeys,
-                              BucketRuns* __restrict__ br, Key* __restrict__ run_key,
-                              uint32_t* __restrict__ run_cnt, uint32_t* __restrict__ run_pos,
-                              uint4* __restrict__ head) {
-    const uint32_t i = blockIdx.x * kThreads + threadIdx.x;
-    if (i >= nlong) return;
-    const uint32_t b = list[i];
-    const uint32_t st = off[b], len = off[b + 1] - st;
-    const uint32_t o0 = opos[base[i]], o1 = opos[base[i + 1]];
-    const Key lead = ekeys[st];
-    // others of this bucket below the lead key (they are sorted by key)
-    uint32_t lo = o0, hi = o1;
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        uint32_t sg, p;
-        Key k;
-        sorted_at(s, mid, sg, k, p);
-        if (k < lead) lo = mid + 1;
-        else hi = mid;
-    }
-    BucketRuns r;
-    r.start = st;
-    r.lead_cnt = len - (o1 - o0);
-    r.obase = o0;
-    r.nless = lo - o0;
-    r.rbase = i + rid[o0];  // a lead run per earlier bucket, plus their other runs
-    r.nrless = rid[lo] - rid[o0];
-    br[i] = r;
-    const uint32_t slot = r.rbase + r.nrless;
-    run_key[slot] = lead;
-    run_cnt[slot] = r.lead_cnt;
-    run_pos[slot] = st + r.nless;
-    uint4 e = head[b];
-    e.z = r.rbase;
-    e.w = (rid[o1] - rid[o0]) + 1;
-    head[b] = e;
-}
-
-// Other entries: their kperm slots, and the runs they start.
-template <typename Key>
-__global__ void k_emit_others(Sorted<Key> s, uint32_t nother, const uint32_t* __restrict__ flag,
-                              const uint32_t* __restrict__ rid,
-                              const BucketRuns* __restrict__ br, const uint32_t* __restrict__ ids,
-                              Key* __restrict__ run_key, uint32_t* __restrict__ run_pos,
-                              uint32_t* __restrict__ rstart, uint32_t* __restrict__ rslot,
-                              uint32_t* __restrict__ kperm) {
-    const uint32_t t = blockIdx.x * kThreads + threadIdx.x;
-    if (t >= nother) return;
-    uint32_t seg, p;
-    Key k;
-    sorted_at(s, t, seg, k, p);
-    const BucketRuns r = br[seg];
-    const uint32_t lt = t - r.obase;
-    const bool above = lt >= r.nless;  // key above the lead key
-    const uint32_t at = r.start + lt + (above ? r.lead_cnt : 0u);
-    kperm[at] = ids[p];
-    if (flag[t]) {
-        const uint32_t g = rid[t];  // index among all other runs
-        const uint32_t slot = r.rbase + (g - rid[r.obase]) + (above ? 1u : 0u);
-        run_key[slot] = k;
-        run_pos[slot] = at;
-        rstart[g] = t;
-        rslot[g] = slot;
-    }
-}
-
-// counts of the other runs (runs never cross buckets); *nruns other runs
-__global__ void k_other_cnt(const uint32_t* __restrict__ rstart,
-                            const uint32_t* __restrict__ rslot, const uint32_t* __restrict__ nruns,
-                            uint32_t nother, uint32_t* __restrict__ run_cnt) {
-    const uint32_t g = blockIdx.x * kThreads + threadIdx.x;
-    const uint32_t R = *nruns;
-    if (g >= R) return;
-    run_cnt[rslot[g]] = ((g + 1 < R) ? rstart[g + 1] : nother) - rstart[g];
-}
-
-// Lead-key entries: kperm slots in bucket order, after the bucket's lower others.
-__global__ __launch_bounds__(kThreads) void k_emit_lead(
-    const uint32_t* __restrict__ base, uint32_t nlong, uint32_t total,
-    const uint32_t* __restrict__ other, const uint32_t* __restrict__ opos,
-    const BucketRuns* __restrict__ br, const uint32_t* __restrict__ ids,
-    uint32_t* __restrict__ kperm) {
-    __shared__ uint32_t range[2];
-    const uint32_t j = blockIdx.x * kThreads + threadIdx.x;
-    const uint32_t i = block_owner(base, nlong, total, j, range);
-    if (j >= total || other[j]) return;
-    const BucketRuns r = br[i];
-    const uint32_t lj = j - base[i];                 // position in the bucket
-    const uint32_t rank = lj - (opos[j] - r.obase);  // lead entries before it
-    kperm[r.start + r.nless + rank] = ids[r.start + lj];
-}
-
-// per-bin tallies -> two count arrays
-__global__ void k_split_tally(const uint2* __restrict__ tally, uint32_t bins,
-                              uint32_t* __restrict__ cnt, uint32_t* __restrict__ len) {
-    const uint32_t g = blockIdx.x * kThreads + threadIdx.x;
-    if (g < bins) {
-        const uint2 t = tally[g];
-        cnt[g] = t.x;
-        len[g] = t.y;
-    }
-}
-
-// Long buckets of every bin with any, ascending, at the bin's slot range.
-__global__ __launch_bounds__(kThreads) void k_list_long(const uint32_t* __restrict__ off,
-                                                        uint32_t V, uint32_t k, uint32_t bins,
-                                                        const uint2* __restrict__ tally,
-                                                        const uint32_t* __restrict__ pre,
-                                                        uint32_t* __restrict__ list) {
-    __shared__ uint32_t tmp[kThreads / kWave + 1];
-    const uint32_t NB = 1u << k;
+__global__ __launch_bounds__(kRT) void k_runs_general(
+    const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ ids,
+    const Key* __restrict__ ekeys, const uint32_t* __restrict__ bin_start, uint32_t bins,
+    IndexOut ix, G2 g2, uint32_t* __restrict__ ctr) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const BucketLds<Key> m(smem);
     for (uint32_t g = blockIdx.x; g < bins; g += gridDim.x) {
-        if (tally[g].x == 0) continue;  // uniform across the workgroup
-        const uint32_t v0 = g << k, nb = (V - v0 < NB) ? V - v0 : NB;
-        uint32_t at = pre[g];
-        for (uint32_t c0 = 0; c0 < nb; c0 += kThreads) {
-            const uint32_t v = c0 + threadIdx.x;
-            const uint32_t f = (v < nb && off[v0 + v + 1] - off[v0 + v] > kRunBucket) ? 1u : 0u;
-            uint32_t all;
-            const uint32_t r = block_excl_scan<kThreads>(f, tmp, &all);
-            if (f) list[at + r] = v0 + v;
-            at += all;
+        const uint32_t listed = ix.gen_cnt[g];
+        if (listed == 0) continue;  // uniform across the workgroup
+        const uint32_t* list = ix.gen_list + gen_region(bin_start[g], g);
+        for (uint32_t t = 0; t < listed; ++t) {
+            const uint32_t b = list[t];
+            const uint32_t st = offsets[b], len = offsets[b + 1] - st;
+            const Key lead = ekeys[st];
+            if (len > small_cap<Key>()) {
+                if (threadIdx.x == 0) {
+                    const uint32_t nch = (len + kChunk - 1) / kChunk;
+                    const uint32_t i = atomicAdd(&ctr[0], 1u);
+                    const uint32_t c0 = atomicAdd(&ctr[1], nch);
+                    m.sh[2] = i;
+                    m.sh[3] = c0;
+                    if (i < g2.cap && c0 + nch <= g2.chunk_cap) {
+                        g2.list[i] = b;
+                        g2.c0[i] = c0;
+                    }
+                }
+                __syncthreads();
+                const uint32_t i = m.sh[2], c0 = m.sh[3];
+                const uint32_t nch = (len + kChunk - 1) / kChunk;
+                if (i < g2.cap && c0 + nch <= g2.chunk_cap)
+                    for (uint32_t j = threadIdx.x; j < nch; j += kRT) g2.owner[c0 + j] = i;
+                __syncthreads();
+                continue;
+            }
+            // gather the entries that differ from the lead key, in bucket order
+            uint32_t O = 0;
+            for (uint32_t c = 0; c < len; c += kRT) {
+                const uint32_t i = c + threadIdx.x;
+                const Key x = i < len ? ekeys[st + i] : lead;
+                const bool o = x != lead;
+                uint32_t all;
+                const uint32_t ex = block_excl_scan<kRT>(o ? 1u : 0u, m.tmp, &all);
+                if (o) {
+                    m.sk[O + ex] = x;
+                    m.sp[O + ex] = i;
+                }
+                O += all;
+            }
+            if (O == 0) {
+                if (threadIdx.x == 0) single_run<Key>(ix, b, st, len, lead);
+                __syncthreads();
+                continue;
+            }
+            uint32_t n2 = 1;
+            while (n2 < O) n2 <<= 1;
+            for (uint32_t i = O + threadIdx.x; i < n2; i += kRT) {
+                m.sk[i] = (Key)~(Key)0;
+                m.sp[i] = 0xffffffffu;
+            }
+            __syncthreads();
+            lds_bitonic<Key>(m.sk, m.sp, n2);
+            emit_runs<Key>(m.sk, m.sp, O, lead, len, st, b, ids, ix, m);
+            // the lead key's ids, in bucket order, after the smaller keys
+            const uint32_t nless = m.sh[0];
+            uint32_t done = 0;
+            for (uint32_t c = 0; c < len; c += kRT) {
+                const uint32_t i = c + threadIdx.x;
+                const bool isl = i < len && ekeys[st + i] == lead;
+                uint32_t all;
+                const uint32_t ex = block_excl_scan<kRT>(isl ? 1u : 0u, m.tmp, &all);
+                if (isl) ix.runs.kperm[st + nless + done + ex] = ids[st + i];
+                done += all;
+            }
+            __syncthreads();
         }
     }
 }
 
-size_t sort_tmp_bytes(uint32_t total, int key_bits) {
-    size_t a = 0, b = 0;
-    (void)rocprim::radix_sort_pairs((void*)nullptr, a, (uint64_t*)nullptr, (uint64_t*)nullptr,
-                                    (uint32_t*)nullptr, (uint32_t*)nullptr, total, 0, 64);
-    if (key_bits == 64)
-        (void)rocprim::radix_sort_pairs((void*)nullptr, b, (uint32_t*)nullptr,
-                                        (uint32_t*)nullptr, (uint32_t*)nullptr,
-                                        (uint32_t*)nullptr, total, 0, 32);
-    return a > b ? a : b;
-}
-
-struct RunsWs {
-    uint32_t *len, *base, *other, *opos;
-    uint64_t *sk, *sk_s;
-    uint32_t *pos, *pos_s, *idx, *idx_s, *seg, *seg2, *seg2_s, *ord, *ord_s;
-    uint32_t *flag, *rid, *rstart, *rslot;
-    BucketRuns* br;
-    void* scan_ws;
-    void* sort_tmp;
-    size_t sort_bytes;
+// Chunk c of a long bucket: thread t holds entries [t*16, t*16 + 16) of the
+// chunk (consecutive, so thread order is bucket order).
+struct ChunkRef {
+    uint32_t i, b, st, len, base, cl;
 };
 
-// Workspace for `total` long-bucket entries (the other entries are at most as
-// many).
-size_t layout_runs(void* ws, uint64_t nlong, uint64_t total, int key_bits, RunsWs* w) {
-    Carver c(ws);
-    RunsWs t{};
-    t.len = c.take<uint32_t>(nlong + 1);
-    t.base = c.take<uint32_t>(nlong + 1);
-    t.other = c.take<uint32_t>(total);
-    t.opos = c.take<uint32_t>(total + 1);
-    t.sk = c.take<uint64_t>(total);
-    t.sk_s = c.take<uint64_t>(total);
-    t.pos = c.take<uint32_t>(total);
-    t.pos_s = c.take<uint32_t>(total);
-    if (key_bits == 64) {
-        t.idx = c.take<uint32_t>(total);
-        t.idx_s = c.take<uint32_t>(total);
-        t.seg = c.take<uint32_t>(total);
-        t.seg2 = c.take<uint32_t>(total);
-        t.seg2_s = c.take<uint32_t>(total);
-        t.ord = c.take<uint32_t>(total);
-        t.ord_s = c.take<uint32_t>(total);
+template <typename Key>
+__device__ __forceinline__ ChunkRef chunk_at(uint32_t c, const G2& g2,
+                                             const uint32_t* __restrict__ offsets) {
+    ChunkRef r;
+    r.i = g2.owner[c];
+    r.b = g2.list[r.i];
+    r.st = offsets[r.b];
+    r.len = offsets[r.b + 1] - r.st;
+    r.base = (c - g2.c0[r.i]) * kChunk;
+    r.cl = r.len - r.base < kChunk ? r.len - r.base : kChunk;
+    return r;
+}
+
+// Per chunk: entries that differ from the lead key, and of them those below it.
+template <typename Key>
+__global__ __launch_bounds__(kCT) void k_runs_chunk_count(const uint32_t* __restrict__ offsets,
+                                                          const Key* __restrict__ ekeys, G2 g2,
+                                                          const uint32_t* __restrict__ ctr) {
+    __shared__ uint32_t red[2 * (kCT / kWave)];
+    const uint32_t nch = ctr[1] < g2.chunk_cap ? ctr[1] : g2.chunk_cap;
+    for (uint32_t c = blockIdx.x; c < nch; c += gridDim.x) {
+        const ChunkRef r = chunk_at<Key>(c, g2, offsets);
+        const Key lead = ekeys[r.st];
+        uint32_t o = 0, l = 0;
+#pragma unroll 4
+        for (int j = 0; j < kCItems; ++j) {
+            const uint32_t e = threadIdx.x * kCItems + j;
+            if (e < r.cl) {
+                const Key x = ekeys[r.st + r.base + e];
+                o += x != lead;
+                l += x < lead;
+            }
+        }
+        o = wave_sum(o);
+        l = wave_sum(l);
+        if (lane_id() == 0) {
+            red[threadIdx.x / kWave] = o;
+            red[kCT / kWave + threadIdx.x / kWave] = l;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t so = 0, sl = 0;
+            for (int q = 0; q < kCT / kWave; ++q) {
+                so += red[q];
+                sl += red[kCT / kWave + q];
+            }
+            g2.oth[c] = so;
+            g2.less[c] = sl;
+        }
+        __syncthreads();
     }
-    t.flag = c.take<uint32_t>(total);
-    t.rid = c.take<uint32_t>(total + 1);
-    t.rstart = c.take<uint32_t>(total);
-    t.rslot = c.take<uint32_t>(total);
-    t.br = c.take<BucketRuns>(nlong);
-    const uint64_t sn = total > nlong ? total : nlong;
-    t.scan_ws = c.take<char>(scan_ws_bytes(sn));
-    t.sort_bytes = sort_tmp_bytes((uint32_t)total, key_bits);
-    t.sort_tmp = c.take<char>(t.sort_bytes);
-    if (w) *w = t;
-    return c.off + 256;
+}
+
+// Per long bucket: exclusive prefixes of its chunks' counts (in place), the
+// totals, and a bucket of one key finished outright.
+template <typename Key>
+__global__ __launch_bounds__(kRT) void k_runs_chunk_scan(const uint32_t* __restrict__ offsets,
+                                                         const Key* __restrict__ ekeys,
+                                                         IndexOut ix, G2 g2,
+                                                         const uint32_t* __restrict__ ctr) {
+    __shared__ uint32_t tmp[kRT / kWave + 1];
+    const uint32_t nb2 = ctr[0] < g2.cap ? ctr[0] : g2.cap;
+    for (uint32_t i = blockIdx.x; i < nb2; i += gridDim.x) {
+        const uint32_t b = g2.list[i], c0 = g2.c0[i];
+        const uint32_t st = offsets[b], len = offsets[b + 1] - st;
+        const uint32_t nch = (len + kChunk - 1) / kChunk;
+        uint32_t co = 0, cl = 0;
+        for (uint32_t t0 = 0; t0 < nch; t0 += kRT) {
+            const uint32_t j = t0 + threadIdx.x;
+            const uint32_t vo = j < nch ? g2.oth[c0 + j] : 0u;
+            const uint32_t vl = j < nch ? g2.less[c0 + j] : 0u;
+            uint32_t ao, al;
+            const uint32_t eo = block_excl_scan<kRT>(vo, tmp, &ao);
+            const uint32_t el = block_excl_scan<kRT>(vl, tmp, &al);
+            if (j < nch) {
+                g2.oth[c0 + j] = co + eo;
+                g2.less[c0 + j] = cl + el;
+            }
+            co += ao;
+            cl += al;
+        }
+        if (threadIdx.x == 0) {
+            g2.info[2 * i] = co;
+            g2.info[2 * i + 1] = cl;
+            if (co == 0) single_run<Key>(ix, b, st, len, ekeys[st]);
+        }
+    }
+}
+
+// Per chunk (buckets with other keys): the others go contiguously to the
+// scratch arrays (key, position in the bucket), the lead key's ids to kperm
+// after the smaller keys' groups.
+template <typename Key>
+__global__ __launch_bounds__(kCT) void k_runs_chunk_scatter(
+    const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ ids,
+    const Key* __restrict__ ekeys, IndexOut ix, G2 g2, const uint32_t* __restrict__ ctr,
+    Key* __restrict__ skey, uint32_t* __restrict__ spos) {
+    __shared__ uint32_t tmp[kCT / kWave + 1];
+    const uint32_t nch = ctr[1] < g2.chunk_cap ? ctr[1] : g2.chunk_cap;
+    for (uint32_t c = blockIdx.x; c < nch; c += gridDim.x) {
+        const ChunkRef r = chunk_at<Key>(c, g2, offsets);
+        const uint32_t O = g2.info[2 * r.i], nless = g2.info[2 * r.i + 1];
+        if (O == 0) continue;  // uniform: a single run, no kperm
+        const Key lead = ekeys[r.st];
+        const uint32_t obase = g2.oth[c], lbase = r.base - obase;
+        Key x[kCItems];
+        uint32_t mine = 0;
+#pragma unroll
+        for (int j = 0; j < kCItems; ++j) {
+            const uint32_t e = threadIdx.x * kCItems + j;
+            x[j] = e < r.cl ? ekeys[r.st + r.base + e] : lead;
+            mine += x[j] != lead;
+        }
+        uint32_t all;
+        uint32_t o = obase + block_excl_scan<kCT>(mine, tmp, &all);
+        uint32_t l = lbase + threadIdx.x * kCItems - (o - obase);
+#pragma unroll
+        for (int j = 0; j < kCItems; ++j) {
+            const uint32_t e = threadIdx.x * kCItems + j;
+            if (e >= r.cl) break;
+            if (x[j] != lead) {
+                skey[r.st + o] = x[j];
+                spos[r.st + o] = r.base + e;
+                ++o;
+            } else {
+                ix.runs.kperm[r.st + nless + l] = ids[r.st + r.base + e];
+                ++l;
+            }
+        }
+    }
+}
+
+// Per long bucket with other keys: sort the others (LDS when they fit, else a
+// workgroup radix sort through global memory) and write their runs.
+template <typename Key>
+__global__ __launch_bounds__(kRT) void k_runs_chunk_sort(
+    const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ ids,
+    const Key* __restrict__ ekeys, IndexOut ix, G2 g2, const uint32_t* __restrict__ ctr,
+    Key* __restrict__ skey, uint32_t* __restrict__ spos) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const BucketLds<Key> m(smem);
+    const uint32_t nb2 = ctr[0] < g2.cap ? ctr[0] : g2.cap;
+    for (uint32_t i = blockIdx.x; i < nb2; i += gridDim.x) {
+        const uint32_t O = g2.info[2 * i];
+        if (O == 0) continue;
+        const uint32_t b = g2.list[i];
+        const uint32_t st = offsets[b], len = offsets[b + 1] - st;
+        const Key lead = ekeys[st];
+        if (O <= lds_sort_cap<Key>()) {
+            uint32_t n2 = 1;
+            while (n2 < O) n2 <<= 1;
+            for (uint32_t t = threadIdx.x; t < n2; t += kRT) {
+                m.sk[t] = t < O ? skey[st + t] : (Key)~(Key)0;
+                m.sp[t] = t < O ? spos[st + t] : 0xffffffffu;
+            }
+            __syncthreads();
+            lds_bitonic<Key>(m.sk, m.sp, n2);
+            emit_runs<Key>(m.sk, m.sp, O, lead, len, st, b, ids, ix, m);
+        } else {
+            // the run arrays of [st, st + O) serve as the second buffer; the
+            // sorted pairs end back in the scratch arrays
+            wg_radix_sort<Key>(skey + st, spos + st, (Key*)ix.runs.run_key + st,
+                               ix.runs.run_end + st, O, m);
+            emit_runs<Key>(skey + st, spos + st, O, lead, len, st, b, ids, ix, m);
+        }
+    }
+}
+
+template <typename Key>
+hipError_t set_runs_smem() {
+    static std::atomic<uint64_t> done{0};
+    return once_per_device(done, [] {
+        const int lim = 160 * 1024;
+        HG_TRY(hipFuncSetAttribute((const void*)k_runs_general<Key>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+        HG_TRY(hipFuncSetAttribute((const void*)k_runs_chunk_sort<Key>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+        return hipSuccess;
+    });
 }
 
 }  // namespace
 
-size_t tally_ws_bytes(uint32_t bins) {
-    return 2 * align_up(((size_t)bins + 1) * 4, 256) + scan_ws_bytes(bins) + 512;
-}
-
-hipError_t scan_tally(const uint2* tally, uint32_t bins, uint32_t* pre_cnt, uint32_t* pre_len,
-                      void* ws, hipStream_t s) {
-    Carver c(ws);
-    uint32_t* cnt = c.take<uint32_t>((size_t)bins + 1);
-    uint32_t* len = c.take<uint32_t>((size_t)bins + 1);
-    void* sws = c.take<char>(scan_ws_bytes(bins));
-    hipLaunchKernelGGL(k_split_tally, dim3(blocks_for(bins)), dim3(kThreads), 0, s, tally, bins,
-                       cnt, len);
-    HG_TRY(hipGetLastError());
-    HG_TRY(scan_excl<uint32_t>(cnt, bins, pre_cnt, nullptr, sws, s));
-    return scan_excl<uint32_t>(len, bins, pre_len, nullptr, sws, s);
-}
-
-hipError_t list_long_buckets(const uint32_t* offsets, uint64_t V, uint32_t k, uint32_t bins,
-                             const uint2* tally, const uint32_t* pre_cnt, uint32_t* long_list,
-                             hipStream_t s) {
-    const uint32_t grid = bins < 16384 ? bins : 16384;
-    hipLaunchKernelGGL(k_list_long, dim3(grid ? grid : 1), dim3(kThreads), 0, s, offsets,
-                       (uint32_t)V, k, bins, tally, pre_cnt, long_list);
-    return hipGetLastError();
-}
-
-size_t runs_ws_bytes(uint64_t nlong, uint64_t total, int key_bits) {
-    return layout_runs(nullptr, nlong, total, key_bits, nullptr);
+size_t runs_ws_bytes(uint64_t n, uint64_t bins) {
+    (void)bins;
+    return layout_g2(nullptr, n).bytes;
 }
 
 template <typename Key>
 hipError_t run_key_runs(const uint32_t* offsets, const uint32_t* ids, const Key* ekeys,
-                        const uint32_t* long_list, uint32_t nlong, uint32_t total, uint4* head,
-                        const RunsDev& r, void* ws, hipStream_t s) {
-    if (nlong == 0 || total == 0) return hipSuccess;
-    RunsWs w;
-    layout_runs(ws, nlong, total, sizeof(Key) * 8, &w);
+                        uint64_t n, const uint32_t* bin_start, uint32_t bins, const IndexOut& ix,
+                        Key* rkeys, uint32_t* rids, uint32_t* ctr, void* ws, hipStream_t s) {
+    if (n == 0 || bins == 0) return hipSuccess;
+    HG_TRY(set_runs_smem<Key>());
+    const G2 g2 = layout_g2(ws, n).g;
+    const size_t lds = BucketLds<Key>::bytes();
     HG_PROF("runs_build", s);
-    const dim3 gl(blocks_for(nlong)), gt(blocks_for(total)), th(kThreads);
-    hipLaunchKernelGGL(k_long_len, gl, th, 0, s, offsets, long_list, nlong, w.len);
+    const uint32_t gg = bins < kGenGrid ? bins : kGenGrid;
+    hipLaunchKernelGGL(k_runs_general<Key>, dim3(gg), dim3(kRT), lds, s, offsets, ids, ekeys,
+                       bin_start, bins, ix, g2, ctr);
     HG_TRY(hipGetLastError());
-    HG_TRY(scan_excl<uint32_t>(w.len, nlong, w.base, nullptr, w.scan_ws, s));
-    hipLaunchKernelGGL(k_mark_others<Key>, gt, th, 0, s, offsets, long_list,
-                       (const uint32_t*)w.base, nlong, total, ekeys, w.other);
+    // the chunked path: grids sized for the most work there can be, strided
+    // over what the counters hold
+    const uint32_t cg = (uint32_t)(g2.chunk_cap < kChunkGrid ? g2.chunk_cap : kChunkGrid);
+    const uint32_t bg = g2.cap < kBucketGrid ? g2.cap : kBucketGrid;
+    hipLaunchKernelGGL(k_runs_chunk_count<Key>, dim3(cg), dim3(kCT), 0, s, offsets, ekeys, g2,
+                       (const uint32_t*)ctr);
     HG_TRY(hipGetLastError());
-    HG_TRY(scan_excl<uint32_t>(w.other, total, w.opos, nullptr, w.scan_ws, s));
-    // the sort is sized by the number of other entries
-    uint32_t nother = 0;
-    HG_TRY(hipMemcpyAsync(&nother, w.opos + total, 4, hipMemcpyDeviceToHost, s));
-    HG_TRY(hipStreamSynchronize(s));
-    Sorted<Key> sv{};
-    if (nother) {
-        hipLaunchKernelGGL(k_gather_others<Key>, gt, th, 0, s, offsets, long_list,
-                           (const uint32_t*)w.base, nlong, total, ekeys,
-                           (const uint32_t*)w.other, (const uint32_t*)w.opos, w.sk, w.idx, w.seg,
-                           w.pos);
-        HG_TRY(hipGetLastError());
-        size_t tmp = w.sort_bytes;
-        const dim3 go(blocks_for(nother));
-        if constexpr (sizeof(Key) == 4) {
-            HG_TRY(rocprim::radix_sort_pairs(w.sort_tmp, tmp, w.sk, w.sk_s, w.pos, w.pos_s,
-                                             nother, 0u, 32u + bits_for(nlong), s));
-            sv.comp = w.sk_s;
-            sv.spos = w.pos_s;
-        } else {
-            // by key, then stably by list index
-            HG_TRY(rocprim::radix_sort_pairs(w.sort_tmp, tmp, w.sk, w.sk_s, w.idx, w.idx_s,
-                                             nother, 0u, 64u, s));
-            hipLaunchKernelGGL(k_take, go, th, 0, s, (const uint32_t*)w.idx_s,
-                               (const uint32_t*)w.seg, nother, w.seg2, w.ord);
-            HG_TRY(hipGetLastError());
-            const uint32_t sb = bits_for(nlong);
-            tmp = w.sort_bytes;
-            if (sb) {
-                HG_TRY(rocprim::radix_sort_pairs(w.sort_tmp, tmp, w.seg2, w.seg2_s, w.ord,
-                                                 w.ord_s, nother, 0u, sb, s));
-                sv.sseg = w.seg2_s;
-                sv.ord = w.ord_s;
-            } else {
-                sv.sseg = w.seg2;
-                sv.ord = w.ord;
-            }
-            // edge position of each key-sorted entry
-            hipLaunchKernelGGL(k_take, go, th, 0, s, (const uint32_t*)w.idx_s,
-                               (const uint32_t*)w.pos, nother, w.pos_s, (uint32_t*)nullptr);
-            HG_TRY(hipGetLastError());
-            sv.skey = (const Key*)w.sk_s;
-            sv.spos = w.pos_s;
-        }
-        hipLaunchKernelGGL(k_run_flags<Key>, go, th, 0, s, sv, nother, w.flag);
-        HG_TRY(hipGetLastError());
-    }
-    HG_TRY(scan_excl<uint32_t>(w.flag, nother, w.rid, nullptr, w.scan_ws, s));
-    hipLaunchKernelGGL(k_bucket_runs<Key>, gl, th, 0, s, offsets, long_list,
-                       (const uint32_t*)w.base, nlong, (const uint32_t*)w.opos,
-                       (const uint32_t*)w.rid, sv, ekeys, w.br, (Key*)r.run_key, r.run_cnt,
-                       r.run_pos, head);
+    hipLaunchKernelGGL(k_runs_chunk_scan<Key>, dim3(bg), dim3(kRT), 0, s, offsets, ekeys, ix, g2,
+                       (const uint32_t*)ctr);
     HG_TRY(hipGetLastError());
-    if (nother) {
-        const dim3 go(blocks_for(nother));
-        hipLaunchKernelGGL(k_emit_others<Key>, go, th, 0, s, sv, nother, (const uint32_t*)w.flag,
-                           (const uint32_t*)w.rid, (const BucketRuns*)w.br, ids, (Key*)r.run_key,
-                           r.run_pos, w.rstart, w.rslot, r.kperm);
-        HG_TRY(hipGetLastError());
-        hipLaunchKernelGGL(k_other_cnt, go, th, 0, s, (const uint32_t*)w.rstart,
-                           (const uint32_t*)w.rslot, (const uint32_t*)(w.rid + nother), nother,
-                           r.run_cnt);
-        HG_TRY(hipGetLastError());
-    }
-    hipLaunchKernelGGL(k_emit_lead, gt, th, 0, s, (const uint32_t*)w.base, nlong, total,
-                       (const uint32_t*)w.other, (const uint32_t*)w.opos, (const BucketRuns*)w.br,
-                       ids, r.kperm);
+    hipLaunchKernelGGL(k_runs_chunk_scatter<Key>, dim3(cg), dim3(kCT), 0, s, offsets, ids, ekeys,
+                       ix, g2, (const uint32_t*)ctr, rkeys, rids);
+    HG_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_runs_chunk_sort<Key>, dim3(bg), dim3(kRT), lds, s, offsets, ids, ekeys, ix,
+                       g2, (const uint32_t*)ctr, rkeys, rids);
     return hipGetLastError();
 }
 
 template hipError_t run_key_runs<uint32_t>(const uint32_t*, const uint32_t*, const uint32_t*,
-                                           const uint32_t*, uint32_t, uint32_t, uint4*,
-                                           const RunsDev&, void*, hipStream_t);
+                                           uint64_t, const uint32_t*, uint32_t, const IndexOut&,
+                                           uint32_t*, uint32_t*, uint32_t*, void*, hipStream_t);
 template hipError_t run_key_runs<uint64_t>(const uint32_t*, const uint32_t*, const uint64_t*,
-                                           const uint32_t*, uint32_t, uint32_t, uint4*,
-                                           const RunsDev&, void*, hipStream_t);
+                                           uint64_t, const uint32_t*, uint32_t, const IndexOut&,
+                                           uint64_t*, uint32_t*, uint32_t*, void*, hipStream_t);
 
 }  // namespace hg

@@ -283,11 +283,12 @@ size_t partition_smem(uint32_t bits) {
 
 // -------------------------------------------------------- segment setup ---
 
-// Tier-1 segment: the whole input; also clears the oversize-bin counters
-// (oversize bins, split bins, their slices).
+// Tier-1 segment: the whole input; also clears the build's device counters
+// (oversize bins, split bins, their slices, and the general key-run pass's
+// two work counters).
 __global__ void k_segs_single(Segs g, uint32_t n, uint32_t ntiles, uint32_t nchunks,
                               uint32_t* ctr) {
-    if (threadIdx.x < 3) ctr[threadIdx.x] = 0;
+    if (threadIdx.x < 5) ctr[threadIdx.x] = 0;
     if (threadIdx.x == 0) {
         g.seg_start[0] = 0;
         g.seg_start[1] = n;
@@ -502,25 +503,32 @@ __global__ __launch_bounds__(kLocalThreads) void k_huge_place(
     }
 }
 
-// Probe index entries of the split bins' buckets (after their placement).
+// Probe index entries of the split bins' buckets (after their placement);
+// their long buckets are listed for the general pass of the key runs.
 template <typename Key>
 __global__ __launch_bounds__(kLocalThreads) void k_huge_index(
     const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ huge_list,
     const uint32_t* __restrict__ ctr, uint32_t k, uint32_t V,
     const uint32_t* __restrict__ offsets, const Key* __restrict__ ekeys, IndexOut ix) {
-    __shared__ uint32_t tmp[kLocalThreads / kWave + 1];
+    __shared__ uint32_t nlisted;
     const uint32_t NB = 1u << k, nh = ctr[1];
     for (uint32_t idx = blockIdx.x; idx < nh; idx += gridDim.x) {
         const uint32_t b = huge_list[idx];
         const uint32_t v0 = b << k, nb = (V - v0 < NB) ? V - v0 : NB;
-        const uint32_t be = bin_start[b + 1];
-        uint32_t nlong = 0, nlen = 0;
+        const uint32_t bs = bin_start[b], be = bin_start[b + 1];
+        if (threadIdx.x == 0) nlisted = 0;
+        __syncthreads();
         for (uint32_t v = threadIdx.x; v < nb; v += kLocalThreads) {
             const uint32_t lo = offsets[v0 + v];
             const uint32_t hi = (v + 1 < nb) ? offsets[v0 + v + 1] : be;
-            put_index<Key>(ix, v0 + v, lo, hi, ekeys + lo, nlong, nlen);
+            if (hi - lo > kRunBucket)
+                ix.gen_list[gen_region(bs, b) + atomicAdd(&nlisted, 1u)] = v0 + v;
+            else
+                ix.head[v0 + v] = head_entry<Key>(lo, hi, ekeys + lo);
         }
-        put_tally(ix, b, nlong, nlen, tmp);
+        __syncthreads();
+        if (threadIdx.x == 0) ix.gen_cnt[b] = nlisted;
+        __syncthreads();
     }
 }
 
@@ -620,9 +628,11 @@ struct V2Ws {
     void* rkeys;
     uint32_t* rids;
     uint32_t *m1, *c1, *m2, *c2, *bin_start, *heavy_list;
-    uint32_t* ctr;  // [3]: oversize bins, split bins, slices of split bins
+    uint32_t* ctr;  // [5]: oversize bins, split bins, slices of split bins, key-run work
     uint32_t *huge_list, *huge_s0, *slice_owner, *slice_hist;
     uint32_t huge_cap, slice_cap;
+    uint32_t *gen_list, *gen_cnt;  // long buckets left to the general key-run pass
+    void* runs_ws;
     Segs s1, s2;
 };
 
@@ -651,13 +661,16 @@ size_t layout_v2(void* ws, const V2Plan& p, size_t key_size, V2Ws* out) {
     }
     w.bin_start = c.take<uint32_t>((size_t)p.bins + 1);
     w.heavy_list = c.take<uint32_t>((size_t)p.bins);
-    w.ctr = c.take<uint32_t>(3);
+    w.ctr = c.take<uint32_t>(5);
     w.huge_cap = (uint32_t)(p.n / kSliceKeys + 1);
     w.slice_cap = 2 * w.huge_cap;
     w.huge_list = c.take<uint32_t>(w.huge_cap);
     w.huge_s0 = c.take<uint32_t>(w.huge_cap);
     w.slice_owner = c.take<uint32_t>(w.slice_cap);
     w.slice_hist = c.take<uint32_t>((size_t)w.slice_cap << p.k);
+    w.gen_list = c.take<uint32_t>(gen_list_cap(p.n, p.bins));
+    w.gen_cnt = c.take<uint32_t>((size_t)p.bins + 1);
+    w.runs_ws = c.take<char>(runs_ws_bytes(p.n, p.bins));
     if (out) *out = w;
     return c.off + 256;
 }
@@ -780,6 +793,8 @@ hipError_t run_build_v2(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, 
     ix.bins = p.bins;
     V2Ws w;
     layout_v2(ws, p, sizeof(Key), &w);
+    ix.gen_list = w.gen_list;
+    ix.gen_cnt = w.gen_cnt;
     auto hp = KeyTraits<Key>::make(V, seed);
     Key* rkeys = (Key*)w.rkeys;
     {
@@ -825,7 +840,8 @@ hipError_t run_build_v2(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, 
     {
         HG_PROF("v2_local_build", s);
         hipLaunchKernelGGL(k_local_light<Key>, dim3(p.bins), dim3(kLocalThreads),
-                           light_smem<Key>(p.k), s, (const Key*)rkeys, (const uint32_t*)w.rids,
+                           ix.head ? light_smem_index<Key>(p.k) : light_smem<Key>(p.k), s,
+                           (const Key*)rkeys, (const uint32_t*)w.rids,
                            (const uint32_t*)w.bin_start, hp, p.k, offsets, ix, ids, ekeys,
                            !stable);
     }
@@ -867,6 +883,9 @@ hipError_t run_build_v2(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, 
             HG_TRY(hipGetLastError());
         }
     }
+    if (ix.head)
+        HG_TRY(run_key_runs<Key>(offsets, ids, ekeys, n, w.bin_start, p.bins, ix, rkeys, w.rids,
+                                 w.ctr + 3, w.runs_ws, s));
     return hipSuccess;
 }
 

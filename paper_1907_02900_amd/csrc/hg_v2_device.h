@@ -316,27 +316,163 @@ __device__ __forceinline__ uint4 head_entry<uint64_t>(uint32_t start, uint32_t e
     return make_uint4(len, start, (uint32_t)z, (uint32_t)(z >> 32));
 }
 
-// Write bucket b's index entry (the key slots of a bucket longer than
-// kRunBucket are replaced later by its key-run summary) and add it to this
-// thread's tally of long buckets.
+// LDS of the per-bin key runs (after light_smem's layout, 16-byte aligned):
+// the bin's long buckets (their range in the bin and bucket id), two counters
+// and one 64-entry buffer per wave for the keys that differ from a bucket's
+// first key.
 template <typename Key>
-__device__ __forceinline__ void put_index(const IndexOut& ix, uint32_t b, uint32_t start,
-                                          uint32_t end, const Key* k, uint32_t& nlong,
-                                          uint32_t& nlen) {
-    ix.head[b] = head_entry<Key>(start, end, k);
-    if (end - start > kRunBucket) {
-        ++nlong;
-        nlen += end - start;
+struct LongLds {
+    static constexpr uint32_t cap = light_cap<Key>() / (kRunBucket + 1) + 1;
+    uint32_t* cnt;   // [0] long buckets of the bin, [1] of them left to the general pass
+    uint32_t* lohi;  // [cap] lo | hi << 16: the bucket's range in the bin
+    uint32_t* bkt;   // [cap] bucket id
+    Key* wkey;       // [W_LOCAL * 64]
+    uint16_t* wpos;  // [W_LOCAL * 64]
+    __host__ __device__ static constexpr size_t bytes() {
+        return 16 + 8 * cap + (sizeof(Key) + 2) * W_LOCAL * kWave + 32;
+    }
+    __device__ explicit LongLds(unsigned char* p) {
+        cnt = (uint32_t*)p;
+        lohi = cnt + 4;
+        bkt = lohi + cap;
+        wkey = (Key*)(((uintptr_t)(bkt + cap) + 15) & ~(uintptr_t)15);
+        wpos = (uint16_t*)(wkey + W_LOCAL * kWave);
+    }
+};
+
+__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+// LDS bytes of a light bin that also builds its key runs.
+template <typename Key>
+__host__ __device__ inline size_t light_smem_index(uint32_t k) {
+    return align16(light_smem<Key>(k)) + LongLds<Key>::bytes();
+}
+
+// Sort the 64 lanes' (key, position) pairs ascending (bitonic network over
+// lane shuffles; positions are distinct, so the order is total).
+template <typename Key>
+__device__ __forceinline__ void wave_sort_pairs(Key& k, uint32_t& p) {
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (uint32_t size = 2; size <= (uint32_t)kWave; size <<= 1) {
+#pragma unroll
+        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+            const Key ok = __shfl_xor(k, (int)stride, kWave);
+            const uint32_t op = __shfl_xor(p, (int)stride, kWave);
+            const bool up = (lane & size) == 0;
+            const bool lower = (lane & stride) == 0;
+            const bool other_less = ok < k || (ok == k && op < p);
+            if ((lower == up) ? other_less : !other_less) {
+                k = ok;
+                p = op;
+            }
+        }
     }
 }
 
-// The workgroup's long-bucket tally for bin g (all threads call; barriers).
-__device__ __forceinline__ void put_tally(const IndexOut& ix, uint32_t g, uint32_t nlong,
-                                          uint32_t nlen, uint32_t* tmp) {
-    uint32_t tc, tl;
-    block_excl_scan<kLocalThreads>(nlong, tmp, &tc);
-    block_excl_scan<kLocalThreads>(nlen, tmp, &tl);
-    if (threadIdx.x == 0) ix.bin_tally[g] = make_uint2(tc, tl);
+// A bucket's probe index entry, or, for a bucket longer than kRunBucket, its
+// place in the bin's list of long buckets (its entry is written with its key
+// runs).  k points at the bucket's first key in LDS.
+template <typename Key>
+__device__ __forceinline__ void note_bucket(const IndexOut& ix, const LongLds<Key>& lr,
+                                            uint32_t b, uint32_t out, uint32_t lo, uint32_t hi,
+                                            const Key* k) {
+    if (hi - lo > kRunBucket) {
+        const uint32_t t = atomicAdd(&lr.cnt[0], 1u);
+        lr.lohi[t] = lo | (hi << 16);
+        lr.bkt[t] = b;
+    } else {
+        ix.head[b] = head_entry<Key>(out + lo, out + hi, k);
+    }
+}
+
+// Key runs of the long buckets of a bin held in LDS (skeys / sids in bucket
+// order, the bin's first edge at `out`), one wave per bucket.  The entries
+// equal to the bucket's first key (the lead key) form one run; the others,
+// when there are at most 64, are sorted across the wave's lanes and cut into
+// runs, and the lead run is slotted in among them.  A bucket with more other
+// keys is listed for the general pass.  Whole workgroup; barriers.
+template <typename Key>
+__device__ __forceinline__ void bin_long_runs(const IndexOut& ix, const LongLds<Key>& lr,
+                                              const Key* skeys, const uint32_t* sids,
+                                              uint32_t out, uint32_t g) {
+    __syncthreads();
+    const uint32_t nl = lr.cnt[0];
+    const uint32_t w = threadIdx.x / kWave, lane = lane_id();
+    Key* rkey = (Key*)ix.runs.run_key;
+    uint32_t* rend = ix.runs.run_end;
+    uint32_t* kperm = ix.runs.kperm;
+    Key* bk = lr.wkey + w * kWave;
+    uint16_t* bp = lr.wpos + w * kWave;
+    for (uint32_t j = w; j < nl; j += W_LOCAL) {
+        const uint32_t lh = lr.lohi[j], lo = lh & 0xffffu, hi = lh >> 16;
+        const uint32_t b = lr.bkt[j];
+        const uint32_t len = hi - lo, st = out + lo;
+        const Key lead = skeys[lo];
+        uint32_t no = 0;  // entries whose key differs from the lead key
+        for (uint32_t c = lo; c < hi; c += kWave) {
+            const uint32_t p = c + lane;
+            const Key x = p < hi ? skeys[p] : lead;
+            const bool o = x != lead;
+            const uint64_t bal = ballot(o);
+            const uint32_t slot = no + mbcnt(bal);
+            if (o && slot < (uint32_t)kWave) {
+                bk[slot] = x;
+                bp[slot] = (uint16_t)p;
+            }
+            no += (uint32_t)__popcll(bal);
+        }
+        if (no == 0) {  // one key: its ids are the edge array's own
+            if (lane == 0) {
+                rkey[st] = lead;
+                rend[st] = len;
+                ix.head[b] = make_uint4(len, st, 1u, sizeof(Key) == 4 ? (uint32_t)lead : 0u);
+            }
+            continue;
+        }
+        if (no > (uint32_t)kWave) {
+            if (lane == 0) ix.gen_list[gen_region(out, g) + atomicAdd(&lr.cnt[1], 1u)] = b;
+            continue;
+        }
+        // the buffer written above is read by other lanes of the same wave:
+        // LDS executes a wave's operations in order; keep the compiler's too
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const bool valid = lane < no;
+        Key k = valid ? bk[lane] : (Key)~(Key)0;
+        uint32_t p = valid ? (uint32_t)bp[lane] : 0xffffffffu;
+        wave_sort_pairs<Key>(k, p);
+        const Key kprev = __shfl_up(k, 1, kWave);
+        const Key knext = __shfl_down(k, 1, kWave);
+        const bool first = valid && (lane == 0 || kprev != k);
+        const bool last = valid && (lane + 1 == no || knext != k);
+        const bool below = valid && k < lead;
+        const uint64_t fb = ballot(first), lb = ballot(below);
+        const uint32_t nless = (uint32_t)__popcll(lb);       // others below the lead key
+        const uint32_t rl = (uint32_t)__popcll(fb & lb);     // runs below the lead key
+        const uint32_t clead = len - no;
+        const uint32_t r = mbcnt(fb) + (first ? 1u : 0u) - 1u + (below ? 0u : 1u);
+        if (valid) kperm[st + lane + (below ? 0u : clead)] = sids[p];
+        if (first) rkey[st + r] = k;
+        if (last) rend[st + r] = lane + 1 + (below ? 0u : clead);
+        if (lane == 0) {
+            rkey[st + rl] = lead;
+            rend[st + rl] = nless + clead;
+            ix.head[b] = make_uint4(len, st, (uint32_t)__popcll(fb) + 1u, 0u);
+        }
+        // the lead key's ids, in bucket order, after the smaller keys' runs
+        uint32_t done = 0;
+        for (uint32_t c = lo; c < hi; c += kWave) {
+            const uint32_t q = c + lane;
+            const bool isl = q < hi && skeys[q] == lead;
+            const uint64_t bal = ballot(isl);
+            if (isl) kperm[st + nless + done + mbcnt(bal)] = sids[q];
+            done += (uint32_t)__popcll(bal);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) ix.gen_cnt[g] = lr.cnt[1];
 }
 
 // Build one bin of L <= light_cap<Key>() keys whose buckets are [v0, v0 + nb) with
@@ -372,7 +508,8 @@ __device__ __forceinline__ void light_bin_body_by(const Key* __restrict__ src_ke
     uint32_t* wcnt = cnt + NB;                     // W * 64
     uint32_t* dstart = wcnt + W_LOCAL * 64;        // 64
     uint32_t* tmp = dstart + 64;
-    uint32_t nlong = 0, nlen = 0;  // this thread's long buckets (probe index)
+    // the bin's long buckets, when the probe index is written
+    const LongLds<Key> lr(smem + align16(light_smem<Key>(k)));
     const uint32_t w = threadIdx.x / kWave, lane = lane_id();
     // balance the bin over the waves in whole rounds of 64
     const uint32_t wchunk = (((L + W_LOCAL - 1) / W_LOCAL) + kWave - 1) & ~(uint32_t)(kWave - 1);
@@ -394,6 +531,7 @@ __device__ __forceinline__ void light_bin_body_by(const Key* __restrict__ src_ke
         }
     }
     for (uint32_t i = threadIdx.x; i < NB; i += kLocalThreads) cnt[i] = 0;
+    if (ix.head && threadIdx.x < 2) lr.cnt[threadIdx.x] = 0;
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < IT; ++r) {
@@ -438,7 +576,7 @@ __device__ __forceinline__ void light_bin_body_by(const Key* __restrict__ src_ke
         for (uint32_t v = threadIdx.x; v < nb; v += kLocalThreads) {
             const uint32_t lo = v ? cnt[v - 1] : 0u, hi = cnt[v];
             offsets[v0 + v] = out + lo;
-            if (ix.head) put_index<Key>(ix, v0 + v, out + lo, out + hi, skeys + lo, nlong, nlen);
+            if (ix.head) note_bucket<Key>(ix, lr, v0 + v, out, lo, hi, skeys + lo);
         }
     } else {
         sort_chunk_by_bucket<Key, IT>(kk, id, b, rounds, L, wchunk, k, skeys, sids, sb, wcnt,
@@ -447,14 +585,14 @@ __device__ __forceinline__ void light_bin_body_by(const Key* __restrict__ src_ke
         for (uint32_t v = threadIdx.x; v < nb; v += kLocalThreads) {
             const uint32_t lo = cnt[v], hi = (v + 1 < NB) ? cnt[v + 1] : L;
             offsets[v0 + v] = out + lo;
-            if (ix.head) put_index<Key>(ix, v0 + v, out + lo, out + hi, skeys + lo, nlong, nlen);
+            if (ix.head) note_bucket<Key>(ix, lr, v0 + v, out, lo, hi, skeys + lo);
         }
     }
-    if (ix.head) put_tally(ix, v0 >> k, nlong, nlen, tmp);
     for (uint32_t p = threadIdx.x; p < L; p += kLocalThreads) {
         ekeys[out + p] = skeys[p];
         ids[out + p] = sids[p];
     }
+    if (ix.head) bin_long_runs<Key>(ix, lr, skeys, sids, out, v0 >> k);
 }
 
 // The usual bin: buckets [v0, v0 + nb) of the table's hash function.
@@ -597,14 +735,21 @@ __device__ __forceinline__ void heavy_bin_body(const Key* __restrict__ src_keys,
     for (uint32_t i = threadIdx.x; i < nb; i += kLocalThreads) offsets[v0 + i] = cur[i];
     place_in_chunks<Key>(src_keys, src_ids, id_base, L, out, out + L, v0, k, hp, ids, ekeys,
                          smem);
-    // cur[v] is now the end of bucket v; the bin's edges are in ekeys
+    // cur[v] is now the end of bucket v; the bin's edges are in ekeys.  Long
+    // buckets are listed for the general pass, which builds their key runs.
     if (ix.head) {
-        uint32_t nlong = 0, nlen = 0;
+        uint32_t* nlisted = tmp + 2 * W_LOCAL + 2;  // inside heavy_smem's padding
+        if (threadIdx.x == 0) *nlisted = 0;
+        __syncthreads();
         for (uint32_t v = threadIdx.x; v < nb; v += kLocalThreads) {
             const uint32_t lo = v ? cur[v - 1] : out;
-            put_index<Key>(ix, v0 + v, lo, cur[v], ekeys + lo, nlong, nlen);
+            if (cur[v] - lo > kRunBucket)
+                ix.gen_list[gen_region(out, v0 >> k) + atomicAdd(nlisted, 1u)] = v0 + v;
+            else
+                ix.head[v0 + v] = head_entry<Key>(lo, cur[v], ekeys + lo);
         }
-        put_tally(ix, v0 >> k, nlong, nlen, tmp);
+        __syncthreads();
+        if (threadIdx.x == 0) ix.gen_cnt[v0 >> k] = *nlisted;
     }
 }
 

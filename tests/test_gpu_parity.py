@@ -358,25 +358,45 @@ def skew_keys(kind, n, kb, seed):
         return workloads.duplicate_keys(n, 100.0, kb, seed)
     if kind == "few":  # a handful of keys, each in a long bucket
         return (workloads.uniform_keys(n, 32, seed) % 7 + 1000).astype(dt(kb))
+    if kind == "dup30":  # about two keys of 30 copies per bucket (V = n / 60)
+        return workloads.duplicate_keys(n, 30.0, kb, seed)
+    if kind == "dup10":  # about twenty keys of 10 copies per bucket (V = n / 200)
+        return workloads.duplicate_keys(n, 10.0, kb, seed)
     raise ValueError(kind)
 
 
+# Which construction path of the key runs each case takes:
+#   dup100 (V = 2^14): buckets of one repeated key inside LDS bins (one run,
+#     ids read from the edge array);
+#   dup30 (V = n/60): LDS bins whose long buckets hold a few keys (the other
+#     keys sorted across one wave);
+#   dup10 (V = n/200): LDS bins whose long buckets hold more than 64 entries
+#     of other keys (the general pass, sorted in LDS);
+#   few (V = 5000): buckets of one key in bins too large for LDS (chunked path,
+#     one run);
+#   zipf15 (V = n): bins too large for LDS holding a dominant key and a few
+#     others (chunked path, others sorted in LDS);
+#   zipf15 (V = 1): one bucket of every key (chunked path, others radix-sorted
+#     through global memory).
+@pytest.mark.parametrize("any_order", [False, True])
 @pytest.mark.parametrize("kb", [32, 64])
 @pytest.mark.parametrize("kind,n,m,V", [("zipf15", 200000, 300000, 200000),
                                         ("dup100", 150000, 150000, 1 << 14),
+                                        ("dup30", 200000, 150000, 200000 // 60),
+                                        ("dup10", 200000, 150000, 200000 // 200),
                                         ("few", 60000, 50000, 5000),
                                         ("zipf15", 30000, 40000, 1)])
-def test_long_buckets_use_key_runs_with_exact_results(hg, kb, kind, n, m, V):
+def test_long_buckets_use_key_runs_with_exact_results(hg, kb, kind, n, m, V, any_order):
     # buckets longer than 32 entries are probed through their key runs:
     # counts, pairs and intersections must equal the oracle's, and equal the
     # same table probed by scanning (index off)
-    say("key runs", kb, kind, n, m, V)
+    say("key runs", kb, kind, n, m, V, any_order)
     k = skew_keys(kind, n, kb, seed=41)
     q = skew_keys(kind, m, kb, seed=42)
     q[::3] = workloads.uniform_keys(q[::3].size, kb, 43)  # some misses into long buckets
     exp, etot = oracle.probe_counts(k, q, kb)
     dq = hg.to_device(q)
-    t = hg.hg_build(hg.to_device(k), V, seed=17)
+    t = hg.hg_build(hg.to_device(k), V, seed=17, any_order=any_order)
     ts = hg.hg_build(hg.to_device(k), V, seed=17, index=False)
     c, tot = hg.hg_probe(t, dq, counts=True, total=True)
     assert np.array_equal(hg.to_numpy(c, np.uint32), exp) and tot == etot
@@ -388,8 +408,12 @@ def test_long_buckets_use_key_runs_with_exact_results(hg, kb, kind, n, m, V):
     b, p, ptot = hg.hg_probe_pairs(t, hg.to_device(qs))
     eb, ep, et = oracle.probe_pairs(k, qs, kb)
     assert ptot == et
-    assert np.array_equal(hg.to_numpy(p, np.uint32), ep)
-    assert np.array_equal(hg.to_numpy(b, np.uint32), eb)
+    b, p = hg.to_numpy(b, np.uint32)[:et], hg.to_numpy(p, np.uint32)[:et]
+    assert np.array_equal(p, ep)
+    if any_order:  # build ids inside one query follow the bucket's order
+        o = np.lexsort((b, p))
+        b = b[o]
+    assert np.array_equal(b, eb)
     # intersection: A = the table with runs, B = a table of the light queries
     tb = hg.hg_build(hg.to_device(qs), V, seed=17)
     ci, _, _, itot = hg.hg_intersect(t, tb, counts=True, total=True)
