@@ -194,23 +194,30 @@ def run_batched(hg, workloads, torch, tables=4096, reps=5, log=print, any_order=
             "bin_target": info["bin_target"], "plan_create_s": round(create_s, 2)}
 
 
-def run_serving(hg, workloads, torch, requests=600, log=print):
+SERVING_RATES = (2e3, 5e3, 1e4, 1.5e4, 2e4, 3e4, 5e4, 1e6)
+
+
+def run_serving(hg, workloads, torch, requests=2000, rates=SERVING_RATES, log=print):
     """Poisson stream, 30% builds (n log-uniform in [2^10, 2^24]) and 70%
     probes (m log-uniform in [2^10, 2^22]) against resident tables, 64 GB
-    budget; the arrival rate is swept up to saturation.  Keys come from one
-    device pool of uniform keys; a probe takes half its queries from its
-    table's key range (hits) and half from elsewhere."""
+    budget; the arrival rate is swept from well below to beyond saturation,
+    `requests` requests per rate.  Keys come from one device pool of uniform
+    keys; a probe takes half its queries from its table's key range (hits) and
+    half from elsewhere.  The baseline is a sequential loop of the plain
+    entry points over the saturated stream, doing the same work the server
+    does: tables preallocated before the clock (a ring of 64 tables of the
+    largest size, so nothing is allocated or synchronised per request),
+    stable V2 builds with the probe index, counts into preallocated outputs."""
     pool_n = 1 << 26
     pool = hg.to_device(workloads.uniform_keys(pool_n, 32, seed=99))
     qpool = hg.to_device(workloads.uniform_keys(pool_n, 32, seed=98))
-    counts = torch.empty(1 << 22, dtype=torch.int32, device="cuda")
     rng = np.random.default_rng(5)
 
     def build_slice(n):
         o = int(rng.integers(0, pool_n - n))
         return pool[o:o + n], o
 
-    out = {"rates": []}
+    out = {"rates": [], "requests_per_rate": requests}
     srv = hg.Server(budget_bytes=64 << 30, streams=4, max_inflight=16)
     tables = []
     for _ in range(64):  # warm-up: resident tables
@@ -220,87 +227,98 @@ def run_serving(hg, workloads, torch, requests=600, log=print):
         tables.append((tid, o, n))
     srv.drain()
 
-    def one_run(rate, nreq, seed):
-        arr, isb, size, _ = workloads.serving_stream(nreq, rate, seed=seed)
+    def make_plan(nreq, rate, seed):
         # every input is made (and finished) before the clock starts: probe
-        # queries, half from the target table's keys and half from elsewhere,
-        # each probe with its own output slice
-        plan = []
-        mtot = int(sum(int(s) for b_, s in zip(isb, size) if not b_))
-        outc = torch.empty(max(mtot, 1), dtype=torch.int32, device="cuda")
-        mo = 0
+        # queries, half from the target table's keys and half from elsewhere
+        arr, isb, size, _ = workloads.serving_stream(nreq, rate, seed=seed)
+        plan, qs = [], []
         for b_, s in zip(isb, size):
             s = int(s)
             if b_:
                 plan.append(("b",) + build_slice(s) + (s,))
             else:
-                tid, o, n = tables[int(rng.integers(0, 64))]
+                j = int(rng.integers(0, 64))
+                tid, o, n = tables[j]
                 half = min(s // 2, n)
                 q = torch.cat([pool[o:o + half], qpool[:s - half]])
-                plan.append(("p", tid, q, outc[mo:mo + s]))
-                mo += s
+                plan.append(("p", j, q))
+                qs.append(s)
+        outc = torch.empty(max(sum(qs), 1), dtype=torch.int32, device="cuda")
+        return arr, plan, outc
+
+    def one_run(rate, nreq, seed):
+        arr, plan, outc = make_plan(nreq, rate, seed)
         torch.cuda.synchronize()
         srv.reset_stats()
         t0 = time.perf_counter()
+        mo = 0
         for a, item in zip(arr, plan):
             while time.perf_counter() - t0 < a:
                 pass
             if item[0] == "b":
                 _, k, o, s = item
-                tid, _ = srv.submit_build(k, s, seed=s)
-                tables.append((tid, o, s))
+                srv.submit_build(k, s, seed=s)
             else:
-                _, tid, q, c = item
-                srv.submit_probe(tid, q, c)
+                _, j, q = item
+                srv.submit_probe(tables[j][0], q, outc[mo:mo + q.numel()])
+                mo += q.numel()
         srv.drain()
+        wall = time.perf_counter() - t0
         st = srv.stats()
-        return {"rate_per_s": rate, "requests": nreq, "p50_ms": round(st["p50_ms"], 3),
-                "p99_ms": round(st["p99_ms"], 3), "Gkeys": round(st["keys"] / max(st["busy_s"], 1e-9) / 1e9, 2),
+        return {"rate_per_s": rate, "requests": nreq,
+                "achieved_rate_per_s": round(nreq / wall, 1),
+                "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+                "Gkeys": round(st["keys"] / max(st["busy_s"], 1e-9) / 1e9, 2),
                 "merged_requests": st["merged_requests"], "launches": st["launches"],
                 "evictions": st["evictions"], "failed": st["failed"]}
 
-    for rate in (200.0, 1000.0, 4000.0, 1e6):
+    for rate in rates:
         r = one_run(rate, requests, seed=int(rate) % 1000 + 1)
         out["rates"].append(r)
-        log("serving rate %g: p50 %.3f ms p99 %.3f ms %.2f Gkeys/s" % (rate, r["p50_ms"],
-                                                                        r["p99_ms"], r["Gkeys"]))
+        log("serving rate %g: p50 %.3f ms p99 %.3f ms %.2f Gkeys/s (%.0f req/s)" % (
+            rate, r["p50_ms"], r["p99_ms"], r["Gkeys"], r["achieved_rate_per_s"]))
     srv.close()
-    # the same saturated stream as a sequential loop of the plain calls
-    arr, isb, size, _ = workloads.serving_stream(requests, 1e6, seed=1)
-    plan, tabs = [], []
-    for b_, s in zip(isb, size):
-        s = int(s)
-        if b_ or not plan:
-            plan.append(("b",) + build_slice(s) + (s,))
-        else:
-            j = int(rng.integers(0, len([p for p in plan if p[0] == "b"])))
-            plan.append(("p", j, min(s, 1 << 22)))
-    builds = [p for p in plan if p[0] == "b"]
-    queries = {}
-    for i, p in enumerate(plan):
-        if p[0] == "p":
-            _, k, o, n = builds[p[1]]
-            s = p[2]
-            half = min(s // 2, n)
-            queries[i] = torch.cat([pool[o:o + half], qpool[:s - half]])
+    # the knee: the first offered rate the server no longer keeps up with
+    # (achieved below 90% of offered) or whose p99 is over twice the p99 at
+    # the lowest rate
+    base = out["rates"][0]["p99_ms"]
+    knee = None
+    for r in out["rates"]:
+        if r["achieved_rate_per_s"] < 0.9 * r["rate_per_s"] or r["p99_ms"] > 2.0 * base:
+            knee = r["rate_per_s"]
+            break
+    out["knee_rate_per_s"] = knee
+    out["saturation_Gkeys"] = out["rates"][-1]["Gkeys"]
+
+    # the sequential loop over the saturated stream
+    ring = [hg.Table.create(1 << 24, 1 << 24, 32) for _ in range(64)]
+    for i, (tid, o, n) in enumerate(tables[:64]):
+        ring[i].rebuild(pool[o:o + n], n, seed=i)
+    arr, plan, outc = make_plan(requests, rates[-1], seed=int(rates[-1]) % 1000 + 1)
     torch.cuda.synchronize()
+    nxt, keys_done, mo = 0, 0, 0
     t0 = time.perf_counter()
-    keys_done = 0
-    for i, p in enumerate(plan):
-        if p[0] == "b":
-            _, k, o, s = p
-            tabs.append(hg.hg_build(k, s, seed=s))
+    for item in plan:
+        if item[0] == "b":
+            _, k, o, s = item
+            ring[nxt].rebuild(k, s, seed=s)
+            nxt = (nxt + 1) % len(ring)
             keys_done += s
         else:
-            t = tabs[min(p[1], len(tabs) - 1)]
-            q = queries[i]
-            hg.hg_probe(t, q, counts=True, out=counts[:max(q.numel(), 1)])
+            _, j, q = item
+            hg.hg_probe(ring[j], q, counts=True, out=outc[mo:mo + q.numel()])
+            mo += q.numel()
             keys_done += q.numel()
     torch.cuda.synchronize()
     t_loop = time.perf_counter() - t0
-    out["loop_Gkeys"] = round(keys_done / t_loop / 1e9, 2)
-    for t in tabs:
+    for t in ring:
         t.free()
+    out["loop_Gkeys"] = round(keys_done / t_loop / 1e9, 2)
+    out["loop"] = ("sequential hg_table_build (stable, probe index) + hg_probe over %d "
+                   "requests of the saturated stream, 64 preallocated 2^24-key tables"
+                   % requests)
+    out["speedup_at_saturation"] = round(out["saturation_Gkeys"] / max(out["loop_Gkeys"], 1e-9), 2)
+    log("serving loop %.2f Gkeys/s; knee %s req/s" % (out["loop_Gkeys"], knee))
     return out
 
 
@@ -408,7 +426,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--tables", type=int, default=4096)
-    ap.add_argument("--requests", type=int, default=600)
+    ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--stable", action="store_true",
                     help="time the stable (ids ascending in each bucket) V2 layout")
     ap.add_argument("--copy-calibration", action="store_true",

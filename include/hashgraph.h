@@ -32,6 +32,7 @@
 #ifndef HASHGRAPH_H
 #define HASHGRAPH_H
 
+#include <stddef.h>
 #include <stdint.h>
 #include <hip/hip_runtime_api.h>
 
@@ -92,7 +93,15 @@ typedef struct hg_build_opts {
                           per-bucket id ordering; offsets, bucket contents as
                           multisets and probe counts are unchanged.  Rejected
                           with stable=1.  0 = stable layout (default).        */
-    uint32_t reserved[2];
+    int32_t v1_plain;  /* V1: 1 = one device-scope atomic per key in the
+                          histogram and the scatter, as Alg. 1 prints its
+                          loops; 0 (default) = the lanes of a wave whose keys
+                          share a bucket are matched by ballots and merged
+                          into one atomic (the group's leader adds the
+                          group's size and hands out consecutive slots).
+                          Results are identical up to the order inside a
+                          bucket, which V1 leaves unspecified either way.  */
+    uint32_t reserved;
 } hg_build_opts;
 
 typedef struct hg_table hg_table; /* opaque; device-resident */
@@ -115,6 +124,33 @@ const char *hg_status_string(hg_status s);
 /* Version of this ABI (major*10000 + minor*100 + patch). */
 uint32_t hg_version(void);
 
+/* Workspace allocator: lets the caller back the library's temporary device
+ * memory with its own allocator, for example PyTorch's caching allocator.
+ * Every call that needs temporary device
+ * memory -- the build's partition buffers when the table holds no workspace
+ * of its own (hg_build; hg_table_create tables never need any), scan
+ * partials, the positions of pairs, per-chunk totals -- takes its blocks
+ * from alloc_fn(bytes, stream, ctx) and gives each back with
+ * free_fn(ptr, stream, ctx) before the call returns, while work it enqueued
+ * on that stream may still be reading it.  The allocator must therefore
+ * follow stream order: a block freed on a stream is handed out again only to
+ * work ordered after the free on that stream (hipMallocAsync and PyTorch's
+ * caching allocator do this).  alloc_fn returns NULL when it cannot satisfy
+ * the request (the call then fails with HG_ERR_OOM) and must return blocks
+ * aligned to 256 bytes (a misaligned block is freed again and the call fails
+ * with HG_ERR_INVALID_ARG).  Both functions NULL restore the default,
+ * hipMallocAsync / hipFreeAsync; exactly one NULL is HG_ERR_INVALID_ARG.
+ * The setting is process-wide and takes effect for calls that start after
+ * it; a block already handed out is returned to the functions that gave it.
+ * The memory that tables, collections, batch plans and servers keep
+ * (hg_table_create, hg_build, hg_collection_build, hg_batch_create,
+ * hg_server_create) is their own and does not come from the hook, nor does
+ * the per-launch workspace of servers, which counts against their budget.
+ * Needs no device. */
+typedef void *(*hg_alloc_fn)(size_t bytes, hipStream_t stream, void *ctx);
+typedef void (*hg_free_fn)(void *ptr, hipStream_t stream, void *ctx);
+hg_status hg_set_allocator(hg_alloc_fn alloc_fn, hg_free_fn free_fn, void *ctx);
+
 /* ------------------------------------------------------------------------
  * Single steps of the path, exposed so that each can be checked alone.
  * ------------------------------------------------------------------------ */
@@ -129,7 +165,8 @@ hg_status hg_hash(const void *d_keys, uint64_t n, int key_bits, uint64_t hash_ra
 
 /* Alg. 1, loops two and three: d_counts[b] = number of keys whose bucket
  * (as hg_hash) is b, for b in [0, V).  The call zeroes d_counts itself.
- * d_counts: V uint32 (caller-allocated). */
+ * The atomics of lanes whose keys share a bucket are merged inside each wave
+ * (hg_build_opts.v1_plain).  d_counts: V uint32 (caller-allocated). */
 hg_status hg_histogram(const void *d_keys, uint64_t n, int key_bits, uint64_t hash_range,
                        uint64_t seed, uint32_t *d_counts, hipStream_t stream);
 
@@ -173,6 +210,35 @@ typedef struct hg_plan_info {
 
 hg_status hg_build_plan(uint64_t n, uint64_t hash_range, int key_bits, uint32_t bins,
                         hg_plan_info *out);
+
+/* Autotuner of a single build: chooses the launch parameters of
+ * hg_build_opts for these keys by timing candidate builds of them on the
+ * stream (into a temporary table it allocates and frees) and returns the
+ * fastest in *out.  The semantic fields of base (variant, stable, no_index,
+ * any_order; base may be NULL for the defaults) are kept; the tuned fields
+ * are, for V2, bins (bins of about 1024, 2048 or -- 32-bit keys -- 4096 keys
+ * each, which sets the partition width and the per-bin LDS footprint) and,
+ * for V1, block (256, 512 or 1024 threads) and v1_plain (merged or per-key
+ * atomics).  The choice is cached in the process, keyed by (ceil log2 n,
+ * ceil log2 hash_range, key_bits, the semantic fields, skew class), where
+ * the skew class is measured on the first build of these keys (its longest
+ * bucket: at most 32 entries, at most one bin's LDS capacity, or longer); a
+ * later call with the same key times only the default build and the cached
+ * choice, and returns the latter.  info (may be NULL) reports the times.  Waits for the
+ * stream.  Errors as hg_build. */
+typedef struct hg_tune_info {
+    double ms;           /* time of one build with the returned options        */
+    double default_ms;   /* time of one build with the default parameters      */
+    uint32_t candidates; /* configurations timed besides the default (0: cached) */
+    uint32_t skew_class; /* 0: longest bucket <= 32 entries; 1: fits a bin's
+                            LDS (4608 32-bit / 3072 64-bit keys); 2: longer    */
+    uint32_t max_bucket; /* longest bucket of the keys' table                  */
+    uint32_t cached;     /* 1: the choice came from the cache                  */
+} hg_tune_info;
+
+hg_status hg_build_tune(const void *d_keys, uint64_t n, int key_bits, uint64_t hash_range,
+                        uint64_t seed, const hg_build_opts *base, hipStream_t stream,
+                        hg_build_opts *out, hg_tune_info *info);
 
 /* Allocate an empty table able to hold up to n_capacity keys and
  * range_capacity buckets, including the workspace a V2 build of that size
@@ -374,14 +440,29 @@ typedef struct hg_batch_item {
 } hg_batch_item;
 
 typedef struct hg_batch_opts {
-    uint32_t autotune;   /* 1: time candidate bin sizes on this batch and keep
-                            the fastest (default when opts is NULL); 0: use
-                            bin_target or 2048 keys per bin                     */
-    uint32_t bin_target; /* keys per final bin of the partitioned tables; 0 =
-                            autotune / default                                  */
-    uint32_t any_order;  /* 1: order of ids inside a bucket unspecified (as
-                            hg_build_opts.any_order); 0: stable layout          */
-    uint32_t reserved[5];
+    uint32_t autotune;      /* 1 (default when opts is NULL): choose every
+                               launch parameter left at 0 below by timing
+                               candidate graphs on this batch, one dimension
+                               at a time (bin target, then partition keys per
+                               thread, then probe workgroup shape), keeping
+                               the fastest; the choice is cached per batch
+                               shape (tables, total keys, total queries, key
+                               width, layout).  0: parameters left at 0 take
+                               their defaults (2048, 16, 256 x 4).          */
+    uint32_t bin_target;    /* keys per final bin of the partitioned tables
+                               (sets the partition width: the number of
+                               digits a tile scatters to); 0 = tune/default.
+                               Candidates: 1024, 2048 and, for 32-bit keys,
+                               4096.                                         */
+    uint32_t any_order;     /* 1: order of ids inside a bucket unspecified (as
+                               hg_build_opts.any_order); 0: stable layout    */
+    uint32_t part_items;    /* keys per thread of a partition tile (256
+                               threads): 8 or 16; 0 = tune/default (16).     */
+    uint32_t probe_threads; /* probe workgroup shape, threads x queries per  */
+    uint32_t probe_items;   /* thread: 256x4, 256x8, 512x2 or 128x8; both 0 =
+                               tune/default (256x4).  Other values, or one of
+                               the two 0, are HG_ERR_INVALID_ARG.            */
+    uint32_t reserved[2];
 } hg_batch_opts;
 
 typedef struct hg_batch hg_batch; /* opaque plan: device descriptors, workspace
@@ -404,6 +485,11 @@ hg_status hg_batch_run(hg_batch *b, hipStream_t stream);
 
 /* The chosen keys-per-bin target and the workspace the plan holds. */
 hg_status hg_batch_info(const hg_batch *b, uint32_t *bin_target, uint64_t *workspace_bytes);
+
+/* The launch configuration the plan runs with (every tunable field set,
+ * autotune = 0): passing it to hg_batch_create plans the same graph without
+ * tuning. */
+hg_status hg_batch_config(const hg_batch *b, hg_batch_opts *out);
 
 /* Release a plan (waits for the device).  NULL is a no-op. */
 void hg_batch_free(hg_batch *b);

@@ -3,12 +3,26 @@
 // Host-side validation, table objects, workspace handling and dispatch to the
 // kernels.  Nothing here computes on the CPU: every step of the path runs in
 // the HIP kernels of hg_build.hip, hg_scan.hip and hg_probe.hip.
+#include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
+#include <vector>
 
 #include "hashgraph.h"
 #include "hg_internal.h"
 
 using namespace hg;
+
+namespace {
+std::mutex g_hook_mu;
+WsHook g_hook;  // guarded by g_hook_mu
+}  // namespace
+
+WsHook hg::ws_hook() {
+    std::lock_guard<std::mutex> lock(g_hook_mu);
+    return g_hook;
+}
 
 struct hg_table {
     int key_bits = 32;
@@ -59,20 +73,6 @@ bool valid_kb(int kb) { return kb == 32 || kb == 64; }
 bool valid_range(uint64_t V) { return V >= 1 && V <= kU32Max; }
 size_t key_size(int kb) { return kb == 64 ? 8 : 4; }
 
-// Stream-ordered temporary device memory, released in stream order.
-struct Scratch {
-    void* p = nullptr;
-    hipStream_t s;
-    explicit Scratch(hipStream_t st) : s(st) {}
-    hipError_t get(size_t bytes) {
-        if (bytes == 0) bytes = 256;
-        return hipMallocAsync(&p, bytes, s);
-    }
-    ~Scratch() {
-        if (p) (void)hipFreeAsync(p, s);
-    }
-};
-
 hg_status read_u64(const uint64_t* d, uint64_t* h, hipStream_t s) {
     HG_CALL(hipMemcpyAsync(h, d, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     HG_CALL(hipStreamSynchronize(s));
@@ -109,6 +109,7 @@ hg_status build_into(hg_table* t, const void* keys, uint64_t n, uint64_t V, uint
     if (stable && variant == HG_VARIANT_V1) return HG_ERR_INVALID_ARG;
     const uint32_t bins = opts ? opts->bins : 0;
     const uint32_t block = opts ? opts->block : 0;
+    const bool v1_plain = opts && opts->v1_plain;
     const bool want_head = variant == HG_VARIANT_V2 && !(opts && opts->no_index);
     const bool any_order = opts && opts->any_order;
     if (any_order && stable) return HG_ERR_INVALID_ARG;
@@ -116,7 +117,7 @@ hg_status build_into(hg_table* t, const void* keys, uint64_t n, uint64_t V, uint
     if (bins && bins > V) return HG_ERR_INVALID_ARG;
 
     const size_t need = build_ws_bytes(variant, n, V, t->key_bits, bins);
-    Scratch tmp(s);
+    Workspace tmp(s);
     void* ws = t->ws;
     if (!ws || t->ws_bytes < need) {
         HG_CALL(tmp.get(need));
@@ -132,13 +133,13 @@ hg_status build_into(hg_table* t, const void* keys, uint64_t n, uint64_t V, uint
     if (t->key_bits == 32) {
         e = variant == HG_VARIANT_V1
                 ? run_build_v1<uint32_t>((const uint32_t*)keys, n, V, seed, t->offsets, t->ids,
-                                         (uint32_t*)t->keys, ws, block, s)
+                                         (uint32_t*)t->keys, ws, block, v1_plain, s)
                 : run_build_v2<uint32_t>((const uint32_t*)keys, n, V, seed, t->offsets, t->ids,
                                          (uint32_t*)t->keys, ix, ws, bins, !any_order, s);
     } else {
         e = variant == HG_VARIANT_V1
                 ? run_build_v1<uint64_t>((const uint64_t*)keys, n, V, seed, t->offsets, t->ids,
-                                         (uint64_t*)t->keys, ws, block, s)
+                                         (uint64_t*)t->keys, ws, block, v1_plain, s)
                 : run_build_v2<uint64_t>((const uint64_t*)keys, n, V, seed, t->offsets, t->ids,
                                          (uint64_t*)t->keys, ix, ws, bins, !any_order, s);
     }
@@ -202,6 +203,84 @@ TableDev dev_view(const hg_table* t) {
     return d;
 }
 
+hg_status check_pairs_args(const hg_table* t, const void* d_queries, uint64_t m,
+                           const uint32_t* d_build_ids, const uint32_t* d_probe_ids,
+                           uint64_t capacity, const uint64_t* h_total) {
+    if (check_table_arg(t) != HG_OK || m > kU32Max || (m && !d_queries) || !h_total)
+        return HG_ERR_INVALID_ARG;
+    if (capacity && (!d_build_ids || !d_probe_ids)) return HG_ERR_INVALID_ARG;
+    if (t->V == 0) return HG_ERR_INVALID_ARG;
+    if (device_ready() != HG_OK) return HG_ERR_DEVICE;
+    return HG_OK;
+}
+
+// Probe-Standard pairs in two passes over a workspace of probe_ws_bytes(m):
+// per-query counts, their exclusive scan (64-bit positions), the total read
+// back, then each query writes its pairs at its position.  Every byte of the
+// workspace that is read is written first by the same call.
+hg_status probe_pairs_into(const hg_table* t, const void* d_queries, uint64_t m,
+                           uint32_t* d_build_ids, uint32_t* d_probe_ids, uint64_t capacity,
+                           uint64_t* h_total, void* ws, hipStream_t stream) {
+    Carver c(ws);
+    uint32_t* counts = c.take<uint32_t>(m);
+    uint64_t* pos = c.take<uint64_t>(m + 1);
+    void* scan_ws = c.take<char>(scan_ws_bytes(m));
+    TableDev d = dev_view(t);
+    hipError_t e = t->key_bits == 32
+                       ? run_probe_counts<uint32_t>(d, (const uint32_t*)d_queries, m, counts, nullptr, stream)
+                       : run_probe_counts<uint64_t>(d, (const uint64_t*)d_queries, m, counts, nullptr, stream);
+    if (e != hipSuccess) return from_hip(e);
+    HG_CALL(scan_excl<uint64_t>(counts, m, pos, nullptr, scan_ws, stream));
+    hg_status st = read_u64(pos + m, h_total, stream);
+    if (st != HG_OK) return st;
+    if (*h_total > capacity) return HG_ERR_CAPACITY;
+    if (*h_total == 0) return HG_OK;
+    e = t->key_bits == 32
+            ? run_probe_pairs<uint32_t>(d, (const uint32_t*)d_queries, m, pos, d_build_ids, d_probe_ids, stream)
+            : run_probe_pairs<uint64_t>(d, (const uint64_t*)d_queries, m, pos, d_build_ids, d_probe_ids, stream);
+    if (e != hipSuccess) return from_hip(e);
+    HG_CALL(hipStreamSynchronize(stream));
+    return HG_OK;
+}
+
+// ---- single-table autotuner ----------------------------------------------
+
+// skew class of a built table from its longest bucket: 0 = no bucket beyond
+// the probe index's short form (32 entries), 1 = none beyond a bin's LDS
+// capacity, 2 = longer (heavy skew)
+uint32_t skew_class_of(uint32_t max_len, int kb) {
+    if (max_len <= 32) return 0;
+    return max_len <= (kb == 64 ? 3072u : 4608u) ? 1u : 2u;
+}
+
+using TuneKey = std::tuple<uint32_t, uint32_t, int, int, int, int, int, uint32_t>;
+std::mutex g_tune_mu;
+std::map<TuneKey, hg_build_opts> g_tuned;  // guarded by g_tune_mu
+
+// Average time of `reps` builds with options o into t (after one warm-up),
+// timed with events on the stream.
+hg_status time_builds(hg_table* t, const void* keys, uint64_t n, uint64_t V, uint64_t seed,
+                      const hg_build_opts& o, int reps, hipStream_t s, double* ms) {
+    HG_CALL_ST(build_into(t, keys, n, V, seed, &o, s));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    hg_status st = HG_OK;
+    for (int r = 0; r < reps && e == hipSuccess && st == HG_OK; ++r)
+        st = build_into(t, keys, n, V, seed, &o, s);
+    if (e == hipSuccess && st == HG_OK) e = hipEventRecord(e1, s);
+    if (e == hipSuccess && st == HG_OK) e = hipEventSynchronize(e1);
+    float f = 0.f;
+    if (e == hipSuccess && st == HG_OK) e = hipEventElapsedTime(&f, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st != HG_OK) return st;
+    if (e != hipSuccess) return from_hip(e);
+    *ms = (double)f / reps;
+    return HG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -222,6 +301,15 @@ const char* hg_status_string(hg_status s) {
 
 uint32_t hg_version(void) { return 100; }
 
+hg_status hg_set_allocator(hg_alloc_fn alloc_fn, hg_free_fn free_fn, void* ctx) {
+    if (!alloc_fn != !free_fn) return HG_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(g_hook_mu);
+    g_hook.alloc = alloc_fn;
+    g_hook.free = free_fn;
+    g_hook.ctx = alloc_fn ? ctx : nullptr;
+    return HG_OK;
+}
+
 hg_status hg_hash(const void* d_keys, uint64_t n, int key_bits, uint64_t hash_range,
                   uint64_t seed, uint32_t* d_buckets, hipStream_t stream) {
     if (!valid_kb(key_bits) || !valid_range(hash_range) || n > kU32Max) return HG_ERR_INVALID_ARG;
@@ -239,8 +327,8 @@ hg_status hg_histogram(const void* d_keys, uint64_t n, int key_bits, uint64_t ha
     if ((n && !d_keys) || !d_counts) return HG_ERR_INVALID_ARG;
     if (device_ready() != HG_OK) return HG_ERR_DEVICE;
     hipError_t e = key_bits == 32
-                       ? run_histogram<uint32_t>((const uint32_t*)d_keys, n, hash_range, seed, d_counts, 0, stream)
-                       : run_histogram<uint64_t>((const uint64_t*)d_keys, n, hash_range, seed, d_counts, 0, stream);
+                       ? run_histogram<uint32_t>((const uint32_t*)d_keys, n, hash_range, seed, d_counts, 0, false, stream)
+                       : run_histogram<uint64_t>((const uint64_t*)d_keys, n, hash_range, seed, d_counts, 0, false, stream);
     return from_hip(e);
 }
 
@@ -249,7 +337,7 @@ hg_status hg_exclusive_scan(const uint32_t* d_counts, uint64_t V, uint32_t* d_of
     if (V > kU32Max || !d_offsets || (V && !d_counts)) return HG_ERR_INVALID_ARG;
     if (V && d_counts == d_offsets) return HG_ERR_INVALID_ARG;
     if (device_ready() != HG_OK) return HG_ERR_DEVICE;
-    Scratch ws(stream);
+    Workspace ws(stream);
     HG_CALL(ws.get(scan_ws_bytes(V)));
     return from_hip(scan_excl<uint32_t>(d_counts, V, d_offsets, nullptr, ws.p, stream));
 }
@@ -270,6 +358,109 @@ hg_status hg_build_plan(uint64_t n, uint64_t hash_range, int key_bits, uint32_t 
     out->tiles[1] = p.tiers == 2 ? p.ntiles2_ub : 0u;
     out->tile_keys = kPartTile;
     out->workspace_bytes = build_ws_bytes(HG_VARIANT_V2, n, hash_range, key_bits, bins);
+    return HG_OK;
+}
+
+hg_status hg_build_tune(const void* d_keys, uint64_t n, int key_bits, uint64_t hash_range,
+                        uint64_t seed, const hg_build_opts* base, hipStream_t stream,
+                        hg_build_opts* out, hg_tune_info* info) {
+    if (!out || !valid_kb(key_bits) || !valid_range(hash_range) || n > kU32Max || (n && !d_keys))
+        return HG_ERR_INVALID_ARG;
+    hg_build_opts o = base ? *base : hg_build_opts{};
+    if (o.variant == HG_VARIANT_AUTO) o.variant = HG_VARIANT_V2;
+    if ((o.variant != HG_VARIANT_V1 && o.variant != HG_VARIANT_V2) ||
+        (o.stable && (o.variant == HG_VARIANT_V1 || o.any_order)) ||
+        (o.bins && o.bins > hash_range) || (o.block && (o.block % 64 || o.block > 1024)))
+        return HG_ERR_INVALID_ARG;
+    if (device_ready() != HG_OK) return HG_ERR_DEVICE;
+    const bool v1 = o.variant == HG_VARIANT_V1;
+    // the launch parameters are the tuner's to choose
+    o.bins = 0;
+    o.block = 0;
+    o.v1_plain = 0;
+    hg_table* t = nullptr;
+    HG_CALL_ST(alloc_table(n, hash_range, key_bits, true, &t));
+    struct Guard {
+        hg_table* t;
+        ~Guard() { hg_table_free(t); }
+    } guard{t};
+    double def_ms = 0.0;
+    HG_CALL_ST(time_builds(t, d_keys, n, hash_range, seed, o, 2, stream, &def_ms));
+    // skew class of these keys, from the table just built
+    Workspace ws(stream);
+    HG_CALL(ws.get(256));
+    HG_CALL(max_bucket_len(t->offsets, hash_range, (uint32_t*)ws.p, stream));
+    uint32_t max_len = 0;
+    HG_CALL(hipMemcpyAsync(&max_len, ws.p, 4, hipMemcpyDeviceToHost, stream));
+    HG_CALL(hipStreamSynchronize(stream));
+    const uint32_t skew = skew_class_of(max_len, key_bits);
+    const TuneKey key{log2_ceil(n ? n : 1), log2_ceil(hash_range), key_bits, o.variant,
+                      o.any_order ? 1 : 0, o.stable ? 1 : 0, o.no_index ? 1 : 0, skew};
+    hg_tune_info ti{};
+    ti.default_ms = def_ms;
+    ti.skew_class = skew;
+    ti.max_bucket = max_len;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        auto it = g_tuned.find(key);
+        if (it != g_tuned.end()) {
+            *out = it->second;
+            ti.cached = 1;
+        }
+    }
+    if (ti.cached) {
+        HG_CALL_ST(time_builds(t, d_keys, n, hash_range, seed, *out, 2, stream, &ti.ms));
+        if (info) *info = ti;
+        return HG_OK;
+    }
+    // candidates: V1 -- threads per block and merged / per-key atomics;
+    // V2 -- the bin size (keys per final bin 1024, 2048, 4096 for 32-bit
+    // keys), which sets the partition width and the per-bin LDS footprint
+    std::vector<hg_build_opts> cands;
+    if (v1) {
+        for (uint32_t blk : {256u, 512u, 1024u})
+            for (int plain : {0, 1}) {
+                hg_build_opts c = o;
+                c.block = blk;
+                c.v1_plain = plain;
+                cands.push_back(c);
+            }
+    } else {
+        std::vector<uint32_t> seen_k;
+        const uint32_t kv = log2_ceil(hash_range);
+        for (double target : {1024.0, 2048.0, 4096.0}) {
+            if (key_bits == 64 && target > 2048.0) continue;
+            const double r = n ? target * (double)hash_range / (double)n : 1e30;
+            uint32_t k = 0;
+            while (k < kMaxLocalBits && (double)(1ull << (k + 1)) <= r) ++k;
+            if (k > kv) k = kv;
+            bool dup = false;
+            for (uint32_t x : seen_k) dup |= x == k;
+            if (dup) continue;
+            seen_k.push_back(k);
+            hg_build_opts c = o;
+            c.bins = (uint32_t)ceil_div(hash_range, 1ull << k);
+            cands.push_back(c);
+        }
+    }
+    hg_build_opts best = o;
+    double best_ms = def_ms;
+    for (const hg_build_opts& c : cands) {
+        double ms = 0.0;
+        HG_CALL_ST(time_builds(t, d_keys, n, hash_range, seed, c, 2, stream, &ms));
+        ++ti.candidates;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_tuned[key] = best;
+    }
+    *out = best;
+    ti.ms = best_ms;
+    if (info) *info = ti;
     return HG_OK;
 }
 
@@ -329,7 +520,7 @@ hg_status hg_table_export(const hg_table* t, uint32_t* d_offsets, uint32_t* d_id
     if (!t || t->V == 0) return HG_ERR_INVALID_ARG;
     if (t->has_len) {
         // compacted CSR of the live entries
-        Scratch ws(stream);
+        Workspace ws(stream);
         HG_CALL(ws.get(align_up((t->V + 1) * 4, 256) + scan_ws_bytes(t->V)));
         Carver c(ws.p);
         uint32_t* own = c.take<uint32_t>(t->V + 1);
@@ -369,7 +560,7 @@ hg_status hg_table_erase(hg_table* t, const void* d_keys, uint64_t m, uint64_t* 
         HG_CALL(init_lengths(t->offsets, t->V, t->len, stream));
         t->has_len = true;
     }
-    Scratch ws(stream);
+    Workspace ws(stream);
     HG_CALL(ws.get(256));
     unsigned long long* d_removed = (unsigned long long*)ws.p;
     HG_CALL(fill_u32((uint32_t*)d_removed, 2, 0u, stream));
@@ -425,7 +616,7 @@ hg_status coll_build_into(hg_collection* c, const void* d_keys, const uint32_t* 
     HG_CALL(hipMalloc((void**)&c->bb, ((uint64_t)S + 2) * 8));
     HG_CALL(hipMemcpyAsync(c->set_off, d_set_offsets, ((uint64_t)S + 1) * 4,
                            hipMemcpyDeviceToDevice, stream));
-    Scratch pws(stream);
+    Workspace pws(stream);
     HG_CALL(pws.get(coll_plan_ws_bytes(S)));
     CollPlan plan{};
     HG_CALL(coll_plan(c->set_off, S, c->shift, pws.p, c->bb, &plan, stream));
@@ -439,7 +630,7 @@ hg_status coll_build_into(hg_collection* c, const void* d_keys, const uint32_t* 
     HG_CALL(hipMalloc(&c->keys, (plan.n ? plan.n : 1) * ks));
     c->bytes = ((uint64_t)S + 1) * 4 + ((uint64_t)S + 2) * 8 + (plan.buckets + 1) * 4 +
                plan.n * (4 + ks);
-    Scratch bws(stream);
+    Workspace bws(stream);
     HG_CALL(bws.get(coll_build_ws_bytes(plan, c->key_bits)));
     bool bad = false;
     HG_CALL(c->key_bits == 32
@@ -524,7 +715,7 @@ hg_status hg_collection_intersect(const hg_collection* a, const hg_collection* b
     if (a->key_bits != b->key_bits || a->seed != b->seed) return HG_ERR_MISMATCH;
     if (device_ready() != HG_OK) return HG_ERR_DEVICE;
     if (h_total) *h_total = 0;
-    Scratch ws(stream);
+    Workspace ws(stream);
     HG_CALL(ws.get(coll_pairs_ws_bytes(pairs)));
     bool bad = false;
     HG_CALL(a->key_bits == 32
@@ -565,7 +756,7 @@ hg_status hg_probe(const hg_table* t, const void* d_queries, uint64_t m, uint32_
     if (!d_counts && !h_total) return HG_ERR_INVALID_ARG;
     if (t->V == 0) return HG_ERR_INVALID_ARG;  // never built
     if (device_ready() != HG_OK) return HG_ERR_DEVICE;
-    Scratch ws(stream);
+    Workspace ws(stream);
     unsigned long long* d_total = nullptr;
     if (h_total) {
         HG_CALL(ws.get(probe_total_slots(m) * 8));
@@ -583,37 +774,15 @@ hg_status hg_probe(const hg_table* t, const void* d_queries, uint64_t m, uint32_
 hg_status hg_probe_pairs(const hg_table* t, const void* d_queries, uint64_t m,
                          uint32_t* d_build_ids, uint32_t* d_probe_ids, uint64_t capacity,
                          uint64_t* h_total, hipStream_t stream) {
-    if (check_table_arg(t) != HG_OK || m > kU32Max || (m && !d_queries) || !h_total)
-        return HG_ERR_INVALID_ARG;
-    if (capacity && (!d_build_ids || !d_probe_ids)) return HG_ERR_INVALID_ARG;
-    if (t->V == 0) return HG_ERR_INVALID_ARG;
-    if (device_ready() != HG_OK) return HG_ERR_DEVICE;
+    HG_CALL_ST(check_pairs_args(t, d_queries, m, d_build_ids, d_probe_ids, capacity, h_total));
     if (m == 0) {
         *h_total = 0;
         return HG_OK;
     }
-    Scratch ws(stream);
+    Workspace ws(stream);
     HG_CALL(ws.get(probe_ws_bytes(m)));
-    Carver c(ws.p);
-    uint32_t* counts = c.take<uint32_t>(m);
-    uint64_t* pos = c.take<uint64_t>(m + 1);
-    void* scan_ws = c.take<char>(scan_ws_bytes(m));
-    TableDev d = dev_view(t);
-    hipError_t e = t->key_bits == 32
-                       ? run_probe_counts<uint32_t>(d, (const uint32_t*)d_queries, m, counts, nullptr, stream)
-                       : run_probe_counts<uint64_t>(d, (const uint64_t*)d_queries, m, counts, nullptr, stream);
-    if (e != hipSuccess) return from_hip(e);
-    HG_CALL(scan_excl<uint64_t>(counts, m, pos, nullptr, scan_ws, stream));
-    hg_status st = read_u64(pos + m, h_total, stream);
-    if (st != HG_OK) return st;
-    if (*h_total > capacity) return HG_ERR_CAPACITY;
-    if (*h_total == 0) return HG_OK;
-    e = t->key_bits == 32
-            ? run_probe_pairs<uint32_t>(d, (const uint32_t*)d_queries, m, pos, d_build_ids, d_probe_ids, stream)
-            : run_probe_pairs<uint64_t>(d, (const uint64_t*)d_queries, m, pos, d_build_ids, d_probe_ids, stream);
-    if (e != hipSuccess) return from_hip(e);
-    HG_CALL(hipStreamSynchronize(stream));
-    return HG_OK;
+    return probe_pairs_into(t, d_queries, m, d_build_ids, d_probe_ids, capacity, h_total, ws.p,
+                            stream);
 }
 
 hg_status hg_intersect_edges(const hg_table* a, const hg_table* b, uint32_t* d_counts_edges,
@@ -626,7 +795,7 @@ hg_status hg_intersect_edges(const hg_table* a, const hg_table* b, uint32_t* d_c
         if (h_total) *h_total = 0;
         return HG_OK;
     }
-    Scratch ws(stream);
+    Workspace ws(stream);
     unsigned long long* d_total = nullptr;
     if (h_total) {
         HG_CALL(ws.get(probe_total_slots(b->n) * 8));
@@ -656,7 +825,7 @@ hg_status hg_intersect(const hg_table* a, const hg_table* b, uint32_t* d_counts_
     }
     TableDev da = dev_view(a), db = dev_view(b);
     const bool pairs = capacity > 0;
-    Scratch ws(stream);
+    Workspace ws(stream);
     HG_CALL(ws.get(probe_ws_bytes(nb) + probe_total_slots(nb) * 8 + 256));
     Carver c(ws.p);
     uint32_t* edge = c.take<uint32_t>(nb);

@@ -32,9 +32,14 @@ namespace {
 
 using namespace v2dev;
 
-constexpr int kBProbeThreads = 256;
-constexpr int kBProbeItems = 4;
-constexpr uint32_t kBProbeTile = kBProbeThreads * kBProbeItems;
+// Launch shapes the tuner chooses between (defaults first): keys per thread
+// of the partition tiles (256 threads each), and threads x queries per thread
+// of the probe workgroups.
+constexpr uint32_t kPartItemsChoices[] = {16u, 8u};
+struct ProbeShape {
+    uint32_t threads, items;
+};
+constexpr ProbeShape kProbeShapes[] = {{256u, 4u}, {256u, 8u}, {512u, 2u}, {128u, 8u}};
 
 enum : uint32_t { kDirect = 0, kPartitioned = 1, kEmpty = 2 };
 
@@ -84,10 +89,11 @@ __global__ void k_bclear(uint32_t* heavy_count) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *heavy_count = 0;
 }
 
-template <typename Key>
+template <typename Key, int IT>
 __global__ __launch_bounds__(kPartThreads) void k_bhist(const BTable<Key>* __restrict__ tabs,
                                                         BPrefix pre, uint32_t tiles,
                                                         uint32_t* __restrict__ mat) {
+    constexpr uint32_t TILE = kPartThreads * IT;
     extern __shared__ uint32_t cnt[];
     const uint32_t t = xcd_map(blockIdx.x, tiles);
     if (t >= tiles) return;
@@ -95,10 +101,9 @@ __global__ __launch_bounds__(kPartThreads) void k_bhist(const BTable<Key>* __res
     const BTable<Key>& tb = tabs[i];
     const uint32_t lt = t - pre.tile[i];
     const uint32_t D = 1u << tb.b1;
-    const uint32_t begin = lt * kPartTile;
-    const uint32_t end = (tb.n - begin > kPartTile) ? begin + kPartTile : tb.n;
+    const uint32_t begin = lt * TILE;
+    const uint32_t end = (tb.n - begin > TILE) ? begin + TILE : tb.n;
     for (uint32_t d = threadIdx.x; d < D; d += kPartThreads) cnt[d] = 0;
-    constexpr int IT = kPartItems;
     Key k[IT];
 #pragma unroll
     for (int r = 0; r < IT; ++r) {
@@ -156,13 +161,13 @@ __global__ __launch_bounds__(256) void k_bcolscan(const BTable<Key>* __restrict_
 
 // STABLE: equal digits keep their order; otherwise their order is
 // unspecified (ranked with LDS atomics, no ballots).
-template <typename Key, bool STABLE>
+template <typename Key, bool STABLE, int IT>
 __global__ __launch_bounds__(kPartThreads) void k_bpart(const BTable<Key>* __restrict__ tabs,
                                                         BPrefix pre, uint32_t tiles,
                                                         const uint32_t* __restrict__ mat,
                                                         Key* __restrict__ rkeys,
                                                         uint32_t* __restrict__ rids) {
-    constexpr int IT = kPartItems;
+    constexpr uint32_t TILE = kPartThreads * IT;
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t t = xcd_map(blockIdx.x, tiles);
     if (t >= tiles) return;
@@ -171,14 +176,14 @@ __global__ __launch_bounds__(kPartThreads) void k_bpart(const BTable<Key>* __res
     const uint32_t lt = t - pre.tile[i];
     const uint32_t bits = tb.b1, D = 1u << bits;
     Key* skeys = (Key*)smem;
-    uint32_t* sids = (uint32_t*)(skeys + kPartTile);
-    uint16_t* sdig = (uint16_t*)(sids + kPartTile);
-    uint32_t* wcnt = (uint32_t*)(sdig + kPartTile);
+    uint32_t* sids = (uint32_t*)(skeys + TILE);
+    uint16_t* sdig = (uint16_t*)(sids + TILE);
+    uint32_t* wcnt = (uint32_t*)(sdig + TILE);
     uint32_t* dstart = wcnt + W_PART * D;
     uint32_t* tbase = dstart + D;
     uint32_t* tmp = tbase + D;
-    const uint32_t begin = lt * kPartTile;
-    const uint32_t cnt = (tb.n - begin > kPartTile) ? kPartTile : tb.n - begin;
+    const uint32_t begin = lt * TILE;
+    const uint32_t cnt = (tb.n - begin > TILE) ? TILE : tb.n - begin;
     const uint32_t w = threadIdx.x / kWave, lane = lane_id();
     const uint32_t wbase = w * (kWave * IT);
     Key k[IT];
@@ -288,24 +293,24 @@ __global__ __launch_bounds__(kLocalThreads) void k_bheavy(
     }
 }
 
-template <typename Key>
-__global__ __launch_bounds__(kBProbeThreads) void k_bprobe(const BTable<Key>* __restrict__ tabs,
-                                                           BPrefix pre, uint32_t qtiles) {
+template <typename Key, int THREADS, int ITEMS>
+__global__ __launch_bounds__(THREADS) void k_bprobe(const BTable<Key>* __restrict__ tabs,
+                                                    BPrefix pre, uint32_t qtiles) {
     const uint32_t qt = blockIdx.x;
     if (qt >= qtiles) return;
     const uint32_t i = find_table(pre.qtile, pre.T, qt);
     const BTable<Key>& tb = tabs[i];
-    const uint32_t base = (qt - pre.qtile[i]) * kBProbeTile + threadIdx.x;
-    Key q[kBProbeItems];
-    uint32_t lo[kBProbeItems], hi[kBProbeItems];
+    const uint32_t base = (qt - pre.qtile[i]) * (THREADS * ITEMS) + threadIdx.x;
+    Key q[ITEMS];
+    uint32_t lo[ITEMS], hi[ITEMS];
 #pragma unroll
-    for (int r = 0; r < kBProbeItems; ++r) {
-        const uint32_t j = base + r * kBProbeThreads;
+    for (int r = 0; r < ITEMS; ++r) {
+        const uint32_t j = base + r * THREADS;
         q[r] = (j < tb.m) ? tb.queries[j] : (Key)0;
     }
 #pragma unroll
-    for (int r = 0; r < kBProbeItems; ++r) {
-        const uint32_t j = base + r * kBProbeThreads;
+    for (int r = 0; r < ITEMS; ++r) {
+        const uint32_t j = base + r * THREADS;
         if (j < tb.m) {
             const uint32_t h = KeyTraits<Key>::bucket(q[r], tb.hp);
             lo[r] = tb.offsets[h];
@@ -315,17 +320,17 @@ __global__ __launch_bounds__(kBProbeThreads) void k_bprobe(const BTable<Key>* __
         }
     }
 #pragma unroll
-    for (int r = 0; r < kBProbeItems; ++r) {
-        const uint32_t j = base + r * kBProbeThreads;
+    for (int r = 0; r < ITEMS; ++r) {
+        const uint32_t j = base + r * THREADS;
         uint32_t c = 0;
         for (uint32_t p = lo[r]; p < hi[r]; ++p) c += (tb.ekeys[p] == q[r]) ? 1u : 0u;
         if (j < tb.m) tb.counts[j] = c;
     }
 }
 
-size_t part_smem_bytes(size_t key_size, uint32_t bits) {
+size_t part_smem_bytes(size_t key_size, uint32_t bits, uint32_t tile) {
     const size_t D = 1u << bits;
-    return kPartTile * (key_size + 4 + 2) + W_PART * D * 4 + 2 * D * 4 + (W_PART + 1) * 4 + 64;
+    return tile * (key_size + 4 + 2) + W_PART * D * 4 + 2 * D * 4 + (W_PART + 1) * 4 + 64;
 }
 
 uint32_t pick_k(uint64_t n, uint64_t V, uint32_t target) {
@@ -354,6 +359,10 @@ struct BatchPlan : BatchPlanBase {
     uint64_t mat_entries = 0, ws_keys = 0;
     bool build = true;  // false: probe existing tables only
     bool any_order = false;  // order inside a bucket unspecified
+    uint32_t part_items = kPartItemsChoices[0];  // keys per partition thread
+    ProbeShape probe = kProbeShapes[0];          // probe workgroup shape
+    uint32_t part_tile() const { return kPartThreads * part_items; }
+    uint32_t probe_tile() const { return probe.threads * probe.items; }
     std::vector<BTable<Key>> host;
     std::vector<uint32_t> tile_pre, bin_pre, qtile_pre;
     // device memory (one block, owned or lent by the caller)
@@ -419,7 +428,7 @@ struct BatchPlan : BatchPlanBase {
         uint64_t qt = 0;
         for (uint32_t i = 0; i < T; ++i) {
             qtile_pre[i] = (uint32_t)qt;
-            qt += ceil_div(host[i].m, kBProbeTile);
+            qt += ceil_div(host[i].m, probe_tile());
         }
         qtile_pre[T] = (uint32_t)qt;
         tiles = bins = 0;
@@ -470,7 +479,7 @@ struct BatchPlan : BatchPlanBase {
             } else {
                 tb.kind = kPartitioned;
                 tb.b1 = bits;
-                tb.ntiles = (uint32_t)ceil_div(it.n, kPartTile);
+                tb.ntiles = (uint32_t)ceil_div(it.n, part_tile());
                 tb.mat_base = (uint32_t)mat64;
                 tb.key_base = (uint32_t)keys64;
                 mat64 += (uint64_t)tb.ntiles << bits;
@@ -483,7 +492,7 @@ struct BatchPlan : BatchPlanBase {
             qtile_pre[i] = (uint32_t)qt64;
             tiles64 += tb.ntiles;
             bins64 += bins;
-            qt64 += ceil_div(it.m, kBProbeTile);
+            qt64 += ceil_div(it.m, probe_tile());
         }
         tile_pre[count] = (uint32_t)tiles64;
         bin_pre[count] = (uint32_t)bins64;
@@ -521,24 +530,7 @@ struct BatchPlan : BatchPlanBase {
             HG_TRY(hipGetLastError());
         }
         if (tiles) {
-            const uint32_t grid = (uint32_t)(8 * ceil_div(tiles, 8));
-            hipLaunchKernelGGL(k_bhist<Key>, dim3(grid), dim3(kPartThreads), (4u << max_b1), s,
-                               (const BTable<Key>*)d_tabs, pre, tiles, d_mat);
-            HG_TRY(hipGetLastError());
-            hipLaunchKernelGGL(k_bcolscan<Key>, dim3(T), dim3(256), 0, s,
-                               (const BTable<Key>*)d_tabs, d_mat);
-            HG_TRY(hipGetLastError());
-            if (any_order)
-                hipLaunchKernelGGL((k_bpart<Key, false>), dim3(grid), dim3(kPartThreads),
-                                   part_smem_bytes(sizeof(Key), max_b1), s,
-                                   (const BTable<Key>*)d_tabs, pre, tiles, (const uint32_t*)d_mat,
-                                   d_rkeys, d_rids);
-            else
-                hipLaunchKernelGGL((k_bpart<Key, true>), dim3(grid), dim3(kPartThreads),
-                                   part_smem_bytes(sizeof(Key), max_b1), s,
-                                   (const BTable<Key>*)d_tabs, pre, tiles, (const uint32_t*)d_mat,
-                                   d_rkeys, d_rids);
-            HG_TRY(hipGetLastError());
+            HG_TRY(part_items == 8 ? enqueue_partition<8>(pre, s) : enqueue_partition<16>(pre, s));
         }
         if (bins) {
             hipLaunchKernelGGL(k_blocal<Key>, dim3(bins), dim3(kLocalThreads),
@@ -554,12 +546,45 @@ struct BatchPlan : BatchPlanBase {
                                (const uint32_t*)heavy_count);
             HG_TRY(hipGetLastError());
         }
-        if (qtiles) {
-            hipLaunchKernelGGL(k_bprobe<Key>, dim3(qtiles), dim3(kBProbeThreads), 0, s,
-                               (const BTable<Key>*)d_tabs, pre, qtiles);
-            HG_TRY(hipGetLastError());
-        }
+        if (qtiles) HG_TRY(enqueue_probe(pre, s));
         return hipSuccess;
+    }
+
+    template <int IT>
+    hipError_t enqueue_partition(const BPrefix& pre, hipStream_t s) {
+        const uint32_t grid = (uint32_t)(8 * ceil_div(tiles, 8));
+        hipLaunchKernelGGL((k_bhist<Key, IT>), dim3(grid), dim3(kPartThreads), (4u << max_b1), s,
+                           (const BTable<Key>*)d_tabs, pre, tiles, d_mat);
+        HG_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_bcolscan<Key>, dim3(T), dim3(256), 0, s, (const BTable<Key>*)d_tabs,
+                           d_mat);
+        HG_TRY(hipGetLastError());
+        const size_t smem = part_smem_bytes(sizeof(Key), max_b1, kPartThreads * IT);
+        if (any_order)
+            hipLaunchKernelGGL((k_bpart<Key, false, IT>), dim3(grid), dim3(kPartThreads), smem, s,
+                               (const BTable<Key>*)d_tabs, pre, tiles, (const uint32_t*)d_mat,
+                               d_rkeys, d_rids);
+        else
+            hipLaunchKernelGGL((k_bpart<Key, true, IT>), dim3(grid), dim3(kPartThreads), smem, s,
+                               (const BTable<Key>*)d_tabs, pre, tiles, (const uint32_t*)d_mat,
+                               d_rkeys, d_rids);
+        return hipGetLastError();
+    }
+
+    hipError_t enqueue_probe(const BPrefix& pre, hipStream_t s) {
+        const BTable<Key>* tabs = d_tabs;
+#define HG_BPROBE(TH, IT)                                                                  \
+    if (probe.threads == TH && probe.items == IT) {                                        \
+        hipLaunchKernelGGL((k_bprobe<Key, TH, IT>), dim3(qtiles), dim3(TH), 0, s, tabs, pre, \
+                           qtiles);                                                        \
+        return hipGetLastError();                                                          \
+    }
+        HG_BPROBE(256, 4)
+        HG_BPROBE(256, 8)
+        HG_BPROBE(512, 2)
+        HG_BPROBE(128, 8)
+#undef HG_BPROBE
+        return hipErrorInvalidValue;
     }
 
     hipError_t capture() {
@@ -588,9 +613,17 @@ static hipError_t set_batch_smem() {
     static std::atomic<uint64_t> done{0};
     return once_per_device(done, [] {
         const int lim = 160 * 1024;
-        HG_TRY(hipFuncSetAttribute((const void*)k_bpart<Key, true>,
+        HG_TRY(hipFuncSetAttribute((const void*)k_bpart<Key, true, 16>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, lim));
-        HG_TRY(hipFuncSetAttribute((const void*)k_bpart<Key, false>,
+        HG_TRY(hipFuncSetAttribute((const void*)k_bpart<Key, false, 16>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+        HG_TRY(hipFuncSetAttribute((const void*)k_bpart<Key, true, 8>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+        HG_TRY(hipFuncSetAttribute((const void*)k_bpart<Key, false, 8>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+        HG_TRY(hipFuncSetAttribute((const void*)k_bhist<Key, 16>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+        HG_TRY(hipFuncSetAttribute((const void*)k_bhist<Key, 8>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, lim));
         HG_TRY(hipFuncSetAttribute((const void*)k_blocal<Key>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, lim));
@@ -600,9 +633,17 @@ static hipError_t set_batch_smem() {
     });
 }
 
-// Autotuning cache: (tables, total keys, total queries, key bits) -> target.
+// A batch plan's tunable launch configuration.
+struct BConfig {
+    uint32_t target;      // keys per final bin (sets the partition width)
+    uint32_t part_items;  // keys per thread of a partition tile
+    ProbeShape probe;     // probe workgroup: threads x queries per thread
+};
+
+// Autotuning cache: (tables, total keys, total queries, key bits, any order)
+// -> the configuration the tuner chose.
 static std::mutex g_tune_mu;
-static std::map<std::tuple<uint32_t, uint64_t, uint64_t, int, bool>, uint32_t> g_tune;
+static std::map<std::tuple<uint32_t, uint64_t, uint64_t, int, bool>, BConfig> g_tune;
 
 }  // namespace hg
 
@@ -612,6 +653,8 @@ struct hg_batch {
     int key_bits = 32;
     BatchPlanBase* plan = nullptr;
     uint32_t target = 0;
+    uint32_t part_items = 0;
+    uint32_t probe_threads = 0, probe_items = 0;
 };
 
 namespace {
@@ -622,6 +665,57 @@ hg_status hstat(hipError_t e) {
     return HG_ERR_DEVICE;
 }
 
+// Lay out, upload and capture one candidate plan.
+template <typename Key>
+hg_status make_plan(const hg_batch_item* items, uint32_t count, bool any_order, const BConfig& c,
+                    BatchPlan<Key>** out) {
+    BatchPlan<Key>* p = new (std::nothrow) BatchPlan<Key>();
+    if (!p) return HG_ERR_OOM;
+    p->any_order = any_order;
+    p->part_items = c.part_items;
+    p->probe = c.probe;
+    hg_status st = p->layout(items, count, c.target);
+    if (st == HG_OK) st = hstat(p->upload());
+    if (st == HG_OK) st = hstat(p->capture());
+    if (st != HG_OK) {
+        delete p;
+        return st;
+    }
+    *out = p;
+    return HG_OK;
+}
+
+// Time two replays of a captured plan (after one warm-up replay).
+template <typename Key>
+hg_status time_plan(BatchPlan<Key>* p, float* ms) {
+    hipStream_t ts = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t te = hipStreamCreateWithFlags(&ts, hipStreamNonBlocking);
+    if (te == hipSuccess) te = hipEventCreate(&e0);
+    if (te == hipSuccess) te = hipEventCreate(&e1);
+    if (te == hipSuccess) te = hipGraphLaunch(p->exec, ts);
+    if (te == hipSuccess) te = hipEventRecord(e0, ts);
+    for (int r = 0; r < 2 && te == hipSuccess; ++r) te = hipGraphLaunch(p->exec, ts);
+    if (te == hipSuccess) te = hipEventRecord(e1, ts);
+    if (te == hipSuccess) te = hipEventSynchronize(e1);
+    if (te == hipSuccess) te = hipEventElapsedTime(ms, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (ts) (void)hipStreamDestroy(ts);
+    return hstat(te);
+}
+
+bool probe_shape_ok(uint32_t threads, uint32_t items) {
+    for (const ProbeShape& ps : kProbeShapes)
+        if (ps.threads == threads && ps.items == items) return true;
+    return false;
+}
+
+// The tuner searches one dimension at a time over the batch itself: the bin
+// target (partition width) with the default tile shapes, then the partition
+// tile's keys per thread at the best target, then the probe workgroup shape.
+// Each step keeps the fastest graph; a dimension fixed in opts is not
+// searched.  The result is cached per batch shape.
 template <typename Key>
 hg_status create_plan(const hg_batch_item* items, uint32_t count, const hg_batch_opts* opts,
                       hg_batch* b) {
@@ -633,76 +727,89 @@ hg_status create_plan(const hg_batch_item* items, uint32_t count, const hg_batch
         tm += items[i].m;
     }
     const int kb = (int)sizeof(Key) * 8;
-    std::vector<uint32_t> cands;
+    const bool any_order = opts && opts->any_order;
     const bool autotune = !opts || opts->autotune != 0;
-    if (opts && opts->bin_target) {
-        cands.push_back(opts->bin_target);
-    } else if (autotune) {
+    const bool fix_target = opts && opts->bin_target;
+    const bool fix_part = opts && opts->part_items;
+    const bool fix_probe = opts && opts->probe_threads;
+    BConfig cfg{fix_target ? opts->bin_target : 2048u,
+                fix_part ? opts->part_items : kPartItemsChoices[0],
+                fix_probe ? ProbeShape{opts->probe_threads, opts->probe_items} : kProbeShapes[0]};
+    const auto key = std::make_tuple(count, tn, tm, kb, any_order);
+    bool tune = autotune && !(fix_target && fix_part && fix_probe);
+    if (tune) {
         // a batch of the same shape tuned before keeps its choice
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        auto it = g_tune.find(std::make_tuple(count, tn, tm, kb, opts && opts->any_order));
-        if (it != g_tune.end()) cands.push_back(it->second);
-    }
-    const bool tune = cands.empty() && autotune;
-    if (cands.empty()) {
-        // a light bin holds up to light_cap<Key>() keys (4608 / 3072)
-        if (tune && sizeof(Key) == 4) cands = {1024u, 2048u, 4096u};
-        else if (tune) cands = {1024u, 2048u};
-        else cands = {2048u};
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            if (!fix_target) cfg.target = it->second.target;
+            if (!fix_part) cfg.part_items = it->second.part_items;
+            if (!fix_probe) cfg.probe = it->second.probe;
+            tune = false;
+        }
     }
     BatchPlan<Key>* best = nullptr;
-    float best_ms = 0.f;
-    for (uint32_t tgt : cands) {
-        BatchPlan<Key>* p = new (std::nothrow) BatchPlan<Key>();
-        if (!p) return HG_ERR_OOM;
-        p->any_order = opts && opts->any_order;
-        hg_status st = p->layout(items, count, tgt);
-        if (st == HG_OK) st = hstat(p->upload());
-        if (st == HG_OK) st = hstat(p->capture());
+    if (!tune) {
+        hg_status st = make_plan<Key>(items, count, any_order, cfg, &best);
+        if (st != HG_OK) return st;
+    } else {
+        float best_ms = 0.f;
+        // candidate configurations of one dimension, timed against the best
+        auto search = [&](const std::vector<BConfig>& cands) -> hg_status {
+            for (const BConfig& c : cands) {
+                BatchPlan<Key>* p = nullptr;
+                hg_status st = make_plan<Key>(items, count, any_order, c, &p);
+                float ms = 0.f;
+                if (st == HG_OK) st = time_plan<Key>(p, &ms);
+                if (st != HG_OK) {
+                    delete p;
+                    return st;
+                }
+                if (!best || ms < best_ms) {
+                    delete best;
+                    best = p;
+                    best_ms = ms;
+                    cfg = c;
+                } else {
+                    delete p;
+                }
+            }
+            return HG_OK;
+        };
+        std::vector<BConfig> cands;
+        if (fix_target) {
+            cands.push_back(cfg);
+        } else {
+            // a light bin holds up to light_cap<Key>() keys (4608 / 3072)
+            for (uint32_t t : {1024u, 2048u, 4096u})
+                if (t < light_cap<Key>()) cands.push_back(BConfig{t, cfg.part_items, cfg.probe});
+        }
+        hg_status st = search(cands);
+        if (st == HG_OK && !fix_part) {
+            cands.clear();
+            for (uint32_t it : kPartItemsChoices)
+                if (it != cfg.part_items) cands.push_back(BConfig{cfg.target, it, cfg.probe});
+            st = search(cands);
+        }
+        if (st == HG_OK && !fix_probe) {
+            cands.clear();
+            for (const ProbeShape& ps : kProbeShapes)
+                if (ps.threads != cfg.probe.threads || ps.items != cfg.probe.items)
+                    cands.push_back(BConfig{cfg.target, cfg.part_items, ps});
+            st = search(cands);
+        }
         if (st != HG_OK) {
-            delete p;
             delete best;
             return st;
         }
-        if (cands.size() > 1) {
-            // time two replays of the candidate graph
-            hipStream_t ts;
-            hipEvent_t e0, e1;
-            float ms = 0.f;
-            hipError_t te = hipStreamCreateWithFlags(&ts, hipStreamNonBlocking);
-            if (te == hipSuccess) te = hipEventCreate(&e0);
-            if (te == hipSuccess) te = hipEventCreate(&e1);
-            if (te == hipSuccess) te = hipGraphLaunch(p->exec, ts);  // warm-up
-            if (te == hipSuccess) te = hipEventRecord(e0, ts);
-            for (int r = 0; r < 2 && te == hipSuccess; ++r) te = hipGraphLaunch(p->exec, ts);
-            if (te == hipSuccess) te = hipEventRecord(e1, ts);
-            if (te == hipSuccess) te = hipEventSynchronize(e1);
-            if (te == hipSuccess) te = hipEventElapsedTime(&ms, e0, e1);
-            (void)hipEventDestroy(e0);
-            (void)hipEventDestroy(e1);
-            (void)hipStreamDestroy(ts);
-            if (te != hipSuccess) {
-                delete p;
-                delete best;
-                return hstat(te);
-            }
-            if (!best || ms < best_ms) {
-                delete best;
-                best = p;
-                best_ms = ms;
-            } else {
-                delete p;
-            }
-        } else {
-            best = p;
-        }
-    }
-    if (tune) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune[std::make_tuple(count, tn, tm, kb, opts && opts->any_order)] = best->target;
+        g_tune[key] = cfg;
     }
     b->plan = best;
     b->target = best->target;
+    b->part_items = best->part_items;
+    b->probe_threads = best->probe.threads;
+    b->probe_items = best->probe.items;
     return HG_OK;
 }
 
@@ -713,6 +820,10 @@ extern "C" {
 hg_status hg_batch_create(const hg_batch_item* items, uint32_t count, int key_bits,
                           const hg_batch_opts* opts, hg_batch** out) {
     if (!out || (count && !items) || (key_bits != 32 && key_bits != 64)) return HG_ERR_INVALID_ARG;
+    if (opts && ((opts->part_items && opts->part_items != 8 && opts->part_items != 16) ||
+                 (!opts->probe_threads != !opts->probe_items) ||
+                 (opts->probe_threads && !probe_shape_ok(opts->probe_threads, opts->probe_items))))
+        return HG_ERR_INVALID_ARG;
     for (uint32_t i = 0; i < count; ++i) {
         const hg_batch_item& it = items[i];
         if (it.hash_range < 1 || it.hash_range > 0xffffffffull || it.n > 0xffffffffull ||
@@ -742,6 +853,20 @@ hg_status hg_batch_run(hg_batch* b, hipStream_t stream) {
     hipGraphExec_t exec = b->key_bits == 32 ? ((BatchPlan<uint32_t>*)b->plan)->exec
                                             : ((BatchPlan<uint64_t>*)b->plan)->exec;
     return hstat(hipGraphLaunch(exec, stream));
+}
+
+hg_status hg_batch_config(const hg_batch* b, hg_batch_opts* out) {
+    if (!b || !b->plan || !out) return HG_ERR_INVALID_ARG;
+    const bool any_order = b->key_bits == 32 ? ((BatchPlan<uint32_t>*)b->plan)->any_order
+                                             : ((BatchPlan<uint64_t>*)b->plan)->any_order;
+    *out = hg_batch_opts{};
+    out->autotune = 0;
+    out->bin_target = b->target;
+    out->any_order = any_order ? 1u : 0u;
+    out->part_items = b->part_items;
+    out->probe_threads = b->probe_threads;
+    out->probe_items = b->probe_items;
+    return HG_OK;
 }
 
 hg_status hg_batch_info(const hg_batch* b, uint32_t* bin_target, uint64_t* workspace_bytes) {

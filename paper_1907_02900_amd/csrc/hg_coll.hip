@@ -406,15 +406,6 @@ hipError_t copy_to_host(void* h, const void* d, size_t bytes, hipStream_t s) {
 // temporary storage of the (bucket, position) radix sort
 size_t pair_sort_bytes(uint64_t n) { return n ? sort_pairs_ws_bytes(n) : 0; }
 
-// stream-ordered buffer released at scope exit
-struct AsyncBuf {
-    void* p = nullptr;
-    hipStream_t s = nullptr;
-    ~AsyncBuf() {
-        if (p) (void)hipFreeAsync(p, s);
-    }
-};
-
 }  // namespace
 
 // ---- host side ---------------------------------------------------------------
@@ -605,10 +596,9 @@ hipError_t run_coll_intersect(const CollDev& A, const CollDev& B, uint64_t seed,
         return hipSuccess;
     }
     const uint64_t chunks = ceil_div(T, kPairChunk);
-    AsyncBuf part;
+    Workspace part(s);
     if (chunks) {
-        HG_TRY(hipMallocAsync(&part.p, (chunks + 1) * sizeof(unsigned long long), s));
-        part.s = s;
+        HG_TRY(part.get((chunks + 1) * sizeof(unsigned long long)));
         HG_PROF("coll_pair_count", s);
         hipLaunchKernelGGL(k_pair_count<Key>, dim3((uint32_t)chunks), dim3(kT), 0, s, pairs,
                            (const uint64_t*)W, Q, T, a, b, seed, counts,

@@ -56,6 +56,49 @@ struct ProfRange {
 #define HG_PROF_CAT(a, b) HG_PROF_CAT2(a, b)
 #define HG_PROF(name, s) ::hg::ProfRange HG_PROF_CAT(hg_prof_, __LINE__)(name, s)
 
+// The allocator that temporary workspace comes from (hg_set_allocator); both
+// functions NULL means hipMallocAsync / hipFreeAsync.
+struct WsHook {
+    void* (*alloc)(size_t bytes, hipStream_t s, void* ctx) = nullptr;
+    void (*free)(void* p, hipStream_t s, void* ctx) = nullptr;
+    void* ctx = nullptr;
+};
+WsHook ws_hook();  // the hook installed now (hg_api.hip)
+
+// Temporary device memory of one call, released at scope exit in stream
+// order: work already enqueued on s may still be using it.  The block goes
+// back to the allocator that gave it, even if another hook was installed
+// meanwhile.
+struct Workspace {
+    void* p = nullptr;
+    hipStream_t s;
+    WsHook h{};
+    explicit Workspace(hipStream_t st) : s(st) {}
+    Workspace(const Workspace&) = delete;
+    Workspace& operator=(const Workspace&) = delete;
+    hipError_t get(size_t bytes) {
+        if (p) return hipErrorInvalidValue;  // one block per object
+        if (bytes == 0) bytes = 256;
+        h = ws_hook();
+        if (!h.alloc) return hipMallocAsync(&p, bytes, s);
+        p = h.alloc(bytes, s, h.ctx);
+        if (!p) return hipErrorOutOfMemory;
+        if ((uintptr_t)p % 256) {  // the carvers and vector loads assume 256-byte blocks
+            h.free(p, s, h.ctx);
+            p = nullptr;
+            return hipErrorInvalidValue;
+        }
+        return hipSuccess;
+    }
+    ~Workspace() {
+        if (!p) return;
+        if (h.alloc)
+            h.free(p, s, h.ctx);
+        else
+            (void)hipFreeAsync(p, s);
+    }
+};
+
 // A bump allocator over one workspace buffer (sizes first, then pointers).
 struct Carver {
     char* base;
@@ -118,6 +161,8 @@ hipError_t scan_excl(const uint32_t* in, uint64_t n, OutT* out, uint32_t* copy, 
                      hipStream_t s);
 
 hipError_t fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
+// *out = the longest bucket (max of offsets[b+1] - offsets[b] over b < V).
+hipError_t max_bucket_len(const uint32_t* offsets, uint64_t V, uint32_t* out, hipStream_t s);
 
 // Stable LSD radix sort of n (key, value) uint32 pairs by the low `bits` bits
 // of the key (hg_sort.hip): ping-pongs between (k0, v0) and (k1, v1); the
@@ -141,11 +186,12 @@ hipError_t run_hash(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, uint
 
 template <typename Key>
 hipError_t run_histogram(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, uint32_t* counts,
-                         uint32_t block, hipStream_t s);
+                         uint32_t block, bool plain, hipStream_t s);
 
 template <typename Key>
 hipError_t run_build_v1(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, uint32_t* offsets,
-                        uint32_t* ids, Key* ekeys, void* ws, uint32_t block, hipStream_t s);
+                        uint32_t* ids, Key* ekeys, void* ws, uint32_t block, bool plain,
+                        hipStream_t s);
 
 // ---- probe index -------------------------------------------------------------
 // Buckets holding more entries than this get a key-run summary: their distinct

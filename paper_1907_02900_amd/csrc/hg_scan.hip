@@ -133,6 +133,31 @@ __global__ __launch_bounds__(256) void k_sum_u64(const unsigned long long* __res
     }
 }
 
+// Longest bucket of a CSR offset array: max over b of off[b+1] - off[b].
+// One atomic max per workgroup (at most 1024 on one address).
+__global__ __launch_bounds__(256) void k_max_gap(const uint32_t* __restrict__ off, uint64_t V,
+                                                 uint32_t* __restrict__ out) {
+    __shared__ uint32_t red[256 / kWave];
+    uint32_t m = 0;
+    const uint64_t st = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < V; b += st) {
+        const uint32_t g = off[b + 1] - off[b];
+        m = g > m ? g : m;
+    }
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) {
+        const uint32_t o = (uint32_t)__shfl_xor((int)m, d, kWave);
+        m = o > m ? o : m;
+    }
+    if (lane_id() == 0) red[threadIdx.x / kWave] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t all = 0;
+        for (int i = 0; i < 256 / kWave; ++i) all = red[i] > all ? red[i] : all;
+        if (all) atomicMax(out, all);
+    }
+}
+
 template <typename OutT>
 __global__ void k_set_one(OutT* p, OutT v) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
@@ -149,6 +174,15 @@ hipError_t sum_u64(const unsigned long long* v, uint64_t n, unsigned long long* 
     uint64_t blocks = ceil_div(n, 256 * 8);
     if (blocks > 256) blocks = 256;
     hipLaunchKernelGGL(k_sum_u64, dim3((uint32_t)blocks), dim3(256), 0, s, v, n, out);
+    return hipGetLastError();
+}
+
+hipError_t max_bucket_len(const uint32_t* offsets, uint64_t V, uint32_t* out, hipStream_t s) {
+    HG_TRY(fill_u32(out, 1, 0u, s));
+    if (V == 0) return hipSuccess;
+    uint64_t blocks = ceil_div(V, 256 * 8);
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(k_max_gap, dim3((uint32_t)blocks), dim3(256), 0, s, offsets, V, out);
     return hipGetLastError();
 }
 

@@ -35,7 +35,7 @@ class BuildOpts(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("stable", ctypes.c_int32),
                 ("bins", ctypes.c_uint32), ("block", ctypes.c_uint32),
                 ("no_index", ctypes.c_int32), ("any_order", ctypes.c_int32),
-                ("reserved", ctypes.c_uint32 * 2)]
+                ("v1_plain", ctypes.c_int32), ("reserved", ctypes.c_uint32)]
 
 
 class TableInfo(ctypes.Structure):
@@ -116,6 +116,52 @@ def _ptr(t):
 
 # ---------------------------------------------------------------- arrays ---
 
+# ------------------------------------------------------- workspace hook ---
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+_hook = None  # the installed callbacks, kept alive while the library may call them
+
+
+def set_allocator(alloc=None, free=None):
+    """hg_set_allocator: alloc(bytes, stream_handle) -> device address (0 on
+    failure) and free(address, stream_handle) back the library's temporary
+    workspace; both None restores hipMallocAsync.  The functions are kept
+    referenced here until replaced."""
+    global _hook
+    L = lib()
+    if not hasattr(L, "_alloc_sig"):
+        L.hg_set_allocator.argtypes = [ALLOC_FN, FREE_FN, ctypes.c_void_p]
+        L.hg_set_allocator.restype = ctypes.c_int
+        L._alloc_sig = True
+    if alloc is None and free is None:
+        _check(L.hg_set_allocator(ALLOC_FN(), FREE_FN(), None), "hg_set_allocator")
+        _hook = None
+        return
+    if alloc is None or free is None:
+        raise ValueError("give both alloc and free, or neither")
+
+    def _a(nbytes, stream, _ctx):
+        try:
+            return int(alloc(int(nbytes), int(stream or 0))) or None
+        except Exception:  # noqa: BLE001 -- a failed allocation is reported as NULL
+            return None
+
+    def _f(ptr, stream, _ctx):
+        free(int(ptr), int(stream or 0))
+
+    cb = (ALLOC_FN(_a), FREE_FN(_f))
+    _check(L.hg_set_allocator(cb[0], cb[1], None), "hg_set_allocator")
+    _hook = cb
+
+
+def use_torch_allocator():
+    """Back the library's workspace with PyTorch's caching allocator (stream
+    ordered: a freed block is reused by later work on the same stream)."""
+    set_allocator(lambda nbytes, stream: torch.cuda.caching_allocator_alloc(nbytes, stream=stream),
+                  lambda ptr, stream: torch.cuda.caching_allocator_delete(ptr))
+
+
 def to_device(a: np.ndarray, device="cuda") -> torch.Tensor:
     """numpy unsigned array -> device tensor of the same bits (signed dtype)."""
     a = np.ascontiguousarray(a)
@@ -187,11 +233,13 @@ def build_plan(n: int, hash_range: int, key_bits: int = 32, bins: int = 0) -> di
             "tile_keys": p.tile_keys, "workspace_bytes": p.workspace_bytes}
 
 
-def _opts(variant=VARIANT_AUTO, stable=0, bins=0, block=0, index=True, any_order=False):
+def _opts(variant=VARIANT_AUTO, stable=0, bins=0, block=0, index=True, any_order=False,
+          v1_plain=False):
     o = BuildOpts()
     o.variant, o.stable, o.bins, o.block = int(variant), int(stable), int(bins), int(block)
     o.no_index = 0 if index else 1
     o.any_order = 1 if any_order else 0
+    o.v1_plain = 1 if v1_plain else 0
     return o
 
 
@@ -210,9 +258,10 @@ class Table:
         return cls(h, torch.device(device))
 
     def rebuild(self, keys: torch.Tensor, hash_range: int, seed: int = 0, variant=VARIANT_AUTO,
-                stable=0, bins=0, block=0, index=True, any_order=False, stream=None):
+                stable=0, bins=0, block=0, index=True, any_order=False, v1_plain=False,
+                stream=None):
         keys = _dev_keys(keys)
-        o = _opts(variant, stable, bins, block, index, any_order)
+        o = _opts(variant, stable, bins, block, index, any_order, v1_plain)
         _check(lib().hg_table_build(self._h, _ptr(keys), keys.numel(), int(hash_range),
                                     int(seed) & (2**64 - 1), ctypes.byref(o), _stream(stream)),
                "hg_table_build")
@@ -272,14 +321,44 @@ class Table:
 
 
 def hg_build(keys: torch.Tensor, hash_range: int, seed: int = 0, variant=VARIANT_AUTO, stable=0,
-             bins=0, block=0, index=True, any_order=False, stream=None) -> Table:
+             bins=0, block=0, index=True, any_order=False, v1_plain=False, stream=None) -> Table:
     keys = _dev_keys(keys)
-    o = _opts(variant, stable, bins, block, index, any_order)
+    o = _opts(variant, stable, bins, block, index, any_order, v1_plain)
     h = ctypes.c_void_p()
     _check(lib().hg_build(_ptr(keys), keys.numel(), _key_bits(keys), int(hash_range),
                           int(seed) & (2**64 - 1), ctypes.byref(o), _stream(stream),
                           ctypes.byref(h)), "hg_build")
     return Table(h, keys.device)
+
+
+class TuneInfo(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double), ("default_ms", ctypes.c_double),
+                ("candidates", ctypes.c_uint32), ("skew_class", ctypes.c_uint32),
+                ("max_bucket", ctypes.c_uint32), ("cached", ctypes.c_uint32)]
+
+
+def build_tune(keys: torch.Tensor, hash_range: int, seed: int = 0, variant=VARIANT_AUTO,
+               stable=0, index=True, any_order=False, stream=None):
+    """hg_build_tune: (keyword arguments of hg_build / Table.rebuild with the
+    tuned launch parameters, info dict)."""
+    keys = _dev_keys(keys)
+    L = lib()
+    if not hasattr(L, "_tune_sig"):
+        L.hg_build_tune.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int,
+                                    ctypes.c_uint64, ctypes.c_uint64, ctypes.POINTER(BuildOpts),
+                                    ctypes.c_void_p, ctypes.POINTER(BuildOpts),
+                                    ctypes.POINTER(TuneInfo)]
+        L.hg_build_tune.restype = ctypes.c_int
+        L._tune_sig = True
+    base = _opts(variant, stable, 0, 0, index, any_order)
+    out, info = BuildOpts(), TuneInfo()
+    _check(L.hg_build_tune(_ptr(keys), keys.numel(), _key_bits(keys), int(hash_range),
+                           int(seed) & (2**64 - 1), ctypes.byref(base), _stream(stream),
+                           ctypes.byref(out), ctypes.byref(info)), "hg_build_tune")
+    kw = {"variant": out.variant, "stable": out.stable, "bins": out.bins, "block": out.block,
+          "index": not out.no_index, "any_order": bool(out.any_order),
+          "v1_plain": bool(out.v1_plain)}
+    return kw, {f: getattr(info, f) for f, _ in TuneInfo._fields_}
 
 
 def hg_probe(table: Table, queries: torch.Tensor, counts=True, total=False, out=None,
@@ -519,7 +598,9 @@ class BatchItem(ctypes.Structure):
 
 class BatchOpts(ctypes.Structure):
     _fields_ = [("autotune", ctypes.c_uint32), ("bin_target", ctypes.c_uint32),
-                ("any_order", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 5)]
+                ("any_order", ctypes.c_uint32), ("part_items", ctypes.c_uint32),
+                ("probe_threads", ctypes.c_uint32), ("probe_items", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 2)]
 
 
 def _batch_sig():
@@ -534,6 +615,8 @@ def _batch_sig():
     L.hg_batch_info.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32),
                                 ctypes.POINTER(ctypes.c_uint64)]
     L.hg_batch_info.restype = ctypes.c_int
+    L.hg_batch_config.argtypes = [vp, ctypes.POINTER(BatchOpts)]
+    L.hg_batch_config.restype = ctypes.c_int
     L.hg_batch_free.argtypes, L.hg_batch_free.restype = [vp], None
     L._batch_ready = True
     return L
@@ -547,7 +630,8 @@ class Batch:
     two integers.  Missing outputs are allocated here.  The plan keeps the
     tensors alive."""
 
-    def __init__(self, tables, key_bits=32, autotune=True, bin_target=0, any_order=False):
+    def __init__(self, tables, key_bits=32, autotune=True, bin_target=0, any_order=False,
+                 part_items=0, probe_shape=(0, 0)):
         L = _batch_sig()
         self.tables = []
         items = (BatchItem * max(1, len(tables)))()
@@ -579,6 +663,8 @@ class Batch:
         o.autotune = 1 if autotune else 0
         o.bin_target = int(bin_target)
         o.any_order = 1 if any_order else 0
+        o.part_items = int(part_items)
+        o.probe_threads, o.probe_items = int(probe_shape[0]), int(probe_shape[1])
         h = ctypes.c_void_p()
         _check(L.hg_batch_create(items, len(tables), int(key_bits), ctypes.byref(o),
                                  ctypes.byref(h)), "hg_batch_create")
@@ -592,7 +678,11 @@ class Batch:
         w = ctypes.c_uint64(0)
         _check(_batch_sig().hg_batch_info(self._h, ctypes.byref(t), ctypes.byref(w)),
                "hg_batch_info")
-        return {"bin_target": int(t.value), "workspace_bytes": int(w.value)}
+        o = BatchOpts()
+        _check(_batch_sig().hg_batch_config(self._h, ctypes.byref(o)), "hg_batch_config")
+        return {"bin_target": int(t.value), "workspace_bytes": int(w.value),
+                "part_items": int(o.part_items),
+                "probe_shape": (int(o.probe_threads), int(o.probe_items))}
 
     def free(self):
         if self._h is not None and self._h.value:

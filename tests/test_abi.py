@@ -138,3 +138,50 @@ def test_build_plan_is_host_only_and_consistent(lib):
                 (10, 7, 32, 8)):
         with pytest.raises(hg.HGError):
             hg.build_plan(*bad)
+
+
+def test_set_allocator_validates_and_needs_no_device(lib):
+    """hg_set_allocator takes both functions or neither (restoring
+    hipMallocAsync); it is host state only and needs no device."""
+    from paper_1907_02900_amd import hg
+    L = hg.lib()
+    L.hg_set_allocator.argtypes = [hg.ALLOC_FN, hg.FREE_FN, ctypes.c_void_p]
+    L.hg_set_allocator.restype = ctypes.c_int
+    a = hg.ALLOC_FN(lambda n, s, c: None)
+    f = hg.FREE_FN(lambda p, s, c: None)
+    assert L.hg_set_allocator(a, hg.FREE_FN(), None) == 1
+    assert L.hg_set_allocator(hg.ALLOC_FN(), f, None) == 1
+    assert L.hg_set_allocator(a, f, None) == 0
+    assert L.hg_set_allocator(hg.ALLOC_FN(), hg.FREE_FN(), None) == 0
+    with pytest.raises(ValueError):
+        hg.set_allocator(alloc=lambda n, s: 0)
+    hg.set_allocator()
+
+
+def test_batch_options_validated_on_host(lib):
+    """Unsupported launch shapes are rejected before any device work."""
+    from paper_1907_02900_amd import hg
+    L = hg._batch_sig()
+    for part, th, it in ((12, 0, 0), (16, 256, 0), (16, 0, 4), (16, 64, 4), (8, 512, 8)):
+        o = hg.BatchOpts()
+        o.autotune, o.part_items, o.probe_threads, o.probe_items = 0, part, th, it
+        out = ctypes.c_void_p()
+        assert L.hg_batch_create(None, 0, 32, ctypes.byref(o), ctypes.byref(out)) == 1
+        assert not out.value
+
+
+def test_build_tune_rejects_bad_arguments_on_host(lib):
+    from paper_1907_02900_amd import hg
+    L = hg.lib()
+    vp = ctypes.c_void_p
+    L.hg_build_tune.argtypes = [vp, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint64,
+                                ctypes.c_uint64, ctypes.POINTER(hg.BuildOpts), vp,
+                                ctypes.POINTER(hg.BuildOpts), ctypes.POINTER(hg.TuneInfo)]
+    out = hg.BuildOpts()
+    dummy = vp(0x1000)
+    assert L.hg_build_tune(dummy, 10, 32, 100, 0, None, None, None, None) == 1      # no out
+    assert L.hg_build_tune(dummy, 10, 16, 100, 0, None, None, ctypes.byref(out), None) == 1
+    assert L.hg_build_tune(dummy, 10, 32, 0, 0, None, None, ctypes.byref(out), None) == 1
+    bad = hg._opts(variant=hg.VARIANT_V1, stable=1)
+    assert L.hg_build_tune(dummy, 10, 32, 100, 0, ctypes.byref(bad), None,
+                           ctypes.byref(out), None) == 1

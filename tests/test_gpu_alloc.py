@@ -1,0 +1,84 @@
+"""hg_set_allocator: the library's temporary workspace taken from PyTorch's
+caching allocator through the C ABI's hook, with results identical to the
+oracle's and every block handed back."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1907_02900_amd import hg, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture
+def counted_torch_allocator():
+    calls = {"alloc": 0, "free": 0, "bytes": 0, "live": set()}
+
+    def alloc(nbytes, stream):
+        p = torch.cuda.caching_allocator_alloc(nbytes, stream=stream)
+        calls["alloc"] += 1
+        calls["bytes"] += nbytes
+        calls["live"].add(p)
+        return p
+
+    def free(ptr, stream):
+        calls["live"].discard(ptr)
+        calls["free"] += 1
+        torch.cuda.caching_allocator_delete(ptr)
+
+    hg.set_allocator(alloc, free)
+    try:
+        yield calls
+    finally:
+        hg.set_allocator()
+
+
+def test_workspace_from_torch_caching_allocator(counted_torch_allocator):
+    calls = counted_torch_allocator
+    n, V, seed = 300_007, 250_000, 11
+    keys = workloads.duplicate_keys(n, 3.0, 32, seed=4)
+    queries = workloads.probe_queries(keys, 200_003, 0.5, seed=5)
+    dk, dq = hg.to_device(keys), hg.to_device(queries)
+    before = torch.cuda.memory_stats()["allocation.all.allocated"]
+    t = hg.hg_build(dk, V, seed=seed)               # V2 partition buffers: workspace
+    counts, total = hg.hg_probe(t, dq, counts=True, total=True)  # per-block totals
+    bids, pids, ptotal = hg.hg_probe_pairs(t, dq)   # counts, positions, scan partials
+    b = hg.hg_build(dq, V, seed=seed)
+    cb, _, _, itot = hg.hg_intersect(t, b, counts=True, total=True)
+    torch.cuda.synchronize()
+    after = torch.cuda.memory_stats()["allocation.all.allocated"]
+    assert calls["alloc"] >= 5 and calls["alloc"] == calls["free"] and not calls["live"]
+    assert after - before >= calls["alloc"]  # the blocks came from torch's allocator
+
+    o_off, o_ids, o_ek = oracle.build_table(keys, V, seed)
+    o_counts, o_total = oracle.probe_counts(keys, queries)
+    off, ids, ek = t.export()
+    assert np.array_equal(hg.to_numpy(off, np.uint32), o_off)
+    assert np.array_equal(hg.to_numpy(ids, np.uint32), o_ids)
+    assert np.array_equal(hg.to_numpy(counts, np.uint32), o_counts)
+    assert total == o_total == ptotal == itot
+    assert np.array_equal(hg.to_numpy(cb, np.uint32), o_counts)
+    o_b, o_p, o_ptotal = oracle.probe_pairs(keys, queries)
+    assert ptotal == o_ptotal
+    # a stable table gives pairs as (probe id ascending, build id ascending)
+    assert np.array_equal(hg.to_numpy(pids, np.uint32), o_p)
+    assert np.array_equal(hg.to_numpy(bids, np.uint32), o_b)
+
+
+def test_failing_allocator_reports_oom_and_default_is_restored():
+    n, V = 100_000, 100_000
+    keys = workloads.uniform_keys(n, 32, seed=9)
+    dk = hg.to_device(keys)
+    hg.set_allocator(lambda nbytes, stream: 0, lambda ptr, stream: None)
+    try:
+        with pytest.raises(hg.HGError) as ei:
+            hg.hg_build(dk, V, seed=1)
+        assert ei.value.status == hg.HG_ERR_OOM
+    finally:
+        hg.set_allocator()
+    t = hg.hg_build(dk, V, seed=1)
+    off, ids, _ = t.export()
+    o_off, o_ids, _ = oracle.build_table(keys, V, 1)
+    assert np.array_equal(hg.to_numpy(off, np.uint32), o_off)
+    assert np.array_equal(hg.to_numpy(ids, np.uint32), o_ids)

@@ -62,12 +62,16 @@ def test_batch_matches_oracle_over_replays(hg, kb, autotune):
         tabs.append({"keys": hg.to_device(k), "queries": hg.to_device(q), "hash_range": V,
                      "seed": seed})
     b = hg.Batch(tabs, key_bits=kb, autotune=autotune)
-    # the tuner keeps the fastest candidate: 1024, 2048 or (32-bit keys) 4096
-    # keys per bin; without tuning the default is 2048
+    # the tuner keeps the fastest candidate of each dimension: 1024, 2048 or
+    # (32-bit keys) 4096 keys per bin, 8 or 16 keys per partition thread, one
+    # of four probe shapes; without tuning the defaults are 2048, 16, 256x4
+    info = b.info()
     if autotune:
-        assert b.info()["bin_target"] in ((1024, 2048, 4096) if kb == 32 else (1024, 2048))
+        assert info["bin_target"] in ((1024, 2048, 4096) if kb == 32 else (1024, 2048))
+        assert info["part_items"] in (8, 16)
+        assert info["probe_shape"] in ((256, 4), (256, 8), (512, 2), (128, 8))
     else:
-        assert b.info()["bin_target"] == 2048
+        assert (info["bin_target"], info["part_items"], info["probe_shape"]) == (2048, 16, (256, 4))
     dt = np.uint64 if kb == 64 else np.uint32
     for rep in range(3):
         flip = dt((rep * 0x9E3779B1) & 0xFFFFFFFF)
@@ -193,4 +197,42 @@ def test_batch_config_shape_every_bin_target(hg, config_shape, bin_target, any_o
             assert torch.equal(ids, torch.from_numpy(o_ids.astype(np.int64)).cuda()), (rep, n)
             c = t["counts"][:q.size].to(torch.int64) & 0xFFFFFFFF
             assert torch.equal(c, torch.from_numpy(o_cnt.astype(np.int64)).cuda()), (rep, n)
+    b.free()
+
+
+@pytest.mark.parametrize("part_items,probe_shape,any_order",
+                         [(8, (256, 8), False), (8, (512, 2), True), (16, (128, 8), False),
+                          (16, (256, 8), True), (8, (256, 4), False)])
+def test_batch_config_shape_every_tile_shape(hg, config_shape, part_items, probe_shape, any_order):
+    """The launch shapes the tuner can pick besides the bin target (keys per
+    partition thread, probe workgroup shape) at the batched configuration's
+    table sizes: offsets, counts and (stable) tables equal the oracle's."""
+    print("[case] batch tile shape", part_items, probe_shape, any_order, flush=True)
+    tabs = [{"keys": hg.to_device(k), "queries": hg.to_device(q), "hash_range": V, "seed": s}
+            for k, q, V, s, _, _, _ in config_shape]
+    b = hg.Batch(tabs, key_bits=32, autotune=False, bin_target=2048, any_order=any_order,
+                 part_items=part_items, probe_shape=probe_shape)
+    info = b.info()
+    assert (info["part_items"], info["probe_shape"]) == (part_items, probe_shape)
+    b.run()
+    torch.cuda.synchronize()
+    for (k, q, V, s, o_off, o_ids, o_cnt), t in zip(config_shape, b.tables):
+        n = k.size
+        off = t["offsets"].to(torch.int64) & 0xFFFFFFFF
+        assert torch.equal(off, torch.from_numpy(o_off.astype(np.int64)).cuda()), n
+        ids = t["ids"][:n].to(torch.int64) & 0xFFFFFFFF
+        assert torch.equal(t["ekeys"][:n], t["keys"][ids]), n
+        if any_order:
+            seg = torch.repeat_interleave(torch.arange(V, device=ids.device),
+                                          off[1:] - off[:-1], output_size=n)
+            ids = ids[torch.argsort(seg * (1 << 32) + ids)]
+        assert torch.equal(ids, torch.from_numpy(o_ids.astype(np.int64)).cuda()), n
+        c = t["counts"][:q.size].to(torch.int64) & 0xFFFFFFFF
+        assert torch.equal(c, torch.from_numpy(o_cnt.astype(np.int64)).cuda()), n
+    # the reported configuration plans the same graph again, without tuning
+    b2 = hg.Batch(tabs, key_bits=32, autotune=True, bin_target=info["bin_target"],
+                  any_order=any_order, part_items=info["part_items"],
+                  probe_shape=info["probe_shape"])
+    assert b2.info() == info
+    b2.free()
     b.free()

@@ -68,7 +68,8 @@ def test_hash_matches_oracle(hg, kb, n, V, seed):
 
 
 @pytest.mark.parametrize("kb", [32, 64])
-@pytest.mark.parametrize("n,V", [(0, 9), (10000, 1), (300001, 4099), (1 << 20, 1 << 20)])
+@pytest.mark.parametrize("n,V", [(0, 9), (10000, 1), (300001, 4099), (1 << 20, 1 << 20),
+                                 (65, 3), (200003, (1 << 25) + 1)])
 def test_histogram_matches_oracle(hg, kb, n, V):
     say("histogram", kb, n, V)
     k = workloads.duplicate_keys(n, 3.0, kb, seed=7) if n else np.zeros(0, dt(kb))
@@ -154,14 +155,18 @@ def check_v1(off, ids, ek, k, V, seed, kb):
     assert np.array_equal(ek, k[ids])
 
 
+@pytest.mark.parametrize("plain", [False, True])
 @pytest.mark.parametrize("kb", [32, 64])
 @pytest.mark.parametrize("kind,n,V", [("uniform", 0, 3), ("uniform", 1000, 1),
                                       ("uniform", 100003, 100003), ("dup8", 400000, 1 << 16),
-                                      ("zipf", 300000, 300000), ("uniform", (1 << 20) + 3, 1 << 20)])
-def test_build_v1_matches_oracle_as_multisets(hg, kb, kind, n, V):
-    say("build-v1", kb, kind, n, V)
+                                      ("zipf", 300000, 300000), ("uniform", (1 << 20) + 3, 1 << 20),
+                                      ("equal", 200001, 97), ("zipf", 250007, (1 << 26) + 3),
+                                      ("dup8", 123457, (1 << 25) - 1)])
+def test_build_v1_matches_oracle_as_multisets(hg, kb, kind, n, V, plain):
+    # plain: one atomic per key; otherwise same-bucket lanes of a wave share one
+    say("build-v1", kb, kind, n, V, plain)
     k = keys_for(kind, n, kb, seed=5)
-    t = hg.hg_build(hg.to_device(k), V, seed=99, variant=hg.VARIANT_V1)
+    t = hg.hg_build(hg.to_device(k), V, seed=99, variant=hg.VARIANT_V1, v1_plain=plain)
     off, ids, ek = table_np(hg, t, kb)
     check_v1(off, ids, ek, k, V, 99, kb)
 

@@ -1,0 +1,79 @@
+"""hg_build_tune: the single-table autotuner returns launch parameters from
+its candidate set, keeps the caller's semantic options, classifies skew by
+the longest bucket, caches its choice, and builds with the tuned options
+equal the oracle's tables."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1907_02900_amd import hg, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _table(t, kb):
+    off, ids, ek = t.export()
+    torch.cuda.synchronize()
+    dt = np.uint64 if kb == 64 else np.uint32
+    return hg.to_numpy(off, np.uint32), hg.to_numpy(ids, np.uint32), hg.to_numpy(ek, dt)
+
+
+@pytest.mark.parametrize("kb", [32, 64])
+def test_tune_v2_uniform_then_cached(kb):
+    n, V = (1 << 20) + 7, 1 << 20
+    print("[case] tune v2", kb, flush=True)
+    keys = workloads.uniform_keys(n, kb, seed=3)
+    dk = hg.to_device(keys)
+    kw, info = hg.build_tune(dk, V, seed=5)
+    assert info["skew_class"] == 0 and info["max_bucket"] <= 32
+    assert info["cached"] == 0 and info["candidates"] >= 1
+    assert kw["variant"] == hg.VARIANT_V2 and kw["stable"] == 0 and kw["index"]
+    assert not kw["any_order"] and kw["block"] == 0 and not kw["v1_plain"]
+    plan = hg.build_plan(n, V, kb, bins=kw["bins"])
+    per_bin = n * (1 << plan["bucket_bits"]) / V
+    assert kw["bins"] == 0 or 512 <= per_bin <= 4096
+    t = hg.hg_build(dk, V, seed=5, **kw)
+    off, ids, ek = _table(t, kb)
+    o_off, o_ids, o_ek = oracle.build_table(keys, V, 5, kb)
+    assert np.array_equal(off, o_off) and np.array_equal(ids, o_ids)
+    assert np.array_equal(ek, o_ek)
+    # same shape and skew class: the cached choice
+    keys2 = workloads.uniform_keys(n, kb, seed=4)
+    kw2, info2 = hg.build_tune(hg.to_device(keys2), V, seed=5)
+    assert info2["cached"] == 1 and info2["candidates"] == 0 and kw2 == kw
+    assert info2["ms"] > 0 and info2["default_ms"] > 0
+
+
+def test_tune_keeps_layout_and_classifies_skew():
+    n, V = 300_000, 1 << 18
+    print("[case] tune skew", flush=True)
+    keys = np.full(n, 77, dtype=np.uint32)   # one bucket holds every key
+    dk = hg.to_device(keys)
+    kw, info = hg.build_tune(dk, V, seed=1, any_order=True, index=False)
+    assert info["skew_class"] == 2 and info["max_bucket"] == n
+    assert kw["any_order"] and not kw["index"]
+    t = hg.hg_build(dk, V, seed=1, **kw)
+    off, ids, _ = _table(t, 32)
+    o_off, o_ids, _ = oracle.build_table(keys, V, 1)
+    assert np.array_equal(off, o_off) and np.array_equal(np.sort(ids), o_ids)
+    z = workloads.zipf_keys(n, 1.2, distinct=1 << 12, seed=2)
+    _, zi = hg.build_tune(hg.to_device(z), V, seed=1)
+    assert zi["skew_class"] in (1, 2) and zi["max_bucket"] > 32
+
+
+def test_tune_v1_block_and_aggregation():
+    n, V = 400_003, 300_007
+    print("[case] tune v1", flush=True)
+    keys = workloads.zipf_keys(n, 1.2, distinct=1 << 14, seed=6)
+    dk = hg.to_device(keys)
+    kw, info = hg.build_tune(dk, V, seed=2, variant=hg.VARIANT_V1)
+    assert kw["variant"] == hg.VARIANT_V1 and kw["block"] in (0, 256, 512, 1024)
+    assert info["candidates"] == 6
+    t = hg.hg_build(dk, V, seed=2, **kw)
+    off, ids, ek = _table(t, 32)
+    o_off, o_ids, _ = oracle.build_table(keys, V, 2)
+    assert np.array_equal(off, o_off)
+    seg = np.searchsorted(off.astype(np.int64), np.arange(n), side="right") - 1
+    assert np.array_equal(ids[np.lexsort((ids, seg))], o_ids)
+    assert np.array_equal(ek, keys[ids])
