@@ -48,7 +48,8 @@ typedef enum hg_status {
     HG_ERR_CAPACITY = 4,    /* output capacity too small (total reported)    */
     HG_ERR_MISMATCH = 5,    /* tables built with different hash parameters   */
     HG_ERR_BUDGET = 6,      /* request exceeds the server's memory budget    */
-    HG_ERR_NOT_FOUND = 7    /* unknown table or request handle               */
+    HG_ERR_NOT_FOUND = 7,   /* unknown table or request handle               */
+    HG_ERR_TOO_LARGE = 8    /* size beyond the fixed limit of an entry point */
 } hg_status;
 
 /* Build variants (Sec. 3.2 and Sec. 3.3). */
@@ -317,6 +318,25 @@ hg_status hg_probe(const hg_table *t, const void *d_queries, uint64_t m, uint32_
 hg_status hg_probe_pairs(const hg_table *t, const void *d_queries, uint64_t m,
                          uint32_t *d_build_ids, uint32_t *d_probe_ids, uint64_t capacity,
                          uint64_t *h_total, hipStream_t stream);
+
+/* hg_probe_pairs for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, outputs, order and errors as hg_probe_pairs, but the
+ * call's workspace (per-query counts, their 64-bit exclusive scan and the
+ * scan's partials) lives in a fixed device array inside the library instead
+ * of being allocated: the call makes no allocation of any kind.  That array
+ * (52 MiB) exists once per device the library runs on and stays held until
+ * the process ends.  Limit: m <= HG_NOALLOC_MAX_QUERIES (2^22); larger m
+ * returns HG_ERR_TOO_LARGE before anything is enqueued.  Every call on a
+ * device shares that device's array and the array keeps what the last call
+ * left in it (each call writes every byte it reads first, so nothing needs
+ * clearing): calls that overlap on one device -- from two host threads, or
+ * on two streams -- race and give wrong pairs; serialise them.  Waits for
+ * the stream (it returns the total). */
+#define HG_NOALLOC_MAX_QUERIES (1u << 22)
+hg_status hg_probe_pairs_noalloc(const hg_table *t, const void *d_queries, uint64_t m,
+                                 uint32_t *d_build_ids, uint32_t *d_probe_ids,
+                                 uint64_t capacity, uint64_t *h_total, hipStream_t stream);
 
 /* HashGraph-Probe-New (Alg. 3): bucket-wise intersection of tables a and b,
  * which must share key_bits, hash_range and seed (else HG_ERR_MISMATCH).

@@ -243,6 +243,37 @@ hg_status probe_pairs_into(const hg_table* t, const void* d_queries, uint64_t m,
     return HG_OK;
 }
 
+// ---- fixed device scratch of the allocation-free entry point -------------
+//
+// hg_probe_pairs_noalloc's workspace lives in this array, which the code
+// object holds on every device the library is loaded on until the process
+// ends.  In host code `scratch` names a host-side stand-in, not device
+// memory: its device address on the current device comes from
+// hipGetSymbolAddress, taken once per device and kept in g_scratch_dev.
+constexpr size_t kScratchBytes = (size_t)52 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_dev[64] = {};  // per device ordinal; guarded by g_scratch_mu
+
+// The current device's copy of scratch (looked up on the first call with that
+// device current), if it holds `bytes`.
+hg_status static_scratch(size_t bytes, void** out) {
+    if (bytes > kScratchBytes) return HG_ERR_TOO_LARGE;
+    int dev = 0;
+    HG_CALL(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return HG_ERR_DEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        HG_CALL(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return HG_ERR_DEVICE;
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return HG_OK;
+}
+
 // ---- single-table autotuner ----------------------------------------------
 
 // skew class of a built table from its longest bucket: 0 = no bucket beyond
@@ -295,6 +326,7 @@ const char* hg_status_string(hg_status s) {
         case HG_ERR_MISMATCH: return "tables differ in key width, hash range or seed";
         case HG_ERR_BUDGET: return "request exceeds the memory budget";
         case HG_ERR_NOT_FOUND: return "unknown table or request";
+        case HG_ERR_TOO_LARGE: return "size exceeds the fixed limit of this entry point";
     }
     return "unknown status";
 }
@@ -782,6 +814,21 @@ hg_status hg_probe_pairs(const hg_table* t, const void* d_queries, uint64_t m,
     Workspace ws(stream);
     HG_CALL(ws.get(probe_ws_bytes(m)));
     return probe_pairs_into(t, d_queries, m, d_build_ids, d_probe_ids, capacity, h_total, ws.p,
+                            stream);
+}
+
+hg_status hg_probe_pairs_noalloc(const hg_table* t, const void* d_queries, uint64_t m,
+                                 uint32_t* d_build_ids, uint32_t* d_probe_ids, uint64_t capacity,
+                                 uint64_t* h_total, hipStream_t stream) {
+    HG_CALL_ST(check_pairs_args(t, d_queries, m, d_build_ids, d_probe_ids, capacity, h_total));
+    if (m > HG_NOALLOC_MAX_QUERIES) return HG_ERR_TOO_LARGE;
+    if (m == 0) {
+        *h_total = 0;
+        return HG_OK;
+    }
+    void* ws = nullptr;
+    HG_CALL_ST(static_scratch(probe_ws_bytes(m), &ws));
+    return probe_pairs_into(t, d_queries, m, d_build_ids, d_probe_ids, capacity, h_total, ws,
                             stream);
 }
 

@@ -22,6 +22,8 @@ LIB_PATH = os.environ.get("HG_LIB", os.path.join(_PKG, "libhashgraph.so"))
 
 HG_OK, HG_ERR_INVALID_ARG, HG_ERR_OOM, HG_ERR_DEVICE = 0, 1, 2, 3
 HG_ERR_CAPACITY, HG_ERR_MISMATCH, HG_ERR_BUDGET, HG_ERR_NOT_FOUND = 4, 5, 6, 7
+HG_ERR_TOO_LARGE = 8
+NOALLOC_MAX_QUERIES = 1 << 22
 VARIANT_AUTO, VARIANT_V1, VARIANT_V2 = 0, 1, 2
 
 
@@ -83,6 +85,7 @@ def lib():
         "hg_table_free": ([vp], None),
         "hg_probe": ([vp, vp, u64, vp, pu64, vp], i32),
         "hg_probe_pairs": ([vp, vp, u64, vp, vp, u64, pu64, vp], i32),
+        "hg_probe_pairs_noalloc": ([vp, vp, u64, vp, vp, u64, pu64, vp], i32),
         "hg_intersect": ([vp, vp, vp, vp, vp, u64, pu64, vp], i32),
         "hg_intersect_edges": ([vp, vp, vp, pu64, vp], i32),
         "hg_table_erase": ([vp, vp, u64, pu64, vp], i32),
@@ -390,6 +393,22 @@ def hg_probe_pairs(table: Table, queries: torch.Tensor, capacity=None, stream=No
     _check(rc, "hg_probe_pairs")
     t = int(tot.value)
     return b[:t], p[:t], t
+
+
+def hg_probe_pairs_noalloc(table: Table, queries: torch.Tensor, build_ids: torch.Tensor,
+                           probe_ids: torch.Tensor, stream=None):
+    """hg_probe_pairs into caller-allocated pair arrays (capacity = their
+    length) with the library's fixed workspace: (total, status).  status is
+    HG_OK or HG_ERR_CAPACITY (total still reported); other errors raise."""
+    queries = _dev_keys(queries)
+    cap = min(build_ids.numel(), probe_ids.numel())
+    tot = ctypes.c_uint64(0)
+    rc = lib().hg_probe_pairs_noalloc(table.handle, _ptr(queries), queries.numel(),
+                                      _ptr(build_ids), _ptr(probe_ids), cap, ctypes.byref(tot),
+                                      _stream(stream))
+    if rc not in (HG_OK, HG_ERR_CAPACITY):
+        _check(rc, "hg_probe_pairs_noalloc")
+    return int(tot.value), rc
 
 
 def hg_intersect(a: Table, b: Table, counts=True, total=True, capacity=0, stream=None):
