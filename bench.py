@@ -191,7 +191,8 @@ def run_batched(hg, workloads, torch, tables=4096, reps=5, log=print, any_order=
     return {"tables": tables, "keys_plus_queries": tot, "graph_ms": round(t_graph, 3),
             "graph_Gkeys": round(tot / t_graph / 1e6, 2), "loop_ms": round(t_loop, 3),
             "loop_Gkeys": round(tot / t_loop / 1e6, 2), "speedup": round(t_loop / t_graph, 2),
-            "bin_target": info["bin_target"], "plan_create_s": round(create_s, 2)}
+            "bin_target": info["bin_target"], "part_items": info["part_items"],
+            "probe_shape": list(info["probe_shape"]), "plan_create_s": round(create_s, 2)}
 
 
 SERVING_RATES = (2e3, 5e3, 1e4, 1.5e4, 2e4, 3e4, 5e4, 1e6)
@@ -597,6 +598,8 @@ def main():
             t_v2x = timed(lambda: big.rebuild(dk, Vs, 0, variant=hg.VARIANT_V2, index=False),
                           reps, torch)
             t_prx = timed(lambda: hg.hg_probe(big, dq, counts=True, out=counts), reps, torch)
+            t_v1p = timed(lambda: big.rebuild(dk, Vs, 0, variant=hg.VARIANT_V1, v1_plain=True), 2,
+                          torch)
             t_v1 = timed(lambda: big.rebuild(dk, Vs, 0, variant=hg.VARIANT_V1), 2, torch)
             t_pr1 = timed(lambda: hg.hg_probe(big, dq, counts=True, out=counts), reps, torch)
             ex["V=2^%d" % lv] = {"build_v2_ms": round(t_v2, 3),
@@ -605,6 +608,7 @@ def main():
                                  "build_v2_any_order_ms": round(t_v2a, 3),
                                  "build_v1_ms": round(t_v1, 3),
                                  "build_v1_Gkeys": round(n / t_v1 / 1e6, 2),
+                                 "build_v1_plain_ms": round(t_v1p, 3),
                                  "probe_ms": round(t_pr, 3),
                                  "probe_Gkeys": round(m / t_pr / 1e6, 2),
                                  "probe_noindex_ms": round(t_prx, 3),
@@ -675,9 +679,13 @@ def main():
         tb = timed(lambda: tz.rebuild(kz, nz, 9), 2, torch)
         tp = timed(lambda: hg.hg_probe(tz, qz, counts=True, out=counts), 2, torch)
         _, ztot = hg.hg_probe(tz, qz, counts=False, total=True)
+        # V1 on the skewed keys: merged per-wave atomics against one per key
+        tz1 = timed(lambda: tz.rebuild(kz, nz, 9, variant=hg.VARIANT_V1), 2, torch)
+        tz1p = timed(lambda: tz.rebuild(kz, nz, 9, variant=hg.VARIANT_V1, v1_plain=True), 2, torch)
         ex["zipf1.2_join"] = {"build_ms": round(tb, 3), "build_Gkeys": round(nz / tb / 1e6, 2),
                               "probe_ms": round(tp, 3), "probe_Gkeys": round(m / tp / 1e6, 2),
-                              "matches": ztot}
+                              "matches": ztot, "build_v1_ms": round(tz1, 3),
+                              "build_v1_plain_ms": round(tz1p, 3)}
         log("zipf join build %.3f ms probe %.3f ms, %d matches" % (tb, tp, ztot))
         tz.free()
         del kz, qz, tz

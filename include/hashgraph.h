@@ -538,7 +538,9 @@ typedef struct hg_server_opts {
     uint32_t merge_max;    /* most requests merged into one launch; 0 = 64,
                               1 = never merge                                  */
     uint32_t merge_keys;   /* requests of at most this many keys or queries
-                              may be merged; 0 = 65536                         */
+                              may be merged; 0 = 2^18.  Tables built in a
+                              merged launch carry no probe index (their
+                              probes read offsets and scan)                  */
     uint32_t reserved[4];
 } hg_server_opts;
 

@@ -905,7 +905,11 @@ void hg_batch_free(hg_batch* b) {
 // resident tables plus in-flight workspace under a byte budget, evicting the
 // least recently used tables that no pending or running request uses.
 // Latency is measured from submission to the moment the loop sees the
-// request's completion event.
+// request's completion event.  The loop's thread holds the server's lock only
+// for bookkeeping (choosing and accounting a launch, finishing requests):
+// device allocations, kernel launches and event polls run with it released,
+// so submissions from other threads never wait for the device API.  Each
+// table is one device allocation carved into its arrays.
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -920,6 +924,7 @@ using Clock = std::chrono::steady_clock;
 struct STable {
     int key_bits = 32;
     uint64_t n = 0, V = 0, seed = 0;
+    void* block = nullptr;  // one device allocation holding every array below
     uint32_t* offsets = nullptr;
     uint32_t* ids = nullptr;
     void* keys = nullptr;
@@ -1019,10 +1024,24 @@ struct Server {
     }
 
     void free_table(STable& t, hipStream_t s) {
-        void* ptrs[] = {t.offsets, t.ids, t.keys, t.head, t.runs.run_key, t.runs.run_end,
-                        t.runs.kperm};
-        for (void* q : ptrs)
-            if (q) (void)hipFreeAsync(q, s);
+        if (t.block) (void)hipFreeAsync(t.block, s);
+        t.block = nullptr;
+    }
+
+    // Carve a table's arrays out of one block (sizes first when base is null).
+    static size_t carve_table(STable& t, void* base) {
+        Carver c(base);
+        const uint64_t nn = t.n ? t.n : 1, ks = (uint64_t)(t.key_bits / 8);
+        t.offsets = c.take<uint32_t>(t.V + 1);
+        t.ids = c.take<uint32_t>(nn);
+        t.keys = c.take<char>(nn * ks);
+        if (t.has_index) {
+            t.head = c.take<uint4>(t.V);
+            t.runs.run_key = c.take<char>(nn * ks);
+            t.runs.run_end = c.take<uint32_t>(nn);
+            t.runs.kperm = c.take<uint32_t>(nn);
+        }
+        return c.off + 256;
     }
 
     bool evict_for(uint64_t need) {
@@ -1071,26 +1090,46 @@ struct Server {
         }
     }
 
-    void retire() {
+    // Finish the launches whose events have completed.  Only this thread
+    // changes `inflight` (under the lock), so the events are polled with the
+    // lock released; the requests are finished under it, and the launches'
+    // workspace is released after it is dropped again.
+    void retire(std::unique_lock<std::mutex>& lk) {
+        if (inflight.empty()) return;
+        std::vector<hipError_t> q(inflight.size());
+        lk.unlock();
+        bool any = false;
+        for (size_t i = 0; i < q.size(); ++i) {
+            q[i] = hipEventQuery(inflight[i].ev);
+            any |= q[i] != hipErrorNotReady;
+        }
+        lk.lock();
+        if (!any) return;
         const double t = now();
-        for (size_t i = 0; i < inflight.size();) {
+        std::vector<std::pair<void*, int>> frees;
+        std::vector<Launch> keep;
+        keep.reserve(inflight.size());
+        for (size_t i = 0; i < inflight.size(); ++i) {
             Launch& L = inflight[i];
-            const hipError_t q = hipEventQuery(L.ev);
-            if (q == hipErrorNotReady) {
-                ++i;
+            if (i >= q.size() || q[i] == hipErrorNotReady) {
+                keep.push_back(L);
                 continue;
             }
-            const hg_status st = q == hipSuccess ? HG_OK : HG_ERR_DEVICE;
+            const hg_status st = q[i] == hipSuccess ? HG_OK : HG_ERR_DEVICE;
             for (uint64_t rid : L.reqs) finish_req(rid, st, t);
             if (L.transient) {
-                (void)hipFreeAsync(L.transient, streams[L.stream]);
+                frees.push_back({L.transient, L.stream});
                 transient -= L.transient_bytes;
             }
             if (L.pinned) pinned_free.push_back({L.pinned, pinned_sizes[L.pinned]});
             event_pool.push_back(L.ev);
-            inflight.erase(inflight.begin() + i);
-            cv_done.notify_all();
         }
+        inflight.swap(keep);
+        cv_done.notify_all();
+        if (frees.empty()) return;
+        lk.unlock();
+        for (auto& f : frees) (void)hipFreeAsync(f.first, streams[f.second]);
+        lk.lock();
     }
 
     bool small(const SReq& r) const { return r.count <= o.merge_keys; }
@@ -1098,7 +1137,7 @@ struct Server {
     // Start the oldest pending request, merged with other pending requests
     // of the same kind and key width when they are small.  Returns false if
     // it has to wait for memory.
-    bool admit_one() {
+    bool admit_one(std::unique_lock<std::mutex>& lk) {
         const uint64_t rid0 = pending.front();
         SReq& r0 = reqs[rid0];
         std::vector<uint64_t> group{rid0};
@@ -1153,6 +1192,12 @@ struct Server {
                     if (p64.layout(items.data(), (uint32_t)items.size(), 2048) != HG_OK) group.resize(1);
                     else merged_ws = p64.carve(nullptr);
                 }
+            } else {
+                // probes of built (or launched) tables: descriptors and
+                // prefixes in one workspace block
+                merged_ws = kb == 32 ? layout_merged_probe<uint32_t>(p32, group)
+                                     : layout_merged_probe<uint64_t>(p64, group);
+                ws = merged_ws;
             }
         }
         if (r0.kind == 0) {
@@ -1195,86 +1240,94 @@ struct Server {
         L.stream = next_stream;
         next_stream = (next_stream + 1) % (int)streams.size();
         hipStream_t s = streams[L.stream];
-        hipError_t e = hipSuccess;
-        // allocate new tables
-        if (r0.kind == 0) {
-            for (uint64_t rid : group) {
-                STable& t = tables[reqs[rid].table];
-                if (e == hipSuccess) e = hipMallocAsync((void**)&t.offsets, (t.V + 1) * 4, s);
-                if (e == hipSuccess) e = hipMallocAsync((void**)&t.ids, (t.n ? t.n : 1) * 4, s);
-                const uint64_t nn = t.n ? t.n : 1, ks = (uint64_t)(t.key_bits / 8);
-                if (e == hipSuccess) e = hipMallocAsync(&t.keys, nn * ks, s);
-                if (e == hipSuccess && t.has_index) {
-                    e = hipMallocAsync((void**)&t.head, t.V * 16, s);
-                    if (e == hipSuccess) e = hipMallocAsync(&t.runs.run_key, nn * ks, s);
-                    if (e == hipSuccess) e = hipMallocAsync((void**)&t.runs.run_end, nn * 4, s);
-                    if (e == hipSuccess) e = hipMallocAsync((void**)&t.runs.kperm, nn * 4, s);
-                }
-                resident += t.bytes;
-                t.stream = L.stream;
-            }
+        // The group's requests and tables are reached through pointers from
+        // here on: map nodes do not move when other threads insert, and only
+        // this thread erases them.  Memory is accounted before the lock is
+        // released, so that statistics and admission see it at once.
+        std::vector<SReq*> greq;
+        std::vector<STable*> gtab;
+        for (uint64_t rid : group) {
+            SReq* r = &reqs[rid];
+            greq.push_back(r);
+            gtab.push_back(&tables[r->table]);
         }
-        if (e == hipSuccess && ws) {
-            e = hipMallocAsync(&L.transient, ws, s);
-            if (e == hipSuccess) {
-                L.transient_bytes = ws;
-                transient += ws;
+        std::vector<size_t> tbytes;
+        if (r0.kind == 0)
+            for (STable* t : gtab) {
+                tbytes.push_back(carve_table(*t, nullptr));
+                resident += t->bytes;
+                t->stream = L.stream;
             }
+        if (ws) {
+            L.transient_bytes = ws;
+            transient += ws;
         }
         if (resident + transient > peak) peak = resident + transient;
-        // probes wait for their tables' builds
-        if (e == hipSuccess && r0.kind == 1)
-            for (uint64_t rid : group) {
-                const STable& t = tables[reqs[rid].table];
-                if (!t.built && t.ready && t.stream != L.stream)
-                    e = hipStreamWaitEvent(s, t.ready, 0);
+        const SReq rq0 = r0;
+        // device work: allocations, launches and events, without the lock
+        // (submissions go on meanwhile)
+        lk.unlock();
+        hipError_t e = hipSuccess;
+        if (r0.kind == 0)
+            for (size_t i = 0; i < gtab.size() && e == hipSuccess; ++i) {
+                STable& t = *gtab[i];
+                e = hipMallocAsync(&t.block, tbytes[i], s);
+                if (e == hipSuccess) carve_table(t, t.block);
             }
+        if (e == hipSuccess && ws) e = hipMallocAsync(&L.transient, ws, s);
+        // probes wait for their tables' builds
+        if (e == hipSuccess && rq0.kind == 1)
+            for (STable* t : gtab)
+                if (!t->built && t->ready && t->stream != L.stream)
+                    e = hipStreamWaitEvent(s, t->ready, 0);
         if (e == hipSuccess) {
-            if (r0.kind == 0 && group.size() == 1) {
-                STable& t = tables[r0.table];
+            if (rq0.kind == 0 && group.size() == 1) {
+                STable& t = *gtab[0];
                 IndexOut ix{};
                 ix.head = t.head;
                 ix.runs = t.runs;
-                e = kb == 32 ? run_build_v2<uint32_t>((const uint32_t*)r0.data, t.n, t.V, t.seed,
+                e = kb == 32 ? run_build_v2<uint32_t>((const uint32_t*)rq0.data, t.n, t.V, t.seed,
                                                       t.offsets, t.ids, (uint32_t*)t.keys,
                                                       ix, L.transient, 0, true, s)
-                             : run_build_v2<uint64_t>((const uint64_t*)r0.data, t.n, t.V, t.seed,
+                             : run_build_v2<uint64_t>((const uint64_t*)rq0.data, t.n, t.V, t.seed,
                                                       t.offsets, t.ids, (uint64_t*)t.keys,
                                                       ix, L.transient, 0, true, s);
-            } else if (r0.kind == 1 && group.size() == 1) {
-                const STable& t = tables[r0.table];
+            } else if (rq0.kind == 1 && group.size() == 1) {
+                const STable& t = *gtab[0];
                 TableDev d{t.offsets, t.ids, t.keys, t.n, t.V, t.seed};
                 if (t.has_index) {
                     d.head = t.head;
                     d.runs = t.runs;
                 }
-                e = kb == 32 ? run_probe_counts<uint32_t>(d, (const uint32_t*)r0.data, r0.count,
-                                                          r0.counts, nullptr, s)
-                             : run_probe_counts<uint64_t>(d, (const uint64_t*)r0.data, r0.count,
-                                                          r0.counts, nullptr, s);
+                e = kb == 32 ? run_probe_counts<uint32_t>(d, (const uint32_t*)rq0.data, rq0.count,
+                                                          rq0.counts, nullptr, s)
+                             : run_probe_counts<uint64_t>(d, (const uint64_t*)rq0.data, rq0.count,
+                                                          rq0.counts, nullptr, s);
             } else {
-                e = kb == 32 ? enqueue_merged<uint32_t>(p32, items, group, L, s)
-                             : enqueue_merged<uint64_t>(p64, items, group, L, s);
-                merged += group.size();
+                e = kb == 32 ? enqueue_merged<uint32_t>(p32, rq0.kind == 0, gtab, L, s)
+                             : enqueue_merged<uint64_t>(p64, rq0.kind == 0, gtab, L, s);
             }
         }
-        if (e == hipSuccess && r0.kind == 0)
-            for (uint64_t rid : group) {
-                STable& t = tables[reqs[rid].table];
-                if (!t.ready) t.ready = take_event();
-                e = hipEventRecord(t.ready, s);
-                t.enqueued = true;
+        if (e == hipSuccess && rq0.kind == 0)
+            for (STable* t : gtab) {
+                if (!t->ready) t->ready = take_event();
+                e = hipEventRecord(t->ready, s);
+                if (e != hipSuccess) break;
+                t->enqueued = true;
             }
         L.ev = take_event();
         if (e == hipSuccess) e = hipEventRecord(L.ev, s);
+        if (e != hipSuccess) (void)hipStreamSynchronize(s);
+        lk.lock();
         ++launches;
+        if (group.size() > 1) merged += group.size();
         if (e != hipSuccess) {
-            (void)hipStreamSynchronize(s);
             for (uint64_t rid : group) finish_req(rid, HG_ERR_DEVICE, now());
             if (L.transient) {
                 (void)hipFreeAsync(L.transient, s);
-                transient -= L.transient_bytes;
+                L.transient = nullptr;
             }
+            transient -= L.transient_bytes;
             event_pool.push_back(L.ev);
             cv_done.notify_all();
             return true;
@@ -1283,41 +1336,44 @@ struct Server {
         return true;
     }
 
+    // Probe-only layout of a group of small probes (under the lock); returns
+    // the workspace bytes of the merged launch.
     template <typename Key>
-    hipError_t enqueue_merged(BatchPlan<Key>& p, std::vector<hg_batch_item>& items,
-                              const std::vector<uint64_t>& group, Launch& L, hipStream_t s) {
-        if (reqs[group[0]].kind == 0) {
-            for (size_t i = 0; i < group.size(); ++i) {
-                const STable& t = tables[reqs[group[i]].table];
+    size_t layout_merged_probe(BatchPlan<Key>& p, const std::vector<uint64_t>& group) {
+        std::vector<BTable<Key>> tabs;
+        for (uint64_t rid : group) {
+            const SReq& r = reqs[rid];
+            const STable& t = tables[r.table];
+            BTable<Key> b{};
+            b.queries = (const Key*)r.data;
+            b.offsets = t.offsets;
+            b.ids = t.ids;
+            b.ekeys = (Key*)t.keys;
+            b.counts = r.counts;
+            b.hp = KeyTraits<Key>::make(t.V, t.seed);
+            b.n = (uint32_t)t.n;
+            b.m = (uint32_t)r.count;
+            b.V = (uint32_t)t.V;
+            b.kind = kEmpty;
+            tabs.push_back(b);
+        }
+        p.layout_probe(tabs);
+        return p.carve(nullptr);
+    }
+
+    // A merged launch of the group's builds or probes into the launch's
+    // workspace (called without the lock: it reaches the tables only through
+    // the pointers given).
+    template <typename Key>
+    hipError_t enqueue_merged(BatchPlan<Key>& p, bool builds, const std::vector<STable*>& gtab,
+                              Launch& L, hipStream_t s) {
+        if (builds)
+            for (size_t i = 0; i < gtab.size(); ++i) {
+                const STable& t = *gtab[i];
                 p.host[i].offsets = t.offsets;
                 p.host[i].ids = t.ids;
                 p.host[i].ekeys = (Key*)t.keys;
             }
-        } else {
-            std::vector<BTable<Key>> tabs;
-            for (uint64_t rid : group) {
-                const SReq& r = reqs[rid];
-                const STable& t = tables[r.table];
-                BTable<Key> b{};
-                b.queries = (const Key*)r.data;
-                b.offsets = t.offsets;
-                b.ids = t.ids;
-                b.ekeys = (Key*)t.keys;
-                b.counts = r.counts;
-                b.hp = KeyTraits<Key>::make(t.V, t.seed);
-                b.n = (uint32_t)t.n;
-                b.m = (uint32_t)r.count;
-                b.V = (uint32_t)t.V;
-                b.kind = kEmpty;
-                tabs.push_back(b);
-            }
-            p.layout_probe(tabs);
-            const size_t need = p.carve(nullptr);
-            HG_TRY(hipMallocAsync(&L.transient, need, s));
-            L.transient_bytes = need;
-            transient += need;
-        }
-        (void)items;
         p.carve(L.transient);
         const size_t img = p.host_image_bytes();
         L.pinned = take_pinned(img);
@@ -1331,9 +1387,9 @@ struct Server {
         (void)hipSetDevice(device);
         std::unique_lock<std::mutex> lk(mu);
         for (;;) {
-            retire();
+            retire(lk);
             while (!pending.empty() && inflight.size() < o.max_inflight)
-                if (!admit_one()) break;
+                if (!admit_one(lk)) break;
             if (stop && pending.empty() && inflight.empty()) break;
             if (inflight.empty() && pending.empty())
                 cv_work.wait(lk);
@@ -1364,7 +1420,7 @@ hg_status hg_server_create(const hg_server_opts* opts, hg_server** out) {
     if (!s.o.streams) s.o.streams = 4;
     if (!s.o.max_inflight) s.o.max_inflight = 8;
     if (!s.o.merge_max) s.o.merge_max = 64;
-    if (!s.o.merge_keys) s.o.merge_keys = 65536;
+    if (!s.o.merge_keys) s.o.merge_keys = 1u << 18;
     if (s.o.streams > 16 || s.o.max_inflight > 256) {
         delete h;
         return HG_ERR_INVALID_ARG;

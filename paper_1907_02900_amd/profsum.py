@@ -33,6 +33,8 @@ RANGES = [
     ("k_tile_hist", "v2_tile_hist"),
     ("k_hist_global", "v1_hist_global"),
     ("k_scatter_v1", "v1_scatter"),
+    ("k_hist_wave", "v1_hist_wave"),
+    ("k_scatter_wave", "v1_scatter_wave"),
     ("k_intersect_count", "intersect_count"),
 ]
 
