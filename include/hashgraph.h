@@ -223,7 +223,8 @@ hg_status hg_build_plan(uint64_t n, uint64_t hash_range, int key_bits, uint32_t 
  * atomics).  The choice is cached in the process, keyed by (ceil log2 n,
  * ceil log2 hash_range, key_bits, the semantic fields, skew class), where
  * the skew class is measured on the first build of these keys (its longest
- * bucket: at most 32 entries, at most one bin's LDS capacity, or longer); a
+ * bucket: at most 32, 128 or 512 entries, at most one bin's LDS capacity,
+ * or longer); a
  * later call with the same key times only the default build and the cached
  * choice, and returns the latter.  info (may be NULL) reports the times.  Waits for the
  * stream.  Errors as hg_build. */
@@ -231,8 +232,9 @@ typedef struct hg_tune_info {
     double ms;           /* time of one build with the returned options        */
     double default_ms;   /* time of one build with the default parameters      */
     uint32_t candidates; /* configurations timed besides the default (0: cached) */
-    uint32_t skew_class; /* 0: longest bucket <= 32 entries; 1: fits a bin's
-                            LDS (4608 32-bit / 3072 64-bit keys); 2: longer    */
+    uint32_t skew_class; /* longest bucket <= 32 entries: 0; <= 128: 1;
+                            <= 512: 2; fits a bin's LDS (4608 32-bit / 3072
+                            64-bit keys): 3; longer: 4                        */
     uint32_t max_bucket; /* longest bucket of the keys' table                  */
     uint32_t cached;     /* 1: the choice came from the cache                  */
 } hg_tune_info;

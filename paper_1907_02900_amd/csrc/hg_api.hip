@@ -277,11 +277,13 @@ hg_status static_scratch(size_t bytes, void** out) {
 // ---- single-table autotuner ----------------------------------------------
 
 // skew class of a built table from its longest bucket: 0 = no bucket beyond
-// the probe index's short form (32 entries), 1 = none beyond a bin's LDS
-// capacity, 2 = longer (heavy skew)
+// the probe index's short form (32 entries), 1 = none beyond 128, 2 = none
+// beyond 512, 3 = none beyond a bin's LDS capacity, 4 = longer (heavy skew)
 uint32_t skew_class_of(uint32_t max_len, int kb) {
     if (max_len <= 32) return 0;
-    return max_len <= (kb == 64 ? 3072u : 4608u) ? 1u : 2u;
+    if (max_len <= 128) return 1;
+    if (max_len <= 512) return 2;
+    return max_len <= (kb == 64 ? 3072u : 4608u) ? 3u : 4u;
 }
 
 using TuneKey = std::tuple<uint32_t, uint32_t, int, int, int, int, int, uint32_t>;
@@ -872,19 +874,29 @@ hg_status hg_intersect(const hg_table* a, const hg_table* b, uint32_t* d_counts_
     }
     TableDev da = dev_view(a), db = dev_view(b);
     const bool pairs = capacity > 0;
+    // Counts by B's input index: Alg. 3 writes them in B's edge order, then
+    // they are scattered through B's ids (a permutation of B's inputs) in
+    // L2-sized windows.  After an erase B's ids hold stale copies, so the
+    // counts are scattered one by one as they are found instead.
+    const bool staged = d_counts_b && !b->has_len;
     Workspace ws(stream);
-    HG_CALL(ws.get(probe_ws_bytes(nb) + probe_total_slots(nb) * 8 + 256));
+    HG_CALL(ws.get(probe_ws_bytes(nb) + probe_total_slots(nb) * 8 + 512 +
+                   (staged ? scatter_perm_ws_bytes(nb) : 0)));
     Carver c(ws.p);
     uint32_t* edge = c.take<uint32_t>(nb);
     uint64_t* pos = c.take<uint64_t>(nb + 1);
     void* scan_ws = c.take<char>(scan_ws_bytes(nb));
     unsigned long long* d_total = (unsigned long long*)c.take<uint64_t>(probe_total_slots(nb));
+    void* sc_ws = staged ? c.take<char>(scatter_perm_ws_bytes(nb)) : nullptr;
+    uint32_t* by_edge = (pairs || staged) ? edge : nullptr;
+    uint32_t* by_input = staged ? nullptr : d_counts_b;
     hipError_t e = a->key_bits == 32
-                       ? run_intersect_counts<uint32_t>(da, db, pairs ? edge : nullptr, d_counts_b,
+                       ? run_intersect_counts<uint32_t>(da, db, by_edge, by_input,
                                                         (h_total && !pairs) ? d_total : nullptr, stream)
-                       : run_intersect_counts<uint64_t>(da, db, pairs ? edge : nullptr, d_counts_b,
+                       : run_intersect_counts<uint64_t>(da, db, by_edge, by_input,
                                                         (h_total && !pairs) ? d_total : nullptr, stream);
     if (e != hipSuccess) return from_hip(e);
+    if (staged) HG_CALL(scatter_perm(db.ids, edge, nb, d_counts_b, sc_ws, stream));
     if (!pairs) {
         if (h_total) return read_u64((const uint64_t*)d_total, h_total, stream);
         return HG_OK;

@@ -336,6 +336,26 @@ def test_intersect_matches_oracle(hg, kb, na, nb, V, kind):
         assert np.array_equal(got, np.stack([ep, eb], 1))
 
 
+@pytest.mark.parametrize("kb,nb,any_order", [(32, (3 << 20) + 17, False), (32, 1 << 22, True),
+                                             (64, (1 << 21) + 4097, False),
+                                             (32, (1 << 20) + 1, True)])
+def test_intersect_counts_by_input_windowed_scatter(hg, kb, nb, any_order):
+    """Counts by B's input index above 2^20 entries go through the windowed
+    scatter (B's ids partitioned by their top bits into L2-sized windows, the
+    last window partial, a window count that is not a multiple of eight):
+    they equal the oracle's counts of B's keys against A."""
+    say("intersect windowed", kb, nb, any_order)
+    ka = workloads.duplicate_keys(nb // 2 + 3, 3.0, kb, seed=61)
+    kbk = workloads.probe_queries(ka, nb, 0.5, seed=62, key_bits=kb)
+    V = nb // 2 + 11
+    a = hg.hg_build(hg.to_device(ka), V, seed=8)
+    b = hg.hg_build(hg.to_device(kbk), V, seed=8, any_order=any_order)
+    c, _, _, tot = hg.hg_intersect(a, b, counts=True, total=True)
+    exp, etot = oracle.probe_counts(ka, kbk, kb)
+    assert tot == etot
+    assert np.array_equal(hg.to_numpy(c, np.uint32), exp)
+
+
 @pytest.mark.parametrize("kb", [32, 64])
 @pytest.mark.parametrize("kind", ["uniform", "dup100"])
 def test_intersect_edge_order_counts(hg, kb, kind):
