@@ -432,7 +432,16 @@ def main():
                     help="time the stable (ids ascending in each bucket) V2 layout")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device-to-device (reference for HBM counters)")
+    ap.add_argument("--random-calibration", action="store_true",
+                    help="only run the random 16-byte read micro-benchmark over 4 GiB "
+                         "(2 launches of 2^27 reads; reference for HBM counters)")
     args = ap.parse_args()
+    if args.random_calibration:
+        from paper_1907_02900_amd import hg
+        rate = hg.random_access_rate(hg.MICRO_READ16, 1 << 32, 1 << 27)
+        print(json.dumps({"footprint_bytes": 1 << 32, "reads_per_launch": 1 << 27,
+                          "launches": 2, "read16_G_per_s": round(rate / 1e9, 2)}))
+        return
     if args.copy_calibration:
         import torch
         src = torch.ones(1 << 28, dtype=torch.int32, device="cuda")

@@ -7,12 +7,15 @@ Two commands, both reading what ``rocprofv3 -d DIR -o run`` wrote:
     duration) from a ``--kernel-trace --stats`` run, plus the launch shape of
     each library kernel.
 
-``traffic --fetch DB --write DB --copy-fetch DB --copy-write DB --out JSON``
+``traffic --fetch DB --write DB --copy-fetch DB --copy-write DB --out JSON
+[--rand-fetch DB]``
     HBM bytes per launch of the library's kernels from two ``--pmc`` runs
     (FETCH_SIZE, then WRITE_SIZE; both in KiB per dispatch).  Each counter is
     scaled by what it reads for a plain 1 GiB device-to-device copy (the
     ``bench.py --copy-calibration`` run), so that the figures are in bytes of
-    HBM traffic.  The JSON carries the digest of the kernel sources it was
+    HBM traffic.  With ``--rand-fetch`` (a FETCH_SIZE run of ``bench.py
+    --random-calibration``) it also records what the counter reads per random
+    16-byte read, raw and scaled.  The JSON carries the digest of the kernel sources it was
     taken on; bench.py reports the traffic only while that digest matches.
 
 Usage: python3 -m paper_1907_02900_amd.profsum trace|traffic ...
@@ -106,6 +109,15 @@ def cmd_traffic(a):
         w = median(wb.get(full, [0.0])) * 1024.0 * sw
         res["kernels"][key] = {"kernel": s, "fetch_bytes": f, "write_bytes": w,
                                "hbm_bytes_per_launch": f + w, "dispatches": len(vals)}
+    if a.rand_fetch:
+        # random 16-byte reads of known count: bytes the counter sees per read
+        rv = [x for k, vs in per_kernel(a.rand_fetch, "FETCH_SIZE").items()
+              if "k_rand_read16" in k for x in vs]
+        raw = median(rv) * 1024.0 / float(a.rand_accesses)
+        res["random_read16"] = {"reads_per_dispatch": int(a.rand_accesses),
+                                "dispatches": len(rv),
+                                "fetch_bytes_per_read_raw": raw,
+                                "fetch_bytes_per_read_scaled": raw * sf}
     with open(a.out, "w") as f:
         json.dump(res, f, indent=1)
     print(json.dumps(res, indent=1))
@@ -123,6 +135,8 @@ def main(argv=None):
     p = sub.add_parser("traffic")
     for k in ("fetch", "write", "copy_fetch", "copy_write", "out", "digest", "cmd"):
         p.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
+    p.add_argument("--rand-fetch", dest="rand_fetch", default=None)
+    p.add_argument("--rand-accesses", dest="rand_accesses", type=int, default=1 << 27)
     p.set_defaults(fn=cmd_traffic)
     a = ap.parse_args(argv)
     a.fn(a)
