@@ -162,8 +162,8 @@ hipError_t scan_excl(const uint32_t* in, uint64_t n, OutT* out, uint32_t* copy, 
 
 hipError_t fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
 // out[ids[p]] = vals[p] for p < n, where ids holds every index of [0, n)
-// once; windowed through L2 for large n (hg_scatter.hip).  ws:
-// scatter_perm_ws_bytes(n) bytes.
+// once; for large n through the V2 partition passes by id and per-bin LDS
+// placement (hg_v2.hip).  ws: scatter_perm_ws_bytes(n) bytes.
 size_t scatter_perm_ws_bytes(uint64_t n);
 hipError_t scatter_perm(const uint32_t* ids, const uint32_t* vals, uint64_t n, uint32_t* out,
                         void* ws, hipStream_t s);

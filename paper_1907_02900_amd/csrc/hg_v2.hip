@@ -73,12 +73,15 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t ub) {
 
 // ---------------------------------------------------- tile histograms -----
 
-template <typename Key>
+// ID_DIGIT: the digit is a bit-field of the entry's id (ids[i] >> shift)
+// instead of the bucket of its key (the scatter by a permutation below).
+template <typename Key, bool ID_DIGIT = false>
 __global__ __launch_bounds__(kPartThreads) void k_tile_hist(const Key* __restrict__ keys, Segs g,
                                                             typename KeyTraits<Key>::Params hp,
                                                             uint32_t shift, uint32_t bits,
                                                             uint32_t* __restrict__ mat,
-                                                            uint32_t tiles_ub) {
+                                                            uint32_t tiles_ub,
+                                                            const uint32_t* __restrict__ ids = nullptr) {
     extern __shared__ uint32_t cnt[];
     const uint32_t D = 1u << bits;
     const uint32_t t = xcd_tile(blockIdx.x, tiles_ub);
@@ -90,14 +93,16 @@ __global__ __launch_bounds__(kPartThreads) void k_tile_hist(const Key* __restric
 #pragma unroll
     for (int r = 0; r < IT; ++r) {
         const uint32_t i = begin + r * kPartThreads + threadIdx.x;
-        k[r] = (i < end) ? keys[i] : (Key)0;
+        if (ID_DIGIT) k[r] = (i < end) ? (Key)ids[i] : (Key)0;
+        else k[r] = (i < end) ? keys[i] : (Key)0;
     }
     __syncthreads();
     const uint32_t mask = D - 1;
 #pragma unroll
     for (int r = 0; r < IT; ++r) {
         const uint32_t i = begin + r * kPartThreads + threadIdx.x;
-        if (i < end) atomicAdd(&cnt[(KeyTraits<Key>::bucket(k[r], hp) >> shift) & mask], 1u);
+        const uint32_t v = ID_DIGIT ? (uint32_t)k[r] : KeyTraits<Key>::bucket(k[r], hp);
+        if (i < end) atomicAdd(&cnt[(v >> shift) & mask], 1u);
     }
     __syncthreads();
     uint32_t* row = mat + (size_t)t * D;
@@ -206,7 +211,7 @@ __global__ __launch_bounds__(256) void k_colscan_down(uint32_t* __restrict__ mat
 // digit.
 // STABLE: entries of equal digit keep their order (rank_stable); otherwise
 // their order inside a run is unspecified (rank_any, no ballots).
-template <typename Key, bool HAS_IDS, bool STABLE>
+template <typename Key, bool HAS_IDS, bool STABLE, bool ID_DIGIT = false>
 __global__ __launch_bounds__(kPartThreads) void k_tile_partition(
     const Key* __restrict__ src_keys, const uint32_t* __restrict__ src_ids,
     Key* __restrict__ dst_keys, uint32_t* __restrict__ dst_ids, Segs g,
@@ -247,7 +252,8 @@ __global__ __launch_bounds__(kPartThreads) void k_tile_partition(
 #pragma unroll
     for (int r = 0; r < IT; ++r) {
         const uint32_t e = wbase + r * kWave + lane;
-        dig[r] = (e < cnt) ? ((KeyTraits<Key>::bucket(k[r], hp) >> shift) & mask) : D;
+        const uint32_t v = ID_DIGIT ? id[r] : KeyTraits<Key>::bucket(k[r], hp);
+        dig[r] = (e < cnt) ? ((v >> shift) & mask) : D;
     }
     if (STABLE) rank_stable<kPartThreads, IT>(dig, bits, wcnt, dstart, tmp, pos);
     else rank_any<kPartThreads, IT>(dig, bits, wcnt, dstart, tmp, pos);
@@ -573,6 +579,38 @@ __global__ __launch_bounds__(kLocalThreads) void k_local_heavy(
     }
 }
 
+// Final step of the scatter by a permutation: bin g holds the entries whose
+// ids are [g << k, (g << k) + 2^k) (every id occurs once, so the bin starts at
+// g << k after the partition passes); they are placed in LDS by id and
+// written out with coalesced stores.
+__global__ __launch_bounds__(512) void k_perm_place(const uint32_t* __restrict__ vals,
+                                                    const uint32_t* __restrict__ ids, uint64_t n,
+                                                    uint32_t k, uint32_t* __restrict__ out) {
+    __shared__ uint32_t buf[1u << kMaxLocalBits];
+    const uint64_t start = (uint64_t)blockIdx.x << k;
+    const uint32_t len = (uint32_t)(n - start < (1ull << k) ? n - start : (1ull << k));
+    for (uint32_t i = threadIdx.x; i < len; i += 512) {
+        const uint32_t off = (uint32_t)(ids[start + i] - start);
+        if (off < len) buf[off] = vals[start + i];
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < len; i += 512) out[start + i] = buf[i];
+}
+
+__global__ void k_perm_direct(const uint32_t* __restrict__ ids, const uint32_t* __restrict__ vals,
+                              uint64_t n, uint32_t* __restrict__ out) {
+    uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t st = (uint64_t)gridDim.x * blockDim.x;
+    for (; p < n; p += st) {
+        const uint32_t id = ids[p];
+        if (id < n) out[id] = vals[p];
+    }
+}
+
+constexpr uint64_t kPermDirectMax = 1ull << 20;  // below this the output stays in L2
+
+V2Plan perm_plan(uint64_t n);
+
 }  // namespace
 
 // ------------------------------------------------------------------ plan --
@@ -706,18 +744,25 @@ void launch_partition(dim3 grid, size_t smem, hipStream_t s, const Key* src_keys
                        tiles_ub);
 }
 
+// One stable (or any-order) partition pass over the tiles of segments g.
+// id_digit (32-bit entries with ids only): the digit comes from the id.
 template <typename Key>
 hipError_t partition_pass(const Key* src_keys, const uint32_t* src_ids, Key* dst_keys,
                           uint32_t* dst_ids, const Segs& g, typename KeyTraits<Key>::Params hp,
                           uint32_t shift, uint32_t bits, uint32_t* mat, uint32_t* csum,
                           uint32_t tiles_ub, uint32_t nchunks_ub, int tier, bool stable,
-                          hipStream_t s) {
+                          hipStream_t s, bool id_digit = false) {
     const uint32_t D = 1u << bits;
     const uint32_t grid = (uint32_t)(8 * ceil_div(tiles_ub, 8));
+    if (id_digit && (sizeof(Key) != 4 || !src_ids || stable)) return hipErrorInvalidValue;
     {
         HG_PROF(tier == 1 ? "v2_tile_hist_t1" : "v2_tile_hist_t2", s);
-        hipLaunchKernelGGL(k_tile_hist<Key>, dim3(grid), dim3(kPartThreads), D * 4, s, src_keys,
-                           g, hp, shift, bits, mat, tiles_ub);
+        if (id_digit)
+            hipLaunchKernelGGL((k_tile_hist<Key, true>), dim3(grid), dim3(kPartThreads), D * 4, s,
+                               src_keys, g, hp, shift, bits, mat, tiles_ub, src_ids);
+        else
+            hipLaunchKernelGGL((k_tile_hist<Key, false>), dim3(grid), dim3(kPartThreads), D * 4, s,
+                               src_keys, g, hp, shift, bits, mat, tiles_ub, nullptr);
     }
     HG_TRY(hipGetLastError());
     HG_TRY(colscan(mat, g, D, csum, nchunks_ub, s));
@@ -725,7 +770,11 @@ hipError_t partition_pass(const Key* src_keys, const uint32_t* src_ids, Key* dst
     {
         HG_PROF(tier == 1 ? "v2_partition_t1" : "v2_partition_t2", s);
         const dim3 gr(grid);
-        if (src_ids && stable)
+        if (id_digit)
+            hipLaunchKernelGGL((k_tile_partition<Key, true, false, true>), gr, dim3(kPartThreads),
+                               smem, s, src_keys, src_ids, dst_keys, dst_ids, g, hp, shift, bits,
+                               (const uint32_t*)mat, tiles_ub);
+        else if (src_ids && stable)
             launch_partition<Key, true, true>(gr, smem, s, src_keys, src_ids, dst_keys, dst_ids,
                                               g, hp, shift, bits, mat, tiles_ub);
         else if (src_ids)
@@ -751,6 +800,8 @@ hipError_t set_smem_limits() {
         HG_TRY(hipFuncSetAttribute((const void*)k_tile_partition<Key, false, true>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, lim));
         HG_TRY(hipFuncSetAttribute((const void*)k_tile_partition<Key, true, false>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+        HG_TRY(hipFuncSetAttribute((const void*)k_tile_partition<Key, true, false, true>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, lim));
         HG_TRY(hipFuncSetAttribute((const void*)k_tile_partition<Key, false, false>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, lim));
@@ -887,6 +938,80 @@ hipError_t run_build_v2(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, 
         HG_TRY(run_key_runs<Key>(offsets, ids, ekeys, n, w.bin_start, p.bins, ix, rkeys, w.rids,
                                  w.ctr + 3, w.runs_ws, s));
     return hipSuccess;
+}
+
+// ------------------------------------------------ scatter by a permutation --
+//
+// out[ids[p]] = vals[p] for p < n, where ids holds every index of [0, n)
+// once (a table's edge ids): Alg. 3's counts, found in B's edge order, put
+// back in B's input order.  One random 4-byte store per entry would leave
+// partial lines beyond the L2; instead the (value, id) pairs go through the
+// same stable partition passes as a V2 build, with the digits taken from the
+// id instead of a key's bucket, down to bins of 4096 consecutive ids, and
+// each bin is placed in LDS and written out with coalesced stores.
+
+namespace {
+
+V2Plan perm_plan(uint64_t n) {
+    // the ids are the "buckets": V = n, bins of 2^12 ids
+    return plan_v2(n, n, 32, (uint32_t)ceil_div(n, 1ull << kMaxLocalBits));
+}
+
+size_t perm_layout(void* ws, const V2Plan& p, V2Ws* w, uint32_t** xv, uint32_t** xi) {
+    Carver c(ws);
+    void* v2 = c.take<char>(layout_v2(nullptr, p, 4, nullptr));
+    *xv = c.take<uint32_t>(p.n);
+    *xi = c.take<uint32_t>(p.n);
+    if (ws) layout_v2(v2, p, 4, w);
+    return c.off + 256;
+}
+
+}  // namespace
+
+size_t scatter_perm_ws_bytes(uint64_t n) {
+    if (n <= kPermDirectMax) return 256;
+    uint32_t *xv, *xi;
+    return perm_layout(nullptr, perm_plan(n), nullptr, &xv, &xi);
+}
+
+hipError_t scatter_perm(const uint32_t* ids, const uint32_t* vals, uint64_t n, uint32_t* out,
+                        void* ws, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    if (n <= kPermDirectMax) {
+        HG_PROF("scatter_direct", s);
+        const uint64_t g = ceil_div(n, 256 * 4);
+        hipLaunchKernelGGL(k_perm_direct, dim3((uint32_t)(g > 4096 ? 4096 : g)), dim3(256), 0, s,
+                           ids, vals, n, out);
+        return hipGetLastError();
+    }
+    HG_TRY(set_smem_limits<uint32_t>());
+    const V2Plan p = perm_plan(n);
+    V2Ws w;
+    uint32_t *xv, *xi;
+    perm_layout(ws, p, &w, &xv, &xi);
+    const auto hp = KeyTraits<uint32_t>::make(1, 0);  // unused: digits come from the ids
+    uint32_t* rv = (uint32_t*)w.rkeys;
+    hipLaunchKernelGGL(k_segs_single, dim3(1), dim3(64), 0, s, w.s1, (uint32_t)n, p.ntiles1,
+                       p.nchunks1, w.ctr);
+    HG_TRY(hipGetLastError());
+    if (p.tiers == 1) {
+        HG_TRY(partition_pass<uint32_t>(vals, ids, rv, w.rids, w.s1, hp, p.k, p.b1, w.m1, w.c1,
+                                        p.ntiles1, p.nchunks1, 1, false, s, true));
+    } else {
+        HG_TRY(partition_pass<uint32_t>(vals, ids, xv, xi, w.s1, hp, p.k + p.b2, p.b1, w.m1,
+                                        w.c1, p.ntiles1, p.nchunks1, 1, false, s, true));
+        hipLaunchKernelGGL(k_segs_from_bases, dim3(1), dim3(1024), 0, s, (const uint32_t*)w.m1,
+                           p.ntiles1, (uint32_t)n, w.s2);
+        HG_TRY(hipGetLastError());
+        HG_TRY(partition_pass<uint32_t>(xv, xi, rv, w.rids, w.s2, hp, p.k, p.b2, w.m2, w.c2,
+                                        p.ntiles2_ub, p.nchunks2_ub, 2, false, s, true));
+    }
+    {
+        HG_PROF("scatter_place", s);
+        hipLaunchKernelGGL(k_perm_place, dim3(p.bins), dim3(512), 0, s, (const uint32_t*)rv,
+                           (const uint32_t*)w.rids, n, p.k, out);
+    }
+    return hipGetLastError();
 }
 
 template hipError_t run_build_v2<uint32_t>(const uint32_t*, uint64_t, uint64_t, uint64_t,
