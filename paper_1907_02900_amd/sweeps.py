@@ -5,8 +5,10 @@ seeded generators and the C ABI, and prints one JSON object:
 
 ``appearances``  Sec. 5.1 / Fig. 3, 4, 7: N = 2^25 keys drawn uniformly from a
                  range of N / R values (R appearances per key on average,
-                 R = 1/8 ... 32), V = N.  V1 build, V2 build (stable and any
-                 order), Probe-Standard counts and Probe-New (build the query
+                 R = 1/8 ... 32), V = N.  V1 build (per-wave merged and
+                 per-key atomics), V2 build (stable; any order with and
+                 without the probe index, and with hg_build_tune's choice of
+                 bins), Probe-Standard counts and Probe-New (build the query
                  table, intersect: counts in its edge order) with queries from
                  the same range.
 ``bins``         Fig. 4 / 5: V2 build time over sizes 2^21, 2^23, 2^25 and bin
@@ -57,7 +59,11 @@ def appearances(n=1 << 25):
         k = hg.to_device(workloads.duplicate_keys(n, R, 32, seed=1))
         q = hg.to_device(workloads.duplicate_keys(n, R, 32, seed=2))
         v1 = _timed(lambda: t.rebuild(k, n, 0, variant=hg.VARIANT_V1))
+        v1p = _timed(lambda: t.rebuild(k, n, 0, variant=hg.VARIANT_V1, v1_plain=True))
         v2a = _timed(lambda: t.rebuild(k, n, 0, any_order=True))
+        v2x = _timed(lambda: t.rebuild(k, n, 0, any_order=True, index=False))
+        kw, _ = hg.build_tune(k, n, 0, any_order=True)
+        v2t = _timed(lambda: t.rebuild(k, n, 0, **kw))
         v2 = _timed(lambda: t.rebuild(k, n, 0))
         ps = _timed(lambda: hg.hg_probe(t, q, counts=True, out=counts))
 
@@ -66,8 +72,10 @@ def appearances(n=1 << 25):
             hg.hg_intersect_edges(t, tq, counts=True, total=False, out=counts)
 
         pn = _timed(probe_new)
-        rows.append({"R": R, "v1_Gkeys": _rate(n, v1), "v2_stable_Gkeys": _rate(n, v2),
-                     "v2_any_Gkeys": _rate(n, v2a), "probe_standard_Gq": _rate(n, ps),
+        rows.append({"R": R, "v1_Gkeys": _rate(n, v1), "v1_per_key_atomics_Gkeys": _rate(n, v1p),
+                     "v2_stable_Gkeys": _rate(n, v2), "v2_any_Gkeys": _rate(n, v2a),
+                     "v2_any_no_index_Gkeys": _rate(n, v2x), "v2_any_tuned_Gkeys": _rate(n, v2t),
+                     "tuned_bins": kw["bins"], "probe_standard_Gq": _rate(n, ps),
                      "probe_new_Gq": _rate(n, pn)})
         print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
     t.free()
