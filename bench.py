@@ -202,7 +202,8 @@ def run_serving(hg, workloads, torch, requests=2000, rates=SERVING_RATES, log=pr
     """Poisson stream, 30% builds (n log-uniform in [2^10, 2^24]) and 70%
     probes (m log-uniform in [2^10, 2^22]) against resident tables, 64 GB
     budget; the arrival rate is swept from well below to beyond saturation,
-    `requests` requests per rate.  Keys come from one device pool of uniform
+    `requests` requests per rate; the server runs 4 launching threads over 8
+    streams with up to 32 launches in flight.  Keys come from one device pool of uniform
     keys; a probe takes half its queries from its table's key range (hits) and
     half from elsewhere.  The baseline is a sequential loop of the plain
     entry points over the saturated stream, doing the same work the server
@@ -219,7 +220,7 @@ def run_serving(hg, workloads, torch, requests=2000, rates=SERVING_RATES, log=pr
         return pool[o:o + n], o
 
     out = {"rates": [], "requests_per_rate": requests}
-    srv = hg.Server(budget_bytes=64 << 30, streams=4, max_inflight=16)
+    srv = hg.Server(budget_bytes=64 << 30, streams=8, max_inflight=32, workers=4)
     tables = []
     for _ in range(64):  # warm-up: resident tables
         n = int(np.exp2(rng.uniform(10, 24)))

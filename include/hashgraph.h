@@ -543,7 +543,11 @@ typedef struct hg_server_opts {
                               may be merged; 0 = 2^18.  Tables built in a
                               merged launch carry no probe index (their
                               probes read offsets and scan)                  */
-    uint32_t reserved[4];
+    uint32_t workers;      /* host threads that launch the device work, each
+                              on its own share of the streams; 0 = 2 (or 1
+                              with one stream); at most 8 and at most
+                              `streams`                                      */
+    uint32_t reserved[3];
 } hg_server_opts;
 
 typedef struct hg_server_stats {

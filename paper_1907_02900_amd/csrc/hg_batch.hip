@@ -904,11 +904,13 @@ void hg_batch_free(hg_batch* b) {
 // batched probe.  Tables stay resident in HBM until evicted; admission keeps
 // resident tables plus in-flight workspace under a byte budget, evicting the
 // least recently used tables that no pending or running request uses.
-// Latency is measured from submission to the moment the loop sees the
-// request's completion event.  The loop's thread holds the server's lock only
-// for bookkeeping (choosing and accounting a launch, finishing requests):
-// device allocations, kernel launches and event polls run with it released,
-// so submissions from other threads never wait for the device API.  Each
+// Latency is measured from submission to the moment a worker sees the
+// request's completion event.  Several worker threads (two by default) run
+// the loop, each launching on its own share of the streams; they hold the
+// server's lock only for bookkeeping (choosing and accounting a launch,
+// taking pooled events and pinned buffers, finishing requests): device
+// allocations, kernel launches and event polls run with it released, so
+// neither submissions nor the other workers wait for the device API.  Each
 // table is one device allocation carved into its arrays.
 #include <chrono>
 #include <condition_variable>
@@ -955,6 +957,7 @@ struct SReq {
 
 struct Launch {
     std::vector<uint64_t> reqs;
+    uint64_t seq = 0;  // unique per launch (events are pooled and reused)
     hipEvent_t ev = nullptr;
     int stream = 0;
     void* transient = nullptr;
@@ -975,11 +978,12 @@ struct Server {
     std::vector<hipStream_t> streams;
     std::vector<std::pair<void*, size_t>> pinned_free;
     std::vector<hipEvent_t> event_pool;
-    int next_stream = 0;
     uint64_t resident = 0, transient = 0, peak = 0, clock = 0;
     uint64_t next_id = 1;
     bool stop = false;
-    std::thread worker;
+    std::vector<std::thread> workers;
+    std::vector<uint32_t> worker_next;  // per worker: its next stream
+    uint64_t next_seq = 1;
     // statistics
     std::vector<double> lat_ms;
     uint64_t completed = 0, failed = 0, rejected = 0, evictions = 0, launches = 0, merged = 0,
@@ -1090,32 +1094,37 @@ struct Server {
         }
     }
 
-    // Finish the launches whose events have completed.  Only this thread
-    // changes `inflight` (under the lock), so the events are polled with the
-    // lock released; the requests are finished under it, and the launches'
-    // workspace is released after it is dropped again.
+    // Finish the launches whose events have completed.  The events are
+    // polled with the lock released, from a snapshot taken under it; a
+    // launch is finished (under the lock) only if it is still in flight, so
+    // several workers may retire at once.  The launches' workspace is
+    // released after the lock is dropped again.
     void retire(std::unique_lock<std::mutex>& lk) {
         if (inflight.empty()) return;
-        std::vector<hipError_t> q(inflight.size());
+        std::vector<std::pair<uint64_t, hipEvent_t>> snap;
+        snap.reserve(inflight.size());
+        for (const Launch& L : inflight) snap.push_back({L.seq, L.ev});
+        std::vector<std::pair<uint64_t, hipError_t>> done;
         lk.unlock();
-        bool any = false;
-        for (size_t i = 0; i < q.size(); ++i) {
-            q[i] = hipEventQuery(inflight[i].ev);
-            any |= q[i] != hipErrorNotReady;
+        for (auto& x : snap) {
+            const hipError_t q = hipEventQuery(x.second);
+            if (q != hipErrorNotReady) done.push_back({x.first, q});
         }
         lk.lock();
-        if (!any) return;
+        if (done.empty()) return;
         const double t = now();
         std::vector<std::pair<void*, int>> frees;
         std::vector<Launch> keep;
         keep.reserve(inflight.size());
-        for (size_t i = 0; i < inflight.size(); ++i) {
-            Launch& L = inflight[i];
-            if (i >= q.size() || q[i] == hipErrorNotReady) {
+        for (Launch& L : inflight) {
+            const hipError_t* q = nullptr;
+            for (auto& d : done)
+                if (d.first == L.seq) q = &d.second;
+            if (!q) {
                 keep.push_back(L);
                 continue;
             }
-            const hg_status st = q[i] == hipSuccess ? HG_OK : HG_ERR_DEVICE;
+            const hg_status st = *q == hipSuccess ? HG_OK : HG_ERR_DEVICE;
             for (uint64_t rid : L.reqs) finish_req(rid, st, t);
             if (L.transient) {
                 frees.push_back({L.transient, L.stream});
@@ -1137,7 +1146,7 @@ struct Server {
     // Start the oldest pending request, merged with other pending requests
     // of the same kind and key width when they are small.  Returns false if
     // it has to wait for memory.
-    bool admit_one(std::unique_lock<std::mutex>& lk) {
+    bool admit_one(std::unique_lock<std::mutex>& lk, uint32_t wk) {
         const uint64_t rid0 = pending.front();
         SReq& r0 = reqs[rid0];
         std::vector<uint64_t> group{rid0};
@@ -1237,8 +1246,14 @@ struct Server {
                 }
         Launch L;
         L.reqs = group;
-        L.stream = next_stream;
-        next_stream = (next_stream + 1) % (int)streams.size();
+        L.seq = next_seq++;
+        // worker wk launches on streams wk, wk + workers, ... in turn
+        {
+            const uint32_t W = (uint32_t)workers.size() ? (uint32_t)workers.size() : 1u;
+            const uint32_t per = ((uint32_t)streams.size() + W - 1 - wk) / W;  // >= 1
+            L.stream = (int)(wk + W * (worker_next[wk] % per));
+            worker_next[wk] += 1;
+        }
         hipStream_t s = streams[L.stream];
         // The group's requests and tables are reached through pointers from
         // here on: map nodes do not move when other threads insert, and only
@@ -1263,6 +1278,19 @@ struct Server {
             transient += ws;
         }
         if (resident + transient > peak) peak = resident + transient;
+        // pooled events and the merged launch's pinned descriptor image are
+        // taken here, under the lock
+        L.ev = take_event();
+        if (r0.kind == 0)
+            for (STable* t : gtab)
+                if (!t->ready) t->ready = take_event();
+        if (group.size() > 1)
+            L.pinned = take_pinned(kb == 32 ? p32.host_image_bytes() : p64.host_image_bytes());
+        // probes wait for their tables' builds launched on other streams
+        std::vector<hipEvent_t> waits;
+        if (r0.kind == 1)
+            for (STable* t : gtab)
+                if (!t->built && t->ready && t->stream != L.stream) waits.push_back(t->ready);
         const SReq rq0 = r0;
         // device work: allocations, launches and events, without the lock
         // (submissions go on meanwhile)
@@ -1275,11 +1303,8 @@ struct Server {
                 if (e == hipSuccess) carve_table(t, t.block);
             }
         if (e == hipSuccess && ws) e = hipMallocAsync(&L.transient, ws, s);
-        // probes wait for their tables' builds
-        if (e == hipSuccess && rq0.kind == 1)
-            for (STable* t : gtab)
-                if (!t->built && t->ready && t->stream != L.stream)
-                    e = hipStreamWaitEvent(s, t->ready, 0);
+        for (size_t i = 0; i < waits.size() && e == hipSuccess; ++i)
+            e = hipStreamWaitEvent(s, waits[i], 0);
         if (e == hipSuccess) {
             if (rq0.kind == 0 && group.size() == 1) {
                 STable& t = *gtab[0];
@@ -1310,15 +1335,16 @@ struct Server {
         }
         if (e == hipSuccess && rq0.kind == 0)
             for (STable* t : gtab) {
-                if (!t->ready) t->ready = take_event();
                 e = hipEventRecord(t->ready, s);
                 if (e != hipSuccess) break;
-                t->enqueued = true;
             }
-        L.ev = take_event();
         if (e == hipSuccess) e = hipEventRecord(L.ev, s);
         if (e != hipSuccess) (void)hipStreamSynchronize(s);
         lk.lock();
+        // other workers admit probes of these tables from now on (their
+        // arrays were written before the lock was taken again)
+        if (e == hipSuccess && rq0.kind == 0)
+            for (STable* t : gtab) t->enqueued = true;
         ++launches;
         if (group.size() > 1) merged += group.size();
         if (e != hipSuccess) {
@@ -1329,6 +1355,7 @@ struct Server {
             }
             transient -= L.transient_bytes;
             event_pool.push_back(L.ev);
+            if (L.pinned) pinned_free.push_back({L.pinned, pinned_sizes[L.pinned]});
             cv_done.notify_all();
             return true;
         }
@@ -1375,21 +1402,19 @@ struct Server {
                 p.host[i].ekeys = (Key*)t.keys;
             }
         p.carve(L.transient);
-        const size_t img = p.host_image_bytes();
-        L.pinned = take_pinned(img);
         if (!L.pinned) return hipErrorOutOfMemory;
         p.host_image(L.pinned);
         HG_TRY(p.copy_image_async(L.pinned, s));
         return p.enqueue(s);
     }
 
-    void loop() {
+    void loop(uint32_t wk) {
         (void)hipSetDevice(device);
         std::unique_lock<std::mutex> lk(mu);
         for (;;) {
             retire(lk);
             while (!pending.empty() && inflight.size() < o.max_inflight)
-                if (!admit_one(lk)) break;
+                if (!admit_one(lk, wk)) break;
             if (stop && pending.empty() && inflight.empty()) break;
             if (inflight.empty() && pending.empty())
                 cv_work.wait(lk);
@@ -1421,7 +1446,9 @@ hg_status hg_server_create(const hg_server_opts* opts, hg_server** out) {
     if (!s.o.max_inflight) s.o.max_inflight = 8;
     if (!s.o.merge_max) s.o.merge_max = 64;
     if (!s.o.merge_keys) s.o.merge_keys = 1u << 18;
-    if (s.o.streams > 16 || s.o.max_inflight > 256) {
+    if (!s.o.workers) s.o.workers = s.o.streams < 2 ? s.o.streams : 2;
+    if (s.o.streams > 16 || s.o.max_inflight > 256 || s.o.workers > 8 ||
+        s.o.workers > s.o.streams) {
         delete h;
         return HG_ERR_INVALID_ARG;
     }
@@ -1439,7 +1466,13 @@ hg_status hg_server_create(const hg_server_opts* opts, hg_server** out) {
         delete h;
         return st;
     }
-    s.worker = std::thread([&s] { s.loop(); });
+    s.worker_next.assign(s.o.workers, 0u);
+    {
+        // workers start under the lock, so that none runs before all exist
+        std::lock_guard<std::mutex> lk(s.mu);
+        for (uint32_t w = 0; w < s.o.workers; ++w)
+            s.workers.emplace_back([&s, w] { s.loop(w); });
+    }
     *out = h;
     return HG_OK;
 }
@@ -1620,7 +1653,8 @@ void hg_server_destroy(hg_server* h) {
         s.stop = true;
         s.cv_work.notify_all();
     }
-    if (s.worker.joinable()) s.worker.join();
+    for (auto& w : s.workers)
+        if (w.joinable()) w.join();
     for (auto q : s.streams) (void)hipStreamSynchronize(q);
     for (auto& kv : s.tables) {
         hg::srv::STable& t = kv.second;

@@ -720,7 +720,8 @@ class Batch:
 class ServerOpts(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_uint64), ("streams", ctypes.c_uint32),
                 ("max_inflight", ctypes.c_uint32), ("merge_max", ctypes.c_uint32),
-                ("merge_keys", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 4)]
+                ("merge_keys", ctypes.c_uint32), ("workers", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 3)]
 
 
 class ServerStats(ctypes.Structure):
@@ -761,11 +762,13 @@ class Server:
     """The library's request loop.  Submitted tensors are kept alive here
     until their request completes."""
 
-    def __init__(self, budget_bytes=0, streams=0, max_inflight=0, merge_max=0, merge_keys=0):
+    def __init__(self, budget_bytes=0, streams=0, max_inflight=0, merge_max=0, merge_keys=0,
+                 workers=0):
         L = _server_sig()
         o = ServerOpts()
         o.budget_bytes, o.streams, o.max_inflight = int(budget_bytes), int(streams), int(max_inflight)
         o.merge_max, o.merge_keys = int(merge_max), int(merge_keys)
+        o.workers = int(workers)
         h = ctypes.c_void_p()
         _check(L.hg_server_create(ctypes.byref(o), ctypes.byref(h)), "hg_server_create")
         self._h = h
