@@ -47,11 +47,12 @@ def make_requests(seed=3, nbuild=24, nprobe=56):
     return builds, reqs
 
 
-def run(hg, builds, reqs, alone):
+def run(hg, builds, reqs, alone, workers=0):
     if alone:
         srv = hg.Server(streams=1, max_inflight=1, merge_max=1)
     else:
-        srv = hg.Server(streams=4, max_inflight=16, merge_max=64, merge_keys=1 << 16)
+        srv = hg.Server(streams=8 if workers > 2 else 4, max_inflight=16, merge_max=64,
+                        merge_keys=1 << 16, workers=workers)
     dk = [hg.to_device(k) for k, _, _ in builds]
     tids, counts, qs = {}, [], []
     rng = np.random.default_rng(9)
@@ -83,12 +84,14 @@ def run(hg, builds, reqs, alone):
     return tables, cnts, qs, st
 
 
-def test_results_same_alone_and_in_mix(hg):
+@pytest.mark.parametrize("workers", [1, 2, 4])
+def test_results_same_alone_and_in_mix(hg, workers):
+    # the mix runs with one, two or four threads launching device work
     builds, reqs = make_requests()
     print("[case] serve alone", flush=True)
     t_alone, c_alone, qs, st_alone = run(hg, builds, reqs, alone=True)
-    print("[case] serve mix", flush=True)
-    t_mix, c_mix, _, st_mix = run(hg, builds, reqs, alone=False)
+    print("[case] serve mix, workers", workers, flush=True)
+    t_mix, c_mix, _, st_mix = run(hg, builds, reqs, alone=False, workers=workers)
     assert st_alone["merged_requests"] == 0
     assert st_mix["completed"] == len(reqs) and st_mix["failed"] == 0
     for b in t_alone:
@@ -138,3 +141,10 @@ def test_budget_eviction_and_pinning(hg):
     srv.drain()
     assert srv.stats()["rejected"] >= 1
     srv.close()
+
+
+def test_server_options_validated(hg):
+    for kw in ({"streams": 2, "workers": 3}, {"workers": 9, "streams": 16}, {"streams": 17}):
+        with pytest.raises(hg.HGError) as e:
+            hg.Server(**kw)
+        assert e.value.status == hg.HG_ERR_INVALID_ARG
