@@ -370,19 +370,64 @@ __device__ __forceinline__ void wave_sort_pairs(Key& k, uint32_t& p) {
     }
 }
 
-// A bucket's probe index entry, or, for a bucket longer than kRunBucket, its
-// place in the bin's list of long buckets (its entry is written with its key
-// runs).  k points at the bucket's first key in LDS.
+// Buckets whose index entry is built by one lane: up to 8 entries (a few
+// overlapped LDS reads).  Longer ones up to kRunBucket entries -- common only
+// when keys repeat many times -- are listed and built by a whole wave
+// (bin_medium_heads) instead of one lane walking them in dependent rounds.
+template <typename Key>
+constexpr uint32_t head_lane_max() { return 8u; }
+
+// A bucket's probe index entry, or its place in one of the bin's lists: the
+// long buckets (more than kRunBucket entries; their entries are written with
+// their key runs) and the medium ones (their entries are written a wave per
+// bucket), med[] packing lo | len << 13 | v << 19 (v = local bucket).  k
+// points at the bucket's first key in LDS.
 template <typename Key>
 __device__ __forceinline__ void note_bucket(const IndexOut& ix, const LongLds<Key>& lr,
-                                            uint32_t b, uint32_t out, uint32_t lo, uint32_t hi,
+                                            uint32_t* med, uint32_t v0, uint32_t v,
+                                            uint32_t out, uint32_t lo, uint32_t hi,
                                             const Key* k) {
-    if (hi - lo > kRunBucket) {
+    const uint32_t len = hi - lo;
+    if (len > kRunBucket) {
         const uint32_t t = atomicAdd(&lr.cnt[0], 1u);
         lr.lohi[t] = lo | (hi << 16);
-        lr.bkt[t] = b;
+        lr.bkt[t] = v0 + v;
+    } else if (len > head_lane_max<Key>()) {
+        med[atomicAdd(&lr.cnt[2], 1u)] = lo | (len << 13) | (v << 19);
     } else {
-        ix.head[b] = head_entry<Key>(out + lo, out + hi, k);
+        ix.head[v0 + v] = head_entry<Key>(out + lo, out + hi, k);
+    }
+}
+
+// Index entries of the bin's medium buckets (more than head_lane_max and at
+// most kRunBucket entries), one wave per bucket: lane i holds the bucket's
+// key i; the first key's count is a ballot and the filter an OR over the
+// lanes -- the same entry head_entry builds with one lane.  Called by whole
+// waves after a barrier that follows the lists' construction.
+template <typename Key>
+__device__ __forceinline__ void bin_medium_heads(const IndexOut& ix, const LongLds<Key>& lr,
+                                                 const uint32_t* med, const Key* skeys,
+                                                 uint32_t out, uint32_t v0) {
+    const uint32_t nm = lr.cnt[2];
+    const uint32_t w = threadIdx.x / kWave, lane = lane_id();
+    for (uint32_t j = w; j < nm; j += W_LOCAL) {
+        const uint32_t e = med[j];
+        const uint32_t lo = e & 0x1fffu, len = (e >> 13) & 0x3fu, v = e >> 19;
+        const bool in = lane < len;
+        const Key k0 = skeys[lo];
+        const Key kx = in ? skeys[lo + lane] : k0;
+        if constexpr (sizeof(Key) == 4) {
+            const uint32_t c0 = (uint32_t)__popcll(ballot(in && kx == k0));
+            uint32_t f = (in && kx != k0) ? (1u << filter_bit((uint32_t)kx)) : 0u;
+#pragma unroll
+            for (int d = kWave / 2; d >= 1; d >>= 1) f |= (uint32_t)__shfl_xor((int)f, d, kWave);
+            if (lane == 0) ix.head[v0 + v] = make_uint4(len, out + lo, (uint32_t)k0, c0 | f << 8);
+        } else {
+            uint64_t z = in ? filter_bits64((uint64_t)kx) : 0ull;
+#pragma unroll
+            for (int d = kWave / 2; d >= 1; d >>= 1) z |= __shfl_xor(z, d, kWave);
+            if (lane == 0) ix.head[v0 + v] = make_uint4(len, out + lo, (uint32_t)z, (uint32_t)(z >> 32));
+        }
     }
 }
 
@@ -394,9 +439,11 @@ __device__ __forceinline__ void note_bucket(const IndexOut& ix, const LongLds<Ke
 // keys is listed for the general pass.  Whole workgroup; barriers.
 template <typename Key>
 __device__ __forceinline__ void bin_long_runs(const IndexOut& ix, const LongLds<Key>& lr,
-                                              const Key* skeys, const uint32_t* sids,
-                                              uint32_t out, uint32_t g) {
+                                              const uint32_t* med, const Key* skeys,
+                                              const uint32_t* sids, uint32_t out, uint32_t g,
+                                              uint32_t v0) {
     __syncthreads();
+    bin_medium_heads<Key>(ix, lr, med, skeys, out, v0);
     const uint32_t nl = lr.cnt[0];
     const uint32_t w = threadIdx.x / kWave, lane = lane_id();
     Key* rkey = (Key*)ix.runs.run_key;
@@ -504,6 +551,9 @@ __device__ __forceinline__ void light_bin_body_by(const Key* __restrict__ src_ke
     Key* skeys = (Key*)smem;
     uint32_t* sids = (uint32_t*)(skeys + kLightCap);
     uint16_t* sb = (uint16_t*)(sids + kLightCap);
+    // the bucket sort's scratch holds the list of medium buckets afterwards
+    // (at most kLightCap / (head_lane_max + 1) of them; room for kLightCap / 2)
+    uint32_t* med = (uint32_t*)sb;
     uint32_t* cnt = (uint32_t*)(sb + kLightCap);  // NB
     uint32_t* wcnt = cnt + NB;                     // W * 64
     uint32_t* dstart = wcnt + W_LOCAL * 64;        // 64
@@ -531,7 +581,7 @@ __device__ __forceinline__ void light_bin_body_by(const Key* __restrict__ src_ke
         }
     }
     for (uint32_t i = threadIdx.x; i < NB; i += kLocalThreads) cnt[i] = 0;
-    if (ix.head && threadIdx.x < 2) lr.cnt[threadIdx.x] = 0;
+    if (ix.head && threadIdx.x < 3) lr.cnt[threadIdx.x] = 0;
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < IT; ++r) {
@@ -576,7 +626,7 @@ __device__ __forceinline__ void light_bin_body_by(const Key* __restrict__ src_ke
         for (uint32_t v = threadIdx.x; v < nb; v += kLocalThreads) {
             const uint32_t lo = v ? cnt[v - 1] : 0u, hi = cnt[v];
             offsets[v0 + v] = out + lo;
-            if (ix.head) note_bucket<Key>(ix, lr, v0 + v, out, lo, hi, skeys + lo);
+            if (ix.head) note_bucket<Key>(ix, lr, med, v0, v, out, lo, hi, skeys + lo);
         }
     } else {
         sort_chunk_by_bucket<Key, IT>(kk, id, b, rounds, L, wchunk, k, skeys, sids, sb, wcnt,
@@ -585,14 +635,14 @@ __device__ __forceinline__ void light_bin_body_by(const Key* __restrict__ src_ke
         for (uint32_t v = threadIdx.x; v < nb; v += kLocalThreads) {
             const uint32_t lo = cnt[v], hi = (v + 1 < NB) ? cnt[v + 1] : L;
             offsets[v0 + v] = out + lo;
-            if (ix.head) note_bucket<Key>(ix, lr, v0 + v, out, lo, hi, skeys + lo);
+            if (ix.head) note_bucket<Key>(ix, lr, med, v0, v, out, lo, hi, skeys + lo);
         }
     }
     for (uint32_t p = threadIdx.x; p < L; p += kLocalThreads) {
         ekeys[out + p] = skeys[p];
         ids[out + p] = sids[p];
     }
-    if (ix.head) bin_long_runs<Key>(ix, lr, skeys, sids, out, v0 >> k);
+    if (ix.head) bin_long_runs<Key>(ix, lr, med, skeys, sids, out, v0 >> k, v0);
 }
 
 // The usual bin: buckets [v0, v0 + nb) of the table's hash function.
