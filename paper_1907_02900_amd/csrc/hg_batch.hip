@@ -296,7 +296,9 @@ __global__ __launch_bounds__(kLocalThreads) void k_bheavy(
 template <typename Key, int THREADS, int ITEMS>
 __global__ __launch_bounds__(THREADS) void k_bprobe(const BTable<Key>* __restrict__ tabs,
                                                     BPrefix pre, uint32_t qtiles) {
-    const uint32_t qt = blockIdx.x;
+    // each XCD walks a contiguous range of probe tiles, so a table's
+    // offsets and keys are read through one L2
+    const uint32_t qt = xcd_map(blockIdx.x, qtiles);
     if (qt >= qtiles) return;
     const uint32_t i = find_table(pre.qtile, pre.T, qt);
     const BTable<Key>& tb = tabs[i];
@@ -319,11 +321,21 @@ __global__ __launch_bounds__(THREADS) void k_bprobe(const BTable<Key>* __restric
             lo[r] = hi[r] = 0;
         }
     }
+    // the first two keys of every bucket are loaded together (one round of
+    // overlapped random reads; at load 1 most buckets hold at most two keys),
+    // then the rest of each bucket is scanned
+    Key k0[ITEMS], k1[ITEMS];
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+        k0[r] = lo[r] < hi[r] ? tb.ekeys[lo[r]] : (Key)0;
+        k1[r] = lo[r] + 1 < hi[r] ? tb.ekeys[lo[r] + 1] : (Key)0;
+    }
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
         const uint32_t j = base + r * THREADS;
-        uint32_t c = 0;
-        for (uint32_t p = lo[r]; p < hi[r]; ++p) c += (tb.ekeys[p] == q[r]) ? 1u : 0u;
+        uint32_t c = (lo[r] < hi[r] && k0[r] == q[r]) ? 1u : 0u;
+        c += (lo[r] + 1 < hi[r] && k1[r] == q[r]) ? 1u : 0u;
+        for (uint32_t p = lo[r] + 2; p < hi[r]; ++p) c += (tb.ekeys[p] == q[r]) ? 1u : 0u;
         if (j < tb.m) tb.counts[j] = c;
     }
 }
@@ -573,9 +585,10 @@ struct BatchPlan : BatchPlanBase {
 
     hipError_t enqueue_probe(const BPrefix& pre, hipStream_t s) {
         const BTable<Key>* tabs = d_tabs;
+        const uint32_t qgrid = (uint32_t)(8 * ceil_div(qtiles, 8));
 #define HG_BPROBE(TH, IT)                                                                  \
     if (probe.threads == TH && probe.items == IT) {                                        \
-        hipLaunchKernelGGL((k_bprobe<Key, TH, IT>), dim3(qtiles), dim3(TH), 0, s, tabs, pre, \
+        hipLaunchKernelGGL((k_bprobe<Key, TH, IT>), dim3(qgrid), dim3(TH), 0, s, tabs, pre, \
                            qtiles);                                                        \
         return hipGetLastError();                                                          \
     }
