@@ -559,7 +559,8 @@ typedef struct hg_server_stats {
     double busy_s;            /* first submission -> last completion           */
     uint64_t resident_bytes, peak_bytes;
     uint32_t resident_tables;
-    uint32_t reserved;
+    uint32_t held_requests;   /* request records not yet released (see
+                                 hg_server_wait / hg_server_drain)             */
 } hg_server_stats;
 
 /* Start a server on the current device (opts may be NULL). */
@@ -568,7 +569,9 @@ hg_status hg_server_create(const hg_server_opts *opts, hg_server **out);
 /* Queue a build of n keys (device pointer, must stay valid until the request
  * completes).  *table_id names the table for later probes; *request_id (may
  * be NULL) can be waited on.  A table larger than the whole budget fails with
- * HG_ERR_BUDGET (reported by hg_server_wait). */
+ * HG_ERR_BUDGET (reported by hg_server_wait).  A request submitted with
+ * request_id NULL keeps no record after it completes; otherwise its record
+ * (status) is kept until hg_server_wait or hg_server_drain releases it. */
 hg_status hg_server_submit_build(hg_server *s, const void *d_keys, uint64_t n, int key_bits,
                                  uint64_t hash_range, uint64_t seed, uint64_t *table_id,
                                  uint64_t *request_id);
@@ -581,10 +584,12 @@ hg_status hg_server_submit_probe(hg_server *s, uint64_t table_id, const void *d_
                                  uint64_t m, uint32_t *d_counts, uint64_t *request_id);
 
 /* Block until a request has completed; *result (may be NULL) receives its
- * status. */
+ * status.  The request's record is then released: a second wait on the same
+ * id (or a wait after hg_server_drain) returns HG_ERR_NOT_FOUND. */
 hg_status hg_server_wait(hg_server *s, uint64_t request_id, hg_status *result);
 
-/* Block until every submitted request has completed. */
+/* Block until every submitted request has completed, then release the
+ * records of all completed requests. */
 hg_status hg_server_drain(hg_server *s);
 
 /* The CSR arrays of a resident, built table (device pointers owned by the

@@ -953,6 +953,7 @@ struct STable {
     bool enqueued = false;   // build launched
     bool built = false;      // build completed
     bool failed = false;
+    bool accounted = false;  // bytes counted in the server's resident total
     int stream = -1;         // stream of the build
 };
 
@@ -966,6 +967,7 @@ struct SReq {
     double t_arrive = 0, t_done = 0;
     hg_status status = HG_OK;
     bool done = false;
+    bool keep = true;  // record kept after completion until waited on or drained
 };
 
 struct Launch {
@@ -988,6 +990,7 @@ struct Server {
     std::unordered_map<uint64_t, SReq> reqs;
     std::unordered_map<uint64_t, STable> tables;
     std::vector<Launch> inflight;
+    uint32_t admitting = 0;  // groups taken off `pending` whose launch is not yet in `inflight`
     std::vector<hipStream_t> streams;
     std::vector<std::pair<void*, size_t>> pinned_free;
     std::vector<hipEvent_t> event_pool;
@@ -1072,16 +1075,15 @@ struct Server {
                 }
             }
             if (!victim) return false;
-            STable& t = tables[victim];
-            free_table(t, streams[0]);
-            if (t.ready) event_pool.push_back(t.ready);
-            resident -= t.bytes;
-            tables.erase(victim);
+            drop_table(tables.find(victim));
             ++evictions;
         }
         return true;
     }
 
+    // Complete a request (under the lock).  A record that no caller can
+    // wait on is released here; a table whose build failed is released once
+    // no pending request names it.
     void finish_req(uint64_t rid, hg_status st, double t) {
         SReq& r = reqs[rid];
         r.status = st;
@@ -1096,6 +1098,7 @@ struct Server {
                 tb.failed = st != HG_OK;
             }
             tb.last_use = ++clock;
+            if (tb.failed && tb.pins == 0) drop_table(it);
         }
         if (st == HG_OK) {
             ++completed;
@@ -1105,6 +1108,17 @@ struct Server {
         } else {
             ++failed;
         }
+        if (!r.keep) reqs.erase(rid);
+    }
+
+    // Free a table's memory and forget it (under the lock; no request may
+    // still need it).
+    void drop_table(std::unordered_map<uint64_t, STable>::iterator it) {
+        STable& t = it->second;
+        free_table(t, streams[t.stream >= 0 ? t.stream : 0]);
+        if (t.ready) event_pool.push_back(t.ready);
+        if (t.accounted) resident -= t.bytes;
+        tables.erase(it);
     }
 
     // Finish the launches whose events have completed.  The events are
@@ -1169,7 +1183,8 @@ struct Server {
                 if (r.kind == r0.kind && r.key_bits == r0.key_bits && small(r)) {
                     if (r.kind == 1) {
                         auto it = tables.find(r.table);
-                        if (it == tables.end() || !it->second.enqueued) continue;
+                        if (it == tables.end() || !it->second.enqueued || it->second.failed)
+                            continue;
                     }
                     group.push_back(pending[j]);
                 }
@@ -1189,74 +1204,89 @@ struct Server {
         // memory: new tables (builds) plus workspace
         uint64_t need_tables = 0, ws = 0;
         const int kb = r0.key_bits;
-        uint64_t merged_ws = 0;
         // merged launches carry descriptors + workspace in one block
         BatchPlan<uint32_t> p32;
         BatchPlan<uint64_t> p64;
-        std::vector<hg_batch_item> items;
-        if (group.size() > 1) {
-            if (r0.kind == 0) {
-                for (uint64_t rid : group) {
-                    const SReq& r = reqs[rid];
-                    const STable& t = tables[r.table];
-                    hg_batch_item it{};
-                    it.d_keys = r.data;
-                    it.n = r.count;
-                    it.hash_range = t.V;
-                    it.seed = t.seed;
-                    items.push_back(it);
-                }
-                // output pointers are filled after allocation
-                if (kb == 32) {
-                    if (p32.layout(items.data(), (uint32_t)items.size(), 2048) != HG_OK) group.resize(1);
-                    else merged_ws = p32.carve(nullptr);
-                } else {
-                    if (p64.layout(items.data(), (uint32_t)items.size(), 2048) != HG_OK) group.resize(1);
-                    else merged_ws = p64.carve(nullptr);
-                }
-            } else {
-                // probes of built (or launched) tables: descriptors and
-                // prefixes in one workspace block
-                merged_ws = kb == 32 ? layout_merged_probe<uint32_t>(p32, group)
-                                     : layout_merged_probe<uint64_t>(p64, group);
-                ws = merged_ws;
-            }
-        }
-        if (r0.kind == 0) {
-            // a build of its own writes the probe index and key runs; merged
-            // small builds (the batched kernels) do not
-            const bool idx = group.size() == 1;
-            for (uint64_t rid : group) {
-                STable& t = tables[reqs[rid].table];
-                t.has_index = idx;
-                t.bytes = table_bytes(t.n, t.V, t.key_bits, idx);
-                need_tables += t.bytes;
-            }
-            ws = idx ? build_ws_bytes(2, r0.count, tables[r0.table].V, kb, 0) : merged_ws;
-        }
-        if (resident + transient + need_tables + ws > o.budget_bytes) {
-            if (!evict_for(need_tables + ws)) {
-                if (inflight.empty()) {
-                    // can never fit: reject the oldest request
-                    pending.pop_front();
-                    if (r0.kind == 0) {
-                        tables[r0.table].failed = true;
-                        ++rejected;
+        for (;;) {
+            need_tables = ws = 0;
+            uint64_t merged_ws = 0;
+            if (group.size() > 1) {
+                if (r0.kind == 0) {
+                    std::vector<hg_batch_item> items;
+                    for (uint64_t rid : group) {
+                        const SReq& r = reqs[rid];
+                        const STable& t = tables[r.table];
+                        hg_batch_item it{};
+                        it.d_keys = r.data;
+                        it.n = r.count;
+                        it.hash_range = t.V;
+                        it.seed = t.seed;
+                        items.push_back(it);
                     }
-                    finish_req(rid0, HG_ERR_BUDGET, now());
-                    cv_done.notify_all();
-                    return true;
+                    // output pointers are filled after allocation
+                    const hg_status ls = kb == 32
+                        ? p32.layout(items.data(), (uint32_t)items.size(), 2048)
+                        : p64.layout(items.data(), (uint32_t)items.size(), 2048);
+                    if (ls != HG_OK) group.resize(1);
+                    else merged_ws = kb == 32 ? p32.carve(nullptr) : p64.carve(nullptr);
+                } else {
+                    // probes of built (or launched) tables: descriptors and
+                    // prefixes in one workspace block
+                    merged_ws = kb == 32 ? layout_merged_probe<uint32_t>(p32, group)
+                                         : layout_merged_probe<uint64_t>(p64, group);
+                    ws = merged_ws;
                 }
-                return false;
             }
+            if (r0.kind == 0) {
+                // a build of its own writes the probe index and key runs;
+                // merged small builds (the batched kernels) do not
+                const bool idx = group.size() == 1;
+                for (uint64_t rid : group) {
+                    STable& t = tables[reqs[rid].table];
+                    t.has_index = idx;
+                    t.bytes = table_bytes(t.n, t.V, t.key_bits, idx);
+                    need_tables += t.bytes;
+                }
+                ws = idx ? build_ws_bytes(2, r0.count, tables[r0.table].V, kb, 0) : merged_ws;
+            }
+            const uint64_t need = need_tables + ws;
+            if (resident + transient + need <= o.budget_bytes) break;
+            // evict least recently used tables only if that makes room
+            uint64_t evictable = 0;
+            for (auto& kv : tables)
+                if (kv.second.pins == 0 && kv.second.built) evictable += kv.second.bytes;
+            if (need <= o.budget_bytes && resident + transient - evictable + need <= o.budget_bytes) {
+                if (!evict_for(need)) return false;
+                break;
+            }
+            // a merged group that does not fit falls back to its oldest request
+            if (group.size() > 1) {
+                group.resize(1);
+                continue;
+            }
+            // larger than the whole budget, or nothing running will free
+            // memory: reject; otherwise wait for running launches
+            if (need > o.budget_bytes || (inflight.empty() && !admitting)) {
+                pending.pop_front();
+                if (r0.kind == 0) {
+                    tables[r0.table].failed = true;
+                    ++rejected;
+                }
+                finish_req(rid0, HG_ERR_BUDGET, now());
+                cv_done.notify_all();
+                return true;
+            }
+            return false;
         }
-        // remove the group from pending
+        // remove the group from pending; until its launch is published (or
+        // has failed) `admitting` keeps hg_server_drain waiting for it
         for (uint64_t rid : group)
             for (size_t j = 0; j < pending.size(); ++j)
                 if (pending[j] == rid) {
                     pending.erase(pending.begin() + j);
                     break;
                 }
+        ++admitting;
         Launch L;
         L.reqs = group;
         L.seq = next_seq++;
@@ -1284,6 +1314,7 @@ struct Server {
             for (STable* t : gtab) {
                 tbytes.push_back(carve_table(*t, nullptr));
                 resident += t->bytes;
+                t->accounted = true;
                 t->stream = L.stream;
             }
         if (ws) {
@@ -1354,6 +1385,7 @@ struct Server {
         if (e == hipSuccess) e = hipEventRecord(L.ev, s);
         if (e != hipSuccess) (void)hipStreamSynchronize(s);
         lk.lock();
+        --admitting;
         // other workers admit probes of these tables from now on (their
         // arrays were written before the lock was taken again)
         if (e == hipSuccess && rq0.kind == 0)
@@ -1514,6 +1546,7 @@ hg_status hg_server_submit_build(hg_server* h, const void* d_keys, uint64_t n, i
     r.data = d_keys;
     r.count = n;
     r.key_bits = key_bits;
+    r.keep = request_id != nullptr;
     r.t_arrive = s.now();
     if (s.first_arrive < 0) s.first_arrive = r.t_arrive;
     s.pending.push_back(rid);
@@ -1541,6 +1574,7 @@ hg_status hg_server_submit_probe(hg_server* h, uint64_t table_id, const void* d_
     r.count = m;
     r.key_bits = it->second.key_bits;
     r.counts = d_counts;
+    r.keep = request_id != nullptr;
     r.t_arrive = s.now();
     if (s.first_arrive < 0) s.first_arrive = r.t_arrive;
     s.pending.push_back(rid);
@@ -1553,10 +1587,16 @@ hg_status hg_server_wait(hg_server* h, uint64_t request_id, hg_status* result) {
     if (!h) return HG_ERR_INVALID_ARG;
     hg::srv::Server& s = h->s;
     std::unique_lock<std::mutex> lk(s.mu);
+    if (s.reqs.find(request_id) == s.reqs.end()) return HG_ERR_NOT_FOUND;
+    // another waiter (or a drain) may release the record meanwhile
+    s.cv_done.wait(lk, [&] {
+        auto f = s.reqs.find(request_id);
+        return f == s.reqs.end() || f->second.done;
+    });
     auto it = s.reqs.find(request_id);
     if (it == s.reqs.end()) return HG_ERR_NOT_FOUND;
-    s.cv_done.wait(lk, [&] { return s.reqs[request_id].done; });
-    if (result) *result = s.reqs[request_id].status;
+    if (result) *result = it->second.status;
+    s.reqs.erase(it);
     return HG_OK;
 }
 
@@ -1564,7 +1604,11 @@ hg_status hg_server_drain(hg_server* h) {
     if (!h) return HG_ERR_INVALID_ARG;
     hg::srv::Server& s = h->s;
     std::unique_lock<std::mutex> lk(s.mu);
-    s.cv_done.wait(lk, [&] { return s.pending.empty() && s.inflight.empty(); });
+    s.cv_done.wait(lk, [&] { return s.pending.empty() && s.inflight.empty() && !s.admitting; });
+    // every request has completed: release the records
+    for (auto it = s.reqs.begin(); it != s.reqs.end();)
+        it = it->second.done ? s.reqs.erase(it) : std::next(it);
+    s.cv_done.notify_all();
     return HG_OK;
 }
 
@@ -1642,6 +1686,7 @@ hg_status hg_server_stats_get(hg_server* h, hg_server_stats* out) {
     for (auto& kv : s.tables)
         if (kv.second.built) ++nt;
     r.resident_tables = nt;
+    r.held_requests = s.reqs.size() > 0xffffffffull ? 0xffffffffu : (uint32_t)s.reqs.size();
     *out = r;
     return HG_OK;
 }

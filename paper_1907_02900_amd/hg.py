@@ -732,7 +732,7 @@ class ServerStats(ctypes.Structure):
                 ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
                 ("max_ms", ctypes.c_double), ("busy_s", ctypes.c_double),
                 ("resident_bytes", ctypes.c_uint64), ("peak_bytes", ctypes.c_uint64),
-                ("resident_tables", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("resident_tables", ctypes.c_uint32), ("held_requests", ctypes.c_uint32)]
 
 
 def _server_sig():
@@ -772,29 +772,36 @@ class Server:
         h = ctypes.c_void_p()
         _check(L.hg_server_create(ctypes.byref(o), ctypes.byref(h)), "hg_server_create")
         self._h = h
-        self._keep = {}
+        self._keep = {}  # tensors the device still reads, until their request completes
         self._meta = {}
+        self._seq = 0
 
-    def submit_build(self, keys: torch.Tensor, hash_range: int, seed: int = 0):
+    def submit_build(self, keys: torch.Tensor, hash_range: int, seed: int = 0, want_id=True):
+        """(table_id, request_id).  With want_id False the request keeps no
+        record after it completes (request_id None: it cannot be waited on;
+        drain() waits for it)."""
         keys = _dev_keys(keys)
         tid, rid = ctypes.c_uint64(0), ctypes.c_uint64(0)
         _check(_server_sig().hg_server_submit_build(
             self._h, _ptr(keys), keys.numel(), _key_bits(keys), int(hash_range),
-            int(seed) & (2**64 - 1), ctypes.byref(tid), ctypes.byref(rid)), "hg_server_submit_build")
-        self._keep[rid.value] = (keys,)
+            int(seed) & (2**64 - 1), ctypes.byref(tid), ctypes.byref(rid) if want_id else None),
+            "hg_server_submit_build")
+        self._hold(rid.value if want_id else None, (keys,))
         self._meta[tid.value] = (keys.numel(), int(hash_range), _key_bits(keys))
-        return tid.value, rid.value
+        return tid.value, (rid.value if want_id else None)
 
-    def submit_probe(self, table_id: int, queries: torch.Tensor, counts: torch.Tensor = None):
+    def submit_probe(self, table_id: int, queries: torch.Tensor, counts: torch.Tensor = None,
+                     want_id=True):
+        """(request_id, counts); request_id is None with want_id False."""
         queries = _dev_keys(queries)
         if counts is None:
             counts = _u32(max(queries.numel(), 1), queries.device)
         rid = ctypes.c_uint64(0)
         _check(_server_sig().hg_server_submit_probe(
             self._h, int(table_id), _ptr(queries), queries.numel(), _ptr(counts),
-            ctypes.byref(rid)), "hg_server_submit_probe")
-        self._keep[rid.value] = (queries, counts)
-        return rid.value, counts
+            ctypes.byref(rid) if want_id else None), "hg_server_submit_probe")
+        self._hold(rid.value if want_id else None, (queries, counts))
+        return (rid.value if want_id else None), counts
 
     def wait(self, request_id: int) -> int:
         st = ctypes.c_int(0)
@@ -802,6 +809,13 @@ class Server:
                "hg_server_wait")
         self._keep.pop(int(request_id), None)
         return int(st.value)
+
+    def _hold(self, rid, tensors):
+        # a request without an id is held under a negative key until drain()
+        if rid is None:
+            self._seq += 1
+            rid = -self._seq
+        self._keep[rid] = tensors
 
     def drain(self):
         _check(_server_sig().hg_server_drain(self._h), "hg_server_drain")

@@ -148,3 +148,60 @@ def test_server_options_validated(hg):
         with pytest.raises(hg.HGError) as e:
             hg.Server(**kw)
         assert e.value.status == hg.HG_ERR_INVALID_ARG
+
+
+def test_request_records_released(hg):
+    # one stream, one launch in flight: requests complete in submission order
+    srv = hg.Server(streams=1, max_inflight=1, merge_max=1)
+    k_np = workloads.uniform_keys(30000, 32, seed=21)
+    q_np = workloads.probe_queries(k_np, 5000, 0.5, seed=22)
+    dk, dq = hg.to_device(k_np), hg.to_device(q_np)
+    tid, _ = srv.submit_build(dk, 30000, 4, want_id=False)
+    outs = [srv.submit_probe(tid, dq, want_id=False)[1] for _ in range(3)]
+    rid, c = srv.submit_probe(tid, dq)
+    assert srv.wait(rid) == hg.HG_OK
+    # the id-less requests left no record; the waited one was released
+    assert srv.stats()["held_requests"] == 0
+    with pytest.raises(hg.HGError) as e:
+        srv.wait(rid)
+    assert e.value.status == hg.HG_ERR_NOT_FOUND
+    exp = oracle.probe_counts(k_np, q_np)[0]
+    for x in outs + [c]:
+        assert np.array_equal(hg.to_numpy(x[:q_np.size], np.uint32), exp)
+    # records with ids are kept until drain releases them
+    rids = [srv.submit_probe(tid, dq)[0] for _ in range(4)]
+    srv.drain()
+    assert srv.stats()["held_requests"] == 0
+    with pytest.raises(hg.HGError) as e:
+        srv.wait(rids[0])
+    assert e.value.status == hg.HG_ERR_NOT_FOUND
+    st = srv.stats()
+    assert st["completed"] == 9 and st["failed"] == 0
+    srv.close()
+
+
+def test_failed_build_releases_its_table(hg):
+    # a build larger than the budget fails; its table is forgotten, probes
+    # queued behind it fail, and the budget accounting is unchanged
+    srv = hg.Server(budget_bytes=4_000_000, streams=1, max_inflight=1, merge_max=1)
+    small = hg.to_device(workloads.uniform_keys(20000, 32, seed=31))
+    tid_ok, rid = srv.submit_build(small, 20000, 1)
+    assert srv.wait(rid) == hg.HG_OK
+    before = srv.stats()["resident_bytes"]
+    big = hg.to_device(workloads.uniform_keys(500000, 32, seed=32))  # about 20 MB
+    tid_big, rid_big = srv.submit_build(big, 500000, 2)
+    try:
+        rid_p, _ = srv.submit_probe(tid_big, big[:100])
+    except hg.HGError as e:  # the build was already rejected
+        assert e.status == hg.HG_ERR_NOT_FOUND
+        rid_p = None
+    assert srv.wait(rid_big) == hg.HG_ERR_BUDGET
+    if rid_p is not None:
+        assert srv.wait(rid_p) == hg.HG_ERR_NOT_FOUND
+    with pytest.raises(hg.HGError) as e:
+        srv.submit_probe(tid_big, big[:100])
+    assert e.value.status == hg.HG_ERR_NOT_FOUND
+    st = srv.stats()
+    assert st["resident_bytes"] == before and st["resident_tables"] == 1
+    assert srv.export(tid_ok) is not None and srv.export(tid_big) is None
+    srv.close()
