@@ -370,17 +370,19 @@ __device__ __forceinline__ void wave_sort_pairs(Key& k, uint32_t& p) {
     }
 }
 
-// Buckets whose index entry is built by one lane: up to 8 entries (a few
-// overlapped LDS reads).  Longer ones up to kRunBucket entries -- common only
-// when keys repeat many times -- are listed and built by a whole wave
-// (bin_medium_heads) instead of one lane walking them in dependent rounds.
+// Buckets whose index entry is built by one lane: up to 16 entries (rounds
+// of four overlapped LDS reads).  Longer ones up to kRunBucket entries --
+// common only when keys repeat many times -- are listed and built by groups
+// of 32 lanes (bin_medium_heads) instead of one lane walking them in up to
+// eight rounds.  (Groups of 16 lanes for buckets of 9-16 entries were faster
+// only when keys repeat about 16 times, and slower below that.)
 template <typename Key>
-constexpr uint32_t head_lane_max() { return 8u; }
+constexpr uint32_t head_lane_max() { return 16u; }
 
 // A bucket's probe index entry, or its place in one of the bin's lists: the
 // long buckets (more than kRunBucket entries; their entries are written with
-// their key runs) and the medium ones (their entries are written a wave per
-// bucket), med[] packing lo | len << 13 | v << 19 (v = local bucket).  k
+// their key runs) and the medium ones (their entries are written by lane
+// groups), med[] packing lo | len << 13 | v << 19 (v = local bucket).  k
 // points at the bucket's first key in LDS.
 template <typename Key>
 __device__ __forceinline__ void note_bucket(const IndexOut& ix, const LongLds<Key>& lr,
@@ -399,36 +401,72 @@ __device__ __forceinline__ void note_bucket(const IndexOut& ix, const LongLds<Ke
     }
 }
 
+// OR over each row of 16 lanes, left in the row's last lane (lanes 15, 31,
+// 47, 63): four DPP row shifts (a lane shifted in from outside the row reads
+// 0).  Whole wave.
+__device__ __forceinline__ uint32_t row_or16(uint32_t f) {
+    f |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)f, 0x111, 0xf, 0xf, false);  // row_shr:1
+    f |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)f, 0x112, 0xf, 0xf, false);  // row_shr:2
+    f |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)f, 0x114, 0xf, 0xf, false);  // row_shr:4
+    f |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)f, 0x118, 0xf, 0xf, false);  // row_shr:8
+    return f;
+}
+
+// The OR of group g's lanes (groups of G = 16 or 32 lanes), from the rows'
+// ORs; uniform values, selected per lane.
+template <uint32_t G>
+__device__ __forceinline__ uint32_t group_or(uint32_t f, uint32_t g) {
+    const uint32_t r = row_or16(f);
+    const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)r, 15);
+    const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)r, 31);
+    const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)r, 47);
+    const uint32_t d = (uint32_t)__builtin_amdgcn_readlane((int)r, 63);
+    if constexpr (G == 16) return g == 0 ? a : g == 1 ? b : g == 2 ? c : d;
+    else return g == 0 ? (a | b) : (c | d);
+}
+
+// Index entries of the medium buckets in list[0, n), whose lengths are at
+// most G: each wave takes 64 / G buckets at a time, lane s of group g holding
+// key s of its bucket; the first key's count is a ballot and the filter an
+// OR over the group -- the same entry head_entry builds with one lane.
+template <typename Key, uint32_t G>
+__device__ __forceinline__ void medium_heads_by(const IndexOut& ix, const uint32_t* list,
+                                                uint32_t n, const Key* skeys, uint32_t out,
+                                                uint32_t v0) {
+    constexpr uint32_t PER = kWave / G;
+    const uint32_t w = threadIdx.x / kWave, lane = lane_id();
+    const uint32_t g = lane / G, s = lane % G;
+    for (uint32_t j0 = w * PER; j0 < n; j0 += W_LOCAL * PER) {  // uniform per wave
+        const uint32_t j = j0 + g;
+        const bool have = j < n;
+        const uint32_t e = have ? list[j] : 0u;
+        const uint32_t lo = e & 0x1fffu, len = (e >> 13) & 0x3fu, v = e >> 19;
+        const bool in = have && s < len;
+        const Key k0 = skeys[lo];
+        const Key kx = in ? skeys[lo + s] : k0;
+        if constexpr (sizeof(Key) == 4) {
+            const uint64_t eq = ballot(in && kx == k0);
+            const uint32_t c0 = (uint32_t)__popcll((eq >> (g * G)) & ((1ull << G) - 1ull));
+            const uint32_t f =
+                group_or<G>((in && kx != k0) ? (1u << filter_bit((uint32_t)kx)) : 0u, g);
+            if (have && s == 0) ix.head[v0 + v] = make_uint4(len, out + lo, (uint32_t)k0, c0 | f << 8);
+        } else {
+            const uint64_t z = in ? filter_bits64((uint64_t)kx) : 0ull;
+            const uint32_t zl = group_or<G>((uint32_t)z, g), zh = group_or<G>((uint32_t)(z >> 32), g);
+            if (have && s == 0) ix.head[v0 + v] = make_uint4(len, out + lo, zl, zh);
+        }
+    }
+}
+
 // Index entries of the bin's medium buckets (more than head_lane_max and at
-// most kRunBucket entries), one wave per bucket: lane i holds the bucket's
-// key i; the first key's count is a ballot and the filter an OR over the
-// lanes -- the same entry head_entry builds with one lane.  Called by whole
-// waves after a barrier that follows the lists' construction.
+// most kRunBucket entries).  Called by whole waves after a barrier that
+// follows the list's construction.
 template <typename Key>
 __device__ __forceinline__ void bin_medium_heads(const IndexOut& ix, const LongLds<Key>& lr,
                                                  const uint32_t* med, const Key* skeys,
                                                  uint32_t out, uint32_t v0) {
-    const uint32_t nm = lr.cnt[2];
-    const uint32_t w = threadIdx.x / kWave, lane = lane_id();
-    for (uint32_t j = w; j < nm; j += W_LOCAL) {
-        const uint32_t e = med[j];
-        const uint32_t lo = e & 0x1fffu, len = (e >> 13) & 0x3fu, v = e >> 19;
-        const bool in = lane < len;
-        const Key k0 = skeys[lo];
-        const Key kx = in ? skeys[lo + lane] : k0;
-        if constexpr (sizeof(Key) == 4) {
-            const uint32_t c0 = (uint32_t)__popcll(ballot(in && kx == k0));
-            uint32_t f = (in && kx != k0) ? (1u << filter_bit((uint32_t)kx)) : 0u;
-#pragma unroll
-            for (int d = kWave / 2; d >= 1; d >>= 1) f |= (uint32_t)__shfl_xor((int)f, d, kWave);
-            if (lane == 0) ix.head[v0 + v] = make_uint4(len, out + lo, (uint32_t)k0, c0 | f << 8);
-        } else {
-            uint64_t z = in ? filter_bits64((uint64_t)kx) : 0ull;
-#pragma unroll
-            for (int d = kWave / 2; d >= 1; d >>= 1) z |= __shfl_xor(z, d, kWave);
-            if (lane == 0) ix.head[v0 + v] = make_uint4(len, out + lo, (uint32_t)z, (uint32_t)(z >> 32));
-        }
-    }
+    static_assert(kRunBucket <= 32u, "a medium bucket fits a group of 32 lanes");
+    medium_heads_by<Key, 32>(ix, med, lr.cnt[2], skeys, out, v0);
 }
 
 // Key runs of the long buckets of a bin held in LDS (skeys / sids in bucket
@@ -553,6 +591,7 @@ __device__ __forceinline__ void light_bin_body_by(const Key* __restrict__ src_ke
     uint16_t* sb = (uint16_t*)(sids + kLightCap);
     // the bucket sort's scratch holds the list of medium buckets afterwards
     // (at most kLightCap / (head_lane_max + 1) of them; room for kLightCap / 2)
+    static_assert(kLightCap <= 8192u, "a medium-list entry holds lo in 13 bits");
     uint32_t* med = (uint32_t*)sb;
     uint32_t* cnt = (uint32_t*)(sb + kLightCap);  // NB
     uint32_t* wcnt = cnt + NB;                     // W * 64

@@ -275,6 +275,25 @@ def test_probe_index_on_and_off_agree_with_oracle(hg, kb, kind, n, V):
             assert np.array_equal(hg.to_numpy(b, np.uint32), eb)
 
 
+@pytest.mark.parametrize("kb", [32, 64])
+@pytest.mark.parametrize("R", [8.0, 16.0, 32.0])
+def test_probe_index_of_medium_buckets(hg, kb, R):
+    # keys repeated about R times, V = n (the appearances sweep's shape):
+    # buckets of 9-16 and 17-32 entries get their index entries from groups
+    # of 16 and 32 lanes; stable and any-order builds
+    say("medium buckets", kb, R)
+    n = 400003
+    k = workloads.duplicate_keys(n, R, kb, seed=71)
+    q = workloads.probe_queries(k, 300001, 0.5, seed=72, key_bits=kb)
+    exp, etot = oracle.probe_counts(k, q, kb)
+    dk, dq = hg.to_device(k), hg.to_device(q)
+    for any_order in (False, True):
+        t = hg.hg_build(dk, n, seed=73, any_order=any_order)
+        c, tot = hg.hg_probe(t, dq, counts=True, total=True)
+        assert np.array_equal(hg.to_numpy(c, np.uint32), exp), any_order
+        assert tot == etot
+
+
 def test_probe_index_follows_rebuilds(hg):
     # one table object rebuilt with the index, without it, and with it again
     # under other keys and ranges: a probe never sees a stale index
