@@ -296,7 +296,10 @@ hg_status hg_table_erase(hg_table *t, const void *d_keys, uint64_t m, uint64_t *
 hg_status hg_table_lengths(const hg_table *t, const uint32_t **d_lengths, uint64_t *live);
 
 /* Release a table (waits for the device to finish using it).  NULL is a
- * no-op. */
+ * no-op.  Like every call here that frees device memory (hg_collection_free,
+ * hg_batch_free, hg_server_destroy), it must not run while a stream of the
+ * device is being captured into a graph: the free synchronises, which ends
+ * such a capture with an error. */
 void hg_table_free(hg_table *t);
 
 /* ------------------------------------------------------------------------

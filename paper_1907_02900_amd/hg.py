@@ -27,6 +27,41 @@ NOALLOC_MAX_QUERIES = 1 << 22
 VARIANT_AUTO, VARIANT_V1, VARIANT_V2 = 0, 1, 2
 
 
+# Releases that arrived while the current stream was being captured into a
+# graph.  Freeing device memory synchronises, which would invalidate the
+# capture (a Table dropped by the garbage collector in the middle of someone's
+# torch.cuda.graph block), so such releases wait for the next release made
+# outside a capture.
+_deferred = []
+
+
+def _capturing() -> bool:
+    try:
+        return torch.cuda.is_available() and torch.cuda.is_current_stream_capturing()
+    except Exception:
+        return False
+
+
+def _release(fn, handle):
+    """Run fn(handle) now, or later if a stream capture is in progress."""
+    if _capturing():
+        _deferred.append((fn, handle))
+        return
+    while _deferred:
+        f, h = _deferred.pop()
+        f(h)
+    fn(handle)
+
+
+def flush_deferred_releases():
+    """Free the objects whose release was deferred during a stream capture
+    (no-op while capturing)."""
+    if not _capturing():
+        while _deferred:
+            f, h = _deferred.pop()
+            f(h)
+
+
 class HGError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = int(status)
@@ -313,7 +348,7 @@ class Table:
 
     def free(self):
         if self._h is not None and self._h.value:
-            lib().hg_table_free(self._h)
+            _release(lib().hg_table_free, self._h)
         self._h = None
 
     def __del__(self):
@@ -538,7 +573,7 @@ class Collection:
 
     def free(self):
         if self._h is not None and self._h.value:
-            _coll_sig().hg_collection_free(self._h)
+            _release(_coll_sig().hg_collection_free, self._h)
         self._h = None
 
     def __del__(self):
@@ -705,7 +740,7 @@ class Batch:
 
     def free(self):
         if self._h is not None and self._h.value:
-            _batch_sig().hg_batch_free(self._h)
+            _release(_batch_sig().hg_batch_free, self._h)
         self._h = None
 
     def __del__(self):
@@ -846,9 +881,11 @@ class Server:
 
     def close(self):
         if self._h is not None and self._h.value:
-            _server_sig().hg_server_destroy(self._h)
+            # the tensors stay referenced until the server has finished
+            keep = self._keep
+            _release(lambda h: (_server_sig().hg_server_destroy(h), keep.clear()), self._h)
         self._h = None
-        self._keep.clear()
+        self._keep = {}
 
     def __del__(self):
         try:

@@ -95,3 +95,33 @@ def test_indexed_build_and_probe_replay_from_a_graph(hg, kb, kind, n, V, any_ord
     assert tot == et and np.array_equal(p[o], ep) and np.array_equal(b[o], eb)
     del g
     t.free()
+
+
+def test_table_dropped_during_capture_is_freed_after(hg):
+    # a table whose last reference goes away inside a torch.cuda.graph block
+    # (as when the garbage collector runs there) is not freed during the
+    # capture: freeing device memory would invalidate it
+    n = 50000
+    keys = workloads.uniform_keys(n, 32, seed=81)
+    q = workloads.probe_queries(keys, n, 0.5, seed=82)
+    dk, dq = hg.to_device(keys), hg.to_device(q)
+    t = hg.Table.create(n, n, 32)
+    counts = torch.empty(n, dtype=torch.int32, device="cuda")
+    t.rebuild(dk, n, seed=5)
+    hg.hg_probe(t, dq, counts=True, out=counts)
+    doomed = hg.hg_build(hg.to_device(workloads.uniform_keys(1000, 32, seed=83)), 1000)
+    torch.cuda.synchronize()
+    before = len(hg._deferred)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        t.rebuild(dk, n, seed=5)
+        del doomed
+        hg.hg_probe(t, dq, counts=True, out=counts)
+    assert len(hg._deferred) == before + 1
+    counts.fill_(-1)
+    g.replay()
+    torch.cuda.synchronize()
+    assert np.array_equal(hg.to_numpy(counts, np.uint32), oracle.probe_counts(keys, q)[0])
+    hg.flush_deferred_releases()
+    assert not hg._deferred
+    t.free()
