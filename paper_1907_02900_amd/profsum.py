@@ -18,7 +18,14 @@ Two commands, both reading what ``rocprofv3 -d DIR -o run`` wrote:
     16-byte read, raw and scaled.  The JSON carries the digest of the kernel sources it was
     taken on; bench.py reports the traffic only while that digest matches.
 
-Usage: python3 -m paper_1907_02900_amd.profsum trace|traffic ...
+``counters DB [DB ...] --title T --cmd C``
+    Markdown table of the SQ (shader sequencer) counters of the step's
+    kernels from one or more ``--pmc`` runs (per kernel, the mean over its
+    dispatches; a counter present in several runs keeps the last run's), with
+    the share of wave time spent waiting and per-wave VALU, LDS and LDS
+    bank-conflict cycles.
+
+Usage: python3 -m paper_1907_02900_amd.profsum trace|traffic|counters ...
 """
 import argparse
 import collections
@@ -123,6 +130,43 @@ def cmd_traffic(a):
     print(json.dumps(res, indent=1))
 
 
+SQ_COLS = ["SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_WAIT_ANY", "SQ_WAIT_INST_LDS",
+           "SQ_INSTS_LDS", "SQ_ACTIVE_INST_LDS", "SQ_LDS_BANK_CONFLICT", "SQ_ACTIVE_INST_VALU"]
+SQ_KERNELS = ("k_tile_hist", "k_tile_partition", "k_local_light", "k_probe_count")
+
+
+def cmd_counters(a):
+    rows = collections.OrderedDict()
+    for db in a.dbs:
+        c = sqlite3.connect(db)
+        agg = collections.defaultdict(lambda: collections.defaultdict(list))
+        for name, cn, cv in c.execute("select name, counter_name, counter_value from pmc_events"):
+            if any(k in name for k in SQ_KERNELS):
+                agg[short_name(name)][cn].append(cv)
+        for k in sorted(agg):
+            rows.setdefault(k, {}).update({cn: sum(v) / len(v) for cn, v in agg[k].items()})
+    cols = [c for c in SQ_COLS if any(c in d for d in rows.values())]
+    out = ["# %s" % a.title, "", "Commands (from the repository root, one MI355X):", "",
+           "    %s" % a.cmd, "",
+           "Per kernel, the mean over its dispatches of each counter (as rocprofv3 reports "
+           "them; cycle counters of the sampled shader engines).  wait = SQ_WAIT_ANY / "
+           "SQ_WAVE_CYCLES; per wave = counter / SQ_WAVES.", "",
+           "| kernel | " + " | ".join(cols) + " | wait | per wave: VALU / LDS / LDS bank-conflict |",
+           "|---|" + "---|" * (len(cols) + 2)]
+    for k, d in rows.items():
+        w = d.get("SQ_WAVES", 0) or 1
+        wait = d.get("SQ_WAIT_ANY", 0) / (d.get("SQ_WAVE_CYCLES", 0) or 1)
+        out.append("| %s | %s | %.2f | %.0f / %.0f / %.0f |" % (
+            k, " | ".join("%.0f" % d.get(c, 0) for c in cols), wait,
+            d.get("SQ_ACTIVE_INST_VALU", 0) / w, d.get("SQ_ACTIVE_INST_LDS", 0) / w,
+            d.get("SQ_LDS_BANK_CONFLICT", 0) / w))
+    text = "\n".join(out) + "\n"
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write(text)
+    sys.stdout.write(text)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(prog="profsum")
     sub = ap.add_subparsers(dest="what", required=True)
@@ -138,6 +182,12 @@ def main(argv=None):
     p.add_argument("--rand-fetch", dest="rand_fetch", default=None)
     p.add_argument("--rand-accesses", dest="rand_accesses", type=int, default=1 << 27)
     p.set_defaults(fn=cmd_traffic)
+    q = sub.add_parser("counters")
+    q.add_argument("dbs", nargs="+")
+    q.add_argument("--title", required=True)
+    q.add_argument("--cmd", required=True)
+    q.add_argument("--out")
+    q.set_defaults(fn=cmd_counters)
     a = ap.parse_args(argv)
     a.fn(a)
 
