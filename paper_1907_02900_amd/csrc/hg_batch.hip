@@ -193,6 +193,16 @@ __global__ __launch_bounds__(kPartThreads) void k_bpart(const BTable<Key>* __res
         const uint32_t e = wbase + r * kWave + lane;
         k[r] = (e < cnt) ? tb.keys[begin + e] : (Key)0;
     }
+    // the tile's digit bases, loaded now so that their latency overlaps the
+    // ranking (D <= 2048: at most kRowPer per thread)
+    constexpr int kRowPer = (1 << kMaxDigitBits) / kPartThreads;
+    const uint32_t* row = mat + tb.mat_base + (size_t)lt * D;
+    uint32_t rowv[kRowPer];
+#pragma unroll
+    for (int j = 0; j < kRowPer; ++j) {
+        const uint32_t d = threadIdx.x + j * kPartThreads;
+        rowv[j] = d < D ? row[d] : 0u;
+    }
 #pragma unroll
     for (int r = 0; r < IT; ++r) {
         const uint32_t e = wbase + r * kWave + lane;
@@ -200,8 +210,11 @@ __global__ __launch_bounds__(kPartThreads) void k_bpart(const BTable<Key>* __res
     }
     if (STABLE) rank_stable<kPartThreads, IT>(dig, bits, wcnt, dstart, tmp, pos);
     else rank_any<kPartThreads, IT>(dig, bits, wcnt, dstart, tmp, pos);
-    const uint32_t* row = mat + tb.mat_base + (size_t)lt * D;
-    for (uint32_t d = threadIdx.x; d < D; d += kPartThreads) tbase[d] = row[d] - dstart[d];
+#pragma unroll
+    for (int j = 0; j < kRowPer; ++j) {
+        const uint32_t d = threadIdx.x + j * kPartThreads;
+        if (d < D) tbase[d] = rowv[j] - dstart[d];
+    }
 #pragma unroll
     for (int r = 0; r < IT; ++r) {
         if (dig[r] < D) {

@@ -471,15 +471,18 @@ __global__ __launch_bounds__(kCT) void k_runs_chunk_scatter(
         uint32_t l = lbase + threadIdx.x * kCItems - (o - obase);
 #pragma unroll
         for (int j = 0; j < kCItems; ++j) {
+            // a predicate rather than a break, so that the loop unrolls and
+            // x[] stays in registers
             const uint32_t e = threadIdx.x * kCItems + j;
-            if (e >= r.cl) break;
-            if (x[j] != lead) {
-                skey[r.st + o] = x[j];
-                spos[r.st + o] = r.base + e;
-                ++o;
-            } else {
-                ix.runs.kperm[r.st + nless + l] = ids[r.st + r.base + e];
-                ++l;
+            if (e < r.cl) {
+                if (x[j] != lead) {
+                    skey[r.st + o] = x[j];
+                    spos[r.st + o] = r.base + e;
+                    ++o;
+                } else {
+                    ix.runs.kperm[r.st + nless + l] = ids[r.st + r.base + e];
+                    ++l;
+                }
             }
         }
     }

@@ -249,6 +249,16 @@ __global__ __launch_bounds__(kPartThreads) void k_tile_partition(
             id[r] = 0;
         }
     }
+    // the tile's digit bases, loaded now so that their latency overlaps the
+    // ranking (D <= 2048: at most kRowPer per thread)
+    constexpr int kRowPer = (1 << kMaxDigitBits) / kPartThreads;
+    const uint32_t* row = base + (size_t)t * D;
+    uint32_t rowv[kRowPer];
+#pragma unroll
+    for (int j = 0; j < kRowPer; ++j) {
+        const uint32_t d = threadIdx.x + j * kPartThreads;
+        rowv[j] = d < D ? row[d] : 0u;
+    }
 #pragma unroll
     for (int r = 0; r < IT; ++r) {
         const uint32_t e = wbase + r * kWave + lane;
@@ -257,8 +267,11 @@ __global__ __launch_bounds__(kPartThreads) void k_tile_partition(
     }
     if (STABLE) rank_stable<kPartThreads, IT>(dig, bits, wcnt, dstart, tmp, pos);
     else rank_any<kPartThreads, IT>(dig, bits, wcnt, dstart, tmp, pos);
-    const uint32_t* row = base + (size_t)t * D;
-    for (uint32_t d = threadIdx.x; d < D; d += kPartThreads) tbase[d] = row[d] - dstart[d];
+#pragma unroll
+    for (int j = 0; j < kRowPer; ++j) {
+        const uint32_t d = threadIdx.x + j * kPartThreads;
+        if (d < D) tbase[d] = rowv[j] - dstart[d];
+    }
 #pragma unroll
     for (int r = 0; r < IT; ++r) {
         if (dig[r] < D) {
@@ -755,6 +768,7 @@ hipError_t partition_pass(const Key* src_keys, const uint32_t* src_ids, Key* dst
     const uint32_t D = 1u << bits;
     const uint32_t grid = (uint32_t)(8 * ceil_div(tiles_ub, 8));
     if (id_digit && (sizeof(Key) != 4 || !src_ids || stable)) return hipErrorInvalidValue;
+    if (bits > kMaxDigitBits) return hipErrorInvalidValue;  // the kernels hold at most 2048 digits
     {
         HG_PROF(tier == 1 ? "v2_tile_hist_t1" : "v2_tile_hist_t2", s);
         if (id_digit)
