@@ -186,6 +186,43 @@ __device__ __forceinline__ void sort_chunk_by_bucket(Key (&kk)[ITEMS], uint32_t 
         }
 }
 
+// Put the s <= 8 entries of one bucket in LDS (ids[0..s), keys[0..s)) in
+// ascending id order, in registers: load them, run Batcher's odd-even merge
+// network for 8 (19 compare-exchanges; empty places hold id 0xffffffff,
+// above every real id, and sort last), store them back.  Unlike an insertion
+// sort in LDS it has no chain of dependent LDS reads.
+template <typename Key>
+__device__ __forceinline__ void sort8_by_id(uint32_t* ids, Key* keys, uint32_t s) {
+    uint32_t a[8];
+    Key k[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        a[j] = (uint32_t)j < s ? ids[j] : 0xffffffffu;
+        k[j] = (uint32_t)j < s ? keys[j] : Key(0);
+    }
+    auto cx = [&](int i, int j) {
+        const bool sw = a[j] < a[i];
+        const uint32_t ai = sw ? a[j] : a[i], aj = sw ? a[i] : a[j];
+        const Key ki = sw ? k[j] : k[i], kj = sw ? k[i] : k[j];
+        a[i] = ai;
+        a[j] = aj;
+        k[i] = ki;
+        k[j] = kj;
+    };
+    cx(0, 1); cx(2, 3); cx(4, 5); cx(6, 7);
+    cx(0, 2); cx(1, 3); cx(4, 6); cx(5, 7);
+    cx(1, 2); cx(5, 6);
+    cx(0, 4); cx(1, 5); cx(2, 6); cx(3, 7);
+    cx(2, 4); cx(3, 5);
+    cx(1, 2); cx(3, 4); cx(5, 6);
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+        if ((uint32_t)j < s) {
+            ids[j] = a[j];
+            keys[j] = k[j];
+        }
+}
+
 // Exclusive scan of cnt[0..NB) in place (NB a power of two); returns via
 // cnt; *total gets the sum.  All threads must call it.
 __device__ __forceinline__ void scan_counts(uint32_t* cnt, uint32_t NB, uint32_t base,
@@ -621,6 +658,7 @@ __device__ __forceinline__ void light_bin_body_by(const Key* __restrict__ src_ke
     }
     for (uint32_t i = threadIdx.x; i < NB; i += kLocalThreads) cnt[i] = 0;
     if (ix.head && threadIdx.x < 3) lr.cnt[threadIdx.x] = 0;
+    if (threadIdx.x == 0) dstart[0] = 0;  // list of multi-entry buckets (stable path)
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < IT; ++r) {
@@ -645,20 +683,36 @@ __device__ __forceinline__ void light_bin_body_by(const Key* __restrict__ src_ke
         }
         __syncthreads();
         // cnt[v] is now the end of bucket v; ids are put back in ascending
-        // order inside each (short) bucket unless any order is allowed
-        for (uint32_t v = threadIdx.x; v < NB && !any_order; v += kLocalThreads) {
-            const uint32_t lo = v ? cnt[v - 1] : 0u, hi = cnt[v];
-            for (uint32_t i = lo + 1; i < hi; ++i) {
-                const uint32_t idv = sids[i];
-                const Key kv = skeys[i];
-                uint32_t j = i;
-                while (j > lo && sids[j - 1] > idv) {
-                    sids[j] = sids[j - 1];
-                    skeys[j] = skeys[j - 1];
-                    --j;
+        // order inside each (short) bucket unless any order is allowed.  The
+        // buckets of two or more entries are listed first (in the bucket
+        // sort's scratch, unused on this path: at most L / 2 of them, packed
+        // lo | len << 16), so that every lane of the sorting pass has one.
+        if (!any_order) {
+            uint32_t* multi = (uint32_t*)sb;
+            for (uint32_t v = threadIdx.x; v < NB; v += kLocalThreads) {
+                const uint32_t lo = v ? cnt[v - 1] : 0u, hi = cnt[v];
+                if (hi - lo >= 2) multi[atomicAdd(&dstart[0], 1u)] = lo | ((hi - lo) << 16);
+            }
+            __syncthreads();
+            const uint32_t nmulti = dstart[0];
+            for (uint32_t j = threadIdx.x; j < nmulti; j += kLocalThreads) {
+                const uint32_t lo = multi[j] & 0xffffu, len = multi[j] >> 16, hi = lo + len;
+                if (len <= 8) {
+                    sort8_by_id<Key>(sids + lo, skeys + lo, len);
+                    continue;
                 }
-                sids[j] = idv;
-                skeys[j] = kv;
+                for (uint32_t i = lo + 1; i < hi; ++i) {
+                    const uint32_t idv = sids[i];
+                    const Key kv = skeys[i];
+                    uint32_t j2 = i;
+                    while (j2 > lo && sids[j2 - 1] > idv) {
+                        sids[j2] = sids[j2 - 1];
+                        skeys[j2] = skeys[j2 - 1];
+                        --j2;
+                    }
+                    sids[j2] = idv;
+                    skeys[j2] = kv;
+                }
             }
         }
         __syncthreads();
