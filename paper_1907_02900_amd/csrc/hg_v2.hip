@@ -454,48 +454,85 @@ __global__ __launch_bounds__(kLocalThreads) void k_huge_hist(
     }
 }
 
-// One workgroup per split bin: bucket starts (written to offsets) and, in
-// place of each slice's counts, the position of the slice's first entry of
-// every bucket.
-__global__ __launch_bounds__(kLocalThreads) void k_huge_scan(
+// The scan over the split bins' slice histograms, in three steps so that a
+// bin of many slices is spread over many threads: per (bin, bucket) the total
+// over the bin's slices; per bin the bucket starts (written to offsets, and
+// kept in place of the totals); per (bin, bucket) the position of every
+// slice's first entry of the bucket, in place of its count.
+
+// Slices of split bin idx: [s0, s0 + ns).
+__device__ __forceinline__ uint32_t huge_slices(const uint32_t* __restrict__ bin_start,
+                                                const uint32_t* __restrict__ huge_list,
+                                                uint32_t idx) {
+    const uint32_t b = huge_list[idx];
+    return (bin_start[b + 1] - bin_start[b] + kSliceKeys - 1) / kSliceKeys;
+}
+
+__global__ __launch_bounds__(256) void k_huge_tot(
     const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ huge_list,
     const uint32_t* __restrict__ huge_s0, const uint32_t* __restrict__ ctr, uint32_t k,
-    uint32_t V, uint32_t* __restrict__ hist, uint32_t* __restrict__ offsets) {
+    uint32_t huge_cap, const uint32_t* __restrict__ hist, uint32_t* __restrict__ tot) {
+    const uint32_t NB = 1u << k, nh = ctr[1] < huge_cap ? ctr[1] : huge_cap;
+    const uint64_t all = (uint64_t)nh << k, st = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < all; x += st) {
+        const uint32_t idx = (uint32_t)(x >> k), v = (uint32_t)x & (NB - 1);
+        const uint32_t s0 = huge_s0[idx], ns = huge_slices(bin_start, huge_list, idx);
+        const uint32_t* h = hist + (size_t)s0 * NB + v;
+        uint32_t acc = 0;
+#pragma unroll 4
+        for (uint32_t sl = 0; sl < ns; ++sl) acc += h[(size_t)sl * NB];
+        tot[x] = acc;
+    }
+}
+
+__global__ __launch_bounds__(kLocalThreads) void k_huge_starts(
+    const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ huge_list,
+    const uint32_t* __restrict__ ctr, uint32_t k, uint32_t V, uint32_t huge_cap,
+    uint32_t* __restrict__ tot, uint32_t* __restrict__ offsets) {
     __shared__ uint32_t tmp[kLocalThreads / kWave + 1];
-    const uint32_t NB = 1u << k, nh = ctr[1];
+    const uint32_t NB = 1u << k, nh = ctr[1] < huge_cap ? ctr[1] : huge_cap;
     const uint32_t per = NB >= (uint32_t)kLocalThreads ? NB / kLocalThreads : 1u;  // <= 16
     const uint32_t i0 = threadIdx.x * per;
     for (uint32_t idx = blockIdx.x; idx < nh; idx += gridDim.x) {
-        const uint32_t b = huge_list[idx], s0 = huge_s0[idx];
-        const uint32_t bs = bin_start[b], L = bin_start[b + 1] - bs;
-        const uint32_t ns = (L + kSliceKeys - 1) / kSliceKeys;
+        const uint32_t b = huge_list[idx];
         const uint32_t v0 = b << k, nb = (V - v0 < NB) ? V - v0 : NB;
-        uint32_t tot[16];
+        uint32_t* t = tot + ((size_t)idx << k);
+        uint32_t c[16];
         uint32_t mine = 0;
         for (uint32_t j = 0; j < per; ++j) {
-            uint32_t acc = 0;
-            if (i0 + j < NB)
-                for (uint32_t sl = 0; sl < ns; ++sl) acc += hist[(size_t)(s0 + sl) * NB + i0 + j];
-            tot[j] = acc;
-            mine += acc;
+            c[j] = i0 + j < NB ? t[i0 + j] : 0u;
+            mine += c[j];
         }
         uint32_t all;
-        uint32_t run = bs + block_excl_scan<kLocalThreads>(mine, tmp, &all);
+        uint32_t run = bin_start[b] + block_excl_scan<kLocalThreads>(mine, tmp, &all);
         for (uint32_t j = 0; j < per; ++j) {
             const uint32_t v = i0 + j;
             if (v < NB) {
                 if (v < nb) offsets[v0 + v] = run;
-                uint32_t r = run;
-                for (uint32_t sl = 0; sl < ns; ++sl) {
-                    const size_t at = (size_t)(s0 + sl) * NB + v;
-                    const uint32_t x = hist[at];
-                    hist[at] = r;
-                    r += x;
-                }
+                t[v] = run;
             }
-            run += tot[j];
+            run += c[j];
         }
         __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_huge_down(
+    const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ huge_list,
+    const uint32_t* __restrict__ huge_s0, const uint32_t* __restrict__ ctr, uint32_t k,
+    uint32_t huge_cap, const uint32_t* __restrict__ tot, uint32_t* __restrict__ hist) {
+    const uint32_t NB = 1u << k, nh = ctr[1] < huge_cap ? ctr[1] : huge_cap;
+    const uint64_t all = (uint64_t)nh << k, st = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < all; x += st) {
+        const uint32_t idx = (uint32_t)(x >> k), v = (uint32_t)x & (NB - 1);
+        const uint32_t s0 = huge_s0[idx], ns = huge_slices(bin_start, huge_list, idx);
+        uint32_t* h = hist + (size_t)s0 * NB + v;
+        uint32_t r = tot[x];
+        for (uint32_t sl = 0; sl < ns; ++sl) {
+            const uint32_t c = h[(size_t)sl * NB];
+            h[(size_t)sl * NB] = r;
+            r += c;
+        }
     }
 }
 
@@ -680,7 +717,7 @@ struct V2Ws {
     uint32_t* rids;
     uint32_t *m1, *c1, *m2, *c2, *bin_start, *heavy_list;
     uint32_t* ctr;  // [5]: oversize bins, split bins, slices of split bins, key-run work
-    uint32_t *huge_list, *huge_s0, *slice_owner, *slice_hist;
+    uint32_t *huge_list, *huge_s0, *slice_owner, *slice_hist, *huge_tot;
     uint32_t huge_cap, slice_cap;
     uint32_t *gen_list, *gen_cnt;  // long buckets left to the general key-run pass
     void* runs_ws;
@@ -719,6 +756,7 @@ size_t layout_v2(void* ws, const V2Plan& p, size_t key_size, V2Ws* out) {
     w.huge_s0 = c.take<uint32_t>(w.huge_cap);
     w.slice_owner = c.take<uint32_t>(w.slice_cap);
     w.slice_hist = c.take<uint32_t>((size_t)w.slice_cap << p.k);
+    w.huge_tot = c.take<uint32_t>((size_t)w.huge_cap << p.k);
     w.gen_list = c.take<uint32_t>(gen_list_cap(p.n, p.bins));
     w.gen_cnt = c.take<uint32_t>((size_t)p.bins + 1);
     w.runs_ws = c.take<char>(runs_ws_bytes(p.n, p.bins));
@@ -931,9 +969,19 @@ hipError_t run_build_v2(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, 
                            (const uint32_t*)w.slice_owner, (const uint32_t*)w.ctr, hp, p.k,
                            w.slice_hist);
         HG_TRY(hipGetLastError());
-        hipLaunchKernelGGL(k_huge_scan, dim3(256), dim3(kLocalThreads), 0, s, bs,
+        hipLaunchKernelGGL(k_huge_tot, dim3(1024), dim3(256), 0, s, bs,
                            (const uint32_t*)w.huge_list, (const uint32_t*)w.huge_s0,
-                           (const uint32_t*)w.ctr, p.k, (uint32_t)V, w.slice_hist, offsets);
+                           (const uint32_t*)w.ctr, p.k, w.huge_cap,
+                           (const uint32_t*)w.slice_hist, w.huge_tot);
+        HG_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_huge_starts, dim3(256), dim3(kLocalThreads), 0, s, bs,
+                           (const uint32_t*)w.huge_list, (const uint32_t*)w.ctr, p.k,
+                           (uint32_t)V, w.huge_cap, w.huge_tot, offsets);
+        HG_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_huge_down, dim3(1024), dim3(256), 0, s, bs,
+                           (const uint32_t*)w.huge_list, (const uint32_t*)w.huge_s0,
+                           (const uint32_t*)w.ctr, p.k, w.huge_cap,
+                           (const uint32_t*)w.huge_tot, w.slice_hist);
         HG_TRY(hipGetLastError());
         hipLaunchKernelGGL(k_huge_place<Key>, dim3(1024), dim3(kLocalThreads),
                            heavy_smem<Key>(p.k), s, (const Key*)rkeys, (const uint32_t*)w.rids,
