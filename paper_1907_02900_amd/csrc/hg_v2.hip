@@ -445,8 +445,15 @@ __global__ __launch_bounds__(kLocalThreads) void k_huge_hist(
         const uint32_t v0 = r.b << k;
         for (uint32_t i = threadIdx.x; i < NB; i += kLocalThreads) cnt[i] = 0;
         __syncthreads();
-        for (uint32_t i = r.begin + threadIdx.x; i < r.end; i += kLocalThreads)
-            atomicAdd(&cnt[KeyTraits<Key>::bucket(src_keys[i], hp) - v0], 1u);
+        // a split bin holds a hot key: lanes sharing the first active lane's
+        // bucket add their count with one LDS atomic, the others one each
+        for (uint32_t i = r.begin + threadIdx.x; i < r.end; i += kLocalThreads) {
+            const uint32_t b = KeyTraits<Key>::bucket(src_keys[i], hp) - v0;
+            const uint32_t b0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)b);
+            const uint64_t same = ballot(b == b0);
+            if (b != b0) atomicAdd(&cnt[b], 1u);
+            else if (mbcnt(same) == 0) atomicAdd(&cnt[b0], (uint32_t)__popcll(same));
+        }
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < NB; i += kLocalThreads)
             hist[(size_t)item * NB + i] = cnt[i];

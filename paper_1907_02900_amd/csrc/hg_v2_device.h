@@ -821,13 +821,21 @@ __device__ __forceinline__ void place_in_chunks(const Key* __restrict__ src_keys
         }
         for (uint32_t i = threadIdx.x; i < NB; i += kLocalThreads) tcnt[i] = 0;
         __syncthreads();
+        // bins this large usually hold a hot key: the lanes whose bucket
+        // equals the wave's first lane's add their count with one atomic (a
+        // single LDS address hit by every lane would serialise 64 ways), the
+        // others add one each
 #pragma unroll
         for (int r = 0; r < IT; ++r) {
-            if ((uint32_t)r < rounds && r * kWave + lane < mylen) {
-                b[r] = KeyTraits<Key>::bucket(kk[r], hp) - v0;
+            const bool valid = (uint32_t)r < rounds && r * kWave + lane < mylen;
+            b[r] = valid ? KeyTraits<Key>::bucket(kk[r], hp) - v0 : NB;
+            const uint32_t b0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)b[r]);
+            const bool first = valid && b[r] == b0;
+            const uint64_t same = ballot(first);
+            if (first) {
+                if (mbcnt(same) == 0) atomicAdd(&tcnt[b0], (uint32_t)__popcll(same));
+            } else if (valid) {
                 atomicAdd(&tcnt[b[r]], 1u);
-            } else {
-                b[r] = NB;
             }
         }
         sort_chunk_by_bucket<Key, IT>(kk, id, b, rounds, cl, wchunk, k, skeys, sids, sb, wcnt,
