@@ -558,7 +558,9 @@ typedef struct hg_server_stats {
     uint64_t launches;        /* device launches issued                        */
     uint64_t merged_requests; /* requests that ran inside merged launches      */
     uint64_t keys;            /* keys + queries of completed requests          */
-    double p50_ms, p99_ms, mean_ms, max_ms; /* submission -> completion         */
+    double p50_ms, p99_ms, mean_ms, max_ms; /* submission -> completion, over
+                                               the last 2^20 completed requests
+                                               since the last reset           */
     double busy_s;            /* first submission -> last completion           */
     uint64_t resident_bytes, peak_bytes;
     uint32_t resident_tables;

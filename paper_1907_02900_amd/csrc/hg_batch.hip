@@ -1014,7 +1014,10 @@ struct Server {
     std::vector<uint32_t> worker_next;  // per worker: its next stream
     uint64_t next_seq = 1;
     // statistics
+    // latencies of the last kLatKeep completed requests (a ring once full)
+    static constexpr size_t kLatKeep = size_t(1) << 20;
     std::vector<double> lat_ms;
+    size_t lat_next = 0;
     uint64_t completed = 0, failed = 0, rejected = 0, evictions = 0, launches = 0, merged = 0,
              keys = 0;
     double first_arrive = -1, last_done = 0;
@@ -1116,7 +1119,9 @@ struct Server {
         if (st == HG_OK) {
             ++completed;
             keys += r.count;
-            lat_ms.push_back((t - r.t_arrive) * 1e3);
+            const double ms = (t - r.t_arrive) * 1e3;
+            if (lat_ms.size() < kLatKeep) lat_ms.push_back(ms);
+            else lat_ms[lat_next++ % kLatKeep] = ms;
             if (t > last_done) last_done = t;
         } else {
             ++failed;
@@ -1709,6 +1714,7 @@ hg_status hg_server_reset_stats(hg_server* h) {
     hg::srv::Server& s = h->s;
     std::lock_guard<std::mutex> lk(s.mu);
     s.lat_ms.clear();
+    s.lat_next = 0;
     s.completed = s.failed = s.rejected = s.evictions = s.launches = s.merged = s.keys = 0;
     s.first_arrive = -1;
     s.last_done = 0;
