@@ -550,7 +550,8 @@ __global__ __launch_bounds__(kLocalThreads) void k_huge_place(
     const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ huge_list,
     const uint32_t* __restrict__ huge_s0, const uint32_t* __restrict__ slice_owner,
     const uint32_t* __restrict__ ctr, typename KeyTraits<Key>::Params hp, uint32_t k,
-    const uint32_t* __restrict__ hist, uint32_t* __restrict__ ids, Key* __restrict__ ekeys) {
+    const uint32_t* __restrict__ hist, uint32_t* __restrict__ ids, Key* __restrict__ ekeys,
+    bool any_order) {
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t NB = 1u << k, nsl = ctr[2];
     const HeavyLds<Key> m(smem, NB);
@@ -561,7 +562,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_huge_place(
         __syncthreads();
         place_in_chunks<Key>(src_keys + r.begin, src_ids + r.begin, 0u, r.end - r.begin,
                              bin_start[r.b], bin_start[r.b + 1], r.b << k, k, hp, ids, ekeys,
-                             smem);
+                             smem, any_order);
         __syncthreads();
     }
 }
@@ -621,7 +622,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_local_heavy(
     const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ heavy_list,
     const uint32_t* __restrict__ heavy_count, typename KeyTraits<Key>::Params hp, uint32_t k,
     uint32_t* __restrict__ offsets, IndexOut ix, uint32_t* __restrict__ ids,
-    Key* __restrict__ ekeys) {
+    Key* __restrict__ ekeys, bool any_order) {
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t NB = 1u << k, V = hp.range;
     const uint32_t nheavy = *heavy_count;
@@ -631,7 +632,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_local_heavy(
         const uint32_t v0 = g << k;
         const uint32_t nb = (V - v0 < NB) ? V - v0 : NB;
         heavy_bin_body<Key>(src_keys + start, src_ids + start, 0u, end - start, start, v0, k, nb,
-                            hp, offsets, ix, ids, ekeys, smem);
+                            hp, offsets, ix, ids, ekeys, smem, any_order);
         __syncthreads();
     }
 }
@@ -962,7 +963,7 @@ hipError_t run_build_v2(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, 
         hipLaunchKernelGGL(k_local_heavy<Key>, dim3(hg_grid), dim3(kLocalThreads),
                            heavy_smem<Key>(p.k), s, (const Key*)rkeys, (const uint32_t*)w.rids,
                            (const uint32_t*)w.bin_start, (const uint32_t*)w.heavy_list,
-                           (const uint32_t*)w.ctr, hp, p.k, offsets, ix, ids, ekeys);
+                           (const uint32_t*)w.ctr, hp, p.k, offsets, ix, ids, ekeys, !stable);
     }
     HG_TRY(hipGetLastError());
     if (n > kSliceKeys) {
@@ -994,7 +995,7 @@ hipError_t run_build_v2(const Key* keys, uint64_t n, uint64_t V, uint64_t seed, 
                            heavy_smem<Key>(p.k), s, (const Key*)rkeys, (const uint32_t*)w.rids,
                            bs, (const uint32_t*)w.huge_list, (const uint32_t*)w.huge_s0,
                            (const uint32_t*)w.slice_owner, (const uint32_t*)w.ctr, hp, p.k,
-                           (const uint32_t*)w.slice_hist, ids, ekeys);
+                           (const uint32_t*)w.slice_hist, ids, ekeys, !stable);
         HG_TRY(hipGetLastError());
         if (ix.head) {
             hipLaunchKernelGGL(k_huge_index<Key>, dim3(256), dim3(kLocalThreads), 0, s, bs,

@@ -778,8 +778,11 @@ struct HeavyLds {
 // order: each chunk is sorted by bucket in LDS and written at the running
 // per-bucket cursors cur[0 .. 2^k), which hold absolute edge positions on
 // entry and are advanced past the placed entries on return.  Writes outside
-// [lo, hi) are dropped (they cannot happen for consistent counts).  Uses the
-// heavy_smem layout; whole workgroup.
+// [lo, hi) are dropped (they cannot happen for consistent counts).  With
+// any_order a chunk is grouped by bucket with one returning LDS atomic per
+// key (the lanes sharing the wave's first lane's bucket take one for the
+// group) instead of two stable ranking passes.  Uses the heavy_smem layout;
+// whole workgroup.
 template <typename Key>
 __device__ __forceinline__ void place_in_chunks(const Key* __restrict__ src_keys,
                                                 const uint32_t* __restrict__ src_ids,
@@ -787,7 +790,8 @@ __device__ __forceinline__ void place_in_chunks(const Key* __restrict__ src_keys
                                                 uint32_t hi, uint32_t v0, uint32_t k,
                                                 const typename KeyTraits<Key>::Params& hp,
                                                 uint32_t* __restrict__ ids,
-                                                Key* __restrict__ ekeys, unsigned char* smem) {
+                                                Key* __restrict__ ekeys, unsigned char* smem,
+                                                bool any_order = false) {
     constexpr int IT = kHeavyItems;
     constexpr uint32_t CAP = kHeavyChunk;
     const uint32_t NB = 1u << k;
@@ -838,6 +842,48 @@ __device__ __forceinline__ void place_in_chunks(const Key* __restrict__ src_keys
                 atomicAdd(&tcnt[b[r]], 1u);
             }
         }
+        if (any_order) {
+            __syncthreads();
+            // chunk-local bucket starts; the slots taken below turn them into
+            // bucket ends, and a bucket starts where the one before it ends
+            scan_counts(tcnt, NB, 0u, tmp);
+#pragma unroll
+            for (int r = 0; r < IT; ++r) {
+                const bool valid = b[r] < NB;
+                const uint32_t b0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)b[r]);
+                const bool first = valid && b[r] == b0;
+                const uint64_t same = ballot(first);
+                uint32_t slot = 0;
+                if (first) {
+                    uint32_t base = 0;
+                    if (mbcnt(same) == 0) base = atomicAdd(&tcnt[b0], (uint32_t)__popcll(same));
+                    slot = (uint32_t)__shfl((int)base, (int)__builtin_ctzll(same), kWave) +
+                           mbcnt(same);
+                } else if (valid) {
+                    slot = atomicAdd(&tcnt[b[r]], 1u);
+                }
+                if (valid) {
+                    skeys[slot] = kk[r];
+                    sids[slot] = id[r];
+                    sb[slot] = (uint16_t)b[r];
+                }
+            }
+            __syncthreads();
+            for (uint32_t p = threadIdx.x; p < cl; p += kLocalThreads) {
+                const uint32_t bb = sb[p];
+                const uint32_t st = bb ? tcnt[bb - 1] : 0u;
+                const uint32_t o = cur[bb] + (p - st);
+                if (o - lo < hi - lo) {
+                    ekeys[o] = skeys[p];
+                    ids[o] = sids[p];
+                }
+            }
+            __syncthreads();
+            for (uint32_t i = threadIdx.x; i < NB; i += kLocalThreads)
+                cur[i] += tcnt[i] - (i ? tcnt[i - 1] : 0u);
+            __syncthreads();
+            continue;
+        }
         sort_chunk_by_bucket<Key, IT>(kk, id, b, rounds, cl, wchunk, k, skeys, sids, sb, wcnt,
                                       dstart, tmp);
         __syncthreads();
@@ -872,20 +918,27 @@ __device__ __forceinline__ void heavy_bin_body(const Key* __restrict__ src_keys,
                                                uint32_t* __restrict__ offsets,
                                                const IndexOut& ix,
                                                uint32_t* __restrict__ ids, Key* __restrict__ ekeys,
-                                               unsigned char* smem) {
+                                               unsigned char* smem, bool any_order = false) {
     const uint32_t NB = 1u << k;
     const HeavyLds<Key> m(smem, NB);
     uint32_t *cur = m.cur, *tmp = m.tmp;
 
     for (uint32_t i = threadIdx.x; i < NB; i += kLocalThreads) cur[i] = 0;
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < L; i += kLocalThreads)
-        atomicAdd(&cur[KeyTraits<Key>::bucket(src_keys[i], hp) - v0], 1u);
+    // lanes sharing the first active lane's bucket (a hot key) count with one
+    // LDS atomic, the others one each
+    for (uint32_t i = threadIdx.x; i < L; i += kLocalThreads) {
+        const uint32_t b = KeyTraits<Key>::bucket(src_keys[i], hp) - v0;
+        const uint32_t b0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)b);
+        const uint64_t same = ballot(b == b0);
+        if (b != b0) atomicAdd(&cur[b], 1u);
+        else if (mbcnt(same) == 0) atomicAdd(&cur[b0], (uint32_t)__popcll(same));
+    }
     __syncthreads();
     scan_counts(cur, NB, out, tmp);
     for (uint32_t i = threadIdx.x; i < nb; i += kLocalThreads) offsets[v0 + i] = cur[i];
     place_in_chunks<Key>(src_keys, src_ids, id_base, L, out, out + L, v0, k, hp, ids, ekeys,
-                         smem);
+                         smem, any_order);
     // cur[v] is now the end of bucket v; the bin's edges are in ekeys.  Long
     // buckets are listed for the general pass, which builds their key runs.
     if (ix.head) {
