@@ -214,20 +214,24 @@ hg_status check_pairs_args(const hg_table* t, const void* d_queries, uint64_t m,
     return HG_OK;
 }
 
-// Probe-Standard pairs in two passes over a workspace of probe_ws_bytes(m):
-// per-query counts, their exclusive scan (64-bit positions), the total read
-// back, then each query writes its pairs at its position.  Every byte of the
-// workspace that is read is written first by the same call.
+// Probe-Standard pairs in two passes over a workspace of probe_ws_bytes(m)
+// (plus m bytes with `held`): per-query counts, their exclusive scan (64-bit
+// positions), the total read back, then each query writes its pairs at its
+// position.  With `held` the counting pass also leaves, per query, the
+// matching keys of a bucket held whole in its index entry, so the pairs pass
+// need not read that entry again.  Every byte of the workspace that is read
+// is written first by the same call.
 hg_status probe_pairs_into(const hg_table* t, const void* d_queries, uint64_t m,
                            uint32_t* d_build_ids, uint32_t* d_probe_ids, uint64_t capacity,
-                           uint64_t* h_total, void* ws, hipStream_t stream) {
+                           uint64_t* h_total, void* ws, hipStream_t stream, bool with_held) {
     Carver c(ws);
     uint32_t* counts = c.take<uint32_t>(m);
     uint64_t* pos = c.take<uint64_t>(m + 1);
     void* scan_ws = c.take<char>(scan_ws_bytes(m));
+    uint8_t* held = with_held && t->key_bits == 32 && t->has_head ? c.take<uint8_t>(m) : nullptr;
     TableDev d = dev_view(t);
     hipError_t e = t->key_bits == 32
-                       ? run_probe_counts<uint32_t>(d, (const uint32_t*)d_queries, m, counts, nullptr, stream)
+                       ? run_probe_counts<uint32_t>(d, (const uint32_t*)d_queries, m, counts, nullptr, stream, held)
                        : run_probe_counts<uint64_t>(d, (const uint64_t*)d_queries, m, counts, nullptr, stream);
     if (e != hipSuccess) return from_hip(e);
     HG_CALL(scan_excl<uint64_t>(counts, m, pos, nullptr, scan_ws, stream));
@@ -236,7 +240,7 @@ hg_status probe_pairs_into(const hg_table* t, const void* d_queries, uint64_t m,
     if (*h_total > capacity) return HG_ERR_CAPACITY;
     if (*h_total == 0) return HG_OK;
     e = t->key_bits == 32
-            ? run_probe_pairs<uint32_t>(d, (const uint32_t*)d_queries, m, pos, d_build_ids, d_probe_ids, stream)
+            ? run_probe_pairs<uint32_t>(d, (const uint32_t*)d_queries, m, pos, d_build_ids, d_probe_ids, stream, held)
             : run_probe_pairs<uint64_t>(d, (const uint64_t*)d_queries, m, pos, d_build_ids, d_probe_ids, stream);
     if (e != hipSuccess) return from_hip(e);
     HG_CALL(hipStreamSynchronize(stream));
@@ -814,9 +818,9 @@ hg_status hg_probe_pairs(const hg_table* t, const void* d_queries, uint64_t m,
         return HG_OK;
     }
     Workspace ws(stream);
-    HG_CALL(ws.get(probe_ws_bytes(m)));
+    HG_CALL(ws.get(probe_ws_bytes(m) + align_up(m, 256)));
     return probe_pairs_into(t, d_queries, m, d_build_ids, d_probe_ids, capacity, h_total, ws.p,
-                            stream);
+                            stream, true);
 }
 
 hg_status hg_probe_pairs_noalloc(const hg_table* t, const void* d_queries, uint64_t m,
@@ -831,7 +835,7 @@ hg_status hg_probe_pairs_noalloc(const hg_table* t, const void* d_queries, uint6
     void* ws = nullptr;
     HG_CALL_ST(static_scratch(probe_ws_bytes(m), &ws));
     return probe_pairs_into(t, d_queries, m, d_build_ids, d_probe_ids, capacity, h_total, ws,
-                            stream);
+                            stream, false);
 }
 
 hg_status hg_intersect_edges(const hg_table* a, const hg_table* b, uint32_t* d_counts_edges,

@@ -314,16 +314,21 @@ hipError_t run_export_live(const TableDev& t, const uint32_t* len, const uint32_
 size_t probe_ws_bytes(uint64_t m);
 
 // counts (may be null) and/or the total (may be null: else a buffer of
-// probe_total_slots(m) uint64, the total lands in slot 0).
+// probe_total_slots(m) uint64, the total lands in slot 0).  held (may be
+// null; 32-bit keys with the probe index): per query, 0x80 | the mask of the
+// matching keys when its bucket is held whole in its index entry, else 0 --
+// what the pairs pass needs instead of that entry.
 template <typename Key>
 hipError_t run_probe_counts(const TableDev& t, const Key* queries, uint64_t m, uint32_t* counts,
-                            unsigned long long* d_total, hipStream_t s);
+                            unsigned long long* d_total, hipStream_t s,
+                            uint8_t* held = nullptr);
 
-// positions[j] = first pair slot of query j (exclusive scan of counts).
+// positions[j] = first pair slot of query j (exclusive scan of counts);
+// held: the counting pass's per-query codes, or null.
 template <typename Key>
 hipError_t run_probe_pairs(const TableDev& t, const Key* queries, uint64_t m,
                            const uint64_t* positions, uint32_t* build_ids, uint32_t* probe_ids,
-                           hipStream_t s);
+                           hipStream_t s, const uint8_t* held = nullptr);
 
 // Intersection over b's edges: per-edge counts (edge order) and, optionally,
 // counts scattered to b's input order.

@@ -163,6 +163,20 @@ __device__ __forceinline__ uint32_t count_with_head(const uint4& e, const Key* _
     return c;
 }
 
+// For the pairs pass: 0x80 | the mask of the entry's keys equal to q when the
+// bucket (1-3 32-bit keys) is held whole in its entry, else 0.
+template <typename Key>
+__device__ __forceinline__ uint8_t held_code(const uint4& e, Key q) {
+    using HK = HeadKeys<uint32_t>;
+    const uint32_t len = e.x;
+    if (len == 0 || len > HK::full) return 0;
+    uint32_t mask = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < HK::full; ++i)
+        mask |= (i < len && HK::key(e, len, i) == (uint32_t)q) ? 1u << i : 0u;
+    return (uint8_t)(0x80u | mask);
+}
+
 // Probe-Standard counts.  HEAD: each query reads its bucket's 16-byte index
 // entry (one random access for buckets of up to three 32-bit keys or one
 // 64-bit key); otherwise it reads
@@ -172,7 +186,7 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_count(
     const Key* __restrict__ q, uint64_t m, typename KeyTraits<Key>::Params hp,
     const uint32_t* __restrict__ off, const uint4* __restrict__ head, Runs<Key> runs,
     const Key* __restrict__ ekeys, uint32_t* __restrict__ counts,
-    unsigned long long* __restrict__ total) {
+    unsigned long long* __restrict__ total, uint8_t* __restrict__ held) {
     __shared__ uint64_t red[kProbeThreads / kWave + 1];
     const uint64_t base = (uint64_t)blockIdx.x * (kProbeThreads * kProbeItems) + threadIdx.x;
     Key qq[kProbeItems];
@@ -204,6 +218,7 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_count(
         const uint32_t c = HEAD ? count_with_head(e[r], ekeys, runs, qq[r])
                                 : count_in_bucket(ekeys, e[r].x, e[r].y, qq[r]);
         if (j < m && counts) counts[j] = c;
+        if (HEAD && sizeof(Key) == 4 && held && j < m) held[j] = held_code(e[r], qq[r]);
         sum += c;
     }
     if (total) {
@@ -219,29 +234,34 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_pairs(
     const uint32_t* __restrict__ off, const uint4* __restrict__ head, Runs<Key> runs,
     const Key* __restrict__ ekeys, const uint32_t* __restrict__ eids,
     const uint64_t* __restrict__ positions, uint32_t* __restrict__ build_ids,
-    uint32_t* __restrict__ probe_ids) {
+    uint32_t* __restrict__ probe_ids, const uint8_t* __restrict__ held) {
     using HK = HeadKeys<Key>;
     // as in k_probe_count: every thread first loads the index entries (or
     // offsets) of its kProbeItems queries, so that their random reads overlap;
     // a query whose output range [positions[j], positions[j+1]) is empty has
     // no match and reads nothing more
     const uint64_t base = (uint64_t)blockIdx.x * (kProbeThreads * kProbeItems) + threadIdx.x;
+    // (with the counting pass's codes, a query whose bucket is held whole in
+    // its entry skips the entry: it knows its matching keys and reads only
+    // the bucket's start)
     Key qq[kProbeItems];
     uint32_t hh[kProbeItems];
     uint4 e[kProbeItems];
     uint64_t pend[kProbeItems];
     bool none[kProbeItems];
+    uint32_t code[kProbeItems];
 #pragma unroll
     for (int r = 0; r < kProbeItems; ++r) {
         const uint64_t j = base + (uint64_t)r * kProbeThreads;
         qq[r] = (j < m) ? q[j] : (Key)0;
         pend[r] = (j < m) ? positions[j + 1] : 0ull;
         none[r] = j >= m || positions[j] == pend[r];
+        code[r] = (HEAD && held && j < m) ? held[j] : 0u;
     }
 #pragma unroll
     for (int r = 0; r < kProbeItems; ++r) {
         hh[r] = KeyTraits<Key>::bucket(qq[r], hp);
-        if (none[r]) {
+        if (none[r] || code[r]) {
             e[r] = make_uint4(0u, 0u, 0u, 0u);
         } else if (HEAD) {
             e[r] = head[hh[r]];
@@ -262,7 +282,9 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_pairs(
         via_runs[r] = false;
         nn[r] = 0;
         st[r] = er.x;
-        if (HEAD && !skip[r]) {
+        if (HEAD && !skip[r] && code[r]) {
+            st[r] = off[hh[r]];
+        } else if (HEAD && !skip[r]) {
             const uint32_t len = er.x;
             const bool longb = len > kRunBucket;
             via_runs[r] = longb && er.z != 0u;
@@ -284,6 +306,16 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_pairs(
         const Key k = qq[r];
         const uint4 er = e[r];
         uint64_t pos = positions[j];
+        if (code[r]) {
+#pragma unroll
+            for (uint32_t i = 0; i < 3; ++i)
+                if (((code[r] >> i) & 1u) && pos < pend[r]) {
+                    build_ids[pos] = eids[st[r] + i];
+                    probe_ids[pos] = (uint32_t)j;
+                    ++pos;
+                }
+            continue;
+        }
         if (via_runs[r]) {
             // the ids of q's group, in bucket order: the edge array's own for
             // a bucket of one key, else its group in kperm
@@ -428,7 +460,7 @@ uint64_t probe_total_slots(uint64_t m) {
 
 template <typename Key>
 hipError_t run_probe_counts(const TableDev& t, const Key* queries, uint64_t m, uint32_t* counts,
-                            unsigned long long* d_total, hipStream_t s) {
+                            unsigned long long* d_total, hipStream_t s, uint8_t* held) {
     if (m == 0) return d_total ? fill_u32((uint32_t*)d_total, 2, 0u, s) : hipSuccess;
     auto hp = KeyTraits<Key>::make(t.V, t.seed);
     const dim3 grid(grid_for(m, kProbeThreads * kProbeItems));
@@ -437,11 +469,11 @@ hipError_t run_probe_counts(const TableDev& t, const Key* queries, uint64_t m, u
         if (t.head)
             hipLaunchKernelGGL((k_probe_count<Key, true>), grid, dim3(kProbeThreads), 0, s,
                                queries, m, hp, t.offsets, t.head, runs_of<Key>(t),
-                               (const Key*)t.keys, counts, d_total);
+                               (const Key*)t.keys, counts, d_total, held);
         else
             hipLaunchKernelGGL((k_probe_count<Key, false>), grid, dim3(kProbeThreads), 0, s,
                                queries, m, hp, t.offsets, t.head, runs_of<Key>(t),
-                               (const Key*)t.keys, counts, d_total);
+                               (const Key*)t.keys, counts, d_total, (uint8_t*)nullptr);
     }
     HG_TRY(hipGetLastError());
     return d_total ? sum_u64(d_total + 1, grid.x, d_total, s) : hipSuccess;
@@ -450,7 +482,7 @@ hipError_t run_probe_counts(const TableDev& t, const Key* queries, uint64_t m, u
 template <typename Key>
 hipError_t run_probe_pairs(const TableDev& t, const Key* queries, uint64_t m,
                            const uint64_t* positions, uint32_t* build_ids, uint32_t* probe_ids,
-                           hipStream_t s) {
+                           hipStream_t s, const uint8_t* held) {
     if (m == 0) return hipSuccess;
     auto hp = KeyTraits<Key>::make(t.V, t.seed);
     const uint32_t g = grid_for(m, kProbeThreads * kProbeItems);
@@ -459,11 +491,13 @@ hipError_t run_probe_pairs(const TableDev& t, const Key* queries, uint64_t m,
         if (t.head)
             hipLaunchKernelGGL((k_probe_pairs<Key, true>), dim3(g), dim3(kProbeThreads), 0, s,
                                queries, m, hp, t.offsets, t.head, runs_of<Key>(t),
-                               (const Key*)t.keys, t.ids, positions, build_ids, probe_ids);
+                               (const Key*)t.keys, t.ids, positions, build_ids, probe_ids,
+                               sizeof(Key) == 4 ? held : nullptr);
         else
             hipLaunchKernelGGL((k_probe_pairs<Key, false>), dim3(g), dim3(kProbeThreads), 0, s,
                                queries, m, hp, t.offsets, t.head, runs_of<Key>(t),
-                               (const Key*)t.keys, t.ids, positions, build_ids, probe_ids);
+                               (const Key*)t.keys, t.ids, positions, build_ids, probe_ids,
+                               (const uint8_t*)nullptr);
     }
     return hipGetLastError();
 }
@@ -504,10 +538,10 @@ hipError_t run_intersect_pairs(const TableDev& a, const TableDev& b, const uint6
 
 #define HG_PINST(Key)                                                                           \
     template hipError_t run_probe_counts<Key>(const TableDev&, const Key*, uint64_t, uint32_t*, \
-                                              unsigned long long*, hipStream_t);                \
+                                              unsigned long long*, hipStream_t, uint8_t*);      \
     template hipError_t run_probe_pairs<Key>(const TableDev&, const Key*, uint64_t,             \
                                              const uint64_t*, uint32_t*, uint32_t*,             \
-                                             hipStream_t);                                      \
+                                             hipStream_t, const uint8_t*);                      \
     template hipError_t run_intersect_counts<Key>(const TableDev&, const TableDev&, uint32_t*,  \
                                                   uint32_t*, unsigned long long*, hipStream_t); \
     template hipError_t run_intersect_pairs<Key>(const TableDev&, const TableDev&,              \
