@@ -265,9 +265,10 @@ G2Layout layout_g2(void* ws, uint64_t n) {
     return G2Layout{g, c.off + 256};
 }
 
-// The listed long buckets of every bin: small ones are finished here, in
-// LDS; longer ones are handed to the chunked path (ctr[0] buckets, ctr[1]
-// chunks).
+// The listed long buckets of every bin: first each wave finishes the buckets
+// whose entries other than the lead key fit its lanes (marking them done in
+// the list), then the workgroup sorts the other small ones in LDS; longer ones
+// are handed to the chunked path (ctr[0] buckets, ctr[1] chunks).
 template <typename Key>
 __global__ __launch_bounds__(kRT) void k_runs_general(
     const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ ids,
@@ -278,9 +279,27 @@ __global__ __launch_bounds__(kRT) void k_runs_general(
     for (uint32_t g = blockIdx.x; g < bins; g += gridDim.x) {
         const uint32_t listed = ix.gen_cnt[g];
         if (listed == 0) continue;  // uniform across the workgroup
-        const uint32_t* list = ix.gen_list + gen_region(bin_start[g], g);
+        uint32_t* list = ix.gen_list + gen_region(bin_start[g], g);
+        {
+            // a wave per bucket, its 64-entry buffers in the sort buffers
+            const uint32_t w = threadIdx.x / kWave, lane = lane_id();
+            Key* bk = m.sk + w * kWave;
+            uint16_t* bp = (uint16_t*)m.sp + w * kWave;
+            for (uint32_t t = w; t < listed; t += W_LOCAL) {
+                const uint32_t b = list[t];
+                const uint32_t st = offsets[b], len = offsets[b + 1] - st;
+                // (a bucket much longer than a wave rarely has its other
+                // keys fit one; it goes to the workgroup below directly)
+                if (len > 4u * kWave) continue;
+                if (wave_bucket_runs<Key>(ix, ekeys, ids, st, st + len, st, b, bk, bp) &&
+                    lane == 0)
+                    list[t] = ~0u;  // done
+            }
+        }
+        __syncthreads();
         for (uint32_t t = 0; t < listed; ++t) {
             const uint32_t b = list[t];
+            if (b == ~0u) continue;  // uniform: finished by a wave above
             const uint32_t st = offsets[b], len = offsets[b + 1] - st;
             const Key lead = ekeys[st];
             if (len > small_cap<Key>()) {

@@ -506,6 +506,85 @@ __device__ __forceinline__ void bin_medium_heads(const IndexOut& ix, const LongL
     medium_heads_by<Key, 32>(ix, med, lr.cnt[2], skeys, out, v0);
 }
 
+// Key runs and index entry of one long bucket, by one wave: its entries are
+// keys[lo, hi) with ids ids_[lo, hi) (in LDS or in global memory), its first
+// edge is at st, its bucket id b.  The entries equal to the bucket's first
+// key (the lead key) form one run; the others, when there are at most 64, are
+// sorted across the wave's lanes and cut into runs, and the lead run is
+// slotted in among them.  bk / bp: the wave's 64-entry LDS buffers.  Returns
+// false, having written nothing, when more than 64 entries differ from the
+// lead key (uniform across the wave).
+template <typename Key>
+__device__ __forceinline__ bool wave_bucket_runs(const IndexOut& ix, const Key* keys,
+                                                 const uint32_t* ids_, uint32_t lo, uint32_t hi,
+                                                 uint32_t st, uint32_t b, Key* bk, uint16_t* bp) {
+    const uint32_t lane = lane_id();
+    Key* rkey = (Key*)ix.runs.run_key;
+    uint32_t* rend = ix.runs.run_end;
+    uint32_t* kperm = ix.runs.kperm;
+    const uint32_t len = hi - lo;
+    const Key lead = keys[lo];
+    uint32_t no = 0;  // entries whose key differs from the lead key
+    for (uint32_t c = lo; c < hi; c += kWave) {
+        const uint32_t p = c + lane;
+        const Key x = p < hi ? keys[p] : lead;
+        const bool o = x != lead;
+        const uint64_t bal = ballot(o);
+        const uint32_t slot = no + mbcnt(bal);
+        if (o && slot < (uint32_t)kWave) {
+            bk[slot] = x;
+            bp[slot] = (uint16_t)(p - lo);
+        }
+        no += (uint32_t)__popcll(bal);
+        if (no > (uint32_t)kWave) return false;  // too many others: stop reading
+    }
+    if (no == 0) {  // one key: its ids are the edge array's own
+        if (lane == 0) {
+            rkey[st] = lead;
+            rend[st] = len;
+            ix.head[b] = make_uint4(len, st, 1u, sizeof(Key) == 4 ? (uint32_t)lead : 0u);
+        }
+        return true;
+    }
+    // the buffer written above is read by other lanes of the same wave:
+    // LDS executes a wave's operations in order; keep the compiler's too
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const bool valid = lane < no;
+    Key k = valid ? bk[lane] : (Key)~(Key)0;
+    uint32_t p = valid ? (uint32_t)bp[lane] : 0xffffffffu;
+    wave_sort_pairs<Key>(k, p);
+    const Key kprev = __shfl_up(k, 1, kWave);
+    const Key knext = __shfl_down(k, 1, kWave);
+    const bool first = valid && (lane == 0 || kprev != k);
+    const bool last = valid && (lane + 1 == no || knext != k);
+    const bool below = valid && k < lead;
+    const uint64_t fb = ballot(first), lb = ballot(below);
+    const uint32_t nless = (uint32_t)__popcll(lb);       // others below the lead key
+    const uint32_t rl = (uint32_t)__popcll(fb & lb);     // runs below the lead key
+    const uint32_t clead = len - no;
+    const uint32_t r = mbcnt(fb) + (first ? 1u : 0u) - 1u + (below ? 0u : 1u);
+    if (valid) kperm[st + lane + (below ? 0u : clead)] = ids_[lo + p];
+    if (first) rkey[st + r] = k;
+    if (last) rend[st + r] = lane + 1 + (below ? 0u : clead);
+    if (lane == 0) {
+        rkey[st + rl] = lead;
+        rend[st + rl] = nless + clead;
+        ix.head[b] = make_uint4(len, st, (uint32_t)__popcll(fb) + 1u, 0u);
+    }
+    // the lead key's ids, in bucket order, after the smaller keys' runs
+    uint32_t done = 0;
+    for (uint32_t c = lo; c < hi; c += kWave) {
+        const uint32_t q = c + lane;
+        const bool isl = q < hi && keys[q] == lead;
+        const uint64_t bal = ballot(isl);
+        if (isl) kperm[st + nless + done + mbcnt(bal)] = ids_[q];
+        done += (uint32_t)__popcll(bal);
+    }
+    return true;
+}
+
 // Key runs of the long buckets of a bin held in LDS (skeys / sids in bucket
 // order, the bin's first edge at `out`), one wave per bucket.  The entries
 // equal to the bucket's first key (the lead key) form one run; the others,
@@ -521,77 +600,13 @@ __device__ __forceinline__ void bin_long_runs(const IndexOut& ix, const LongLds<
     bin_medium_heads<Key>(ix, lr, med, skeys, out, v0);
     const uint32_t nl = lr.cnt[0];
     const uint32_t w = threadIdx.x / kWave, lane = lane_id();
-    Key* rkey = (Key*)ix.runs.run_key;
-    uint32_t* rend = ix.runs.run_end;
-    uint32_t* kperm = ix.runs.kperm;
     Key* bk = lr.wkey + w * kWave;
     uint16_t* bp = lr.wpos + w * kWave;
     for (uint32_t j = w; j < nl; j += W_LOCAL) {
         const uint32_t lh = lr.lohi[j], lo = lh & 0xffffu, hi = lh >> 16;
         const uint32_t b = lr.bkt[j];
-        const uint32_t len = hi - lo, st = out + lo;
-        const Key lead = skeys[lo];
-        uint32_t no = 0;  // entries whose key differs from the lead key
-        for (uint32_t c = lo; c < hi; c += kWave) {
-            const uint32_t p = c + lane;
-            const Key x = p < hi ? skeys[p] : lead;
-            const bool o = x != lead;
-            const uint64_t bal = ballot(o);
-            const uint32_t slot = no + mbcnt(bal);
-            if (o && slot < (uint32_t)kWave) {
-                bk[slot] = x;
-                bp[slot] = (uint16_t)p;
-            }
-            no += (uint32_t)__popcll(bal);
-        }
-        if (no == 0) {  // one key: its ids are the edge array's own
-            if (lane == 0) {
-                rkey[st] = lead;
-                rend[st] = len;
-                ix.head[b] = make_uint4(len, st, 1u, sizeof(Key) == 4 ? (uint32_t)lead : 0u);
-            }
-            continue;
-        }
-        if (no > (uint32_t)kWave) {
-            if (lane == 0) ix.gen_list[gen_region(out, g) + atomicAdd(&lr.cnt[1], 1u)] = b;
-            continue;
-        }
-        // the buffer written above is read by other lanes of the same wave:
-        // LDS executes a wave's operations in order; keep the compiler's too
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const bool valid = lane < no;
-        Key k = valid ? bk[lane] : (Key)~(Key)0;
-        uint32_t p = valid ? (uint32_t)bp[lane] : 0xffffffffu;
-        wave_sort_pairs<Key>(k, p);
-        const Key kprev = __shfl_up(k, 1, kWave);
-        const Key knext = __shfl_down(k, 1, kWave);
-        const bool first = valid && (lane == 0 || kprev != k);
-        const bool last = valid && (lane + 1 == no || knext != k);
-        const bool below = valid && k < lead;
-        const uint64_t fb = ballot(first), lb = ballot(below);
-        const uint32_t nless = (uint32_t)__popcll(lb);       // others below the lead key
-        const uint32_t rl = (uint32_t)__popcll(fb & lb);     // runs below the lead key
-        const uint32_t clead = len - no;
-        const uint32_t r = mbcnt(fb) + (first ? 1u : 0u) - 1u + (below ? 0u : 1u);
-        if (valid) kperm[st + lane + (below ? 0u : clead)] = sids[p];
-        if (first) rkey[st + r] = k;
-        if (last) rend[st + r] = lane + 1 + (below ? 0u : clead);
-        if (lane == 0) {
-            rkey[st + rl] = lead;
-            rend[st + rl] = nless + clead;
-            ix.head[b] = make_uint4(len, st, (uint32_t)__popcll(fb) + 1u, 0u);
-        }
-        // the lead key's ids, in bucket order, after the smaller keys' runs
-        uint32_t done = 0;
-        for (uint32_t c = lo; c < hi; c += kWave) {
-            const uint32_t q = c + lane;
-            const bool isl = q < hi && skeys[q] == lead;
-            const uint64_t bal = ballot(isl);
-            if (isl) kperm[st + nless + done + mbcnt(bal)] = sids[q];
-            done += (uint32_t)__popcll(bal);
-        }
+        if (!wave_bucket_runs<Key>(ix, skeys, sids, lo, hi, out + lo, b, bk, bp) && lane == 0)
+            ix.gen_list[gen_region(out, g) + atomicAdd(&lr.cnt[1], 1u)] = b;
     }
     __syncthreads();
     if (threadIdx.x == 0) ix.gen_cnt[g] = lr.cnt[1];
