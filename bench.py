@@ -101,10 +101,26 @@ def kernel_bytes(name, n, m, V, kb, sum_len, plan):
                       tile x digit bases it reads;
       v2_tile_hist_*  phase 1: reads the keys, writes the tile histograms.
 
+    When the probe first groups its queries by bucket range (hg_probe does at
+    this size), three passes of the same kind as the build's come with it:
+
+      probe_group_hist  reads the queries, writes their tile histograms;
+      probe_group       reads the queries and the tile bases, writes the
+                        queries and their input positions in grouped order;
+      probe_ungroup     reads positions and counts in grouped order and two
+                        rows of bases per four tiles, writes the counts.
+
     The per-bucket probe index is this design's addition and is not counted
     here (index_bytes gives the bytes with it)."""
+    gm = group_matrix_bytes(m, V)
     if name == "probe_count":
         return m * kb + 8 * m + kb * sum_len + 4 * m
+    if name == "probe_group_hist":
+        return m * kb + gm
+    if name == "probe_group":
+        return m * kb + gm + m * kb + 4 * m
+    if name == "probe_ungroup":
+        return 4 * m + 4 * m + 4 * m + gm // 2
     if name == "v2_local_build":
         return 2 * n * (kb + 4) + (V + 1) * 4
     if name == "v2_partition_t1":
@@ -116,6 +132,14 @@ def kernel_bytes(name, n, m, V, kb, sum_len, plan):
     if name == "v2_tile_hist_t2":
         return n * kb + plan["m2_bytes"]
     return None
+
+
+def group_matrix_bytes(m, V):
+    """Tile x range matrix of the probe's query grouping: 4096 queries per
+    tile, 2^min(9, ceil(log2 V)) ranges (at least 2), 4 bytes each."""
+    kv = max(int(V - 1).bit_length(), 0)
+    bits = 9 if kv >= 9 else max(kv, 1)
+    return -(-m // 4096) * (1 << bits) * 4
 
 
 def index_bytes(name, n, m, V, kb, sum_tail):
@@ -335,7 +359,7 @@ def copy_gbps(torch, nbytes=1 << 30, reps=5):
     return 2 * nbytes / (t / 1000.0) / 1e9
 
 
-def hbm_fractions(build_ms, probe_ms, n, m, V, kb, sum_len, digest, copy):
+def hbm_fractions(build_ms, probe_ms, n, m, V, kb, sum_len, digest, copy, grouped=False):
     """Per phase of the step: HBM bytes the counters saw (profiles/
     pmc_traffic.json, same kernel sources) over the phase time, against the
     8 TB/s peak and the measured copy bandwidth; and the compulsory bytes
@@ -344,14 +368,16 @@ def hbm_fractions(build_ms, probe_ms, n, m, V, kb, sum_len, digest, copy):
     tr = {k: load_traffic(k, digest) for k in ("v2_tile_hist", "v2_partition_t1",
                                                "v2_partition_t2", "v2_local_build",
                                                "probe_count")}
+    grp = {k: load_traffic(k, digest) for k in ("probe_group_hist", "probe_group",
+                                                "probe_ungroup")}
     b_min = {"build": n * kb + n * (kb + 4) + 4 * (V + 1),
              "probe": m * kb + 8 * m + kb * sum_len + 4 * m}
     ms = {"build": build_ms, "probe": probe_ms}
     meas = None
-    if all(tr.values()):
+    if all(tr.values()) and (not grouped or all(grp.values())):
         meas = {"build": 2 * tr["v2_tile_hist"] + tr["v2_partition_t1"] +
                 tr["v2_partition_t2"] + tr["v2_local_build"],
-                "probe": tr["probe_count"]}
+                "probe": tr["probe_count"] + (sum(grp.values()) if grouped else 0)}
     out = {"peak_GBps": HBM_PEAK_GBS, "copy_GBps": round(copy, 1)}
     for ph in ("build", "probe"):
         t = ms[ph] / 1000.0
@@ -549,6 +575,7 @@ def main():
         if bi:
             kernels[name]["index_bytes"] = bi
             kernels[name]["index_GBps"] = round(bi / (avg / 1000.0) / 1e9, 1)
+    grouped = "probe_ungroup" in kernels
     dom = max((k for k in kernels if kernels[k]["alg_bytes"]),
               key=lambda k: kernels[k]["ms_per_step"])
     dk_ = kernels[dom]
@@ -582,16 +609,24 @@ def main():
         roofline["frac_of_random_read_rate"] = round(
             roofline["random_lines_G_per_s"] / rate, 3)
         roofline["micro_roofline"] = micro
+    if grouped:
+        # the queries were grouped by bucket range first: each XCD then reads
+        # one window of the index at a time and reuses its lines from L2, so
+        # the probe can pass the rate of random lines over the whole index
+        # (frac_of_random_read_rate above 1); the grouping's own passes are
+        # the probe_group* and probe_ungroup kernels
+        roofline["probe_order"] = "grouped by bucket range"
 
     phases = {"kernels": kernels, "source_digest": digest,
               "probe_sum_bucket_len": sum_len, "probe_sum_keys_past_index": sum_tail}
     build_ms = sum(v["ms_per_step"] for k, v in kernels.items()
                    if k.startswith("v2_") or k == "fill")
-    probe_ms = kernels.get("probe_count", {}).get("ms_per_step", 0.0)
+    # the probe with its query grouping and column scans, when it grouped
+    probe_ms = sum(v["ms_per_step"] for k, v in kernels.items() if k.startswith("probe_"))
     phases["build_v2_ms"] = round(build_ms, 3)
     phases["probe_ms"] = round(probe_ms, 3)
     phases["hbm"] = hbm_fractions(build_ms, probe_ms, n, m, V, kb, sum_len, digest,
-                                  copy_gbps(torch))
+                                  copy_gbps(torch), grouped)
 
     if not args.no_extras:
         log("extras")

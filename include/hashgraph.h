@@ -310,9 +310,33 @@ void hg_table_free(hg_table *t);
  * whose key equals d_queries[j] (all instances, not only the first).
  * d_queries: m keys of the table's key_bits.  d_counts: m uint32 or NULL.
  * h_total: if not NULL, receives the sum of all counts (uint64); this waits
- * for the stream.  At least one of d_counts and h_total must be given. */
+ * for the stream.  At least one of d_counts and h_total must be given.
+ * The order the queries are probed in is chosen as by hg_probe_ordered with
+ * HG_PROBE_AUTO. */
 hg_status hg_probe(const hg_table *t, const void *d_queries, uint64_t m, uint32_t *d_counts,
                    uint64_t *h_total, hipStream_t stream);
+
+/* hg_probe with the probing order given by the caller; counts and total are
+ * identical for every order.
+ *   HG_PROBE_INPUT_ORDER: every query reads its bucket where it stands (one
+ *     random read of the probe index per query, Sec. 3.4).
+ *   HG_PROBE_GROUPED: the queries are first partitioned into up to 512
+ *     ranges of buckets (with their input positions), probed range by range
+ *     with each XCD reading one window of the index at a time, and the
+ *     counts are put back in input order.  Needs m * (key_bits / 8 + 8) bytes
+ *     of workspace plus 2 KiB per 4096 queries (from the allocator,
+ *     hg_set_allocator).
+ *   HG_PROBE_AUTO: grouped when the table has a probe index,
+ *     m >= hash_range / 2 and hash_range >= 2^27 (2^26 when only the total
+ *     is asked for), the sizes from which grouping measured faster; else
+ *     input order.
+ * Any other order is HG_ERR_INVALID_ARG. */
+#define HG_PROBE_AUTO 0
+#define HG_PROBE_INPUT_ORDER 1
+#define HG_PROBE_GROUPED 2
+hg_status hg_probe_ordered(const hg_table *t, const void *d_queries, uint64_t m,
+                           uint32_t *d_counts, uint64_t *h_total, int32_t order,
+                           hipStream_t stream);
 
 /* The matching pairs themselves: d_build_ids[p], d_probe_ids[p] for p below
  * the total, grouped by probe id ascending; inside one probe id the build

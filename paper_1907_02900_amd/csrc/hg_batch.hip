@@ -80,11 +80,6 @@ __device__ __forceinline__ uint32_t find_table(const uint32_t* __restrict__ pre,
     return lo;
 }
 
-__device__ __forceinline__ uint32_t xcd_map(uint32_t b, uint32_t ub) {
-    const uint32_t per = (ub + 7) >> 3;
-    return (b & 7u) * per + (b >> 3);
-}
-
 __global__ void k_bclear(uint32_t* heavy_count) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *heavy_count = 0;
 }
@@ -95,7 +90,7 @@ __global__ __launch_bounds__(kPartThreads) void k_bhist(const BTable<Key>* __res
                                                         uint32_t* __restrict__ mat) {
     constexpr uint32_t TILE = kPartThreads * IT;
     extern __shared__ uint32_t cnt[];
-    const uint32_t t = xcd_map(blockIdx.x, tiles);
+    const uint32_t t = xcd_tile(blockIdx.x, tiles);
     if (t >= tiles) return;
     const uint32_t i = find_table(pre.tile, pre.T, t);
     const BTable<Key>& tb = tabs[i];
@@ -169,7 +164,7 @@ __global__ __launch_bounds__(kPartThreads) void k_bpart(const BTable<Key>* __res
                                                         uint32_t* __restrict__ rids) {
     constexpr uint32_t TILE = kPartThreads * IT;
     extern __shared__ __align__(16) unsigned char smem[];
-    const uint32_t t = xcd_map(blockIdx.x, tiles);
+    const uint32_t t = xcd_tile(blockIdx.x, tiles);
     if (t >= tiles) return;
     const uint32_t i = find_table(pre.tile, pre.T, t);
     const BTable<Key>& tb = tabs[i];
@@ -311,7 +306,7 @@ __global__ __launch_bounds__(THREADS) void k_bprobe(const BTable<Key>* __restric
                                                     BPrefix pre, uint32_t qtiles) {
     // each XCD walks a contiguous range of probe tiles, so a table's
     // offsets and keys are read through one L2
-    const uint32_t qt = xcd_map(blockIdx.x, qtiles);
+    const uint32_t qt = xcd_tile(blockIdx.x, qtiles);
     if (qt >= qtiles) return;
     const uint32_t i = find_table(pre.qtile, pre.T, qt);
     const BTable<Key>& tb = tabs[i];

@@ -139,6 +139,15 @@ struct KeyTraits<uint64_t> {
     }
 };
 
+// Workgroups are dispatched round-robin over the 8 XCDs.  Block b of a grid
+// of 8 * ceil(ub / 8) blocks takes tile (b % 8) * per + b / 8, so each XCD
+// walks one contiguous range of tiles, and what neighbouring tiles read or
+// write meets in that XCD's L2.  Tiles at or past ub are empty.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t ub) {
+    const uint32_t per = (ub + 7) >> 3;
+    return (b & 7u) * per + (b >> 3);
+}
+
 // ---------------------------------------------------------------- wave64 ---
 
 __device__ __forceinline__ uint32_t lane_id() {

@@ -318,10 +318,20 @@ size_t probe_ws_bytes(uint64_t m);
 // null; 32-bit keys with the probe index): per query, 0x80 | the mask of the
 // matching keys when its bucket is held whole in its index entry, else 0 --
 // what the pairs pass needs instead of that entry.
+// xcd_order: query tiles are dealt out per XCD (xcd_tile), for queries that
+// are grouped by bucket range.
 template <typename Key>
 hipError_t run_probe_counts(const TableDev& t, const Key* queries, uint64_t m, uint32_t* counts,
                             unsigned long long* d_total, hipStream_t s,
-                            uint8_t* held = nullptr);
+                            uint8_t* held = nullptr, bool xcd_order = false);
+
+// The same counts (and total) with the queries first grouped by bucket range
+// and the counts put back in input order; ws holds
+// probe_grouped_ws_bytes(m, t.V, sizeof(Key)) bytes.
+size_t probe_grouped_ws_bytes(uint64_t m, uint64_t V, size_t key_size);
+template <typename Key>
+hipError_t run_probe_grouped(const TableDev& t, const Key* queries, uint64_t m, uint32_t* counts,
+                             unsigned long long* d_total, void* ws, hipStream_t s);
 
 // positions[j] = first pair slot of query j (exclusive scan of counts);
 // held: the counting pass's per-query codes, or null.

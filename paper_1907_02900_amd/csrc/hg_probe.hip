@@ -180,15 +180,20 @@ __device__ __forceinline__ uint8_t held_code(const uint4& e, Key q) {
 // Probe-Standard counts.  HEAD: each query reads its bucket's 16-byte index
 // entry (one random access for buckets of up to three 32-bit keys or one
 // 64-bit key); otherwise it reads
-// offsets[h], offsets[h+1] and scans the edge array.
+// offsets[h], offsets[h+1] and scans the edge array.  xcd_tiles = 0: block b
+// takes query tile b; else the grid has 8 * ceil(xcd_tiles / 8) blocks and
+// tiles are dealt out by xcd_tile, so that each XCD walks one contiguous run
+// of queries (queries grouped by bucket range then read one L2-sized window
+// of the index per XCD at a time).
 template <typename Key, bool HEAD>
 __global__ __launch_bounds__(kProbeThreads) void k_probe_count(
     const Key* __restrict__ q, uint64_t m, typename KeyTraits<Key>::Params hp,
     const uint32_t* __restrict__ off, const uint4* __restrict__ head, Runs<Key> runs,
     const Key* __restrict__ ekeys, uint32_t* __restrict__ counts,
-    unsigned long long* __restrict__ total, uint8_t* __restrict__ held) {
+    unsigned long long* __restrict__ total, uint8_t* __restrict__ held, uint32_t xcd_tiles) {
     __shared__ uint64_t red[kProbeThreads / kWave + 1];
-    const uint64_t base = (uint64_t)blockIdx.x * (kProbeThreads * kProbeItems) + threadIdx.x;
+    const uint32_t tile = xcd_tiles ? xcd_tile(blockIdx.x, xcd_tiles) : blockIdx.x;
+    const uint64_t base = (uint64_t)tile * (kProbeThreads * kProbeItems) + threadIdx.x;
     Key qq[kProbeItems];
     uint4 e[kProbeItems];
 #pragma unroll
@@ -455,25 +460,29 @@ size_t probe_ws_bytes(uint64_t m) {
 }
 
 uint64_t probe_total_slots(uint64_t m) {
-    return 1 + (m ? grid_for(m, kProbeThreads * kProbeItems) : 0);
+    // one per block, the grid rounded up to whole XCD rounds (xcd_order)
+    return 1 + (m ? 8 * (((uint64_t)grid_for(m, kProbeThreads * kProbeItems) + 7) / 8) : 0);
 }
 
 template <typename Key>
 hipError_t run_probe_counts(const TableDev& t, const Key* queries, uint64_t m, uint32_t* counts,
-                            unsigned long long* d_total, hipStream_t s, uint8_t* held) {
+                            unsigned long long* d_total, hipStream_t s, uint8_t* held,
+                            bool xcd_order) {
     if (m == 0) return d_total ? fill_u32((uint32_t*)d_total, 2, 0u, s) : hipSuccess;
     auto hp = KeyTraits<Key>::make(t.V, t.seed);
-    const dim3 grid(grid_for(m, kProbeThreads * kProbeItems));
+    const uint32_t tiles = grid_for(m, kProbeThreads * kProbeItems);
+    const uint32_t xt = xcd_order ? tiles : 0u;
+    const dim3 grid(xcd_order ? 8 * ((tiles + 7) / 8) : tiles);
     {
         HG_PROF("probe_count", s);
         if (t.head)
             hipLaunchKernelGGL((k_probe_count<Key, true>), grid, dim3(kProbeThreads), 0, s,
                                queries, m, hp, t.offsets, t.head, runs_of<Key>(t),
-                               (const Key*)t.keys, counts, d_total, held);
+                               (const Key*)t.keys, counts, d_total, held, xt);
         else
             hipLaunchKernelGGL((k_probe_count<Key, false>), grid, dim3(kProbeThreads), 0, s,
                                queries, m, hp, t.offsets, t.head, runs_of<Key>(t),
-                               (const Key*)t.keys, counts, d_total, (uint8_t*)nullptr);
+                               (const Key*)t.keys, counts, d_total, (uint8_t*)nullptr, xt);
     }
     HG_TRY(hipGetLastError());
     return d_total ? sum_u64(d_total + 1, grid.x, d_total, s) : hipSuccess;
@@ -538,7 +547,7 @@ hipError_t run_intersect_pairs(const TableDev& a, const TableDev& b, const uint6
 
 #define HG_PINST(Key)                                                                           \
     template hipError_t run_probe_counts<Key>(const TableDev&, const Key*, uint64_t, uint32_t*, \
-                                              unsigned long long*, hipStream_t, uint8_t*);      \
+                                              unsigned long long*, hipStream_t, uint8_t*, bool); \
     template hipError_t run_probe_pairs<Key>(const TableDev&, const Key*, uint64_t,             \
                                              const uint64_t*, uint32_t*, uint32_t*,             \
                                              hipStream_t, const uint8_t*);                      \

@@ -63,19 +63,16 @@ __device__ __forceinline__ bool locate_tile(const Segs& g, uint32_t t, uint32_t&
     return true;
 }
 
-// Workgroups are dispatched round-robin over the 8 XCDs.  Block b gets tile
-// (b % 8) * per + b / 8, so each XCD walks one contiguous range of tiles and
-// the runs that neighbouring tiles write for a digit meet in that XCD's L2.
-__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t ub) {
-    const uint32_t per = (ub + 7) >> 3;
-    return (b & 7u) * per + (b >> 3);
-}
+// (xcd_tile: the runs that neighbouring tiles write for a digit meet in
+// one XCD's L2)
 
 // ---------------------------------------------------- tile histograms -----
 
 // ID_DIGIT: the digit is a bit-field of the entry's id (ids[i] >> shift)
 // instead of the bucket of its key (the scatter by a permutation below).
-template <typename Key, bool ID_DIGIT = false>
+// QUERIES: the same code, instantiated apart for grouping a probe's queries
+// so that kernel traces tell it from the build's passes (also below).
+template <typename Key, bool ID_DIGIT = false, bool QUERIES = false>
 __global__ __launch_bounds__(kPartThreads) void k_tile_hist(const Key* __restrict__ keys, Segs g,
                                                             typename KeyTraits<Key>::Params hp,
                                                             uint32_t shift, uint32_t bits,
@@ -211,7 +208,7 @@ __global__ __launch_bounds__(256) void k_colscan_down(uint32_t* __restrict__ mat
 // digit.
 // STABLE: entries of equal digit keep their order (rank_stable); otherwise
 // their order inside a run is unspecified (rank_any, no ballots).
-template <typename Key, bool HAS_IDS, bool STABLE, bool ID_DIGIT = false>
+template <typename Key, bool HAS_IDS, bool STABLE, bool ID_DIGIT = false, bool QUERIES = false>
 __global__ __launch_bounds__(kPartThreads) void k_tile_partition(
     const Key* __restrict__ src_keys, const uint32_t* __restrict__ src_ids,
     Key* __restrict__ dst_keys, uint32_t* __restrict__ dst_ids, Segs g,
@@ -288,9 +285,112 @@ __global__ __launch_bounds__(kPartThreads) void k_tile_partition(
         const uint32_t o = tbase[sdig[p]] + p;
         if (o - seg_lo < seg_len) {
             dst_keys[o] = skeys[p];
-            dst_ids[o] = sids[p];
+            if (HAS_IDS || dst_ids) dst_ids[o] = sids[p];  // positions may be dropped
         }
     }
+}
+
+// ------------------------------------------------------ grouped probing ---
+
+// Puts values computed in grouped order back in input order.  Entry e of
+// partition tile t was written (HAS_IDS = false, so its id is its input
+// position) to base(t, d) + its rank inside the tile's run of digit d, with
+// its position in gpos.  The runs of kUngroupTiles consecutive tiles are
+// adjacent in grouped order, so one workgroup takes such a group of tiles:
+// its run of digit d is [base(t0, d), next(t1, d)), next being base(t1, d),
+// or past the last tile the start of digit d + 1 (m after the last digit),
+// long enough that every read uses whole lines.  Each thread takes entries
+// of the group's runs in order (a binary search over the runs' starts gives
+// the digit: skew only lengthens runs), loads position and value, places the
+// value in LDS by its position, and the group's values are then written in
+// input order.  One segment (S = 1).
+constexpr uint32_t kUngroupThreads = 1024;
+constexpr uint32_t kUngroupTiles = 4;
+constexpr uint32_t kUngroupSpan = kUngroupTiles * kPartTile;  // entries per workgroup
+
+__global__ __launch_bounds__(kUngroupThreads) void k_ungroup_by_pos(
+    uint64_t m, uint32_t ntiles, uint32_t bits, const uint32_t* __restrict__ base,
+    uint32_t groups, const uint32_t* __restrict__ gpos, const uint32_t* __restrict__ src,
+    uint32_t* __restrict__ dst) {
+    extern __shared__ __align__(16) uint32_t ush[];
+    uint32_t* sval = ush;                          // [kUngroupSpan]
+    uint32_t* rstart = sval + kUngroupSpan;        // [D + 1] run starts inside the group
+    uint32_t* rbase = rstart + (1u << bits) + 1;   // [D] grouped start - run start
+    uint32_t* tmp = rbase + (1u << bits);          // [kUngroupThreads / 64 + 1]
+    const uint32_t D = 1u << bits;
+    const uint32_t gi = xcd_tile(blockIdx.x, groups);
+    if (gi >= groups) return;
+    const uint32_t t0 = gi * kUngroupTiles;
+    const uint32_t t1 = t0 + kUngroupTiles < ntiles ? t0 + kUngroupTiles : ntiles;
+    const uint64_t begin = (uint64_t)t0 * kPartTile;
+    const uint64_t end64 = (uint64_t)t1 * kPartTile;
+    const uint32_t cnt = (uint32_t)((end64 < m ? end64 : m) - begin);
+    constexpr uint32_t kPer = (1u << kMaxDigitBits) / kUngroupThreads;
+    const uint32_t per = (D + kUngroupThreads - 1) / kUngroupThreads;
+    const uint32_t d0 = threadIdx.x * per;
+    const uint32_t* row = base + (size_t)t0 * D;
+    const uint32_t* nrow = base + (size_t)t1 * D;
+    uint32_t b[kPer], c[kPer];
+    uint32_t mine = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < kPer; ++j) {
+        const uint32_t d = d0 + j;
+        b[j] = c[j] = 0;
+        if (j < per && d < D) {
+            b[j] = row[d];
+            const uint32_t nx =
+                t1 < ntiles ? nrow[d] : (d + 1 < D ? base[d + 1] : (uint32_t)m);
+            c[j] = nx - b[j];
+        }
+        mine += c[j];
+    }
+    uint32_t all;
+    uint32_t run = block_excl_scan<kUngroupThreads>(mine, tmp, &all);
+#pragma unroll
+    for (uint32_t j = 0; j < kPer; ++j) {
+        const uint32_t d = d0 + j;
+        if (j < per && d < D) {
+            rstart[d] = run;
+            rbase[d] = b[j] - run;
+            run += c[j];
+        }
+    }
+    __syncthreads();
+    // all grouped positions of a thread first, then their loads, so that the
+    // loads overlap
+    constexpr int IT = kUngroupSpan / kUngroupThreads;
+    uint32_t o[IT];
+#pragma unroll
+    for (int r = 0; r < IT; ++r) {
+        const uint32_t p = r * kUngroupThreads + threadIdx.x;
+        o[r] = ~0u;
+        if (p < cnt) {
+            uint32_t lo = 0, hi = D;  // the last digit whose run starts at or before p
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (rstart[mid] <= p) lo = mid;
+                else hi = mid;
+            }
+            o[r] = rbase[lo] + p;
+        }
+    }
+    uint32_t gp[IT], v[IT];
+#pragma unroll
+    for (int r = 0; r < IT; ++r) {
+        gp[r] = o[r] < m ? gpos[o[r]] : 0u;
+        v[r] = o[r] < m ? src[o[r]] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < IT; ++r) {
+        const uint64_t li = (uint64_t)gp[r] - begin;
+        if (o[r] < m && li < cnt) sval[li] = v[r];
+    }
+    __syncthreads();
+    for (uint32_t p = threadIdx.x; p < cnt; p += kUngroupThreads) dst[begin + p] = sval[p];
+}
+
+size_t ungroup_smem(uint32_t bits) {
+    return 4 * ((size_t)kUngroupSpan + 2 * ((size_t)1 << bits) + 1 + kUngroupThreads / 64 + 1);
 }
 
 template <typename Key>
@@ -772,21 +872,22 @@ size_t layout_v2(void* ws, const V2Plan& p, size_t key_size, V2Ws* out) {
     return c.off + 256;
 }
 
+// for_probe: profiled under the grouped probe's names
 hipError_t colscan(uint32_t* mat, const Segs& g, uint32_t D, uint32_t* csum, uint32_t nchunks_ub,
-                   hipStream_t s) {
+                   hipStream_t s, bool for_probe) {
     {
-        HG_PROF("v2_colscan_reduce", s);
+        HG_PROF(for_probe ? "probe_group_scan_reduce" : "v2_colscan_reduce", s);
         hipLaunchKernelGGL(k_colscan_reduce, dim3(nchunks_ub), dim3(256), 0, s,
                            (const uint32_t*)mat, g, D, csum);
     }
     HG_TRY(hipGetLastError());
     {
-        HG_PROF("v2_colscan_seg", s);
+        HG_PROF(for_probe ? "probe_group_scan_seg" : "v2_colscan_seg", s);
         hipLaunchKernelGGL(k_colscan_seg, dim3(g.S), dim3(256), 0, s, g, D, csum);
     }
     HG_TRY(hipGetLastError());
     {
-        HG_PROF("v2_colscan_down", s);
+        HG_PROF(for_probe ? "probe_group_scan_down" : "v2_colscan_down", s);
         hipLaunchKernelGGL(k_colscan_down, dim3(nchunks_ub), dim3(256), 0, s, mat, g, D,
                            (const uint32_t*)csum);
     }
@@ -805,6 +906,8 @@ void launch_partition(dim3 grid, size_t smem, hipStream_t s, const Key* src_keys
 
 // One stable (or any-order) partition pass over the tiles of segments g.
 // id_digit (32-bit entries with ids only): the digit comes from the id.
+// tier: 1 or 2 for the build's passes, 3 for grouping the queries of a probe
+// (profiled under its own names); dst_ids may be null without src_ids.
 template <typename Key>
 hipError_t partition_pass(const Key* src_keys, const uint32_t* src_ids, Key* dst_keys,
                           uint32_t* dst_ids, const Segs& g, typename KeyTraits<Key>::Params hp,
@@ -816,24 +919,31 @@ hipError_t partition_pass(const Key* src_keys, const uint32_t* src_ids, Key* dst
     if (id_digit && (sizeof(Key) != 4 || !src_ids || stable)) return hipErrorInvalidValue;
     if (bits > kMaxDigitBits) return hipErrorInvalidValue;  // the kernels hold at most 2048 digits
     {
-        HG_PROF(tier == 1 ? "v2_tile_hist_t1" : "v2_tile_hist_t2", s);
+        HG_PROF(tier == 1 ? "v2_tile_hist_t1" : tier == 2 ? "v2_tile_hist_t2" : "probe_group_hist", s);
         if (id_digit)
             hipLaunchKernelGGL((k_tile_hist<Key, true>), dim3(grid), dim3(kPartThreads), D * 4, s,
                                src_keys, g, hp, shift, bits, mat, tiles_ub, src_ids);
+        else if (tier == 3)
+            hipLaunchKernelGGL((k_tile_hist<Key, false, true>), dim3(grid), dim3(kPartThreads),
+                               D * 4, s, src_keys, g, hp, shift, bits, mat, tiles_ub, nullptr);
         else
             hipLaunchKernelGGL((k_tile_hist<Key, false>), dim3(grid), dim3(kPartThreads), D * 4, s,
                                src_keys, g, hp, shift, bits, mat, tiles_ub, nullptr);
     }
     HG_TRY(hipGetLastError());
-    HG_TRY(colscan(mat, g, D, csum, nchunks_ub, s));
+    HG_TRY(colscan(mat, g, D, csum, nchunks_ub, s, tier == 3));
     const size_t smem = partition_smem<Key>(bits);
     {
-        HG_PROF(tier == 1 ? "v2_partition_t1" : "v2_partition_t2", s);
+        HG_PROF(tier == 1 ? "v2_partition_t1" : tier == 2 ? "v2_partition_t2" : "probe_group", s);
         const dim3 gr(grid);
         if (id_digit)
             hipLaunchKernelGGL((k_tile_partition<Key, true, false, true>), gr, dim3(kPartThreads),
                                smem, s, src_keys, src_ids, dst_keys, dst_ids, g, hp, shift, bits,
                                (const uint32_t*)mat, tiles_ub);
+        else if (tier == 3 && !src_ids && !stable)
+            hipLaunchKernelGGL((k_tile_partition<Key, false, false, false, true>), gr,
+                               dim3(kPartThreads), smem, s, src_keys, src_ids, dst_keys, dst_ids,
+                               g, hp, shift, bits, (const uint32_t*)mat, tiles_ub);
         else if (src_ids && stable)
             launch_partition<Key, true, true>(gr, smem, s, src_keys, src_ids, dst_keys, dst_ids,
                                               g, hp, shift, bits, mat, tiles_ub);
@@ -865,11 +975,15 @@ hipError_t set_smem_limits() {
                                    hipFuncAttributeMaxDynamicSharedMemorySize, lim));
         HG_TRY(hipFuncSetAttribute((const void*)k_tile_partition<Key, false, false>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+        HG_TRY(hipFuncSetAttribute((const void*)k_tile_partition<Key, false, false, false, true>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, lim));
         HG_TRY(hipFuncSetAttribute((const void*)k_local_light<Key>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, lim));
         HG_TRY(hipFuncSetAttribute((const void*)k_local_heavy<Key>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, lim));
         HG_TRY(hipFuncSetAttribute((const void*)k_huge_place<Key>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+        HG_TRY(hipFuncSetAttribute((const void*)k_ungroup_by_pos,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, lim));
         return hipSuccess;
     });
@@ -1083,6 +1197,103 @@ hipError_t scatter_perm(const uint32_t* ids, const uint32_t* vals, uint64_t n, u
     }
     return hipGetLastError();
 }
+
+// --------------------------------------------- grouped Probe-Standard ---
+// The queries are first partitioned into up to 2^kGroupBits ranges of
+// buckets with their input positions (one tile-histogram, column-scan and
+// partition pass, as in the build), probed in that order with the tiles
+// dealt out per XCD -- each XCD then reads one window of the index at a time
+// (8 MiB at 2^28 buckets), which its L2 holds, instead of random lines of
+// the whole index -- and the counts are put back in input order by
+// k_ungroup_by_pos.
+
+namespace {
+
+constexpr uint32_t kGroupBits = 9;
+
+struct GroupPlan {
+    uint32_t bits, shift, ntiles, ch, nchunks;
+};
+
+GroupPlan group_plan(uint64_t m, uint64_t V) {
+    GroupPlan p;
+    const uint32_t kv = log2_ceil(V);
+    p.bits = kv < kGroupBits ? (kv ? kv : 1u) : kGroupBits;  // at least two ranges
+    p.shift = kv > p.bits ? kv - p.bits : 0u;
+    p.ntiles = (uint32_t)ceil_div(m, kPartTile);
+    p.ch = (uint32_t)pow2_ceil(ceil_div(p.ntiles ? p.ntiles : 1, 256));
+    p.nchunks = (uint32_t)ceil_div(p.ntiles, p.ch);
+    return p;
+}
+
+struct GroupWs {
+    void* gq;        // the queries in grouped order
+    uint32_t* gpos;  // their input positions
+    uint32_t* gc;    // their counts in grouped order
+    uint32_t *mat, *csum, *ctr;
+    Segs seg;
+};
+
+size_t layout_group(void* ws, const GroupPlan& p, uint64_t m, size_t key_size, GroupWs* out) {
+    Carver c(ws);
+    GroupWs w{};
+    const uint32_t D = 1u << p.bits;
+    w.gq = c.take<char>(m * key_size);
+    w.gpos = c.take<uint32_t>(m);
+    w.gc = c.take<uint32_t>(m);
+    w.mat = c.take<uint32_t>((size_t)p.ntiles * D);
+    w.csum = c.take<uint32_t>((size_t)p.nchunks * D);
+    w.ctr = c.take<uint32_t>(5);
+    w.seg.seg_start = c.take<uint32_t>(2);
+    w.seg.tile_prefix = c.take<uint32_t>(2);
+    w.seg.chunk_prefix = c.take<uint32_t>(2);
+    w.seg.S = 1;
+    w.seg.ch = p.ch;
+    if (out) *out = w;
+    return c.off + 256;
+}
+
+}  // namespace
+
+size_t probe_grouped_ws_bytes(uint64_t m, uint64_t V, size_t key_size) {
+    return layout_group(nullptr, group_plan(m, V), m, key_size, nullptr);
+}
+
+template <typename Key>
+hipError_t run_probe_grouped(const TableDev& t, const Key* queries, uint64_t m, uint32_t* counts,
+                             unsigned long long* d_total, void* ws, hipStream_t s) {
+    if (m == 0) return run_probe_counts<Key>(t, queries, m, counts, d_total, s);
+    HG_TRY(set_smem_limits<Key>());
+    const GroupPlan p = group_plan(m, t.V);
+    GroupWs w;
+    layout_group(ws, p, m, sizeof(Key), &w);
+    const auto hp = KeyTraits<Key>::make(t.V, t.seed);
+    hipLaunchKernelGGL(k_segs_single, dim3(1), dim3(64), 0, s, w.seg, (uint32_t)m, p.ntiles,
+                       p.nchunks, w.ctr);
+    HG_TRY(hipGetLastError());
+    Key* gq = (Key*)w.gq;
+    // positions only when the counts go back to input order
+    HG_TRY(partition_pass<Key>(queries, nullptr, gq, counts ? w.gpos : nullptr, w.seg, hp,
+                               p.shift, p.bits, w.mat, w.csum, p.ntiles, p.nchunks, 3, false, s));
+    HG_TRY(run_probe_counts<Key>(t, gq, m, counts ? w.gc : nullptr, d_total, s, nullptr, true));
+    if (!counts) return hipSuccess;
+    {
+        HG_PROF("probe_ungroup", s);
+        const uint32_t groups = (uint32_t)ceil_div(p.ntiles, kUngroupTiles);
+        const uint32_t grid = (uint32_t)(8 * ceil_div(groups, 8));
+        hipLaunchKernelGGL(k_ungroup_by_pos, dim3(grid), dim3(kUngroupThreads),
+                           ungroup_smem(p.bits), s, m, p.ntiles, p.bits, (const uint32_t*)w.mat,
+                           groups, (const uint32_t*)w.gpos, (const uint32_t*)w.gc, counts);
+    }
+    return hipGetLastError();
+}
+
+template hipError_t run_probe_grouped<uint32_t>(const TableDev&, const uint32_t*, uint64_t,
+                                                uint32_t*, unsigned long long*, void*,
+                                                hipStream_t);
+template hipError_t run_probe_grouped<uint64_t>(const TableDev&, const uint64_t*, uint64_t,
+                                                uint32_t*, unsigned long long*, void*,
+                                                hipStream_t);
 
 template hipError_t run_build_v2<uint32_t>(const uint32_t*, uint64_t, uint64_t, uint64_t,
                                            uint32_t*, uint32_t*, uint32_t*, IndexOut&, void*,

@@ -119,6 +119,7 @@ def lib():
         "hg_table_export": ([vp, vp, vp, vp, vp], i32),
         "hg_table_free": ([vp], None),
         "hg_probe": ([vp, vp, u64, vp, pu64, vp], i32),
+        "hg_probe_ordered": ([vp, vp, u64, vp, pu64, i32, vp], i32),
         "hg_probe_pairs": ([vp, vp, u64, vp, vp, u64, pu64, vp], i32),
         "hg_probe_pairs_noalloc": ([vp, vp, u64, vp, vp, u64, pu64, vp], i32),
         "hg_intersect": ([vp, vp, vp, vp, vp, u64, pu64, vp], i32),
@@ -409,6 +410,24 @@ def hg_probe(table: Table, queries: torch.Tensor, counts=True, total=False, out=
     tot = ctypes.c_uint64(0)
     _check(lib().hg_probe(table.handle, _ptr(queries), queries.numel(), _ptr(c),
                           ctypes.byref(tot) if total else None, _stream(stream)), "hg_probe")
+    return c, (int(tot.value) if total else None)
+
+
+PROBE_AUTO, PROBE_INPUT_ORDER, PROBE_GROUPED = 0, 1, 2
+
+
+def hg_probe_ordered(table: Table, queries: torch.Tensor, order: int, counts=True, total=False,
+                     out=None, stream=None):
+    """hg_probe with the probing order given: PROBE_INPUT_ORDER, PROBE_GROUPED
+    (queries grouped by bucket range first) or PROBE_AUTO."""
+    queries = _dev_keys(queries)
+    c = None
+    if counts:
+        c = out if out is not None else _u32(queries.numel(), queries.device)
+    tot = ctypes.c_uint64(0)
+    _check(lib().hg_probe_ordered(table.handle, _ptr(queries), queries.numel(), _ptr(c),
+                                  ctypes.byref(tot) if total else None, int(order),
+                                  _stream(stream)), "hg_probe_ordered")
     return c, (int(tot.value) if total else None)
 
 

@@ -36,6 +36,10 @@ import sys
 # library kernel -> name of the timed range bench.py reports it under
 RANGES = [
     ("k_probe_count", "probe_count"),
+    # the probe's query grouping before the build's passes of the same code
+    ("k_tile_partition<unsigned int, false, false, false, true", "probe_group"),
+    ("k_tile_hist<unsigned int, false, true", "probe_group_hist"),
+    ("k_ungroup_by_pos", "probe_ungroup"),
     ("k_local_light", "v2_local_build"),
     ("k_local_heavy", "v2_local_heavy"),
     ("k_tile_partition<unsigned int, false", "v2_partition_t1"),

@@ -150,6 +150,9 @@ def test_erase_any_order_table_and_rebuild(hg):
     q = workloads.probe_queries(k, 80000, 0.5, seed=22)
     c, _ = hg.hg_probe(t, hg.to_device(q))
     assert np.array_equal(hg.to_numpy(c, np.uint32), oracle.probe_counts(k[live], q)[0])
+    # queries grouped by bucket range see the same live lengths
+    c, _ = hg.hg_probe_ordered(t, hg.to_device(q), hg.PROBE_GROUPED)
+    assert np.array_equal(hg.to_numpy(c, np.uint32), oracle.probe_counts(k[live], q)[0])
     # a rebuild starts from a full table again
     t.rebuild(hg.to_device(k), V, seed=2)
     assert t.lengths() is None and t.live() == n

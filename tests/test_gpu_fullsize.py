@@ -100,7 +100,8 @@ def test_full_uniform_bench_step(hg, uniform, layout):
     """The benchmark's timed step exactly as bench.py runs it: a table created
     at capacity (2^28 keys, V = 2^28), rebuilt in place with the probe index
     (any order, as timed by default; stable with --stable), then
-    Probe-Standard counts of all 2^28 queries into a preallocated buffer.
+    Probe-Standard counts of all 2^28 queries into a preallocated buffer
+    (grouped by bucket range, as hg_probe chooses here, and in input order).
     Offsets are exact; the buckets, as multisets, equal the oracle's (ids
     sorted inside each bucket equal torch's stable argsort of the oracle's
     buckets); the stable layout equals it entry for entry; every count and the
@@ -119,6 +120,12 @@ def test_full_uniform_bench_step(hg, uniform, layout):
     torch.cuda.synchronize()
     assert np.array_equal(hg.to_numpy(counts, np.uint32), exp)
     assert tot == etot
+    # hg_probe groups the queries by bucket range at this size; the same
+    # counts probed in input order
+    counts.fill_(-1)
+    hg.hg_probe_ordered(table, dq, hg.PROBE_INPUT_ORDER, out=counts)
+    torch.cuda.synchronize()
+    assert np.array_equal(hg.to_numpy(counts, np.uint32), exp)
     del counts
     h = torch.from_numpy(oracle.hash_buckets(keys, V, 0).astype(np.int64)).cuda()
     off, ids = check_table(hg, table, u64(dk), h, V, stable=not any_order)

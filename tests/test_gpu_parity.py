@@ -235,6 +235,46 @@ def test_probe_counts_match_oracle(hg, kb, variant, kind, n, m, V):
 
 
 @pytest.mark.parametrize("kb", [32, 64])
+@pytest.mark.parametrize("kind,n,m,V,index", [
+    ("uniform", 0, 5000, 7, True),                    # empty table
+    ("uniform", 1000, 1, 1000, True),                 # one query
+    ("uniform", 100003, 3 * 4096 + 123, 100003, True),  # a few tiles and a ragged tail
+    ("uniform", 300007, 300007, 300007, True),        # 1024 ranges, V not a power of two
+    ("uniform", 200000, 250001, 600, True),           # fewer buckets than ranges
+    ("uniform", 50000, 70000, 1, True),               # one bucket, one range
+    ("dup8", 300000, 300000, 1 << 16, False),         # no index: offsets and edge scans
+    ("zipf", 200000, 300000, 200000, True),           # long buckets answered by key runs
+    ("uniform", 400000, 300000, 50000, True)])        # buckets of 4..32 keys
+def test_grouped_probe_matches_oracle(hg, kb, kind, n, m, V, index):
+    # queries partitioned by bucket range, probed range by range and their
+    # counts put back in input order: the same counts and total as the oracle,
+    # over stable and any-order tables, in both probing orders
+    say("grouped probe", kb, kind, n, m, V, index)
+    k = keys_for(kind, n, kb, seed=31)
+    q = workloads.probe_queries(k if n else workloads.uniform_keys(8, kb, 0), m, 0.5, seed=32,
+                                key_bits=kb)
+    exp, etot = oracle.probe_counts(k, q, kb)
+    dq = hg.to_device(q)
+    for any_order in (False, True):
+        t = hg.hg_build(hg.to_device(k), V, seed=33, index=index, any_order=any_order)
+        for order in (hg.PROBE_GROUPED, hg.PROBE_INPUT_ORDER, hg.PROBE_AUTO):
+            c, tot = hg.hg_probe_ordered(t, dq, order, counts=True, total=True)
+            assert np.array_equal(hg.to_numpy(c, np.uint32), exp), (any_order, order)
+            assert tot == etot
+        _, tot = hg.hg_probe_ordered(t, dq, hg.PROBE_GROUPED, counts=False, total=True)
+        assert tot == etot
+        c, tot = hg.hg_probe_ordered(t, dq[:0], hg.PROBE_GROUPED, total=True)
+        assert c.numel() == 0 and tot == 0
+
+
+def test_grouped_probe_rejects_unknown_order(hg):
+    k = workloads.uniform_keys(1000, 32, 3)
+    t = hg.hg_build(hg.to_device(k), 1000, seed=1)
+    with pytest.raises(hg.HGError):
+        hg.hg_probe_ordered(t, hg.to_device(k), 3)
+
+
+@pytest.mark.parametrize("kb", [32, 64])
 def test_probe_pairs_match_oracle_in_canonical_order(hg, kb):
     n, m, V = 200003, 150001, 100000
     say("pairs", kb)
