@@ -326,14 +326,19 @@ hg_status hg_probe(const hg_table *t, const void *d_queries, uint64_t m, uint32_
  *     counts are put back in input order.  Needs m * (key_bits / 8 + 8) bytes
  *     of workspace plus 2 KiB per 4096 queries (from the allocator,
  *     hg_set_allocator).
- *   HG_PROBE_AUTO: grouped when the table has a probe index,
- *     m >= hash_range / 2 and hash_range >= 2^27 (2^26 when only the total
- *     is asked for), the sizes from which grouping measured faster; else
- *     input order.
+ *   HG_PROBE_GROUPED_UNLESS_SKEWED: the queries' histogram over the ranges
+ *     is taken first and, on the device, a range holding more than 8 times
+ *     its share of them (skewed queries, whose index lines stay cached
+ *     anyway) keeps input order; else grouped.  Workspace as for grouped.
+ *   HG_PROBE_AUTO: HG_PROBE_GROUPED_UNLESS_SKEWED when the table has a probe
+ *     index, m >= hash_range / 2 and hash_range >= 2^27 (2^26 when only the
+ *     total is asked for), the sizes from which grouping measured faster;
+ *     else input order.
  * Any other order is HG_ERR_INVALID_ARG. */
 #define HG_PROBE_AUTO 0
 #define HG_PROBE_INPUT_ORDER 1
 #define HG_PROBE_GROUPED 2
+#define HG_PROBE_GROUPED_UNLESS_SKEWED 3
 hg_status hg_probe_ordered(const hg_table *t, const void *d_queries, uint64_t m,
                            uint32_t *d_counts, uint64_t *h_total, int32_t order,
                            hipStream_t stream);

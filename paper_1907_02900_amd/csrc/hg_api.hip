@@ -793,12 +793,13 @@ hg_status hg_probe_ordered(const hg_table* t, const void* d_queries, uint64_t m,
                            hipStream_t stream) {
     if (check_table_arg(t) != HG_OK || m > kU32Max || (m && !d_queries)) return HG_ERR_INVALID_ARG;
     if (!d_counts && !h_total) return HG_ERR_INVALID_ARG;
-    if (order != HG_PROBE_AUTO && order != HG_PROBE_INPUT_ORDER && order != HG_PROBE_GROUPED)
+    if (order != HG_PROBE_AUTO && order != HG_PROBE_INPUT_ORDER && order != HG_PROBE_GROUPED &&
+        order != HG_PROBE_GROUPED_UNLESS_SKEWED)
         return HG_ERR_INVALID_ARG;
     if (t->V == 0) return HG_ERR_INVALID_ARG;  // never built
     if (device_ready() != HG_OK) return HG_ERR_DEVICE;
     TableDev d = dev_view(t);
-    bool grouped = order == HG_PROBE_GROUPED;
+    bool grouped = order == HG_PROBE_GROUPED || order == HG_PROBE_GROUPED_UNLESS_SKEWED;
     if (order == HG_PROBE_AUTO)  // where grouping measured faster on MI355X
         grouped = d.head != nullptr && m >= t->V / 2 &&
                   t->V >= (d_counts ? (1ull << 27) : (1ull << 26));
@@ -810,10 +811,12 @@ hg_status hg_probe_ordered(const hg_table* t, const void* d_queries, uint64_t m,
     unsigned long long* d_total = h_total ? (unsigned long long*)ws.p : nullptr;
     void* gws = (char*)ws.p + tot_bytes;
     hipError_t e;
+    // skewed queries keep input order, decided on the device
+    const bool decide = order == HG_PROBE_AUTO || order == HG_PROBE_GROUPED_UNLESS_SKEWED;
     if (grouped)
         e = t->key_bits == 32
-                ? run_probe_grouped<uint32_t>(d, (const uint32_t*)d_queries, m, d_counts, d_total, gws, stream)
-                : run_probe_grouped<uint64_t>(d, (const uint64_t*)d_queries, m, d_counts, d_total, gws, stream);
+                ? run_probe_grouped<uint32_t>(d, (const uint32_t*)d_queries, m, d_counts, d_total, gws, stream, decide)
+                : run_probe_grouped<uint64_t>(d, (const uint64_t*)d_queries, m, d_counts, d_total, gws, stream, decide);
     else
         e = t->key_bits == 32
                 ? run_probe_counts<uint32_t>(d, (const uint32_t*)d_queries, m, d_counts, d_total, stream)

@@ -319,19 +319,27 @@ size_t probe_ws_bytes(uint64_t m);
 // matching keys when its bucket is held whole in its index entry, else 0 --
 // what the pairs pass needs instead of that entry.
 // xcd_order: query tiles are dealt out per XCD (xcd_tile), for queries that
-// are grouped by bucket range.
+// are grouped by bucket range.  gate (device, may be null): when *gate == 0
+// the launch probes q_in into counts_in in input order instead.
 template <typename Key>
 hipError_t run_probe_counts(const TableDev& t, const Key* queries, uint64_t m, uint32_t* counts,
                             unsigned long long* d_total, hipStream_t s,
-                            uint8_t* held = nullptr, bool xcd_order = false);
+                            uint8_t* held = nullptr, bool xcd_order = false,
+                            const uint32_t* gate = nullptr, const Key* q_in = nullptr,
+                            uint32_t* counts_in = nullptr);
 
 // The same counts (and total) with the queries first grouped by bucket range
 // and the counts put back in input order; ws holds
-// probe_grouped_ws_bytes(m, t.V, sizeof(Key)) bytes.
+// probe_grouped_ws_bytes(m, t.V, sizeof(Key)) bytes.  decide: a sample of
+// the queries taken on the device first picks input order instead when one
+// range would hold more than kGroupSkew times its share of them (skewed
+// queries read few index lines, which stay cached anyway); the grouping
+// passes then find no tiles and the probe launch reads the queries in place.
 size_t probe_grouped_ws_bytes(uint64_t m, uint64_t V, size_t key_size);
 template <typename Key>
 hipError_t run_probe_grouped(const TableDev& t, const Key* queries, uint64_t m, uint32_t* counts,
-                             unsigned long long* d_total, void* ws, hipStream_t s);
+                             unsigned long long* d_total, void* ws, hipStream_t s,
+                             bool decide = false);
 
 // positions[j] = first pair slot of query j (exclusive scan of counts);
 // held: the counting pass's per-query codes, or null.

@@ -184,15 +184,24 @@ __device__ __forceinline__ uint8_t held_code(const uint4& e, Key q) {
 // takes query tile b; else the grid has 8 * ceil(xcd_tiles / 8) blocks and
 // tiles are dealt out by xcd_tile, so that each XCD walks one contiguous run
 // of queries (queries grouped by bucket range then read one L2-sized window
-// of the index per XCD at a time).
+// of the index per XCD at a time).  gate (may be null): when *gate == 0 the
+// launch probes q_in into counts_in instead, block b taking tile b (the
+// grouped probe decides on the device whether its queries were grouped).
 template <typename Key, bool HEAD>
 __global__ __launch_bounds__(kProbeThreads) void k_probe_count(
     const Key* __restrict__ q, uint64_t m, typename KeyTraits<Key>::Params hp,
     const uint32_t* __restrict__ off, const uint4* __restrict__ head, Runs<Key> runs,
     const Key* __restrict__ ekeys, uint32_t* __restrict__ counts,
-    unsigned long long* __restrict__ total, uint8_t* __restrict__ held, uint32_t xcd_tiles) {
+    unsigned long long* __restrict__ total, uint8_t* __restrict__ held, uint32_t xcd_tiles,
+    const uint32_t* __restrict__ gate, const Key* __restrict__ q_in,
+    uint32_t* __restrict__ counts_in) {
     __shared__ uint64_t red[kProbeThreads / kWave + 1];
-    const uint32_t tile = xcd_tiles ? xcd_tile(blockIdx.x, xcd_tiles) : blockIdx.x;
+    uint32_t tile = xcd_tiles ? xcd_tile(blockIdx.x, xcd_tiles) : blockIdx.x;
+    if (gate && *gate == 0u) {
+        q = q_in;
+        counts = counts_in;
+        tile = blockIdx.x;
+    }
     const uint64_t base = (uint64_t)tile * (kProbeThreads * kProbeItems) + threadIdx.x;
     Key qq[kProbeItems];
     uint4 e[kProbeItems];
@@ -467,7 +476,8 @@ uint64_t probe_total_slots(uint64_t m) {
 template <typename Key>
 hipError_t run_probe_counts(const TableDev& t, const Key* queries, uint64_t m, uint32_t* counts,
                             unsigned long long* d_total, hipStream_t s, uint8_t* held,
-                            bool xcd_order) {
+                            bool xcd_order, const uint32_t* gate, const Key* q_in,
+                            uint32_t* counts_in) {
     if (m == 0) return d_total ? fill_u32((uint32_t*)d_total, 2, 0u, s) : hipSuccess;
     auto hp = KeyTraits<Key>::make(t.V, t.seed);
     const uint32_t tiles = grid_for(m, kProbeThreads * kProbeItems);
@@ -478,11 +488,13 @@ hipError_t run_probe_counts(const TableDev& t, const Key* queries, uint64_t m, u
         if (t.head)
             hipLaunchKernelGGL((k_probe_count<Key, true>), grid, dim3(kProbeThreads), 0, s,
                                queries, m, hp, t.offsets, t.head, runs_of<Key>(t),
-                               (const Key*)t.keys, counts, d_total, held, xt);
+                               (const Key*)t.keys, counts, d_total, held, xt, gate, q_in,
+                               counts_in);
         else
             hipLaunchKernelGGL((k_probe_count<Key, false>), grid, dim3(kProbeThreads), 0, s,
                                queries, m, hp, t.offsets, t.head, runs_of<Key>(t),
-                               (const Key*)t.keys, counts, d_total, (uint8_t*)nullptr, xt);
+                               (const Key*)t.keys, counts, d_total, (uint8_t*)nullptr, xt,
+                               gate, q_in, counts_in);
     }
     HG_TRY(hipGetLastError());
     return d_total ? sum_u64(d_total + 1, grid.x, d_total, s) : hipSuccess;
@@ -547,7 +559,8 @@ hipError_t run_intersect_pairs(const TableDev& a, const TableDev& b, const uint6
 
 #define HG_PINST(Key)                                                                           \
     template hipError_t run_probe_counts<Key>(const TableDev&, const Key*, uint64_t, uint32_t*, \
-                                              unsigned long long*, hipStream_t, uint8_t*, bool); \
+                                              unsigned long long*, hipStream_t, uint8_t*, bool,  \
+                                              const uint32_t*, const Key*, uint32_t*);           \
     template hipError_t run_probe_pairs<Key>(const TableDev&, const Key*, uint64_t,             \
                                              const uint64_t*, uint32_t*, uint32_t*,             \
                                              hipStream_t, const uint8_t*);                      \

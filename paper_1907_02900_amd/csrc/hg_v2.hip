@@ -311,7 +311,8 @@ constexpr uint32_t kUngroupSpan = kUngroupTiles * kPartTile;  // entries per wor
 __global__ __launch_bounds__(kUngroupThreads) void k_ungroup_by_pos(
     uint64_t m, uint32_t ntiles, uint32_t bits, const uint32_t* __restrict__ base,
     uint32_t groups, const uint32_t* __restrict__ gpos, const uint32_t* __restrict__ src,
-    uint32_t* __restrict__ dst) {
+    uint32_t* __restrict__ dst, const uint32_t* __restrict__ gate) {
+    if (gate && *gate != 1u) return;  // the probe kept input order
     extern __shared__ __align__(16) uint32_t ush[];
     uint32_t* sval = ush;                          // [kUngroupSpan]
     uint32_t* rstart = sval + kUngroupSpan;        // [D + 1] run starts inside the group
@@ -387,6 +388,65 @@ __global__ __launch_bounds__(kUngroupThreads) void k_ungroup_by_pos(
     }
     __syncthreads();
     for (uint32_t p = threadIdx.x; p < cnt; p += kUngroupThreads) dst[begin + p] = sval[p];
+}
+
+// A range holding more than kGroupSkew times an even share of the sampled
+// queries keeps a probe in input order.
+constexpr uint32_t kGroupSkew = 8;
+
+// Whether grouping pays for these queries, from a sample: up to kGroupSample
+// queries spread evenly over the input are hashed into the ranges, and when
+// one range holds more than kGroupSkew times an even share of them the probe
+// keeps input order (skewed queries read few index lines, which stay cached
+// anyway).  Writes the one segment of the grouping passes -- with no tiles
+// at all for input order, so that every grouping kernel returns at once --
+// and gate[0] = 1 (grouped) or 0 (input order).  One workgroup.
+constexpr uint32_t kGroupSample = 1u << 14;  // 16 per thread, loaded together
+
+template <typename Key>
+__global__ __launch_bounds__(1024) void k_group_sample(const Key* __restrict__ q, uint64_t m,
+                                                       typename KeyTraits<Key>::Params hp,
+                                                       uint32_t shift, uint32_t bits, Segs g,
+                                                       uint32_t ntiles, uint32_t nchunks,
+                                                       uint32_t* __restrict__ gate) {
+    __shared__ uint32_t cnt[1u << kMaxDigitBits];
+    __shared__ uint32_t wmax[1024 / kWave];
+    const uint32_t D = 1u << bits;
+    for (uint32_t d = threadIdx.x; d < D; d += 1024) cnt[d] = 0;
+    __syncthreads();
+    const uint32_t S = m < kGroupSample ? (uint32_t)m : kGroupSample;
+    constexpr int IT = kGroupSample / 1024;
+    Key k[IT];
+#pragma unroll
+    for (int r = 0; r < IT; ++r) {
+        const uint32_t i = r * 1024 + threadIdx.x;
+        k[r] = i < S ? q[(uint64_t)i * m / S] : (Key)0;
+    }
+#pragma unroll
+    for (int r = 0; r < IT; ++r) {
+        const uint32_t i = r * 1024 + threadIdx.x;
+        if (i < S) atomicAdd(&cnt[(KeyTraits<Key>::bucket(k[r], hp) >> shift) & (D - 1)], 1u);
+    }
+    __syncthreads();
+    uint32_t mx = 0;
+    for (uint32_t d = threadIdx.x; d < D; d += 1024) mx = cnt[d] > mx ? cnt[d] : mx;
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        const uint32_t x = (uint32_t)__shfl_xor((int)mx, o, kWave);
+        mx = x > mx ? x : mx;
+    }
+    if (lane_id() == 0) wmax[threadIdx.x / kWave] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 1024 / kWave; ++w) mx = wmax[w] > mx ? wmax[w] : mx;
+        const bool grouped = (uint64_t)mx * D <= (uint64_t)kGroupSkew * S;
+        gate[0] = grouped ? 1u : 0u;
+        g.seg_start[0] = 0;
+        g.seg_start[1] = (uint32_t)m;
+        g.tile_prefix[0] = 0;
+        g.tile_prefix[1] = grouped ? ntiles : 0u;
+        g.chunk_prefix[0] = 0;
+        g.chunk_prefix[1] = grouped ? nchunks : 0u;
+    }
 }
 
 size_t ungroup_smem(uint32_t bits) {
@@ -1261,21 +1321,29 @@ size_t probe_grouped_ws_bytes(uint64_t m, uint64_t V, size_t key_size) {
 
 template <typename Key>
 hipError_t run_probe_grouped(const TableDev& t, const Key* queries, uint64_t m, uint32_t* counts,
-                             unsigned long long* d_total, void* ws, hipStream_t s) {
+                             unsigned long long* d_total, void* ws, hipStream_t s, bool decide) {
     if (m == 0) return run_probe_counts<Key>(t, queries, m, counts, d_total, s);
     HG_TRY(set_smem_limits<Key>());
     const GroupPlan p = group_plan(m, t.V);
     GroupWs w;
     layout_group(ws, p, m, sizeof(Key), &w);
     const auto hp = KeyTraits<Key>::make(t.V, t.seed);
-    hipLaunchKernelGGL(k_segs_single, dim3(1), dim3(64), 0, s, w.seg, (uint32_t)m, p.ntiles,
-                       p.nchunks, w.ctr);
+    const uint32_t* gate = decide ? w.ctr : nullptr;  // ctr[0]: 1 grouped, 0 input order
+    if (decide)
+        hipLaunchKernelGGL(k_group_sample<Key>, dim3(1), dim3(1024), 0, s, queries, m, hp,
+                           p.shift, p.bits, w.seg, p.ntiles, p.nchunks, w.ctr);
+    else
+        hipLaunchKernelGGL(k_segs_single, dim3(1), dim3(64), 0, s, w.seg, (uint32_t)m, p.ntiles,
+                           p.nchunks, w.ctr);
     HG_TRY(hipGetLastError());
     Key* gq = (Key*)w.gq;
     // positions only when the counts go back to input order
     HG_TRY(partition_pass<Key>(queries, nullptr, gq, counts ? w.gpos : nullptr, w.seg, hp,
                                p.shift, p.bits, w.mat, w.csum, p.ntiles, p.nchunks, 3, false, s));
-    HG_TRY(run_probe_counts<Key>(t, gq, m, counts ? w.gc : nullptr, d_total, s, nullptr, true));
+    // one probe launch: the grouped queries, or (gate 0) the queries in input
+    // order straight into counts
+    HG_TRY(run_probe_counts<Key>(t, gq, m, counts ? w.gc : nullptr, d_total, s, nullptr, true,
+                                 gate, queries, counts));
     if (!counts) return hipSuccess;
     {
         HG_PROF("probe_ungroup", s);
@@ -1283,17 +1351,17 @@ hipError_t run_probe_grouped(const TableDev& t, const Key* queries, uint64_t m, 
         const uint32_t grid = (uint32_t)(8 * ceil_div(groups, 8));
         hipLaunchKernelGGL(k_ungroup_by_pos, dim3(grid), dim3(kUngroupThreads),
                            ungroup_smem(p.bits), s, m, p.ntiles, p.bits, (const uint32_t*)w.mat,
-                           groups, (const uint32_t*)w.gpos, (const uint32_t*)w.gc, counts);
+                           groups, (const uint32_t*)w.gpos, (const uint32_t*)w.gc, counts, gate);
     }
     return hipGetLastError();
 }
 
 template hipError_t run_probe_grouped<uint32_t>(const TableDev&, const uint32_t*, uint64_t,
                                                 uint32_t*, unsigned long long*, void*,
-                                                hipStream_t);
+                                                hipStream_t, bool);
 template hipError_t run_probe_grouped<uint64_t>(const TableDev&, const uint64_t*, uint64_t,
                                                 uint32_t*, unsigned long long*, void*,
-                                                hipStream_t);
+                                                hipStream_t, bool);
 
 template hipError_t run_build_v2<uint32_t>(const uint32_t*, uint64_t, uint64_t, uint64_t,
                                            uint32_t*, uint32_t*, uint32_t*, IndexOut&, void*,

@@ -413,13 +413,14 @@ def hg_probe(table: Table, queries: torch.Tensor, counts=True, total=False, out=
     return c, (int(tot.value) if total else None)
 
 
-PROBE_AUTO, PROBE_INPUT_ORDER, PROBE_GROUPED = 0, 1, 2
+PROBE_AUTO, PROBE_INPUT_ORDER, PROBE_GROUPED, PROBE_GROUPED_UNLESS_SKEWED = 0, 1, 2, 3
 
 
 def hg_probe_ordered(table: Table, queries: torch.Tensor, order: int, counts=True, total=False,
                      out=None, stream=None):
     """hg_probe with the probing order given: PROBE_INPUT_ORDER, PROBE_GROUPED
-    (queries grouped by bucket range first) or PROBE_AUTO."""
+    (queries grouped by bucket range first), PROBE_GROUPED_UNLESS_SKEWED (the
+    device keeps input order for skewed queries) or PROBE_AUTO."""
     queries = _dev_keys(queries)
     c = None
     if counts:

@@ -136,7 +136,8 @@ def cmd_traffic(a):
 
 SQ_COLS = ["SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_WAIT_ANY", "SQ_WAIT_INST_LDS",
            "SQ_INSTS_LDS", "SQ_ACTIVE_INST_LDS", "SQ_LDS_BANK_CONFLICT", "SQ_ACTIVE_INST_VALU"]
-SQ_KERNELS = ("k_tile_hist", "k_tile_partition", "k_local_light", "k_probe_count")
+SQ_KERNELS = ("k_tile_hist", "k_tile_partition", "k_local_light", "k_probe_count",
+              "k_ungroup_by_pos")
 
 
 def cmd_counters(a):

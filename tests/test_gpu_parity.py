@@ -257,21 +257,47 @@ def test_grouped_probe_matches_oracle(hg, kb, kind, n, m, V, index):
     dq = hg.to_device(q)
     for any_order in (False, True):
         t = hg.hg_build(hg.to_device(k), V, seed=33, index=index, any_order=any_order)
-        for order in (hg.PROBE_GROUPED, hg.PROBE_INPUT_ORDER, hg.PROBE_AUTO):
+        for order in (hg.PROBE_GROUPED, hg.PROBE_INPUT_ORDER, hg.PROBE_AUTO,
+                      hg.PROBE_GROUPED_UNLESS_SKEWED):
             c, tot = hg.hg_probe_ordered(t, dq, order, counts=True, total=True)
             assert np.array_equal(hg.to_numpy(c, np.uint32), exp), (any_order, order)
             assert tot == etot
-        _, tot = hg.hg_probe_ordered(t, dq, hg.PROBE_GROUPED, counts=False, total=True)
-        assert tot == etot
+        for order in (hg.PROBE_GROUPED, hg.PROBE_GROUPED_UNLESS_SKEWED):
+            _, tot = hg.hg_probe_ordered(t, dq, order, counts=False, total=True)
+            assert tot == etot
         c, tot = hg.hg_probe_ordered(t, dq[:0], hg.PROBE_GROUPED, total=True)
         assert c.numel() == 0 and tot == 0
+
+
+@pytest.mark.parametrize("kb", [32, 64])
+@pytest.mark.parametrize("qkind", ["uniform", "zipf"])
+def test_grouped_unless_skewed_takes_either_path(hg, kb, qkind):
+    # uniform queries spread over the ranges and are grouped; Zipf queries
+    # crowd into a few ranges and keep input order (the device decides after
+    # the histogram): counts and total equal the oracle's either way, on two
+    # calls in a row
+    say("grouped unless skewed", kb, qkind)
+    n, m, V = 300007, 400009, 300007
+    k = keys_for("uniform", n, kb, seed=41)
+    if qkind == "zipf":
+        q = workloads.zipf_keys(m, 1.2, distinct=1 << 14, seed=42).astype(dt(kb))
+        k = np.concatenate([k, q[:n // 4]])
+    else:
+        q = workloads.probe_queries(k, m, 0.5, seed=42, key_bits=kb)
+    exp, etot = oracle.probe_counts(k, q, kb)
+    t = hg.hg_build(hg.to_device(k), V, seed=43)
+    for _ in range(2):
+        c, tot = hg.hg_probe_ordered(t, hg.to_device(q), hg.PROBE_GROUPED_UNLESS_SKEWED,
+                                     counts=True, total=True)
+        assert np.array_equal(hg.to_numpy(c, np.uint32), exp)
+        assert tot == etot
 
 
 def test_grouped_probe_rejects_unknown_order(hg):
     k = workloads.uniform_keys(1000, 32, 3)
     t = hg.hg_build(hg.to_device(k), 1000, seed=1)
     with pytest.raises(hg.HGError):
-        hg.hg_probe_ordered(t, hg.to_device(k), 3)
+        hg.hg_probe_ordered(t, hg.to_device(k), 4)
 
 
 @pytest.mark.parametrize("kb", [32, 64])
