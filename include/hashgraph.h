@@ -332,8 +332,8 @@ hg_status hg_probe(const hg_table *t, const void *d_queries, uint64_t m, uint32_
  *     anyway) keeps input order; else grouped.  Workspace as for grouped.
  *   HG_PROBE_AUTO: HG_PROBE_GROUPED_UNLESS_SKEWED when the table has a probe
  *     index, m >= hash_range / 2 and hash_range >= 2^27 (2^26 when only the
- *     total is asked for), the sizes from which grouping measured faster;
- *     else input order.
+ *     total is asked for), the sizes from which grouping measured faster,
+ *     and its workspace can be allocated; else input order.
  * Any other order is HG_ERR_INVALID_ARG. */
 #define HG_PROBE_AUTO 0
 #define HG_PROBE_INPUT_ORDER 1

@@ -807,7 +807,16 @@ hg_status hg_probe_ordered(const hg_table* t, const void* d_queries, uint64_t m,
     const size_t kbytes = t->key_bits / 8;
     const size_t tot_bytes = h_total ? align_up(probe_total_slots(m) * 8, 256) : 0;
     Workspace ws(stream);
-    HG_CALL(ws.get(tot_bytes + (grouped ? probe_grouped_ws_bytes(m, t->V, kbytes) : 0) + 256));
+    hipError_t ae =
+        ws.get(tot_bytes + (grouped ? probe_grouped_ws_bytes(m, t->V, kbytes) : 0) + 256);
+    if (ae == hipErrorOutOfMemory && grouped && order == HG_PROBE_AUTO) {
+        // the grouping's workspace is out of reach: probe in input order
+        (void)hipGetLastError();  // the failed allocation's error is not the probe's
+        ws.p = nullptr;
+        grouped = false;
+        ae = ws.get(tot_bytes + 256);
+    }
+    if (ae != hipSuccess) return from_hip(ae);
     unsigned long long* d_total = h_total ? (unsigned long long*)ws.p : nullptr;
     void* gws = (char*)ws.p + tot_bytes;
     hipError_t e;

@@ -82,3 +82,34 @@ def test_failing_allocator_reports_oom_and_default_is_restored():
     o_off, o_ids, _ = oracle.build_table(keys, V, 1)
     assert np.array_equal(hg.to_numpy(off, np.uint32), o_off)
     assert np.array_equal(hg.to_numpy(ids, np.uint32), o_ids)
+
+
+def test_auto_probe_falls_back_to_input_order_without_grouping_workspace():
+    # a table large enough for hg_probe to group its queries (2^27 buckets,
+    # m >= V / 2); with an allocator that refuses the grouping's workspace
+    # (about 12 bytes per query) the probe runs in input order instead of
+    # failing, with the counts and total of the input-order probe (whose
+    # parity with the oracle the parity tests cover)
+    n = V = 1 << 27
+    m = 1 << 26
+    keys = workloads.uniform_keys(n, 32, seed=31)
+    q = workloads.probe_queries(keys, m, 0.5, seed=32)
+    dk, dq = hg.to_device(keys), hg.to_device(q)
+    del keys, q
+    t = hg.hg_build(dk, V, seed=3)
+    exp, etot = hg.hg_probe_ordered(t, dq, hg.PROBE_INPUT_ORDER, total=True)
+    limit = 64 << 20
+
+    def alloc(nbytes, stream):
+        return 0 if nbytes > limit else torch.cuda.caching_allocator_alloc(nbytes, stream=stream)
+
+    hg.set_allocator(alloc, lambda ptr, stream: torch.cuda.caching_allocator_delete(ptr))
+    try:
+        with pytest.raises(hg.HGError) as ei:
+            hg.hg_probe_ordered(t, dq, hg.PROBE_GROUPED)
+        assert ei.value.status == hg.HG_ERR_OOM
+        c, tot = hg.hg_probe(t, dq, counts=True, total=True)
+    finally:
+        hg.set_allocator()
+    assert torch.equal(c, exp) and tot == etot
+    t.free()
