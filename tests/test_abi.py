@@ -93,6 +93,30 @@ def test_invalid_arguments_rejected_on_host(lib):
     assert lib.hg_random_access_rate(1, 1 << 20, 1000, None, None) == 1
 
 
+def test_probe_orders_match_the_header():
+    # the binding's probing orders are the header's defines
+    import re
+    from paper_1907_02900_amd import hg
+    with open(os.path.join(ROOT, "include", "hashgraph.h")) as f:
+        text = f.read()
+    got = dict(re.findall(r"#define (HG_PROBE_[A-Z_]+) (\d+)", text))
+    assert "hg_probe_ordered" in declared_functions()
+    assert {k: int(v) for k, v in got.items()} == {
+        "HG_PROBE_AUTO": hg.PROBE_AUTO, "HG_PROBE_INPUT_ORDER": hg.PROBE_INPUT_ORDER,
+        "HG_PROBE_GROUPED": hg.PROBE_GROUPED,
+        "HG_PROBE_GROUPED_UNLESS_SKEWED": hg.PROBE_GROUPED_UNLESS_SKEWED}
+
+
+def test_bench_grouping_matrix_matches_the_documented_workspace():
+    # 2 KiB of tile x range matrix per 4096 queries once V has 2^9 buckets
+    # (512 ranges), fewer ranges (at least 2) below
+    import bench
+    assert bench.group_matrix_bytes(1 << 28, 1 << 28) == (1 << 16) * 2048
+    assert bench.group_matrix_bytes(4097, 1 << 20) == 2 * 2048
+    assert bench.group_matrix_bytes(4096, 100) == 128 * 4
+    assert bench.group_matrix_bytes(10, 1) == 2 * 4
+
+
 def test_no_cpu_fallback_without_gpu(lib):
     import torch
     if torch.cuda.is_available():
